@@ -1,0 +1,203 @@
+/*
+ * ocm.h -- exact optimal cycle mean on one AMD Instinct MI355X (gfx950).
+ *
+ * The optimal cycle mean problem (Section 2.1, Definition "OCM problem"):
+ * for a digraph G = (V, E) with integer edge weights w, the mean of a cycle is
+ * its weight divided by its number of edges, and the minimum cycle mean is the
+ * smallest mean over all cycles.  The maximum cycle mean (the worst sustainable
+ * load of Sections 1 and 4) is minus the minimum over negated weights.
+ *
+ * The solver is Howard's policy iteration (Alg. 2, Section 2.5) decomposed
+ * into data-parallel phases as in Section 3.1 (Alg. 3): policy improvement,
+ * cycle detection in the one-successor policy graph, minimum-mean cycle
+ * selection, rebuilding the policy graph around that cycle, and value
+ * propagation from the cycle's smallest vertex.  All arithmetic is exact
+ * (int64 values scaled by the cycle length, int128 comparisons of means), and
+ * every choice the paper leaves open is fixed deterministically:
+ *   - a vertex changes policy only on strict improvement, to the lowest CSR
+ *     position attaining the best value;
+ *   - cycles are ordered by mean, then by their smallest vertex index;
+ *   - the source is the smallest vertex index on the chosen cycle;
+ *   - vertices that cannot reach the chosen cycle through the policy are
+ *     attached in breadth-first rounds, each taking its lowest-position edge
+ *     into the set attached before the round.
+ * Results therefore do not depend on scheduling: repeated calls return
+ * identical bytes.
+ *
+ * Graph layout (Section 2.3, Fig. 2b): CSR.  row_ptr[n+1] holds the offset of
+ * each vertex's first out-edge; col[m] holds edge targets ordered by source;
+ * w[m] holds the weight of each edge in the same order (int32 or int64).
+ * Edges are identified by their CSR position, so parallel edges and
+ * self-loops are distinct.
+ *
+ * Memory: every array pointer is HIP device memory owned by the caller,
+ * except ocm_result and ocm_profile, which are host memory.  Inputs are never
+ * modified.  The library allocates no device memory in ocm_min / ocm_max: all
+ * scratch space is the caller's workspace (see ocm_workspace_size).
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = null stream).
+ * Every call enqueues its kernels on that stream and synchronises it before
+ * returning (loop control reads small counters back to the host).
+ *
+ * Errors: functions return ocm_status; nothing aborts or throws across the
+ * ABI.  ocm_last_error() returns a thread-local message for the last failure.
+ * Calls are reentrant as long as concurrent calls use distinct workspaces.
+ */
+#ifndef OCM_H
+#define OCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OCM_OK = 0,
+    OCM_E_INVALID_ARG = -1,            /* null pointer, n < 1, m < 1, bad enum  */
+    OCM_E_BAD_CSR = -2,                /* row_ptr not 0..m monotone, col outside [0,n) */
+    OCM_E_NO_OUT_EDGE = -3,            /* a vertex without out-edges            */
+    OCM_E_NOT_STRONGLY_CONNECTED = -4, /* some vertex cannot reach the chosen cycle */
+    OCM_E_OVERFLOW = -5,               /* a value would leave the int64 range   */
+    OCM_E_CAPACITY = -6,               /* cycle_cap (or another cap) too small  */
+    OCM_E_NOT_CONVERGED = -7,          /* max_iters reached with changes left   */
+    OCM_E_WORKSPACE = -8,              /* workspace null or too small           */
+    OCM_E_HIP = -9                     /* a HIP runtime call failed             */
+} ocm_status;
+
+enum { OCM_W_I32 = 0, OCM_W_I64 = 1 };
+
+/* ocm_result.flags */
+enum {
+    OCM_F_TIE = 1u,            /* another critical cycle exists (exact test)   */
+    OCM_F_TIE_UNCHECKED = 2u,  /* the uniqueness test was not run              */
+    OCM_F_TIGHT_EDGES = 4u     /* some non-policy edge is tight at the optimum */
+};
+
+typedef struct {
+    int64_t n, m;              /* 1 <= n, 1 <= m < 2^31                        */
+    const int32_t *row_ptr;    /* device, n+1 entries                          */
+    const int32_t *col;        /* device, m entries                            */
+    const void *w;             /* device, m entries of int32 or int64          */
+    int32_t wtype;             /* OCM_W_I32 or OCM_W_I64                       */
+} ocm_graph;
+
+typedef struct {
+    int64_t p, q;              /* optimum = p/q, q >= 1, gcd(|p|, q) = 1       */
+    int64_t cycle_len;         /* |C|, also set on OCM_E_CAPACITY              */
+    int32_t source;            /* smallest vertex on C; C starts at its edge   */
+    int32_t iterations;        /* policy-improvement sweeps, first and last included */
+    uint32_t flags;            /* OCM_F_*                                      */
+    int32_t connect_rounds;    /* breadth-first connect rounds, all iterations */
+    int32_t jump_rounds;       /* pointer-jumping rounds, all iterations       */
+    int32_t fast_iters;        /* iterations resolved by the fused fast path   */
+    int64_t W, L;              /* unreduced optimum W/L: weight and length of C */
+    int64_t tight_edges;       /* tight non-policy edges at the optimum        */
+} ocm_result;
+
+/* Per-phase device time, filled when ocm_options.profile is non-null. */
+enum {
+    OCM_PH_VALIDATE = 0, OCM_PH_SWEEP, OCM_PH_CYCLES, OCM_PH_SELECT,
+    OCM_PH_CONNECT, OCM_PH_VALUES, OCM_PH_FAST, OCM_PH_RESULT, OCM_PH_COUNT
+};
+typedef struct {
+    double ms[OCM_PH_COUNT];       /* summed kernel time per phase (hipEvents) */
+    int32_t launches[OCM_PH_COUNT];
+} ocm_profile;
+
+typedef struct {
+    int32_t max_iters;         /* 0 = unlimited                                */
+    int32_t validate;          /* 1 = check the CSR on the device first        */
+    int32_t schedule;          /* lanes per vertex in the sweep: 1..64 (power
+                                  of two), 0 = chosen from the mean degree     */
+    int32_t tie_check;         /* 1 = run the exact uniqueness test of C       */
+    int32_t fast_path;         /* 1 = fuse cycle/value phases while the critical
+                                  cycle is unchanged (same results)            */
+    int32_t connect_mode;      /* rebuild rounds: 0 = pick pull or push per
+                                  round, 1 = pull only, 2 = push only (same
+                                  results)                                     */
+    int32_t *policy_out;       /* device int32[n] or NULL: final policy (edge positions) */
+    int64_t *potential_out;    /* device int64[n] or NULL: final values scaled by L */
+    ocm_profile *profile;      /* host, or NULL                                */
+} ocm_options;
+
+/* Fills *o with the defaults: max_iters 0, validate 1, schedule 0,
+ * tie_check 1, fast_path 1, connect_mode 0, no outputs, no profile. */
+void ocm_default_options(ocm_options *o);
+
+/* Bytes of workspace ocm_min / ocm_max / ocm_* phases need for this graph
+ * (about 120 bytes per vertex plus 8 per edge).  Returns 0 on invalid input. */
+size_t ocm_workspace_size(const ocm_graph *g, const ocm_options *o);
+
+/* Minimum cycle mean (Definition "OCM problem", Section 2.1) by policy
+ * iteration (Alg. 2, Alg. 3).  The graph must be strongly connected for a
+ * guaranteed answer (Section 2.5); otherwise the call either returns the
+ * optimum (still exact) or OCM_E_NOT_STRONGLY_CONNECTED.
+ *   ws, ws_bytes   device workspace of at least ocm_workspace_size bytes;
+ *   cycle_edges    device int32[cycle_cap]: receives C as CSR edge positions
+ *                  in traversal order, starting with the edge leaving source;
+ *   out            host result.
+ * o may be NULL (defaults). */
+ocm_status ocm_min(const ocm_graph *g, const ocm_options *o, void *ws,
+                   size_t ws_bytes, int32_t *cycle_edges, int64_t cycle_cap,
+                   ocm_result *out, void *stream);
+
+/* Maximum cycle mean: minus the minimum over negated weights, with the same
+ * rules (so the same cycle and iteration count as ocm_min on -w). */
+ocm_status ocm_max(const ocm_graph *g, const ocm_options *o, void *ws,
+                   size_t ws_bytes, int32_t *cycle_edges, int64_t cycle_cap,
+                   ocm_result *out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Single phases of one policy-iteration step (Alg. 3), on caller arrays.  */
+/* They share the workspace layout of ocm_min and exist so that each phase */
+/* can be driven from a recorded state.  neg = 1 negates the weights.      */
+/* ---------------------------------------------------------------------- */
+
+/* Policy improvement sweep (Alg. 2 main loop; SPFPassIter of Alg. 3).  For
+ * every vertex v: best = min over out-edges e = v->u of V[u] + L*w(e) - W,
+ * taken at the lowest position; if first != 0 (pi = nil, V = 0, lambda = 0)
+ * or best < V[v], pi[v] <- that position.  V may be NULL when first != 0.
+ * *changed receives the number of vertices whose policy was written. */
+ocm_status ocm_phase_sweep(const ocm_graph *g, int32_t neg, int32_t first,
+                           const int64_t *V, int64_t W, int64_t L,
+                           int32_t *pi, int32_t schedule, void *ws,
+                           size_t ws_bytes, int64_t *changed, void *stream);
+
+/* Policy-graph cycles (GpiPreprocess, elimination and cycleIdentification
+ * of Alg. 3).  rep[v] = smallest vertex index on the cycle that v's policy
+ * path enters; on_cycle[v] = 1 for cycle vertices.  *ncycles = cycles. */
+ocm_status ocm_phase_cycles(const ocm_graph *g, const int32_t *pi,
+                            int32_t *rep, uint8_t *on_cycle, void *ws,
+                            size_t ws_bytes, int64_t *ncycles, void *stream);
+
+/* Minimum-mean cycle (reduce_min, setMinCycle): among cycles of the policy
+ * graph the smallest W/L, ties to the smallest rep.  s = that rep. */
+ocm_status ocm_phase_select(const ocm_graph *g, int32_t neg, const int32_t *pi,
+                            const int32_t *rep, const uint8_t *on_cycle,
+                            void *ws, size_t ws_bytes, int32_t *s, int64_t *W,
+                            int64_t *L, void *stream);
+
+/* Rebuild (markMinComponent, connectGpi): vertices with rep == s keep pi
+ * (layer 0); the others are attached in rounds k = 1, 2, ... (layer k).
+ * *rounds = number of rounds; OCM_E_NOT_STRONGLY_CONNECTED if stuck. */
+ocm_status ocm_phase_connect(const ocm_graph *g, const int32_t *rep, int32_t s,
+                             int32_t *pi, int32_t *layer, void *ws,
+                             size_t ws_bytes, int32_t *rounds, void *stream);
+
+/* Value propagation (val[source] <- 0, valuePropagate of Alg. 4):
+ * V[s] = 0 and V[v] = V[succ v] + L*w(pi v) - W over the policy tree cut at
+ * s.  OCM_E_OVERFLOW if a value leaves [-2^62, 2^62]. */
+ocm_status ocm_phase_values(const ocm_graph *g, int32_t neg, const int32_t *pi,
+                            int32_t s, int64_t W, int64_t L, int64_t *V,
+                            void *ws, size_t ws_bytes, int32_t *rounds,
+                            void *stream);
+
+const char *ocm_status_string(ocm_status s);
+const char *ocm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OCM_H */

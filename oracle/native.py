@@ -40,7 +40,7 @@ class _Result(C.Structure):
     _fields_ = [("p", C.c_int64), ("q", C.c_int64), ("cycle_len", C.c_int64),
                 ("source", C.c_int32), ("iterations", C.c_int32),
                 ("tie", C.c_int32), ("ncycles_first", C.c_int32),
-                ("W", C.c_int64), ("L", C.c_int64)]
+                ("W", C.c_int64), ("L", C.c_int64), ("tight", C.c_int64)]
 
 
 def lib():
@@ -119,6 +119,7 @@ class Solution:
     ncycles_first: int
     W: int
     L: int
+    tight: int               # tight non-policy edges at the optimum
     V: np.ndarray | None     # potential scaled by L (int64), if requested
 
     @property
@@ -140,7 +141,7 @@ def solve(row_ptr, col, w, mode: str = "min", max_iters: int = 0,
     if rc:
         raise OracleError(rc, "solve")
     return Solution(res.p, res.q, cyc[:res.cycle_len].copy(), res.source,
-                    res.iterations, res.tie, res.ncycles_first, res.W, res.L, V)
+                    res.iterations, res.tie, res.ncycles_first, res.W, res.L, res.tight, V)
 
 
 def certify(row_ptr, col, w, p, q, cycle, V, K, mode: str = "min") -> int:

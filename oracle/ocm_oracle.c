@@ -503,6 +503,7 @@ typedef struct {
     int32_t tie;
     int32_t ncycles_first;   /* cycles in the first policy graph */
     int64_t W, L;            /* unreduced lambda */
+    int64_t tight;           /* non-policy edges with V(v) = V(u) + L*w - W */
 } orc_result;
 
 /* Full sequential solve.  cycle_edges (capacity cap) receives the critical
@@ -549,6 +550,10 @@ int orc_solve(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
             }
         }
         res->tie = do_tie ? orc_state_tie(st) : -1;
+        res->tight = 0;
+        for (int64_t v = 0; v < n; ++v)
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+                if (e != st->pi[v] && edge_value(st, e) == st->val[v]) res->tight++;
         if (val_out) {
             rc = orc_state_get_val(st, val_out);
             if (rc) goto done;

@@ -1,0 +1,103 @@
+// Shared declarations of the device kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ocm {
+
+constexpr int kWG = 256;        // threads per workgroup (4 waves of 64)
+constexpr int kWI32 = 0, kWI64 = 1;
+constexpr int kListItems = 4096;  // LDS list buffer of the connect kernels (16 KiB)
+
+constexpr unsigned kErrBadCsr = 1u;
+constexpr unsigned kErrNoOut = 2u;
+
+constexpr unsigned kClrChanged = 1u;
+constexpr unsigned kClrCount = 2u;
+constexpr unsigned kClrAll = 4u;
+
+// |V| must stay within 2^62 so that V[u] + (L*w - W) cannot leave int64 when
+// |L*w - W| < 2^62 as well.
+constexpr long long kValLimit = (1ll << 62);
+constexpr unsigned kHopOverflow = 0x80000000u;
+
+// Device control block: loop counters and the current lambda = W / L.
+struct alignas(16) Ctl {
+    long long W, L;                // current lambda, unreduced
+    int s;                         // current source (min vertex of C)
+    unsigned ncyc;                 // cycles found by the cycle phase
+    unsigned long long changed;    // sweep: vertices whose policy changed
+    unsigned long long tight;      // tie scan: tight non-policy edges
+    unsigned ucnt[2];              // connect: unattached-list sizes
+    unsigned fcnt[2];              // connect: frontier-list sizes
+    unsigned active;               // values: unfinished vertices
+    unsigned active2;
+    unsigned err;                  // validation error bits
+    unsigned cbroken;              // sweep: a vertex of C changed policy
+    unsigned long long maxabsw;    // validation: max |w|
+    unsigned overflow;             // values: a value left [-2^62, 2^62]
+    unsigned pad;
+};
+
+// Pointer-jumping entry of the value phase: the first H edges of v's policy
+// path lead to J and carry the sum D of (L*w - W).  Bit 31 of H flags an
+// int64 overflow of D.
+struct alignas(16) Jmp {
+    long long D;
+    int J;
+    unsigned H;
+};
+
+struct SweepArgs {
+    int n;
+    int neg;
+    const int* row_ptr;
+    const int* col;
+    const long long* V;
+    long long W, L;
+    int* pi;
+    const unsigned char* onC;      // optional: flags vertices of the current C
+    Ctl* ctl;
+};
+
+void launch_validate(int n, int m, const int* row_ptr, const int* col, const void* w, int wtype,
+                     int check_csr, Ctl* ctl, hipStream_t st);
+void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool first, bool tie,
+                  unsigned grid, hipStream_t st);
+void launch_pj_init(int n, const int* col, const int* pi, int* succ, unsigned long long* P,
+                    unsigned char* onc, hipStream_t st);
+void launch_pj_round(int n, const unsigned long long* Pin, unsigned long long* Pout,
+                     hipStream_t st);
+void launch_pj_final(int n, const unsigned long long* P, int* rep, unsigned char* onc,
+                     hipStream_t st);
+void launch_cyc_zero(int n, const int* rep, const unsigned char* onc, long long* wsum,
+                     unsigned* lcnt, int* cyc_list, Ctl* ctl, hipStream_t st);
+void launch_cyc_sum(int n, const int* rep, const unsigned char* onc, const int* pi, const void* w,
+                    int wtype, int neg, long long* wsum, unsigned* lcnt, hipStream_t st);
+void launch_select(const int* cyc_list, const long long* wsum, const unsigned* lcnt, Ctl* ctl,
+                   hipStream_t st);
+void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, int* layer,
+                      unsigned char* onC, int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt,
+                      hipStream_t st);
+void launch_conn_pull(int k, const int* row_ptr, const int* col, int* layer, int* pi,
+                      const int* in_list, unsigned in_cnt, int* ulist, unsigned* ucnt, int* flist,
+                      unsigned* fcnt, hipStream_t st);
+void launch_conn_push(int k, const int* rin_ptr, const int* rin_src, const int* rin_edge,
+                      int* layer, int* pi, int* cand, const int* fin, unsigned f_cnt, int* fout,
+                      unsigned* fout_cnt, hipStream_t st);
+void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
+                      unsigned* tot, int* rin_ptr, int* rin_src, int* rin_edge, int* cand,
+                      hipStream_t st);
+void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
+                     int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl, hipStream_t st);
+void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st);
+void launch_val_final(int n, const Jmp* Q, long long* V, Ctl* ctl, hipStream_t st);
+void launch_cycle_list(int n, int s, long long L, const unsigned char* onC, const int* pi,
+                       const Jmp* Q, int* out, hipStream_t st);
+void launch_ctl_clear(Ctl* ctl, unsigned what, hipStream_t st);
+void launch_ctl_set(Ctl* ctl, int s, long long W, long long L, hipStream_t st);
+void launch_zero2(unsigned* a, unsigned* b, hipStream_t st);
+void launch_fill_u8(unsigned char* p, int64_t n, unsigned char v, hipStream_t st);
+
+}  // namespace ocm

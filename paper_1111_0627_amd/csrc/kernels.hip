@@ -1,0 +1,970 @@
+// Device kernels of the exact optimal-cycle-mean solver (gfx950, wave64).
+//
+// Howard's policy iteration (Alg. 2) decomposed into data-parallel phases as
+// in Alg. 3.  Phase names follow the paper's kernels:
+//   sweep    SPFPassIter: policy improvement over the CSR out-edges
+//   cycles   GpiPreprocess + elimination + cycleIdentification, done here by
+//            pointer jumping over the one-successor policy graph
+//   select   reduce_min + setMinCycle: minimum-mean cycle, exact order
+//   connect  markMinComponent + connectGpi: breadth-first rebuild rounds
+//   values   val[source] <- 0 + valuePropagate (Alg. 4), by pointer jumping
+// All values are exact integers: V is scaled by L = |C| so that lambda = W/L
+// never has to be divided.
+#include "kernels.h"
+
+namespace ocm {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remapping the block
+// index gives every XCD one contiguous slice of the vertex range, so the
+// gathers of neighbouring vertices hit that XCD's own L2.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    if ((nb & 7) != 0) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+template <typename WT>
+__device__ __forceinline__ int64_t wval(const WT* w, int64_t e, int neg)
+{
+    int64_t x = (int64_t)w[e];
+    return neg ? -x : x;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long y = __shfl_xor(x, off, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// Sum over the workgroup; the result is valid in thread 0.  Counters are
+// reduced per workgroup so a launch issues one global atomic per block, not
+// one per wave (same-address atomics serialise in the L2).
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x)
+{
+    __shared__ unsigned long long part[kWG / 64];
+    x = wave_sum_u64(x);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kWG / 64; ++i) t += part[i];
+    return t;
+}
+
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long x)
+{
+    __shared__ unsigned long long part[kWG / 64];
+    x = wave_max_u64(x);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kWG / 64; ++i) t = part[i] > t ? part[i] : t;
+    return t;
+}
+
+// Workgroup-buffered list append: items go to an LDS buffer first and the
+// block reserves its slice of the global list with one atomic at the end.
+struct BlockList {
+    int* buf;          // LDS, capacity kListItems
+    unsigned* n;       // LDS counter
+};
+
+__device__ __forceinline__ void blist_push(BlockList& b, bool want, int item)
+{
+    const unsigned long long mask = __ballot(want);
+    if (!mask) return;
+    const unsigned lane = threadIdx.x & 63;
+    const unsigned leader = (unsigned)__ffsll((long long)mask) - 1u;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(b.n, (unsigned)__popcll(mask));
+    base = __shfl(base, (int)leader, 64);
+    if (want) b.buf[base + __popcll(mask & ((1ull << lane) - 1ull))] = item;
+}
+
+__device__ __forceinline__ void blist_flush(BlockList& b, int* out, unsigned* out_cnt)
+{
+    __shared__ unsigned base;
+    __syncthreads();
+    const unsigned cnt = *b.n;
+    if (threadIdx.x == 0) base = cnt ? atomicAdd(out_cnt, cnt) : 0u;
+    __syncthreads();
+    for (unsigned j = threadIdx.x; j < cnt; j += kWG) out[base + j] = b.buf[j];
+}
+
+// |x| as unsigned, defined for INT64_MIN too.
+__device__ __forceinline__ unsigned long long uabs64(int64_t x)
+{
+    return x < 0 ? (unsigned long long)(-(x + 1)) + 1ull : (unsigned long long)x;
+}
+
+// Appends `want` lanes' items to a global list with one atomic per wave.
+// Returns this lane's slot (valid only when want is true).
+__device__ __forceinline__ unsigned wave_append(bool want, unsigned* counter)
+{
+    unsigned long long mask = __ballot(want);
+    unsigned lane = threadIdx.x & 63;
+    unsigned before = __popcll(mask & ((1ull << lane) - 1ull));
+    unsigned total = __popcll(mask);
+    unsigned leader = mask ? (unsigned)__ffsll((long long)mask) - 1u : 0u;
+    unsigned base = 0;
+    if (want && lane == leader) base = atomicAdd(counter, total);
+    base = __shfl(base, (int)leader, 64);
+    return base + before;
+}
+
+// ---------------------------------------------------------------------------
+// validation: CSR shape of Fig. 2b, out-degree >= 1, max |w|
+// ---------------------------------------------------------------------------
+template <typename WT>
+__global__ __launch_bounds__(kWG) void k_validate(int n, int m, const int* __restrict__ row_ptr,
+                                                  const int* __restrict__ col,
+                                                  const WT* __restrict__ w, int check_csr,
+                                                  Ctl* ctl)
+{
+    unsigned err = 0;
+    unsigned long long mx = 0;
+    const int64_t total = (int64_t)(n > m ? n : m);
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * kWG) {
+        if (check_csr && i < n) {
+            int a = row_ptr[i], b = row_ptr[i + 1];
+            if (b < a) err |= kErrBadCsr;
+            if (b == a) err |= kErrNoOut;
+            if (i == 0 && (a != 0 || row_ptr[n] != m)) err |= kErrBadCsr;
+        }
+        if (i < m) {
+            if (check_csr) {
+                int c = col[i];
+                if (c < 0 || c >= n) err |= kErrBadCsr;
+            }
+            unsigned long long a = uabs64((int64_t)w[i]);
+            mx = a > mx ? a : mx;
+        }
+    }
+    mx = block_max_u64(mx);
+    __shared__ unsigned eor;
+    if (threadIdx.x == 0) eor = 0;
+    __syncthreads();
+    if (err) atomicOr(&eor, err);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (mx) atomicMax(&ctl->maxabsw, mx);
+        if (eor) atomicOr(&ctl->err, eor);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sweep (SPFPassIter): G lanes per vertex, segmented argmin over out-edges
+// ---------------------------------------------------------------------------
+template <int G, typename WT, bool FIRST, bool TIE>
+__global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a, const WT* __restrict__ w)
+{
+    constexpr int VPB = kWG / G;             // vertices per block per step
+    const int64_t L = FIRST ? 1 : a.L;
+    const int64_t W = FIRST ? 0 : a.W;
+    const int lane = threadIdx.x & (G - 1);
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t per = ((int64_t)a.n + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)b * per;
+    const int64_t v1 = v0 + per < a.n ? v0 + per : a.n;
+    unsigned long long cnt = 0;
+    unsigned cbroken = 0;
+    for (int64_t vb = v0; vb < v1; vb += VPB) {
+        const int64_t v = vb + threadIdx.x / G;
+        const bool live = v < v1;
+        int beg = 0, end = 0;
+        int64_t own = 0;
+        int cur = -1;
+        if (live) {
+            beg = a.row_ptr[v];
+            end = a.row_ptr[v + 1];
+            if (!FIRST) own = a.V[v];
+            if (TIE) cur = a.pi[v];
+        }
+        int64_t best = INT64_MAX;
+        int bpos = INT32_MAX;
+        for (int e = beg + lane; e < end; e += G) {
+            const int64_t we = wval(w, e, a.neg);
+            const int64_t key = FIRST ? we : a.V[a.col[e]] + L * we - W;
+            if (TIE) {
+                // tie scan: tight edges other than the policy edge
+                if (key == own && e != cur) cnt++;
+            } else if (key < best) {
+                best = key;
+                bpos = e;
+            }
+        }
+        if (TIE) continue;
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+            const int64_t ob = __shfl_xor(best, off, G);
+            const int op = __shfl_xor(bpos, off, G);
+            if (ob < best || (ob == best && op < bpos)) {
+                best = ob;
+                bpos = op;
+            }
+        }
+        if (live && lane == 0 && (FIRST || best < own)) {
+            a.pi[v] = bpos;
+            cnt++;
+            if (!FIRST && a.onC && a.onC[v]) cbroken = 1;
+        }
+    }
+    cnt = block_sum_u64(cnt);
+    const unsigned long long brk = block_sum_u64(cbroken);
+    if (threadIdx.x == 0) {
+        if (cnt) atomicAdd(TIE ? &a.ctl->tight : &a.ctl->changed, cnt);
+        if (brk) atomicOr(&a.ctl->cbroken, 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cycles: pointer jumping over the policy graph.  Entry P[v] packs
+// (J = succ^(2^k)(v), M = min vertex among the first 2^k vertices of v's
+// policy path).  After K rounds with 2^K >= n, J is on v's cycle and M at a
+// cycle vertex is the whole cycle's minimum.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long pj_pack(int j, int mn)
+{
+    return ((unsigned long long)(unsigned)j << 32) | (unsigned)mn;
+}
+
+__global__ __launch_bounds__(kWG) void k_pj_init(int n, const int* __restrict__ col,
+                                                 const int* __restrict__ pi, int* __restrict__ succ,
+                                                 unsigned long long* __restrict__ P,
+                                                 unsigned char* __restrict__ onc)
+{
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v >= n) return;
+    const int s = col[pi[v]];
+    succ[v] = s;
+    P[v] = pj_pack(s, v);
+    onc[v] = 0;
+}
+
+__global__ __launch_bounds__(kWG) void k_pj_round(int n, const unsigned long long* __restrict__ Pin,
+                                                  unsigned long long* __restrict__ Pout)
+{
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v >= n) return;
+    const unsigned long long p = Pin[v];
+    const int j = (int)(p >> 32);
+    const unsigned long long q = Pin[j];
+    const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
+    Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
+}
+
+__global__ __launch_bounds__(kWG) void k_pj_final(int n, const unsigned long long* __restrict__ P,
+                                                  int* __restrict__ rep,
+                                                  unsigned char* __restrict__ onc)
+{
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v >= n) return;
+    const int c = (int)(P[v] >> 32);
+    rep[v] = (int)(unsigned)P[c];
+    onc[c] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// select: per-cycle (W, L) keyed by rep, then the minimum in exact order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_cyc_zero(int n, const int* __restrict__ rep,
+                                                  const unsigned char* __restrict__ onc,
+                                                  long long* __restrict__ wsum,
+                                                  unsigned* __restrict__ lcnt,
+                                                  int* __restrict__ cyc_list, Ctl* ctl)
+{
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    const bool head = v < n && onc[v] && rep[v] == v;
+    if (head) {
+        wsum[v] = 0;
+        lcnt[v] = 0;
+    }
+    const unsigned slot = wave_append(head, &ctl->ncyc);
+    if (head) cyc_list[slot] = v;
+}
+
+template <typename WT>
+__global__ __launch_bounds__(kWG) void k_cyc_sum(int n, const int* __restrict__ rep,
+                                                 const unsigned char* __restrict__ onc,
+                                                 const int* __restrict__ pi,
+                                                 const WT* __restrict__ w, int neg,
+                                                 long long* __restrict__ wsum,
+                                                 unsigned* __restrict__ lcnt)
+{
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v >= n || !onc[v]) return;
+    const int r = rep[v];
+    atomicAdd((unsigned long long*)&wsum[r], (unsigned long long)wval(w, pi[v], neg));
+    atomicAdd(&lcnt[r], 1u);
+}
+
+struct Cand {
+    long long W;
+    long long L;
+    int r;
+};
+
+// a < b in the order (W/L, r); L > 0.
+__device__ __forceinline__ bool cand_less(const Cand& a, const Cand& b)
+{
+    if (b.r < 0) return a.r >= 0;
+    if (a.r < 0) return false;
+    const __int128 x = (__int128)a.W * b.L, y = (__int128)b.W * a.L;
+    if (x != y) return x < y;
+    return a.r < b.r;
+}
+
+__global__ __launch_bounds__(1024) void k_select(const int* __restrict__ cyc_list,
+                                                 const long long* __restrict__ wsum,
+                                                 const unsigned* __restrict__ lcnt, Ctl* ctl)
+{
+    __shared__ Cand sh[1024];
+    const unsigned nc = ctl->ncyc;
+    Cand best{0, 1, -1};
+    for (unsigned i = threadIdx.x; i < nc; i += 1024) {
+        const int r = cyc_list[i];
+        Cand c{wsum[r], (long long)lcnt[r], r};
+        if (cand_less(c, best)) best = c;
+    }
+    sh[threadIdx.x] = best;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (threadIdx.x < st && cand_less(sh[threadIdx.x + st], sh[threadIdx.x]))
+            sh[threadIdx.x] = sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ctl->s = sh[0].r;
+        ctl->W = sh[0].W;
+        ctl->L = sh[0].L;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// connect: keep the chosen cycle's component, attach the rest breadth-first
+// ---------------------------------------------------------------------------
+// Each block owns a contiguous range of at most kListItems inputs; outputs
+// are buffered in LDS and written with one global atomic per block.
+//
+// The rebuild attaches vertices in rounds.  In round k an unattached vertex u
+// can only have out-edges into layer k-1 (an edge into an earlier layer would
+// have attached it earlier), so "the lowest-position out-edge into the set
+// attached before round k" can be found two ways with identical results:
+//   pull: u scans its own out-edges in CSR order (k_conn_pull);
+//   push: every frontier vertex x of layer k-1 offers its in-edges e = u->x
+//         and u keeps the minimum e (atomicMin, order-independent;
+//         k_conn_push + k_conn_push_fin).
+// The host picks the cheaper direction per round.
+__global__ __launch_bounds__(kWG) void k_conn_init(int n, const int* __restrict__ rep,
+                                                   const unsigned char* __restrict__ onc,
+                                                   int s, unsigned per, int* __restrict__ layer,
+                                                   unsigned char* __restrict__ onC,
+                                                   int* __restrict__ ulist, unsigned* ucnt,
+                                                   int* __restrict__ flist, unsigned* fcnt)
+{
+    __shared__ int ubuf[kListItems], fbuf[kListItems];
+    __shared__ unsigned nu, nf;
+    if (threadIdx.x == 0) nu = nf = 0;
+    __syncthreads();
+    BlockList bu{ubuf, &nu}, bf{fbuf, &nf};
+    const int64_t v0 = (int64_t)blockIdx.x * per;
+    const int64_t v1 = v0 + per < n ? v0 + per : n;
+    for (int64_t vb = v0; vb < v1; vb += kWG) {
+        const int64_t v = vb + threadIdx.x;
+        bool live = v < v1, comp = false;
+        if (live) {
+            comp = rep[v] == s;
+            layer[v] = comp ? 0 : -1;
+            if (onC) onC[v] = (unsigned char)(comp && onc && onc[v]);
+        }
+        blist_push(bu, live && !comp, (int)v);
+        blist_push(bf, live && comp, (int)v);
+    }
+    blist_flush(bu, ulist, ucnt);
+    blist_flush(bf, flist, fcnt);
+}
+
+__global__ __launch_bounds__(kWG) void k_conn_pull(int k, const int* __restrict__ row_ptr,
+                                                   const int* __restrict__ col,
+                                                   int* __restrict__ layer, int* __restrict__ pi,
+                                                   const int* __restrict__ in_list, unsigned in_cnt,
+                                                   unsigned per, int* __restrict__ ulist,
+                                                   unsigned* ucnt, int* __restrict__ flist,
+                                                   unsigned* fcnt)
+{
+    __shared__ int ubuf[kListItems], fbuf[kListItems];
+    __shared__ unsigned nu, nf;
+    if (threadIdx.x == 0) nu = nf = 0;
+    __syncthreads();
+    BlockList bu{ubuf, &nu}, bf{fbuf, &nf};
+    const int64_t i0 = (int64_t)blockIdx.x * per;
+    const int64_t i1 = i0 + per < in_cnt ? i0 + per : in_cnt;
+    for (int64_t ib = i0; ib < i1; ib += kWG) {
+        const int64_t i = ib + threadIdx.x;
+        bool left = false, got = false;
+        int u = 0;
+        if (i < i1) {
+            u = in_list[i];
+            if (layer[u] == -1) {     // entries attached by a push round are dropped
+                int hit = -1;
+                for (int e = row_ptr[u], end = row_ptr[u + 1]; e < end; ++e) {
+                    // layers written in this round equal k, so "< k" only
+                    // sees vertices attached before the round
+                    const int t = layer[col[e]];
+                    if (t >= 0 && t < k) {
+                        hit = e;
+                        break;
+                    }
+                }
+                if (hit >= 0) {
+                    pi[u] = hit;
+                    layer[u] = k;
+                    got = true;
+                } else {
+                    left = true;
+                }
+            }
+        }
+        blist_push(bu, left, u);
+        blist_push(bf, got, u);
+    }
+    blist_flush(bu, ulist, ucnt);
+    blist_flush(bf, flist, fcnt);
+}
+
+__global__ __launch_bounds__(kWG) void k_conn_push(const int* __restrict__ rin_ptr,
+                                                   const int* __restrict__ rin_src,
+                                                   const int* __restrict__ rin_edge,
+                                                   const int* __restrict__ layer,
+                                                   int* __restrict__ cand,
+                                                   const int* __restrict__ fin, unsigned f_cnt,
+                                                   unsigned per, int* __restrict__ fout,
+                                                   unsigned* fout_cnt)
+{
+    __shared__ int buf[kListItems];
+    __shared__ unsigned nb, base;
+    __shared__ int maxlen;
+    if (threadIdx.x == 0) nb = 0;
+    BlockList bl{buf, &nb};
+    const int64_t i0 = (int64_t)blockIdx.x * per;
+    const int64_t i1 = i0 + per < f_cnt ? i0 + per : f_cnt;
+    for (int64_t ib = i0; ib < i1; ib += kWG) {
+        const int64_t i = ib + threadIdx.x;
+        int beg = 0, len = 0;
+        if (i < i1) {
+            const int x = fin[i];
+            beg = rin_ptr[x];
+            len = rin_ptr[x + 1] - beg;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) maxlen = 0;
+        __syncthreads();
+        if (len) atomicMax(&maxlen, len);
+        __syncthreads();
+        const int ml = maxlen;
+        for (int j = 0; j < ml; ++j) {
+            bool touch = false;
+            int u = 0;
+            if (j < len) {
+                u = rin_src[beg + j];
+                if (layer[u] == -1) touch = atomicMin(&cand[u], rin_edge[beg + j]) == INT32_MAX;
+            }
+            blist_push(bl, touch, u);
+            __syncthreads();
+            const unsigned cnt = nb;
+            if (cnt > kListItems - kWG) {           // block-uniform: flush
+                if (threadIdx.x == 0) base = atomicAdd(fout_cnt, cnt);
+                __syncthreads();
+                for (unsigned t = threadIdx.x; t < cnt; t += kWG) fout[base + t] = buf[t];
+                __syncthreads();
+                if (threadIdx.x == 0) nb = 0;
+                __syncthreads();
+            }
+        }
+    }
+    blist_flush(bl, fout, fout_cnt);
+}
+
+__global__ __launch_bounds__(kWG) void k_conn_push_fin(int k, int* __restrict__ pi,
+                                                       int* __restrict__ layer,
+                                                       int* __restrict__ cand,
+                                                       const int* __restrict__ flist,
+                                                       const unsigned* fcnt)
+{
+    const unsigned cnt = *fcnt;
+    for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < cnt; i += gridDim.x * kWG) {
+        const int u = flist[i];
+        pi[u] = cand[u];
+        layer[u] = k;
+        cand[u] = INT32_MAX;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse CSR (in-edges with their source and CSR position), built once per
+// solve when the rebuild needs push rounds
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_rev_count(int n, const int* __restrict__ row_ptr,
+                                                   const int* __restrict__ col,
+                                                   unsigned* __restrict__ deg)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x; e < row_ptr[n];
+         e += (int64_t)gridDim.x * kWG)
+        atomicAdd(&deg[col[e]], 1u);
+}
+
+__global__ __launch_bounds__(kWG) void k_rev_fill(int n, const int* __restrict__ row_ptr,
+                                                  const int* __restrict__ col,
+                                                  unsigned* __restrict__ cursor,
+                                                  int* __restrict__ rin_src,
+                                                  int* __restrict__ rin_edge)
+{
+    for (int64_t u = (int64_t)blockIdx.x * kWG + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * kWG) {
+        for (int e = row_ptr[u], end = row_ptr[u + 1]; e < end; ++e) {
+            const unsigned pos = atomicAdd(&cursor[col[e]], 1u);
+            rin_src[pos] = (int)u;
+            rin_edge[pos] = e;
+        }
+    }
+}
+
+// Exclusive prefix sum of len unsigned values (three launches: per-block
+// scans, a single-block scan of the block totals, and the offsets added).
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kWG * kScanItems;
+
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned x)
+{
+    const int lane = threadIdx.x & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+__global__ __launch_bounds__(kWG) void k_scan_a(int64_t len, const unsigned* __restrict__ in,
+                                                unsigned* __restrict__ out,
+                                                unsigned* __restrict__ tot)
+{
+    __shared__ unsigned wt[kWG / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    unsigned v[kScanItems];
+    unsigned sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const unsigned t = base + i < len ? in[base + i] : 0u;
+        v[i] = sum;
+        sum += t;
+    }
+    const unsigned incl = wave_incl_scan(sum);
+    if ((threadIdx.x & 63) == 63) wt[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    unsigned wbase = 0;
+    for (int wv = 0; wv < (int)(threadIdx.x >> 6); ++wv) wbase += wt[wv];
+    const unsigned excl = wbase + incl - sum;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < len) out[base + i] = v[i] + excl;
+    if (threadIdx.x == kWG - 1) tot[blockIdx.x] = wbase + incl;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_b(unsigned nb, unsigned* __restrict__ tot)
+{
+    __shared__ unsigned wt[16];
+    __shared__ unsigned carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (unsigned b0 = 0; b0 < nb; b0 += 1024) {
+        const unsigned i = b0 + threadIdx.x;
+        const unsigned x = i < nb ? tot[i] : 0u;
+        const unsigned incl = wave_incl_scan(x);
+        if ((threadIdx.x & 63) == 63) wt[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        unsigned wbase = 0;
+        for (int wv = 0; wv < (int)(threadIdx.x >> 6); ++wv) wbase += wt[wv];
+        const unsigned excl = carry + wbase + incl - x;
+        if (i < nb) tot[i] = excl;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = excl + x;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_scan_c(int64_t len, unsigned* __restrict__ out,
+                                                const unsigned* __restrict__ tot)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kWG)
+        out[i] += tot[i / kScanBlock];
+}
+
+__global__ __launch_bounds__(kWG) void k_copy_u32(int64_t len, const unsigned* __restrict__ in,
+                                                  unsigned* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kWG)
+        out[i] = in[i];
+}
+
+__global__ __launch_bounds__(kWG) void k_fill_u32(int64_t len, unsigned* __restrict__ p,
+                                                  unsigned v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kWG)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// values: pointer jumping toward the source over the policy tree cut at s.
+// Entry: D = sum of (L*w - W) over the first H edges of v's path, J = the
+// vertex reached.  A vertex is finished once J == s.
+// ---------------------------------------------------------------------------
+template <typename WT>
+__global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__ col,
+                                                  const int* __restrict__ pi,
+                                                  const WT* __restrict__ w, int neg, int s,
+                                                  long long W, long long L,
+                                                  int* __restrict__ succ, Jmp* __restrict__ Q,
+                                                  Ctl* ctl)
+{
+    unsigned long long act = 0;
+    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kWG) {
+        Jmp q;
+        const int e = pi[v];
+        const int t = col[e];
+        succ[v] = t;
+        if (v == s) {
+            q.D = 0;
+            q.J = s;
+            q.H = 0;
+        } else {
+            q.D = L * wval(w, e, neg) - W;
+            q.J = t;
+            q.H = 1;
+            act += t != s;
+        }
+        Q[v] = q;
+    }
+    act = block_sum_u64(act);
+    if (threadIdx.x == 0 && act) atomicAdd(&ctl->active, (unsigned)act);
+}
+
+__global__ __launch_bounds__(kWG) void k_val_round(int n, int s, const Jmp* __restrict__ Qin,
+                                                   Jmp* __restrict__ Qout, unsigned* active)
+{
+    unsigned long long act = 0;
+    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kWG) {
+        Jmp q = Qin[v];
+        if (q.J != s) {
+            const Jmp r = Qin[q.J];
+            long long d;
+            if (__builtin_add_overflow(q.D, r.D, &d)) {
+                d = 0;
+                q.H |= kHopOverflow;
+            }
+            q.D = d;
+            q.J = r.J;
+            q.H = ((q.H & ~kHopOverflow) + (r.H & ~kHopOverflow)) | ((q.H | r.H) & kHopOverflow);
+            act += q.J != s;
+        }
+        Qout[v] = q;
+    }
+    act = block_sum_u64(act);
+    if (threadIdx.x == 0 && act) atomicAdd(active, (unsigned)act);
+}
+
+__global__ __launch_bounds__(kWG) void k_val_final(int n, const Jmp* __restrict__ Q,
+                                                   long long* __restrict__ V, Ctl* ctl)
+{
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    unsigned bad = 0;
+    if (v < n) {
+        const Jmp q = Q[v];
+        V[v] = q.D;
+        if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
+    }
+    if (__ballot(bad != 0) && (threadIdx.x & 63) == 0) atomicOr(&ctl->overflow, 1u);
+}
+
+// Cycle C listed from the source: vertex c_j (j steps after s) is H = L - j
+// hops before s on the tree cut at s.
+__global__ __launch_bounds__(kWG) void k_cycle_list(int n, int s, long long L,
+                                                    const unsigned char* __restrict__ onC,
+                                                    const int* __restrict__ pi,
+                                                    const Jmp* __restrict__ Q,
+                                                    int* __restrict__ out)
+{
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v >= n || !onC[v]) return;
+    const long long j = v == s ? 0 : L - (long long)(Q[v].H & ~kHopOverflow);
+    if (j >= 0 && j < L) out[j] = pi[v];
+}
+
+__global__ void k_ctl_clear(Ctl* ctl, unsigned what)
+{
+    if (threadIdx.x != 0) return;
+    if (what & kClrChanged) {
+        ctl->changed = 0;
+        ctl->cbroken = 0;
+        ctl->tight = 0;
+    }
+    if (what & kClrCount) {
+        ctl->ncyc = 0;
+        ctl->ucnt[0] = ctl->ucnt[1] = 0;
+        ctl->fcnt[0] = ctl->fcnt[1] = 0;
+        ctl->active = 0;
+        ctl->active2 = 0;
+    }
+    if (what & kClrAll) {
+        ctl->err = 0;
+        ctl->maxabsw = 0;
+        ctl->overflow = 0;
+    }
+}
+
+__global__ void k_zero2(unsigned* a, unsigned* b)
+{
+    if (threadIdx.x == 0) {
+        *a = 0;
+        *b = 0;
+    }
+}
+
+__global__ void k_ctl_set(Ctl* ctl, int s, long long W, long long L)
+{
+    if (threadIdx.x != 0) return;
+    ctl->s = s;
+    ctl->W = W;
+    ctl->L = L;
+}
+
+__global__ __launch_bounds__(kWG) void k_fill_u8(unsigned char* p, int64_t n, unsigned char v)
+{
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kWG - 1) / kWG); }
+
+// Grid of a grid-stride kernel: enough blocks to fill the chip, few enough
+// that per-block counter atomics stay cheap.
+static inline unsigned stride_grid(int64_t n)
+{
+    const unsigned b = blocks_for(n);
+    return b < 2048 ? b : 2048;
+}
+
+template <typename WT>
+static void launch_sweep_t(const SweepArgs& a, const void* w, int G, bool first, bool tie,
+                           unsigned grid, hipStream_t st)
+{
+    const WT* ww = (const WT*)w;
+#define OCM_SWEEP_CASE(GG)                                                                        \
+    case GG:                                                                                      \
+        if (tie) k_sweep<GG, WT, false, true><<<grid, kWG, 0, st>>>(a, ww);                       \
+        else if (first) k_sweep<GG, WT, true, false><<<grid, kWG, 0, st>>>(a, ww);                \
+        else k_sweep<GG, WT, false, false><<<grid, kWG, 0, st>>>(a, ww);                          \
+        break;
+    switch (G) {
+        OCM_SWEEP_CASE(1)
+        OCM_SWEEP_CASE(2)
+        OCM_SWEEP_CASE(4)
+        OCM_SWEEP_CASE(8)
+        OCM_SWEEP_CASE(16)
+        OCM_SWEEP_CASE(32)
+        OCM_SWEEP_CASE(64)
+        default: break;
+    }
+#undef OCM_SWEEP_CASE
+}
+
+void launch_validate(int n, int m, const int* row_ptr, const int* col, const void* w, int wtype,
+                     int check_csr, Ctl* ctl, hipStream_t st)
+{
+    const int64_t total = n > m ? n : m;
+    const unsigned grid = stride_grid(total);
+    if (wtype == kWI64)
+        k_validate<long long><<<grid, kWG, 0, st>>>(n, m, row_ptr, col, (const long long*)w,
+                                                    check_csr, ctl);
+    else
+        k_validate<int><<<grid, kWG, 0, st>>>(n, m, row_ptr, col, (const int*)w, check_csr, ctl);
+}
+
+void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool first, bool tie,
+                  unsigned grid, hipStream_t st)
+{
+    if (wtype == kWI64) launch_sweep_t<long long>(a, w, G, first, tie, grid, st);
+    else launch_sweep_t<int>(a, w, G, first, tie, grid, st);
+}
+
+void launch_pj_init(int n, const int* col, const int* pi, int* succ, unsigned long long* P,
+                    unsigned char* onc, hipStream_t st)
+{
+    k_pj_init<<<blocks_for(n), kWG, 0, st>>>(n, col, pi, succ, P, onc);
+}
+
+void launch_pj_round(int n, const unsigned long long* Pin, unsigned long long* Pout, hipStream_t st)
+{
+    k_pj_round<<<blocks_for(n), kWG, 0, st>>>(n, Pin, Pout);
+}
+
+void launch_pj_final(int n, const unsigned long long* P, int* rep, unsigned char* onc,
+                     hipStream_t st)
+{
+    k_pj_final<<<blocks_for(n), kWG, 0, st>>>(n, P, rep, onc);
+}
+
+void launch_cyc_zero(int n, const int* rep, const unsigned char* onc, long long* wsum,
+                     unsigned* lcnt, int* cyc_list, Ctl* ctl, hipStream_t st)
+{
+    k_cyc_zero<<<blocks_for(n), kWG, 0, st>>>(n, rep, onc, wsum, lcnt, cyc_list, ctl);
+}
+
+void launch_cyc_sum(int n, const int* rep, const unsigned char* onc, const int* pi, const void* w,
+                    int wtype, int neg, long long* wsum, unsigned* lcnt, hipStream_t st)
+{
+    if (wtype == kWI64)
+        k_cyc_sum<long long><<<blocks_for(n), kWG, 0, st>>>(n, rep, onc, pi, (const long long*)w,
+                                                            neg, wsum, lcnt);
+    else
+        k_cyc_sum<int><<<blocks_for(n), kWG, 0, st>>>(n, rep, onc, pi, (const int*)w, neg, wsum,
+                                                      lcnt);
+}
+
+void launch_select(const int* cyc_list, const long long* wsum, const unsigned* lcnt, Ctl* ctl,
+                   hipStream_t st)
+{
+    k_select<<<1, 1024, 0, st>>>(cyc_list, wsum, lcnt, ctl);
+}
+
+// Items per block for list-producing kernels: spread over about 2048 blocks,
+// at most kListItems so the LDS buffer cannot overflow.
+static unsigned list_per_block(int64_t items)
+{
+    int64_t per = (items + 2047) / 2048;
+    per = (per + kWG - 1) / kWG * kWG;
+    if (per < kWG) per = kWG;
+    if (per > kListItems) per = kListItems;
+    return (unsigned)per;
+}
+
+void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, int* layer,
+                      unsigned char* onC, int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt,
+                      hipStream_t st)
+{
+    const unsigned per = list_per_block(n);
+    const unsigned grid = (unsigned)(((int64_t)n + per - 1) / per);
+    k_conn_init<<<grid, kWG, 0, st>>>(n, rep, onc, s, per, layer, onC, ulist, ucnt, flist, fcnt);
+}
+
+void launch_conn_pull(int k, const int* row_ptr, const int* col, int* layer, int* pi,
+                      const int* in_list, unsigned in_cnt, int* ulist, unsigned* ucnt, int* flist,
+                      unsigned* fcnt, hipStream_t st)
+{
+    if (in_cnt == 0) return;
+    const unsigned per = list_per_block(in_cnt);
+    const unsigned grid = (unsigned)(((int64_t)in_cnt + per - 1) / per);
+    k_conn_pull<<<grid, kWG, 0, st>>>(k, row_ptr, col, layer, pi, in_list, in_cnt, per, ulist,
+                                      ucnt, flist, fcnt);
+}
+
+void launch_conn_push(int k, const int* rin_ptr, const int* rin_src, const int* rin_edge,
+                      int* layer, int* pi, int* cand, const int* fin, unsigned f_cnt, int* fout,
+                      unsigned* fout_cnt, hipStream_t st)
+{
+    if (f_cnt == 0) return;
+    const unsigned per = list_per_block(f_cnt);
+    const unsigned grid = (unsigned)(((int64_t)f_cnt + per - 1) / per);
+    k_conn_push<<<grid, kWG, 0, st>>>(rin_ptr, rin_src, rin_edge, layer, cand, fin, f_cnt, per,
+                                      fout, fout_cnt);
+    k_conn_push_fin<<<2048, kWG, 0, st>>>(k, pi, layer, cand, fout, fout_cnt);
+}
+
+void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
+                      unsigned* tot, int* rin_ptr, int* rin_src, int* rin_edge, int* cand,
+                      hipStream_t st)
+{
+    const int64_t len = (int64_t)n + 1;
+    k_fill_u32<<<stride_grid(len), kWG, 0, st>>>(len, deg, 0u);
+    k_rev_count<<<stride_grid(m), kWG, 0, st>>>(n, row_ptr, col, deg);
+    const unsigned nb = (unsigned)((len + kScanBlock - 1) / kScanBlock);
+    k_scan_a<<<nb, kWG, 0, st>>>(len, deg, (unsigned*)rin_ptr, tot);
+    k_scan_b<<<1, 1024, 0, st>>>(nb, tot);
+    k_scan_c<<<stride_grid(len), kWG, 0, st>>>(len, (unsigned*)rin_ptr, tot);
+    k_copy_u32<<<stride_grid(n), kWG, 0, st>>>(n, (const unsigned*)rin_ptr, deg);
+    k_rev_fill<<<stride_grid(n), kWG, 0, st>>>(n, row_ptr, col, deg, rin_src, rin_edge);
+    k_fill_u32<<<stride_grid(n), kWG, 0, st>>>(n, (unsigned*)cand, (unsigned)INT32_MAX);
+}
+
+void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
+                     int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl, hipStream_t st)
+{
+    if (wtype == kWI64)
+        k_val_init<long long><<<stride_grid(n), kWG, 0, st>>>(n, col, pi, (const long long*)w, neg,
+                                                             s, W, L, succ, Q, ctl);
+    else
+        k_val_init<int><<<stride_grid(n), kWG, 0, st>>>(n, col, pi, (const int*)w, neg, s, W, L,
+                                                       succ, Q, ctl);
+}
+
+void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st)
+{
+    k_val_round<<<stride_grid(n), kWG, 0, st>>>(n, s, Qin, Qout, active);
+}
+
+void launch_val_final(int n, const Jmp* Q, long long* V, Ctl* ctl, hipStream_t st)
+{
+    k_val_final<<<blocks_for(n), kWG, 0, st>>>(n, Q, V, ctl);
+}
+
+void launch_cycle_list(int n, int s, long long L, const unsigned char* onC, const int* pi,
+                       const Jmp* Q, int* out, hipStream_t st)
+{
+    k_cycle_list<<<blocks_for(n), kWG, 0, st>>>(n, s, L, onC, pi, Q, out);
+}
+
+void launch_ctl_clear(Ctl* ctl, unsigned what, hipStream_t st)
+{
+    k_ctl_clear<<<1, 64, 0, st>>>(ctl, what);
+}
+
+void launch_zero2(unsigned* a, unsigned* b, hipStream_t st)
+{
+    k_zero2<<<1, 64, 0, st>>>(a, b);
+}
+
+void launch_ctl_set(Ctl* ctl, int s, long long W, long long L, hipStream_t st)
+{
+    k_ctl_set<<<1, 64, 0, st>>>(ctl, s, W, L);
+}
+
+void launch_fill_u8(unsigned char* p, int64_t n, unsigned char v, hipStream_t st)
+{
+    if (n > 0) k_fill_u8<<<blocks_for(n), kWG, 0, st>>>(p, n, v);
+}
+
+}  // namespace ocm

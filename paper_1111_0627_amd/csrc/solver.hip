@@ -1,0 +1,672 @@
+// Host driver of the exact optimal-cycle-mean solver: the loop of Alg. 3
+// (Howard's policy iteration, Alg. 2) over the device phases, behind the
+// C ABI declared in include/ocm.h.
+#include "ocm.h"
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using ocm::Ctl;
+using ocm::Jmp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ocm_status fail(ocm_status s, const char* what)
+{
+    g_last_error = what;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            char b_[256];                                                              \
+            snprintf(b_, sizeof b_, "%s: %s", #expr, hipGetErrorString(e_));           \
+            return fail(OCM_E_HIP, b_);                                                \
+        }                                                                              \
+    } while (0)
+
+#define OCM_TRY(expr)                                                                  \
+    do {                                                                               \
+        ocm_status s_ = (expr);                                                        \
+        if (s_ != OCM_OK) return s_;                                                   \
+    } while (0)
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Hard bound on policy iterations when the caller sets none.
+constexpr int kIterCap = 1 << 20;
+
+// Workspace carved into the solver's device arrays.
+struct Ws {
+    Ctl* ctl;
+    long long* V;        // values scaled by L
+    int* pi;             // policy: CSR position of each vertex's edge
+    int* succ;           // policy successor
+    Jmp* Q[2];           // pointer-jumping buffers (values; cycles alias them)
+    int* rep;            // smallest vertex of the reached cycle
+    unsigned char* onc;  // on a policy-graph cycle
+    unsigned char* onC;  // on the chosen cycle C
+    int* layer;          // connect round of each vertex
+    int* list[2];        // connect: unattached vertices
+    int* flist[2];       // connect: frontier (last attached layer)
+    unsigned* rdeg;      // reverse CSR: in-degree, then fill cursor (n+1)
+    unsigned* stot;      // prefix-sum block totals
+    int* rin_ptr;        // reverse CSR offsets (n+1)
+    int* rin_src;        // reverse CSR: source of each in-edge (m)
+    int* rin_edge;       // reverse CSR: CSR position of each in-edge (m)
+    int* cand;           // push rounds: best edge offered so far
+    long long* wsum;     // per-cycle weight sums, keyed by rep
+    unsigned* lcnt;      // per-cycle lengths, keyed by rep
+    int* cyc;            // cycle heads
+    size_t total;
+};
+
+Ws carve(void* base, int64_t n, int64_t m)
+{
+    char* b = (char*)base;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        size_t o = off;
+        off += align_up(bytes);
+        return b ? (void*)(b + o) : nullptr;
+    };
+    Ws w;
+    const size_t N = (size_t)n;
+    w.ctl = (Ctl*)take(sizeof(Ctl));
+    w.V = (long long*)take(8 * N);
+    w.pi = (int*)take(4 * N);
+    w.succ = (int*)take(4 * N);
+    w.Q[0] = (Jmp*)take(sizeof(Jmp) * N);
+    w.Q[1] = (Jmp*)take(sizeof(Jmp) * N);
+    w.rep = (int*)take(4 * N);
+    w.onc = (unsigned char*)take(N);
+    w.onC = (unsigned char*)take(N);
+    w.layer = (int*)take(4 * N);
+    w.list[0] = (int*)take(4 * N);
+    w.list[1] = (int*)take(4 * N);
+    w.flist[0] = (int*)take(4 * N);
+    w.flist[1] = (int*)take(4 * N);
+    const size_t M = (size_t)m;
+    w.rdeg = (unsigned*)take(4 * (N + 1));
+    w.stot = (unsigned*)take(4 * ((N + 1) / 2048 + 2));
+    w.rin_ptr = (int*)take(4 * (N + 1));
+    w.rin_src = (int*)take(4 * M);
+    w.rin_edge = (int*)take(4 * M);
+    w.cand = (int*)take(4 * N);
+    w.wsum = (long long*)take(8 * N);
+    w.lcnt = (unsigned*)take(4 * N);
+    w.cyc = (int*)take(4 * N);
+    w.total = off;
+    return w;
+}
+
+// Per-phase timing with hipEvents, when requested.
+struct Prof {
+    ocm_profile* out = nullptr;
+    hipStream_t st = nullptr;
+    struct Rec {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    int open = -1;
+    void begin(int ph)
+    {
+        if (!out) return;
+        Rec r{ph, nullptr, nullptr};
+        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+        (void)hipEventRecord(r.a, st);
+        recs.push_back(r);
+        open = (int)recs.size() - 1;
+    }
+    void end()
+    {
+        if (!out || open < 0) return;
+        (void)hipEventRecord(recs[open].b, st);
+        open = -1;
+    }
+    void finish()
+    {
+        if (!out) return;
+        for (auto& r : recs) {
+            float ms = 0.f;
+            if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                out->ms[r.phase] += ms;
+                out->launches[r.phase] += 1;
+            }
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        recs.clear();
+    }
+};
+
+struct Ctx {
+    int n, m;
+    const int* row_ptr;
+    const int* col;
+    const void* w;
+    int wtype;
+    int neg;
+    hipStream_t st;
+    Ws ws;
+    Ctl h;               // host copy of the control block
+    Prof prof;
+    int G;               // lanes per vertex in the sweep
+    unsigned sweep_grid;
+    int jump_rounds = 0;
+    int connect_rounds = 0;
+    int connect_mode = 0;   // 0 auto, 1 pull only, 2 push only
+    bool rev_built = false;
+};
+
+// Push rounds pay off once many vertices are unattached and the frontier is
+// small next to them; below this size pull rounds are cheap anyway.
+constexpr unsigned kPushMinUnattached = 1u << 16;
+
+ocm_status read_ctl(Ctx& c)
+{
+    HIP_TRY(hipMemcpyAsync(&c.h, c.ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    return OCM_OK;
+}
+
+int choose_lanes(int64_t n, int64_t m, int schedule)
+{
+    if (schedule > 0) return schedule;
+    const double d = (double)m / (double)n;
+    int G = 1;
+    while (G < 64 && G < d) G <<= 1;
+    return G;
+}
+
+unsigned sweep_grid(int64_t n, int G)
+{
+    const int64_t vpb = ocm::kWG / G;
+    int64_t g = (n + vpb - 1) / vpb;
+    if (g > 8192) g = 8192;
+    if (g >= 8) g &= ~int64_t(7);
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+bool valid_lanes(int G) { return G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32 || G == 64; }
+
+ocm_status check_graph(const ocm_graph* g)
+{
+    if (!g) return fail(OCM_E_INVALID_ARG, "graph is null");
+    if (g->n < 1 || g->m < 1) return fail(OCM_E_INVALID_ARG, "n and m must be >= 1");
+    if (g->n >= (int64_t(1) << 31) - 1 || g->m >= (int64_t(1) << 31))
+        return fail(OCM_E_INVALID_ARG, "n and m must stay below 2^31");
+    if (!g->row_ptr || !g->col || !g->w) return fail(OCM_E_INVALID_ARG, "null graph array");
+    if (g->wtype != OCM_W_I32 && g->wtype != OCM_W_I64) return fail(OCM_E_INVALID_ARG, "bad wtype");
+    return OCM_OK;
+}
+
+ocm_status setup(Ctx& c, const ocm_graph* g, int neg, void* ws, size_t ws_bytes, void* stream,
+                 ocm_profile* prof)
+{
+    OCM_TRY(check_graph(g));
+    c.n = (int)g->n;
+    c.m = (int)g->m;
+    c.row_ptr = g->row_ptr;
+    c.col = g->col;
+    c.w = g->w;
+    c.wtype = g->wtype;
+    c.neg = neg;
+    c.st = (hipStream_t)stream;
+    c.ws = carve(nullptr, g->n, g->m);
+    if (!ws || ws_bytes < c.ws.total) return fail(OCM_E_WORKSPACE, "workspace missing or too small");
+    c.ws = carve(ws, g->n, g->m);
+    c.prof.out = prof;
+    c.prof.st = c.st;
+    memset(&c.h, 0, sizeof c.h);
+    return OCM_OK;
+}
+
+// Validation kernel, then the bound that keeps every value inside int64:
+// |L*w - W| <= 2 n max|w| must stay below 2^62.
+ocm_status validate(Ctx& c, int check_csr)
+{
+    ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrAll | ocm::kClrCount | ocm::kClrChanged, c.st);
+    c.prof.begin(OCM_PH_VALIDATE);
+    ocm::launch_validate(c.n, c.m, c.row_ptr, c.col, c.w, c.wtype, check_csr, c.ws.ctl, c.st);
+    c.prof.end();
+    HIP_TRY(hipGetLastError());
+    OCM_TRY(read_ctl(c));
+    if (c.h.err & ocm::kErrBadCsr) return fail(OCM_E_BAD_CSR, "malformed CSR");
+    if (c.h.err & ocm::kErrNoOut) return fail(OCM_E_NO_OUT_EDGE, "a vertex has no out-edge");
+    const unsigned __int128 bound = (unsigned __int128)2 * (unsigned)c.n * c.h.maxabsw;
+    if (bound >= ((unsigned __int128)1 << 62)) return fail(OCM_E_OVERFLOW, "weights too large for int64 values");
+    return OCM_OK;
+}
+
+// Policy improvement sweep; afterwards c.h.changed / cbroken are current.
+ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long long W, long long L,
+                       int* pi, const unsigned char* onC)
+{
+    ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrChanged, c.st);
+    ocm::SweepArgs a;
+    a.n = c.n;
+    a.neg = c.neg;
+    a.row_ptr = c.row_ptr;
+    a.col = c.col;
+    a.V = V;
+    a.W = W;
+    a.L = L;
+    a.pi = pi;
+    a.onC = onC;
+    a.ctl = c.ws.ctl;
+    c.prof.begin(tie ? OCM_PH_RESULT : OCM_PH_SWEEP);
+    ocm::launch_sweep(a, c.w, c.wtype, c.G, first, tie, c.sweep_grid, c.st);
+    c.prof.end();
+    HIP_TRY(hipGetLastError());
+    return read_ctl(c);
+}
+
+// Cycles of the policy graph: rep and on_cycle for every vertex.
+ocm_status phase_cycles(Ctx& c, const int* pi, int* rep, unsigned char* onc)
+{
+    auto* P0 = (unsigned long long*)c.ws.Q[0];
+    auto* P1 = (unsigned long long*)c.ws.Q[1];
+    int K = 0;
+    while ((int64_t(1) << K) < c.n) ++K;
+    c.prof.begin(OCM_PH_CYCLES);
+    ocm::launch_pj_init(c.n, c.col, pi, c.ws.succ, P0, onc, c.st);
+    for (int k = 0; k < K; ++k) {
+        ocm::launch_pj_round(c.n, P0, P1, c.st);
+        std::swap(P0, P1);
+    }
+    ocm::launch_pj_final(c.n, P0, rep, onc, c.st);
+    c.prof.end();
+    c.jump_rounds += K;
+    HIP_TRY(hipGetLastError());
+    return OCM_OK;
+}
+
+// Minimum-mean cycle in the order (W/L, rep); c.h gets s, W, L, ncyc.
+ocm_status phase_select(Ctx& c, const int* pi, const int* rep, const unsigned char* onc)
+{
+    ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrCount, c.st);
+    c.prof.begin(OCM_PH_SELECT);
+    ocm::launch_cyc_zero(c.n, rep, onc, c.ws.wsum, c.ws.lcnt, c.ws.cyc, c.ws.ctl, c.st);
+    ocm::launch_cyc_sum(c.n, rep, onc, pi, c.w, c.wtype, c.neg, c.ws.wsum, c.ws.lcnt, c.st);
+    ocm::launch_select(c.ws.cyc, c.ws.wsum, c.ws.lcnt, c.ws.ctl, c.st);
+    c.prof.end();
+    HIP_TRY(hipGetLastError());
+    OCM_TRY(read_ctl(c));
+    if (c.h.ncyc == 0 || c.h.s < 0) return fail(OCM_E_HIP, "no policy cycle found");
+    return OCM_OK;
+}
+
+// Rebuild around C: component of C keeps pi, the rest attaches breadth-first.
+// Each round is a pull or a push round (same result, see k_conn_push).
+ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s, int* pi,
+                         int* layer, unsigned char* onC, int* rounds)
+{
+    Ws& w = c.ws;
+    ocm::launch_ctl_clear(w.ctl, ocm::kClrCount, c.st);
+    c.prof.begin(OCM_PH_CONNECT);
+    ocm::launch_conn_init(c.n, rep, onc, s, layer, onC, w.list[0], &w.ctl->ucnt[0], w.flist[0],
+                          &w.ctl->fcnt[0], c.st);
+    c.prof.end();
+    HIP_TRY(hipGetLastError());
+    OCM_TRY(read_ctl(c));
+    unsigned left = c.h.ucnt[0], ulen = left, front = c.h.fcnt[0];
+    int ua = 0, fa = 0, k = 0;
+    ocm_status rc = OCM_OK;
+    while (left > 0) {
+        ++k;
+        const int ub = ua ^ 1, fb = fa ^ 1;
+        bool push = false;
+        if (c.connect_mode == 2) push = front > 0;
+        else if (c.connect_mode == 0)
+            push = left >= kPushMinUnattached && (uint64_t)front * 4 < left;
+        if (push && !c.rev_built) {
+            c.prof.begin(OCM_PH_CONNECT);
+            ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr,
+                                  w.rin_src, w.rin_edge, w.cand, c.st);
+            c.prof.end();
+            HIP_TRY(hipGetLastError());
+            c.rev_built = true;
+        }
+        ocm::launch_zero2(&w.ctl->ucnt[ub], &w.ctl->fcnt[fb], c.st);
+        c.prof.begin(OCM_PH_CONNECT);
+        if (push)
+            ocm::launch_conn_push(k, w.rin_ptr, w.rin_src, w.rin_edge, layer, pi, w.cand,
+                                  w.flist[fa], front, w.flist[fb], &w.ctl->fcnt[fb], c.st);
+        else
+            ocm::launch_conn_pull(k, c.row_ptr, c.col, layer, pi, w.list[ua], ulen, w.list[ub],
+                                  &w.ctl->ucnt[ub], w.flist[fb], &w.ctl->fcnt[fb], c.st);
+        c.prof.end();
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        const unsigned got = c.h.fcnt[fb];
+        if (got == 0) {
+            rc = fail(OCM_E_NOT_STRONGLY_CONNECTED, "some vertex cannot reach the chosen cycle");
+            break;
+        }
+        if (push) {
+            left -= got;
+        } else {
+            ulen = c.h.ucnt[ub];
+            left = ulen;
+            ua = ub;
+        }
+        front = got;
+        fa = fb;
+    }
+    if (rounds) *rounds = k;
+    c.connect_rounds += k;
+    return rc;
+}
+
+// Values by pointer jumping toward s.  With `probe` set the policy graph may
+// hold vertices that never reach s; the phase then stops as soon as a round
+// finishes no vertex and reports *stalled = true (no values written).
+// Otherwise every vertex must reach s.  *qfinal is the buffer holding the
+// final entries (their hop counts list C).
+ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, long long* V,
+                        bool probe, bool* stalled, int* rounds, int* qfinal)
+{
+    if (stalled) *stalled = false;
+    ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrCount, c.st);
+    const int ph = probe ? OCM_PH_FAST : OCM_PH_VALUES;
+    c.prof.begin(ph);
+    ocm::launch_val_init(c.n, c.col, pi, c.w, c.wtype, c.neg, s, W, L, c.ws.succ, c.ws.Q[0],
+                         c.ws.ctl, c.st);
+    c.prof.end();
+    HIP_TRY(hipGetLastError());
+    OCM_TRY(read_ctl(c));
+    unsigned act = c.h.active;
+    int a = 0, k = 0;
+    while (act > 0) {
+        if (k > 64) return fail(OCM_E_HIP, "value propagation did not converge");
+        ++k;
+        const int b = a ^ 1;
+        HIP_TRY(hipMemsetAsync(&c.ws.ctl->active2, 0, sizeof(unsigned), c.st));
+        c.prof.begin(ph);
+        ocm::launch_val_round(c.n, s, c.ws.Q[a], c.ws.Q[b], &c.ws.ctl->active2, c.st);
+        c.prof.end();
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        const unsigned now = c.h.active2;
+        a = b;
+        if (now == act) {
+            c.jump_rounds += k;
+            if (rounds) *rounds = k;
+            if (probe) {
+                if (stalled) *stalled = true;
+                return OCM_OK;
+            }
+            return fail(OCM_E_NOT_STRONGLY_CONNECTED, "policy graph does not reach the source");
+        }
+        act = now;
+    }
+    c.jump_rounds += k;
+    if (rounds) *rounds = k;
+    c.prof.begin(ph);
+    ocm::launch_val_final(c.n, c.ws.Q[a], V, c.ws.ctl, c.st);
+    c.prof.end();
+    HIP_TRY(hipGetLastError());
+    OCM_TRY(read_ctl(c));
+    if (c.h.overflow) return fail(OCM_E_OVERFLOW, "a value left [-2^62, 2^62]");
+    if (qfinal) *qfinal = a;
+    return OCM_OK;
+}
+
+long long gcd_ll(long long a, long long b)
+{
+    if (a < 0) a = -a;
+    if (b < 0) b = -b;
+    while (b) {
+        long long t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t ws_bytes,
+                 int32_t* cycle_edges, int64_t cap, ocm_result* out, void* stream, int neg)
+{
+    if (!out) return fail(OCM_E_INVALID_ARG, "result pointer is null");
+    memset(out, 0, sizeof *out);
+    ocm_options o;
+    if (o_in) o = *o_in;
+    else ocm_default_options(&o);
+    if (o.profile) memset(o.profile, 0, sizeof *o.profile);
+    Ctx c;
+    OCM_TRY(setup(c, g, neg, wsp, ws_bytes, stream, o.profile));
+    if (cap > 0 && !cycle_edges) return fail(OCM_E_INVALID_ARG, "cycle_edges is null");
+    c.G = choose_lanes(c.n, c.m, o.schedule);
+    if (!valid_lanes(c.G)) return fail(OCM_E_INVALID_ARG, "schedule must be a power of two <= 64");
+    c.sweep_grid = sweep_grid(c.n, c.G);
+    c.connect_mode = o.connect_mode;
+    if (c.connect_mode < 0 || c.connect_mode > 2) return fail(OCM_E_INVALID_ARG, "bad connect_mode");
+
+    ocm_status rc = validate(c, o.validate != 0);
+    if (rc != OCM_OK) { c.prof.finish(); return rc; }
+
+    Ws& w = c.ws;
+    int iter = 0, fast = 0, qf = 0;
+    bool have_c = false;
+    int s = -1;
+    long long W = 0, L = 1;
+    for (;;) {
+        rc = phase_sweep(c, iter == 0, false, w.V, W, L, w.pi, have_c ? w.onC : nullptr);
+        if (rc != OCM_OK) break;
+        ++iter;
+        if (iter >= 2 && c.h.changed == 0) break;            // no strict improvement left
+        if ((o.max_iters > 0 && iter >= o.max_iters) || iter >= kIterCap) {
+            rc = fail(OCM_E_NOT_CONVERGED, "max_iters reached");
+            break;
+        }
+        if (o.fast_path && have_c && !c.h.cbroken) {
+            // C is still a cycle of the new policy.  If every vertex still
+            // reaches s, C is the policy graph's only cycle: the cycle, select
+            // and connect phases would change nothing, so only values remain.
+            bool stalled = false;
+            rc = phase_values(c, w.pi, s, W, L, w.V, true, &stalled, nullptr, &qf);
+            if (rc != OCM_OK) break;
+            if (!stalled) {
+                ++fast;
+                continue;
+            }
+        }
+        rc = phase_cycles(c, w.pi, w.rep, w.onc);
+        if (rc != OCM_OK) break;
+        rc = phase_select(c, w.pi, w.rep, w.onc);
+        if (rc != OCM_OK) break;
+        s = c.h.s;
+        W = c.h.W;
+        L = c.h.L;
+        rc = phase_connect(c, w.rep, w.onc, s, w.pi, w.layer, w.onC, nullptr);
+        if (rc != OCM_OK) break;
+        rc = phase_values(c, w.pi, s, W, L, w.V, false, nullptr, nullptr, &qf);
+        if (rc != OCM_OK) break;
+        have_c = true;
+    }
+    out->iterations = iter;
+    out->connect_rounds = c.connect_rounds;
+    out->jump_rounds = c.jump_rounds;
+    out->fast_iters = fast;
+    if (rc != OCM_OK) {
+        c.prof.finish();
+        return rc;
+    }
+    const long long gg = gcd_ll(W, L);
+    out->p = (neg ? -W : W) / gg;
+    out->q = L / gg;
+    out->W = neg ? -W : W;
+    out->L = L;
+    out->source = s;
+    out->cycle_len = L;
+    if (cap < L) {
+        c.prof.finish();
+        return fail(OCM_E_CAPACITY, "cycle_cap smaller than the critical cycle");
+    }
+    c.prof.begin(OCM_PH_RESULT);
+    ocm::launch_cycle_list(c.n, s, L, w.onC, w.pi, w.Q[qf], cycle_edges, c.st);
+    c.prof.end();
+    HIP_TRY(hipGetLastError());
+    if (o.tie_check) {
+        rc = phase_sweep(c, false, true, w.V, W, L, w.pi, nullptr);
+        if (rc != OCM_OK) {
+            c.prof.finish();
+            return rc;
+        }
+        out->tight_edges = (int64_t)c.h.tight;
+        if (c.h.tight > 0) out->flags |= OCM_F_TIGHT_EDGES | OCM_F_TIE_UNCHECKED;
+    } else {
+        out->flags |= OCM_F_TIE_UNCHECKED;
+        out->tight_edges = -1;
+    }
+    if (o.policy_out)
+        HIP_TRY(hipMemcpyAsync(o.policy_out, w.pi, 4 * (size_t)c.n, hipMemcpyDeviceToDevice, c.st));
+    if (o.potential_out)
+        HIP_TRY(hipMemcpyAsync(o.potential_out, w.V, 8 * (size_t)c.n, hipMemcpyDeviceToDevice, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    c.prof.finish();
+    return OCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ocm_default_options(ocm_options* o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->validate = 1;
+    o->tie_check = 1;
+    o->fast_path = 1;
+}
+
+size_t ocm_workspace_size(const ocm_graph* g, const ocm_options* o)
+{
+    (void)o;
+    if (check_graph(g) != OCM_OK) return 0;
+    return carve(nullptr, g->n, g->m).total;
+}
+
+ocm_status ocm_min(const ocm_graph* g, const ocm_options* o, void* ws, size_t ws_bytes,
+                   int32_t* cycle_edges, int64_t cycle_cap, ocm_result* out, void* stream)
+{
+    return solve(g, o, ws, ws_bytes, cycle_edges, cycle_cap, out, stream, 0);
+}
+
+ocm_status ocm_max(const ocm_graph* g, const ocm_options* o, void* ws, size_t ws_bytes,
+                   int32_t* cycle_edges, int64_t cycle_cap, ocm_result* out, void* stream)
+{
+    return solve(g, o, ws, ws_bytes, cycle_edges, cycle_cap, out, stream, 1);
+}
+
+ocm_status ocm_phase_sweep(const ocm_graph* g, int32_t neg, int32_t first, const int64_t* V,
+                           int64_t W, int64_t L, int32_t* pi, int32_t schedule, void* ws,
+                           size_t ws_bytes, int64_t* changed, void* stream)
+{
+    Ctx c;
+    OCM_TRY(setup(c, g, neg != 0, ws, ws_bytes, stream, nullptr));
+    if (!pi || !changed || (!first && !V)) return fail(OCM_E_INVALID_ARG, "null argument");
+    if (!first && L < 1) return fail(OCM_E_INVALID_ARG, "L must be >= 1");
+    c.G = choose_lanes(c.n, c.m, schedule);
+    if (!valid_lanes(c.G)) return fail(OCM_E_INVALID_ARG, "schedule must be a power of two <= 64");
+    c.sweep_grid = sweep_grid(c.n, c.G);
+    OCM_TRY(phase_sweep(c, first != 0, false, (const long long*)V, W, L, pi, nullptr));
+    *changed = (int64_t)c.h.changed;
+    return OCM_OK;
+}
+
+ocm_status ocm_phase_cycles(const ocm_graph* g, const int32_t* pi, int32_t* rep,
+                            uint8_t* on_cycle, void* ws, size_t ws_bytes, int64_t* ncycles,
+                            void* stream)
+{
+    Ctx c;
+    OCM_TRY(setup(c, g, 0, ws, ws_bytes, stream, nullptr));
+    if (!pi || !rep || !on_cycle) return fail(OCM_E_INVALID_ARG, "null argument");
+    OCM_TRY(phase_cycles(c, pi, rep, on_cycle));
+    if (ncycles) {
+        // count cycle heads with the select phase's first kernel
+        ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrCount, c.st);
+        ocm::launch_cyc_zero(c.n, rep, on_cycle, c.ws.wsum, c.ws.lcnt, c.ws.cyc, c.ws.ctl, c.st);
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        *ncycles = c.h.ncyc;
+    }
+    HIP_TRY(hipStreamSynchronize(c.st));
+    return OCM_OK;
+}
+
+ocm_status ocm_phase_select(const ocm_graph* g, int32_t neg, const int32_t* pi,
+                            const int32_t* rep, const uint8_t* on_cycle, void* ws,
+                            size_t ws_bytes, int32_t* s, int64_t* W, int64_t* L, void* stream)
+{
+    Ctx c;
+    OCM_TRY(setup(c, g, neg != 0, ws, ws_bytes, stream, nullptr));
+    if (!pi || !rep || !on_cycle || !s || !W || !L) return fail(OCM_E_INVALID_ARG, "null argument");
+    OCM_TRY(phase_select(c, pi, rep, on_cycle));
+    *s = c.h.s;
+    *W = c.h.W;
+    *L = c.h.L;
+    return OCM_OK;
+}
+
+ocm_status ocm_phase_connect(const ocm_graph* g, const int32_t* rep, int32_t s, int32_t* pi,
+                             int32_t* layer, void* ws, size_t ws_bytes, int32_t* rounds,
+                             void* stream)
+{
+    Ctx c;
+    OCM_TRY(setup(c, g, 0, ws, ws_bytes, stream, nullptr));
+    if (!rep || !pi || !layer) return fail(OCM_E_INVALID_ARG, "null argument");
+    if (s < 0 || s >= c.n) return fail(OCM_E_INVALID_ARG, "source out of range");
+    int r = 0;
+    ocm_status rc = phase_connect(c, rep, nullptr, s, pi, layer, nullptr, &r);
+    if (rounds) *rounds = r;
+    HIP_TRY(hipStreamSynchronize(c.st));
+    return rc;
+}
+
+ocm_status ocm_phase_values(const ocm_graph* g, int32_t neg, const int32_t* pi, int32_t s,
+                            int64_t W, int64_t L, int64_t* V, void* ws, size_t ws_bytes,
+                            int32_t* rounds, void* stream)
+{
+    Ctx c;
+    OCM_TRY(setup(c, g, neg != 0, ws, ws_bytes, stream, nullptr));
+    if (!pi || !V) return fail(OCM_E_INVALID_ARG, "null argument");
+    if (s < 0 || s >= c.n || L < 1) return fail(OCM_E_INVALID_ARG, "bad source or L");
+    int r = 0;
+    ocm_status rc = phase_values(c, pi, s, W, L, (long long*)V, false, nullptr, &r, nullptr);
+    if (rounds) *rounds = r;
+    HIP_TRY(hipStreamSynchronize(c.st));
+    return rc;
+}
+
+const char* ocm_status_string(ocm_status s)
+{
+    switch (s) {
+        case OCM_OK: return "ok";
+        case OCM_E_INVALID_ARG: return "invalid argument";
+        case OCM_E_BAD_CSR: return "malformed CSR";
+        case OCM_E_NO_OUT_EDGE: return "vertex without out-edge";
+        case OCM_E_NOT_STRONGLY_CONNECTED: return "graph not strongly connected";
+        case OCM_E_OVERFLOW: return "int64 overflow";
+        case OCM_E_CAPACITY: return "capacity too small";
+        case OCM_E_NOT_CONVERGED: return "not converged within max_iters";
+        case OCM_E_WORKSPACE: return "workspace missing or too small";
+        case OCM_E_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char* ocm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

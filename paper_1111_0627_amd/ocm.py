@@ -1,0 +1,305 @@
+"""Python binding of ``libocm.so`` (the C ABI of include/ocm.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of the library.  Tensors must be contiguous device tensors on the current
+GPU; calls are enqueued on torch's current stream.  There is no CPU fallback:
+if the library is missing every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from fractions import Fraction
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libocm.so")
+
+OCM_OK = 0
+OCM_E_INVALID_ARG = -1
+OCM_E_BAD_CSR = -2
+OCM_E_NO_OUT_EDGE = -3
+OCM_E_NOT_STRONGLY_CONNECTED = -4
+OCM_E_OVERFLOW = -5
+OCM_E_CAPACITY = -6
+OCM_E_NOT_CONVERGED = -7
+OCM_E_WORKSPACE = -8
+OCM_E_HIP = -9
+
+OCM_W_I32, OCM_W_I64 = 0, 1
+OCM_F_TIE, OCM_F_TIE_UNCHECKED, OCM_F_TIGHT_EDGES = 1, 2, 4
+
+PHASES = ("validate", "sweep", "cycles", "select", "connect", "values", "fast", "result")
+
+
+class OCMError(RuntimeError):
+    def __init__(self, status: int, message: str = ""):
+        super().__init__(f"ocm status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Graph(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("w", C.c_void_p), ("wtype", C.c_int32)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("p", C.c_int64), ("q", C.c_int64), ("cycle_len", C.c_int64),
+                ("source", C.c_int32), ("iterations", C.c_int32), ("flags", C.c_uint32),
+                ("connect_rounds", C.c_int32), ("jump_rounds", C.c_int32),
+                ("fast_iters", C.c_int32), ("W", C.c_int64), ("L", C.c_int64),
+                ("tight_edges", C.c_int64)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("ms", C.c_double * len(PHASES)), ("launches", C.c_int32 * len(PHASES))]
+
+    def as_dict(self):
+        return {p: (self.ms[i], self.launches[i]) for i, p in enumerate(PHASES)}
+
+
+class Options(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("validate", C.c_int32), ("schedule", C.c_int32),
+                ("tie_check", C.c_int32), ("fast_path", C.c_int32),
+                ("connect_mode", C.c_int32), ("policy_out", C.c_void_p), ("potential_out", C.c_void_p),
+                ("profile", C.POINTER(Profile))]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OCMError(OCM_E_HIP, f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1111_0627_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        G, O = C.POINTER(Graph), C.POINTER(Options)
+        L.ocm_default_options.argtypes = [O]
+        L.ocm_workspace_size.argtypes = [G, O]
+        L.ocm_workspace_size.restype = C.c_size_t
+        for f in (L.ocm_min, L.ocm_max):
+            f.argtypes = [G, O, P, C.c_size_t, P, i64, C.POINTER(_Result), P]
+            f.restype = C.c_int
+        L.ocm_phase_sweep.argtypes = [G, i32, i32, P, i64, i64, P, i32, P, C.c_size_t,
+                                      C.POINTER(i64), P]
+        L.ocm_phase_cycles.argtypes = [G, P, P, P, P, C.c_size_t, C.POINTER(i64), P]
+        L.ocm_phase_select.argtypes = [G, i32, P, P, P, P, C.c_size_t, C.POINTER(i32),
+                                       C.POINTER(i64), C.POINTER(i64), P]
+        L.ocm_phase_connect.argtypes = [G, P, i32, P, P, P, C.c_size_t, C.POINTER(i32), P]
+        L.ocm_phase_values.argtypes = [G, i32, P, i32, i64, i64, P, P, C.c_size_t,
+                                       C.POINTER(i32), P]
+        for f in (L.ocm_phase_sweep, L.ocm_phase_cycles, L.ocm_phase_select,
+                  L.ocm_phase_connect, L.ocm_phase_values):
+            f.restype = C.c_int
+        L.ocm_status_string.argtypes = [C.c_int]
+        L.ocm_status_string.restype = C.c_char_p
+        L.ocm_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OCM_OK:
+        raise OCMError(rc, lib().ocm_last_error().decode())
+
+
+def _dev(t: torch.Tensor, dtypes, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} must have dtype in {dtypes}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def make_graph(row_ptr: torch.Tensor, col: torch.Tensor, w: torch.Tensor) -> Graph:
+    _dev(row_ptr, (torch.int32,), "row_ptr")
+    _dev(col, (torch.int32,), "col")
+    _dev(w, (torch.int32, torch.int64), "w")
+    if w.numel() != col.numel():
+        raise ValueError("w and col must have the same length")
+    return Graph(row_ptr.numel() - 1, col.numel(), row_ptr.data_ptr(), col.data_ptr(),
+                 w.data_ptr(), OCM_W_I64 if w.dtype == torch.int64 else OCM_W_I32)
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_ws_cache: dict = {}
+
+
+def workspace(g: Graph, device) -> torch.Tensor:
+    """A cached device workspace of at least ocm_workspace_size bytes."""
+    need = lib().ocm_workspace_size(C.byref(g), None)
+    if need == 0:
+        _check(OCM_E_INVALID_ARG)
+    key = torch.device(device)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < need:
+        _ws_cache.pop(key, None)
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def release_workspace():
+    _ws_cache.clear()
+
+
+@dataclasses.dataclass
+class Result:
+    p: int
+    q: int
+    cycle_edges: torch.Tensor      # int32 CSR edge positions from the source
+    source: int
+    iterations: int
+    flags: int
+    W: int
+    L: int
+    tight_edges: int
+    connect_rounds: int
+    jump_rounds: int
+    fast_iters: int
+    policy: torch.Tensor | None = None
+    potential: torch.Tensor | None = None
+    profile: dict | None = None
+
+    @property
+    def value(self) -> Fraction:
+        return Fraction(self.p, self.q)
+
+    @property
+    def tie(self):
+        """True / False, or None when the uniqueness test did not decide."""
+        if self.flags & OCM_F_TIE:
+            return True
+        if self.flags & OCM_F_TIE_UNCHECKED:
+            return None
+        return False
+
+
+CONNECT_MODES = {"auto": 0, "pull": 1, "push": 2}
+
+
+def options(max_iters=0, validate=True, schedule=0, tie_check=True, fast_path=True,
+            connect="auto") -> Options:
+    o = Options()
+    lib().ocm_default_options(C.byref(o))
+    o.max_iters, o.validate, o.schedule = max_iters, int(validate), schedule
+    o.tie_check, o.fast_path = int(tie_check), int(fast_path)
+    o.connect_mode = CONNECT_MODES[connect]
+    return o
+
+
+def _solve(fn, row_ptr, col, w, want_policy, want_potential, profile, **opt) -> Result:
+    g = make_graph(row_ptr, col, w)
+    dev = col.device
+    o = options(**opt)
+    pol = torch.empty(g.n, dtype=torch.int32, device=dev) if want_policy else None
+    pot = torch.empty(g.n, dtype=torch.int64, device=dev) if want_potential else None
+    o.policy_out = pol.data_ptr() if want_policy else None
+    o.potential_out = pot.data_ptr() if want_potential else None
+    prof = Profile() if profile else None
+    if prof is not None:
+        o.profile = C.pointer(prof)
+    ws = workspace(g, dev)
+    cyc = torch.empty(g.n, dtype=torch.int32, device=dev)
+    res = _Result()
+    _check(fn(C.byref(g), C.byref(o), C.c_void_p(ws.data_ptr()), ws.numel(),
+              C.c_void_p(cyc.data_ptr()), g.n, C.byref(res), _stream()))
+    return Result(res.p, res.q, cyc[:res.cycle_len], res.source, res.iterations, res.flags,
+                  res.W, res.L, res.tight_edges, res.connect_rounds, res.jump_rounds,
+                  res.fast_iters, pol, pot, prof.as_dict() if prof is not None else None)
+
+
+def min_cycle_mean(row_ptr, col, w, *, want_policy=False, want_potential=False,
+                   profile=False, **opt) -> Result:
+    """Exact minimum cycle mean and one critical cycle (ocm_min)."""
+    return _solve(lib().ocm_min, row_ptr, col, w, want_policy, want_potential, profile, **opt)
+
+
+def max_cycle_mean(row_ptr, col, w, *, want_policy=False, want_potential=False,
+                   profile=False, **opt) -> Result:
+    """Exact maximum cycle mean and one critical cycle (ocm_max)."""
+    return _solve(lib().ocm_max, row_ptr, col, w, want_policy, want_potential, profile, **opt)
+
+
+def cycle_mean(row_ptr, col, w, mode: str = "min", **kw) -> Result:
+    if mode not in ("min", "max"):
+        raise ValueError("mode must be 'min' or 'max'")
+    return (min_cycle_mean if mode == "min" else max_cycle_mean)(row_ptr, col, w, **kw)
+
+
+# -------------------------------------------------------------------------
+# single phases (ocm_phase_*), driven from a given state
+# -------------------------------------------------------------------------
+def phase_sweep(row_ptr, col, w, pi, V=None, W=0, L=1, first=False, neg=False, schedule=0):
+    g = make_graph(row_ptr, col, w)
+    _dev(pi, (torch.int32,), "pi")
+    if V is not None:
+        _dev(V, (torch.int64,), "V")
+    ws = workspace(g, col.device)
+    ch = C.c_int64()
+    _check(lib().ocm_phase_sweep(C.byref(g), int(neg), int(first),
+                                 None if V is None else C.c_void_p(V.data_ptr()), W, L,
+                                 C.c_void_p(pi.data_ptr()), schedule, C.c_void_p(ws.data_ptr()),
+                                 ws.numel(), C.byref(ch), _stream()))
+    return ch.value
+
+
+def phase_cycles(row_ptr, col, w, pi):
+    g = make_graph(row_ptr, col, w)
+    _dev(pi, (torch.int32,), "pi")
+    rep = torch.empty(g.n, dtype=torch.int32, device=col.device)
+    onc = torch.empty(g.n, dtype=torch.uint8, device=col.device)
+    ws = workspace(g, col.device)
+    nc = C.c_int64()
+    _check(lib().ocm_phase_cycles(C.byref(g), C.c_void_p(pi.data_ptr()),
+                                  C.c_void_p(rep.data_ptr()), C.c_void_p(onc.data_ptr()),
+                                  C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(nc), _stream()))
+    return rep, onc, nc.value
+
+
+def phase_select(row_ptr, col, w, pi, rep, onc, neg=False):
+    g = make_graph(row_ptr, col, w)
+    ws = workspace(g, col.device)
+    s, W, L = C.c_int32(), C.c_int64(), C.c_int64()
+    _check(lib().ocm_phase_select(C.byref(g), int(neg), C.c_void_p(pi.data_ptr()),
+                                  C.c_void_p(rep.data_ptr()), C.c_void_p(onc.data_ptr()),
+                                  C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(s), C.byref(W),
+                                  C.byref(L), _stream()))
+    return s.value, W.value, L.value
+
+
+def phase_connect(row_ptr, col, w, rep, s, pi):
+    """Rewires ``pi`` in place; returns (layer, rounds)."""
+    g = make_graph(row_ptr, col, w)
+    _dev(pi, (torch.int32,), "pi")
+    layer = torch.empty(g.n, dtype=torch.int32, device=col.device)
+    ws = workspace(g, col.device)
+    r = C.c_int32()
+    _check(lib().ocm_phase_connect(C.byref(g), C.c_void_p(rep.data_ptr()), s,
+                                   C.c_void_p(pi.data_ptr()), C.c_void_p(layer.data_ptr()),
+                                   C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(r), _stream()))
+    return layer, r.value
+
+
+def phase_values(row_ptr, col, w, pi, s, W, L, neg=False):
+    g = make_graph(row_ptr, col, w)
+    V = torch.empty(g.n, dtype=torch.int64, device=col.device)
+    ws = workspace(g, col.device)
+    r = C.c_int32()
+    _check(lib().ocm_phase_values(C.byref(g), int(neg), C.c_void_p(pi.data_ptr()), s, W, L,
+                                  C.c_void_p(V.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                  C.byref(r), _stream()))
+    return V, r.value

@@ -1,0 +1,351 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every comparison is exact: the rational optimum p/q, the critical cycle (CSR
+edge positions from the source), the source, the iteration count and the
+number of tight non-policy edges must equal the sequential policy
+iteration's, and each phase driven from an oracle state must reproduce the
+oracle's next state array by array.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import brute, closed, native
+from paper_1111_0627_amd import ocm, synth
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    ocm.lib()
+    yield
+    ocm.release_workspace()
+
+
+def to_dev(rp, cl, w, wdtype=None):
+    w = np.asarray(w)
+    if wdtype is not None:
+        w = w.astype(wdtype)
+    elif w.dtype not in (np.int32, np.int64):
+        w = w.astype(np.int64)
+    return (torch.from_numpy(np.ascontiguousarray(rp, np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(cl, np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(w)).cuda())
+
+
+def assert_same(res, sol, tie=True):
+    got = (res.p, res.q, res.cycle_edges.cpu().tolist(), res.source, res.iterations)
+    exp = (sol.p, sol.q, sol.cycle.tolist(), sol.source, sol.iterations)
+    assert got == exp
+    if tie:
+        assert res.tight_edges == sol.tight
+
+
+def gpu_solve(rp, cl, w, mode="min", wdtype=None, **kw):
+    return ocm.cycle_mean(*to_dev(rp, cl, w, wdtype), mode=mode, **kw)
+
+
+# ---------------------------------------------------------------------------
+# hand-derived traces
+# ---------------------------------------------------------------------------
+def _traces():
+    with open(os.path.join(GOLD, "hand_traces.json")) as f:
+        return json.load(f)["traces"]
+
+
+@pytest.mark.parametrize("tr", _traces(), ids=lambda t: t["name"])
+def test_hand_traces_full_solve(tr):
+    rp, cl, w = (np.array(tr[k]) for k in ("row_ptr", "col", "w"))
+    r = tr["result"]
+    for fast in (0, 1):
+        res = gpu_solve(rp, cl, w, fast_path=fast)
+        assert (res.p, res.q, res.cycle_edges.cpu().tolist(), res.source, res.iterations) == \
+            (r["p"], r["q"], r["cycle"], r["source"], r["iterations"])
+        assert (res.tight_edges > 0) == bool(r["tie"])
+
+
+@pytest.mark.parametrize("tr", _traces(), ids=lambda t: t["name"])
+def test_hand_traces_phase_by_phase(tr):
+    rp, cl, w = to_dev(*(np.array(tr[k]) for k in ("row_ptr", "col", "w")))
+    n = rp.numel() - 1
+    pi = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    V = torch.zeros(n, dtype=torch.int64, device="cuda")
+    W, L = 0, 1
+    for k, it in enumerate(tr["iterations"]):
+        ch = ocm.phase_sweep(rp, cl, w, pi, V, W, L, first=(k == 0))
+        assert ch == it["changed"]
+        assert pi.cpu().tolist() == it["pi"]
+        if "rep" not in it:
+            break
+        rep, onc, _ = ocm.phase_cycles(rp, cl, w, pi)
+        assert rep.cpu().tolist() == it["rep"]
+        assert onc.cpu().tolist() == it["on_cycle"]
+        s, W, L = ocm.phase_select(rp, cl, w, pi, rep, onc)
+        assert (s, W, L) == (it["s"], it["W"], it["L"])
+        layer, rounds = ocm.phase_connect(rp, cl, w, rep, s, pi)
+        assert rounds == it["rounds"]
+        assert layer.cpu().tolist() == it["layer"]
+        assert pi.cpu().tolist() == it["pi_connected"]
+        V, _ = ocm.phase_values(rp, cl, w, pi, s, W, L)
+        assert V.cpu().tolist() == it["V"]
+
+
+# ---------------------------------------------------------------------------
+# trace-driven phases on larger graphs: each GPU phase starts from the
+# oracle's state and must reproduce the oracle's next state exactly
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,dlo,dhi,wlo,whi,seed,mode", [
+    (5000, 1, 4, 1, 100, 0, "min"),
+    (20011, 2, 10, -5000, 5000, 1, "max"),
+    (65537, 1, 8, 1, 10, 2, "min"),
+])
+def test_trace_driven_phases(n, dlo, dhi, wlo, whi, seed, mode):
+    g = synth.random_digraph(n, dlo, dhi, wlo, whi, np.int32, seed)
+    neg = mode == "max"
+    rp, cl, w = to_dev(g.row_ptr, g.col, g.w)
+    st = native.Stepper(g.row_ptr, g.col, g.w, mode)
+    pi = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    V = torch.zeros(n, dtype=torch.int64, device="cuda")
+    W, L = 0, 1
+    first = True
+    for _ in range(200):
+        ch_o = st.sweep()
+        ch_g = ocm.phase_sweep(rp, cl, w, pi, V, W, L, first=first, neg=neg)
+        first = False
+        assert ch_g == ch_o
+        assert np.array_equal(pi.cpu().numpy(), st.get("pi"))
+        if st.iter >= 2 and ch_o == 0:
+            break
+        st.cycles()
+        rep, onc, _ = ocm.phase_cycles(rp, cl, w, pi)
+        assert np.array_equal(rep.cpu().numpy(), st.get("rep"))
+        assert np.array_equal(onc.cpu().numpy(), st.get("on_cycle"))
+        so = st.select()
+        s, W, L = ocm.phase_select(rp, cl, w, pi, rep, onc, neg=neg)
+        assert (s, W, L) == so
+        assert st.connect() == 0
+        layer, rounds = ocm.phase_connect(rp, cl, w, rep, s, pi)
+        assert rounds == st.rounds
+        assert np.array_equal(layer.cpu().numpy(), st.get("layer"))
+        assert np.array_equal(pi.cpu().numpy(), st.get("pi"))
+        st.values()
+        V, _ = ocm.phase_values(rp, cl, w, pi, s, W, L, neg=neg)
+        assert np.array_equal(V.cpu().numpy(), st.get("val"))
+    else:
+        pytest.fail("no convergence")
+
+
+# ---------------------------------------------------------------------------
+# full solves against the oracle
+# ---------------------------------------------------------------------------
+def test_random_tiny_graphs_against_oracle_and_brute_force():
+    rng = np.random.default_rng(2024)
+    for i in range(400):
+        n = int(rng.integers(1, 8))
+        rp, cl, w = brute.random_tiny(rng, n, 3, -3 if i % 3 == 0 else 1, 4 if i % 2 else 9)
+        mode = "min" if i % 4 else "max"
+        sol = native.solve(rp, cl, w, mode=mode)
+        res = gpu_solve(rp, cl, w, mode=mode, wdtype=np.int32 if i % 2 else np.int64)
+        assert_same(res, sol)
+        val, crit = brute.optimum(rp, cl, w, mode)
+        assert res.value == val and tuple(res.cycle_edges.cpu().tolist()) in crit
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_graphs_spanning_tiles(seed):
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(6):
+        n = int(rng.integers(2, 40000))
+        dlo = int(rng.integers(1, 4))
+        dhi = dlo + int(rng.integers(0, 40 if n < 5000 else 8))
+        lo = int(rng.integers(-1000, 10))
+        hi = lo + int(rng.integers(0, 3000))
+        wdt = np.int64 if rng.integers(0, 2) else np.int32
+        g = synth.random_digraph(n, dlo, dhi, lo, hi, wdt, int(rng.integers(0, 1 << 30)))
+        mode = "max" if rng.integers(0, 2) else "min"
+        sol = native.solve(g.row_ptr, g.col, g.w, mode=mode)
+        res = gpu_solve(g.row_ptr, g.col, g.w, mode=mode, want_potential=True)
+        assert_same(res, sol)
+        assert native.certify(g.row_ptr, g.col, g.w, res.p, res.q, res.cycle_edges.cpu().numpy(),
+                              res.potential.cpu().numpy(), res.L, mode) == 0
+
+
+def test_schedules_and_fast_path_give_identical_bytes():
+    g = synth.random_digraph(30000, 1, 20, 1, 50, np.int32, 9)
+    sol = native.solve(g.row_ptr, g.col, g.w)
+    rp, cl, w = to_dev(g.row_ptr, g.col, g.w)
+    ref = None
+    for G in (1, 2, 4, 8, 16, 32, 64):
+        for fast in (0, 1):
+            res = ocm.min_cycle_mean(rp, cl, w, schedule=G, fast_path=fast, want_policy=True,
+                                     want_potential=True)
+            assert_same(res, sol)
+            cur = (res.policy.cpu().numpy(), res.potential.cpu().numpy())
+            if ref is None:
+                ref = cur
+            assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1])
+
+
+@pytest.mark.parametrize("kind", ["product", "random"])
+def test_connect_directions_give_identical_bytes(kind):
+    if kind == "product":
+        g = synth.product_graph(5, 16, 0.3, 1, 1000, 4)
+    else:
+        g = synth.random_digraph(300000, 1, 6, 1, 20, np.int32, 8)
+    sol = native.solve(g.row_ptr, g.col, g.w)
+    rp, cl, w = to_dev(g.row_ptr, g.col, g.w)
+    ref = None
+    for mode in ("pull", "push", "auto"):
+        res = ocm.min_cycle_mean(rp, cl, w, connect=mode, want_policy=True, want_potential=True)
+        assert_same(res, sol)
+        cur = (res.policy.cpu().numpy(), res.potential.cpu().numpy(), res.connect_rounds)
+        if ref is None:
+            ref = cur
+        assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1])
+        assert cur[2] == ref[2]
+
+
+def test_product_graph_small_against_closed_form():
+    for procs, states, seed in ((3, 8, 1), (4, 16, 2), (5, 16, 3)):
+        g = synth.product_graph(procs, states, 0.3, 1, 1000, seed)
+        has2, t2, cost = synth.product_tables(procs, states, 0.3, 1, 1000, seed)
+        locs = [synth.local_automaton(has2, t2, cost, i) for i in range(procs)]
+        for mode in ("min", "max"):
+            sol = native.solve(g.row_ptr, g.col, g.w, mode=mode)
+            res = gpu_solve(g.row_ptr, g.col, g.w, mode=mode)
+            assert_same(res, sol)
+            assert res.value == closed.product_optimum(locs, mode)
+
+
+def test_invariants_shift_scale_negate():
+    g = synth.random_digraph(12000, 1, 6, -300, 300, np.int64, 5)
+    base = gpu_solve(g.row_ptr, g.col, g.w)
+    for c in (-1000, 7):
+        r = gpu_solve(g.row_ptr, g.col, g.w + c)
+        assert r.value == base.value + c
+        assert (r.cycle_edges.cpu().tolist(), r.iterations) == \
+            (base.cycle_edges.cpu().tolist(), base.iterations)
+    r = gpu_solve(g.row_ptr, g.col, g.w * 3)
+    assert r.value == base.value * 3 and r.iterations == base.iterations
+    r = gpu_solve(g.row_ptr, g.col, -g.w, mode="max")
+    assert r.value == -base.value
+    assert r.cycle_edges.cpu().tolist() == base.cycle_edges.cpu().tolist()
+
+
+def test_repeated_runs_are_byte_identical():
+    g = synth.workload("rand1k")
+    rp, cl, w = to_dev(g.row_ptr, g.col, g.w)
+    outs = set()
+    for _ in range(10):
+        r = ocm.min_cycle_mean(rp, cl, w, want_policy=True, want_potential=True)
+        outs.add((r.p, r.q, r.iterations, r.source, tuple(r.cycle_edges.cpu().tolist()),
+                  r.policy.cpu().numpy().tobytes(), r.potential.cpu().numpy().tobytes()))
+    assert len(outs) == 1
+
+
+# ---------------------------------------------------------------------------
+# errors forced from the host
+# ---------------------------------------------------------------------------
+def _expect(status, *args, **kw):
+    with pytest.raises(ocm.OCMError) as ex:
+        gpu_solve(*args, **kw)
+    assert ex.value.status == status
+
+
+def test_error_conventions():
+    # Fig. 2b offsets: vertex 2 has no out-edge
+    cl = np.array([1, 2, 3, 0, 3, 1, 0])
+    w = np.ones(7, np.int32)
+    _expect(ocm.OCM_E_NO_OUT_EDGE, np.array([0, 3, 5, 5, 7]), cl, w)
+    _expect(ocm.OCM_E_BAD_CSR, np.array([0, 3, 2, 7, 7]), cl, w)
+    _expect(ocm.OCM_E_BAD_CSR, np.array([0, 3, 5, 6, 7]), np.array([1, 2, 3, 0, 9, 1, 0]), w)
+    # two disjoint rings: no vertex of the second can reach the first
+    rp = np.array([0, 1, 2, 3, 4])
+    _expect(ocm.OCM_E_NOT_STRONGLY_CONNECTED, rp, np.array([1, 0, 3, 2]), np.array([1, 1, 5, 5]))
+    g = synth.random_digraph(3000, 1, 4, 1, 100, np.int32, 1)
+    _expect(ocm.OCM_E_NOT_CONVERGED, g.row_ptr, g.col, g.w, max_iters=1)
+    ok = native.solve(g.row_ptr, g.col, g.w)
+    r = gpu_solve(g.row_ptr, g.col, g.w, max_iters=ok.iterations)
+    assert r.value == ok.value
+    big = np.full(g.m, 2**60, np.int64)
+    _expect(ocm.OCM_E_OVERFLOW, g.row_ptr, g.col, big)
+
+
+def test_fig1_graph_certified_or_rejected():
+    a, b, c, d, e, f, gg = range(7)
+    adj = {a: [b, f, a], b: [c, e], c: [d], d: [c], e: [f], f: [b], gg: [e]}
+    rp = np.cumsum([0] + [len(adj[v]) for v in range(7)])
+    cl = np.array([t for v in range(7) for t in adj[v]])
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        w = rng.integers(-5, 6, len(cl))
+        try:
+            sol = native.solve(rp, cl, w)
+        except native.OracleError as ex:
+            _expect(ex.code, rp, cl, w)
+            continue
+        assert_same(gpu_solve(rp, cl, w), sol)
+
+
+def test_workspace_and_capacity_checks():
+    import ctypes as C
+    g = synth.random_digraph(500, 1, 4, 1, 100, np.int32, 3)
+    rp, cl, w = to_dev(g.row_ptr, g.col, g.w)
+    G = ocm.make_graph(rp, cl, w)
+    L = ocm.lib()
+    need = L.ocm_workspace_size(C.byref(G), None)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    cyc = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    res = ocm._Result()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = L.ocm_min(C.byref(G), None, C.c_void_p(ws.data_ptr()), need - 1,
+                   C.c_void_p(cyc.data_ptr()), g.n, C.byref(res), st)
+    assert rc == ocm.OCM_E_WORKSPACE
+    rc = L.ocm_min(C.byref(G), None, C.c_void_p(ws.data_ptr()), need,
+                   C.c_void_p(cyc.data_ptr()), 0, C.byref(res), st)
+    assert rc == ocm.OCM_E_CAPACITY and res.cycle_len > 0
+    rc = L.ocm_min(C.byref(G), None, C.c_void_p(ws.data_ptr()), need,
+                   C.c_void_p(cyc.data_ptr()), res.cycle_len, C.byref(res), st)
+    assert rc == ocm.OCM_OK
+
+
+# ---------------------------------------------------------------------------
+# the measured workloads at full size
+# ---------------------------------------------------------------------------
+def test_workload_rand1k_against_oracle_and_karp():
+    g = synth.workload("rand1k")
+    sol = native.solve(g.row_ptr, g.col, g.w)
+    res = gpu_solve(g.row_ptr, g.col, g.w)
+    assert_same(res, sol)
+    assert res.value == native.karp(g.row_ptr, g.col, g.w)
+
+
+def _golden():
+    p = os.path.join(GOLD, "workloads.json")
+    with open(p) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["rand1m_max", "product16x6", "rand4m_i64"])
+def test_full_workloads_against_oracle_results(name):
+    gold = _golden()[name]
+    g = synth.workload(name)
+    assert (g.n, g.m) == (gold["n"], gold["m"])
+    res = gpu_solve(g.row_ptr, g.col, g.w, mode=gold["mode"], want_potential=True)
+    got = (res.p, res.q, res.cycle_edges.cpu().tolist(), res.source, res.iterations, res.tight_edges)
+    exp = (gold["p"], gold["q"], gold["cycle"], gold["source"], gold["iterations"], gold["tight"])
+    assert got == exp
+    # independent optimality certificate of the GPU's own potential
+    assert native.certify(g.row_ptr, g.col, g.w, res.p, res.q, res.cycle_edges.cpu().numpy(),
+                          res.potential.cpu().numpy(), res.L, gold["mode"]) == 0
+    if name == "product16x6":
+        has2, t2, cost = synth.product_tables(6, 16, 0.3, 1, 1000, 0)
+        locs = [synth.local_automaton(has2, t2, cost, i) for i in range(6)]
+        assert res.value == closed.product_optimum(locs)
