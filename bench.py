@@ -28,21 +28,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes per launch of each phase (each element counted once at
-# its size; the sweep's policy writes are left out, so figures are lower
-# bounds).  sw = bytes per weight.
-def sweep_bytes(n, m, sw, first):
-    if first:
-        return m * (4 + sw) + 4 * (n + 1)
-    return m * (4 + sw + 8) + 4 * (n + 1) + 8 * n
+KERNEL_NAMES = {
+    "sweep": "k_sweep (policy improvement)",
+    "tiescan": "k_sweep<TIE> (tight-edge count)",
+    "cycles": "k_pj_init/round/final (policy-graph cycles)",
+    "select": "k_cyc_zero/sum + k_select (minimum-mean cycle)",
+    "conn_pull": "k_conn_init/pull (rebuild, pull rounds)",
+    "conn_offer": "k_conn_offer (rebuild, push offers)",
+    "conn_collect": "k_conn_collect (rebuild, push collection)",
+    "reverse": "k_rev_count/fill + scan (reverse CSR)",
+    "values": "k_val_init/round/final (values after a rebuild)",
+    "fast": "k_val_init/round/final (values, fast path)",
+    "result": "k_cycle_list",
+    "validate": "k_validate",
+}
 
 
-def jump_round_bytes(n):       # cycles: 8 B own read + 8 B gather + 8 B write
-    return 24 * n
-
-
-def value_round_bytes(n):      # values: 16 B own read + 16 B gather + 16 B write
-    return 48 * n
+def roofline(cls, ms, launches, nbytes):
+    """HBM roofline of one kernel class from the library's live hipEvent
+    timings and its algorithmic bytes (both summed over the timed steps)."""
+    gbs = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    return {"kernel": KERNEL_NAMES.get(cls, cls), "bound": "hbm", "achieved": gbs,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "traffic": None, "bytes_per_launch": nbytes / max(launches, 1),
+            "avg_launch_us": ms * 1e3 / max(launches, 1)}
 
 
 def cpu_baseline(g, mode, budget_s=30.0):
@@ -55,8 +64,7 @@ def cpu_baseline(g, mode, budget_s=30.0):
     return dict(value=g.m * sol.iterations / dt, unit="edges/s", cores=1, kind="oracle",
                 sample=f"one full sequential policy-iteration solve of the same workload "
                        f"({sol.iterations} iterations, {dt:.1f} s, single thread)",
-                seconds=round(dt, 2), iterations=sol.iterations,
-                agrees=(sol.p, sol.q) is not None)
+                seconds=round(dt, 2), iterations=sol.iterations, p=sol.p, q=sol.q)
 
 
 def main():
@@ -67,6 +75,9 @@ def main():
     ap.add_argument("--workload", default="product16x6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before timing, copy one buffer of this many MiB (a plain copy "
+                         "kernel of known size, to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1"}))
@@ -87,6 +98,16 @@ def main():
     w = torch.from_numpy(g.w).to(dev)
     sw = g.w.dtype.itemsize
     torch.cuda.synchronize()
+
+    if args.calib_copy_mb > 0:
+        nb = args.calib_copy_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mb} MiB done")
+        del src, dst
 
     def step(profile):
         return ocm.cycle_mean(rp, cl, w, mode=mode, profile=profile)
@@ -120,10 +141,11 @@ def main():
         per_step.append((time.perf_counter() - ts) * 1e3)
         results.add((r.p, r.q, r.iterations, r.source, r.L))
         if r.profile:
-            for k, (ms, cnt) in r.profile.items():
-                a = phase.setdefault(k, [0.0, 0])
-                a[0] += ms
+            for k, (pms, cnt, nbytes) in r.profile.items():
+                a = phase.setdefault(k, [0.0, 0, 0.0])
+                a[0] += pms
                 a[1] += cnt
+                a[2] += nbytes
     e1.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -144,44 +166,23 @@ def main():
                                  "cold": cold_ms, "events_total": ev_ms},
         "result": {"p": r.p, "q": r.q, "cycle_len": r.L, "source": r.source,
                    "tight_edges": r.tight_edges, "fast_iters": r.fast_iters,
-                   "jump_rounds": r.jump_rounds, "connect_rounds": r.connect_rounds},
+                   "jump_rounds": r.jump_rounds, "connect_rounds": r.connect_rounds,
+                   **r.counters},
     }
     if phase:
         K = args.steps
         out["phase_ms_per_step"] = {k: v[0] / K for k, v in phase.items() if v[1]}
         out["phase_launches_per_step"] = {k: v[1] / K for k, v in phase.items() if v[1]}
-        # roofline of the sweep (policy improvement, the only O(m) phase)
-        sb = (sweep_bytes(g.n, g.m, sw, True) + (iters - 1) * sweep_bytes(g.n, g.m, sw, False))
-        sweep_ms = phase["sweep"][0] / K
-        sweep_launches = phase["sweep"][1] / K
-        gbs = sb / (sweep_ms / 1e3) / 1e9
-        roof_sweep = {"kernel": "k_sweep (policy improvement)", "bound": "hbm",
-                      "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                      "frac": gbs / PEAK_HBM_GBS, "traffic": None,
-                      "bytes_per_launch": sb / sweep_launches,
-                      "avg_launch_us": sweep_ms * 1e3 / sweep_launches}
-        cand = {"sweep": roof_sweep}
-        if phase.get("cycles", [0, 0])[1]:
-            # each cycles launch group = init + rounds + final
-            jr = r.jump_rounds
-            cb = phase["cycles"][0] / K
-            # bytes: rounds plus init/final passes (about 21 B per vertex each)
-            nb = (r.jump_rounds and 1)  # noqa: F841
-            cyc_launch_groups = phase["cycles"][1] / K
-            cyc_bytes = cyc_launch_groups * 42 * g.n
-            # rounds counted in jump_rounds include value rounds; use phase split
-            gbs_c = None
-            cand["cycles"] = {"kernel": "k_pj_round (cycle detection)", "bound": "hbm",
-                              "ms_per_step": cb, "launch_groups": cyc_launch_groups,
-                              "jump_rounds_total": jr, "approx_bytes_init_final": cyc_bytes,
-                              "achieved": gbs_c}
-        dom = max(((k, v[0]) for k, v in phase.items() if v[1]), key=lambda kv: kv[1])[0]
-        out["dominant_phase"] = dom
-        out["roofline"] = roof_sweep
-        out["roofline_phases"] = cand
+        out["phase_gbs"] = {k: v[2] / (v[0] / 1e3) / 1e9 for k, v in phase.items() if v[1] and v[0] > 0}
+        dom = max((k for k, v in phase.items() if v[1]), key=lambda k: phase[k][0])
+        out["roofline"] = roofline(dom, *phase[dom])
+        out["roofline"]["class"] = dom
+        out["roofline_sweep"] = roofline("sweep", *phase["sweep"])
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle ...")
-        out["cpu_baseline"] = cpu_baseline(g, mode)
+        cb = cpu_baseline(g, mode)
+        cb["agrees_with_gpu"] = (cb["p"], cb["q"], cb["iterations"]) == (r.p, r.q, r.iterations)
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

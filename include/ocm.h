@@ -94,16 +94,35 @@ typedef struct {
     int32_t fast_iters;        /* iterations resolved by the fused fast path   */
     int64_t W, L;              /* unreduced optimum W/L: weight and length of C */
     int64_t tight_edges;       /* tight non-policy edges at the optimum        */
+    int64_t push_frontier;     /* frontier vertices expanded by push rounds    */
+    int64_t push_in_edges;     /* in-edges scanned by push rounds              */
+    int32_t general_iters;     /* iterations that ran the cycle/select/rebuild phases */
+    int32_t value_rounds;      /* pointer-jumping rounds of the value phases   */
 } ocm_result;
 
-/* Per-phase device time, filled when ocm_options.profile is non-null. */
+/* Device time per kernel class, filled when ocm_options.profile is non-null
+ * (hipEvents recorded around each launch on the call's stream). */
 enum {
-    OCM_PH_VALIDATE = 0, OCM_PH_SWEEP, OCM_PH_CYCLES, OCM_PH_SELECT,
-    OCM_PH_CONNECT, OCM_PH_VALUES, OCM_PH_FAST, OCM_PH_RESULT, OCM_PH_COUNT
+    OCM_K_VALIDATE = 0,   /* CSR validation and max |w|                      */
+    OCM_K_SWEEP,          /* policy-improvement sweeps                       */
+    OCM_K_TIESCAN,        /* tight-edge count at the optimum                 */
+    OCM_K_CYCLES,         /* policy-graph cycles: init, jump rounds, final   */
+    OCM_K_SELECT,         /* per-cycle sums and the minimum-mean select      */
+    OCM_K_CONN_PULL,      /* rebuild: init and pull rounds                   */
+    OCM_K_CONN_OFFER,     /* rebuild: push-round offers                      */
+    OCM_K_CONN_COLLECT,   /* rebuild: push-round collection                  */
+    OCM_K_REVERSE,        /* reverse CSR build                               */
+    OCM_K_VALUES,         /* value propagation after a rebuild               */
+    OCM_K_FAST,           /* value propagation of the fast path              */
+    OCM_K_RESULT,         /* cycle listing                                   */
+    OCM_K_COUNT
 };
 typedef struct {
-    double ms[OCM_PH_COUNT];       /* summed kernel time per phase (hipEvents) */
-    int32_t launches[OCM_PH_COUNT];
+    double ms[OCM_K_COUNT];        /* summed kernel time per class             */
+    int32_t launches[OCM_K_COUNT];
+    double bytes[OCM_K_COUNT];     /* algorithmic bytes moved per class: each
+                                      element the method reads or writes counted
+                                      once at its size                        */
 } ocm_profile;
 
 typedef struct {

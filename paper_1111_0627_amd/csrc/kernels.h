@@ -38,6 +38,8 @@ struct alignas(16) Ctl {
     unsigned long long maxabsw;    // validation: max |w|
     unsigned overflow;             // values: a value left [-2^62, 2^62]
     unsigned pad;
+    unsigned long long pedges;     // connect: in-edges scanned by push offers
+    unsigned long long ledges;     // connect: out-edges scanned by pull rounds
 };
 
 // Pointer-jumping entry of the value phase: the first H edges of v's policy
@@ -75,19 +77,23 @@ void launch_cyc_zero(int n, const int* rep, const unsigned char* onc, long long*
                      unsigned* lcnt, int* cyc_list, Ctl* ctl, hipStream_t st);
 void launch_cyc_sum(int n, const int* rep, const unsigned char* onc, const int* pi, const void* w,
                     int wtype, int neg, long long* wsum, unsigned* lcnt, hipStream_t st);
+// scratch: kSelectParts * 32 bytes of device memory
+constexpr int kSelectParts = 512;
 void launch_select(const int* cyc_list, const long long* wsum, const unsigned* lcnt, Ctl* ctl,
-                   hipStream_t st);
+                   void* scratch, hipStream_t st);
 void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, int* layer,
                       unsigned char* onC, int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt,
                       hipStream_t st);
 void launch_conn_pull(int k, const int* row_ptr, const int* col, int* layer, int* pi,
                       const int* in_list, unsigned in_cnt, int* ulist, unsigned* ucnt, int* flist,
-                      unsigned* fcnt, hipStream_t st);
-void launch_conn_push(int k, const int* rin_ptr, const int* rin_src, const int* rin_edge,
-                      int* layer, int* pi, int* cand, const int* fin, unsigned f_cnt, int* fout,
-                      unsigned* fout_cnt, hipStream_t st);
+                      unsigned* fcnt, unsigned long long* ledges, hipStream_t st);
+void launch_conn_offer(const int* rin_ptr, const int2* rin, const int* layer, int* cand,
+                       unsigned char* touched, const int* fin, unsigned f_cnt, Ctl* ctl,
+                       hipStream_t st);
+void launch_conn_collect(int k, int n, unsigned char* touched, int* cand, int* pi, int* layer,
+                         int* fout, unsigned* fout_cnt, hipStream_t st);
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
-                      unsigned* tot, int* rin_ptr, int* rin_src, int* rin_edge, int* cand,
+                      unsigned* tot, int* rin_ptr, int2* rin, int* cand, unsigned char* touched,
                       hipStream_t st);
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
                      int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl, hipStream_t st);

@@ -286,18 +286,27 @@ __global__ __launch_bounds__(kWG) void k_pj_final(int n, const unsigned long lon
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kWG) void k_cyc_zero(int n, const int* __restrict__ rep,
                                                   const unsigned char* __restrict__ onc,
-                                                  long long* __restrict__ wsum,
+                                                  unsigned per, long long* __restrict__ wsum,
                                                   unsigned* __restrict__ lcnt,
                                                   int* __restrict__ cyc_list, Ctl* ctl)
 {
-    const int v = blockIdx.x * kWG + threadIdx.x;
-    const bool head = v < n && onc[v] && rep[v] == v;
-    if (head) {
-        wsum[v] = 0;
-        lcnt[v] = 0;
+    __shared__ int hbuf[kListItems];
+    __shared__ unsigned nh;
+    if (threadIdx.x == 0) nh = 0;
+    __syncthreads();
+    BlockList bl{hbuf, &nh};
+    const int64_t v0 = (int64_t)blockIdx.x * per;
+    const int64_t v1 = v0 + per < n ? v0 + per : n;
+    for (int64_t vb = v0; vb < v1; vb += kWG) {
+        const int64_t v = vb + threadIdx.x;
+        const bool head = v < v1 && onc[v] && rep[v] == v;
+        if (head) {
+            wsum[v] = 0;
+            lcnt[v] = 0;
+        }
+        blist_push(bl, head, (int)v);
     }
-    const unsigned slot = wave_append(head, &ctl->ncyc);
-    if (head) cyc_list[slot] = v;
+    blist_flush(bl, cyc_list, &ctl->ncyc);
 }
 
 template <typename WT>
@@ -331,29 +340,58 @@ __device__ __forceinline__ bool cand_less(const Cand& a, const Cand& b)
     return a.r < b.r;
 }
 
-__global__ __launch_bounds__(1024) void k_select(const int* __restrict__ cyc_list,
-                                                 const long long* __restrict__ wsum,
-                                                 const unsigned* __restrict__ lcnt, Ctl* ctl)
+__device__ __forceinline__ Cand cand_shfl_xor(const Cand& c, int off)
 {
-    __shared__ Cand sh[1024];
+    Cand o;
+    o.W = __shfl_xor(c.W, off, 64);
+    o.L = __shfl_xor(c.L, off, 64);
+    o.r = __shfl_xor(c.r, off, 64);
+    return o;
+}
+
+// Best candidate of the workgroup (valid in thread 0).
+__device__ __forceinline__ Cand block_best(Cand best)
+{
+    __shared__ Cand sh[kWG / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        const Cand o = cand_shfl_xor(best, off);
+        if (cand_less(o, best)) best = o;
+    }
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = 1; i < kWG / 64; ++i)
+            if (cand_less(sh[i], best)) best = sh[i];
+    return best;
+}
+
+__global__ __launch_bounds__(kWG) void k_select_part(const int* __restrict__ cyc_list,
+                                                     const long long* __restrict__ wsum,
+                                                     const unsigned* __restrict__ lcnt,
+                                                     const Ctl* ctl, Cand* __restrict__ part)
+{
     const unsigned nc = ctl->ncyc;
     Cand best{0, 1, -1};
-    for (unsigned i = threadIdx.x; i < nc; i += 1024) {
+    for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < nc; i += gridDim.x * kWG) {
         const int r = cyc_list[i];
-        Cand c{wsum[r], (long long)lcnt[r], r};
+        const Cand c{wsum[r], (long long)lcnt[r], r};
         if (cand_less(c, best)) best = c;
     }
-    sh[threadIdx.x] = best;
-    __syncthreads();
-    for (int st = 512; st > 0; st >>= 1) {
-        if (threadIdx.x < st && cand_less(sh[threadIdx.x + st], sh[threadIdx.x]))
-            sh[threadIdx.x] = sh[threadIdx.x + st];
-        __syncthreads();
-    }
+    best = block_best(best);
+    if (threadIdx.x == 0) part[blockIdx.x] = best;
+}
+
+__global__ __launch_bounds__(kWG) void k_select_final(const Cand* __restrict__ part, int nparts,
+                                                      Ctl* ctl)
+{
+    Cand best{0, 1, -1};
+    for (int i = threadIdx.x; i < nparts; i += kWG)
+        if (cand_less(part[i], best)) best = part[i];
+    best = block_best(best);
     if (threadIdx.x == 0) {
-        ctl->s = sh[0].r;
-        ctl->W = sh[0].W;
-        ctl->L = sh[0].L;
+        ctl->s = best.r;
+        ctl->W = best.W;
+        ctl->L = best.L;
     }
 }
 
@@ -370,7 +408,7 @@ __global__ __launch_bounds__(1024) void k_select(const int* __restrict__ cyc_lis
 //   pull: u scans its own out-edges in CSR order (k_conn_pull);
 //   push: every frontier vertex x of layer k-1 offers its in-edges e = u->x
 //         and u keeps the minimum e (atomicMin, order-independent;
-//         k_conn_push + k_conn_push_fin).
+//         offer and claim passes of k_conn_push).
 // The host picks the cheaper direction per round.
 __global__ __launch_bounds__(kWG) void k_conn_init(int n, const int* __restrict__ rep,
                                                    const unsigned char* __restrict__ onc,
@@ -407,7 +445,7 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, const int* __restrict_
                                                    const int* __restrict__ in_list, unsigned in_cnt,
                                                    unsigned per, int* __restrict__ ulist,
                                                    unsigned* ucnt, int* __restrict__ flist,
-                                                   unsigned* fcnt)
+                                                   unsigned* fcnt, unsigned long long* ledges)
 {
     __shared__ int ubuf[kListItems], fbuf[kListItems];
     __shared__ unsigned nu, nf;
@@ -416,6 +454,7 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, const int* __restrict_
     BlockList bu{ubuf, &nu}, bf{fbuf, &nf};
     const int64_t i0 = (int64_t)blockIdx.x * per;
     const int64_t i1 = i0 + per < in_cnt ? i0 + per : in_cnt;
+    unsigned long long scanned = 0;
     for (int64_t ib = i0; ib < i1; ib += kWG) {
         const int64_t i = ib + threadIdx.x;
         bool left = false, got = false;
@@ -427,6 +466,7 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, const int* __restrict_
                 for (int e = row_ptr[u], end = row_ptr[u + 1]; e < end; ++e) {
                     // layers written in this round equal k, so "< k" only
                     // sees vertices attached before the round
+                    ++scanned;
                     const int t = layer[col[e]];
                     if (t >= 0 && t < k) {
                         hit = e;
@@ -449,72 +489,85 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, const int* __restrict_
     blist_flush(bf, flist, fcnt);
 }
 
-__global__ __launch_bounds__(kWG) void k_conn_push(const int* __restrict__ rin_ptr,
-                                                   const int* __restrict__ rin_src,
-                                                   const int* __restrict__ rin_edge,
-                                                   const int* __restrict__ layer,
-                                                   int* __restrict__ cand,
-                                                   const int* __restrict__ fin, unsigned f_cnt,
-                                                   unsigned per, int* __restrict__ fout,
-                                                   unsigned* fout_cnt)
+// Push round k in two launches:
+//   offer:   G lanes per frontier vertex x (layer k-1) walk its in-edges
+//            e = u->x (coalesced 8-byte (u, e) entries); every unattached u
+//            receives atomicMin(cand[u], e) (result unused, so the atomic
+//            needs no return) and touched[u] = 1 (plain byte store);
+//   collect: one coalesced pass over the touched bytes attaches every
+//            touched u with its minimum offer (pi, layer = k), resets cand
+//            and touched, and appends u to the next frontier.
+template <int G>
+__global__ __launch_bounds__(kWG) void k_conn_offer(const int* __restrict__ rin_ptr,
+                                                    const int2* __restrict__ rin,
+                                                    const int* __restrict__ layer,
+                                                    int* __restrict__ cand,
+                                                    unsigned char* __restrict__ touched,
+                                                    const int* __restrict__ fin, unsigned f_cnt,
+                                                    Ctl* ctl)
 {
-    __shared__ int buf[kListItems];
-    __shared__ unsigned nb, base;
-    __shared__ int maxlen;
-    if (threadIdx.x == 0) nb = 0;
-    BlockList bl{buf, &nb};
-    const int64_t i0 = (int64_t)blockIdx.x * per;
-    const int64_t i1 = i0 + per < f_cnt ? i0 + per : f_cnt;
-    for (int64_t ib = i0; ib < i1; ib += kWG) {
-        const int64_t i = ib + threadIdx.x;
-        int beg = 0, len = 0;
-        if (i < i1) {
-            const int x = fin[i];
-            beg = rin_ptr[x];
-            len = rin_ptr[x + 1] - beg;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) maxlen = 0;
-        __syncthreads();
-        if (len) atomicMax(&maxlen, len);
-        __syncthreads();
-        const int ml = maxlen;
-        for (int j = 0; j < ml; ++j) {
-            bool touch = false;
-            int u = 0;
-            if (j < len) {
-                u = rin_src[beg + j];
-                if (layer[u] == -1) touch = atomicMin(&cand[u], rin_edge[beg + j]) == INT32_MAX;
-            }
-            blist_push(bl, touch, u);
-            __syncthreads();
-            const unsigned cnt = nb;
-            if (cnt > kListItems - kWG) {           // block-uniform: flush
-                if (threadIdx.x == 0) base = atomicAdd(fout_cnt, cnt);
-                __syncthreads();
-                for (unsigned t = threadIdx.x; t < cnt; t += kWG) fout[base + t] = buf[t];
-                __syncthreads();
-                if (threadIdx.x == 0) nb = 0;
-                __syncthreads();
+    const int gl = threadIdx.x & (G - 1);
+    const int64_t ngroups = (int64_t)gridDim.x * (kWG / G);
+    unsigned long long scanned = 0;
+    for (int64_t i = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G; i < f_cnt; i += ngroups) {
+        const int x = fin[i];
+        for (int j = rin_ptr[x] + gl, end = rin_ptr[x + 1]; j < end; j += G) {
+            const int2 ue = rin[j];
+            ++scanned;
+            if (layer[ue.x] == -1) {
+                atomicMin(&cand[ue.x], ue.y);
+                touched[ue.x] = 1;
             }
         }
     }
-    blist_flush(bl, fout, fout_cnt);
+    scanned = block_sum_u64(scanned);
+    if (threadIdx.x == 0 && scanned) atomicAdd(&ctl->pedges, scanned);
 }
 
-__global__ __launch_bounds__(kWG) void k_conn_push_fin(int k, int* __restrict__ pi,
-                                                       int* __restrict__ layer,
-                                                       int* __restrict__ cand,
-                                                       const int* __restrict__ flist,
-                                                       const unsigned* fcnt)
+constexpr int kCollectVerts = 4096;   // vertices per block, 16 per thread
+
+__global__ __launch_bounds__(kWG) void k_conn_collect(int k, int n,
+                                                      unsigned char* __restrict__ touched,
+                                                      int* __restrict__ cand,
+                                                      int* __restrict__ pi,
+                                                      int* __restrict__ layer,
+                                                      int* __restrict__ fout, unsigned* fout_cnt)
 {
-    const unsigned cnt = *fcnt;
-    for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < cnt; i += gridDim.x * kWG) {
-        const int u = flist[i];
-        pi[u] = cand[u];
-        layer[u] = k;
-        cand[u] = INT32_MAX;
+    __shared__ int buf[kCollectVerts];
+    __shared__ unsigned nb;
+    if (threadIdx.x == 0) nb = 0;
+    __syncthreads();
+    BlockList bl{buf, &nb};
+    const int64_t v0 = (int64_t)blockIdx.x * kCollectVerts + (int64_t)threadIdx.x * 16;
+    uint4 t = make_uint4(0, 0, 0, 0);
+    if (v0 + 16 <= n) {
+        t = *(const uint4*)(touched + v0);
+    } else {
+        unsigned char tmp[16] = {0};
+        for (int q = 0; q < 16 && v0 + q < n; ++q) tmp[q] = touched[v0 + q];
+        t = make_uint4(tmp[0] | tmp[1] << 8 | tmp[2] << 16 | (unsigned)tmp[3] << 24,
+                       tmp[4] | tmp[5] << 8 | tmp[6] << 16 | (unsigned)tmp[7] << 24,
+                       tmp[8] | tmp[9] << 8 | tmp[10] << 16 | (unsigned)tmp[11] << 24,
+                       tmp[12] | tmp[13] << 8 | tmp[14] << 16 | (unsigned)tmp[15] << 24);
     }
+    const unsigned words[4] = {t.x, t.y, t.z, t.w};
+    const bool any = (t.x | t.y | t.z | t.w) != 0;
+    if (any) {
+        if (v0 + 16 <= n) *(uint4*)(touched + v0) = make_uint4(0, 0, 0, 0);
+        else
+            for (int q = 0; q < 16 && v0 + q < n; ++q) touched[v0 + q] = 0;
+    }
+    for (int q = 0; q < 16; ++q) {
+        const bool hit = ((words[q >> 2] >> (8 * (q & 3))) & 0xffu) != 0;
+        const int u = (int)(v0 + q);
+        if (hit) {
+            pi[u] = cand[u];
+            layer[u] = k;
+            cand[u] = INT32_MAX;
+        }
+        blist_push(bl, hit, u);
+    }
+    blist_flush(bl, fout, fout_cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -533,15 +586,15 @@ __global__ __launch_bounds__(kWG) void k_rev_count(int n, const int* __restrict_
 __global__ __launch_bounds__(kWG) void k_rev_fill(int n, const int* __restrict__ row_ptr,
                                                   const int* __restrict__ col,
                                                   unsigned* __restrict__ cursor,
-                                                  int* __restrict__ rin_src,
-                                                  int* __restrict__ rin_edge)
+                                                  int2* __restrict__ rin)
 {
-    for (int64_t u = (int64_t)blockIdx.x * kWG + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * kWG) {
-        for (int e = row_ptr[u], end = row_ptr[u + 1]; e < end; ++e) {
+    constexpr int G = 8;
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t ngroups = (int64_t)gridDim.x * (kWG / G);
+    for (int64_t u = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G; u < n; u += ngroups) {
+        for (int e = row_ptr[u] + lane, end = row_ptr[u + 1]; e < end; e += G) {
             const unsigned pos = atomicAdd(&cursor[col[e]], 1u);
-            rin_src[pos] = (int)u;
-            rin_edge[pos] = e;
+            rin[pos] = make_int2((int)u, e);
         }
     }
 }
@@ -737,6 +790,8 @@ __global__ void k_ctl_clear(Ctl* ctl, unsigned what)
         ctl->active2 = 0;
     }
     if (what & kClrAll) {
+        ctl->pedges = 0;
+        ctl->ledges = 0;
         ctl->err = 0;
         ctl->maxabsw = 0;
         ctl->overflow = 0;
@@ -776,6 +831,17 @@ static inline unsigned stride_grid(int64_t n)
 {
     const unsigned b = blocks_for(n);
     return b < 2048 ? b : 2048;
+}
+
+// Items per block for list-producing kernels: spread over about 2048 blocks,
+// at most kListItems so the LDS buffer cannot overflow.
+static unsigned list_per_block(int64_t items)
+{
+    int64_t per = (items + 2047) / 2048;
+    per = (per + kWG - 1) / kWG * kWG;
+    if (per < kWG) per = kWG;
+    if (per > kListItems) per = kListItems;
+    return (unsigned)per;
 }
 
 template <typename WT>
@@ -841,7 +907,9 @@ void launch_pj_final(int n, const unsigned long long* P, int* rep, unsigned char
 void launch_cyc_zero(int n, const int* rep, const unsigned char* onc, long long* wsum,
                      unsigned* lcnt, int* cyc_list, Ctl* ctl, hipStream_t st)
 {
-    k_cyc_zero<<<blocks_for(n), kWG, 0, st>>>(n, rep, onc, wsum, lcnt, cyc_list, ctl);
+    const unsigned per = list_per_block(n);
+    const unsigned grid = (unsigned)(((int64_t)n + per - 1) / per);
+    k_cyc_zero<<<grid, kWG, 0, st>>>(n, rep, onc, per, wsum, lcnt, cyc_list, ctl);
 }
 
 void launch_cyc_sum(int n, const int* rep, const unsigned char* onc, const int* pi, const void* w,
@@ -856,20 +924,11 @@ void launch_cyc_sum(int n, const int* rep, const unsigned char* onc, const int* 
 }
 
 void launch_select(const int* cyc_list, const long long* wsum, const unsigned* lcnt, Ctl* ctl,
-                   hipStream_t st)
+                   void* scratch, hipStream_t st)
 {
-    k_select<<<1, 1024, 0, st>>>(cyc_list, wsum, lcnt, ctl);
-}
-
-// Items per block for list-producing kernels: spread over about 2048 blocks,
-// at most kListItems so the LDS buffer cannot overflow.
-static unsigned list_per_block(int64_t items)
-{
-    int64_t per = (items + 2047) / 2048;
-    per = (per + kWG - 1) / kWG * kWG;
-    if (per < kWG) per = kWG;
-    if (per > kListItems) per = kListItems;
-    return (unsigned)per;
+    Cand* part = (Cand*)scratch;
+    k_select_part<<<kSelectParts, kWG, 0, st>>>(cyc_list, wsum, lcnt, ctl, part);
+    k_select_final<<<1, kWG, 0, st>>>(part, kSelectParts, ctl);
 }
 
 void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, int* layer,
@@ -883,29 +942,34 @@ void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, in
 
 void launch_conn_pull(int k, const int* row_ptr, const int* col, int* layer, int* pi,
                       const int* in_list, unsigned in_cnt, int* ulist, unsigned* ucnt, int* flist,
-                      unsigned* fcnt, hipStream_t st)
+                      unsigned* fcnt, unsigned long long* ledges, hipStream_t st)
 {
     if (in_cnt == 0) return;
     const unsigned per = list_per_block(in_cnt);
     const unsigned grid = (unsigned)(((int64_t)in_cnt + per - 1) / per);
     k_conn_pull<<<grid, kWG, 0, st>>>(k, row_ptr, col, layer, pi, in_list, in_cnt, per, ulist,
-                                      ucnt, flist, fcnt);
+                                      ucnt, flist, fcnt, ledges);
 }
 
-void launch_conn_push(int k, const int* rin_ptr, const int* rin_src, const int* rin_edge,
-                      int* layer, int* pi, int* cand, const int* fin, unsigned f_cnt, int* fout,
-                      unsigned* fout_cnt, hipStream_t st)
+void launch_conn_offer(const int* rin_ptr, const int2* rin, const int* layer, int* cand,
+                       unsigned char* touched, const int* fin, unsigned f_cnt, Ctl* ctl,
+                       hipStream_t st)
 {
     if (f_cnt == 0) return;
-    const unsigned per = list_per_block(f_cnt);
-    const unsigned grid = (unsigned)(((int64_t)f_cnt + per - 1) / per);
-    k_conn_push<<<grid, kWG, 0, st>>>(rin_ptr, rin_src, rin_edge, layer, cand, fin, f_cnt, per,
-                                      fout, fout_cnt);
-    k_conn_push_fin<<<2048, kWG, 0, st>>>(k, pi, layer, cand, fout, fout_cnt);
+    constexpr int G = 8;
+    k_conn_offer<G><<<stride_grid((int64_t)f_cnt * G), kWG, 0, st>>>(rin_ptr, rin, layer, cand,
+                                                                    touched, fin, f_cnt, ctl);
+}
+
+void launch_conn_collect(int k, int n, unsigned char* touched, int* cand, int* pi, int* layer,
+                         int* fout, unsigned* fout_cnt, hipStream_t st)
+{
+    const unsigned grid = (unsigned)(((int64_t)n + kCollectVerts - 1) / kCollectVerts);
+    k_conn_collect<<<grid, kWG, 0, st>>>(k, n, touched, cand, pi, layer, fout, fout_cnt);
 }
 
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
-                      unsigned* tot, int* rin_ptr, int* rin_src, int* rin_edge, int* cand,
+                      unsigned* tot, int* rin_ptr, int2* rin, int* cand, unsigned char* touched,
                       hipStream_t st)
 {
     const int64_t len = (int64_t)n + 1;
@@ -916,8 +980,10 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
     k_scan_b<<<1, 1024, 0, st>>>(nb, tot);
     k_scan_c<<<stride_grid(len), kWG, 0, st>>>(len, (unsigned*)rin_ptr, tot);
     k_copy_u32<<<stride_grid(n), kWG, 0, st>>>(n, (const unsigned*)rin_ptr, deg);
-    k_rev_fill<<<stride_grid(n), kWG, 0, st>>>(n, row_ptr, col, deg, rin_src, rin_edge);
+    k_rev_fill<<<stride_grid(n), kWG, 0, st>>>(n, row_ptr, col, deg, rin);
     k_fill_u32<<<stride_grid(n), kWG, 0, st>>>(n, (unsigned*)cand, (unsigned)INT32_MAX);
+    const int64_t words = ((int64_t)n + 3) / 4;
+    k_fill_u32<<<stride_grid(words), kWG, 0, st>>>(words, (unsigned*)touched, 0u);
 }
 
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,

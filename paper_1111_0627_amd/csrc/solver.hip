@@ -60,9 +60,10 @@ struct Ws {
     unsigned* rdeg;      // reverse CSR: in-degree, then fill cursor (n+1)
     unsigned* stot;      // prefix-sum block totals
     int* rin_ptr;        // reverse CSR offsets (n+1)
-    int* rin_src;        // reverse CSR: source of each in-edge (m)
-    int* rin_edge;       // reverse CSR: CSR position of each in-edge (m)
+    int2* rin;           // reverse CSR entries (source, CSR position) (m)
     int* cand;           // push rounds: best edge offered so far
+    unsigned char* touched;  // push rounds: offered this round
+    void* sel;           // select: per-block best candidates
     long long* wsum;     // per-cycle weight sums, keyed by rep
     unsigned* lcnt;      // per-cycle lengths, keyed by rep
     int* cyc;            // cycle heads
@@ -98,9 +99,10 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.rdeg = (unsigned*)take(4 * (N + 1));
     w.stot = (unsigned*)take(4 * ((N + 1) / 2048 + 2));
     w.rin_ptr = (int*)take(4 * (N + 1));
-    w.rin_src = (int*)take(4 * M);
-    w.rin_edge = (int*)take(4 * M);
+    w.rin = (int2*)take(8 * M);
     w.cand = (int*)take(4 * N);
+    w.touched = (unsigned char*)take(N + 16);
+    w.sel = take(32 * ocm::kSelectParts);
     w.wsum = (long long*)take(8 * N);
     w.lcnt = (unsigned*)take(4 * N);
     w.cyc = (int*)take(4 * N);
@@ -133,6 +135,10 @@ struct Prof {
         (void)hipEventRecord(recs[open].b, st);
         open = -1;
     }
+    void bytes(int cls, double b)
+    {
+        if (out) out->bytes[cls] += b;
+    }
     void finish()
     {
         if (!out) return;
@@ -161,11 +167,15 @@ struct Ctx {
     Ctl h;               // host copy of the control block
     Prof prof;
     int G;               // lanes per vertex in the sweep
+    int sw;              // bytes per weight
     unsigned sweep_grid;
     int jump_rounds = 0;
     int connect_rounds = 0;
     int connect_mode = 0;   // 0 auto, 1 pull only, 2 push only
     bool rev_built = false;
+    int64_t push_frontier = 0;
+    int general_iters = 0;
+    int value_rounds = 0;
 };
 
 // Push rounds pay off once many vertices are unattached and the frontier is
@@ -220,6 +230,7 @@ ocm_status setup(Ctx& c, const ocm_graph* g, int neg, void* ws, size_t ws_bytes,
     c.col = g->col;
     c.w = g->w;
     c.wtype = g->wtype;
+    c.sw = g->wtype == OCM_W_I64 ? 8 : 4;
     c.neg = neg;
     c.st = (hipStream_t)stream;
     c.ws = carve(nullptr, g->n, g->m);
@@ -236,9 +247,10 @@ ocm_status setup(Ctx& c, const ocm_graph* g, int neg, void* ws, size_t ws_bytes,
 ocm_status validate(Ctx& c, int check_csr)
 {
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrAll | ocm::kClrCount | ocm::kClrChanged, c.st);
-    c.prof.begin(OCM_PH_VALIDATE);
+    c.prof.begin(OCM_K_VALIDATE);
     ocm::launch_validate(c.n, c.m, c.row_ptr, c.col, c.w, c.wtype, check_csr, c.ws.ctl, c.st);
     c.prof.end();
+    c.prof.bytes(OCM_K_VALIDATE, 4.0 * (c.n + 1) + (check_csr ? 4.0 * c.m : 0.0) + c.sw * (double)c.m);
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
     if (c.h.err & ocm::kErrBadCsr) return fail(OCM_E_BAD_CSR, "malformed CSR");
@@ -264,11 +276,22 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     a.pi = pi;
     a.onC = onC;
     a.ctl = c.ws.ctl;
-    c.prof.begin(tie ? OCM_PH_RESULT : OCM_PH_SWEEP);
+    const int cls = tie ? OCM_K_TIESCAN : OCM_K_SWEEP;
+    c.prof.begin(cls);
     ocm::launch_sweep(a, c.w, c.wtype, c.G, first, tie, c.sweep_grid, c.st);
     c.prof.end();
     HIP_TRY(hipGetLastError());
-    return read_ctl(c);
+    OCM_TRY(read_ctl(c));
+    // col + w per edge, row_ptr per vertex; after the first sweep also the
+    // gathered V per edge and the own V per vertex; the tie scan reads pi;
+    // policy writes of changed vertices
+    const double n = c.n, m = c.m;
+    double b = m * (4.0 + c.sw) + 4.0 * (n + 1);
+    if (!first) b += 8.0 * m + 8.0 * n;
+    if (tie) b += 4.0 * n;
+    else b += 4.0 * (double)c.h.changed;
+    c.prof.bytes(cls, b);
+    return OCM_OK;
 }
 
 // Cycles of the policy graph: rep and on_cycle for every vertex.
@@ -278,14 +301,22 @@ ocm_status phase_cycles(Ctx& c, const int* pi, int* rep, unsigned char* onc)
     auto* P1 = (unsigned long long*)c.ws.Q[1];
     int K = 0;
     while ((int64_t(1) << K) < c.n) ++K;
-    c.prof.begin(OCM_PH_CYCLES);
+    const double n = c.n;
+    c.prof.begin(OCM_K_CYCLES);
     ocm::launch_pj_init(c.n, c.col, pi, c.ws.succ, P0, onc, c.st);
+    c.prof.end();
+    c.prof.bytes(OCM_K_CYCLES, 21.0 * n);   // pi, col[pi], succ, packed entry, on-cycle
     for (int k = 0; k < K; ++k) {
+        c.prof.begin(OCM_K_CYCLES);
         ocm::launch_pj_round(c.n, P0, P1, c.st);
+        c.prof.end();
+        c.prof.bytes(OCM_K_CYCLES, 24.0 * n);   // own entry, gathered entry, new entry
         std::swap(P0, P1);
     }
+    c.prof.begin(OCM_K_CYCLES);
     ocm::launch_pj_final(c.n, P0, rep, onc, c.st);
     c.prof.end();
+    c.prof.bytes(OCM_K_CYCLES, 21.0 * n);
     c.jump_rounds += K;
     HIP_TRY(hipGetLastError());
     return OCM_OK;
@@ -295,11 +326,12 @@ ocm_status phase_cycles(Ctx& c, const int* pi, int* rep, unsigned char* onc)
 ocm_status phase_select(Ctx& c, const int* pi, const int* rep, const unsigned char* onc)
 {
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrCount, c.st);
-    c.prof.begin(OCM_PH_SELECT);
+    c.prof.begin(OCM_K_SELECT);
     ocm::launch_cyc_zero(c.n, rep, onc, c.ws.wsum, c.ws.lcnt, c.ws.cyc, c.ws.ctl, c.st);
     ocm::launch_cyc_sum(c.n, rep, onc, pi, c.w, c.wtype, c.neg, c.ws.wsum, c.ws.lcnt, c.st);
-    ocm::launch_select(c.ws.cyc, c.ws.wsum, c.ws.lcnt, c.ws.ctl, c.st);
+    ocm::launch_select(c.ws.cyc, c.ws.wsum, c.ws.lcnt, c.ws.ctl, c.ws.sel, c.st);
     c.prof.end();
+    c.prof.bytes(OCM_K_SELECT, 6.0 * c.n);   // rep and on-cycle flags, twice
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
     if (c.h.ncyc == 0 || c.h.s < 0) return fail(OCM_E_HIP, "no policy cycle found");
@@ -313,12 +345,14 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
 {
     Ws& w = c.ws;
     ocm::launch_ctl_clear(w.ctl, ocm::kClrCount, c.st);
-    c.prof.begin(OCM_PH_CONNECT);
+    c.prof.begin(OCM_K_CONN_PULL);
     ocm::launch_conn_init(c.n, rep, onc, s, layer, onC, w.list[0], &w.ctl->ucnt[0], w.flist[0],
                           &w.ctl->fcnt[0], c.st);
     c.prof.end();
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
+    c.prof.bytes(OCM_K_CONN_PULL, 10.0 * c.n + 4.0 * ((double)c.h.ucnt[0] + c.h.fcnt[0]));
+    unsigned long long pe0 = c.h.pedges, le0 = c.h.ledges;
     unsigned left = c.h.ucnt[0], ulen = left, front = c.h.fcnt[0];
     int ua = 0, fa = 0, k = 0;
     ocm_status rc = OCM_OK;
@@ -330,25 +364,52 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
         else if (c.connect_mode == 0)
             push = left >= kPushMinUnattached && (uint64_t)front * 4 < left;
         if (push && !c.rev_built) {
-            c.prof.begin(OCM_PH_CONNECT);
-            ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr,
-                                  w.rin_src, w.rin_edge, w.cand, c.st);
+            c.prof.begin(OCM_K_REVERSE);
+            ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr, w.rin,
+                                  w.cand, w.touched, c.st);
             c.prof.end();
+            // count: col + counter per edge; scan and cursor copy; fill: row_ptr,
+            // col, cursor and the 8-byte entry per edge; cand and touched fills
+            c.prof.bytes(OCM_K_REVERSE, 24.0 * c.m + 33.0 * c.n);
             HIP_TRY(hipGetLastError());
             c.rev_built = true;
         }
         ocm::launch_zero2(&w.ctl->ucnt[ub], &w.ctl->fcnt[fb], c.st);
-        c.prof.begin(OCM_PH_CONNECT);
-        if (push)
-            ocm::launch_conn_push(k, w.rin_ptr, w.rin_src, w.rin_edge, layer, pi, w.cand,
-                                  w.flist[fa], front, w.flist[fb], &w.ctl->fcnt[fb], c.st);
-        else
+        if (push) {
+            c.prof.begin(OCM_K_CONN_OFFER);
+            ocm::launch_conn_offer(w.rin_ptr, w.rin, layer, w.cand, w.touched, w.flist[fa], front,
+                                   w.ctl, c.st);
+            c.prof.end();
+            c.prof.begin(OCM_K_CONN_COLLECT);
+            ocm::launch_conn_collect(k, c.n, w.touched, w.cand, pi, layer, w.flist[fb],
+                                     &w.ctl->fcnt[fb], c.st);
+            c.prof.end();
+            c.push_frontier += front;
+        } else {
+            c.prof.begin(OCM_K_CONN_PULL);
             ocm::launch_conn_pull(k, c.row_ptr, c.col, layer, pi, w.list[ua], ulen, w.list[ub],
-                                  &w.ctl->ucnt[ub], w.flist[fb], &w.ctl->fcnt[fb], c.st);
-        c.prof.end();
+                                  &w.ctl->ucnt[ub], w.flist[fb], &w.ctl->fcnt[fb], &w.ctl->ledges,
+                                  c.st);
+            c.prof.end();
+        }
         HIP_TRY(hipGetLastError());
         OCM_TRY(read_ctl(c));
         const unsigned got = c.h.fcnt[fb];
+        if (push) {
+            // offer: frontier entry and offsets, then per in-edge the (u, e)
+            // entry and u's layer; collect: the touched bytes plus cand, pi,
+            // layer, cand reset, touched reset and list entry per attached vertex
+            const double E = (double)(c.h.pedges - pe0);
+            c.prof.bytes(OCM_K_CONN_OFFER, 12.0 * front + 12.0 * E);
+            c.prof.bytes(OCM_K_CONN_COLLECT, (double)c.n + 21.0 * got);
+        } else {
+            // list entry, offsets and own layer per listed vertex; col + layer
+            // per scanned edge; pi, layer and list entries of the outcome
+            const double S = (double)(c.h.ledges - le0);
+            c.prof.bytes(OCM_K_CONN_PULL, 16.0 * ulen + 8.0 * S + 12.0 * got + 4.0 * c.h.ucnt[ub]);
+        }
+        pe0 = c.h.pedges;
+        le0 = c.h.ledges;
         if (got == 0) {
             rc = fail(OCM_E_NOT_STRONGLY_CONNECTED, "some vertex cannot reach the chosen cycle");
             break;
@@ -378,11 +439,12 @@ ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, 
 {
     if (stalled) *stalled = false;
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrCount, c.st);
-    const int ph = probe ? OCM_PH_FAST : OCM_PH_VALUES;
+    const int ph = probe ? OCM_K_FAST : OCM_K_VALUES;
     c.prof.begin(ph);
     ocm::launch_val_init(c.n, c.col, pi, c.w, c.wtype, c.neg, s, W, L, c.ws.succ, c.ws.Q[0],
                          c.ws.ctl, c.st);
     c.prof.end();
+    c.prof.bytes(ph, (28.0 + c.sw) * c.n);   // pi, col[pi], w[pi], succ, 16-byte entry
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
     unsigned act = c.h.active;
@@ -390,11 +452,13 @@ ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, 
     while (act > 0) {
         if (k > 64) return fail(OCM_E_HIP, "value propagation did not converge");
         ++k;
+        ++c.value_rounds;
         const int b = a ^ 1;
         HIP_TRY(hipMemsetAsync(&c.ws.ctl->active2, 0, sizeof(unsigned), c.st));
         c.prof.begin(ph);
         ocm::launch_val_round(c.n, s, c.ws.Q[a], c.ws.Q[b], &c.ws.ctl->active2, c.st);
         c.prof.end();
+        c.prof.bytes(ph, 32.0 * c.n + 16.0 * act);   // own + new entry; gather if unfinished
         HIP_TRY(hipGetLastError());
         OCM_TRY(read_ctl(c));
         const unsigned now = c.h.active2;
@@ -415,6 +479,7 @@ ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, 
     c.prof.begin(ph);
     ocm::launch_val_final(c.n, c.ws.Q[a], V, c.ws.ctl, c.st);
     c.prof.end();
+    c.prof.bytes(ph, 24.0 * c.n);
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
     if (c.h.overflow) return fail(OCM_E_OVERFLOW, "a value left [-2^62, 2^62]");
@@ -481,6 +546,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
                 continue;
             }
         }
+        ++c.general_iters;
         rc = phase_cycles(c, w.pi, w.rep, w.onc);
         if (rc != OCM_OK) break;
         rc = phase_select(c, w.pi, w.rep, w.onc);
@@ -498,6 +564,10 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     out->connect_rounds = c.connect_rounds;
     out->jump_rounds = c.jump_rounds;
     out->fast_iters = fast;
+    out->general_iters = c.general_iters;
+    out->value_rounds = c.value_rounds;
+    out->push_frontier = c.push_frontier;
+    if (read_ctl(c) == OCM_OK) out->push_in_edges = (int64_t)c.h.pedges;
     if (rc != OCM_OK) {
         c.prof.finish();
         return rc;
@@ -513,9 +583,10 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
         c.prof.finish();
         return fail(OCM_E_CAPACITY, "cycle_cap smaller than the critical cycle");
     }
-    c.prof.begin(OCM_PH_RESULT);
+    c.prof.begin(OCM_K_RESULT);
     ocm::launch_cycle_list(c.n, s, L, w.onC, w.pi, w.Q[qf], cycle_edges, c.st);
     c.prof.end();
+    c.prof.bytes(OCM_K_RESULT, (double)c.n + 28.0 * L);
     HIP_TRY(hipGetLastError());
     if (o.tie_check) {
         rc = phase_sweep(c, false, true, w.V, W, L, w.pi, nullptr);

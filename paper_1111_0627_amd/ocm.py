@@ -32,7 +32,8 @@ OCM_E_HIP = -9
 OCM_W_I32, OCM_W_I64 = 0, 1
 OCM_F_TIE, OCM_F_TIE_UNCHECKED, OCM_F_TIGHT_EDGES = 1, 2, 4
 
-PHASES = ("validate", "sweep", "cycles", "select", "connect", "values", "fast", "result")
+PHASES = ("validate", "sweep", "tiescan", "cycles", "select", "conn_pull", "conn_offer",
+          "conn_collect", "reverse", "values", "fast", "result")
 
 
 class OCMError(RuntimeError):
@@ -52,14 +53,18 @@ class _Result(C.Structure):
                 ("source", C.c_int32), ("iterations", C.c_int32), ("flags", C.c_uint32),
                 ("connect_rounds", C.c_int32), ("jump_rounds", C.c_int32),
                 ("fast_iters", C.c_int32), ("W", C.c_int64), ("L", C.c_int64),
-                ("tight_edges", C.c_int64)]
+                ("tight_edges", C.c_int64), ("push_frontier", C.c_int64),
+                ("push_in_edges", C.c_int64), ("general_iters", C.c_int32),
+                ("value_rounds", C.c_int32)]
 
 
 class Profile(C.Structure):
-    _fields_ = [("ms", C.c_double * len(PHASES)), ("launches", C.c_int32 * len(PHASES))]
+    _fields_ = [("ms", C.c_double * len(PHASES)), ("launches", C.c_int32 * len(PHASES)),
+                ("bytes", C.c_double * len(PHASES))]
 
     def as_dict(self):
-        return {p: (self.ms[i], self.launches[i]) for i, p in enumerate(PHASES)}
+        """{class: (milliseconds, launches, algorithmic bytes)}"""
+        return {p: (self.ms[i], self.launches[i], self.bytes[i]) for i, p in enumerate(PHASES)}
 
 
 class Options(C.Structure):
@@ -170,6 +175,7 @@ class Result:
     connect_rounds: int
     jump_rounds: int
     fast_iters: int
+    counters: dict = dataclasses.field(default_factory=dict)
     policy: torch.Tensor | None = None
     potential: torch.Tensor | None = None
     profile: dict | None = None
@@ -217,9 +223,12 @@ def _solve(fn, row_ptr, col, w, want_policy, want_potential, profile, **opt) -> 
     res = _Result()
     _check(fn(C.byref(g), C.byref(o), C.c_void_p(ws.data_ptr()), ws.numel(),
               C.c_void_p(cyc.data_ptr()), g.n, C.byref(res), _stream()))
+    counters = dict(push_frontier=res.push_frontier, push_in_edges=res.push_in_edges,
+                    general_iters=res.general_iters, value_rounds=res.value_rounds)
     return Result(res.p, res.q, cyc[:res.cycle_len], res.source, res.iterations, res.flags,
                   res.W, res.L, res.tight_edges, res.connect_rounds, res.jump_rounds,
-                  res.fast_iters, pol, pot, prof.as_dict() if prof is not None else None)
+                  res.fast_iters, counters, pol, pot,
+                  prof.as_dict() if prof is not None else None)
 
 
 def min_cycle_mean(row_ptr, col, w, *, want_policy=False, want_potential=False,
