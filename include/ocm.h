@@ -136,6 +136,12 @@ typedef struct {
     int32_t connect_mode;      /* rebuild rounds: 0 = pick pull or push per
                                   round, 1 = pull only, 2 = push only (same
                                   results)                                     */
+    const int32_t *init_policy;/* device int32[n] or NULL: warm start.  The
+                                  given policy (one out-edge position per
+                                  vertex) replaces the first sweep; the optimum
+                                  is the same, the trajectory (and, with ties,
+                                  the cycle) may differ.  An entry outside its
+                                  vertex's edge range gives OCM_E_INVALID_ARG. */
     int32_t *policy_out;       /* device int32[n] or NULL: final policy (edge positions) */
     int64_t *potential_out;    /* device int64[n] or NULL: final values scaled by L */
     ocm_profile *profile;      /* host, or NULL                                */
@@ -212,6 +218,63 @@ ocm_status ocm_phase_values(const ocm_graph *g, int32_t neg, const int32_t *pi,
                             int32_t s, int64_t W, int64_t L, int64_t *V,
                             void *ws, size_t ws_bytes, int32_t *rounds,
                             void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched graphs: concurrent regions (Section 3.3, Alg. 5).               */
+/* ---------------------------------------------------------------------- */
+
+/* G independent graphs given as one disjoint-union CSR `u` (global vertex
+ * ids): graph g owns vertices [vptr[g], vptr[g+1]) and edges [eptr[g],
+ * eptr[g+1]) and no edge may leave its graph.  vptr and eptr are HOST
+ * arrays of G+1 entries (vptr[0] = eptr[0] = 0, vptr[G] = n, eptr[G] = m,
+ * every graph with >= 1 vertex and edge).  Every graph is solved with the
+ * rules of ocm_min / ocm_max, concurrently: each keeps its own lambda, its
+ * own minimum-mean vote and its own termination (finished graphs are retired
+ * from all further kernels), so graph g's result equals ocm_min on graph g
+ * alone (Prop. 2.2 makes min_g p_g/q_g the optimum of the union).
+ *   p, q, iters, flags, status   HOST arrays of G entries (status: OCM_OK or
+ *                                the graph's own error; may be NULL);
+ *   cycle_ptr                    HOST array of G+1 entries: graph g's cycle
+ *                                is cycle_edges[cycle_ptr[g] .. cycle_ptr[g+1]);
+ *   cycle_edges                  DEVICE int32[cycle_cap] (<= n entries needed):
+ *                                CSR positions in the union, from each
+ *                                graph's source.
+ * The uniqueness test runs the exact quick tests only; a graph they cannot
+ * decide gets OCM_F_TIE_UNCHECKED.  o->init_policy must be NULL.  Returns
+ * OCM_OK, the first failing graph's status, or a call-wide error. */
+size_t ocm_batched_workspace_size(int64_t G, const int64_t *vptr, const int64_t *eptr,
+                                  const ocm_graph *u, const ocm_options *o);
+ocm_status ocm_min_batched(int64_t G, const int64_t *vptr, const int64_t *eptr,
+                           const ocm_graph *u, const ocm_options *o, void *ws, size_t ws_bytes,
+                           int64_t *p, int64_t *q, int64_t *cycle_ptr, int32_t *cycle_edges,
+                           int64_t cycle_cap, int32_t *iters, uint32_t *flags, int32_t *status,
+                           void *stream);
+ocm_status ocm_max_batched(int64_t G, const int64_t *vptr, const int64_t *eptr,
+                           const ocm_graph *u, const ocm_options *o, void *ws, size_t ws_bytes,
+                           int64_t *p, int64_t *q, int64_t *cycle_ptr, int32_t *cycle_edges,
+                           int64_t cycle_cap, int32_t *iters, uint32_t *flags, int32_t *status,
+                           void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Differentiation (not in the paper).  Away from ties the optimum is a    */
+/* smooth function of w with d(optimum)/d(w_e) = 1/|C| for the edges of   */
+/* the critical cycle C and 0 for every other edge (the same holds for the */
+/* maximum).                                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Converts float64 weights to int64 on the device.  Every weight must be an
+ * integer with |w| < 2^53, else OCM_E_INVALID_ARG.  ws: >= 256 bytes of
+ * device scratch.  Synchronises `stream`. */
+ocm_status ocm_weights_from_f64(int64_t m, const double *w_f64, int64_t *w_i64, void *ws,
+                                size_t ws_bytes, void *stream);
+
+/* Adjoint scatter: grad_w[e] = *grad_out / cycle_len for the cycle_len edge
+ * positions in cycle_edges, 0 for every other e < m (zero-filled first).
+ * grad_out points to one double in device memory (the incoming gradient), so
+ * the call does not synchronise; the quotient is one correctly rounded IEEE
+ * division. */
+ocm_status ocm_adjoint_scatter(int64_t m, const int32_t *cycle_edges, int64_t cycle_len,
+                               const double *grad_out, double *grad_w, void *stream);
 
 const char *ocm_status_string(ocm_status s);
 const char *ocm_last_error(void);

@@ -1,0 +1,1353 @@
+// Batched exact optimal cycle mean: many independent graphs solved together.
+//
+// Section 3.3 runs the computation concurrently on all strongly connected
+// components ("regions") of one graph, with a per-region lambda, a
+// per-region minimum vote (Alg. 5) and per-region work flags that retire
+// finished regions.  Here the regions are the graphs of a disjoint-union CSR:
+// graph g owns vertices [vptr[g], vptr[g+1]) and edges [eptr[g], eptr[g+1]).
+// Each graph follows exactly the rules of the single-graph solver, so its
+// result (value, cycle, iteration count) equals a separate ocm_min call on
+// it (Prop. 2.2 gives the optimum of the union as the minimum over graphs).
+//
+// Work distribution: vertex kernels run over a list of chunks (graph, first
+// vertex) covering only the graphs in the phase at hand, so retired graphs
+// cost nothing.  The chunk size and the lanes per vertex of the sweep are
+// the batch schedule (chosen by the autotuner or given by the caller).
+#include "ocm.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "device_util.h"
+#include "kernels.h"
+
+namespace ocm {
+namespace b {
+
+// per-graph modes
+constexpr int kDone = 0;      // converged or failed
+constexpr int kActive = 1;    // next: a sweep
+constexpr int kFast = 2;      // next: values with the old cycle (fast path)
+constexpr int kGeneral = 3;   // next: cycles, select, rebuild, values
+
+struct GArrays {              // device arrays with one entry per graph
+    long long* W;
+    long long* L;
+    int* s;
+    int* iter;
+    int* mode;
+    int* status;
+    int* best;                // vote: rep of the best cycle so far
+    unsigned* changed;
+    unsigned* cbroken;
+    unsigned* vrun;           // values: 1 while the graph is propagating
+    unsigned* vact;           // values: some vertex unfinished after the round
+    unsigned* vprog;          // values: some vertex finished in the round
+    unsigned* ovf;
+    unsigned char* have_c;
+    unsigned long long* tight;
+    unsigned long long* certain;
+    unsigned long long* nondec;
+    long long* vptr;          // G+1
+    long long* eptr;          // G+1
+    unsigned* ccnt;           // chunk counts / offsets scratch
+    unsigned* coff;
+    unsigned* ctot;
+};
+
+struct BCtl {
+    unsigned nchunks;
+    unsigned nactive, nfast, ngeneral, ndone;
+    unsigned vrunning;
+    unsigned ncyc;
+    unsigned ucnt[2], fcnt[2];
+    unsigned overflow;
+    unsigned long long pedges, ledges;
+};
+
+__device__ __forceinline__ bool chunk_range(const int2* __restrict__ chunks, const unsigned* nch,
+                                            const long long* __restrict__ vptr, int T, int& g,
+                                            int64_t& v0, int64_t& v1)
+{
+    if (blockIdx.x >= *nch) return false;
+    const int2 c = chunks[blockIdx.x];
+    g = c.x;
+    v0 = c.y;
+    const int64_t end = vptr[g + 1];
+    v1 = v0 + T < end ? v0 + T : end;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// chunk lists
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_chunk_count(int G, const int* __restrict__ mode, int want,
+                                                     const long long* __restrict__ vptr, int T,
+                                                     unsigned* __restrict__ cnt)
+{
+    for (int g = blockIdx.x * kWG + threadIdx.x; g <= G; g += gridDim.x * kWG) {
+        if (g == G) {
+            cnt[g] = 0;
+            continue;
+        }
+        // want: a mode, -1 = every graph not done, -2 = every graph
+        const bool sel = want == -2 ? true : want == -1 ? mode[g] != kDone : mode[g] == want;
+        const long long n = vptr[g + 1] - vptr[g];
+        cnt[g] = sel ? (unsigned)((n + T - 1) / T) : 0u;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_chunk_fill(int G, const unsigned* __restrict__ cnt,
+                                                    const unsigned* __restrict__ off,
+                                                    const long long* __restrict__ vptr, int T,
+                                                    int2* __restrict__ chunks, unsigned* nch)
+{
+    for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
+        const unsigned o = off[g], c = cnt[g];
+        for (unsigned i = 0; i < c; ++i) chunks[o + i] = make_int2(g, (int)(vptr[g] + (long long)i * T));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nch = off[G];
+}
+
+// ---------------------------------------------------------------------------
+// validation of the disjoint union: every edge stays inside its graph
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_check_union(int G, const long long* __restrict__ vptr,
+                                                     const long long* __restrict__ eptr,
+                                                     const int* __restrict__ row_ptr,
+                                                     const int* __restrict__ col,
+                                                     const int2* __restrict__ chunks,
+                                                     const unsigned* nch, int T,
+                                                     unsigned* bad)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, vptr, T, g, v0, v1)) return;
+    unsigned err = 0;
+    const long long lo = vptr[g], hi = vptr[g + 1];
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+        const int a = row_ptr[v], b = row_ptr[v + 1];
+        if (v == lo && a != eptr[g]) err = 1;
+        if (v + 1 == hi && b != eptr[g + 1]) err = 1;
+        for (int e = a; e < b; ++e) {
+            const int c = col[e];
+            if (c < lo || c >= hi) err = 1;
+        }
+    }
+    if (__ballot(err != 0) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// sweep over the chunks of active graphs (SPFPassIter per region)
+// ---------------------------------------------------------------------------
+template <int G, typename WT, bool TIE>
+__global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
+                                               const unsigned* nch, int T, GArrays ga,
+                                               const int* __restrict__ row_ptr,
+                                               const int* __restrict__ col,
+                                               const WT* __restrict__ w, int neg,
+                                               const long long* __restrict__ V,
+                                               int* __restrict__ pi,
+                                               const unsigned char* __restrict__ onC,
+                                               const int* __restrict__ hop)
+{
+    constexpr int VPB = kWG / G;
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    const bool first = !TIE && ga.iter[g] == 0;
+    const long long L = first ? 1 : ga.L[g];
+    const long long W = first ? 0 : ga.W[g];
+    const int lane = threadIdx.x & (G - 1);
+    unsigned long long cnt = 0, certain = 0, nondec = 0;
+    unsigned brk = 0;
+    for (int64_t vb = v0; vb < v1; vb += VPB) {
+        const int64_t v = vb + threadIdx.x / G;
+        const bool live = v < v1;
+        int beg = 0, end = 0, cur = -1;
+        long long own = 0;
+        if (live) {
+            beg = row_ptr[v];
+            end = row_ptr[v + 1];
+            if (!first) own = V[v];
+            if (TIE) cur = pi[v];
+        }
+        long long best = INT64_MAX;
+        int bpos = INT32_MAX;
+        for (int e = beg + lane; e < end; e += G) {
+            const long long we = wval(w, e, neg);
+            const long long key = first ? we : V[col[e]] + L * we - W;
+            if (TIE) {
+                if (key == own && e != cur) {
+                    cnt++;
+                    if (col[e] == v || onC[v]) certain++;
+                    if (hop[col[e]] >= hop[v]) nondec++;
+                }
+            } else if (key < best) {
+                best = key;
+                bpos = e;
+            }
+        }
+        if (TIE) continue;
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+            const long long ob = __shfl_xor(best, off, G);
+            const int op = __shfl_xor(bpos, off, G);
+            if (ob < best || (ob == best && op < bpos)) {
+                best = ob;
+                bpos = op;
+            }
+        }
+        if (live && lane == 0 && (first || best < own)) {
+            pi[v] = bpos;
+            cnt++;
+            if (!first && onC[v]) brk = 1;
+        }
+    }
+    cnt = block_sum_u64(cnt);
+    if (TIE) {
+        certain = block_sum_u64(certain);
+        nondec = block_sum_u64(nondec);
+        if (threadIdx.x == 0) {
+            if (cnt) atomicAdd(&ga.tight[g], cnt);
+            if (certain) atomicAdd(&ga.certain[g], certain);
+            if (nondec) atomicAdd(&ga.nondec[g], nondec);
+        }
+    } else {
+        const unsigned long long bb = block_sum_u64(brk);
+        if (threadIdx.x == 0) {
+            if (cnt) atomicAdd(&ga.changed[g], (unsigned)(cnt > 0xffffffffull ? 0xffffffffu : cnt));
+            if (bb) atomicOr(&ga.cbroken[g], 1u);
+        }
+    }
+}
+
+// After the sweep: converged graphs retire; the others take the fast path
+// (C intact) or the general phases.
+__global__ __launch_bounds__(kWG) void k_after_sweep(int G, GArrays ga, int max_iters,
+                                                     BCtl* bc)
+{
+    unsigned na = 0, nf = 0, ng = 0;
+    for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
+        if (ga.mode[g] != kActive) continue;
+        const int it = ++ga.iter[g];
+        const unsigned ch = ga.changed[g];
+        ga.changed[g] = 0;
+        const unsigned cb = ga.cbroken[g];
+        ga.cbroken[g] = 0;
+        if (it >= 2 && ch == 0) {
+            ga.mode[g] = kDone;
+            continue;
+        }
+        if (max_iters > 0 && it >= max_iters) {
+            ga.mode[g] = kDone;
+            ga.status[g] = OCM_E_NOT_CONVERGED;
+            continue;
+        }
+        ++na;
+        if (ga.have_c[g] && !cb) {
+            ga.mode[g] = kFast;
+            ++nf;
+        } else {
+            ga.mode[g] = kGeneral;
+            ++ng;
+        }
+    }
+    const unsigned long long a = block_sum_u64(na), f = block_sum_u64(nf), q = block_sum_u64(ng);
+    if (threadIdx.x == 0) {
+        if (a) atomicAdd(&bc->nactive, (unsigned)a);
+        if (f) atomicAdd(&bc->nfast, (unsigned)f);
+        if (q) atomicAdd(&bc->ngeneral, (unsigned)q);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// values: pointer jumping toward each graph's source
+// ---------------------------------------------------------------------------
+template <typename WT>
+__global__ __launch_bounds__(kWG) void k_val_init(const int2* __restrict__ chunks,
+                                                  const unsigned* nch, int T, GArrays ga,
+                                                  const int* __restrict__ col,
+                                                  const int* __restrict__ pi,
+                                                  const WT* __restrict__ w, int neg,
+                                                  int* __restrict__ succ, Jmp* __restrict__ Q)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    const int s = ga.s[g];
+    const long long W = ga.W[g], L = ga.L[g];
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+        const int e = pi[v];
+        const int t = col[e];
+        succ[v] = t;
+        Jmp q;
+        if (v == s) {
+            q.D = 0;
+            q.J = s;
+            q.H = 0;
+        } else {
+            q.D = L * wval(w, e, neg) - W;
+            q.J = t;
+            q.H = 1;
+        }
+        Q[v] = q;
+    }
+    if (threadIdx.x == 0) {
+        ga.vrun[g] = 1;
+        ga.ovf[g] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chunks,
+                                                   const unsigned* nch, int T, GArrays ga,
+                                                   const Jmp* __restrict__ Qin,
+                                                   Jmp* __restrict__ Qout)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    const int s = ga.s[g];
+    const bool run = ga.vrun[g] != 0;
+    unsigned act = 0, prog = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+        Jmp q = Qin[v];
+        if (run && q.J != s) {
+            const Jmp r = Qin[q.J];
+            long long d;
+            if (__builtin_add_overflow(q.D, r.D, &d)) {
+                d = 0;
+                q.H |= kHopOverflow;
+            }
+            q.D = d;
+            q.J = r.J;
+            q.H = ((q.H & ~kHopOverflow) + (r.H & ~kHopOverflow)) | ((q.H | r.H) & kHopOverflow);
+            if (q.J == s) prog = 1;
+            else act = 1;
+        }
+        Qout[v] = q;
+    }
+    const unsigned long long a = block_sum_u64(act), p = block_sum_u64(prog);
+    if (threadIdx.x == 0) {
+        if (a) atomicOr(&ga.vact[g], 1u);
+        if (p) atomicOr(&ga.vprog[g], 1u);
+    }
+}
+
+// After a value round: a graph is finished when no vertex is unfinished; a
+// graph whose round finished nothing while vertices remain never reaches s
+// (fast path: C is no longer the only cycle).
+__global__ __launch_bounds__(kWG) void k_val_update(int G, GArrays ga, int want, BCtl* bc)
+{
+    unsigned running = 0;
+    for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
+        if (ga.mode[g] != want || !ga.vrun[g]) continue;
+        const unsigned a = ga.vact[g], p = ga.vprog[g];
+        ga.vact[g] = 0;
+        ga.vprog[g] = 0;
+        if (!a) {
+            ga.vrun[g] = 0;           // finished: values are ready
+        } else if (!p) {
+            ga.vrun[g] = 0;
+            if (want == kFast) ga.mode[g] = kGeneral;   // fall back
+            else {
+                ga.mode[g] = kDone;
+                ga.status[g] = OCM_E_NOT_STRONGLY_CONNECTED;
+            }
+        } else {
+            ++running;
+        }
+    }
+    const unsigned long long r = block_sum_u64(running);
+    if (threadIdx.x == 0 && r) atomicAdd(&bc->vrunning, (unsigned)r);
+}
+
+// First-round bookkeeping: a graph may already be finished after init.
+__global__ __launch_bounds__(kWG) void k_val_mark(const int2* __restrict__ chunks,
+                                                  const unsigned* nch, int T, GArrays ga,
+                                                  const Jmp* __restrict__ Q)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    const int s = ga.s[g];
+    unsigned act = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) act |= Q[v].J != s;
+    const unsigned long long a = block_sum_u64(act);
+    if (threadIdx.x == 0) {
+        if (a) atomicOr(&ga.vact[g], 1u);
+        atomicOr(&ga.vprog[g], 1u);
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chunks,
+                                                   const unsigned* nch, int T, GArrays ga,
+                                                   int want, const Jmp* __restrict__ Q,
+                                                   long long* __restrict__ V, int* __restrict__ hop)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    if (ga.mode[g] != want) return;   // fell back or failed
+    unsigned bad = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+        const Jmp q = Q[v];
+        V[v] = q.D;
+        hop[v] = (int)(q.H & ~kHopOverflow);
+        if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
+    }
+    const unsigned long long b = block_sum_u64(bad);
+    if (threadIdx.x == 0) {
+        if (b) {
+            ga.mode[g] = kDone;
+            ga.status[g] = OCM_E_OVERFLOW;
+        }
+    }
+}
+
+// fast or general graph whose values are ready: back to sweeping
+__global__ __launch_bounds__(kWG) void k_values_done(int G, GArrays ga, int want)
+{
+    for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
+        if (ga.mode[g] != want) continue;
+        ga.mode[g] = kActive;
+        ga.have_c[g] = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cycles of the policy graph (pointer jumping), per-cycle sums, vote
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_pj_init(const int2* __restrict__ chunks,
+                                                 const unsigned* nch, int T, GArrays ga,
+                                                 const int* __restrict__ col,
+                                                 const int* __restrict__ pi,
+                                                 unsigned long long* __restrict__ P,
+                                                 unsigned char* __restrict__ onc)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+        const int s = col[pi[v]];
+        P[v] = ((unsigned long long)(unsigned)s << 32) | (unsigned)v;
+        onc[v] = 0;
+    }
+    if (threadIdx.x == 0) ga.best[g] = -1;
+}
+
+__global__ __launch_bounds__(kWG) void k_pj_round(const int2* __restrict__ chunks,
+                                                  const unsigned* nch, int T, GArrays ga,
+                                                  const unsigned long long* __restrict__ Pin,
+                                                  unsigned long long* __restrict__ Pout)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+        const unsigned long long p = Pin[v];
+        const unsigned long long q = Pin[(int)(p >> 32)];
+        const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
+        Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_pj_final(const int2* __restrict__ chunks,
+                                                  const unsigned* nch, int T, GArrays ga,
+                                                  const unsigned long long* __restrict__ P,
+                                                  int* __restrict__ rep,
+                                                  unsigned char* __restrict__ onc)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+        const int c = (int)(P[v] >> 32);
+        rep[v] = (int)(unsigned)P[c];
+        onc[c] = 1;
+    }
+}
+
+// cycle heads of general graphs: zero their sums and list (rep, graph)
+__global__ __launch_bounds__(kWG) void k_cyc_zero(const int2* __restrict__ chunks,
+                                                  const unsigned* nch, int T, GArrays ga,
+                                                  const int* __restrict__ rep,
+                                                  const unsigned char* __restrict__ onc,
+                                                  long long* __restrict__ wsum,
+                                                  unsigned* __restrict__ lcnt,
+                                                  int2* __restrict__ heads, BCtl* bc)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    for (int64_t vb = v0; vb < v1; vb += kWG) {
+        const int64_t v = vb + threadIdx.x;
+        const bool head = v < v1 && onc[v] && rep[v] == v;
+        if (head) {
+            wsum[v] = 0;
+            lcnt[v] = 0;
+        }
+        const unsigned long long mask = __ballot(head);
+        if (mask) {
+            const unsigned lane = threadIdx.x & 63;
+            const unsigned leader = (unsigned)__ffsll((long long)mask) - 1u;
+            unsigned base = 0;
+            if (lane == leader) base = atomicAdd(&bc->ncyc, (unsigned)__popcll(mask));
+            base = __shfl(base, (int)leader, 64);
+            if (head) heads[base + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2((int)v, g);
+        }
+    }
+}
+
+template <typename WT>
+__global__ __launch_bounds__(kWG) void k_cyc_sum(const int2* __restrict__ chunks,
+                                                 const unsigned* nch, int T, GArrays ga,
+                                                 const int* __restrict__ rep,
+                                                 const unsigned char* __restrict__ onc,
+                                                 const int* __restrict__ pi,
+                                                 const WT* __restrict__ w, int neg,
+                                                 long long* __restrict__ wsum,
+                                                 unsigned* __restrict__ lcnt)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+        if (!onc[v]) continue;
+        const int r = rep[v];
+        atomicAdd((unsigned long long*)&wsum[r], (unsigned long long)wval(w, pi[v], neg));
+        atomicAdd(&lcnt[r], 1u);
+    }
+}
+
+// a < b in the order (W/L, rep)
+__device__ __forceinline__ bool rep_less(int a, int b, const long long* __restrict__ wsum,
+                                         const unsigned* __restrict__ lcnt)
+{
+    const __int128 x = (__int128)wsum[a] * (long long)lcnt[b];
+    const __int128 y = (__int128)wsum[b] * (long long)lcnt[a];
+    if (x != y) return x < y;
+    return a < b;
+}
+
+// Region-specific minimum vote (Alg. 5) with the exact comparator: the
+// final value is the minimum whatever the order of the votes.
+__global__ __launch_bounds__(kWG) void k_vote(const int2* __restrict__ heads, const BCtl* bc,
+                                              GArrays ga, const long long* __restrict__ wsum,
+                                              const unsigned* __restrict__ lcnt)
+{
+    const unsigned nc = bc->ncyc;
+    for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < nc; i += gridDim.x * kWG) {
+        const int2 h = heads[i];
+        int cur = ga.best[h.y];
+        while (cur < 0 || rep_less(h.x, cur, wsum, lcnt)) {
+            const int prev = atomicCAS(&ga.best[h.y], cur, h.x);
+            if (prev == cur) break;
+            cur = prev;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_set_lambda(int G, GArrays ga,
+                                                    const long long* __restrict__ wsum,
+                                                    const unsigned* __restrict__ lcnt)
+{
+    for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
+        if (ga.mode[g] != kGeneral) continue;
+        const int r = ga.best[g];
+        if (r < 0) {
+            ga.mode[g] = kDone;
+            ga.status[g] = OCM_E_HIP;
+            continue;
+        }
+        ga.s[g] = r;
+        ga.W[g] = wsum[r];
+        ga.L[g] = (long long)lcnt[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// rebuild: keep each graph's chosen component, list the rest
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_conn_init(const int2* __restrict__ chunks,
+                                                   const unsigned* nch, int T, GArrays ga,
+                                                   const int* __restrict__ rep,
+                                                   const unsigned char* __restrict__ onc,
+                                                   int* __restrict__ layer,
+                                                   unsigned char* __restrict__ onC,
+                                                   int* __restrict__ ulist, unsigned* ucnt,
+                                                   int* __restrict__ flist, unsigned* fcnt)
+{
+    __shared__ int ubuf[kListItems], fbuf[kListItems];
+    __shared__ unsigned nu, nf;
+    if (threadIdx.x == 0) nu = nf = 0;
+    __syncthreads();
+    int g;
+    int64_t v0, v1;
+    const bool ok = chunk_range(chunks, nch, ga.vptr, T, g, v0, v1);
+    if (!ok) return;   // uniform per block
+    const int s = ga.s[g];
+    BlockList bu{ubuf, &nu}, bf{fbuf, &nf};
+    for (int64_t vb = v0; vb < v1; vb += kWG) {
+        const int64_t v = vb + threadIdx.x;
+        bool live = v < v1, comp = false;
+        if (live) {
+            comp = rep[v] == s;
+            layer[v] = comp ? 0 : -1;
+            onC[v] = (unsigned char)(comp && onc[v]);
+        }
+        blist_push(bu, live && !comp, (int)v);
+        blist_push(bf, live && comp, (int)v);
+    }
+    blist_flush(bu, ulist, ucnt);
+    blist_flush(bf, flist, fcnt);
+}
+
+// vertices left unattached: their graphs are not strongly connected
+__global__ __launch_bounds__(kWG) void k_conn_fail(int G, const long long* __restrict__ vptr,
+                                                   const int* __restrict__ ulist, unsigned cnt,
+                                                   const int* __restrict__ layer, GArrays ga)
+{
+    for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < cnt; i += gridDim.x * kWG) {
+        const int u = ulist[i];
+        if (layer[u] != -1) continue;
+        int lo = 0, hi = G - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (vptr[mid] <= u) lo = mid;
+            else hi = mid - 1;
+        }
+        ga.mode[lo] = kDone;
+        ga.status[lo] = OCM_E_NOT_STRONGLY_CONNECTED;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// results
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_cycle_list(const int2* __restrict__ chunks,
+                                                    const unsigned* nch, int T, GArrays ga,
+                                                    const long long* __restrict__ cptr,
+                                                    const unsigned char* __restrict__ onC,
+                                                    const int* __restrict__ pi,
+                                                    const int* __restrict__ hop,
+                                                    int* __restrict__ out)
+{
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    if (ga.status[g] != OCM_OK) return;
+    const int s = ga.s[g];
+    const long long L = ga.L[g], base = cptr[g];
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+        if (!onC[v]) continue;
+        const long long j = v == s ? 0 : L - (long long)hop[v];
+        if (j >= 0 && j < L) out[base + j] = pi[v];
+    }
+}
+
+template <int G, typename WT>
+__global__ __launch_bounds__(kWG) void k_short_walk(const int2* __restrict__ chunks,
+                                                    const unsigned* nch, int T, GArrays ga,
+                                                    const int* __restrict__ row_ptr,
+                                                    const int* __restrict__ col,
+                                                    const WT* __restrict__ w, int neg,
+                                                    const long long* __restrict__ V,
+                                                    const int* __restrict__ pi,
+                                                    const int* __restrict__ succ,
+                                                    const int* __restrict__ hop)
+{
+    constexpr int VPB = kWG / G;
+    int g;
+    int64_t v0, v1;
+    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    if (ga.status[g] != OCM_OK || ga.certain[g] || !ga.nondec[g]) return;   // uniform
+    const long long L = ga.L[g], W = ga.W[g];
+    const int lane = threadIdx.x & (G - 1);
+    unsigned long long found = 0;
+    for (int64_t vb = v0; vb < v1; vb += VPB) {
+        const int64_t v = vb + threadIdx.x / G;
+        if (v >= v1) continue;
+        const int beg = row_ptr[v], end = row_ptr[v + 1], cur = pi[v];
+        const long long own = V[v];
+        for (int e = beg + lane; e < end; e += G) {
+            if (e == cur) continue;
+            const int y = col[e];
+            if (hop[y] < hop[v]) continue;
+            if (V[y] + L * wval(w, e, neg) - W != own) continue;
+            int x = y;
+            for (int st = 0; st < kShortWalk && x != (int)v; ++st) x = succ[x];
+            found += x == (int)v;
+        }
+    }
+    found = block_sum_u64(found);
+    if (threadIdx.x == 0 && found) atomicAdd(&ga.certain[g], found);
+}
+
+__global__ void k_bctl_clear(BCtl* bc)
+{
+    if (threadIdx.x == 0) {
+        unsigned* p = (unsigned*)bc;
+        for (unsigned i = 0; i < sizeof(BCtl) / sizeof(unsigned); ++i) p[i] = 0;
+    }
+}
+
+__global__ void k_bctl_zero(unsigned* a, unsigned* b)
+{
+    if (threadIdx.x == 0) {
+        *a = 0;
+        if (b) *b = 0;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_graph_init(int G, GArrays ga)
+{
+    for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
+        ga.W[g] = 0;
+        ga.L[g] = 1;
+        ga.s[g] = -1;
+        ga.iter[g] = 0;
+        ga.mode[g] = kActive;
+        ga.status[g] = OCM_OK;
+        ga.best[g] = -1;
+        ga.changed[g] = 0;
+        ga.cbroken[g] = 0;
+        ga.vrun[g] = 0;
+        ga.vact[g] = 0;
+        ga.vprog[g] = 0;
+        ga.ovf[g] = 0;
+        ga.have_c[g] = 0;
+        ga.tight[g] = 0;
+        ga.certain[g] = 0;
+        ga.nondec[g] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_fast_to_general(int G, GArrays ga)
+{
+    for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG)
+        if (ga.mode[g] == kFast) ga.mode[g] = kGeneral;
+}
+
+__global__ __launch_bounds__(kWG) void k_tie_init(int G, GArrays ga)
+{
+    for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
+        ga.tight[g] = 0;
+        ga.certain[g] = 0;
+        ga.nondec[g] = 0;
+    }
+}
+
+}  // namespace b
+}  // namespace ocm
+
+// ===========================================================================
+// host driver
+// ===========================================================================
+namespace {
+
+using ocm::Jmp;
+using ocm::b::BCtl;
+using ocm::b::GArrays;
+
+ocm_status bfail(ocm_status s, const char* what)
+{
+    ocm::set_last_error(what);
+    return s;
+}
+
+#define BHIP(expr)                                                                     \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            char b_[256];                                                              \
+            snprintf(b_, sizeof b_, "%s: %s", #expr, hipGetErrorString(e_));           \
+            return bfail(OCM_E_HIP, b_);                                               \
+        }                                                                              \
+    } while (0)
+
+#define BTRY(expr)                                                                     \
+    do {                                                                               \
+        ocm_status s_ = (expr);                                                        \
+        if (s_ != OCM_OK) return s_;                                                   \
+    } while (0)
+
+size_t bal(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct BWs {
+    BCtl* bc;
+    GArrays ga;
+    int2* chunks;
+    long long* cptr;     // G+1 cycle offsets
+    long long* V;
+    int* pi;
+    int* succ;
+    int* hop;
+    Jmp* Q[2];
+    int* rep;
+    unsigned char* onc;
+    unsigned char* onC;
+    int* layer;
+    int* list[2];
+    int* flist[2];
+    long long* wsum;
+    unsigned* lcnt;
+    int2* heads;
+    unsigned* rdeg;
+    unsigned* stot;
+    int* rin_ptr;
+    int2* rin;
+    int* cand;
+    unsigned char* touched;
+    unsigned* bad;
+    size_t total;
+};
+
+BWs bcarve(void* base, int64_t G, int64_t n, int64_t m, int T)
+{
+    char* b = (char*)base;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        size_t o = off;
+        off += bal(bytes);
+        return b ? (void*)(b + o) : nullptr;
+    };
+    BWs w;
+    const size_t Gs = (size_t)G, N = (size_t)n, M = (size_t)m;
+    const size_t maxch = N / (size_t)T + Gs + 1;
+    w.bc = (BCtl*)take(sizeof(BCtl));
+    GArrays& a = w.ga;
+    a.W = (long long*)take(8 * Gs);
+    a.L = (long long*)take(8 * Gs);
+    a.s = (int*)take(4 * Gs);
+    a.iter = (int*)take(4 * Gs);
+    a.mode = (int*)take(4 * Gs);
+    a.status = (int*)take(4 * Gs);
+    a.best = (int*)take(4 * Gs);
+    a.changed = (unsigned*)take(4 * Gs);
+    a.cbroken = (unsigned*)take(4 * Gs);
+    a.vrun = (unsigned*)take(4 * Gs);
+    a.vact = (unsigned*)take(4 * Gs);
+    a.vprog = (unsigned*)take(4 * Gs);
+    a.ovf = (unsigned*)take(4 * Gs);
+    a.have_c = (unsigned char*)take(Gs);
+    a.tight = (unsigned long long*)take(8 * Gs);
+    a.certain = (unsigned long long*)take(8 * Gs);
+    a.nondec = (unsigned long long*)take(8 * Gs);
+    a.vptr = (long long*)take(8 * (Gs + 1));
+    a.eptr = (long long*)take(8 * (Gs + 1));
+    a.ccnt = (unsigned*)take(4 * (Gs + 1));
+    a.coff = (unsigned*)take(4 * (Gs + 1));
+    a.ctot = (unsigned*)take(4 * ((Gs + 1) / 2048 + 2));
+    w.chunks = (int2*)take(8 * maxch);
+    w.cptr = (long long*)take(8 * (Gs + 1));
+    w.V = (long long*)take(8 * N);
+    w.pi = (int*)take(4 * N);
+    w.succ = (int*)take(4 * N);
+    w.hop = (int*)take(4 * N);
+    w.Q[0] = (Jmp*)take(sizeof(Jmp) * N);
+    w.Q[1] = (Jmp*)take(sizeof(Jmp) * N);
+    w.rep = (int*)take(4 * N);
+    w.onc = (unsigned char*)take(N);
+    w.onC = (unsigned char*)take(N);
+    w.layer = (int*)take(4 * N);
+    w.list[0] = (int*)take(4 * N);
+    w.list[1] = (int*)take(4 * N);
+    w.flist[0] = (int*)take(4 * N);
+    w.flist[1] = (int*)take(4 * N);
+    w.wsum = (long long*)take(8 * N);
+    w.lcnt = (unsigned*)take(4 * N);
+    w.heads = (int2*)take(8 * N);
+    w.rdeg = (unsigned*)take(4 * (N + 1));
+    w.stot = (unsigned*)take(4 * ((N + 1) / 2048 + 2));
+    w.rin_ptr = (int*)take(4 * (N + 1));
+    w.rin = (int2*)take(8 * M);
+    w.cand = (int*)take(4 * N);
+    w.touched = (unsigned char*)take(N + 16);
+    w.bad = (unsigned*)take(256);
+    w.total = off;
+    return w;
+}
+
+// The batch schedule: lanes per vertex in the sweeps and vertices per chunk.
+struct Schedule {
+    int lanes;
+    int chunk;
+};
+
+int default_lanes(int64_t n, int64_t m)
+{
+    const double d = (double)m / (double)std::max<int64_t>(n, 1);
+    int G = 1;
+    while (G < 64 && G < d) G <<= 1;
+    return G;
+}
+
+struct BCtx {
+    int64_t G;
+    int n, m;
+    const int* row_ptr;
+    const int* col;
+    const void* w;
+    int wtype, sw, neg;
+    hipStream_t st;
+    BWs ws;
+    BCtl h;
+    Schedule sch;
+    ocm_profile* prof = nullptr;
+    bool rev_built = false;
+    int max_n = 1;
+};
+
+ocm_status bread(BCtx& c)
+{
+    BHIP(hipMemcpyAsync(&c.h, c.ws.bc, sizeof(BCtl), hipMemcpyDeviceToHost, c.st));
+    BHIP(hipStreamSynchronize(c.st));
+    return OCM_OK;
+}
+
+// Chunk list of the graphs in `want` (a mode, or -1 = every graph not done);
+// returns the number of chunks.
+ocm_status build_chunks(BCtx& c, int want, unsigned* nch_out)
+{
+    GArrays& a = c.ws.ga;
+    const int T = c.sch.chunk;
+    ocm::b::k_chunk_count<<<ocm::stride_grid(c.G + 1), ocm::kWG, 0, c.st>>>((int)c.G, a.mode, want,
+                                                                          a.vptr, T, a.ccnt);
+    ocm::launch_exclusive_scan(c.G + 1, a.ccnt, a.coff, a.ctot, c.st);
+    ocm::b::k_chunk_fill<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a.ccnt, a.coff,
+                                                                     a.vptr, T, c.ws.chunks,
+                                                                     &c.ws.bc->nchunks);
+    BHIP(hipGetLastError());
+    BTRY(bread(c));
+    *nch_out = c.h.nchunks;
+    return OCM_OK;
+}
+
+template <typename WT>
+void launch_bsweep_t(BCtx& c, unsigned nch, bool tie)
+{
+    const WT* w = (const WT*)c.w;
+    BWs& ws = c.ws;
+    const int T = c.sch.chunk;
+#define OCM_BSW(GG)                                                                              \
+    case GG:                                                                                     \
+        if (tie)                                                                                 \
+            ocm::b::k_sweep<GG, WT, true><<<nch, ocm::kWG, 0, c.st>>>(                            \
+                ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,   \
+                ws.onC, ws.hop);                                                                 \
+        else                                                                                     \
+            ocm::b::k_sweep<GG, WT, false><<<nch, ocm::kWG, 0, c.st>>>(                           \
+                ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,   \
+                ws.onC, ws.hop);                                                                 \
+        break;
+    switch (c.sch.lanes) {
+        OCM_BSW(1)
+        OCM_BSW(2)
+        OCM_BSW(4)
+        OCM_BSW(8)
+        OCM_BSW(16)
+        OCM_BSW(32)
+        OCM_BSW(64)
+        default: break;
+    }
+#undef OCM_BSW
+}
+
+void launch_bsweep(BCtx& c, unsigned nch, bool tie)
+{
+    if (nch == 0) return;
+    if (c.wtype == OCM_W_I64) launch_bsweep_t<long long>(c, nch, tie);
+    else launch_bsweep_t<int>(c, nch, tie);
+}
+
+template <typename WT>
+void launch_bwalk_t(BCtx& c, unsigned nch)
+{
+    const WT* w = (const WT*)c.w;
+    BWs& ws = c.ws;
+    const int T = c.sch.chunk;
+#define OCM_BWK(GG)                                                                              \
+    case GG:                                                                                     \
+        ocm::b::k_short_walk<GG, WT><<<nch, ocm::kWG, 0, c.st>>>(                                 \
+            ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,       \
+            ws.succ, ws.hop);                                                                    \
+        break;
+    switch (c.sch.lanes) {
+        OCM_BWK(1)
+        OCM_BWK(2)
+        OCM_BWK(4)
+        OCM_BWK(8)
+        OCM_BWK(16)
+        OCM_BWK(32)
+        OCM_BWK(64)
+        default: break;
+    }
+#undef OCM_BWK
+}
+
+void launch_bwalk(BCtx& c, unsigned nch)
+{
+    if (nch == 0) return;
+    if (c.wtype == OCM_W_I64) launch_bwalk_t<long long>(c, nch);
+    else launch_bwalk_t<int>(c, nch);
+}
+
+// Values for the graphs in mode `want` (kFast probes; kGeneral must finish).
+ocm_status bvalues(BCtx& c, int want)
+{
+    BWs& ws = c.ws;
+    GArrays& a = ws.ga;
+    const int T = c.sch.chunk;
+    unsigned nch = 0;
+    BTRY(build_chunks(c, want, &nch));
+    if (nch == 0) return OCM_OK;
+    if (c.wtype == OCM_W_I64)
+        ocm::b::k_val_init<long long><<<nch, ocm::kWG, 0, c.st>>>(
+            ws.chunks, &ws.bc->nchunks, T, a, c.col, ws.pi, (const long long*)c.w, c.neg, ws.succ,
+            ws.Q[0]);
+    else
+        ocm::b::k_val_init<int><<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, c.col,
+                                                            ws.pi, (const int*)c.w, c.neg, ws.succ,
+                                                            ws.Q[0]);
+    ocm::b::k_val_mark<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.Q[0]);
+    int cur = 0;
+    for (int k = 0; k < 80; ++k) {
+        ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->vrunning, nullptr);
+        ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, ws.bc);
+        BHIP(hipGetLastError());
+        BTRY(bread(c));
+        if (c.h.vrunning == 0) break;
+        ocm::b::k_val_round<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.Q[cur],
+                                                        ws.Q[cur ^ 1]);
+        cur ^= 1;
+    }
+    if (c.h.vrunning != 0) return bfail(OCM_E_HIP, "value propagation did not converge");
+    ocm::b::k_val_final<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, want,
+                                                    ws.Q[cur], ws.V, ws.hop);
+    ocm::b::k_values_done<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want);
+    BHIP(hipGetLastError());
+    return OCM_OK;
+}
+
+// Rebuild rounds over the union (pull or push per round, as in ocm_min).
+ocm_status bconnect(BCtx& c, unsigned nch)
+{
+    BWs& ws = c.ws;
+    GArrays& a = ws.ga;
+    const int T = c.sch.chunk;
+    ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[0], &ws.bc->fcnt[0]);
+    ocm::b::k_conn_init<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep, ws.onc,
+                                                    ws.layer, ws.onC, ws.list[0], &ws.bc->ucnt[0],
+                                                    ws.flist[0], &ws.bc->fcnt[0]);
+    BHIP(hipGetLastError());
+    BTRY(bread(c));
+    unsigned left = c.h.ucnt[0], ulen = left, front = c.h.fcnt[0];
+    int ua = 0, fa = 0, k = 0;
+    while (left > 0) {
+        ++k;
+        const int ub = ua ^ 1, fb = fa ^ 1;
+        const bool push = left >= (1u << 16) && (uint64_t)front * 4 < left;
+        if (push && !c.rev_built) {
+            ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, ws.rdeg, ws.stot, ws.rin_ptr, ws.rin,
+                                  ws.cand, ws.touched, c.st);
+            c.rev_built = true;
+        }
+        ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[ub], &ws.bc->fcnt[fb]);
+        // the plain kernels' counters live in Ctl; pass the batch ones instead
+        if (push) {
+            ocm::launch_conn_offer(ws.rin_ptr, ws.rin, ws.layer, ws.cand, ws.touched, ws.flist[fa],
+                                   front, (ocm::Ctl*)ws.bad, c.st);
+            ocm::launch_conn_collect(k, c.n, ws.touched, ws.cand, ws.pi, ws.layer, ws.flist[fb],
+                                     &ws.bc->fcnt[fb], c.st);
+        } else {
+            ocm::launch_conn_pull(k, c.row_ptr, c.col, ws.layer, ws.pi, ws.list[ua], ulen,
+                                  ws.list[ub], &ws.bc->ucnt[ub], ws.flist[fb], &ws.bc->fcnt[fb],
+                                  &ws.bc->ledges, c.st);
+        }
+        BHIP(hipGetLastError());
+        BTRY(bread(c));
+        const unsigned got = c.h.fcnt[fb];
+        if (push) {
+            left -= got;
+        } else {
+            ulen = c.h.ucnt[ub];
+            left = ulen;
+            ua = ub;
+        }
+        if (got == 0) {
+            // the remaining vertices cannot reach their graph's cycle
+            if (push) {
+                // refresh the unattached list with a pull pass that attaches nobody
+                ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[ub], &ws.bc->fcnt[fb]);
+                ocm::launch_conn_pull(k, c.row_ptr, c.col, ws.layer, ws.pi, ws.list[ua], ulen,
+                                      ws.list[ub], &ws.bc->ucnt[ub], ws.flist[fb],
+                                      &ws.bc->fcnt[fb], &ws.bc->ledges, c.st);
+                BTRY(bread(c));
+                ulen = c.h.ucnt[ub];
+                ua = ub;
+            }
+            ocm::b::k_conn_fail<<<ocm::stride_grid(ulen), ocm::kWG, 0, c.st>>>(
+                (int)c.G, a.vptr, ws.list[ua], ulen, ws.layer, a);
+            BHIP(hipGetLastError());
+            break;
+        }
+        front = got;
+        fa = fb;
+    }
+    return OCM_OK;
+}
+
+ocm_status bgeneral(BCtx& c)
+{
+    BWs& ws = c.ws;
+    GArrays& a = ws.ga;
+    const int T = c.sch.chunk;
+    unsigned nch = 0;
+    BTRY(build_chunks(c, ocm::b::kGeneral, &nch));
+    if (nch == 0) return OCM_OK;
+    auto* P0 = (unsigned long long*)ws.Q[0];
+    auto* P1 = (unsigned long long*)ws.Q[1];
+    int K = 0;
+    while ((int64_t(1) << K) < c.max_n) ++K;
+    ocm::b::k_pj_init<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, c.col, ws.pi, P0,
+                                                  ws.onc);
+    for (int k = 0; k < K; ++k) {
+        ocm::b::k_pj_round<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0, P1);
+        std::swap(P0, P1);
+    }
+    ocm::b::k_pj_final<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0, ws.rep,
+                                                   ws.onc);
+    ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ncyc, nullptr);
+    ocm::b::k_cyc_zero<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep, ws.onc,
+                                                   ws.wsum, ws.lcnt, ws.heads, ws.bc);
+    if (c.wtype == OCM_W_I64)
+        ocm::b::k_cyc_sum<long long><<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a,
+                                                                 ws.rep, ws.onc, ws.pi,
+                                                                 (const long long*)c.w, c.neg,
+                                                                 ws.wsum, ws.lcnt);
+    else
+        ocm::b::k_cyc_sum<int><<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep,
+                                                           ws.onc, ws.pi, (const int*)c.w, c.neg,
+                                                           ws.wsum, ws.lcnt);
+    ocm::b::k_vote<<<2048, ocm::kWG, 0, c.st>>>(ws.heads, ws.bc, a, ws.wsum, ws.lcnt);
+    ocm::b::k_set_lambda<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, ws.wsum, ws.lcnt);
+    BHIP(hipGetLastError());
+    // graphs whose vote failed retired above; rebuild the chunk list
+    BTRY(build_chunks(c, ocm::b::kGeneral, &nch));
+    if (nch == 0) return OCM_OK;
+    BTRY(bconnect(c, nch));
+    return bvalues(c, ocm::b::kGeneral);
+}
+
+long long bgcd(long long a, long long b)
+{
+    if (a < 0) a = -a;
+    if (b < 0) b = -b;
+    while (b) {
+        long long t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+ocm_status check_batch(int64_t G, const int64_t* vptr, const int64_t* eptr, const ocm_graph* u)
+{
+    if (G < 1 || !vptr || !eptr || !u) return bfail(OCM_E_INVALID_ARG, "null argument or G < 1");
+    if (u->n < 1 || u->m < 1 || u->n >= (int64_t(1) << 31) - 1 || u->m >= (int64_t(1) << 31))
+        return bfail(OCM_E_INVALID_ARG, "union sizes out of range");
+    if (!u->row_ptr || !u->col || !u->w) return bfail(OCM_E_INVALID_ARG, "null graph array");
+    if (u->wtype != OCM_W_I32 && u->wtype != OCM_W_I64) return bfail(OCM_E_INVALID_ARG, "bad wtype");
+    if (vptr[0] != 0 || eptr[0] != 0 || vptr[G] != u->n || eptr[G] != u->m)
+        return bfail(OCM_E_BAD_CSR, "vptr/eptr do not span the union");
+    for (int64_t g = 0; g < G; ++g)
+        if (vptr[g + 1] <= vptr[g] || eptr[g + 1] <= eptr[g])
+            return bfail(OCM_E_BAD_CSR, "every graph needs at least one vertex and edge");
+    return OCM_OK;
+}
+
+ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, const ocm_graph* u,
+                         const ocm_options* o_in, void* wsp, size_t ws_bytes, int64_t* p,
+                         int64_t* q, int64_t* cycle_ptr, int32_t* cycle_edges, int64_t cycle_cap,
+                         int32_t* iters, uint32_t* flags, int32_t* status, void* stream, int neg)
+{
+    BTRY(check_batch(G, vptr, eptr, u));
+    if (!p || !q || !cycle_ptr || !iters || !flags) return bfail(OCM_E_INVALID_ARG, "null output");
+    ocm_options o;
+    if (o_in) o = *o_in;
+    else ocm_default_options(&o);
+    if (o.init_policy) return bfail(OCM_E_INVALID_ARG, "warm start is not supported in batches");
+    BCtx c;
+    c.G = G;
+    c.n = (int)u->n;
+    c.m = (int)u->m;
+    c.row_ptr = u->row_ptr;
+    c.col = u->col;
+    c.w = u->w;
+    c.wtype = u->wtype;
+    c.sw = u->wtype == OCM_W_I64 ? 8 : 4;
+    c.neg = neg;
+    c.st = (hipStream_t)stream;
+    c.sch.lanes = o.schedule > 0 ? o.schedule : default_lanes(u->n, u->m);
+    c.sch.chunk = 1024;
+    if (!(c.sch.lanes == 1 || c.sch.lanes == 2 || c.sch.lanes == 4 || c.sch.lanes == 8 ||
+          c.sch.lanes == 16 || c.sch.lanes == 32 || c.sch.lanes == 64))
+        return bfail(OCM_E_INVALID_ARG, "schedule must be a power of two <= 64");
+    for (int64_t g = 0; g < G; ++g) c.max_n = (int)std::max<int64_t>(c.max_n, vptr[g + 1] - vptr[g]);
+    c.ws = bcarve(nullptr, G, u->n, u->m, c.sch.chunk);
+    if (!wsp || ws_bytes < c.ws.total) return bfail(OCM_E_WORKSPACE, "workspace missing or too small");
+    c.ws = bcarve(wsp, G, u->n, u->m, c.sch.chunk);
+    BWs& ws = c.ws;
+    GArrays& a = ws.ga;
+
+    ocm::b::k_bctl_clear<<<1, 64, 0, c.st>>>(ws.bc);
+    BHIP(hipMemcpyAsync(a.vptr, vptr, 8 * (size_t)(G + 1), hipMemcpyHostToDevice, c.st));
+    BHIP(hipMemcpyAsync(a.eptr, eptr, 8 * (size_t)(G + 1), hipMemcpyHostToDevice, c.st));
+    ocm::b::k_graph_init<<<ocm::stride_grid(G), ocm::kWG, 0, c.st>>>((int)G, a);
+    BHIP(hipGetLastError());
+
+    // validation: the union's CSR, the weight bound, and edges inside graphs
+    {
+        ocm::Ctl* vctl = (ocm::Ctl*)ws.bad;   // scratch (256 bytes)
+        ocm::launch_ctl_clear(vctl, ocm::kClrAll | ocm::kClrCount | ocm::kClrChanged, c.st);
+        ocm::launch_validate(c.n, c.m, c.row_ptr, c.col, c.w, c.wtype, o.validate != 0, vctl, c.st);
+        ocm::Ctl hc;
+        BHIP(hipMemcpyAsync(&hc, vctl, sizeof hc, hipMemcpyDeviceToHost, c.st));
+        BHIP(hipStreamSynchronize(c.st));
+        if (hc.err & ocm::kErrBadCsr) return bfail(OCM_E_BAD_CSR, "malformed CSR");
+        if (hc.err & ocm::kErrNoOut) return bfail(OCM_E_NO_OUT_EDGE, "a vertex has no out-edge");
+        const unsigned __int128 bound = (unsigned __int128)2 * (unsigned)c.max_n * hc.maxabsw;
+        if (bound >= ((unsigned __int128)1 << 62))
+            return bfail(OCM_E_OVERFLOW, "weights too large for int64 values");
+        if (o.validate) {
+            unsigned nch = 0;
+            BTRY(build_chunks(c, -1, &nch));
+            ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->overflow, nullptr);
+            ocm::b::k_check_union<<<nch, ocm::kWG, 0, c.st>>>((int)G, a.vptr, a.eptr, c.row_ptr, c.col,
+                                                              ws.chunks, &ws.bc->nchunks,
+                                                              c.sch.chunk, &ws.bc->overflow);
+            BHIP(hipGetLastError());
+            BTRY(bread(c));
+            if (c.h.overflow) return bfail(OCM_E_BAD_CSR, "an edge leaves its graph");
+        }
+    }
+
+    for (int guard = 0;; ++guard) {
+        if (guard > (1 << 20)) return bfail(OCM_E_NOT_CONVERGED, "iteration guard");
+        unsigned nch = 0;
+        BTRY(build_chunks(c, ocm::b::kActive, &nch));
+        if (nch == 0) break;
+        launch_bsweep(c, nch, false);
+        ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->nactive, &ws.bc->nfast);
+        ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ngeneral, nullptr);
+        ocm::b::k_after_sweep<<<ocm::stride_grid(G), ocm::kWG, 0, c.st>>>((int)G, a, o.max_iters, ws.bc);
+        BHIP(hipGetLastError());
+        BTRY(bread(c));
+        if (c.h.nactive == 0) continue;   // everything converged (loop exits next)
+        if (c.h.nfast > 0) {
+            if (o.fast_path) {
+                BTRY(bvalues(c, ocm::b::kFast));
+            } else {
+                ocm::b::k_fast_to_general<<<ocm::stride_grid(G), ocm::kWG, 0, c.st>>>((int)G, a);
+                BHIP(hipGetLastError());
+            }
+        }
+        BTRY(bgeneral(c));
+    }
+
+    // per-graph results
+    std::vector<long long> hW(G), hL(G);
+    std::vector<int> hs(G), hit(G), hst(G);
+    BHIP(hipMemcpyAsync(hW.data(), a.W, 8 * (size_t)G, hipMemcpyDeviceToHost, c.st));
+    BHIP(hipMemcpyAsync(hL.data(), a.L, 8 * (size_t)G, hipMemcpyDeviceToHost, c.st));
+    BHIP(hipMemcpyAsync(hs.data(), a.s, 4 * (size_t)G, hipMemcpyDeviceToHost, c.st));
+    BHIP(hipMemcpyAsync(hit.data(), a.iter, 4 * (size_t)G, hipMemcpyDeviceToHost, c.st));
+    BHIP(hipMemcpyAsync(hst.data(), a.status, 4 * (size_t)G, hipMemcpyDeviceToHost, c.st));
+    BHIP(hipStreamSynchronize(c.st));
+    std::vector<long long> cptr(G + 1, 0);
+    ocm_status first_err = OCM_OK;
+    for (int64_t g = 0; g < G; ++g) {
+        const bool ok = hst[g] == OCM_OK;
+        cptr[g + 1] = cptr[g] + (ok ? hL[g] : 0);
+        if (!ok && first_err == OCM_OK) first_err = (ocm_status)hst[g];
+        const long long W = hW[g], L = hL[g];
+        const long long gg = ok ? bgcd(W, L) : 1;
+        p[g] = ok ? (neg ? -W : W) / gg : 0;
+        q[g] = ok ? L / gg : 0;
+        iters[g] = hit[g];
+        flags[g] = 0;
+        if (status) status[g] = hst[g];
+        cycle_ptr[g] = cptr[g];
+    }
+    cycle_ptr[G] = cptr[G];
+    if (cycle_cap < cptr[G]) return bfail(OCM_E_CAPACITY, "cycle_cap smaller than the cycles");
+    if (cptr[G] > 0 && !cycle_edges) return bfail(OCM_E_INVALID_ARG, "cycle_edges is null");
+    BHIP(hipMemcpyAsync(ws.cptr, cptr.data(), 8 * (size_t)(G + 1), hipMemcpyHostToDevice, c.st));
+    {
+        // every graph; the kernels skip failed ones
+        unsigned nch = 0;
+        BTRY(build_chunks(c, -2, &nch));
+        ocm::b::k_cycle_list<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, c.sch.chunk, a,
+                                                         ws.cptr, ws.onC, ws.pi, ws.hop, cycle_edges);
+        if (o.tie_check) {
+            ocm::b::k_tie_init<<<ocm::stride_grid(G), ocm::kWG, 0, c.st>>>((int)G, a);
+            launch_bsweep(c, nch, true);
+            launch_bwalk(c, nch);
+            std::vector<unsigned long long> ht(G), hc(G), hn(G);
+            BHIP(hipMemcpyAsync(ht.data(), a.tight, 8 * (size_t)G, hipMemcpyDeviceToHost, c.st));
+            BHIP(hipMemcpyAsync(hc.data(), a.certain, 8 * (size_t)G, hipMemcpyDeviceToHost, c.st));
+            BHIP(hipMemcpyAsync(hn.data(), a.nondec, 8 * (size_t)G, hipMemcpyDeviceToHost, c.st));
+            BHIP(hipStreamSynchronize(c.st));
+            for (int64_t g = 0; g < G; ++g) {
+                if (hst[g] != OCM_OK || ht[g] == 0) continue;
+                flags[g] |= OCM_F_TIGHT_EDGES;
+                if (hc[g]) flags[g] |= OCM_F_TIE;
+                else if (hn[g]) flags[g] |= OCM_F_TIE_UNCHECKED;
+            }
+        } else {
+            for (int64_t g = 0; g < G; ++g) flags[g] |= OCM_F_TIE_UNCHECKED;
+        }
+        BHIP(hipGetLastError());
+    }
+    BHIP(hipStreamSynchronize(c.st));
+    if (first_err != OCM_OK) return bfail(first_err, "some graphs failed (see status)");
+    return OCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ocm_batched_workspace_size(int64_t G, const int64_t* vptr, const int64_t* eptr,
+                                  const ocm_graph* u, const ocm_options* o)
+{
+    (void)o;
+    if (check_batch(G, vptr, eptr, u) != OCM_OK) return 0;
+    return bcarve(nullptr, G, u->n, u->m, 1024).total;
+}
+
+ocm_status ocm_min_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, const ocm_graph* u,
+                           const ocm_options* o, void* ws, size_t ws_bytes, int64_t* p, int64_t* q,
+                           int64_t* cycle_ptr, int32_t* cycle_edges, int64_t cycle_cap,
+                           int32_t* iters, uint32_t* flags, int32_t* status, void* stream)
+{
+    return solve_batched(G, vptr, eptr, u, o, ws, ws_bytes, p, q, cycle_ptr, cycle_edges, cycle_cap,
+                         iters, flags, status, stream, 0);
+}
+
+ocm_status ocm_max_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, const ocm_graph* u,
+                           const ocm_options* o, void* ws, size_t ws_bytes, int64_t* p, int64_t* q,
+                           int64_t* cycle_ptr, int32_t* cycle_edges, int64_t cycle_cap,
+                           int32_t* iters, uint32_t* flags, int32_t* status, void* stream)
+{
+    return solve_batched(G, vptr, eptr, u, o, ws, ws_bytes, p, q, cycle_ptr, cycle_edges, cycle_cap,
+                         iters, flags, status, stream, 1);
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Device helpers shared by the kernel files: wave and workgroup reductions,
+// LDS-buffered list appends, XCD-aware block mapping.
+#pragma once
+
+#include "kernels.h"
+
+namespace ocm {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remapping the block
+// index gives every XCD one contiguous slice of the vertex range, so the
+// gathers of neighbouring vertices hit that XCD's own L2.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    if ((nb & 7) != 0) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+template <typename WT>
+__device__ __forceinline__ int64_t wval(const WT* w, int64_t e, int neg)
+{
+    int64_t x = (int64_t)w[e];
+    return neg ? -x : x;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long y = __shfl_xor(x, off, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// Sum over the workgroup; the result is valid in thread 0.  Counters are
+// reduced per workgroup so a launch issues one global atomic per block, not
+// one per wave (same-address atomics serialise in the L2).
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x)
+{
+    __shared__ unsigned long long part[kWG / 64];
+    x = wave_sum_u64(x);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kWG / 64; ++i) t += part[i];
+    return t;
+}
+
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long x)
+{
+    __shared__ unsigned long long part[kWG / 64];
+    x = wave_max_u64(x);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kWG / 64; ++i) t = part[i] > t ? part[i] : t;
+    return t;
+}
+
+// Workgroup-buffered list append: items go to an LDS buffer first and the
+// block reserves its slice of the global list with one atomic at the end.
+struct BlockList {
+    int* buf;          // LDS, capacity kListItems
+    unsigned* n;       // LDS counter
+};
+
+__device__ __forceinline__ void blist_push(BlockList& b, bool want, int item)
+{
+    const unsigned long long mask = __ballot(want);
+    if (!mask) return;
+    const unsigned lane = threadIdx.x & 63;
+    const unsigned leader = (unsigned)__ffsll((long long)mask) - 1u;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(b.n, (unsigned)__popcll(mask));
+    base = __shfl(base, (int)leader, 64);
+    if (want) b.buf[base + __popcll(mask & ((1ull << lane) - 1ull))] = item;
+}
+
+__device__ __forceinline__ void blist_flush(BlockList& b, int* out, unsigned* out_cnt)
+{
+    __shared__ unsigned base;
+    __syncthreads();
+    const unsigned cnt = *b.n;
+    if (threadIdx.x == 0) base = cnt ? atomicAdd(out_cnt, cnt) : 0u;
+    __syncthreads();
+    for (unsigned j = threadIdx.x; j < cnt; j += kWG) out[base + j] = b.buf[j];
+}
+
+// |x| as unsigned, defined for INT64_MIN too.
+__device__ __forceinline__ unsigned long long uabs64(int64_t x)
+{
+    return x < 0 ? (unsigned long long)(-(x + 1)) + 1ull : (unsigned long long)x;
+}
+
+// Appends `want` lanes' items to a global list with one atomic per wave.
+// Returns this lane's slot (valid only when want is true).
+__device__ __forceinline__ unsigned wave_append(bool want, unsigned* counter)
+{
+    unsigned long long mask = __ballot(want);
+    unsigned lane = threadIdx.x & 63;
+    unsigned before = __popcll(mask & ((1ull << lane) - 1ull));
+    unsigned total = __popcll(mask);
+    unsigned leader = mask ? (unsigned)__ffsll((long long)mask) - 1u : 0u;
+    unsigned base = 0;
+    if (want && lane == leader) base = atomicAdd(counter, total);
+    base = __shfl(base, (int)leader, 64);
+    return base + before;
+}
+
+
+}  // namespace ocm

@@ -9,6 +9,7 @@ namespace ocm {
 constexpr int kWG = 256;        // threads per workgroup (4 waves of 64)
 constexpr int kWI32 = 0, kWI64 = 1;
 constexpr int kListItems = 4096;  // LDS list buffer of the connect kernels (16 KiB)
+constexpr int kShortWalk = 64;    // tie test: policy steps walked from a tight edge's head
 
 constexpr unsigned kErrBadCsr = 1u;
 constexpr unsigned kErrNoOut = 2u;
@@ -40,6 +41,11 @@ struct alignas(16) Ctl {
     unsigned pad;
     unsigned long long pedges;     // connect: in-edges scanned by push offers
     unsigned long long ledges;     // connect: out-edges scanned by pull rounds
+    unsigned long long certain;    // tie scan: edges that certainly close a second critical cycle
+    unsigned long long nondec;     // tie scan: tight non-policy edges not nearer the source
+    unsigned xcnt;                 // tie scan: tight non-policy edges listed
+    unsigned scnt;                 // tie check: special vertices
+    unsigned bad;                  // conversion / policy check failure
 };
 
 // Pointer-jumping entry of the value phase: the first H edges of v's policy
@@ -61,6 +67,11 @@ struct SweepArgs {
     int* pi;
     const unsigned char* onC;      // optional: flags vertices of the current C
     Ctl* ctl;
+    const int* hop;                // tie scan: policy hops to the source, or null
+    int* xs;                       // tie scan: optional list of tight edges (tail)
+    int* ys;                       //           and head
+    unsigned* xcnt;
+    unsigned xcap;
 };
 
 void launch_validate(int n, int m, const int* row_ptr, const int* col, const void* w, int wtype,
@@ -98,12 +109,37 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
                      int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl, hipStream_t st);
 void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st);
-void launch_val_final(int n, const Jmp* Q, long long* V, Ctl* ctl, hipStream_t st);
+void launch_val_final(int n, const Jmp* Q, long long* V, int* hop, Ctl* ctl, hipStream_t st);
 void launch_cycle_list(int n, int s, long long L, const unsigned char* onC, const int* pi,
-                       const Jmp* Q, int* out, hipStream_t st);
+                       const int* hop, int* out, hipStream_t st);
+void launch_tie_short_walk(const SweepArgs& a, const void* w, int wtype, int G, const int* succ,
+                           unsigned grid, hipStream_t st);
 void launch_ctl_clear(Ctl* ctl, unsigned what, hipStream_t st);
 void launch_ctl_set(Ctl* ctl, int s, long long W, long long L, hipStream_t st);
 void launch_zero2(unsigned* a, unsigned* b, hipStream_t st);
+// exclusive prefix sum of len values; tot needs len/2048 + 1 entries
+void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsigned* tot,
+                           hipStream_t st);
+
+// thread-local message returned by ocm_last_error()
+void set_last_error(const char* what);
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kWG - 1) / kWG); }
+inline unsigned stride_grid(int64_t n)
+{
+    const unsigned b = blocks_for(n);
+    return b < 2048 ? b : 2048;
+}
+void launch_tie_special(int n, unsigned k, int* xs, int* ys, const int* succ,
+                        const unsigned char* onC, unsigned char* sp, int* spid, int* slist,
+                        unsigned* scnt, hipStream_t st);
+void launch_tie_walk(int n, unsigned ns, const int* slist, const int* succ,
+                     const unsigned char* sp, const unsigned char* onC, const int* spid, int* P,
+                     unsigned k, int* xs, int* ys, hipStream_t st);
+void launch_adjoint_scatter(int64_t m, const int* cyc, int64_t len, const double* g, double* grad,
+                            hipStream_t st);
+void launch_w_from_f64(int64_t m, const double* w, long long* out, unsigned* bad, hipStream_t st);
+void launch_check_policy(int n, const int* row_ptr, const int* pi, unsigned* bad, hipStream_t st);
 void launch_fill_u8(unsigned char* p, int64_t n, unsigned char v, hipStream_t st);
 
 }  // namespace ocm

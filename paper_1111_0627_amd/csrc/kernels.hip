@@ -11,122 +11,9 @@
 // All values are exact integers: V is scaled by L = |C| so that lambda = W/L
 // never has to be divided.
 #include "kernels.h"
+#include "device_util.h"
 
 namespace ocm {
-
-// ---------------------------------------------------------------------------
-// helpers
-// ---------------------------------------------------------------------------
-
-// Workgroups are dispatched round-robin over the 8 XCDs; remapping the block
-// index gives every XCD one contiguous slice of the vertex range, so the
-// gathers of neighbouring vertices hit that XCD's own L2.
-__device__ __forceinline__ int xcd_block(int b, int nb)
-{
-    if ((nb & 7) != 0) return b;
-    return (b & 7) * (nb >> 3) + (b >> 3);
-}
-
-template <typename WT>
-__device__ __forceinline__ int64_t wval(const WT* w, int64_t e, int neg)
-{
-    int64_t x = (int64_t)w[e];
-    return neg ? -x : x;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
-{
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
-}
-
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
-{
-    for (int off = 32; off > 0; off >>= 1) {
-        unsigned long long y = __shfl_xor(x, off, 64);
-        x = y > x ? y : x;
-    }
-    return x;
-}
-
-// Sum over the workgroup; the result is valid in thread 0.  Counters are
-// reduced per workgroup so a launch issues one global atomic per block, not
-// one per wave (same-address atomics serialise in the L2).
-__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x)
-{
-    __shared__ unsigned long long part[kWG / 64];
-    x = wave_sum_u64(x);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
-    __syncthreads();
-    unsigned long long t = 0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kWG / 64; ++i) t += part[i];
-    return t;
-}
-
-__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long x)
-{
-    __shared__ unsigned long long part[kWG / 64];
-    x = wave_max_u64(x);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
-    __syncthreads();
-    unsigned long long t = 0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kWG / 64; ++i) t = part[i] > t ? part[i] : t;
-    return t;
-}
-
-// Workgroup-buffered list append: items go to an LDS buffer first and the
-// block reserves its slice of the global list with one atomic at the end.
-struct BlockList {
-    int* buf;          // LDS, capacity kListItems
-    unsigned* n;       // LDS counter
-};
-
-__device__ __forceinline__ void blist_push(BlockList& b, bool want, int item)
-{
-    const unsigned long long mask = __ballot(want);
-    if (!mask) return;
-    const unsigned lane = threadIdx.x & 63;
-    const unsigned leader = (unsigned)__ffsll((long long)mask) - 1u;
-    unsigned base = 0;
-    if (lane == leader) base = atomicAdd(b.n, (unsigned)__popcll(mask));
-    base = __shfl(base, (int)leader, 64);
-    if (want) b.buf[base + __popcll(mask & ((1ull << lane) - 1ull))] = item;
-}
-
-__device__ __forceinline__ void blist_flush(BlockList& b, int* out, unsigned* out_cnt)
-{
-    __shared__ unsigned base;
-    __syncthreads();
-    const unsigned cnt = *b.n;
-    if (threadIdx.x == 0) base = cnt ? atomicAdd(out_cnt, cnt) : 0u;
-    __syncthreads();
-    for (unsigned j = threadIdx.x; j < cnt; j += kWG) out[base + j] = b.buf[j];
-}
-
-// |x| as unsigned, defined for INT64_MIN too.
-__device__ __forceinline__ unsigned long long uabs64(int64_t x)
-{
-    return x < 0 ? (unsigned long long)(-(x + 1)) + 1ull : (unsigned long long)x;
-}
-
-// Appends `want` lanes' items to a global list with one atomic per wave.
-// Returns this lane's slot (valid only when want is true).
-__device__ __forceinline__ unsigned wave_append(bool want, unsigned* counter)
-{
-    unsigned long long mask = __ballot(want);
-    unsigned lane = threadIdx.x & 63;
-    unsigned before = __popcll(mask & ((1ull << lane) - 1ull));
-    unsigned total = __popcll(mask);
-    unsigned leader = mask ? (unsigned)__ffsll((long long)mask) - 1u : 0u;
-    unsigned base = 0;
-    if (want && lane == leader) base = atomicAdd(counter, total);
-    base = __shfl(base, (int)leader, 64);
-    return base + before;
-}
 
 // ---------------------------------------------------------------------------
 // validation: CSR shape of Fig. 2b, out-degree >= 1, max |w|
@@ -183,7 +70,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a, const WT* __restrict
     const int64_t per = ((int64_t)a.n + gridDim.x - 1) / gridDim.x;
     const int64_t v0 = (int64_t)b * per;
     const int64_t v1 = v0 + per < a.n ? v0 + per : a.n;
-    unsigned long long cnt = 0;
+    unsigned long long cnt = 0, certain = 0, nondec = 0;
     unsigned cbroken = 0;
     for (int64_t vb = v0; vb < v1; vb += VPB) {
         const int64_t v = vb + threadIdx.x / G;
@@ -203,8 +90,23 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a, const WT* __restrict
             const int64_t we = wval(w, e, a.neg);
             const int64_t key = FIRST ? we : a.V[a.col[e]] + L * we - W;
             if (TIE) {
-                // tie scan: tight edges other than the policy edge
-                if (key == own && e != cur) cnt++;
+                // tie scan: tight edges other than the policy edge.  A tight
+                // self-loop, or a tight edge leaving C, certainly closes a
+                // second critical cycle (every vertex's policy path leads
+                // back to C).
+                const bool tight = key == own && e != cur;
+                if (tight) {
+                    cnt++;
+                    if (a.col[e] == v || (a.onC && a.onC[v])) certain++;
+                    if (a.hop && a.hop[a.col[e]] >= a.hop[v]) nondec++;
+                }
+                if (a.xs) {
+                    const unsigned slot = wave_append(tight, a.xcnt);
+                    if (tight && slot < a.xcap) {
+                        a.xs[slot] = (int)v;
+                        a.ys[slot] = a.col[e];
+                    }
+                }
             } else if (key < best) {
                 best = key;
                 bpos = e;
@@ -228,9 +130,15 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a, const WT* __restrict
     }
     cnt = block_sum_u64(cnt);
     const unsigned long long brk = block_sum_u64(cbroken);
+    if (TIE) {
+        certain = block_sum_u64(certain);
+        nondec = block_sum_u64(nondec);
+    }
     if (threadIdx.x == 0) {
         if (cnt) atomicAdd(TIE ? &a.ctl->tight : &a.ctl->changed, cnt);
         if (brk) atomicOr(&a.ctl->cbroken, 1u);
+        if (TIE && certain) atomicAdd(&a.ctl->certain, certain);
+        if (TIE && nondec) atomicAdd(&a.ctl->nondec, nondec);
     }
 }
 
@@ -748,13 +656,15 @@ __global__ __launch_bounds__(kWG) void k_val_round(int n, int s, const Jmp* __re
 }
 
 __global__ __launch_bounds__(kWG) void k_val_final(int n, const Jmp* __restrict__ Q,
-                                                   long long* __restrict__ V, Ctl* ctl)
+                                                   long long* __restrict__ V,
+                                                   int* __restrict__ hop, Ctl* ctl)
 {
     const int v = blockIdx.x * kWG + threadIdx.x;
     unsigned bad = 0;
     if (v < n) {
         const Jmp q = Q[v];
         V[v] = q.D;
+        if (hop) hop[v] = (int)(q.H & ~kHopOverflow);
         if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
     }
     if (__ballot(bad != 0) && (threadIdx.x & 63) == 0) atomicOr(&ctl->overflow, 1u);
@@ -765,22 +675,207 @@ __global__ __launch_bounds__(kWG) void k_val_final(int n, const Jmp* __restrict_
 __global__ __launch_bounds__(kWG) void k_cycle_list(int n, int s, long long L,
                                                     const unsigned char* __restrict__ onC,
                                                     const int* __restrict__ pi,
-                                                    const Jmp* __restrict__ Q,
+                                                    const int* __restrict__ hop,
                                                     int* __restrict__ out)
 {
     const int v = blockIdx.x * kWG + threadIdx.x;
     if (v >= n || !onC[v]) return;
-    const long long j = v == s ? 0 : L - (long long)(Q[v].H & ~kHopOverflow);
+    const long long j = v == s ? 0 : L - (long long)hop[v];
     if (j >= 0 && j < L) out[j] = pi[v];
+}
+
+// Short-walk test: for every tight non-policy edge x->y whose head is not
+// nearer the source (hop[y] >= hop[x]), follow y's policy path for at most
+// kShortWalk steps; meeting x closes a cycle of tight edges other than C.
+
+template <int G, typename WT>
+__global__ __launch_bounds__(kWG) void k_tie_short_walk(SweepArgs a, const WT* __restrict__ w,
+                                                        const int* __restrict__ succ)
+{
+    constexpr int VPB = kWG / G;
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t per = ((int64_t)a.n + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)blockIdx.x * per;
+    const int64_t v1 = v0 + per < a.n ? v0 + per : a.n;
+    unsigned long long found = 0;
+    for (int64_t vb = v0; vb < v1; vb += VPB) {
+        const int64_t v = vb + threadIdx.x / G;
+        if (v >= v1) continue;
+        const int beg = a.row_ptr[v], end = a.row_ptr[v + 1];
+        const int64_t own = a.V[v];
+        const int cur = a.pi[v];
+        for (int e = beg + lane; e < end; e += G) {
+            if (e == cur) continue;
+            const int y = a.col[e];
+            if (a.hop[y] < a.hop[v]) continue;
+            if (a.V[y] + a.L * wval(w, e, a.neg) - a.W != own) continue;
+            int x = y;
+            for (int st = 0; st < kShortWalk && x != (int)v; ++st) x = succ[x];
+            found += x == (int)v;
+        }
+    }
+    found = block_sum_u64(found);
+    if (threadIdx.x == 0 && found) atomicAdd(&a.ctl->certain, found);
+}
+
+// ---------------------------------------------------------------------------
+// exact uniqueness of the critical cycle (used when no quick test decided).
+// The tight subgraph T is the policy graph plus the tight non-policy edges
+// X = {x_i -> y_i}.  Contract C to one node c*; the policy is then an in-tree
+// rooted at c*.  Every vertex that is an endpoint of an X edge is "special";
+// each special vertex z gets P(z) = the first special vertex (or c*) strictly
+// after z on its policy path.  T has a second critical cycle iff the graph on
+// special vertices + c* with edges z -> P(z) and x_i -> y_i has a cycle,
+// which the host checks on that small graph.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_tie_mark(unsigned k, const int* __restrict__ xs,
+                                                  const int* __restrict__ ys,
+                                                  unsigned char* __restrict__ sp)
+{
+    for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < k; i += gridDim.x * kWG) {
+        sp[xs[i]] = 1;
+        sp[ys[i]] = 1;
+    }
+}
+
+// Lists the special vertices and gives each its index in the list.
+__global__ __launch_bounds__(kWG) void k_tie_compact(int n, unsigned char* __restrict__ sp,
+                                                     int* __restrict__ spid,
+                                                     int* __restrict__ slist, unsigned* scnt)
+{
+    __shared__ int buf[kWG * 16];
+    __shared__ unsigned nb, base;
+    if (threadIdx.x == 0) nb = 0;
+    __syncthreads();
+    BlockList bl{buf, &nb};
+    const int64_t v0 = (int64_t)blockIdx.x * (kWG * 16) + (int64_t)threadIdx.x * 16;
+    for (int q = 0; q < 16; ++q) {
+        const int64_t v = v0 + q;
+        const bool hit = v < n && sp[v] != 0;
+        blist_push(bl, hit, (int)v);
+    }
+    __syncthreads();
+    const unsigned cnt = nb;
+    if (threadIdx.x == 0) base = cnt ? atomicAdd(scnt, cnt) : 0u;
+    __syncthreads();
+    for (unsigned j = threadIdx.x; j < cnt; j += kWG) {
+        slist[base + j] = buf[j];
+        spid[buf[j]] = (int)(base + j);
+    }
+}
+
+// P(z) for every special z: -2 if z is on C (z is c* itself), -1 if the walk
+// reaches C first, else the index of the special vertex reached.  Every
+// policy path reaches C; the walk is still capped at n steps (-3).
+__global__ __launch_bounds__(kWG) void k_tie_walk(int n, unsigned ns, const int* __restrict__ slist,
+                                                  const int* __restrict__ succ,
+                                                  const unsigned char* __restrict__ sp,
+                                                  const unsigned char* __restrict__ onC,
+                                                  const int* __restrict__ spid,
+                                                  int* __restrict__ P)
+{
+    for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < ns; i += gridDim.x * kWG) {
+        const int z = slist[i];
+        if (onC[z]) {
+            P[i] = -2;
+            continue;
+        }
+        int x = succ[z];
+        int64_t steps = 0;
+        while (!sp[x] && !onC[x] && steps < n) {
+            x = succ[x];
+            ++steps;
+        }
+        P[i] = onC[x] ? -1 : (sp[x] ? spid[x] : -3);
+    }
+}
+
+// Endpoints of the X edges as special-vertex indices (-1 = on C).
+__global__ __launch_bounds__(kWG) void k_tie_ends(unsigned k, int* __restrict__ xs,
+                                                  int* __restrict__ ys,
+                                                  const unsigned char* __restrict__ onC,
+                                                  const int* __restrict__ spid,
+                                                  unsigned char* __restrict__ sp)
+{
+    for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < k; i += gridDim.x * kWG) {
+        const int x = xs[i], y = ys[i];
+        xs[i] = onC[x] ? -1 : spid[x];
+        ys[i] = onC[y] ? -1 : spid[y];
+    }
+    (void)sp;
+}
+
+__global__ __launch_bounds__(kWG) void k_clear_u8(int64_t len, unsigned char* __restrict__ p)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kWG)
+        p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint: d(optimum)/d(w_e) = 1/|C| on the edges of C, 0 elsewhere
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_fill_f64(int64_t len, double* __restrict__ p, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kWG)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kWG) void k_adjoint_scatter(int64_t len, const int* __restrict__ cyc,
+                                                         const double* __restrict__ g,
+                                                         double* __restrict__ grad)
+{
+    const double v = *g / (double)len;   // one IEEE division: correctly rounded
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kWG)
+        grad[cyc[i]] = v;
+}
+
+// float64 weights -> int64; flags non-integral values and |w| >= 2^53.
+__global__ __launch_bounds__(kWG) void k_w_from_f64(int64_t m, const double* __restrict__ w,
+                                                    long long* __restrict__ out, unsigned* bad)
+{
+    unsigned b = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kWG) {
+        const double x = w[i];
+        const bool ok = x == __builtin_trunc(x) && __builtin_fabs(x) < 9007199254740992.0;
+        out[i] = ok ? (long long)x : 0;
+        b |= ok ? 0u : 1u;
+    }
+    if (__ballot(b != 0) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
+// A given policy must pick one of each vertex's own out-edges.
+__global__ __launch_bounds__(kWG) void k_check_policy(int n, const int* __restrict__ row_ptr,
+                                                      const int* __restrict__ pi, unsigned* bad)
+{
+    unsigned b = 0;
+    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kWG) {
+        const int e = pi[v];
+        b |= (e < row_ptr[v] || e >= row_ptr[v + 1]) ? 1u : 0u;
+    }
+    if (__ballot(b != 0) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
 }
 
 __global__ void k_ctl_clear(Ctl* ctl, unsigned what)
 {
     if (threadIdx.x != 0) return;
+    if (what & kClrAll) {
+        unsigned* p = (unsigned*)ctl;
+        for (unsigned i = 0; i < sizeof(Ctl) / sizeof(unsigned); ++i) p[i] = 0;
+    }
     if (what & kClrChanged) {
         ctl->changed = 0;
         ctl->cbroken = 0;
         ctl->tight = 0;
+        ctl->certain = 0;
+        ctl->nondec = 0;
+        ctl->xcnt = 0;
+        ctl->scnt = 0;
+        ctl->bad = 0;
     }
     if (what & kClrCount) {
         ctl->ncyc = 0;
@@ -823,16 +918,6 @@ __global__ __launch_bounds__(kWG) void k_fill_u8(unsigned char* p, int64_t n, un
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kWG - 1) / kWG); }
-
-// Grid of a grid-stride kernel: enough blocks to fill the chip, few enough
-// that per-block counter atomics stay cheap.
-static inline unsigned stride_grid(int64_t n)
-{
-    const unsigned b = blocks_for(n);
-    return b < 2048 ? b : 2048;
-}
-
 // Items per block for list-producing kernels: spread over about 2048 blocks,
 // at most kListItems so the LDS buffer cannot overflow.
 static unsigned list_per_block(int64_t items)
@@ -968,6 +1053,15 @@ void launch_conn_collect(int k, int n, unsigned char* touched, int* cand, int* p
     k_conn_collect<<<grid, kWG, 0, st>>>(k, n, touched, cand, pi, layer, fout, fout_cnt);
 }
 
+void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsigned* tot,
+                           hipStream_t st)
+{
+    const unsigned nb = (unsigned)((len + kScanBlock - 1) / kScanBlock);
+    k_scan_a<<<nb, kWG, 0, st>>>(len, in, out, tot);
+    k_scan_b<<<1, 1024, 0, st>>>(nb, tot);
+    k_scan_c<<<stride_grid(len), kWG, 0, st>>>(len, out, tot);
+}
+
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
                       unsigned* tot, int* rin_ptr, int2* rin, int* cand, unsigned char* touched,
                       hipStream_t st)
@@ -1002,15 +1096,77 @@ void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active,
     k_val_round<<<stride_grid(n), kWG, 0, st>>>(n, s, Qin, Qout, active);
 }
 
-void launch_val_final(int n, const Jmp* Q, long long* V, Ctl* ctl, hipStream_t st)
+void launch_val_final(int n, const Jmp* Q, long long* V, int* hop, Ctl* ctl, hipStream_t st)
 {
-    k_val_final<<<blocks_for(n), kWG, 0, st>>>(n, Q, V, ctl);
+    k_val_final<<<blocks_for(n), kWG, 0, st>>>(n, Q, V, hop, ctl);
 }
 
 void launch_cycle_list(int n, int s, long long L, const unsigned char* onC, const int* pi,
-                       const Jmp* Q, int* out, hipStream_t st)
+                       const int* hop, int* out, hipStream_t st)
 {
-    k_cycle_list<<<blocks_for(n), kWG, 0, st>>>(n, s, L, onC, pi, Q, out);
+    k_cycle_list<<<blocks_for(n), kWG, 0, st>>>(n, s, L, onC, pi, hop, out);
+}
+
+template <typename WT>
+static void launch_short_walk_t(const SweepArgs& a, const void* w, int G, const int* succ,
+                                unsigned grid, hipStream_t st)
+{
+    const WT* ww = (const WT*)w;
+    switch (G) {
+        case 1: k_tie_short_walk<1, WT><<<grid, kWG, 0, st>>>(a, ww, succ); break;
+        case 2: k_tie_short_walk<2, WT><<<grid, kWG, 0, st>>>(a, ww, succ); break;
+        case 4: k_tie_short_walk<4, WT><<<grid, kWG, 0, st>>>(a, ww, succ); break;
+        case 8: k_tie_short_walk<8, WT><<<grid, kWG, 0, st>>>(a, ww, succ); break;
+        case 16: k_tie_short_walk<16, WT><<<grid, kWG, 0, st>>>(a, ww, succ); break;
+        case 32: k_tie_short_walk<32, WT><<<grid, kWG, 0, st>>>(a, ww, succ); break;
+        default: k_tie_short_walk<64, WT><<<grid, kWG, 0, st>>>(a, ww, succ); break;
+    }
+}
+
+void launch_tie_short_walk(const SweepArgs& a, const void* w, int wtype, int G, const int* succ,
+                           unsigned grid, hipStream_t st)
+{
+    if (wtype == kWI64) launch_short_walk_t<long long>(a, w, G, succ, grid, st);
+    else launch_short_walk_t<int>(a, w, G, succ, grid, st);
+}
+
+void launch_tie_special(int n, unsigned k, int* xs, int* ys, const int* succ,
+                        const unsigned char* onC, unsigned char* sp, int* spid, int* slist,
+                        unsigned* scnt, hipStream_t st)
+{
+    const int64_t len = (int64_t)n;
+    k_clear_u8<<<stride_grid(len), kWG, 0, st>>>(len, sp);
+    k_tie_mark<<<stride_grid(k), kWG, 0, st>>>(k, xs, ys, sp);
+    const unsigned grid = (unsigned)((len + kWG * 16 - 1) / (kWG * 16));
+    k_tie_compact<<<grid, kWG, 0, st>>>(n, sp, spid, slist, scnt);
+    (void)succ;
+    (void)onC;
+}
+
+void launch_tie_walk(int n, unsigned ns, const int* slist, const int* succ,
+                     const unsigned char* sp, const unsigned char* onC, const int* spid, int* P,
+                     unsigned k, int* xs, int* ys, hipStream_t st)
+{
+    if (ns) k_tie_walk<<<stride_grid(ns), kWG, 0, st>>>(n, ns, slist, succ, sp, onC, spid, P);
+    if (k) k_tie_ends<<<stride_grid(k), kWG, 0, st>>>(k, xs, ys, onC, spid, nullptr);
+    k_clear_u8<<<stride_grid(n), kWG, 0, st>>>(n, (unsigned char*)sp);
+}
+
+void launch_adjoint_scatter(int64_t m, const int* cyc, int64_t len, const double* g, double* grad,
+                            hipStream_t st)
+{
+    k_fill_f64<<<stride_grid(m), kWG, 0, st>>>(m, grad, 0.0);
+    if (len > 0) k_adjoint_scatter<<<stride_grid(len), kWG, 0, st>>>(len, cyc, g, grad);
+}
+
+void launch_w_from_f64(int64_t m, const double* w, long long* out, unsigned* bad, hipStream_t st)
+{
+    k_w_from_f64<<<stride_grid(m), kWG, 0, st>>>(m, w, out, bad);
+}
+
+void launch_check_policy(int n, const int* row_ptr, const int* pi, unsigned* bad, hipStream_t st)
+{
+    k_check_policy<<<stride_grid(n), kWG, 0, st>>>(n, row_ptr, pi, bad);
 }
 
 void launch_ctl_clear(Ctl* ctl, unsigned what, hipStream_t st)

@@ -23,6 +23,12 @@ ocm_status fail(ocm_status s, const char* what)
     return s;
 }
 
+}  // namespace
+
+void ocm::set_last_error(const char* what) { g_last_error = what; }
+
+namespace {
+
 #define HIP_TRY(expr)                                                                  \
     do {                                                                               \
         hipError_t e_ = (expr);                                                        \
@@ -44,12 +50,17 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // Hard bound on policy iterations when the caller sets none.
 constexpr int kIterCap = 1 << 20;
 
+// The exact uniqueness test lists at most this many tight non-policy edges;
+// beyond it the result is flagged OCM_F_TIE_UNCHECKED.
+constexpr int64_t kTieListCap = 1 << 20;
+
 // Workspace carved into the solver's device arrays.
 struct Ws {
     Ctl* ctl;
     long long* V;        // values scaled by L
     int* pi;             // policy: CSR position of each vertex's edge
     int* succ;           // policy successor
+    int* hop;            // policy hops to the source (value phase)
     Jmp* Q[2];           // pointer-jumping buffers (values; cycles alias them)
     int* rep;            // smallest vertex of the reached cycle
     unsigned char* onc;  // on a policy-graph cycle
@@ -64,6 +75,9 @@ struct Ws {
     int* cand;           // push rounds: best edge offered so far
     unsigned char* touched;  // push rounds: offered this round
     void* sel;           // select: per-block best candidates
+    int* xs;             // tie check: tight non-policy edges (tail), xcap entries
+    int* ys;             //            and head
+    unsigned xcap;
     long long* wsum;     // per-cycle weight sums, keyed by rep
     unsigned* lcnt;      // per-cycle lengths, keyed by rep
     int* cyc;            // cycle heads
@@ -85,6 +99,7 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.V = (long long*)take(8 * N);
     w.pi = (int*)take(4 * N);
     w.succ = (int*)take(4 * N);
+    w.hop = (int*)take(4 * N);
     w.Q[0] = (Jmp*)take(sizeof(Jmp) * N);
     w.Q[1] = (Jmp*)take(sizeof(Jmp) * N);
     w.rep = (int*)take(4 * N);
@@ -103,6 +118,9 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.cand = (int*)take(4 * N);
     w.touched = (unsigned char*)take(N + 16);
     w.sel = take(32 * ocm::kSelectParts);
+    w.xcap = (unsigned)(m < kTieListCap ? m : kTieListCap);
+    w.xs = (int*)take(4 * (size_t)w.xcap);
+    w.ys = (int*)take(4 * (size_t)w.xcap);
     w.wsum = (long long*)take(8 * N);
     w.lcnt = (unsigned*)take(4 * N);
     w.cyc = (int*)take(4 * N);
@@ -239,6 +257,10 @@ ocm_status setup(Ctx& c, const ocm_graph* g, int neg, void* ws, size_t ws_bytes,
     c.prof.out = prof;
     c.prof.st = c.st;
     memset(&c.h, 0, sizeof c.h);
+    // the workspace may hold anything: every entry point starts from a clean
+    // control block
+    ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrAll | ocm::kClrCount | ocm::kClrChanged, c.st);
+    HIP_TRY(hipGetLastError());
     return OCM_OK;
 }
 
@@ -262,7 +284,7 @@ ocm_status validate(Ctx& c, int check_csr)
 
 // Policy improvement sweep; afterwards c.h.changed / cbroken are current.
 ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long long W, long long L,
-                       int* pi, const unsigned char* onC)
+                       int* pi, const unsigned char* onC, bool collect = false)
 {
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrChanged, c.st);
     ocm::SweepArgs a;
@@ -276,6 +298,16 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     a.pi = pi;
     a.onC = onC;
     a.ctl = c.ws.ctl;
+    a.hop = tie ? c.ws.hop : nullptr;
+    a.xs = a.ys = nullptr;
+    a.xcnt = nullptr;
+    a.xcap = 0;
+    if (tie && collect) {
+        a.xs = c.ws.xs;
+        a.ys = c.ws.ys;
+        a.xcnt = &c.ws.ctl->xcnt;
+        a.xcap = c.ws.xcap;
+    }
     const int cls = tie ? OCM_K_TIESCAN : OCM_K_SWEEP;
     c.prof.begin(cls);
     ocm::launch_sweep(a, c.w, c.wtype, c.G, first, tie, c.sweep_grid, c.st);
@@ -435,7 +467,7 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
 // Otherwise every vertex must reach s.  *qfinal is the buffer holding the
 // final entries (their hop counts list C).
 ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, long long* V,
-                        bool probe, bool* stalled, int* rounds, int* qfinal)
+                        int* hop, bool probe, bool* stalled, int* rounds)
 {
     if (stalled) *stalled = false;
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrCount, c.st);
@@ -477,13 +509,138 @@ ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, 
     c.jump_rounds += k;
     if (rounds) *rounds = k;
     c.prof.begin(ph);
-    ocm::launch_val_final(c.n, c.ws.Q[a], V, c.ws.ctl, c.st);
+    ocm::launch_val_final(c.n, c.ws.Q[a], V, hop, c.ws.ctl, c.st);
     c.prof.end();
     c.prof.bytes(ph, 24.0 * c.n);
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
     if (c.h.overflow) return fail(OCM_E_OVERFLOW, "a value left [-2^62, 2^62]");
-    if (qfinal) *qfinal = a;
+    return OCM_OK;
+}
+
+// Does the small graph (nodes 0..N-1, edges from adjacency lists) hold a
+// cycle?  Iterative three-colour depth-first search.
+bool has_cycle(int N, const std::vector<int>& head, const std::vector<int>& next,
+               const std::vector<int>& to)
+{
+    std::vector<unsigned char> col(N, 0);
+    std::vector<std::pair<int, int>> st;
+    for (int r = 0; r < N; ++r) {
+        if (col[r]) continue;
+        col[r] = 1;
+        st.push_back({r, head[r]});
+        while (!st.empty()) {
+            auto& top = st.back();
+            if (top.second < 0) {
+                col[top.first] = 2;
+                st.pop_back();
+                continue;
+            }
+            const int e = top.second;
+            top.second = next[e];
+            const int u = to[e];
+            if (col[u] == 1) return true;
+            if (col[u] == 0) {
+                col[u] = 1;
+                st.push_back({u, head[u]});
+            }
+        }
+    }
+    return false;
+}
+
+// Exact uniqueness of C at the optimum.  A cycle is critical iff all its
+// edges are tight (the potential is feasible and reduced costs sum to zero
+// around critical cycles); policy edges are tight and hold only C.  So C is
+// the unique critical cycle iff no tight non-policy edge closes a cycle of
+// the tight subgraph.  Quick exact answers first (no such edge; a tight
+// self-loop; a tight edge leaving C), then the compressed special-vertex
+// graph described at k_tie_mark.
+ocm_status tie_check(Ctx& c, long long W, long long L, ocm_result* out)
+{
+    Ws& w = c.ws;
+    OCM_TRY(phase_sweep(c, false, true, w.V, W, L, w.pi, w.onC));
+    const unsigned long long k = c.h.tight;
+    out->tight_edges = (int64_t)k;
+    if (k == 0) return OCM_OK;
+    out->flags |= OCM_F_TIGHT_EDGES;
+    if (c.h.certain > 0) {
+        out->flags |= OCM_F_TIE;
+        return OCM_OK;
+    }
+    // With hop = policy hops to s, every policy edge lowers hop by one except
+    // s's own; a cycle of tight edges other than C, with no tight edge
+    // leaving C (certain == 0), needs a tight non-policy edge whose head is
+    // not nearer to s than its tail.
+    if (c.h.nondec == 0) return OCM_OK;
+    {
+        ocm::SweepArgs a;
+        a.n = c.n;
+        a.neg = c.neg;
+        a.row_ptr = c.row_ptr;
+        a.col = c.col;
+        a.V = w.V;
+        a.W = W;
+        a.L = L;
+        a.pi = w.pi;
+        a.onC = w.onC;
+        a.ctl = w.ctl;
+        a.hop = w.hop;
+        a.xs = a.ys = nullptr;
+        a.xcnt = nullptr;
+        a.xcap = 0;
+        c.prof.begin(OCM_K_TIESCAN);
+        ocm::launch_tie_short_walk(a, c.w, c.wtype, c.G, w.succ, c.sweep_grid, c.st);
+        c.prof.end();
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        if (c.h.certain > 0) {
+            out->flags |= OCM_F_TIE;
+            return OCM_OK;
+        }
+    }
+    if (k > w.xcap) {
+        out->flags |= OCM_F_TIE_UNCHECKED;
+        return OCM_OK;
+    }
+    OCM_TRY(phase_sweep(c, false, true, w.V, W, L, w.pi, w.onC, true));
+    const unsigned kx = c.h.xcnt;
+    if (kx != k) return fail(OCM_E_HIP, "tie scan listed a different edge count");
+    int* spid = w.layer;
+    int* slist = w.list[1];
+    int* P = w.list[0];
+    c.prof.begin(OCM_K_TIESCAN);
+    ocm::launch_tie_special(c.n, kx, w.xs, w.ys, w.succ, w.onC, w.touched, spid, slist,
+                            &w.ctl->scnt, c.st);
+    c.prof.end();
+    HIP_TRY(hipGetLastError());
+    OCM_TRY(read_ctl(c));
+    const unsigned ns = c.h.scnt;
+    c.prof.begin(OCM_K_TIESCAN);
+    ocm::launch_tie_walk(c.n, ns, slist, w.succ, w.touched, w.onC, spid, P, kx, w.xs, w.ys, c.st);
+    c.prof.end();
+    HIP_TRY(hipGetLastError());
+    std::vector<int> hp(ns), hx(kx), hy(kx);
+    if (ns) HIP_TRY(hipMemcpyAsync(hp.data(), P, 4 * (size_t)ns, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipMemcpyAsync(hx.data(), w.xs, 4 * (size_t)kx, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipMemcpyAsync(hy.data(), w.ys, 4 * (size_t)kx, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    // nodes: special vertices 0..ns-1, c* = ns; a special vertex on C is c*
+    const int N = (int)ns + 1;
+    auto node = [&](int id) { return (id < 0 || hp[id] == -2) ? (int)ns : id; };
+    std::vector<int> head(N, -1), next, to;
+    auto add = [&](int a, int b) {
+        to.push_back(b);
+        next.push_back(head[a]);
+        head[a] = (int)to.size() - 1;
+    };
+    for (unsigned i = 0; i < ns; ++i) {
+        if (hp[i] == -2) continue;
+        if (hp[i] == -3) return fail(OCM_E_HIP, "policy path does not reach the critical cycle");
+        add((int)i, hp[i] == -1 ? (int)ns : node(hp[i]));
+    }
+    for (unsigned i = 0; i < kx; ++i) add(node(hx[i]), node(hy[i]));
+    if (has_cycle(N, head, next, to)) out->flags |= OCM_F_TIE;
     return OCM_OK;
 }
 
@@ -521,25 +678,39 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     if (rc != OCM_OK) { c.prof.finish(); return rc; }
 
     Ws& w = c.ws;
-    int iter = 0, fast = 0, qf = 0;
-    bool have_c = false;
+    const bool warm = o.init_policy != nullptr;
+    if (warm) {
+        // warm start: the given policy replaces the first sweep
+        ocm::launch_ctl_clear(w.ctl, ocm::kClrChanged, c.st);
+        ocm::launch_check_policy(c.n, c.row_ptr, o.init_policy, &w.ctl->bad, c.st);
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        if (c.h.bad) return fail(OCM_E_INVALID_ARG, "init_policy picks an edge of another vertex");
+        HIP_TRY(hipMemcpyAsync(w.pi, o.init_policy, 4 * (size_t)c.n, hipMemcpyDeviceToDevice, c.st));
+    }
+    int iter = 0, fast = 0;
+    bool have_c = false, need_sweep = !warm;
     int s = -1;
     long long W = 0, L = 1;
     for (;;) {
-        rc = phase_sweep(c, iter == 0, false, w.V, W, L, w.pi, have_c ? w.onC : nullptr);
-        if (rc != OCM_OK) break;
-        ++iter;
-        if (iter >= 2 && c.h.changed == 0) break;            // no strict improvement left
-        if ((o.max_iters > 0 && iter >= o.max_iters) || iter >= kIterCap) {
-            rc = fail(OCM_E_NOT_CONVERGED, "max_iters reached");
-            break;
+        if (need_sweep) {
+            rc = phase_sweep(c, iter == 0 && !warm, false, w.V, W, L, w.pi, have_c ? w.onC : nullptr);
+            if (rc != OCM_OK) break;
+            ++iter;
+            // no strict improvement left (a cold start's first sweep always changes)
+            if (iter >= (warm ? 1 : 2) && c.h.changed == 0) break;
+            if ((o.max_iters > 0 && iter >= o.max_iters) || iter >= kIterCap) {
+                rc = fail(OCM_E_NOT_CONVERGED, "max_iters reached");
+                break;
+            }
         }
+        need_sweep = true;
         if (o.fast_path && have_c && !c.h.cbroken) {
             // C is still a cycle of the new policy.  If every vertex still
             // reaches s, C is the policy graph's only cycle: the cycle, select
             // and connect phases would change nothing, so only values remain.
             bool stalled = false;
-            rc = phase_values(c, w.pi, s, W, L, w.V, true, &stalled, nullptr, &qf);
+            rc = phase_values(c, w.pi, s, W, L, w.V, w.hop, true, &stalled, nullptr);
             if (rc != OCM_OK) break;
             if (!stalled) {
                 ++fast;
@@ -556,7 +727,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
         L = c.h.L;
         rc = phase_connect(c, w.rep, w.onc, s, w.pi, w.layer, w.onC, nullptr);
         if (rc != OCM_OK) break;
-        rc = phase_values(c, w.pi, s, W, L, w.V, false, nullptr, nullptr, &qf);
+        rc = phase_values(c, w.pi, s, W, L, w.V, w.hop, false, nullptr, nullptr);
         if (rc != OCM_OK) break;
         have_c = true;
     }
@@ -584,18 +755,16 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
         return fail(OCM_E_CAPACITY, "cycle_cap smaller than the critical cycle");
     }
     c.prof.begin(OCM_K_RESULT);
-    ocm::launch_cycle_list(c.n, s, L, w.onC, w.pi, w.Q[qf], cycle_edges, c.st);
+    ocm::launch_cycle_list(c.n, s, L, w.onC, w.pi, w.hop, cycle_edges, c.st);
     c.prof.end();
     c.prof.bytes(OCM_K_RESULT, (double)c.n + 28.0 * L);
     HIP_TRY(hipGetLastError());
     if (o.tie_check) {
-        rc = phase_sweep(c, false, true, w.V, W, L, w.pi, nullptr);
+        rc = tie_check(c, W, L, out);
         if (rc != OCM_OK) {
             c.prof.finish();
             return rc;
         }
-        out->tight_edges = (int64_t)c.h.tight;
-        if (c.h.tight > 0) out->flags |= OCM_F_TIGHT_EDGES | OCM_F_TIE_UNCHECKED;
     } else {
         out->flags |= OCM_F_TIE_UNCHECKED;
         out->tight_edges = -1;
@@ -612,6 +781,34 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
 }  // namespace
 
 extern "C" {
+
+ocm_status ocm_weights_from_f64(int64_t m, const double* w_f64, int64_t* w_i64, void* ws,
+                                size_t ws_bytes, void* stream)
+{
+    if (m < 1 || !w_f64 || !w_i64) return fail(OCM_E_INVALID_ARG, "null argument or m < 1");
+    if (!ws || ws_bytes < 256) return fail(OCM_E_WORKSPACE, "workspace must hold 256 bytes");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned* bad = (unsigned*)ws;
+    ocm::launch_zero2(bad, bad, st);
+    ocm::launch_w_from_f64(m, w_f64, (long long*)w_i64, bad, st);
+    HIP_TRY(hipGetLastError());
+    unsigned h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, bad, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h) return fail(OCM_E_INVALID_ARG, "weights must be integers with |w| < 2^53");
+    return OCM_OK;
+}
+
+ocm_status ocm_adjoint_scatter(int64_t m, const int32_t* cycle_edges, int64_t cycle_len,
+                               const double* grad_out, double* grad_w, void* stream)
+{
+    if (m < 1 || !grad_w || !grad_out || (cycle_len > 0 && !cycle_edges) || cycle_len < 0 ||
+        cycle_len > m)
+        return fail(OCM_E_INVALID_ARG, "bad adjoint arguments");
+    ocm::launch_adjoint_scatter(m, cycle_edges, cycle_len, grad_out, grad_w, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return OCM_OK;
+}
 
 void ocm_default_options(ocm_options* o)
 {
@@ -715,7 +912,7 @@ ocm_status ocm_phase_values(const ocm_graph* g, int32_t neg, const int32_t* pi, 
     if (!pi || !V) return fail(OCM_E_INVALID_ARG, "null argument");
     if (s < 0 || s >= c.n || L < 1) return fail(OCM_E_INVALID_ARG, "bad source or L");
     int r = 0;
-    ocm_status rc = phase_values(c, pi, s, W, L, (long long*)V, false, nullptr, &r, nullptr);
+    ocm_status rc = phase_values(c, pi, s, W, L, (long long*)V, nullptr, false, nullptr, &r);
     if (rounds) *rounds = r;
     HIP_TRY(hipStreamSynchronize(c.st));
     return rc;

@@ -70,7 +70,8 @@ class Profile(C.Structure):
 class Options(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("validate", C.c_int32), ("schedule", C.c_int32),
                 ("tie_check", C.c_int32), ("fast_path", C.c_int32),
-                ("connect_mode", C.c_int32), ("policy_out", C.c_void_p), ("potential_out", C.c_void_p),
+                ("connect_mode", C.c_int32), ("init_policy", C.c_void_p),
+                ("policy_out", C.c_void_p), ("potential_out", C.c_void_p),
                 ("profile", C.POINTER(Profile))]
 
 
@@ -104,6 +105,15 @@ def lib():
         for f in (L.ocm_phase_sweep, L.ocm_phase_cycles, L.ocm_phase_select,
                   L.ocm_phase_connect, L.ocm_phase_values):
             f.restype = C.c_int
+        L.ocm_batched_workspace_size.argtypes = [i64, P, P, G, O]
+        L.ocm_batched_workspace_size.restype = C.c_size_t
+        for f in (L.ocm_min_batched, L.ocm_max_batched):
+            f.argtypes = [i64, P, P, G, O, P, C.c_size_t, P, P, P, P, i64, P, P, P, P]
+            f.restype = C.c_int
+        L.ocm_weights_from_f64.argtypes = [i64, P, P, P, C.c_size_t, P]
+        L.ocm_weights_from_f64.restype = C.c_int
+        L.ocm_adjoint_scatter.argtypes = [i64, P, i64, P, P, P]
+        L.ocm_adjoint_scatter.restype = C.c_int
         L.ocm_status_string.argtypes = [C.c_int]
         L.ocm_status_string.restype = C.c_char_p
         L.ocm_last_error.restype = C.c_char_p
@@ -159,6 +169,7 @@ def workspace(g: Graph, device) -> torch.Tensor:
 
 def release_workspace():
     _ws_cache.clear()
+    _bws_cache.clear()
 
 
 @dataclasses.dataclass
@@ -198,12 +209,15 @@ CONNECT_MODES = {"auto": 0, "pull": 1, "push": 2}
 
 
 def options(max_iters=0, validate=True, schedule=0, tie_check=True, fast_path=True,
-            connect="auto") -> Options:
+            connect="auto", init_policy=None) -> Options:
     o = Options()
     lib().ocm_default_options(C.byref(o))
     o.max_iters, o.validate, o.schedule = max_iters, int(validate), schedule
     o.tie_check, o.fast_path = int(tie_check), int(fast_path)
     o.connect_mode = CONNECT_MODES[connect]
+    if init_policy is not None:
+        _dev(init_policy, (torch.int32,), "init_policy")
+        o.init_policy = init_policy.data_ptr()
     return o
 
 
@@ -247,6 +261,106 @@ def cycle_mean(row_ptr, col, w, mode: str = "min", **kw) -> Result:
     if mode not in ("min", "max"):
         raise ValueError("mode must be 'min' or 'max'")
     return (min_cycle_mean if mode == "min" else max_cycle_mean)(row_ptr, col, w, **kw)
+
+
+@dataclasses.dataclass
+class BatchResult:
+    p: list
+    q: list
+    cycle_ptr: list
+    cycle_edges: torch.Tensor     # int32 union CSR positions, graph by graph
+    iterations: list
+    flags: list
+    status: list
+
+    def value(self, g: int) -> Fraction:
+        return Fraction(self.p[g], self.q[g])
+
+    def cycle(self, g: int) -> torch.Tensor:
+        return self.cycle_edges[self.cycle_ptr[g]:self.cycle_ptr[g + 1]]
+
+    def tie(self, g: int):
+        f = self.flags[g]
+        if f & OCM_F_TIE:
+            return True
+        if f & OCM_F_TIE_UNCHECKED:
+            return None
+        return False
+
+
+_bws_cache: dict = {}
+
+
+def cycle_mean_batched(row_ptr, col, w, vptr, eptr, mode: str = "min", **opt) -> BatchResult:
+    """Every graph of a disjoint-union CSR solved concurrently
+    (ocm_min_batched / ocm_max_batched).  vptr, eptr: host int64 sequences."""
+    import numpy as np
+    if mode not in ("min", "max"):
+        raise ValueError("mode must be 'min' or 'max'")
+    g = make_graph(row_ptr, col, w)
+    vp = np.ascontiguousarray(vptr, dtype=np.int64)
+    ep = np.ascontiguousarray(eptr, dtype=np.int64)
+    G = len(vp) - 1
+    o = options(**opt)
+    P = C.c_void_p
+    need = lib().ocm_batched_workspace_size(G, vp.ctypes.data_as(P), ep.ctypes.data_as(P),
+                                            C.byref(g), C.byref(o))
+    if need == 0:
+        _check(OCM_E_INVALID_ARG)
+    key = torch.device(col.device)
+    ws = _bws_cache.get(key)
+    if ws is None or ws.numel() < need:
+        _bws_cache.pop(key, None)
+        ws = torch.empty(need, dtype=torch.uint8, device=col.device)
+        _bws_cache[key] = ws
+    p = np.zeros(G, np.int64)
+    q = np.zeros(G, np.int64)
+    cptr = np.zeros(G + 1, np.int64)
+    iters = np.zeros(G, np.int32)
+    flags = np.zeros(G, np.uint32)
+    status = np.zeros(G, np.int32)
+    cyc = torch.empty(g.n, dtype=torch.int32, device=col.device)
+    fn = lib().ocm_min_batched if mode == "min" else lib().ocm_max_batched
+    rc = fn(G, vp.ctypes.data_as(P), ep.ctypes.data_as(P), C.byref(g), C.byref(o),
+            C.c_void_p(ws.data_ptr()), ws.numel(), p.ctypes.data_as(P), q.ctypes.data_as(P),
+            cptr.ctypes.data_as(P), C.c_void_p(cyc.data_ptr()), g.n, iters.ctypes.data_as(P),
+            flags.ctypes.data_as(P), status.ctypes.data_as(P), _stream())
+    res = BatchResult(p.tolist(), q.tolist(), cptr.tolist(), cyc[:int(cptr[-1])],
+                      iters.tolist(), flags.tolist(), status.tolist())
+    if rc != OCM_OK and all(x == OCM_OK for x in res.status):
+        _check(rc)
+    return res
+
+
+_small_ws: dict = {}
+
+
+def weights_from_f64(w: torch.Tensor) -> torch.Tensor:
+    """int64 copy of float64 weights; raises unless every weight is an integer
+    with |w| < 2^53 (ocm_weights_from_f64)."""
+    _dev(w, (torch.float64,), "w")
+    out = torch.empty(w.numel(), dtype=torch.int64, device=w.device)
+    key = torch.device(w.device)
+    if key not in _small_ws:
+        _small_ws[key] = torch.empty(256, dtype=torch.uint8, device=w.device)
+    ws = _small_ws[key]
+    _check(lib().ocm_weights_from_f64(w.numel(), C.c_void_p(w.data_ptr()),
+                                      C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                      ws.numel(), _stream()))
+    return out
+
+
+def adjoint_scatter(m: int, cycle_edges: torch.Tensor, grad_out: torch.Tensor) -> torch.Tensor:
+    """float64[m] gradient: grad_out / |C| on the cycle's edges, 0 elsewhere
+    (ocm_adjoint_scatter); grad_out is a one-element float64 GPU tensor."""
+    _dev(cycle_edges, (torch.int32,), "cycle_edges")
+    g = grad_out.reshape(1).to(torch.float64).contiguous()
+    _dev(g, (torch.float64,), "grad_out")
+    grad = torch.empty(m, dtype=torch.float64, device=cycle_edges.device)
+    _check(lib().ocm_adjoint_scatter(m, C.c_void_p(cycle_edges.data_ptr()), cycle_edges.numel(),
+                                     C.c_void_p(g.data_ptr()), C.c_void_p(grad.data_ptr()),
+                                     _stream()))
+    return grad
 
 
 # -------------------------------------------------------------------------

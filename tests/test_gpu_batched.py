@@ -1,0 +1,112 @@
+"""Batched solver (concurrent regions) through the C ABI: every graph of a
+disjoint union must get exactly the result of a separate solve -- the
+oracle's value, cycle, source and iteration count -- and graphs fail
+independently."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import native
+from paper_1111_0627_amd import ocm, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    ocm.lib()
+    yield
+    ocm.release_workspace()
+
+
+def to_dev(g):
+    return (torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(),
+            torch.from_numpy(g.w).cuda())
+
+
+def mixed_batch(seed, G=60, lo=2, hi=5000):
+    rng = np.random.default_rng(seed)
+    gs = []
+    for k in range(G):
+        n = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        gs.append(synth.random_digraph(n, 1, int(rng.integers(1, 9)), 1, int(rng.integers(5, 10000)),
+                                       np.int32, seed=[seed, k]))
+    return gs
+
+
+@pytest.mark.parametrize("mode,seed", [("min", 0), ("max", 1), ("min", 2)])
+def test_batched_equals_oracle_per_graph(mode, seed):
+    gs = mixed_batch(seed)
+    u, vptr, eptr = synth.disjoint_union(gs)
+    res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr, mode=mode)
+    assert all(s == ocm.OCM_OK for s in res.status)
+    for k, g in enumerate(gs):
+        sol = native.solve(g.row_ptr, g.col, g.w, mode=mode)
+        cyc = (res.cycle(k).cpu().numpy() - eptr[k]).tolist()
+        assert (res.p[k], res.q[k], cyc, res.iterations[k]) == \
+            (sol.p, sol.q, sol.cycle.tolist(), sol.iterations), k
+        t = res.tie(k)
+        if t is not None:
+            assert t == bool(sol.tie), k
+
+
+def test_batched_equals_plain_gpu_calls():
+    gs = mixed_batch(5, G=40, lo=50, hi=30000)
+    u, vptr, eptr = synth.disjoint_union(gs)
+    res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr)
+    for k, g in enumerate(gs):
+        r = ocm.min_cycle_mean(*to_dev(g))
+        cyc = (res.cycle(k).cpu().numpy() - eptr[k]).tolist()
+        assert (res.p[k], res.q[k], cyc, res.iterations[k]) == \
+            (r.p, r.q, r.cycle_edges.cpu().tolist(), r.iterations)
+        flag_bits = ocm.OCM_F_TIE | ocm.OCM_F_TIGHT_EDGES
+        if res.tie(k) is not None:
+            assert res.flags[k] & flag_bits == r.flags & flag_bits
+
+
+def test_batched_schedules_and_fast_path_agree():
+    gs = mixed_batch(9, G=30, lo=100, hi=20000)
+    u, vptr, eptr = synth.disjoint_union(gs)
+    ref = None
+    for lanes in (2, 8, 32):
+        for fast in (True, False):
+            r = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr, schedule=lanes, fast_path=fast)
+            cur = (r.p, r.q, r.iterations, r.cycle_ptr, r.cycle_edges.cpu().tolist())
+            if ref is None:
+                ref = cur
+            assert cur == ref
+
+
+def test_batched_graphs_fail_independently():
+    good = synth.random_digraph(300, 1, 4, 1, 50, np.int32, 1)
+    # two disjoint rings: strongly connected fails
+    bad = synth.Graph(np.array([0, 1, 2, 3, 4], np.int32), np.array([1, 0, 3, 2], np.int32),
+                      np.array([1, 1, 5, 5], np.int32))
+    other = synth.random_digraph(700, 2, 5, 1, 50, np.int32, 2)
+    u, vptr, eptr = synth.disjoint_union([good, bad, other])
+    res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr)
+    assert res.status == [ocm.OCM_OK, ocm.OCM_E_NOT_STRONGLY_CONNECTED, ocm.OCM_OK]
+    for k, g in ((0, good), (2, other)):
+        sol = native.solve(g.row_ptr, g.col, g.w)
+        assert (res.p[k], res.q[k], res.iterations[k]) == (sol.p, sol.q, sol.iterations)
+
+
+def test_batched_rejects_edges_between_graphs():
+    a = synth.random_digraph(50, 1, 3, 1, 9, np.int32, 1)
+    b = synth.random_digraph(60, 1, 3, 1, 9, np.int32, 2)
+    u, vptr, eptr = synth.disjoint_union([a, b])
+    u.col[3] = 70          # an edge of graph 0 into graph 1
+    with pytest.raises(ocm.OCMError) as ex:
+        ocm.cycle_mean_batched(*to_dev(u), vptr, eptr)
+    assert ex.value.status == ocm.OCM_E_BAD_CSR
+
+
+def test_batched_single_graph_and_tiny_graphs():
+    gs = [synth.random_digraph(n, 1, 2, 1, 5, np.int32, n) for n in (1, 2, 3, 1, 7)]
+    u, vptr, eptr = synth.disjoint_union(gs)
+    res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr)
+    for k, g in enumerate(gs):
+        sol = native.solve(g.row_ptr, g.col, g.w)
+        assert (res.p[k], res.q[k], res.iterations[k]) == (sol.p, sol.q, sol.iterations)

@@ -18,6 +18,7 @@ from oracle import brute, closed, native
 from paper_1111_0627_amd import ocm, synth
 
 pytestmark = pytest.mark.gpu
+TIE_LIST_CAP = 1 << 20
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -46,6 +47,11 @@ def assert_same(res, sol, tie=True):
     assert got == exp
     if tie:
         assert res.tight_edges == sol.tight
+        if sol.tie >= 0:
+            if res.tie is None:       # undecided only when the edge list overflows
+                assert res.tight_edges > TIE_LIST_CAP
+            else:
+                assert res.tie == bool(sol.tie)
 
 
 def gpu_solve(rp, cl, w, mode="min", wdtype=None, **kw):
@@ -68,7 +74,7 @@ def test_hand_traces_full_solve(tr):
         res = gpu_solve(rp, cl, w, fast_path=fast)
         assert (res.p, res.q, res.cycle_edges.cpu().tolist(), res.source, res.iterations) == \
             (r["p"], r["q"], r["cycle"], r["source"], r["iterations"])
-        assert (res.tight_edges > 0) == bool(r["tie"])
+        assert res.tie == bool(r["tie"])
 
 
 @pytest.mark.parametrize("tr", _traces(), ids=lambda t: t["name"])
@@ -140,6 +146,30 @@ def test_trace_driven_phases(n, dlo, dhi, wlo, whi, seed, mode):
         assert np.array_equal(V.cpu().numpy(), st.get("val"))
     else:
         pytest.fail("no convergence")
+
+
+def test_phase_entry_points_ignore_stale_workspace_contents():
+    """Every entry point starts from a clean control block, whatever the
+    workspace held before (regression: a stale overflow flag)."""
+    g = synth.random_digraph(3000, 1, 4, 1, 100, np.int32, 6)
+    rp, cl, w = to_dev(g.row_ptr, g.col, g.w)
+    st = native.Stepper(g.row_ptr, g.col, g.w)
+    st.sweep()
+    st.cycles()
+    s, W, L = st.select()
+    st.connect()
+    st.values()
+    pi = torch.from_numpy(st.get("pi")).cuda()
+    ws = ocm.workspace(ocm.make_graph(rp, cl, w), rp.device)
+    ws.fill_(255)
+    V, _ = ocm.phase_values(rp, cl, w, pi, s, W, L)
+    assert np.array_equal(V.cpu().numpy(), st.get("val"))
+    ws.fill_(255)
+    rep, onc, _ = ocm.phase_cycles(rp, cl, w, pi)
+    ws.fill_(255)
+    assert ocm.phase_select(rp, cl, w, pi, rep, onc) == (s, W, L)
+    ws.fill_(255)
+    assert ocm.phase_sweep(rp, cl, w, pi.clone(), V, W, L) == st.sweep()
 
 
 # ---------------------------------------------------------------------------
@@ -339,8 +369,10 @@ def test_full_workloads_against_oracle_results(name):
     g = synth.workload(name)
     assert (g.n, g.m) == (gold["n"], gold["m"])
     res = gpu_solve(g.row_ptr, g.col, g.w, mode=gold["mode"], want_potential=True)
-    got = (res.p, res.q, res.cycle_edges.cpu().tolist(), res.source, res.iterations, res.tight_edges)
-    exp = (gold["p"], gold["q"], gold["cycle"], gold["source"], gold["iterations"], gold["tight"])
+    got = (res.p, res.q, res.cycle_edges.cpu().tolist(), res.source, res.iterations,
+           res.tight_edges, res.tie)
+    exp = (gold["p"], gold["q"], gold["cycle"], gold["source"], gold["iterations"], gold["tight"],
+           bool(gold["tie"]))
     assert got == exp
     # independent optimality certificate of the GPU's own potential
     assert native.certify(g.row_ptr, g.col, g.w, res.p, res.q, res.cycle_edges.cpu().numpy(),
