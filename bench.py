@@ -67,6 +67,112 @@ def cpu_baseline(g, mode, budget_s=30.0):
                 seconds=round(dt, 2), iterations=sol.iterations, p=sol.p, q=sol.q)
 
 
+def bench_batched(steps: int):
+    """The batched workload: 4,096 random digraphs solved in one batched call
+    (ocm_min_batched), against 4,096 sequential single-graph GPU calls."""
+    import torch
+    from paper_1111_0627_amd import ocm, synth
+    t = time.time()
+    gs = synth.batch_graphs()
+    u, vptr, eptr = synth.disjoint_union(gs)
+    log(f"[bench] batch4096: G={len(gs)} N={u.n} M={u.m} generated in {time.time() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(u.row_ptr).to(dev)
+    cl = torch.from_numpy(u.col).to(dev)
+    w = torch.from_numpy(u.w).to(dev)
+    res = ocm.cycle_mean_batched(rp, cl, w, vptr, eptr)      # cold call
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        t = time.perf_counter()
+        r = ocm.cycle_mean_batched(rp, cl, w, vptr, eptr)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t) * 1e3)
+    assert (r.p, r.q, r.iterations) == (res.p, res.q, res.iterations)
+    # the same graphs, one plain call each (graphs already resident)
+    rps = [rp[int(vptr[k]):int(vptr[k + 1]) + 1] - int(eptr[k]) for k in range(len(gs))]
+    plain_ms = 0.0
+    agree = 0
+    for k in range(len(gs)):
+        e0, e1, v0, v1 = int(eptr[k]), int(eptr[k + 1]), int(vptr[k]), int(vptr[k + 1])
+        rk = rps[k].contiguous()
+        ck = (cl[e0:e1] - v0).contiguous()
+        wk = w[e0:e1]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x = ocm.min_cycle_mean(rk, ck, wk)
+        torch.cuda.synchronize()
+        plain_ms += (time.perf_counter() - t) * 1e3
+        agree += (x.p, x.q, x.iterations) == (r.p[k], r.q[k], r.iterations[k])
+    its = np.array(r.iterations)
+    med = float(np.median(times))
+    return {"workload": "batch4096", "graphs": len(gs), "vertices": u.n, "edges": u.m,
+            "batched_ms": {"median": med, "min": min(times)},
+            "plain_calls_total_ms": plain_ms, "speedup_vs_plain_calls": plain_ms / med,
+            "graphs_agreeing_with_plain": agree,
+            "iterations": {"min": int(its.min()), "median": float(np.median(its)),
+                           "max": int(its.max()), "sum": int(its.sum())},
+            "edges_per_s_per_iter": float(sum(g.m * i for g, i in zip(gs, r.iterations)) / (med / 1e3))}
+
+
+def bench_adjoint(n_fd: int):
+    """The adjoint workload: n = 2^22 random digraph with int64 weights;
+    forward through the autograd Function, backward (adjoint scatter), and the
+    exact unit finite-difference check on a stratified edge sample."""
+    import torch
+    from paper_1111_0627_amd import autograd, gradcheck, ocm, synth
+    g = synth.workload("rand4m_i64")
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    cl = torch.from_numpy(g.col).to(dev)
+    wi = torch.from_numpy(g.w).to(dev)
+    wf = wi.to(torch.float64)
+    base = ocm.min_cycle_mean(rp, cl, wi, want_policy=True)
+    torch.cuda.synchronize()
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t) * 1e3)
+        return float(np.median(ts))
+
+    plain = timed(lambda: ocm.min_cycle_mean(rp, cl, wi))
+
+    def fwd_bwd():
+        x = wf.clone().requires_grad_(True)
+        v = autograd.cycle_mean(x, rp, cl)
+        v.backward()
+        return x.grad
+
+    def fwd_only():
+        with torch.no_grad():
+            return autograd.cycle_mean(wf, rp, cl)
+
+    fwd = timed(fwd_only)
+    fb = timed(fwd_bwd)
+    gout = torch.ones((), dtype=torch.float64, device=dev)
+    scat = timed(lambda: ocm.adjoint_scatter(g.m, base.cycle_edges, gout), reps=20)
+    grad = fwd_bwd()
+    exp = torch.zeros(g.m, dtype=torch.float64, device=dev)
+    exp[base.cycle_edges.long()] = 1.0 / len(base.cycle_edges)
+    edges = gradcheck.stratified_edges(base.cycle_edges.cpu().numpy(), g.row_ptr, g.m, total=n_fd)
+    t = time.perf_counter()
+    rep = gradcheck.fd_check(rp, cl, wi, edges, base=base, w_host=g.w)
+    fd_s = time.perf_counter() - t
+    return {"workload": "rand4m_i64", "n": g.n, "m": g.m, "cycle_len": len(base.cycle_edges),
+            "tie": base.tie, "plain_forward_ms": plain, "autograd_forward_ms": fwd,
+            "forward_backward_ms": fb, "adjoint_scatter_ms": scat,
+            "grad_matches_1_over_C": bool(torch.equal(grad, exp)),
+            "fd": {**rep.as_dict(), "edges": len(edges), "seconds": round(fd_s, 2),
+                   "note": "each perturbed solve warm-started from the base policy; "
+                           "its final no-improvement sweep certifies it"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +181,9 @@ def main():
     ap.add_argument("--workload", default="product16x6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--fd-edges", type=int, default=1000)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy one buffer of this many MiB (a plain copy "
                          "kernel of known size, to calibrate HBM byte counters)")
@@ -178,6 +287,12 @@ def main():
         out["roofline"] = roofline(dom, *phase[dom])
         out["roofline"]["class"] = dom
         out["roofline_sweep"] = roofline("sweep", *phase["sweep"])
+    if not args.no_adjoint:
+        log("[bench] adjoint workload ...")
+        out["adjoint"] = bench_adjoint(args.fd_edges)
+    if not args.no_batched:
+        log("[bench] batched workload ...")
+        out["batched"] = bench_batched(max(2, min(args.steps, 5)))
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle ...")
         cb = cpu_baseline(g, mode)
