@@ -34,8 +34,8 @@ KERNEL_NAMES = {
     "cycles": "k_pj_init/round/final (policy-graph cycles)",
     "select": "k_cyc_zero/sum + k_select (minimum-mean cycle)",
     "conn_pull": "k_conn_init/pull (rebuild, pull rounds)",
-    "conn_offer": "k_conn_offer (rebuild, push offers)",
-    "conn_collect": "k_conn_collect (rebuild, push collection)",
+    "conn_mark": "k_conn_mark (rebuild, push marks)",
+    "conn_claim": "k_conn_claim (rebuild, push claims)",
     "reverse": "k_rev_count/fill + scan (reverse CSR)",
     "values": "k_val_init/round/final (values after a rebuild)",
     "fast": "k_val_init/round/final (values, fast path)",

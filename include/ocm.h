@@ -109,8 +109,8 @@ enum {
     OCM_K_CYCLES,         /* policy-graph cycles: init, jump rounds, final   */
     OCM_K_SELECT,         /* per-cycle sums and the minimum-mean select      */
     OCM_K_CONN_PULL,      /* rebuild: init and pull rounds                   */
-    OCM_K_CONN_OFFER,     /* rebuild: push-round offers                      */
-    OCM_K_CONN_COLLECT,   /* rebuild: push-round collection                  */
+    OCM_K_CONN_MARK,      /* rebuild: push-round marks                       */
+    OCM_K_CONN_CLAIM,     /* rebuild: push-round claims                      */
     OCM_K_REVERSE,        /* reverse CSR build                               */
     OCM_K_VALUES,         /* value propagation after a rebuild               */
     OCM_K_FAST,           /* value propagation of the fast path              */
@@ -129,13 +129,16 @@ typedef struct {
     int32_t max_iters;         /* 0 = unlimited                                */
     int32_t validate;          /* 1 = check the CSR on the device first        */
     int32_t schedule;          /* lanes per vertex in the sweep: 1..64 (power
-                                  of two), 0 = chosen from the mean degree     */
+                                  of two), 0 = chosen from the mean degree
+                                  (batched calls: autotuned)                   */
     int32_t tie_check;         /* 1 = run the exact uniqueness test of C       */
     int32_t fast_path;         /* 1 = fuse cycle/value phases while the critical
                                   cycle is unchanged (same results)            */
     int32_t connect_mode;      /* rebuild rounds: 0 = pick pull or push per
                                   round, 1 = pull only, 2 = push only (same
                                   results)                                     */
+    int32_t tile;              /* batched calls: vertices per work chunk,
+                                  512..4096, 0 = autotuned                     */
     const int32_t *init_policy;/* device int32[n] or NULL: warm start.  The
                                   given policy (one out-edge position per
                                   vertex) replaces the first sweep; the optimum
@@ -254,6 +257,13 @@ ocm_status ocm_max_batched(int64_t G, const int64_t *vptr, const int64_t *eptr,
                            int64_t *p, int64_t *q, int64_t *cycle_ptr, int32_t *cycle_edges,
                            int64_t cycle_cap, int32_t *iters, uint32_t *flags, int32_t *status,
                            void *stream);
+
+/* The schedule the last batched call on this thread used: sweep lanes per
+ * vertex, chunk size, and whether it was timed now (1) or taken from the
+ * autotuner's per-size-class cache (0).  The batched loop runs each
+ * iteration as two captured hipGraphs around the rebuild rounds; setting the
+ * environment variable OCM_BATCH_GRAPH=0 enqueues the same kernels directly. */
+void ocm_batched_last_schedule(int32_t *lanes, int32_t *tile, int32_t *tuned);
 
 /* ---------------------------------------------------------------------- */
 /* Differentiation (not in the paper).  Away from ties the optimum is a    */

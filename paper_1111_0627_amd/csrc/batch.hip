@@ -16,6 +16,7 @@
 #include "ocm.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -28,6 +29,8 @@
 
 namespace ocm {
 namespace b {
+
+constexpr int kMinChunk = 512;   // smallest chunk the workspace is sized for
 
 // per-graph modes
 constexpr int kDone = 0;      // converged or failed
@@ -49,6 +52,7 @@ struct GArrays {              // device arrays with one entry per graph
     unsigned* vact;           // values: some vertex unfinished after the round
     unsigned* vprog;          // values: some vertex finished in the round
     unsigned* ovf;
+    int* fin;                 // values: ping-pong buffer holding the final entries
     unsigned char* have_c;
     unsigned long long* tight;
     unsigned long long* certain;
@@ -312,12 +316,12 @@ __global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chun
     int g;
     int64_t v0, v1;
     if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
+    if (!ga.vrun[g]) return;   // finished or stalled graph: its entries stay put
     const int s = ga.s[g];
-    const bool run = ga.vrun[g] != 0;
     unsigned act = 0, prog = 0;
     for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
         Jmp q = Qin[v];
-        if (run && q.J != s) {
+        if (q.J != s) {
             const Jmp r = Qin[q.J];
             long long d;
             if (__builtin_add_overflow(q.D, r.D, &d)) {
@@ -342,7 +346,8 @@ __global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chun
 // After a value round: a graph is finished when no vertex is unfinished; a
 // graph whose round finished nothing while vertices remain never reaches s
 // (fast path: C is no longer the only cycle).
-__global__ __launch_bounds__(kWG) void k_val_update(int G, GArrays ga, int want, BCtl* bc)
+__global__ __launch_bounds__(kWG) void k_val_update(int G, GArrays ga, int want, int rounds,
+                                                    BCtl* bc)
 {
     unsigned running = 0;
     for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
@@ -351,7 +356,8 @@ __global__ __launch_bounds__(kWG) void k_val_update(int G, GArrays ga, int want,
         ga.vact[g] = 0;
         ga.vprog[g] = 0;
         if (!a) {
-            ga.vrun[g] = 0;           // finished: values are ready
+            ga.vrun[g] = 0;           // finished: entries are in buffer rounds & 1
+            ga.fin[g] = rounds & 1;
         } else if (!p) {
             ga.vrun[g] = 0;
             if (want == kFast) ga.mode[g] = kGeneral;   // fall back
@@ -387,13 +393,22 @@ __global__ __launch_bounds__(kWG) void k_val_mark(const int2* __restrict__ chunk
 
 __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chunks,
                                                    const unsigned* nch, int T, GArrays ga,
-                                                   int want, const Jmp* __restrict__ Q,
+                                                   int want, const Jmp* __restrict__ Q0,
+                                                   const Jmp* __restrict__ Q1,
                                                    long long* __restrict__ V, int* __restrict__ hop)
 {
     int g;
     int64_t v0, v1;
     if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
     if (ga.mode[g] != want) return;   // fell back or failed
+    if (ga.vrun[g]) {                 // did not finish within the rounds
+        if (threadIdx.x == 0) {
+            ga.mode[g] = kDone;
+            ga.status[g] = OCM_E_HIP;
+        }
+        return;
+    }
+    const Jmp* __restrict__ Q = ga.fin[g] ? Q1 : Q0;
     unsigned bad = 0;
     for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
         const Jmp q = Q[v];
@@ -801,15 +816,16 @@ struct BWs {
     unsigned* rdeg;
     unsigned* stot;
     int* rin_ptr;
-    int2* rin;
-    int* cand;
+    int* rin;
+    unsigned* abits;
     unsigned char* touched;
     unsigned* bad;
     size_t total;
 };
 
-BWs bcarve(void* base, int64_t G, int64_t n, int64_t m, int T)
+BWs bcarve(void* base, int64_t G, int64_t n, int64_t m)
 {
+    const int T = ocm::b::kMinChunk;
     char* b = (char*)base;
     size_t off = 0;
     auto take = [&](size_t bytes) -> void* {
@@ -835,6 +851,7 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m, int T)
     a.vact = (unsigned*)take(4 * Gs);
     a.vprog = (unsigned*)take(4 * Gs);
     a.ovf = (unsigned*)take(4 * Gs);
+    a.fin = (int*)take(4 * Gs);
     a.have_c = (unsigned char*)take(Gs);
     a.tight = (unsigned long long*)take(8 * Gs);
     a.certain = (unsigned long long*)take(8 * Gs);
@@ -866,8 +883,8 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m, int T)
     w.rdeg = (unsigned*)take(4 * (N + 1));
     w.stot = (unsigned*)take(4 * ((N + 1) / 2048 + 2));
     w.rin_ptr = (int*)take(4 * (N + 1));
-    w.rin = (int2*)take(8 * M);
-    w.cand = (int*)take(4 * N);
+    w.rin = (int*)take(4 * M);
+    w.abits = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.touched = (unsigned char*)take(N + 16);
     w.bad = (unsigned*)take(256);
     w.total = off;
@@ -906,14 +923,16 @@ struct BCtx {
 
 ocm_status bread(BCtx& c)
 {
-    BHIP(hipMemcpyAsync(&c.h, c.ws.bc, sizeof(BCtl), hipMemcpyDeviceToHost, c.st));
-    BHIP(hipStreamSynchronize(c.st));
+    BHIP(ocm::host_read(c.ws.bc, &c.h, sizeof(BCtl), c.st));
     return OCM_OK;
 }
 
-// Chunk list of the graphs in `want` (a mode, or -1 = every graph not done);
-// returns the number of chunks.
-ocm_status build_chunks(BCtx& c, int want, unsigned* nch_out)
+unsigned max_chunks(const BCtx& c) { return (unsigned)(c.n / ocm::b::kMinChunk + c.G + 1); }
+
+// Chunk list of the graphs in `want` (a mode, -1 = every graph not done,
+// -2 = every graph), built on the device; kernels read the count from
+// device memory, so nothing here waits for the host.
+void enqueue_chunks(BCtx& c, int want)
 {
     GArrays& a = c.ws.ga;
     const int T = c.sch.chunk;
@@ -923,6 +942,11 @@ ocm_status build_chunks(BCtx& c, int want, unsigned* nch_out)
     ocm::b::k_chunk_fill<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a.ccnt, a.coff,
                                                                      a.vptr, T, c.ws.chunks,
                                                                      &c.ws.bc->nchunks);
+}
+
+ocm_status build_chunks(BCtx& c, int want, unsigned* nch_out)
+{
+    enqueue_chunks(c, want);
     BHIP(hipGetLastError());
     BTRY(bread(c));
     *nch_out = c.h.nchunks;
@@ -998,75 +1022,131 @@ void launch_bwalk(BCtx& c, unsigned nch)
     else launch_bwalk_t<int>(c, nch);
 }
 
-// Values for the graphs in mode `want` (kFast probes; kGeneral must finish).
-ocm_status bvalues(BCtx& c, int want)
+int jump_rounds(const BCtx& c)
+{
+    int K = 0;
+    while ((int64_t(1) << K) < c.max_n) ++K;
+    return K;
+}
+
+// Values for the graphs in mode `want` with a fixed number of rounds: every
+// policy path has fewer than max_n edges, so K = ceil(log2 max_n) rounds
+// finish every graph that reaches its source.  kFast graphs that stop
+// progressing fall back to the general phases; kGeneral ones fail.
+void enqueue_values(BCtx& c, int want)
 {
     BWs& ws = c.ws;
     GArrays& a = ws.ga;
     const int T = c.sch.chunk;
-    unsigned nch = 0;
-    BTRY(build_chunks(c, want, &nch));
-    if (nch == 0) return OCM_OK;
+    const unsigned mc = max_chunks(c);
+    enqueue_chunks(c, want);
     if (c.wtype == OCM_W_I64)
-        ocm::b::k_val_init<long long><<<nch, ocm::kWG, 0, c.st>>>(
+        ocm::b::k_val_init<long long><<<mc, ocm::kWG, 0, c.st>>>(
             ws.chunks, &ws.bc->nchunks, T, a, c.col, ws.pi, (const long long*)c.w, c.neg, ws.succ,
             ws.Q[0]);
     else
-        ocm::b::k_val_init<int><<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, c.col,
-                                                            ws.pi, (const int*)c.w, c.neg, ws.succ,
-                                                            ws.Q[0]);
-    ocm::b::k_val_mark<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.Q[0]);
-    int cur = 0;
-    for (int k = 0; k < 80; ++k) {
-        ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->vrunning, nullptr);
-        ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, ws.bc);
-        BHIP(hipGetLastError());
-        BTRY(bread(c));
-        if (c.h.vrunning == 0) break;
-        ocm::b::k_val_round<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.Q[cur],
-                                                        ws.Q[cur ^ 1]);
-        cur ^= 1;
+        ocm::b::k_val_init<int><<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, c.col,
+                                                           ws.pi, (const int*)c.w, c.neg, ws.succ,
+                                                           ws.Q[0]);
+    ocm::b::k_val_mark<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.Q[0]);
+    const int R = jump_rounds(c);
+    for (int r = 0; r < R; ++r) {
+        ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, r,
+                                                                         ws.bc);
+        ocm::b::k_val_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a,
+                                                       ws.Q[r & 1], ws.Q[(r + 1) & 1]);
     }
-    if (c.h.vrunning != 0) return bfail(OCM_E_HIP, "value propagation did not converge");
-    ocm::b::k_val_final<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, want,
-                                                    ws.Q[cur], ws.V, ws.hop);
+    ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, R, ws.bc);
+    ocm::b::k_val_final<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, want, ws.Q[0],
+                                                   ws.Q[1], ws.V, ws.hop);
     ocm::b::k_values_done<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want);
-    BHIP(hipGetLastError());
-    return OCM_OK;
 }
 
-// Rebuild rounds over the union (pull or push per round, as in ocm_min).
-ocm_status bconnect(BCtx& c, unsigned nch)
+// Cycles, exact vote and the start of the rebuild for kGeneral graphs.
+void enqueue_general_head(BCtx& c)
 {
     BWs& ws = c.ws;
     GArrays& a = ws.ga;
     const int T = c.sch.chunk;
+    const unsigned mc = max_chunks(c);
+    enqueue_chunks(c, ocm::b::kGeneral);
+    auto* P0 = (unsigned long long*)ws.Q[0];
+    auto* P1 = (unsigned long long*)ws.Q[1];
+    const int K = jump_rounds(c);
+    ocm::b::k_pj_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, c.col, ws.pi, P0,
+                                                 ws.onc);
+    for (int k = 0; k < K; ++k) {
+        ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0, P1);
+        std::swap(P0, P1);
+    }
+    ocm::b::k_pj_final<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0, ws.rep,
+                                                  ws.onc);
+    ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ncyc, nullptr);
+    ocm::b::k_cyc_zero<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep, ws.onc,
+                                                  ws.wsum, ws.lcnt, ws.heads, ws.bc);
+    if (c.wtype == OCM_W_I64)
+        ocm::b::k_cyc_sum<long long><<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a,
+                                                                ws.rep, ws.onc, ws.pi,
+                                                                (const long long*)c.w, c.neg,
+                                                                ws.wsum, ws.lcnt);
+    else
+        ocm::b::k_cyc_sum<int><<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep,
+                                                          ws.onc, ws.pi, (const int*)c.w, c.neg,
+                                                          ws.wsum, ws.lcnt);
+    ocm::b::k_vote<<<2048, ocm::kWG, 0, c.st>>>(ws.heads, ws.bc, a, ws.wsum, ws.lcnt);
+    ocm::b::k_set_lambda<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, ws.wsum,
+                                                                     ws.lcnt);
+    enqueue_chunks(c, ocm::b::kGeneral);   // graphs whose vote failed retired
     ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[0], &ws.bc->fcnt[0]);
-    ocm::b::k_conn_init<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep, ws.onc,
-                                                    ws.layer, ws.onC, ws.list[0], &ws.bc->ucnt[0],
-                                                    ws.flist[0], &ws.bc->fcnt[0]);
-    BHIP(hipGetLastError());
-    BTRY(bread(c));
+    ocm::b::k_conn_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep, ws.onc,
+                                                   ws.layer, ws.onC, ws.list[0], &ws.bc->ucnt[0],
+                                                   ws.flist[0], &ws.bc->fcnt[0]);
+}
+
+// One iteration up to the rebuild rounds: sweep, retire converged graphs,
+// fast-path values, then cycles / vote / rebuild start for the others.
+void enqueue_head(BCtx& c, int max_iters, bool fast_path)
+{
+    BWs& ws = c.ws;
+    GArrays& a = ws.ga;
+    enqueue_chunks(c, ocm::b::kActive);
+    launch_bsweep(c, max_chunks(c), false);
+    ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->nactive, &ws.bc->nfast);
+    ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ngeneral, nullptr);
+    ocm::b::k_after_sweep<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, max_iters,
+                                                                      ws.bc);
+    if (fast_path) enqueue_values(c, ocm::b::kFast);
+    else ocm::b::k_fast_to_general<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a);
+    enqueue_general_head(c);
+}
+
+// Rebuild rounds over the union after k_conn_init (pull or push per round,
+// as in ocm_min); reads back the list sizes, so it runs outside the graphs.
+ocm_status host_connect(BCtx& c)
+{
+    BWs& ws = c.ws;
+    GArrays& a = ws.ga;
     unsigned left = c.h.ucnt[0], ulen = left, front = c.h.fcnt[0];
     int ua = 0, fa = 0, k = 0;
+    if (left > 0) ocm::launch_bits_from_layer(c.n, ws.layer, ws.abits, c.st);
     while (left > 0) {
         ++k;
         const int ub = ua ^ 1, fb = fa ^ 1;
         const bool push = left >= (1u << 16) && (uint64_t)front * 4 < left;
         if (push && !c.rev_built) {
             ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, ws.rdeg, ws.stot, ws.rin_ptr, ws.rin,
-                                  ws.cand, ws.touched, c.st);
+                                  ws.touched, c.st);
             c.rev_built = true;
         }
         ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[ub], &ws.bc->fcnt[fb]);
-        // the plain kernels' counters live in Ctl; pass the batch ones instead
+        if (k > 1) ocm::launch_bits_set(ws.flist[fa], front, ws.abits, c.st);
         if (push) {
-            ocm::launch_conn_offer(ws.rin_ptr, ws.rin, ws.layer, ws.cand, ws.touched, ws.flist[fa],
-                                   front, (ocm::Ctl*)ws.bad, c.st);
-            ocm::launch_conn_collect(k, c.n, ws.touched, ws.cand, ws.pi, ws.layer, ws.flist[fb],
-                                     &ws.bc->fcnt[fb], c.st);
+            ocm::launch_conn_mark(ws.rin_ptr, ws.rin, ws.abits, ws.touched, ws.flist[fa], front,
+                                  &ws.bc->pedges, c.st);
+            ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, ws.abits, ws.touched, ws.pi, ws.layer,
+                                   ws.flist[fb], &ws.bc->fcnt[fb], &ws.bc->ledges, c.st);
         } else {
-            ocm::launch_conn_pull(k, c.row_ptr, c.col, ws.layer, ws.pi, ws.list[ua], ulen,
+            ocm::launch_conn_pull(k, c.row_ptr, c.col, ws.abits, ws.layer, ws.pi, ws.list[ua], ulen,
                                   ws.list[ub], &ws.bc->ucnt[ub], ws.flist[fb], &ws.bc->fcnt[fb],
                                   &ws.bc->ledges, c.st);
         }
@@ -1083,10 +1163,11 @@ ocm_status bconnect(BCtx& c, unsigned nch)
         if (got == 0) {
             // the remaining vertices cannot reach their graph's cycle
             if (push) {
-                // refresh the unattached list with a pull pass that attaches nobody
+                // refresh the unattached list with a pull pass, which attaches
+                // nobody: the attached set is the one the push round saw
                 ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[ub], &ws.bc->fcnt[fb]);
-                ocm::launch_conn_pull(k, c.row_ptr, c.col, ws.layer, ws.pi, ws.list[ua], ulen,
-                                      ws.list[ub], &ws.bc->ucnt[ub], ws.flist[fb],
+                ocm::launch_conn_pull(k, c.row_ptr, c.col, ws.abits, ws.layer, ws.pi, ws.list[ua],
+                                      ulen, ws.list[ub], &ws.bc->ucnt[ub], ws.flist[fb],
                                       &ws.bc->fcnt[fb], &ws.bc->ledges, c.st);
                 BTRY(bread(c));
                 ulen = c.h.ucnt[ub];
@@ -1103,46 +1184,129 @@ ocm_status bconnect(BCtx& c, unsigned nch)
     return OCM_OK;
 }
 
-ocm_status bgeneral(BCtx& c)
-{
-    BWs& ws = c.ws;
-    GArrays& a = ws.ga;
-    const int T = c.sch.chunk;
-    unsigned nch = 0;
-    BTRY(build_chunks(c, ocm::b::kGeneral, &nch));
-    if (nch == 0) return OCM_OK;
-    auto* P0 = (unsigned long long*)ws.Q[0];
-    auto* P1 = (unsigned long long*)ws.Q[1];
-    int K = 0;
-    while ((int64_t(1) << K) < c.max_n) ++K;
-    ocm::b::k_pj_init<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, c.col, ws.pi, P0,
-                                                  ws.onc);
-    for (int k = 0; k < K; ++k) {
-        ocm::b::k_pj_round<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0, P1);
-        std::swap(P0, P1);
+// The two fixed parts of an iteration as captured hipGraphs.
+struct Loop {
+    hipStream_t cs = nullptr;
+    hipGraphExec_t head = nullptr, tail = nullptr;
+    ~Loop()
+    {
+        if (head) (void)hipGraphExecDestroy(head);
+        if (tail) (void)hipGraphExecDestroy(tail);
+        if (cs) (void)hipStreamDestroy(cs);
     }
-    ocm::b::k_pj_final<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0, ws.rep,
-                                                   ws.onc);
-    ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ncyc, nullptr);
-    ocm::b::k_cyc_zero<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep, ws.onc,
-                                                   ws.wsum, ws.lcnt, ws.heads, ws.bc);
-    if (c.wtype == OCM_W_I64)
-        ocm::b::k_cyc_sum<long long><<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a,
-                                                                 ws.rep, ws.onc, ws.pi,
-                                                                 (const long long*)c.w, c.neg,
-                                                                 ws.wsum, ws.lcnt);
-    else
-        ocm::b::k_cyc_sum<int><<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep,
-                                                           ws.onc, ws.pi, (const int*)c.w, c.neg,
-                                                           ws.wsum, ws.lcnt);
-    ocm::b::k_vote<<<2048, ocm::kWG, 0, c.st>>>(ws.heads, ws.bc, a, ws.wsum, ws.lcnt);
-    ocm::b::k_set_lambda<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, ws.wsum, ws.lcnt);
+};
+
+template <typename F>
+ocm_status capture(BCtx& c, Loop& lp, hipGraphExec_t* out, F&& body)
+{
+    hipStream_t user = c.st;
+    c.st = lp.cs;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(lp.cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        body();
+        e = hipStreamEndCapture(lp.cs, &g);
+    }
+    c.st = user;
+    if (e != hipSuccess || !g) {
+        (void)hipGetLastError();
+        return bfail(OCM_E_HIP, "graph capture failed");
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return bfail(OCM_E_HIP, "graph instantiation failed");
+    return OCM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: lanes per vertex and chunk size, timed on the batch itself
+// (one sweep plus two jump rounds per candidate) and cached per size class
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int wtype, gbits, nbits, lanes0;
+    bool operator<(const TuneKey& o) const
+    {
+        if (wtype != o.wtype) return wtype < o.wtype;
+        if (gbits != o.gbits) return gbits < o.gbits;
+        if (nbits != o.nbits) return nbits < o.nbits;
+        return lanes0 < o.lanes0;
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, Schedule> g_tune;
+thread_local Schedule g_last_sched = {0, 0};
+thread_local int g_last_tuned = 0;
+
+int bits_of(int64_t x)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < x) ++b;
+    return b;
+}
+
+ocm_status autotune(BCtx& c, Schedule* out, int* tuned)
+{
+    const int l0 = default_lanes(c.n, c.m);
+    const TuneKey key{c.wtype, bits_of(c.G), bits_of(c.n / std::max<int64_t>(c.G, 1)), l0};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *out = it->second;
+            *tuned = 0;
+            return OCM_OK;
+        }
+    }
+    std::vector<Schedule> cands;
+    for (int l : {l0 / 2, l0, l0 * 2})
+        if (l >= 1 && l <= 64)
+            for (int t : {512, 1024, 2048}) cands.push_back({l, t});
+    hipEvent_t e0, e1;
+    BHIP(hipEventCreate(&e0));
+    BHIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    Schedule best = {l0, 1024};
+    BWs& ws = c.ws;
+    for (const Schedule& s : cands) {
+        c.sch = s;
+        enqueue_chunks(c, -2);
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+            BHIP(hipEventRecord(e0, c.st));
+            launch_bsweep(c, max_chunks(c), false);   // iteration 0: the first sweep
+            auto* P0 = (unsigned long long*)ws.Q[0];
+            auto* P1 = (unsigned long long*)ws.Q[1];
+            const unsigned mc = max_chunks(c);
+            ocm::b::k_pj_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
+                                                         c.col, ws.pi, P0, ws.onc);
+            ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
+                                                          P0, P1);
+            ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
+                                                          P1, P0);
+            BHIP(hipEventRecord(e1, c.st));
+            BHIP(hipEventSynchronize(e1));
+            float t = 0.f;
+            BHIP(hipEventElapsedTime(&t, e0, e1));
+            ms = rep == 0 ? t : std::min(ms, t);
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = s;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // the timing sweeps touched per-graph counters: start clean
+    ocm::b::k_graph_init<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, ws.ga);
     BHIP(hipGetLastError());
-    // graphs whose vote failed retired above; rebuild the chunk list
-    BTRY(build_chunks(c, ocm::b::kGeneral, &nch));
-    if (nch == 0) return OCM_OK;
-    BTRY(bconnect(c, nch));
-    return bvalues(c, ocm::b::kGeneral);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = best;
+    }
+    *out = best;
+    *tuned = 1;
+    return OCM_OK;
 }
 
 long long bgcd(long long a, long long b)
@@ -1183,6 +1347,9 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
     if (o_in) o = *o_in;
     else ocm_default_options(&o);
     if (o.init_policy) return bfail(OCM_E_INVALID_ARG, "warm start is not supported in batches");
+    // a chunk's vertices are listed through an LDS buffer of kListItems
+    if (o.tile != 0 && (o.tile < ocm::b::kMinChunk || o.tile > ocm::kListItems))
+        return bfail(OCM_E_INVALID_ARG, "tile must be 0 or in [512, 4096]");
     BCtx c;
     c.G = G;
     c.n = (int)u->n;
@@ -1200,9 +1367,9 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
           c.sch.lanes == 16 || c.sch.lanes == 32 || c.sch.lanes == 64))
         return bfail(OCM_E_INVALID_ARG, "schedule must be a power of two <= 64");
     for (int64_t g = 0; g < G; ++g) c.max_n = (int)std::max<int64_t>(c.max_n, vptr[g + 1] - vptr[g]);
-    c.ws = bcarve(nullptr, G, u->n, u->m, c.sch.chunk);
+    c.ws = bcarve(nullptr, G, u->n, u->m);
     if (!wsp || ws_bytes < c.ws.total) return bfail(OCM_E_WORKSPACE, "workspace missing or too small");
-    c.ws = bcarve(wsp, G, u->n, u->m, c.sch.chunk);
+    c.ws = bcarve(wsp, G, u->n, u->m);
     BWs& ws = c.ws;
     GArrays& a = ws.ga;
 
@@ -1238,27 +1405,38 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
         }
     }
 
+    // schedule: given (lanes, tile), or autotuned and cached per size class
+    int tuned = 0;
+    if (o.schedule <= 0 || o.tile <= 0) {
+        Schedule t;
+        BTRY(autotune(c, &t, &tuned));
+        if (o.schedule <= 0) c.sch.lanes = t.lanes;
+        if (o.tile <= 0) c.sch.chunk = t.chunk;
+    }
+    if (o.tile > 0) c.sch.chunk = o.tile;
+    g_last_sched = {c.sch.lanes, c.sch.chunk};
+    g_last_tuned = tuned;
+
+    // iterations: [head graph] -> host rebuild rounds -> [tail graph]
+    const char* env = getenv("OCM_BATCH_GRAPH");
+    const bool use_graph = !(env && env[0] == '0');
+    Loop lp;
+    if (use_graph) {
+        BHIP(hipStreamCreate(&lp.cs));
+        BTRY(capture(c, lp, &lp.head, [&] { enqueue_head(c, o.max_iters, o.fast_path != 0); }));
+        BTRY(capture(c, lp, &lp.tail, [&] { enqueue_values(c, ocm::b::kGeneral); }));
+    }
     for (int guard = 0;; ++guard) {
         if (guard > (1 << 20)) return bfail(OCM_E_NOT_CONVERGED, "iteration guard");
-        unsigned nch = 0;
-        BTRY(build_chunks(c, ocm::b::kActive, &nch));
-        if (nch == 0) break;
-        launch_bsweep(c, nch, false);
-        ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->nactive, &ws.bc->nfast);
-        ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ngeneral, nullptr);
-        ocm::b::k_after_sweep<<<ocm::stride_grid(G), ocm::kWG, 0, c.st>>>((int)G, a, o.max_iters, ws.bc);
+        if (use_graph) BHIP(hipGraphLaunch(lp.head, c.st));
+        else enqueue_head(c, o.max_iters, o.fast_path != 0);
         BHIP(hipGetLastError());
         BTRY(bread(c));
-        if (c.h.nactive == 0) continue;   // everything converged (loop exits next)
-        if (c.h.nfast > 0) {
-            if (o.fast_path) {
-                BTRY(bvalues(c, ocm::b::kFast));
-            } else {
-                ocm::b::k_fast_to_general<<<ocm::stride_grid(G), ocm::kWG, 0, c.st>>>((int)G, a);
-                BHIP(hipGetLastError());
-            }
-        }
-        BTRY(bgeneral(c));
+        if (c.h.nactive == 0) break;   // every graph converged or failed
+        BTRY(host_connect(c));
+        if (use_graph) BHIP(hipGraphLaunch(lp.tail, c.st));
+        else enqueue_values(c, ocm::b::kGeneral);
+        BHIP(hipGetLastError());
     }
 
     // per-graph results
@@ -1293,6 +1471,7 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
         // every graph; the kernels skip failed ones
         unsigned nch = 0;
         BTRY(build_chunks(c, -2, &nch));
+        if (nch == 0) nch = 1;
         ocm::b::k_cycle_list<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, c.sch.chunk, a,
                                                          ws.cptr, ws.onC, ws.pi, ws.hop, cycle_edges);
         if (o.tie_check) {
@@ -1329,7 +1508,7 @@ size_t ocm_batched_workspace_size(int64_t G, const int64_t* vptr, const int64_t*
 {
     (void)o;
     if (check_batch(G, vptr, eptr, u) != OCM_OK) return 0;
-    return bcarve(nullptr, G, u->n, u->m, 1024).total;
+    return bcarve(nullptr, G, u->n, u->m).total;
 }
 
 ocm_status ocm_min_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, const ocm_graph* u,
@@ -1348,6 +1527,13 @@ ocm_status ocm_max_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, 
 {
     return solve_batched(G, vptr, eptr, u, o, ws, ws_bytes, p, q, cycle_ptr, cycle_edges, cycle_cap,
                          iters, flags, status, stream, 1);
+}
+
+void ocm_batched_last_schedule(int32_t* lanes, int32_t* tile, int32_t* tuned)
+{
+    if (lanes) *lanes = g_last_sched.lanes;
+    if (tile) *tile = g_last_sched.chunk;
+    if (tuned) *tuned = g_last_tuned;
 }
 
 }  // extern "C"

@@ -39,8 +39,8 @@ struct alignas(16) Ctl {
     unsigned long long maxabsw;    // validation: max |w|
     unsigned overflow;             // values: a value left [-2^62, 2^62]
     unsigned pad;
-    unsigned long long pedges;     // connect: in-edges scanned by push offers
-    unsigned long long ledges;     // connect: out-edges scanned by pull rounds
+    unsigned long long pedges;     // connect: in-edges scanned by push marks
+    unsigned long long ledges;     // connect: out-edges scanned by pull rounds and push claims
     unsigned long long certain;    // tie scan: edges that certainly close a second critical cycle
     unsigned long long nondec;     // tie scan: tight non-policy edges not nearer the source
     unsigned xcnt;                 // tie scan: tight non-policy edges listed
@@ -95,16 +95,20 @@ void launch_select(const int* cyc_list, const long long* wsum, const unsigned* l
 void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, int* layer,
                       unsigned char* onC, int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt,
                       hipStream_t st);
-void launch_conn_pull(int k, const int* row_ptr, const int* col, int* layer, int* pi,
-                      const int* in_list, unsigned in_cnt, int* ulist, unsigned* ucnt, int* flist,
-                      unsigned* fcnt, unsigned long long* ledges, hipStream_t st);
-void launch_conn_offer(const int* rin_ptr, const int2* rin, const int* layer, int* cand,
-                       unsigned char* touched, const int* fin, unsigned f_cnt, Ctl* ctl,
-                       hipStream_t st);
-void launch_conn_collect(int k, int n, unsigned char* touched, int* cand, int* pi, int* layer,
-                         int* fout, unsigned* fout_cnt, hipStream_t st);
+// bitmap of the vertices attached before the current rebuild round
+void launch_bits_from_layer(int n, const int* layer, unsigned* abits, hipStream_t st);
+void launch_bits_set(const int* list, unsigned cnt, unsigned* abits, hipStream_t st);
+void launch_conn_pull(int k, const int* row_ptr, const int* col, const unsigned* abits, int* layer,
+                      int* pi, const int* in_list, unsigned in_cnt, int* ulist, unsigned* ucnt,
+                      int* flist, unsigned* fcnt, unsigned long long* ledges, hipStream_t st);
+void launch_conn_mark(const int* rin_ptr, const int* rin, const unsigned* abits,
+                      unsigned char* touched, const int* fin, unsigned f_cnt,
+                      unsigned long long* pedges, hipStream_t st);
+void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* abits,
+                       unsigned char* touched, int* pi, int* layer, int* fout, unsigned* fout_cnt,
+                       unsigned long long* cedges, hipStream_t st);
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
-                      unsigned* tot, int* rin_ptr, int2* rin, int* cand, unsigned char* touched,
+                      unsigned* tot, int* rin_ptr, int* rin, unsigned char* touched,
                       hipStream_t st);
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
                      int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl, hipStream_t st);
@@ -120,6 +124,10 @@ void launch_zero2(unsigned* a, unsigned* b, hipStream_t st);
 // exclusive prefix sum of len values; tot needs len/2048 + 1 entries
 void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsigned* tot,
                            hipStream_t st);
+
+// Reads `bytes` (a multiple of 4, at most 256) of device memory into host
+// memory once the stream's earlier work is done.
+hipError_t host_read(const void* dsrc, void* hdst, size_t bytes, hipStream_t st);
 
 // thread-local message returned by ocm_last_error()
 void set_last_error(const char* what);

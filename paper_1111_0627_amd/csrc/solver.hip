@@ -71,9 +71,9 @@ struct Ws {
     unsigned* rdeg;      // reverse CSR: in-degree, then fill cursor (n+1)
     unsigned* stot;      // prefix-sum block totals
     int* rin_ptr;        // reverse CSR offsets (n+1)
-    int2* rin;           // reverse CSR entries (source, CSR position) (m)
-    int* cand;           // push rounds: best edge offered so far
-    unsigned char* touched;  // push rounds: offered this round
+    int* rin;            // reverse CSR entries: the tail of each in-edge (m)
+    unsigned* abits;     // connect: bitmap of the vertices attached before the round
+    unsigned char* touched;  // push rounds: marked this round
     void* sel;           // select: per-block best candidates
     int* xs;             // tie check: tight non-policy edges (tail), xcap entries
     int* ys;             //            and head
@@ -114,8 +114,8 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.rdeg = (unsigned*)take(4 * (N + 1));
     w.stot = (unsigned*)take(4 * ((N + 1) / 2048 + 2));
     w.rin_ptr = (int*)take(4 * (N + 1));
-    w.rin = (int2*)take(8 * M);
-    w.cand = (int*)take(4 * N);
+    w.rin = (int*)take(4 * M);
+    w.abits = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.touched = (unsigned char*)take(N + 16);
     w.sel = take(32 * ocm::kSelectParts);
     w.xcap = (unsigned)(m < kTieListCap ? m : kTieListCap);
@@ -202,8 +202,7 @@ constexpr unsigned kPushMinUnattached = 1u << 16;
 
 ocm_status read_ctl(Ctx& c)
 {
-    HIP_TRY(hipMemcpyAsync(&c.h, c.ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
-    HIP_TRY(hipStreamSynchronize(c.st));
+    HIP_TRY(ocm::host_read(c.ws.ctl, &c.h, sizeof(Ctl), c.st));
     return OCM_OK;
 }
 
@@ -371,7 +370,7 @@ ocm_status phase_select(Ctx& c, const int* pi, const int* rep, const unsigned ch
 }
 
 // Rebuild around C: component of C keeps pi, the rest attaches breadth-first.
-// Each round is a pull or a push round (same result, see k_conn_push).
+// Each round is a pull or a push round (same result, see k_conn_claim).
 ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s, int* pi,
                          int* layer, unsigned char* onC, int* rounds)
 {
@@ -386,6 +385,12 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
     c.prof.bytes(OCM_K_CONN_PULL, 10.0 * c.n + 4.0 * ((double)c.h.ucnt[0] + c.h.fcnt[0]));
     unsigned long long pe0 = c.h.pedges, le0 = c.h.ledges;
     unsigned left = c.h.ucnt[0], ulen = left, front = c.h.fcnt[0];
+    if (left > 0) {
+        c.prof.begin(OCM_K_CONN_PULL);
+        ocm::launch_bits_from_layer(c.n, layer, w.abits, c.st);
+        c.prof.end();
+        c.prof.bytes(OCM_K_CONN_PULL, 4.125 * c.n);
+    }
     int ua = 0, fa = 0, k = 0;
     ocm_status rc = OCM_OK;
     while (left > 0) {
@@ -398,47 +403,58 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
         if (push && !c.rev_built) {
             c.prof.begin(OCM_K_REVERSE);
             ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr, w.rin,
-                                  w.cand, w.touched, c.st);
+                                  w.touched, c.st);
             c.prof.end();
-            // count: col + counter per edge; scan and cursor copy; fill: row_ptr,
-            // col, cursor and the 8-byte entry per edge; cand and touched fills
-            c.prof.bytes(OCM_K_REVERSE, 24.0 * c.m + 33.0 * c.n);
+            // count: col + counter per edge; fill, scan and copy of the
+            // counters; fill: row_ptr, col, cursor and the 4-byte tail per
+            // edge; touched reset
+            c.prof.bytes(OCM_K_REVERSE, 20.0 * c.m + 29.0 * c.n);
             HIP_TRY(hipGetLastError());
             c.rev_built = true;
         }
+        const int cls = push ? OCM_K_CONN_MARK : OCM_K_CONN_PULL;
         ocm::launch_zero2(&w.ctl->ucnt[ub], &w.ctl->fcnt[fb], c.st);
-        if (push) {
-            c.prof.begin(OCM_K_CONN_OFFER);
-            ocm::launch_conn_offer(w.rin_ptr, w.rin, layer, w.cand, w.touched, w.flist[fa], front,
-                                   w.ctl, c.st);
+        if (k > 1) {
+            // the previous round's frontier joins the attached set
+            c.prof.begin(cls);
+            ocm::launch_bits_set(w.flist[fa], front, w.abits, c.st);
             c.prof.end();
-            c.prof.begin(OCM_K_CONN_COLLECT);
-            ocm::launch_conn_collect(k, c.n, w.touched, w.cand, pi, layer, w.flist[fb],
-                                     &w.ctl->fcnt[fb], c.st);
+            c.prof.bytes(cls, 8.0 * front);
+        }
+        if (push) {
+            c.prof.begin(OCM_K_CONN_MARK);
+            ocm::launch_conn_mark(w.rin_ptr, w.rin, w.abits, w.touched, w.flist[fa], front,
+                                  &w.ctl->pedges, c.st);
+            c.prof.end();
+            c.prof.begin(OCM_K_CONN_CLAIM);
+            ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, w.abits, w.touched, pi, layer,
+                                   w.flist[fb], &w.ctl->fcnt[fb], &w.ctl->ledges, c.st);
             c.prof.end();
             c.push_frontier += front;
         } else {
             c.prof.begin(OCM_K_CONN_PULL);
-            ocm::launch_conn_pull(k, c.row_ptr, c.col, layer, pi, w.list[ua], ulen, w.list[ub],
-                                  &w.ctl->ucnt[ub], w.flist[fb], &w.ctl->fcnt[fb], &w.ctl->ledges,
-                                  c.st);
+            ocm::launch_conn_pull(k, c.row_ptr, c.col, w.abits, layer, pi, w.list[ua], ulen,
+                                  w.list[ub], &w.ctl->ucnt[ub], w.flist[fb], &w.ctl->fcnt[fb],
+                                  &w.ctl->ledges, c.st);
             c.prof.end();
         }
         HIP_TRY(hipGetLastError());
         OCM_TRY(read_ctl(c));
         const unsigned got = c.h.fcnt[fb];
+        const double S = (double)(c.h.ledges - le0);
         if (push) {
-            // offer: frontier entry and offsets, then per in-edge the (u, e)
-            // entry and u's layer; collect: the touched bytes plus cand, pi,
-            // layer, cand reset, touched reset and list entry per attached vertex
+            // mark: frontier entry and offsets, then per in-edge the 4-byte
+            // tail and its bit, and one touched byte per attached vertex;
+            // claim: the touched bytes, then per attached vertex its offsets,
+            // pi, layer and list entry, and per scanned out-edge col and a bit
             const double E = (double)(c.h.pedges - pe0);
-            c.prof.bytes(OCM_K_CONN_OFFER, 12.0 * front + 12.0 * E);
-            c.prof.bytes(OCM_K_CONN_COLLECT, (double)c.n + 21.0 * got);
+            c.prof.bytes(OCM_K_CONN_MARK, 12.0 * front + 4.125 * E + got);
+            c.prof.bytes(OCM_K_CONN_CLAIM, (double)c.n + 20.0 * got + 4.125 * S);
         } else {
-            // list entry, offsets and own layer per listed vertex; col + layer
+            // list entry, offsets and own bit per listed vertex; col and a bit
             // per scanned edge; pi, layer and list entries of the outcome
-            const double S = (double)(c.h.ledges - le0);
-            c.prof.bytes(OCM_K_CONN_PULL, 16.0 * ulen + 8.0 * S + 12.0 * got + 4.0 * c.h.ucnt[ub]);
+            c.prof.bytes(OCM_K_CONN_PULL,
+                         12.125 * ulen + 4.125 * S + 12.0 * got + 4.0 * c.h.ucnt[ub]);
         }
         pe0 = c.h.pedges;
         le0 = c.h.ledges;

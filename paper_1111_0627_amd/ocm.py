@@ -32,8 +32,8 @@ OCM_E_HIP = -9
 OCM_W_I32, OCM_W_I64 = 0, 1
 OCM_F_TIE, OCM_F_TIE_UNCHECKED, OCM_F_TIGHT_EDGES = 1, 2, 4
 
-PHASES = ("validate", "sweep", "tiescan", "cycles", "select", "conn_pull", "conn_offer",
-          "conn_collect", "reverse", "values", "fast", "result")
+PHASES = ("validate", "sweep", "tiescan", "cycles", "select", "conn_pull", "conn_mark",
+          "conn_claim", "reverse", "values", "fast", "result")
 
 
 class OCMError(RuntimeError):
@@ -70,7 +70,7 @@ class Profile(C.Structure):
 class Options(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("validate", C.c_int32), ("schedule", C.c_int32),
                 ("tie_check", C.c_int32), ("fast_path", C.c_int32),
-                ("connect_mode", C.c_int32), ("init_policy", C.c_void_p),
+                ("connect_mode", C.c_int32), ("tile", C.c_int32), ("init_policy", C.c_void_p),
                 ("policy_out", C.c_void_p), ("potential_out", C.c_void_p),
                 ("profile", C.POINTER(Profile))]
 
@@ -110,6 +110,7 @@ def lib():
         for f in (L.ocm_min_batched, L.ocm_max_batched):
             f.argtypes = [i64, P, P, G, O, P, C.c_size_t, P, P, P, P, i64, P, P, P, P]
             f.restype = C.c_int
+        L.ocm_batched_last_schedule.argtypes = [P, P, P]
         L.ocm_weights_from_f64.argtypes = [i64, P, P, P, C.c_size_t, P]
         L.ocm_weights_from_f64.restype = C.c_int
         L.ocm_adjoint_scatter.argtypes = [i64, P, i64, P, P, P]
@@ -209,10 +210,10 @@ CONNECT_MODES = {"auto": 0, "pull": 1, "push": 2}
 
 
 def options(max_iters=0, validate=True, schedule=0, tie_check=True, fast_path=True,
-            connect="auto", init_policy=None) -> Options:
+            connect="auto", init_policy=None, tile=0) -> Options:
     o = Options()
     lib().ocm_default_options(C.byref(o))
-    o.max_iters, o.validate, o.schedule = max_iters, int(validate), schedule
+    o.max_iters, o.validate, o.schedule, o.tile = max_iters, int(validate), schedule, tile
     o.tie_check, o.fast_path = int(tie_check), int(fast_path)
     o.connect_mode = CONNECT_MODES[connect]
     if init_policy is not None:
@@ -289,6 +290,13 @@ class BatchResult:
 
 
 _bws_cache: dict = {}
+
+
+def batched_last_schedule():
+    """(lanes, tile, tuned_now) of the last batched call on this thread."""
+    a, b, t = C.c_int32(), C.c_int32(), C.c_int32()
+    lib().ocm_batched_last_schedule(C.byref(a), C.byref(b), C.byref(t))
+    return a.value, b.value, bool(t.value)
 
 
 def cycle_mean_batched(row_ptr, col, w, vptr, eptr, mode: str = "min", **opt) -> BatchResult:

@@ -70,13 +70,36 @@ def test_batched_schedules_and_fast_path_agree():
     gs = mixed_batch(9, G=30, lo=100, hi=20000)
     u, vptr, eptr = synth.disjoint_union(gs)
     ref = None
-    for lanes in (2, 8, 32):
+    for lanes, tile in ((2, 512), (8, 1024), (32, 4096), (0, 0)):
         for fast in (True, False):
-            r = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr, schedule=lanes, fast_path=fast)
-            cur = (r.p, r.q, r.iterations, r.cycle_ptr, r.cycle_edges.cpu().tolist())
+            r = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr, schedule=lanes, tile=tile,
+                                       fast_path=fast)
+            cur = (r.p, r.q, r.iterations, r.cycle_ptr, r.cycle_edges.cpu().tolist(), r.flags)
             if ref is None:
                 ref = cur
             assert cur == ref
+            got = ocm.batched_last_schedule()
+            if lanes:
+                assert got[:2] == (lanes, tile)
+            else:
+                assert got[0] in (1, 2, 4, 8, 16, 32, 64) and got[1] >= 512
+
+
+def test_batched_graph_capture_matches_eager(monkeypatch):
+    """The two captured hipGraphs are replayed once per iteration; every
+    replay feeds the next, so equal final bytes check all replays."""
+    gs = mixed_batch(13, G=50, lo=20, hi=40000)
+    u, vptr, eptr = synth.disjoint_union(gs)
+    dev = to_dev(u)
+    outs = []
+    for flag in ("1", "0", "1"):
+        monkeypatch.setenv("OCM_BATCH_GRAPH", flag)
+        r = ocm.cycle_mean_batched(*dev, vptr, eptr)
+        torch.cuda.synchronize()
+        outs.append((r.p, r.q, r.iterations, r.cycle_ptr, r.cycle_edges.cpu().tolist(), r.flags,
+                     r.status))
+    assert outs[0] == outs[1] == outs[2]
+    assert max(outs[0][2]) >= 3
 
 
 def test_batched_graphs_fail_independently():
@@ -101,6 +124,15 @@ def test_batched_rejects_edges_between_graphs():
     with pytest.raises(ocm.OCMError) as ex:
         ocm.cycle_mean_batched(*to_dev(u), vptr, eptr)
     assert ex.value.status == ocm.OCM_E_BAD_CSR
+
+
+def test_batched_rejects_bad_tiles():
+    gs = mixed_batch(3, G=4, lo=10, hi=100)
+    u, vptr, eptr = synth.disjoint_union(gs)
+    for tile in (256, 8192, -5):
+        with pytest.raises(ocm.OCMError) as ex:
+            ocm.cycle_mean_batched(*to_dev(u), vptr, eptr, tile=tile)
+        assert ex.value.status == ocm.OCM_E_INVALID_ARG
 
 
 def test_batched_single_graph_and_tiny_graphs():
