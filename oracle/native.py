@@ -173,8 +173,9 @@ class Stepper:
             raise OracleError(rc.value, "state")
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orc_state_free(self.h)
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.orc_state_free(self.h)
             self.h = None
 
     def sweep(self) -> int:

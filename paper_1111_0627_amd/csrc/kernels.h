@@ -46,6 +46,7 @@ struct alignas(16) Ctl {
     unsigned xcnt;                 // tie scan: tight non-policy edges listed
     unsigned scnt;                 // tie check: special vertices
     unsigned bad;                  // conversion / policy check failure
+    unsigned pjc[4];               // cycles: per round parity, image size and M changes
 };
 
 // Pointer-jumping entry of the value phase: the first H edges of v's policy
@@ -78,10 +79,17 @@ void launch_validate(int n, int m, const int* row_ptr, const int* col, const voi
                      int check_csr, Ctl* ctl, hipStream_t st);
 void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool first, bool tie,
                   unsigned grid, hipStream_t st);
+// tag0 (optional): byte array marked with 1 at every successor; cnt: the
+// four stop-test counters, cleared
 void launch_pj_init(int n, const int* col, const int* pi, int* succ, unsigned long long* P,
-                    unsigned char* onc, hipStream_t st);
+                    unsigned char* onc, unsigned char* tag0, unsigned* cnt, hipStream_t st);
 void launch_pj_round(int n, const unsigned long long* Pin, unsigned long long* Pout,
                      hipStream_t st);
+// round r >= 1 with the stop-test counters: cnt[2*(r&1)] = size of
+// image(J_{r-1}), cnt[2*(r&1)+1] = M values changed; tprev / tcur alternate
+void launch_pj_round_tagged(int n, int r, const unsigned long long* Pin, unsigned long long* Pout,
+                            const unsigned char* tprev, unsigned char* tcur, unsigned* cnt,
+                            hipStream_t st);
 void launch_pj_final(int n, const unsigned long long* P, int* rep, unsigned char* onc,
                      hipStream_t st);
 void launch_cyc_zero(int n, const int* rep, const unsigned char* onc, long long* wsum,
@@ -149,5 +157,6 @@ void launch_adjoint_scatter(int64_t m, const int* cyc, int64_t len, const double
 void launch_w_from_f64(int64_t m, const double* w, long long* out, unsigned* bad, hipStream_t st);
 void launch_check_policy(int n, const int* row_ptr, const int* pi, unsigned* bad, hipStream_t st);
 void launch_fill_u8(unsigned char* p, int64_t n, unsigned char v, hipStream_t st);
+void launch_fill_u32(unsigned* p, int64_t len, unsigned v, hipStream_t st);
 
 }  // namespace ocm

@@ -145,11 +145,118 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a, const WT* __restrict
     }
 }
 
+#ifndef OCM_SWEEP_UNROLL
+#define OCM_SWEEP_UNROLL 2
+#endif
+
+// Improvement sweep with U vertices per lane group and step: the offsets,
+// each lane's first out-edge and its gathered value are loaded for all U
+// vertices before any of them is reduced, so every wave keeps U independent
+// load chains in flight.  Same result as k_sweep: within a lane edges are
+// visited in CSR order with a strict "<", and the cross-lane reduction
+// breaks ties by the lower position.
+template <int G, typename WT, bool FIRST, int U>
+__global__ __launch_bounds__(kWG) void k_sweep_u(SweepArgs a, const WT* __restrict__ w)
+{
+    constexpr int VPB = kWG / G;             // vertices per block per step and unroll slot
+    const int64_t L = FIRST ? 1 : a.L;
+    const int64_t W = FIRST ? 0 : a.W;
+    const int lane = threadIdx.x & (G - 1);
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t per = ((int64_t)a.n + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)b * per;
+    const int64_t v1 = v0 + per < a.n ? v0 + per : a.n;
+    unsigned long long cnt = 0;
+    unsigned cbroken = 0;
+    for (int64_t vb = v0; vb < v1; vb += U * VPB) {
+        int64_t v[U], own[U], best[U];
+        int beg[U], end[U], bpos[U], c0[U];
+        int64_t w0[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[u] = vb + u * VPB + threadIdx.x / G;
+            beg[u] = end[u] = 0;
+            own[u] = 0;
+            if (v[u] < v1) {
+                beg[u] = a.row_ptr[v[u]];
+                end[u] = a.row_ptr[v[u] + 1];
+                if (!FIRST) own[u] = a.V[v[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = beg[u] + lane;
+            c0[u] = 0;
+            w0[u] = 0;
+            if (e < end[u]) {
+                w0[u] = wval(w, e, a.neg);
+                if (!FIRST) c0[u] = a.col[e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = beg[u] + lane;
+            best[u] = INT64_MAX;
+            bpos[u] = INT32_MAX;
+            if (e < end[u]) {
+                best[u] = FIRST ? w0[u] : a.V[c0[u]] + L * w0[u] - W;
+                bpos[u] = e;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            for (int e = beg[u] + lane + G; e < end[u]; e += G) {
+                const int64_t we = wval(w, e, a.neg);
+                const int64_t key = FIRST ? we : a.V[a.col[e]] + L * we - W;
+                if (key < best[u]) {
+                    best[u] = key;
+                    bpos[u] = e;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+                const int64_t ob = __shfl_xor(best[u], off, G);
+                const int op = __shfl_xor(bpos[u], off, G);
+                if (ob < best[u] || (ob == best[u] && op < bpos[u])) {
+                    best[u] = ob;
+                    bpos[u] = op;
+                }
+            }
+            if (v[u] < v1 && lane == 0 && (FIRST || best[u] < own[u])) {
+                a.pi[v[u]] = bpos[u];
+                cnt++;
+                if (!FIRST && a.onC && a.onC[v[u]]) cbroken = 1;
+            }
+        }
+    }
+    cnt = block_sum_u64(cnt);
+    const unsigned long long brk = block_sum_u64(cbroken);
+    if (threadIdx.x == 0) {
+        if (cnt) atomicAdd(&a.ctl->changed, cnt);
+        if (brk) atomicOr(&a.ctl->cbroken, 1u);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // cycles: pointer jumping over the policy graph.  Entry P[v] packs
 // (J = succ^(2^k)(v), M = min vertex among the first 2^k vertices of v's
 // policy path).  After K rounds with 2^K >= n, J is on v's cycle and M at a
 // cycle vertex is the whole cycle's minimum.
+//
+// The host may stop earlier, after round r, when both of these hold:
+//  * image(J_{r-1}) and image(J_{r-2}) have the same size.  J_{r-1} is
+//    J_{r-2} applied twice, so J_{r-2} then maps its image S onto S, i.e.
+//    permutes S; a permuted vertex returns to itself under succ, so S holds
+//    cycle vertices only and every J_{r-2}(v), hence J_r(v), is on a cycle;
+//  * no M changed in round r.  The update M' = min(M, M o J) at such a fixed
+//    point stays fixed in every later round (J only advances to vertices
+//    whose M is no smaller), so M_r is the minimum over v's whole path, which
+//    at a cycle vertex is the cycle's minimum.
+// Round r marks image(J_r) with tag r+1 in one of two byte arrays
+// (alternating) and counts the vertices tagged r by the round before.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long pj_pack(int j, int mn)
 {
@@ -159,26 +266,56 @@ __device__ __forceinline__ unsigned long long pj_pack(int j, int mn)
 __global__ __launch_bounds__(kWG) void k_pj_init(int n, const int* __restrict__ col,
                                                  const int* __restrict__ pi, int* __restrict__ succ,
                                                  unsigned long long* __restrict__ P,
-                                                 unsigned char* __restrict__ onc)
+                                                 unsigned char* __restrict__ onc,
+                                                 unsigned char* __restrict__ tag0, unsigned* cnt)
 {
     const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v == 0 && cnt) cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
     if (v >= n) return;
     const int s = col[pi[v]];
     succ[v] = s;
     P[v] = pj_pack(s, v);
     onc[v] = 0;
+    if (tag0) tag0[s] = 1;
 }
 
+// cnt = {image count, M changes} of this round; nxt = the next round's pair
 __global__ __launch_bounds__(kWG) void k_pj_round(int n, const unsigned long long* __restrict__ Pin,
-                                                  unsigned long long* __restrict__ Pout)
+                                                  unsigned long long* __restrict__ Pout,
+                                                  const unsigned char* __restrict__ tprev,
+                                                  unsigned char* __restrict__ tcur,
+                                                  unsigned char tag_prev, unsigned char tag_cur,
+                                                  unsigned* cnt, unsigned* nxt)
 {
-    const int v = blockIdx.x * kWG + threadIdx.x;
-    if (v >= n) return;
-    const unsigned long long p = Pin[v];
-    const int j = (int)(p >> 32);
-    const unsigned long long q = Pin[j];
-    const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
-    Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
+    if (tprev == nullptr) {
+        const int v = blockIdx.x * kWG + threadIdx.x;
+        if (v >= n) return;
+        const unsigned long long p = Pin[v];
+        const int j = (int)(p >> 32);
+        const unsigned long long q = Pin[j];
+        const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
+        Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) nxt[0] = nxt[1] = 0;
+    unsigned long long img = 0, chg = 0;
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < n; v += stride) {
+        const unsigned long long p = Pin[v];
+        const int j = (int)(p >> 32);
+        const unsigned long long q = Pin[j];
+        const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
+        Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
+        chg += m1 < m0;
+        tcur[(int)(q >> 32)] = tag_cur;
+        img += tprev[v] == tag_prev;
+    }
+    img = block_sum_u64(img);
+    chg = block_sum_u64(chg);
+    if (threadIdx.x == 0) {
+        if (img) atomicAdd(&cnt[0], (unsigned)img);
+        if (chg) atomicAdd(&cnt[1], (unsigned)chg);
+    }
 }
 
 __global__ __launch_bounds__(kWG) void k_pj_final(int n, const unsigned long long* __restrict__ P,
@@ -985,8 +1122,9 @@ static void launch_sweep_t(const SweepArgs& a, const void* w, int G, bool first,
 #define OCM_SWEEP_CASE(GG)                                                                        \
     case GG:                                                                                      \
         if (tie) k_sweep<GG, WT, false, true><<<grid, kWG, 0, st>>>(a, ww);                       \
-        else if (first) k_sweep<GG, WT, true, false><<<grid, kWG, 0, st>>>(a, ww);                \
-        else k_sweep<GG, WT, false, false><<<grid, kWG, 0, st>>>(a, ww);                          \
+        else if (first)                                                                           \
+            k_sweep_u<GG, WT, true, OCM_SWEEP_UNROLL><<<grid, kWG, 0, st>>>(a, ww);               \
+        else k_sweep_u<GG, WT, false, OCM_SWEEP_UNROLL><<<grid, kWG, 0, st>>>(a, ww);             \
         break;
     switch (G) {
         OCM_SWEEP_CASE(1)
@@ -1021,14 +1159,25 @@ void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool firs
 }
 
 void launch_pj_init(int n, const int* col, const int* pi, int* succ, unsigned long long* P,
-                    unsigned char* onc, hipStream_t st)
+                    unsigned char* onc, unsigned char* tag0, unsigned* cnt, hipStream_t st)
 {
-    k_pj_init<<<blocks_for(n), kWG, 0, st>>>(n, col, pi, succ, P, onc);
+    k_pj_init<<<blocks_for(n), kWG, 0, st>>>(n, col, pi, succ, P, onc, tag0, cnt);
 }
 
-void launch_pj_round(int n, const unsigned long long* Pin, unsigned long long* Pout, hipStream_t st)
+void launch_pj_round(int n, const unsigned long long* Pin, unsigned long long* Pout,
+                     hipStream_t st)
 {
-    k_pj_round<<<blocks_for(n), kWG, 0, st>>>(n, Pin, Pout);
+    k_pj_round<<<blocks_for(n), kWG, 0, st>>>(n, Pin, Pout, nullptr, nullptr, 0, 0, nullptr,
+                                              nullptr);
+}
+
+void launch_pj_round_tagged(int n, int r, const unsigned long long* Pin, unsigned long long* Pout,
+                            const unsigned char* tprev, unsigned char* tcur, unsigned* cnt,
+                            hipStream_t st)
+{
+    k_pj_round<<<stride_grid(n), kWG, 0, st>>>(n, Pin, Pout, tprev, tcur, (unsigned char)r,
+                                               (unsigned char)(r + 1), cnt + 2 * (r & 1),
+                                               cnt + 2 * ((r + 1) & 1));
 }
 
 void launch_pj_final(int n, const unsigned long long* P, int* rep, unsigned char* onc,
@@ -1247,6 +1396,11 @@ void launch_ctl_set(Ctl* ctl, int s, long long W, long long L, hipStream_t st)
 void launch_fill_u8(unsigned char* p, int64_t n, unsigned char v, hipStream_t st)
 {
     if (n > 0) k_fill_u8<<<blocks_for(n), kWG, 0, st>>>(p, n, v);
+}
+
+void launch_fill_u32(unsigned* p, int64_t len, unsigned v, hipStream_t st)
+{
+    if (len > 0) k_fill_u32<<<stride_grid(len), kWG, 0, st>>>(len, p, v);
 }
 
 // ---------------------------------------------------------------------------

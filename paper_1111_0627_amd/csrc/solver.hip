@@ -325,7 +325,9 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     return OCM_OK;
 }
 
-// Cycles of the policy graph: rep and on_cycle for every vertex.
+// Cycles of the policy graph: rep and on_cycle for every vertex.  At most
+// K = ceil(log2 n) jump rounds; the stop test of k_pj_round ends the phase as
+// soon as every jump pointer is on its cycle and the window minima are fixed.
 ocm_status phase_cycles(Ctx& c, const int* pi, int* rep, unsigned char* onc)
 {
     auto* P0 = (unsigned long long*)c.ws.Q[0];
@@ -333,22 +335,45 @@ ocm_status phase_cycles(Ctx& c, const int* pi, int* rep, unsigned char* onc)
     int K = 0;
     while ((int64_t(1) << K) < c.n) ++K;
     const double n = c.n;
+    // the two tag arrays live in the layer array, which the rebuild rewrites
+    unsigned char* tag[2] = {(unsigned char*)c.ws.layer, (unsigned char*)c.ws.layer + c.n};
+    const bool stop_test = K > 2;
     c.prof.begin(OCM_K_CYCLES);
-    ocm::launch_pj_init(c.n, c.col, pi, c.ws.succ, P0, onc, c.st);
+    if (stop_test) ocm::launch_fill_u32((unsigned*)c.ws.layer, ((int64_t)c.n * 2 + 3) / 4, 0u, c.st);
+    ocm::launch_pj_init(c.n, c.col, pi, c.ws.succ, P0, onc, stop_test ? tag[0] : nullptr,
+                        stop_test ? c.ws.ctl->pjc : nullptr, c.st);
     c.prof.end();
-    c.prof.bytes(OCM_K_CYCLES, 21.0 * n);   // pi, col[pi], succ, packed entry, on-cycle
-    for (int k = 0; k < K; ++k) {
+    // pi, col[pi], succ, packed entry, on-cycle (+ tag clear and mark)
+    c.prof.bytes(OCM_K_CYCLES, 21.0 * n + (stop_test ? 3.0 * n : 0.0));
+    HIP_TRY(hipGetLastError());
+    long long img_prev = -1;
+    int r = 0;
+    while (r < K) {
+        ++r;
         c.prof.begin(OCM_K_CYCLES);
-        ocm::launch_pj_round(c.n, P0, P1, c.st);
+        if (stop_test)
+            ocm::launch_pj_round_tagged(c.n, r, P0, P1, tag[(r - 1) & 1], tag[r & 1],
+                                        c.ws.ctl->pjc, c.st);
+        else
+            ocm::launch_pj_round(c.n, P0, P1, c.st);
         c.prof.end();
-        c.prof.bytes(OCM_K_CYCLES, 24.0 * n);   // own entry, gathered entry, new entry
+        // own entry, gathered entry, new entry (+ tag read and mark)
+        c.prof.bytes(OCM_K_CYCLES, (stop_test ? 26.0 : 24.0) * n);
         std::swap(P0, P1);
+        if (stop_test && r < K) {
+            HIP_TRY(hipGetLastError());
+            OCM_TRY(read_ctl(c));
+            const long long img = c.h.pjc[2 * (r & 1)];
+            const unsigned chg = c.h.pjc[2 * (r & 1) + 1];
+            if (r >= 2 && img == img_prev && chg == 0) break;
+            img_prev = img;
+        }
     }
     c.prof.begin(OCM_K_CYCLES);
     ocm::launch_pj_final(c.n, P0, rep, onc, c.st);
     c.prof.end();
     c.prof.bytes(OCM_K_CYCLES, 21.0 * n);
-    c.jump_rounds += K;
+    c.jump_rounds += r;
     HIP_TRY(hipGetLastError());
     return OCM_OK;
 }

@@ -148,6 +148,77 @@ def test_trace_driven_phases(n, dlo, dhi, wlo, whi, seed, mode):
         pytest.fail("no convergence")
 
 
+def _functional_cycles(succ):
+    """rep (minimum vertex of the reached cycle) and on-cycle flags of a
+    functional graph, by walking every path until it repeats."""
+    n = len(succ)
+    rep = np.full(n, -1, np.int64)
+    onc = np.zeros(n, np.uint8)
+    state = np.zeros(n, np.int8)            # 0 new, 1 on the current walk, 2 done
+    for s0 in range(n):
+        if state[s0]:
+            continue
+        path = []
+        v = s0
+        while state[v] == 0:
+            state[v] = 1
+            path.append(v)
+            v = succ[v]
+        if state[v] == 1:                   # closed a new cycle at v
+            cyc = path[path.index(v):]
+            r = min(cyc)
+            for x in cyc:
+                onc[x] = 1
+                rep[x] = r
+        for x in reversed(path):
+            if rep[x] < 0:
+                rep[x] = rep[succ[x]]
+            state[x] = 2
+    return rep, onc
+
+
+def _functional_graph_cases():
+    rng = np.random.default_rng(77)
+    n = 20000
+    # ascending tail into a 3-cycle: window minima never change, so only the
+    # image test can tell when the jump pointers reach the cycle
+    a = np.arange(1, n + 1)
+    a[n - 1] = n - 3
+    yield "ascending-tail", a
+    # descending tail: the minimum moves every round
+    b = np.arange(-1, n - 1)
+    b[0] = 2
+    yield "descending-tail", b
+    # one long cycle in random order with random trees hanging off it
+    perm = rng.permutation(n)
+    c = np.empty(n, np.int64)
+    k = 5000
+    c[perm[:k]] = np.roll(perm[:k], -1)
+    c[perm[k:]] = perm[rng.integers(0, np.arange(k, n))]
+    yield "long-cycle-trees", c
+    # random functional graph (many cycles, varied tails)
+    yield "random", rng.integers(0, n, size=n)
+    for m in (1, 2, 3, 4, 5, 9):
+        yield f"tiny{m}", rng.integers(0, m, size=m)
+
+
+@pytest.mark.parametrize("name,succ", list(_functional_graph_cases()))
+def test_cycle_phase_on_functional_graphs(name, succ):
+    """Cycle phase (with its early stop) on policy graphs built to defeat a
+    stop test that looks at the window minima alone."""
+    succ = np.asarray(succ, np.int64)
+    n = len(succ)
+    rp = np.arange(n + 1, dtype=np.int32)
+    cl = succ.astype(np.int32)
+    w = np.ones(n, np.int32)
+    rep_ref, onc_ref = _functional_cycles(succ)
+    d = to_dev(rp, cl, w)
+    pi = torch.arange(n, dtype=torch.int32, device="cuda")
+    rep, onc, _ = ocm.phase_cycles(*d, pi)
+    assert np.array_equal(rep.cpu().numpy(), rep_ref), name
+    assert np.array_equal(onc.cpu().numpy(), onc_ref), name
+
+
 def test_phase_entry_points_ignore_stale_workspace_contents():
     """Every entry point starts from a clean control block, whatever the
     workspace held before (regression: a stale overflow flag)."""
