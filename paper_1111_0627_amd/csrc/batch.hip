@@ -817,8 +817,8 @@ struct BWs {
     unsigned* stot;
     int* rin_ptr;
     int* rin;
-    unsigned* abits;
-    unsigned char* touched;
+    unsigned* abits[2];
+    unsigned* marks;
     unsigned* bad;
     size_t total;
 };
@@ -884,8 +884,9 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m)
     w.stot = (unsigned*)take(4 * ((N + 1) / 2048 + 2));
     w.rin_ptr = (int*)take(4 * (N + 1));
     w.rin = (int*)take(4 * M);
-    w.abits = (unsigned*)take(4 * ((N + 31) / 32 + 1));
-    w.touched = (unsigned char*)take(N + 16);
+    w.abits[0] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
+    w.abits[1] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
+    w.marks = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.bad = (unsigned*)take(256);
     w.total = off;
     return w;
@@ -1128,26 +1129,28 @@ ocm_status host_connect(BCtx& c)
     GArrays& a = ws.ga;
     unsigned left = c.h.ucnt[0], ulen = left, front = c.h.fcnt[0];
     int ua = 0, fa = 0, k = 0;
-    if (left > 0) ocm::launch_bits_from_layer(c.n, ws.layer, ws.abits, c.st);
+    if (left > 0) ocm::launch_bits_from_layer(c.n, ws.layer, ws.abits[0], ws.abits[1], c.st);
     while (left > 0) {
         ++k;
         const int ub = ua ^ 1, fb = fa ^ 1;
         const bool push = left >= (1u << 16) && (uint64_t)front * 4 < left;
         if (push && !c.rev_built) {
             ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, ws.rdeg, ws.stot, ws.rin_ptr, ws.rin,
-                                  ws.touched, c.st);
+                                  ws.marks, c.st);
             c.rev_built = true;
         }
+        const unsigned* acur = ws.abits[k & 1];
+        unsigned* anext = ws.abits[(k + 1) & 1];
         ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[ub], &ws.bc->fcnt[fb]);
-        if (k > 1) ocm::launch_bits_set(ws.flist[fa], front, ws.abits, c.st);
         if (push) {
-            ocm::launch_conn_mark(ws.rin_ptr, ws.rin, ws.abits, ws.touched, ws.flist[fa], front,
-                                  &ws.bc->pedges, c.st);
-            ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, ws.abits, ws.touched, ws.pi, ws.layer,
+            ocm::launch_conn_mark(ws.rin_ptr, ws.rin, acur, anext, ws.marks, ws.flist[fa], front,
+                                  k > 1, &ws.bc->pedges, c.st);
+            ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, ws.marks, ws.pi, ws.layer,
                                    ws.flist[fb], &ws.bc->fcnt[fb], &ws.bc->ledges, c.st);
         } else {
-            ocm::launch_conn_pull(k, c.row_ptr, c.col, ws.abits, ws.layer, ws.pi, ws.list[ua], ulen,
-                                  ws.list[ub], &ws.bc->ucnt[ub], ws.flist[fb], &ws.bc->fcnt[fb],
+            ocm::launch_conn_pull(k, c.row_ptr, c.col, acur, anext, ws.layer, ws.pi, ws.list[ua],
+                                  ulen, ws.list[ub], &ws.bc->ucnt[ub], ws.flist[fb],
+                                  &ws.bc->fcnt[fb], ws.flist[fa], k > 1 ? front : 0u,
                                   &ws.bc->ledges, c.st);
         }
         BHIP(hipGetLastError());
@@ -1164,11 +1167,12 @@ ocm_status host_connect(BCtx& c)
             // the remaining vertices cannot reach their graph's cycle
             if (push) {
                 // refresh the unattached list with a pull pass, which attaches
-                // nobody: the attached set is the one the push round saw
+                // nobody: it reads the attached set the push round saw
                 ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[ub], &ws.bc->fcnt[fb]);
-                ocm::launch_conn_pull(k, c.row_ptr, c.col, ws.abits, ws.layer, ws.pi, ws.list[ua],
-                                      ulen, ws.list[ub], &ws.bc->ucnt[ub], ws.flist[fb],
-                                      &ws.bc->fcnt[fb], &ws.bc->ledges, c.st);
+                ocm::launch_conn_pull(k, c.row_ptr, c.col, acur, anext, ws.layer, ws.pi,
+                                      ws.list[ua], ulen, ws.list[ub], &ws.bc->ucnt[ub],
+                                      ws.flist[fb], &ws.bc->fcnt[fb], ws.flist[fa], 0u,
+                                      &ws.bc->ledges, c.st);
                 BTRY(bread(c));
                 ulen = c.h.ucnt[ub];
                 ua = ub;

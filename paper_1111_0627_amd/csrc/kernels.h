@@ -103,21 +103,21 @@ void launch_select(const int* cyc_list, const long long* wsum, const unsigned* l
 void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, int* layer,
                       unsigned char* onC, int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt,
                       hipStream_t st);
-// bitmap of the vertices attached before the current rebuild round
-void launch_bits_from_layer(int n, const int* layer, unsigned* abits, hipStream_t st);
-void launch_bits_set(const int* list, unsigned cnt, unsigned* abits, hipStream_t st);
-void launch_conn_pull(int k, const int* row_ptr, const int* col, const unsigned* abits, int* layer,
-                      int* pi, const int* in_list, unsigned in_cnt, int* ulist, unsigned* ucnt,
-                      int* flist, unsigned* fcnt, unsigned long long* ledges, hipStream_t st);
-void launch_conn_mark(const int* rin_ptr, const int* rin, const unsigned* abits,
-                      unsigned char* touched, const int* fin, unsigned f_cnt,
+// rebuild rounds: a0/a1 = the two attached-vertex bitmaps, marks = the push
+// rounds' mark bitmap (all bitmaps hold ceil(n/32) words)
+void launch_bits_from_layer(int n, const int* layer, unsigned* a0, unsigned* a1, hipStream_t st);
+void launch_conn_pull(int k, const int* row_ptr, const int* col, const unsigned* acur,
+                      unsigned* anext, int* layer, int* pi, const int* in_list, unsigned in_cnt,
+                      int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt, const int* fin,
+                      unsigned f_cnt, unsigned long long* ledges, hipStream_t st);
+void launch_conn_mark(const int* rin_ptr, const int* rin, const unsigned* acur, unsigned* anext,
+                      unsigned* marks, const int* fin, unsigned f_cnt, int add_front,
                       unsigned long long* pedges, hipStream_t st);
-void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* abits,
-                       unsigned char* touched, int* pi, int* layer, int* fout, unsigned* fout_cnt,
-                       unsigned long long* cedges, hipStream_t st);
+void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
+                       unsigned* anext, unsigned* marks, int* pi, int* layer, int* fout,
+                       unsigned* fout_cnt, unsigned long long* cedges, hipStream_t st);
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
-                      unsigned* tot, int* rin_ptr, int* rin, unsigned char* touched,
-                      hipStream_t st);
+                      unsigned* tot, int* rin_ptr, int* rin, unsigned* marks, hipStream_t st);
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
                      int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl, hipStream_t st);
 void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st);

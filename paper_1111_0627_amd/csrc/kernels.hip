@@ -279,6 +279,8 @@ __global__ __launch_bounds__(kWG) void k_pj_init(int n, const int* __restrict__ 
     if (tag0) tag0[s] = 1;
 }
 
+constexpr int kJumpUnroll = 4;   // entries in flight per thread in grid-stride jump rounds
+
 // cnt = {image count, M changes} of this round; nxt = the next round's pair
 __global__ __launch_bounds__(kWG) void k_pj_round(int n, const unsigned long long* __restrict__ Pin,
                                                   unsigned long long* __restrict__ Pout,
@@ -299,16 +301,32 @@ __global__ __launch_bounds__(kWG) void k_pj_round(int n, const unsigned long lon
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) nxt[0] = nxt[1] = 0;
     unsigned long long img = 0, chg = 0;
+    // grid-stride with kJumpUnroll independent entries in flight per thread
     const int64_t stride = (int64_t)gridDim.x * kWG;
-    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < n; v += stride) {
-        const unsigned long long p = Pin[v];
-        const int j = (int)(p >> 32);
-        const unsigned long long q = Pin[j];
-        const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
-        Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
-        chg += m1 < m0;
-        tcur[(int)(q >> 32)] = tag_cur;
-        img += tprev[v] == tag_prev;
+    for (int64_t v0 = (int64_t)blockIdx.x * kWG + threadIdx.x; v0 < n;
+         v0 += kJumpUnroll * stride) {
+        unsigned long long p[kJumpUnroll], q[kJumpUnroll];
+#pragma unroll
+        for (int u = 0; u < kJumpUnroll; ++u) {
+            const int64_t v = v0 + u * stride;
+            p[u] = v < n ? Pin[v] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kJumpUnroll; ++u) {
+            const int64_t v = v0 + u * stride;
+            q[u] = v < n ? Pin[(int)(p[u] >> 32)] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kJumpUnroll; ++u) {
+            const int64_t v = v0 + u * stride;
+            if (v < n) {
+                const unsigned m0 = (unsigned)p[u], m1 = (unsigned)q[u];
+                Pout[v] = (q[u] & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
+                chg += m1 < m0;
+                tcur[(int)(q[u] >> 32)] = tag_cur;
+                img += tprev[v] == tag_prev;
+            }
+        }
     }
     img = block_sum_u64(img);
     chg = block_sum_u64(chg);
@@ -453,14 +471,16 @@ __global__ __launch_bounds__(kWG) void k_select_final(const Cand* __restrict__ p
 // can only have out-edges into layer k-1 (an edge into an earlier layer would
 // have attached it earlier), so "the lowest-position out-edge into the set
 // attached before round k" is u's first out-edge, in CSR order, whose head
-// is attached.  A bitmap `abits` (one bit per vertex, small enough to stay in
-// L2) holds exactly the vertices attached before the current round: it is
-// built from the layers after k_conn_init and each round first adds the
-// previous round's frontier (k_bits_set).  Both directions then find u's
-// edge with the same scan:
+// is attached.  Two bitmaps (one bit per vertex, 2 MB at 16.7M vertices, so
+// they stay in L2) alternate: at the start of round k, A[k&1] holds the
+// layers <= k-1 and A[(k+1)&1] the layers <= k-2.  Round k only reads
+// A[k&1]; it adds the previous frontier (layer k-1) and its own attachments
+// (layer k) to A[(k+1)&1], which restores the invariant for round k+1.
+// Both directions then find u's edge with the same scan:
 //   pull: every listed unattached u scans its own out-edges (k_conn_pull);
-//   push: the frontier's in-edges mark their tails (k_conn_mark) and only the
-//         marked vertices scan (k_conn_claim).
+//   push: the frontier's in-edges mark their unattached tails in a third
+//         bitmap (k_conn_mark) and only the marked vertices scan
+//         (k_conn_claim).
 // The host picks the cheaper direction per round.
 __global__ __launch_bounds__(kWG) void k_conn_init(int n, const int* __restrict__ rep,
                                                    const unsigned char* __restrict__ onc,
@@ -496,9 +516,15 @@ __device__ __forceinline__ bool attached(const unsigned* __restrict__ abits, int
     return (abits[v >> 5] >> (v & 31)) & 1u;
 }
 
-// abits[i] = bit j set iff layer[32 i + j] >= 0 (every word written).
+__device__ __forceinline__ void set_bit(unsigned* abits, int v)
+{
+    atomicOr(&abits[v >> 5], 1u << (v & 31));
+}
+
+// a0[i] = a1[i] = bits j with layer[32 i + j] >= 0 (every word written).
 __global__ __launch_bounds__(kWG) void k_bits_from_layer(int n, const int* __restrict__ layer,
-                                                         unsigned* __restrict__ abits)
+                                                         unsigned* __restrict__ a0,
+                                                         unsigned* __restrict__ a1)
 {
     const int64_t words = ((int64_t)n + 31) / 32;
     const int64_t span = (int64_t)gridDim.x * kWG;
@@ -509,18 +535,21 @@ __global__ __launch_bounds__(kWG) void k_bits_from_layer(int n, const int* __res
         const unsigned long long b = __ballot(v < n && layer[v] >= 0);
         const int lane = threadIdx.x & 63;
         const int64_t wd = (vb >> 5) + (lane >> 5);
-        if ((lane & 31) == 0 && wd < words) abits[wd] = (unsigned)(b >> (lane & 32));
+        if ((lane & 31) == 0 && wd < words) {
+            const unsigned x = (unsigned)(b >> (lane & 32));
+            a0[wd] = x;
+            a1[wd] = x;
+        }
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_bits_set(const int* __restrict__ list, unsigned cnt,
-                                                  unsigned* __restrict__ abits)
+// adds the listed vertices to a bitmap (grid-stride over the list)
+__device__ __forceinline__ void add_list_bits(const int* __restrict__ list, unsigned cnt,
+                                              unsigned* abits)
 {
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < cnt;
-         i += (int64_t)gridDim.x * kWG) {
-        const int v = list[i];
-        atomicOr(&abits[v >> 5], 1u << (v & 31));
-    }
+         i += (int64_t)gridDim.x * kWG)
+        set_bit(abits, list[i]);
 }
 
 // First out-edge of u, in CSR order, whose head is attached; -1 if none.
@@ -536,19 +565,24 @@ __device__ __forceinline__ int first_attached_edge(const int* __restrict__ row_p
     return -1;
 }
 
+// Pull round k over the unattached list; also adds the previous frontier
+// (fin, f_cnt; 0 in round 1) and this round's attachments to anext.
 __global__ __launch_bounds__(kWG) void k_conn_pull(int k, const int* __restrict__ row_ptr,
                                                    const int* __restrict__ col,
-                                                   const unsigned* __restrict__ abits,
-                                                   int* __restrict__ layer, int* __restrict__ pi,
+                                                   const unsigned* __restrict__ acur,
+                                                   unsigned* anext, int* __restrict__ layer,
+                                                   int* __restrict__ pi,
                                                    const int* __restrict__ in_list, unsigned in_cnt,
                                                    unsigned per, int* __restrict__ ulist,
                                                    unsigned* ucnt, int* __restrict__ flist,
-                                                   unsigned* fcnt, unsigned long long* ledges)
+                                                   unsigned* fcnt, const int* __restrict__ fin,
+                                                   unsigned f_cnt, unsigned long long* ledges)
 {
     __shared__ int ubuf[kListItems], fbuf[kListItems];
     __shared__ unsigned nu, nf;
     if (threadIdx.x == 0) nu = nf = 0;
     __syncthreads();
+    add_list_bits(fin, f_cnt, anext);
     BlockList bu{ubuf, &nu}, bf{fbuf, &nf};
     const int64_t i0 = (int64_t)blockIdx.x * per;
     const int64_t i1 = i0 + per < in_cnt ? i0 + per : in_cnt;
@@ -560,11 +594,12 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, const int* __restrict_
         // entries attached by a push round since the list was made are dropped
         if (i < i1) {
             u = in_list[i];
-            if (!attached(abits, u)) {
-                const int hit = first_attached_edge(row_ptr, col, abits, u, scanned);
+            if (!attached(acur, u)) {
+                const int hit = first_attached_edge(row_ptr, col, acur, u, scanned);
                 if (hit >= 0) {
                     pi[u] = hit;
                     layer[u] = k;
+                    set_bit(anext, u);
                     got = true;
                 } else {
                     left = true;
@@ -581,80 +616,94 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, const int* __restrict_
 }
 
 // Push round k, mark: G lanes per frontier vertex x walk its in-edges
-// (coalesced 4-byte tails) and set touched[u] = 1 for every tail u not yet
-// attached (plain byte store, idempotent).
+// (coalesced 4-byte tails) and set the bit of every tail u not yet attached
+// in `marks`; x itself joins anext (unless add_front is 0, in round 1).
 template <int G>
 __global__ __launch_bounds__(kWG) void k_conn_mark(const int* __restrict__ rin_ptr,
                                                    const int* __restrict__ rin,
-                                                   const unsigned* __restrict__ abits,
-                                                   unsigned char* __restrict__ touched,
+                                                   const unsigned* __restrict__ acur,
+                                                   unsigned* anext, unsigned* marks,
                                                    const int* __restrict__ fin, unsigned f_cnt,
-                                                   unsigned long long* pedges)
+                                                   int add_front, unsigned long long* pedges)
 {
     const int gl = threadIdx.x & (G - 1);
     const int64_t ngroups = (int64_t)gridDim.x * (kWG / G);
     unsigned long long scanned = 0;
     for (int64_t i = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G; i < f_cnt; i += ngroups) {
         const int x = fin[i];
+        if (add_front && gl == 0) set_bit(anext, x);
         for (int j = rin_ptr[x] + gl, end = rin_ptr[x + 1]; j < end; j += G) {
             const int u = rin[j];
             ++scanned;
-            if (!attached(abits, u)) touched[u] = 1;
+            if (!attached(acur, u)) set_bit(marks, u);
         }
     }
     scanned = block_sum_u64(scanned);
     if (threadIdx.x == 0 && scanned) atomicAdd(pedges, scanned);
 }
 
-constexpr int kClaimVerts = 4096;   // vertices per block, 16 per thread
+constexpr int kClaimWords = 64;                  // mark words per block
+constexpr int kClaimVerts = 32 * kClaimWords;    // 2048 vertices per block
+constexpr int kClaimLanes = 8;                   // lanes per marked vertex
 
-// Push round k, claim: one coalesced pass over the touched bytes (reset on
-// the way); every touched u scans its out-edges for the first attached head
-// (one exists: the edge that marked it), attaches with it (pi, layer = k)
-// and joins the next frontier.
+// Push round k, claim: each block takes kClaimWords words of the mark bitmap
+// (clearing them), lists the marked vertices in LDS, and scans each one's
+// out-edges with kClaimLanes lanes for the first attached head.  One exists:
+// the edge that marked it.  The vertex attaches with that edge (pi, layer =
+// k), joins anext and the next frontier.
 __global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __restrict__ row_ptr,
                                                     const int* __restrict__ col,
-                                                    const unsigned* __restrict__ abits,
-                                                    unsigned char* __restrict__ touched,
+                                                    const unsigned* __restrict__ acur,
+                                                    unsigned* anext, unsigned* marks,
                                                     int* __restrict__ pi, int* __restrict__ layer,
                                                     int* __restrict__ fout, unsigned* fout_cnt,
                                                     unsigned long long* cedges)
 {
-    __shared__ int buf[kClaimVerts];
-    __shared__ unsigned nb;
-    if (threadIdx.x == 0) nb = 0;
+    __shared__ int todo[kClaimVerts];
+    __shared__ int obuf[kClaimVerts];   // at most one output per listed vertex
+    __shared__ unsigned ntodo, nout;
+    if (threadIdx.x == 0) ntodo = nout = 0;
     __syncthreads();
-    BlockList bl{buf, &nb};
-    const int64_t v0 = (int64_t)blockIdx.x * kClaimVerts + (int64_t)threadIdx.x * 16;
-    uint4 t = make_uint4(0, 0, 0, 0);
-    if (v0 + 16 <= n) {
-        t = *(const uint4*)(touched + v0);
-    } else {
-        unsigned char tmp[16] = {0};
-        for (int q = 0; q < 16 && v0 + q < n; ++q) tmp[q] = touched[v0 + q];
-        t = make_uint4(tmp[0] | tmp[1] << 8 | tmp[2] << 16 | (unsigned)tmp[3] << 24,
-                       tmp[4] | tmp[5] << 8 | tmp[6] << 16 | (unsigned)tmp[7] << 24,
-                       tmp[8] | tmp[9] << 8 | tmp[10] << 16 | (unsigned)tmp[11] << 24,
-                       tmp[12] | tmp[13] << 8 | tmp[14] << 16 | (unsigned)tmp[15] << 24);
-    }
-    const unsigned words[4] = {t.x, t.y, t.z, t.w};
-    const bool any = (t.x | t.y | t.z | t.w) != 0;
-    if (any) {
-        if (v0 + 16 <= n) *(uint4*)(touched + v0) = make_uint4(0, 0, 0, 0);
-        else
-            for (int q = 0; q < 16 && v0 + q < n; ++q) touched[v0 + q] = 0;
-    }
-    unsigned long long scanned = 0;
-    for (int q = 0; q < 16; ++q) {
-        const int u = (int)(v0 + q);
-        bool got = false;
-        if (((words[q >> 2] >> (8 * (q & 3))) & 0xffu) != 0 && !attached(abits, u)) {
-            const int hit = first_attached_edge(row_ptr, col, abits, u, scanned);
-            if (hit >= 0) {
-                pi[u] = hit;
-                layer[u] = k;
-                got = true;
+    const int64_t words = ((int64_t)n + 31) / 32;
+    const int64_t wd = (int64_t)blockIdx.x * kClaimWords + threadIdx.x;
+    if (threadIdx.x < kClaimWords && wd < words) {
+        unsigned x = marks[wd];
+        if (x) {
+            marks[wd] = 0u;
+            const unsigned base = atomicAdd(&ntodo, (unsigned)__popc(x));
+            unsigned j = 0;
+            while (x) {
+                const int b = __ffs(x) - 1;
+                x &= x - 1;
+                todo[base + j++] = (int)(wd * 32 + b);
             }
+        }
+    }
+    __syncthreads();
+    const unsigned cnt = ntodo;
+    BlockList bl{obuf, &nout};
+    const int gl = threadIdx.x & (kClaimLanes - 1);
+    const int gshift = threadIdx.x & 63 & ~(kClaimLanes - 1);   // group's first lane in the wave
+    unsigned long long scanned = 0;
+    for (unsigned ib = 0; ib < cnt; ib += kWG / kClaimLanes) {
+        const unsigned i = ib + threadIdx.x / kClaimLanes;
+        int u = 0, hit = -1;
+        if (i < cnt) {
+            u = todo[i];
+            for (int b = row_ptr[u], end = row_ptr[u + 1]; b < end && hit < 0; b += kClaimLanes) {
+                const int e = b + gl;
+                const bool h = e < end && attached(acur, col[e]);
+                const unsigned gm =
+                    (unsigned)(__ballot(h) >> gshift) & ((1u << kClaimLanes) - 1u);
+                if (gm) hit = b + __ffs(gm) - 1;
+                scanned += e < end ? 1 : 0;
+            }
+        }
+        const bool got = gl == 0 && hit >= 0;
+        if (got) {
+            pi[u] = hit;
+            layer[u] = k;
+            set_bit(anext, u);
         }
         blist_push(bl, got, u);
     }
@@ -815,26 +864,47 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
     if (threadIdx.x == 0 && act) atomicAdd(&ctl->active, (unsigned)act);
 }
 
+__device__ __forceinline__ Jmp jmp_combine(Jmp q, const Jmp& r)
+{
+    long long d;
+    if (__builtin_add_overflow(q.D, r.D, &d)) {
+        d = 0;
+        q.H |= kHopOverflow;
+    }
+    q.D = d;
+    q.J = r.J;
+    q.H = ((q.H & ~kHopOverflow) + (r.H & ~kHopOverflow)) | ((q.H | r.H) & kHopOverflow);
+    return q;
+}
+
 __global__ __launch_bounds__(kWG) void k_val_round(int n, int s, const Jmp* __restrict__ Qin,
                                                    Jmp* __restrict__ Qout, unsigned* active)
 {
     unsigned long long act = 0;
-    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * kWG) {
-        Jmp q = Qin[v];
-        if (q.J != s) {
-            const Jmp r = Qin[q.J];
-            long long d;
-            if (__builtin_add_overflow(q.D, r.D, &d)) {
-                d = 0;
-                q.H |= kHopOverflow;
-            }
-            q.D = d;
-            q.J = r.J;
-            q.H = ((q.H & ~kHopOverflow) + (r.H & ~kHopOverflow)) | ((q.H | r.H) & kHopOverflow);
-            act += q.J != s;
+    // grid-stride with kJumpUnroll independent entries in flight per thread
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t v0 = (int64_t)blockIdx.x * kWG + threadIdx.x; v0 < n;
+         v0 += kJumpUnroll * stride) {
+        Jmp q[kJumpUnroll], r[kJumpUnroll];
+#pragma unroll
+        for (int u = 0; u < kJumpUnroll; ++u) {
+            const int64_t v = v0 + u * stride;
+            if (v < n) q[u] = Qin[v];
+            else q[u].J = s;
         }
-        Qout[v] = q;
+#pragma unroll
+        for (int u = 0; u < kJumpUnroll; ++u)
+            if (q[u].J != s) r[u] = Qin[q[u].J];
+#pragma unroll
+        for (int u = 0; u < kJumpUnroll; ++u) {
+            const int64_t v = v0 + u * stride;
+            if (v >= n) continue;
+            if (q[u].J != s) {
+                q[u] = jmp_combine(q[u], r[u]);
+                act += q[u].J != s;
+            }
+            Qout[v] = q[u];
+        }
     }
     act = block_sum_u64(act);
     if (threadIdx.x == 0 && act) atomicAdd(active, (unsigned)act);
@@ -1222,44 +1292,40 @@ void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, in
     k_conn_init<<<grid, kWG, 0, st>>>(n, rep, onc, s, per, layer, onC, ulist, ucnt, flist, fcnt);
 }
 
-void launch_conn_pull(int k, const int* row_ptr, const int* col, const unsigned* abits, int* layer,
-                      int* pi, const int* in_list, unsigned in_cnt, int* ulist, unsigned* ucnt,
-                      int* flist, unsigned* fcnt, unsigned long long* ledges, hipStream_t st)
+void launch_conn_pull(int k, const int* row_ptr, const int* col, const unsigned* acur,
+                      unsigned* anext, int* layer, int* pi, const int* in_list, unsigned in_cnt,
+                      int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt, const int* fin,
+                      unsigned f_cnt, unsigned long long* ledges, hipStream_t st)
 {
-    if (in_cnt == 0) return;
-    const unsigned per = list_per_block(in_cnt);
-    const unsigned grid = (unsigned)(((int64_t)in_cnt + per - 1) / per);
-    k_conn_pull<<<grid, kWG, 0, st>>>(k, row_ptr, col, abits, layer, pi, in_list, in_cnt, per,
-                                      ulist, ucnt, flist, fcnt, ledges);
+    if (in_cnt == 0 && f_cnt == 0) return;
+    const unsigned per = list_per_block(in_cnt > 0 ? in_cnt : 1);
+    unsigned grid = (unsigned)(((int64_t)in_cnt + per - 1) / per);
+    if (grid < 1) grid = 1;
+    k_conn_pull<<<grid, kWG, 0, st>>>(k, row_ptr, col, acur, anext, layer, pi, in_list, in_cnt,
+                                      per, ulist, ucnt, flist, fcnt, fin, f_cnt, ledges);
 }
 
-void launch_bits_from_layer(int n, const int* layer, unsigned* abits, hipStream_t st)
+void launch_bits_from_layer(int n, const int* layer, unsigned* a0, unsigned* a1, hipStream_t st)
 {
-    k_bits_from_layer<<<stride_grid(n), kWG, 0, st>>>(n, layer, abits);
+    k_bits_from_layer<<<stride_grid(n), kWG, 0, st>>>(n, layer, a0, a1);
 }
 
-void launch_bits_set(const int* list, unsigned cnt, unsigned* abits, hipStream_t st)
-{
-    if (cnt == 0) return;
-    k_bits_set<<<stride_grid(cnt), kWG, 0, st>>>(list, cnt, abits);
-}
-
-void launch_conn_mark(const int* rin_ptr, const int* rin, const unsigned* abits,
-                      unsigned char* touched, const int* fin, unsigned f_cnt,
+void launch_conn_mark(const int* rin_ptr, const int* rin, const unsigned* acur, unsigned* anext,
+                      unsigned* marks, const int* fin, unsigned f_cnt, int add_front,
                       unsigned long long* pedges, hipStream_t st)
 {
     if (f_cnt == 0) return;
     constexpr int G = 8;
-    k_conn_mark<G><<<stride_grid((int64_t)f_cnt * G), kWG, 0, st>>>(rin_ptr, rin, abits, touched,
-                                                                   fin, f_cnt, pedges);
+    k_conn_mark<G><<<stride_grid((int64_t)f_cnt * G), kWG, 0, st>>>(
+        rin_ptr, rin, acur, anext, marks, fin, f_cnt, add_front, pedges);
 }
 
-void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* abits,
-                       unsigned char* touched, int* pi, int* layer, int* fout, unsigned* fout_cnt,
-                       unsigned long long* cedges, hipStream_t st)
+void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
+                       unsigned* anext, unsigned* marks, int* pi, int* layer, int* fout,
+                       unsigned* fout_cnt, unsigned long long* cedges, hipStream_t st)
 {
     const unsigned grid = (unsigned)(((int64_t)n + kClaimVerts - 1) / kClaimVerts);
-    k_conn_claim<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, abits, touched, pi, layer, fout,
+    k_conn_claim<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer, fout,
                                        fout_cnt, cedges);
 }
 
@@ -1273,8 +1339,7 @@ void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsig
 }
 
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
-                      unsigned* tot, int* rin_ptr, int* rin, unsigned char* touched,
-                      hipStream_t st)
+                      unsigned* tot, int* rin_ptr, int* rin, unsigned* marks, hipStream_t st)
 {
     const int64_t len = (int64_t)n + 1;
     k_fill_u32<<<stride_grid(len), kWG, 0, st>>>(len, deg, 0u);
@@ -1285,8 +1350,8 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
     k_scan_c<<<stride_grid(len), kWG, 0, st>>>(len, (unsigned*)rin_ptr, tot);
     k_copy_u32<<<stride_grid(n), kWG, 0, st>>>(n, (const unsigned*)rin_ptr, deg);
     k_rev_fill<<<stride_grid(n), kWG, 0, st>>>(n, row_ptr, col, deg, rin);
-    const int64_t words = ((int64_t)n + 3) / 4;
-    k_fill_u32<<<stride_grid(words), kWG, 0, st>>>(words, (unsigned*)touched, 0u);
+    const int64_t words = ((int64_t)n + 31) / 32;
+    k_fill_u32<<<stride_grid(words), kWG, 0, st>>>(words, marks, 0u);
 }
 
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,

@@ -72,8 +72,9 @@ struct Ws {
     unsigned* stot;      // prefix-sum block totals
     int* rin_ptr;        // reverse CSR offsets (n+1)
     int* rin;            // reverse CSR entries: the tail of each in-edge (m)
-    unsigned* abits;     // connect: bitmap of the vertices attached before the round
-    unsigned char* touched;  // push rounds: marked this round
+    unsigned* abits[2];  // connect: attached-vertex bitmaps (alternating by round)
+    unsigned* marks;     // push rounds: marked vertices (bitmap)
+    unsigned char* touched;  // tie check: special-vertex flags
     void* sel;           // select: per-block best candidates
     int* xs;             // tie check: tight non-policy edges (tail), xcap entries
     int* ys;             //            and head
@@ -115,7 +116,9 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.stot = (unsigned*)take(4 * ((N + 1) / 2048 + 2));
     w.rin_ptr = (int*)take(4 * (N + 1));
     w.rin = (int*)take(4 * M);
-    w.abits = (unsigned*)take(4 * ((N + 31) / 32 + 1));
+    w.abits[0] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
+    w.abits[1] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
+    w.marks = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.touched = (unsigned char*)take(N + 16);
     w.sel = take(32 * ocm::kSelectParts);
     w.xcap = (unsigned)(m < kTieListCap ? m : kTieListCap);
@@ -412,9 +415,9 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
     unsigned left = c.h.ucnt[0], ulen = left, front = c.h.fcnt[0];
     if (left > 0) {
         c.prof.begin(OCM_K_CONN_PULL);
-        ocm::launch_bits_from_layer(c.n, layer, w.abits, c.st);
+        ocm::launch_bits_from_layer(c.n, layer, w.abits[0], w.abits[1], c.st);
         c.prof.end();
-        c.prof.bytes(OCM_K_CONN_PULL, 4.125 * c.n);
+        c.prof.bytes(OCM_K_CONN_PULL, 4.25 * c.n);
     }
     int ua = 0, fa = 0, k = 0;
     ocm_status rc = OCM_OK;
@@ -428,39 +431,35 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
         if (push && !c.rev_built) {
             c.prof.begin(OCM_K_REVERSE);
             ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr, w.rin,
-                                  w.touched, c.st);
+                                  w.marks, c.st);
             c.prof.end();
             // count: col + counter per edge; fill, scan and copy of the
             // counters; fill: row_ptr, col, cursor and the 4-byte tail per
-            // edge; touched reset
-            c.prof.bytes(OCM_K_REVERSE, 20.0 * c.m + 29.0 * c.n);
+            // edge; mark bitmap reset
+            c.prof.bytes(OCM_K_REVERSE, 20.0 * c.m + 28.125 * c.n);
             HIP_TRY(hipGetLastError());
             c.rev_built = true;
         }
-        const int cls = push ? OCM_K_CONN_MARK : OCM_K_CONN_PULL;
+        // round k reads abits[k&1] and completes abits[(k+1)&1]
+        const unsigned* acur = w.abits[k & 1];
+        unsigned* anext = w.abits[(k + 1) & 1];
+        const unsigned fadd = k > 1 ? front : 0u;   // round 1: the frontier is in both already
         ocm::launch_zero2(&w.ctl->ucnt[ub], &w.ctl->fcnt[fb], c.st);
-        if (k > 1) {
-            // the previous round's frontier joins the attached set
-            c.prof.begin(cls);
-            ocm::launch_bits_set(w.flist[fa], front, w.abits, c.st);
-            c.prof.end();
-            c.prof.bytes(cls, 8.0 * front);
-        }
         if (push) {
             c.prof.begin(OCM_K_CONN_MARK);
-            ocm::launch_conn_mark(w.rin_ptr, w.rin, w.abits, w.touched, w.flist[fa], front,
-                                  &w.ctl->pedges, c.st);
+            ocm::launch_conn_mark(w.rin_ptr, w.rin, acur, anext, w.marks, w.flist[fa], front,
+                                  k > 1, &w.ctl->pedges, c.st);
             c.prof.end();
             c.prof.begin(OCM_K_CONN_CLAIM);
-            ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, w.abits, w.touched, pi, layer,
+            ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, w.marks, pi, layer,
                                    w.flist[fb], &w.ctl->fcnt[fb], &w.ctl->ledges, c.st);
             c.prof.end();
             c.push_frontier += front;
         } else {
             c.prof.begin(OCM_K_CONN_PULL);
-            ocm::launch_conn_pull(k, c.row_ptr, c.col, w.abits, layer, pi, w.list[ua], ulen,
+            ocm::launch_conn_pull(k, c.row_ptr, c.col, acur, anext, layer, pi, w.list[ua], ulen,
                                   w.list[ub], &w.ctl->ucnt[ub], w.flist[fb], &w.ctl->fcnt[fb],
-                                  &w.ctl->ledges, c.st);
+                                  w.flist[fa], fadd, &w.ctl->ledges, c.st);
             c.prof.end();
         }
         HIP_TRY(hipGetLastError());
@@ -468,18 +467,20 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
         const unsigned got = c.h.fcnt[fb];
         const double S = (double)(c.h.ledges - le0);
         if (push) {
-            // mark: frontier entry and offsets, then per in-edge the 4-byte
-            // tail and its bit, and one touched byte per attached vertex;
-            // claim: the touched bytes, then per attached vertex its offsets,
-            // pi, layer and list entry, and per scanned out-edge col and a bit
+            // mark: frontier entry, offsets and its bit; per in-edge the
+            // 4-byte tail and its bit, and a mark bit per attached vertex;
+            // claim: the mark words, then per attached vertex its offsets,
+            // pi, layer, list entry and bit, and per scanned out-edge col and
+            // a bit
             const double E = (double)(c.h.pedges - pe0);
-            c.prof.bytes(OCM_K_CONN_MARK, 12.0 * front + 4.125 * E + got);
-            c.prof.bytes(OCM_K_CONN_CLAIM, (double)c.n + 20.0 * got + 4.125 * S);
+            c.prof.bytes(OCM_K_CONN_MARK, 12.125 * front + 4.125 * E + 0.125 * got);
+            c.prof.bytes(OCM_K_CONN_CLAIM, 0.25 * c.n + 20.125 * got + 4.125 * S);
         } else {
             // list entry, offsets and own bit per listed vertex; col and a bit
-            // per scanned edge; pi, layer and list entries of the outcome
-            c.prof.bytes(OCM_K_CONN_PULL,
-                         12.125 * ulen + 4.125 * S + 12.0 * got + 4.0 * c.h.ucnt[ub]);
+            // per scanned edge; pi, layer, list entries and bits of the
+            // outcome; the previous frontier's bits
+            c.prof.bytes(OCM_K_CONN_PULL, 12.125 * ulen + 4.125 * S + 12.125 * got +
+                                              4.0 * c.h.ucnt[ub] + 4.125 * fadd);
         }
         pe0 = c.h.pedges;
         le0 = c.h.ledges;
