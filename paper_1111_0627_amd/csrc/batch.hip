@@ -69,9 +69,7 @@ struct BCtl {
     unsigned nactive, nfast, ngeneral, ndone;
     unsigned vrunning;
     unsigned ncyc;
-    unsigned ucnt[2], fcnt[2];
     unsigned overflow;
-    unsigned long long pedges, ledges;
 };
 
 __device__ __forceinline__ bool chunk_range(const int2* __restrict__ chunks, const unsigned* nch,
@@ -589,56 +587,89 @@ __global__ __launch_bounds__(kWG) void k_set_lambda(int G, GArrays ga,
 // ---------------------------------------------------------------------------
 // rebuild: keep each graph's chosen component, list the rest
 // ---------------------------------------------------------------------------
+// Clears, in a bitmap, the bits of this wave's 64 consecutive vertices
+// vb .. vb+63 whose lanes pass `cond` (one atomicAnd per touched word).
+__device__ __forceinline__ void clear_wave_bits(unsigned* bits, int64_t vb, bool cond)
+{
+    const unsigned long long B = __ballot(cond);
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = vb >> 5;
+    // the 64 vertices span at most three words; lane j < 3 handles word w0 + j
+    if (lane < 3) {
+        const int64_t j = w0 + lane;
+        const int64_t lo = (j * 32 > vb ? j * 32 : vb) - vb;
+        const int64_t hi = ((j + 1) * 32 < vb + 64 ? (j + 1) * 32 : vb + 64) - vb;
+        if (lo < hi) {
+            const unsigned long long span = hi - lo == 64 ? ~0ull : ((1ull << (hi - lo)) - 1ull);
+            const unsigned m = (unsigned)(((B >> lo) & span) << ((vb + lo) & 31));
+            if (m) atomicAnd(&bits[j], ~m);
+        }
+    }
+}
+
+// Rebuild init for the graphs in chunks (mode kGeneral): C's component keeps
+// pi (layer 0), the rest is unattached (layer -1).  Both bitmaps start all
+// ones (every other graph counts as attached); here every vertex leaves a0
+// and every unattached one leaves a1, so round 1 sees the components as its
+// frontier.  Counts go to cc's lanes (got = components, left = unattached).
 __global__ __launch_bounds__(kWG) void k_conn_init(const int2* __restrict__ chunks,
                                                    const unsigned* nch, int T, GArrays ga,
                                                    const int* __restrict__ rep,
                                                    const unsigned char* __restrict__ onc,
                                                    int* __restrict__ layer,
                                                    unsigned char* __restrict__ onC,
-                                                   int* __restrict__ ulist, unsigned* ucnt,
-                                                   int* __restrict__ flist, unsigned* fcnt)
+                                                   unsigned* a1, unsigned* a0, Ctl* cc)
 {
-    __shared__ int ubuf[kListItems], fbuf[kListItems];
-    __shared__ unsigned nu, nf;
-    if (threadIdx.x == 0) nu = nf = 0;
-    __syncthreads();
     int g;
     int64_t v0, v1;
     const bool ok = chunk_range(chunks, nch, ga.vptr, T, g, v0, v1);
     if (!ok) return;   // uniform per block
     const int s = ga.s[g];
-    BlockList bu{ubuf, &nu}, bf{fbuf, &nf};
-    for (int64_t vb = v0; vb < v1; vb += kWG) {
-        const int64_t v = vb + threadIdx.x;
-        bool live = v < v1, comp = false;
+    unsigned long long ncomp = 0, nleft = 0;
+    for (int64_t vb = v0 + (threadIdx.x & ~63); vb < v1; vb += kWG) {
+        const int64_t v = vb + (threadIdx.x & 63);
+        const bool live = v < v1;
+        bool comp = false;
         if (live) {
             comp = rep[v] == s;
             layer[v] = comp ? 0 : -1;
             onC[v] = (unsigned char)(comp && onc[v]);
+            ncomp += comp;
+            nleft += !comp;
         }
-        blist_push(bu, live && !comp, (int)v);
-        blist_push(bf, live && comp, (int)v);
+        clear_wave_bits(a0, vb, live);
+        clear_wave_bits(a1, vb, live && !comp);
     }
-    blist_flush(bu, ulist, ucnt);
-    blist_flush(bf, flist, fcnt);
+    ncomp = block_sum_u64(ncomp);
+    nleft = block_sum_u64(nleft);
+    if (threadIdx.x == 0) {
+        if (ncomp) atomicAdd(&my_lane(cc).got, (unsigned)ncomp);
+        if (nleft) atomicAdd(&my_lane(cc).left, (unsigned)nleft);
+    }
 }
 
-// vertices left unattached: their graphs are not strongly connected
-__global__ __launch_bounds__(kWG) void k_conn_fail(int G, const long long* __restrict__ vptr,
-                                                   const int* __restrict__ ulist, unsigned cnt,
-                                                   const int* __restrict__ layer, GArrays ga)
+// Graphs with a vertex that stays unattached (not in acur) are not strongly
+// connected.
+__global__ __launch_bounds__(kWG) void k_conn_fail(int G, int n, const long long* __restrict__ vptr,
+                                                   const unsigned* __restrict__ acur, GArrays ga)
 {
-    for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < cnt; i += gridDim.x * kWG) {
-        const int u = ulist[i];
-        if (layer[u] != -1) continue;
-        int lo = 0, hi = G - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) / 2;
-            if (vptr[mid] <= u) lo = mid;
-            else hi = mid - 1;
+    const int64_t words = ((int64_t)n + 31) / 32;
+    for (int64_t w = (int64_t)blockIdx.x * kWG + threadIdx.x; w < words;
+         w += (int64_t)gridDim.x * kWG) {
+        const int64_t lo32 = w * 32;
+        unsigned un = ~acur[w] & (lo32 + 32 <= n ? 0xffffffffu : (1u << (unsigned)(n - lo32)) - 1u);
+        while (un) {
+            const int u = (int)(lo32 + __ffs(un) - 1);
+            un &= un - 1;
+            int lo = 0, hi = G - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (vptr[mid] <= u) lo = mid;
+                else hi = mid - 1;
+            }
+            ga.mode[lo] = kDone;
+            ga.status[lo] = OCM_E_NOT_STRONGLY_CONNECTED;
         }
-        ga.mode[lo] = kDone;
-        ga.status[lo] = OCM_E_NOT_STRONGLY_CONNECTED;
     }
 }
 
@@ -808,8 +839,6 @@ struct BWs {
     unsigned char* onc;
     unsigned char* onC;
     int* layer;
-    int* list[2];
-    int* flist[2];
     long long* wsum;
     unsigned* lcnt;
     int2* heads;
@@ -818,8 +847,9 @@ struct BWs {
     int* rin_ptr;
     int* rin;
     unsigned* abits[2];
-    unsigned* marks;
+    unsigned char* marks;
     unsigned* bad;
+    void* vctl;          // control block of the validation kernel
     size_t total;
 };
 
@@ -873,10 +903,6 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m)
     w.onc = (unsigned char*)take(N);
     w.onC = (unsigned char*)take(N);
     w.layer = (int*)take(4 * N);
-    w.list[0] = (int*)take(4 * N);
-    w.list[1] = (int*)take(4 * N);
-    w.flist[0] = (int*)take(4 * N);
-    w.flist[1] = (int*)take(4 * N);
     w.wsum = (long long*)take(8 * N);
     w.lcnt = (unsigned*)take(4 * N);
     w.heads = (int2*)take(8 * N);
@@ -886,8 +912,9 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m)
     w.rin = (int*)take(4 * M);
     w.abits[0] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.abits[1] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
-    w.marks = (unsigned*)take(4 * ((N + 31) / 32 + 1));
+    w.marks = (unsigned char*)take(N + 16);
     w.bad = (unsigned*)take(256);
+    w.vctl = take(sizeof(ocm::Ctl));
     w.total = off;
     return w;
 }
@@ -1098,10 +1125,15 @@ void enqueue_general_head(BCtx& c)
     ocm::b::k_set_lambda<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, ws.wsum,
                                                                      ws.lcnt);
     enqueue_chunks(c, ocm::b::kGeneral);   // graphs whose vote failed retired
-    ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[0], &ws.bc->fcnt[0]);
+    // rebuild init: counters and both bitmaps reset (all ones: graphs that
+    // are not rebuilt count as attached)
+    ocm::Ctl* cc = (ocm::Ctl*)ws.vctl;
+    ocm::launch_ctl_clear(cc, ocm::kClrCount, c.st);
+    const int64_t words = ((int64_t)c.n + 31) / 32;
+    ocm::launch_fill_u32(ws.abits[0], words, 0xffffffffu, c.st);
+    ocm::launch_fill_u32(ws.abits[1], words, 0xffffffffu, c.st);
     ocm::b::k_conn_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep, ws.onc,
-                                                   ws.layer, ws.onC, ws.list[0], &ws.bc->ucnt[0],
-                                                   ws.flist[0], &ws.bc->fcnt[0]);
+                                                   ws.layer, ws.onC, ws.abits[1], ws.abits[0], cc);
 }
 
 // One iteration up to the rebuild rounds: sweep, retire converged graphs,
@@ -1122,18 +1154,19 @@ void enqueue_head(BCtx& c, int max_iters, bool fast_path)
 }
 
 // Rebuild rounds over the union after k_conn_init (pull or push per round,
-// as in ocm_min); reads back the list sizes, so it runs outside the graphs.
+// as in ocm_min); reads the counts back, so it runs outside the graphs.
 ocm_status host_connect(BCtx& c)
 {
     BWs& ws = c.ws;
     GArrays& a = ws.ga;
-    unsigned left = c.h.ucnt[0], ulen = left, front = c.h.fcnt[0];
-    int ua = 0, fa = 0, k = 0;
-    if (left > 0) ocm::launch_bits_from_layer(c.n, ws.layer, ws.abits[0], ws.abits[1], c.st);
+    ocm::Ctl* cc = (ocm::Ctl*)ws.vctl;
+    ocm::CtlView h;
+    BHIP(ocm::host_read_ctl(cc, &h, c.st));
+    unsigned left = h.left, front = h.got;
+    int k = 0;
     while (left > 0) {
         ++k;
-        const int ub = ua ^ 1, fb = fa ^ 1;
-        const bool push = left >= (1u << 16) && (uint64_t)front * 4 < left;
+        const bool push = left >= (1u << 16) && (uint64_t)front * 2 < left;
         if (push && !c.rev_built) {
             ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, ws.rdeg, ws.stot, ws.rin_ptr, ws.rin,
                                   ws.marks, c.st);
@@ -1141,49 +1174,27 @@ ocm_status host_connect(BCtx& c)
         }
         const unsigned* acur = ws.abits[k & 1];
         unsigned* anext = ws.abits[(k + 1) & 1];
-        ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[ub], &ws.bc->fcnt[fb]);
+        ocm::launch_ctl_clear(cc, ocm::kClrCount, c.st);
         if (push) {
-            ocm::launch_conn_mark(ws.rin_ptr, ws.rin, acur, anext, ws.marks, ws.flist[fa], front,
-                                  k > 1, &ws.bc->pedges, c.st);
+            ocm::launch_conn_mark(c.n, ws.rin_ptr, ws.rin, acur, anext, ws.marks, nullptr, c.st);
             ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, ws.marks, ws.pi, ws.layer,
-                                   ws.flist[fb], &ws.bc->fcnt[fb], &ws.bc->ledges, c.st);
+                                   cc, nullptr, c.st);
         } else {
-            ocm::launch_conn_pull(k, c.row_ptr, c.col, acur, anext, ws.layer, ws.pi, ws.list[ua],
-                                  ulen, ws.list[ub], &ws.bc->ucnt[ub], ws.flist[fb],
-                                  &ws.bc->fcnt[fb], ws.flist[fa], k > 1 ? front : 0u,
-                                  &ws.bc->ledges, c.st);
+            ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, ws.layer, ws.pi, cc,
+                                  nullptr, c.st);
         }
         BHIP(hipGetLastError());
-        BTRY(bread(c));
-        const unsigned got = c.h.fcnt[fb];
-        if (push) {
-            left -= got;
-        } else {
-            ulen = c.h.ucnt[ub];
-            left = ulen;
-            ua = ub;
-        }
+        BHIP(ocm::host_read_ctl(cc, &h, c.st));
+        const unsigned got = h.got;
         if (got == 0) {
-            // the remaining vertices cannot reach their graph's cycle
-            if (push) {
-                // refresh the unattached list with a pull pass, which attaches
-                // nobody: it reads the attached set the push round saw
-                ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ucnt[ub], &ws.bc->fcnt[fb]);
-                ocm::launch_conn_pull(k, c.row_ptr, c.col, acur, anext, ws.layer, ws.pi,
-                                      ws.list[ua], ulen, ws.list[ub], &ws.bc->ucnt[ub],
-                                      ws.flist[fb], &ws.bc->fcnt[fb], ws.flist[fa], 0u,
-                                      &ws.bc->ledges, c.st);
-                BTRY(bread(c));
-                ulen = c.h.ucnt[ub];
-                ua = ub;
-            }
-            ocm::b::k_conn_fail<<<ocm::stride_grid(ulen), ocm::kWG, 0, c.st>>>(
-                (int)c.G, a.vptr, ws.list[ua], ulen, ws.layer, a);
+            // the vertices still outside acur cannot reach their graph's cycle
+            ocm::b::k_conn_fail<<<ocm::stride_grid((c.n + 31) / 32), ocm::kWG, 0, c.st>>>(
+                (int)c.G, c.n, a.vptr, acur, a);
             BHIP(hipGetLastError());
             break;
         }
+        left -= got;
         front = got;
-        fa = fb;
     }
     return OCM_OK;
 }
@@ -1385,12 +1396,11 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
 
     // validation: the union's CSR, the weight bound, and edges inside graphs
     {
-        ocm::Ctl* vctl = (ocm::Ctl*)ws.bad;   // scratch (256 bytes)
+        ocm::Ctl* vctl = (ocm::Ctl*)ws.vctl;
         ocm::launch_ctl_clear(vctl, ocm::kClrAll | ocm::kClrCount | ocm::kClrChanged, c.st);
         ocm::launch_validate(c.n, c.m, c.row_ptr, c.col, c.w, c.wtype, o.validate != 0, vctl, c.st);
-        ocm::Ctl hc;
-        BHIP(hipMemcpyAsync(&hc, vctl, sizeof hc, hipMemcpyDeviceToHost, c.st));
-        BHIP(hipStreamSynchronize(c.st));
+        ocm::CtlView hc;
+        BHIP(ocm::host_read_ctl(vctl, &hc, c.st));
         if (hc.err & ocm::kErrBadCsr) return bfail(OCM_E_BAD_CSR, "malformed CSR");
         if (hc.err & ocm::kErrNoOut) return bfail(OCM_E_NO_OUT_EDGE, "a vertex has no out-edge");
         const unsigned __int128 bound = (unsigned __int128)2 * (unsigned)c.max_n * hc.maxabsw;

@@ -99,6 +99,16 @@ __device__ __forceinline__ void blist_flush(BlockList& b, int* out, unsigned* ou
     for (unsigned j = threadIdx.x; j < cnt; j += kWG) out[base + j] = b.buf[j];
 }
 
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned x)
+{
+    const int lane = threadIdx.x & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
 // |x| as unsigned, defined for INT64_MIN too.
 __device__ __forceinline__ unsigned long long uabs64(int64_t x)
 {

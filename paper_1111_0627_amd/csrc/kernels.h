@@ -17,37 +17,107 @@ constexpr unsigned kErrNoOut = 2u;
 constexpr unsigned kClrChanged = 1u;
 constexpr unsigned kClrCount = 2u;
 constexpr unsigned kClrAll = 4u;
+constexpr unsigned kClrActive2 = 8u;
 
 // |V| must stay within 2^62 so that V[u] + (L*w - W) cannot leave int64 when
 // |L*w - W| < 2^62 as well.
 constexpr long long kValLimit = (1ll << 62);
 constexpr unsigned kHopOverflow = 0x80000000u;
 
-// Device control block: loop counters and the current lambda = W / L.
-struct alignas(16) Ctl {
-    long long W, L;                // current lambda, unreduced
-    int s;                         // current source (min vertex of C)
-    unsigned ncyc;                 // cycles found by the cycle phase
+// Counters that many workgroups update.  Same-address atomics from
+// thousands of workgroups serialise (about 11 ns apiece measured on MI355X,
+// i.e. ~90 us for one atomic from each of 8192 workgroups), so every
+// workgroup updates copy blockIdx % kLanes and readers fold the copies.
+constexpr int kLanes = 16;
+constexpr int kLaneWords = 32;   // one copy per 128-byte line
+
+struct alignas(128) CtlLane {
     unsigned long long changed;    // sweep: vertices whose policy changed
     unsigned long long tight;      // tie scan: tight non-policy edges
-    unsigned ucnt[2];              // connect: unattached-list sizes
-    unsigned fcnt[2];              // connect: frontier-list sizes
-    unsigned active;               // values: unfinished vertices
-    unsigned active2;
-    unsigned err;                  // validation error bits
-    unsigned cbroken;              // sweep: a vertex of C changed policy
-    unsigned long long maxabsw;    // validation: max |w|
-    unsigned overflow;             // values: a value left [-2^62, 2^62]
-    unsigned pad;
-    unsigned long long pedges;     // connect: in-edges scanned by push marks
-    unsigned long long ledges;     // connect: out-edges scanned by pull rounds and push claims
     unsigned long long certain;    // tie scan: edges that certainly close a second critical cycle
     unsigned long long nondec;     // tie scan: tight non-policy edges not nearer the source
-    unsigned xcnt;                 // tie scan: tight non-policy edges listed
-    unsigned scnt;                 // tie check: special vertices
+    unsigned long long pedges;     // connect: in-edges scanned by push marks
+    unsigned long long ledges;     // connect: out-edges scanned by pull rounds and push claims
+    unsigned long long maxabsw;    // validation: max |w| (max-folded)
+    unsigned active, active2;      // values: unfinished vertices
+    unsigned got;                  // connect: vertices attached in the round (init: C's component)
+    unsigned left;                 // connect init: unattached vertices
+    unsigned err;                  // validation error bits (or-folded, like the next three)
+    unsigned cbroken;              // sweep: a vertex of C changed policy
+    unsigned overflow;             // values: a value left [-2^62, 2^62]
     unsigned bad;                  // conversion / policy check failure
     unsigned pjc[4];               // cycles: per round parity, image size and M changes
 };
+static_assert(sizeof(CtlLane) == 4 * kLaneWords, "one lane per 128-byte line");
+
+// Device control block: the current lambda = W / L, list counters, and the
+// striped counters.
+struct alignas(128) Ctl {
+    long long W, L;                // current lambda, unreduced
+    int s;                         // current source (min vertex of C)
+    unsigned ncyc;                 // cycles found by the cycle phase
+    unsigned ucnt[2];              // connect: unattached-list sizes
+    unsigned fcnt[2];              // connect: frontier-list sizes
+    unsigned xcnt;                 // tie scan: tight non-policy edges listed
+    unsigned scnt;                 // tie check: special vertices
+    CtlLane lane[kLanes];
+};
+
+// Host snapshot of a Ctl with the lanes folded (sums, or / max for flags).
+struct CtlView {
+    long long W, L;
+    int s;
+    unsigned ncyc;
+    unsigned ucnt[2], fcnt[2];
+    unsigned xcnt, scnt;
+    unsigned long long changed, tight, certain, nondec, pedges, ledges, maxabsw;
+    unsigned active, active2, got, left, err, cbroken, overflow, bad;
+    unsigned pjc[4];
+};
+
+__host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
+{
+    v.W = c.W;
+    v.L = c.L;
+    v.s = c.s;
+    v.ncyc = c.ncyc;
+    for (int j = 0; j < 2; ++j) {
+        v.ucnt[j] = c.ucnt[j];
+        v.fcnt[j] = c.fcnt[j];
+    }
+    v.xcnt = c.xcnt;
+    v.scnt = c.scnt;
+    v.changed = v.tight = v.certain = v.nondec = v.pedges = v.ledges = v.maxabsw = 0;
+    v.active = v.active2 = v.got = v.left = v.err = v.cbroken = v.overflow = v.bad = 0;
+    for (int j = 0; j < 4; ++j) v.pjc[j] = 0;
+    for (int l = 0; l < kLanes; ++l) {
+        const CtlLane& ln = c.lane[l];
+        v.changed += ln.changed;
+        v.tight += ln.tight;
+        v.certain += ln.certain;
+        v.nondec += ln.nondec;
+        v.pedges += ln.pedges;
+        v.ledges += ln.ledges;
+        v.maxabsw = ln.maxabsw > v.maxabsw ? ln.maxabsw : v.maxabsw;
+        v.active += ln.active;
+        v.active2 += ln.active2;
+        v.got += ln.got;
+        v.left += ln.left;
+        v.err |= ln.err;
+        v.cbroken |= ln.cbroken;
+        v.overflow |= ln.overflow;
+        v.bad |= ln.bad;
+        for (int j = 0; j < 4; ++j) v.pjc[j] += ln.pjc[j];
+    }
+}
+
+// copy of a striped counter used by the calling workgroup
+__device__ __forceinline__ CtlLane& my_lane(Ctl* c) { return c->lane[blockIdx.x & (kLanes - 1)]; }
+template <typename T>
+__device__ __forceinline__ T* my_copy(T* lane0_field)
+{
+    return (T*)((char*)lane0_field + (blockIdx.x & (kLanes - 1)) * (4 * kLaneWords));
+}
 
 // Pointer-jumping entry of the value phase: the first H edges of v's policy
 // path lead to J and carry the sum D of (L*w - W).  Bit 31 of H flags an
@@ -100,24 +170,24 @@ void launch_cyc_sum(int n, const int* rep, const unsigned char* onc, const int* 
 constexpr int kSelectParts = 512;
 void launch_select(const int* cyc_list, const long long* wsum, const unsigned* lcnt, Ctl* ctl,
                    void* scratch, hipStream_t st);
+// Rebuild (breadth-first attachment to C's component).  a[0], a[1]: the two
+// attached-vertex bitmaps (ceil(n/32) words each); marks: push-round mark
+// bytes (n + 16).  Counts go to the control block's lanes: init -> got (C's
+// component) and left (unattached); every round -> got (attached in it).
 void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, int* layer,
-                      unsigned char* onC, int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt,
+                      unsigned char* onC, unsigned* a1, unsigned* a0, Ctl* ctl, hipStream_t st);
+void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
+                      unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
                       hipStream_t st);
-// rebuild rounds: a0/a1 = the two attached-vertex bitmaps, marks = the push
-// rounds' mark bitmap (all bitmaps hold ceil(n/32) words)
-void launch_bits_from_layer(int n, const int* layer, unsigned* a0, unsigned* a1, hipStream_t st);
-void launch_conn_pull(int k, const int* row_ptr, const int* col, const unsigned* acur,
-                      unsigned* anext, int* layer, int* pi, const int* in_list, unsigned in_cnt,
-                      int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt, const int* fin,
-                      unsigned f_cnt, unsigned long long* ledges, hipStream_t st);
-void launch_conn_mark(const int* rin_ptr, const int* rin, const unsigned* acur, unsigned* anext,
-                      unsigned* marks, const int* fin, unsigned f_cnt, int add_front,
-                      unsigned long long* pedges, hipStream_t st);
+void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned* acur,
+                      unsigned* anext, unsigned char* marks, unsigned long long* pedges,
+                      hipStream_t st);
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
-                       unsigned* anext, unsigned* marks, int* pi, int* layer, int* fout,
-                       unsigned* fout_cnt, unsigned long long* cedges, hipStream_t st);
+                       unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
+                       unsigned long long* cedges, hipStream_t st);
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
-                      unsigned* tot, int* rin_ptr, int* rin, unsigned* marks, hipStream_t st);
+                      unsigned* tot, int* rin_ptr, int* rin, unsigned char* marks,
+                      hipStream_t st);
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
                      int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl, hipStream_t st);
 void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st);
@@ -136,6 +206,8 @@ void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsig
 // Reads `bytes` (a multiple of 4, at most 256) of device memory into host
 // memory once the stream's earlier work is done.
 hipError_t host_read(const void* dsrc, void* hdst, size_t bytes, hipStream_t st);
+// Folds a control block's lanes and reads the snapshot.
+hipError_t host_read_ctl(const Ctl* ctl, CtlView* out, hipStream_t st);
 
 // thread-local message returned by ocm_last_error()
 void set_last_error(const char* what);

@@ -54,8 +54,8 @@ __global__ __launch_bounds__(kWG) void k_validate(int n, int m, const int* __res
     if (err) atomicOr(&eor, err);
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (mx) atomicMax(&ctl->maxabsw, mx);
-        if (eor) atomicOr(&ctl->err, eor);
+        if (mx) atomicMax(&my_lane(ctl).maxabsw, mx);
+        if (eor) atomicOr(&my_lane(ctl).err, eor);
     }
 }
 
@@ -138,10 +138,11 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a, const WT* __restrict
         nondec = block_sum_u64(nondec);
     }
     if (threadIdx.x == 0) {
-        if (cnt) atomicAdd(TIE ? &a.ctl->tight : &a.ctl->changed, cnt);
-        if (brk) atomicOr(&a.ctl->cbroken, 1u);
-        if (TIE && certain) atomicAdd(&a.ctl->certain, certain);
-        if (TIE && nondec) atomicAdd(&a.ctl->nondec, nondec);
+        CtlLane& ln = my_lane(a.ctl);
+        if (cnt) atomicAdd(TIE ? &ln.tight : &ln.changed, cnt);
+        if (brk) atomicOr(&ln.cbroken, 1u);
+        if (TIE && certain) atomicAdd(&ln.certain, certain);
+        if (TIE && nondec) atomicAdd(&ln.nondec, nondec);
     }
 }
 
@@ -235,8 +236,9 @@ __global__ __launch_bounds__(kWG) void k_sweep_u(SweepArgs a, const WT* __restri
     cnt = block_sum_u64(cnt);
     const unsigned long long brk = block_sum_u64(cbroken);
     if (threadIdx.x == 0) {
-        if (cnt) atomicAdd(&a.ctl->changed, cnt);
-        if (brk) atomicOr(&a.ctl->cbroken, 1u);
+        CtlLane& ln = my_lane(a.ctl);
+        if (cnt) atomicAdd(&ln.changed, cnt);
+        if (brk) atomicOr(&ln.cbroken, 1u);
     }
 }
 
@@ -270,7 +272,9 @@ __global__ __launch_bounds__(kWG) void k_pj_init(int n, const int* __restrict__ 
                                                  unsigned char* __restrict__ tag0, unsigned* cnt)
 {
     const int v = blockIdx.x * kWG + threadIdx.x;
-    if (v == 0 && cnt) cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
+    if (v == 0 && cnt)
+        for (int l = 0; l < kLanes; ++l)
+            for (int j = 0; j < 4; ++j) cnt[l * kLaneWords + j] = 0;
     if (v >= n) return;
     const int s = col[pi[v]];
     succ[v] = s;
@@ -299,7 +303,10 @@ __global__ __launch_bounds__(kWG) void k_pj_round(int n, const unsigned long lon
         Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
         return;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) nxt[0] = nxt[1] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kLanes) {
+        nxt[threadIdx.x * kLaneWords] = 0;
+        nxt[threadIdx.x * kLaneWords + 1] = 0;
+    }
     unsigned long long img = 0, chg = 0;
     // grid-stride with kJumpUnroll independent entries in flight per thread
     const int64_t stride = (int64_t)gridDim.x * kWG;
@@ -323,7 +330,9 @@ __global__ __launch_bounds__(kWG) void k_pj_round(int n, const unsigned long lon
                 const unsigned m0 = (unsigned)p[u], m1 = (unsigned)q[u];
                 Pout[v] = (q[u] & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
                 chg += m1 < m0;
-                tcur[(int)(q[u] >> 32)] = tag_cur;
+                // the image shrinks fast: most targets are already tagged
+                const int t = (int)(q[u] >> 32);
+                if (tcur[t] != tag_cur) tcur[t] = tag_cur;
                 img += tprev[v] == tag_prev;
             }
         }
@@ -331,8 +340,9 @@ __global__ __launch_bounds__(kWG) void k_pj_round(int n, const unsigned long lon
     img = block_sum_u64(img);
     chg = block_sum_u64(chg);
     if (threadIdx.x == 0) {
-        if (img) atomicAdd(&cnt[0], (unsigned)img);
-        if (chg) atomicAdd(&cnt[1], (unsigned)chg);
+        unsigned* mine = my_copy(cnt);
+        if (img) atomicAdd(&mine[0], (unsigned)img);
+        if (chg) atomicAdd(&mine[1], (unsigned)chg);
     }
 }
 
@@ -470,246 +480,376 @@ __global__ __launch_bounds__(kWG) void k_select_final(const Cand* __restrict__ p
 // The rebuild attaches vertices in rounds.  In round k an unattached vertex u
 // can only have out-edges into layer k-1 (an edge into an earlier layer would
 // have attached it earlier), so "the lowest-position out-edge into the set
-// attached before round k" is u's first out-edge, in CSR order, whose head
-// is attached.  Two bitmaps (one bit per vertex, 2 MB at 16.7M vertices, so
-// they stay in L2) alternate: at the start of round k, A[k&1] holds the
-// layers <= k-1 and A[(k+1)&1] the layers <= k-2.  Round k only reads
-// A[k&1]; it adds the previous frontier (layer k-1) and its own attachments
-// (layer k) to A[(k+1)&1], which restores the invariant for round k+1.
-// Both directions then find u's edge with the same scan:
-//   pull: every listed unattached u scans its own out-edges (k_conn_pull);
-//   push: the frontier's in-edges mark their unattached tails in a third
-//         bitmap (k_conn_mark) and only the marked vertices scan
+// attached before round k" is u's lowest out-edge whose head is attached.
+//
+// Two bitmaps (one bit per vertex) alternate: at the start of round k,
+// A[k&1] holds the layers <= k-1 and A[(k+1)&1] the layers <= k-2, so the
+// frontier (layer k-1) is A[k&1] & ~A[(k+1)&1].  Round k only reads A[k&1];
+// it adds the frontier and its own attachments (layer k) to A[(k+1)&1],
+// which restores the invariant for round k+1.  No vertex lists are kept:
+// every round kernel owns 64 bitmap words (2048 vertices) per workgroup, so
+// each word has one writer and needs no atomics.
+//   pull: the workgroup lists its unattached vertices and scans their
+//         out-edges (k_conn_pull);
+//   push: the frontier's in-edges mark their unattached tails in a byte
+//         array (k_conn_mark) and only the marked vertices scan
 //         (k_conn_claim).
-// The host picks the cheaper direction per round.
-__global__ __launch_bounds__(kWG) void k_conn_init(int n, const int* __restrict__ rep,
-                                                   const unsigned char* __restrict__ onc,
-                                                   int s, unsigned per, int* __restrict__ layer,
-                                                   unsigned char* __restrict__ onC,
-                                                   int* __restrict__ ulist, unsigned* ucnt,
-                                                   int* __restrict__ flist, unsigned* fcnt)
-{
-    __shared__ int ubuf[kListItems], fbuf[kListItems];
-    __shared__ unsigned nu, nf;
-    if (threadIdx.x == 0) nu = nf = 0;
-    __syncthreads();
-    BlockList bu{ubuf, &nu}, bf{fbuf, &nf};
-    const int64_t v0 = (int64_t)blockIdx.x * per;
-    const int64_t v1 = v0 + per < n ? v0 + per : n;
-    for (int64_t vb = v0; vb < v1; vb += kWG) {
-        const int64_t v = vb + threadIdx.x;
-        bool live = v < v1, comp = false;
-        if (live) {
-            comp = rep[v] == s;
-            layer[v] = comp ? 0 : -1;
-            if (onC) onC[v] = (unsigned char)(comp && onc && onc[v]);
-        }
-        blist_push(bu, live && !comp, (int)v);
-        blist_push(bf, live && comp, (int)v);
-    }
-    blist_flush(bu, ulist, ucnt);
-    blist_flush(bf, flist, fcnt);
-}
+// Both find, for every vertex that attaches, the same (lowest) edge; the host
+// picks the cheaper direction per round.
+// A round workgroup owns kWG * WPT consecutive bitmap words (WPT = 1 or 2
+// words, i.e. 32 or 64 vertices, per thread), so one pass over its span has
+// a single load per thread; the items it finds (frontier, marked or
+// unattached vertices) are processed in LDS batches of kBatch.
+constexpr int kBatch = 2048;
 
 __device__ __forceinline__ bool attached(const unsigned* __restrict__ abits, int v)
 {
     return (abits[v >> 5] >> (v & 31)) & 1u;
 }
 
-__device__ __forceinline__ void set_bit(unsigned* abits, int v)
+__device__ __forceinline__ unsigned valid_bits(int64_t word, int n)
 {
-    atomicOr(&abits[v >> 5], 1u << (v & 31));
+    const int64_t lo = word * 32;
+    return lo + 32 <= n ? 0xffffffffu : (lo >= n ? 0u : (1u << (unsigned)(n - lo)) - 1u);
 }
 
-// a0[i] = a1[i] = bits j with layer[32 i + j] >= 0 (every word written).
-__global__ __launch_bounds__(kWG) void k_bits_from_layer(int n, const int* __restrict__ layer,
-                                                         unsigned* __restrict__ a0,
-                                                         unsigned* __restrict__ a1)
+// Exclusive rank of each thread's count c over the workgroup; *total = sum.
+// All threads call it.
+__device__ __forceinline__ unsigned block_rank(unsigned c, unsigned* wsum, unsigned* total)
+{
+    const unsigned incl = wave_incl_scan(c);
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    unsigned wbase = 0, t = 0;
+    for (int w = 0; w < kWG / 64; ++w) {
+        if (w < (int)(threadIdx.x >> 6)) wbase += wsum[w];
+        t += wsum[w];
+    }
+    __syncthreads();   // wsum may be reused
+    *total = t;
+    return wbase + incl - c;
+}
+
+// Exclusive prefix sum of a[0, cnt) in LDS (cnt <= kBatch); returns the
+// total.  All threads call it.
+__device__ __forceinline__ unsigned block_excl_scan(unsigned* a, unsigned cnt, unsigned* wsum)
+{
+    constexpr int kRun = kBatch / kWG;
+    const unsigned r0 = threadIdx.x * kRun;
+    unsigned run = 0;
+    for (int j = 0; j < kRun; ++j)
+        if (r0 + j < cnt) run += a[r0 + j];
+    unsigned total = 0;
+    const unsigned ex = block_rank(run, wsum, &total);
+    unsigned acc = ex;
+    for (int j = 0; j < kRun; ++j) {
+        if (r0 + j < cnt) {
+            const unsigned d = a[r0 + j];
+            a[r0 + j] = acc;
+            acc += d;
+        }
+    }
+    __syncthreads();
+    return total;
+}
+
+// Last i in [0, cnt) with off[i] <= t (off non-decreasing, off[0] = 0).
+__device__ __forceinline__ unsigned owner_of(const unsigned* off, unsigned cnt, unsigned t)
+{
+    unsigned lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const unsigned mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Writes this thread's items (set bits of mask, item = base_id + bit) whose
+// workgroup rank lies in [b0, b0 + kBatch) to todo[rank - b0].
+__device__ __forceinline__ void emit_batch(unsigned long long mask, int64_t base_id, unsigned rank,
+                                           unsigned b0, int* todo)
+{
+    const unsigned c = (unsigned)__popcll(mask);
+    if (c == 0 || rank + c <= b0 || rank >= b0 + kBatch) return;
+    unsigned r = rank;
+    while (mask && r < b0 + kBatch) {
+        const int b = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        if (r >= b0) todo[r - b0] = (int)(base_id + b);
+        ++r;
+    }
+}
+
+// For each of the cnt listed vertices, the lowest out-edge whose head is
+// attached (INT32_MAX if none): out-edges spread evenly over the workgroup,
+// LDS atomicMin per vertex.  Returns the number of edges scanned.
+__device__ __forceinline__ unsigned lowest_attached_edges(const int* __restrict__ row_ptr,
+                                                          const int* __restrict__ col,
+                                                          const unsigned* __restrict__ acur,
+                                                          const int* todo, unsigned cnt, int* beg,
+                                                          unsigned* off, int* best, unsigned* wsum)
+{
+    for (unsigned i = threadIdx.x; i < cnt; i += kWG) {
+        const int u = todo[i];
+        const int b = row_ptr[u];
+        beg[i] = b;
+        off[i] = (unsigned)(row_ptr[u + 1] - b);
+        best[i] = INT32_MAX;
+    }
+    __syncthreads();
+    const unsigned total = block_excl_scan(off, cnt, wsum);
+    for (unsigned t = threadIdx.x; t < total; t += kWG) {
+        const unsigned i = owner_of(off, cnt, t);
+        const int e = beg[i] + (int)(t - off[i]);
+        if (attached(acur, col[e])) atomicMin(&best[i], e);
+    }
+    __syncthreads();
+    return total;
+}
+
+// Rebuild init: C's component (rep == s) keeps pi (layer 0), every other
+// vertex is unattached (layer -1).  Writes the round-1 bitmaps (a1 = layer
+// 0, a0 = empty) and counts both sets into the lanes (got, left).
+__global__ __launch_bounds__(kWG) void k_conn_init(int n, const int* __restrict__ rep,
+                                                   const unsigned char* __restrict__ onc, int s,
+                                                   int* __restrict__ layer,
+                                                   unsigned char* __restrict__ onC,
+                                                   unsigned* __restrict__ a1,
+                                                   unsigned* __restrict__ a0, Ctl* ctl)
 {
     const int64_t words = ((int64_t)n + 31) / 32;
     const int64_t span = (int64_t)gridDim.x * kWG;
+    const int lane = threadIdx.x & 63;
+    unsigned long long ncomp = 0, nleft = 0;
     // 64 consecutive vertices per wave, two words per ballot
-    for (int64_t vb = ((int64_t)blockIdx.x * kWG + threadIdx.x) & ~(int64_t)63;
-         vb < (int64_t)n; vb += span) {
-        const int64_t v = vb + (threadIdx.x & 63);
-        const unsigned long long b = __ballot(v < n && layer[v] >= 0);
-        const int lane = threadIdx.x & 63;
+    for (int64_t vb = ((int64_t)blockIdx.x * kWG + threadIdx.x) & ~(int64_t)63; vb < (int64_t)n;
+         vb += span) {
+        const int64_t v = vb + lane;
+        bool comp = false;
+        if (v < n) {
+            comp = rep[v] == s;
+            layer[v] = comp ? 0 : -1;
+            if (onC) onC[v] = (unsigned char)(comp && onc && onc[v]);
+        }
+        const unsigned long long b = __ballot(comp);
+        const unsigned long long live = __ballot(v < n);
         const int64_t wd = (vb >> 5) + (lane >> 5);
         if ((lane & 31) == 0 && wd < words) {
-            const unsigned x = (unsigned)(b >> (lane & 32));
-            a0[wd] = x;
-            a1[wd] = x;
+            a1[wd] = (unsigned)(b >> (lane & 32));
+            a0[wd] = 0u;
+        }
+        if (lane == 0) {
+            ncomp += (unsigned long long)__popcll(b);
+            nleft += (unsigned long long)__popcll(live & ~b);
         }
     }
-}
-
-// adds the listed vertices to a bitmap (grid-stride over the list)
-__device__ __forceinline__ void add_list_bits(const int* __restrict__ list, unsigned cnt,
-                                              unsigned* abits)
-{
-    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < cnt;
-         i += (int64_t)gridDim.x * kWG)
-        set_bit(abits, list[i]);
-}
-
-// First out-edge of u, in CSR order, whose head is attached; -1 if none.
-__device__ __forceinline__ int first_attached_edge(const int* __restrict__ row_ptr,
-                                                   const int* __restrict__ col,
-                                                   const unsigned* __restrict__ abits, int u,
-                                                   unsigned long long& scanned)
-{
-    for (int e = row_ptr[u], end = row_ptr[u + 1]; e < end; ++e) {
-        ++scanned;
-        if (attached(abits, col[e])) return e;
+    ncomp = block_sum_u64(ncomp);
+    nleft = block_sum_u64(nleft);
+    if (threadIdx.x == 0) {
+        if (ncomp) atomicAdd(&my_lane(ctl).got, (unsigned)ncomp);
+        if (nleft) atomicAdd(&my_lane(ctl).left, (unsigned)nleft);
     }
-    return -1;
 }
 
-// Pull round k over the unattached list; also adds the previous frontier
-// (fin, f_cnt; 0 in round 1) and this round's attachments to anext.
-__global__ __launch_bounds__(kWG) void k_conn_pull(int k, const int* __restrict__ row_ptr,
+// LDS of the round kernels
+struct RoundLds {
+    int todo[kBatch];
+    int beg[kBatch];
+    unsigned off[kBatch];
+    int best[kBatch];
+    unsigned wsum[kWG / 64];
+};
+
+// Attaches the batch's vertices that found an edge (pi, layer = k) and sets
+// their bits in nb (the workgroup's new words, first word wbase).
+__device__ __forceinline__ unsigned attach_batch(int k, const RoundLds& L, unsigned cnt,
+                                                 int64_t wbase, unsigned* nb, int* __restrict__ pi,
+                                                 int* __restrict__ layer)
+{
+    unsigned got = 0;
+    for (unsigned i = threadIdx.x; i < cnt; i += kWG) {
+        const int h = L.best[i];
+        if (h != INT32_MAX) {
+            const int u = L.todo[i];
+            pi[u] = h;
+            layer[u] = k;
+            atomicOr(&nb[(u >> 5) - wbase], 1u << (u & 31));
+            ++got;
+        }
+    }
+    return got;
+}
+
+// Pull round k: the workgroup's unattached vertices (~acur) scan their
+// out-edges; anext becomes acur plus this round's attachments.
+template <int WPT>
+__global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __restrict__ row_ptr,
                                                    const int* __restrict__ col,
                                                    const unsigned* __restrict__ acur,
-                                                   unsigned* anext, int* __restrict__ layer,
-                                                   int* __restrict__ pi,
-                                                   const int* __restrict__ in_list, unsigned in_cnt,
-                                                   unsigned per, int* __restrict__ ulist,
-                                                   unsigned* ucnt, int* __restrict__ flist,
-                                                   unsigned* fcnt, const int* __restrict__ fin,
-                                                   unsigned f_cnt, unsigned long long* ledges)
+                                                   unsigned* __restrict__ anext,
+                                                   int* __restrict__ layer, int* __restrict__ pi,
+                                                   Ctl* ctl, unsigned long long* ledges)
 {
-    __shared__ int ubuf[kListItems], fbuf[kListItems];
-    __shared__ unsigned nu, nf;
-    if (threadIdx.x == 0) nu = nf = 0;
-    __syncthreads();
-    add_list_bits(fin, f_cnt, anext);
-    BlockList bu{ubuf, &nu}, bf{fbuf, &nf};
-    const int64_t i0 = (int64_t)blockIdx.x * per;
-    const int64_t i1 = i0 + per < in_cnt ? i0 + per : in_cnt;
-    unsigned long long scanned = 0;
-    for (int64_t ib = i0; ib < i1; ib += kWG) {
-        const int64_t i = ib + threadIdx.x;
-        bool left = false, got = false;
-        int u = 0;
-        // entries attached by a push round since the list was made are dropped
-        if (i < i1) {
-            u = in_list[i];
-            if (!attached(acur, u)) {
-                const int hit = first_attached_edge(row_ptr, col, acur, u, scanned);
-                if (hit >= 0) {
-                    pi[u] = hit;
-                    layer[u] = k;
-                    set_bit(anext, u);
-                    got = true;
-                } else {
-                    left = true;
-                }
-            }
+    __shared__ RoundLds L;
+    __shared__ unsigned nb[kWG * WPT];
+    const int64_t words = ((int64_t)n + 31) / 32;
+    const int64_t wbase = (int64_t)blockIdx.x * kWG * WPT;
+    const int64_t w0 = wbase + (int64_t)threadIdx.x * WPT;
+    unsigned a[WPT];
+    unsigned long long mask = 0;
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+        a[j] = 0;
+        nb[threadIdx.x * WPT + j] = 0;
+        if (w0 + j < words) {
+            a[j] = acur[w0 + j];
+            mask |= (unsigned long long)(~a[j] & valid_bits(w0 + j, n)) << (32 * j);
         }
-        blist_push(bu, left, u);
-        blist_push(bf, got, u);
     }
-    blist_flush(bu, ulist, ucnt);
-    blist_flush(bf, flist, fcnt);
-    scanned = block_sum_u64(scanned);
-    if (threadIdx.x == 0 && scanned) atomicAdd(ledges, scanned);
+    unsigned total = 0;
+    const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
+    unsigned got = 0, scanned = 0;
+    for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
+        emit_batch(mask, w0 * 32, rank, b0, L.todo);
+        __syncthreads();
+        const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
+        scanned += lowest_attached_edges(row_ptr, col, acur, L.todo, cnt, L.beg, L.off, L.best,
+                                         L.wsum);
+        got += attach_batch(k, L, cnt, wbase, nb, pi, layer);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < WPT; ++j)
+        if (w0 + j < words) anext[w0 + j] = a[j] | nb[threadIdx.x * WPT + j];
+    const unsigned long long g = block_sum_u64(got);
+    if (threadIdx.x == 0) {
+        if (g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
+        if (ledges && scanned) atomicAdd(my_copy(ledges), (unsigned long long)scanned);
+    }
 }
 
-// Push round k, mark: G lanes per frontier vertex x walk its in-edges
-// (coalesced 4-byte tails) and set the bit of every tail u not yet attached
-// in `marks`; x itself joins anext (unless add_front is 0, in round 1).
-template <int G>
-__global__ __launch_bounds__(kWG) void k_conn_mark(const int* __restrict__ rin_ptr,
+// Push round k, mark: the workgroup lists its frontier vertices
+// (acur & ~anext, folded into anext on the way) and spreads their in-edges
+// over its threads; every tail u gets marks[u] = 1 (plain byte store,
+// idempotent).  Attached tails are dropped by the claim, which reads its own
+// span of acur anyway.
+template <int WPT>
+__global__ __launch_bounds__(kWG) void k_conn_mark(int n, const int* __restrict__ rin_ptr,
                                                    const int* __restrict__ rin,
                                                    const unsigned* __restrict__ acur,
-                                                   unsigned* anext, unsigned* marks,
-                                                   const int* __restrict__ fin, unsigned f_cnt,
-                                                   int add_front, unsigned long long* pedges)
+                                                   unsigned* __restrict__ anext,
+                                                   unsigned char* __restrict__ marks,
+                                                   unsigned long long* pedges)
 {
-    const int gl = threadIdx.x & (G - 1);
-    const int64_t ngroups = (int64_t)gridDim.x * (kWG / G);
-    unsigned long long scanned = 0;
-    for (int64_t i = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G; i < f_cnt; i += ngroups) {
-        const int x = fin[i];
-        if (add_front && gl == 0) set_bit(anext, x);
-        for (int j = rin_ptr[x] + gl, end = rin_ptr[x + 1]; j < end; j += G) {
-            const int u = rin[j];
-            ++scanned;
-            if (!attached(acur, u)) set_bit(marks, u);
+    __shared__ RoundLds L;
+    const int64_t words = ((int64_t)n + 31) / 32;
+    const int64_t wbase = (int64_t)blockIdx.x * kWG * WPT;
+    const int64_t w0 = wbase + (int64_t)threadIdx.x * WPT;
+    unsigned long long mask = 0;
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+        if (w0 + j < words) {
+            const unsigned a = acur[w0 + j];
+            const unsigned f = a & ~anext[w0 + j];
+            if (f) anext[w0 + j] = a;   // anext is a subset of acur
+            mask |= (unsigned long long)f << (32 * j);
         }
     }
-    scanned = block_sum_u64(scanned);
-    if (threadIdx.x == 0 && scanned) atomicAdd(pedges, scanned);
+    unsigned total = 0;
+    const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
+    unsigned long long scanned = 0;
+    for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
+        emit_batch(mask, w0 * 32, rank, b0, L.todo);
+        __syncthreads();
+        const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
+        for (unsigned i = threadIdx.x; i < cnt; i += kWG) {
+            const int x = L.todo[i];
+            const int b = rin_ptr[x];
+            L.beg[i] = b;
+            L.off[i] = (unsigned)(rin_ptr[x + 1] - b);
+        }
+        __syncthreads();
+        const unsigned tot = block_excl_scan(L.off, cnt, L.wsum);
+        for (unsigned t = threadIdx.x; t < tot; t += kWG) {
+            const unsigned i = owner_of(L.off, cnt, t);
+            marks[rin[L.beg[i] + (int)(t - L.off[i])]] = 1;
+        }
+        scanned += tot;
+        __syncthreads();
+    }
+    if (pedges && threadIdx.x == 0 && scanned) atomicAdd(my_copy(pedges), scanned);
 }
 
-constexpr int kClaimWords = 64;                  // mark words per block
-constexpr int kClaimVerts = 32 * kClaimWords;    // 2048 vertices per block
-constexpr int kClaimLanes = 8;                   // lanes per marked vertex
-
-// Push round k, claim: each block takes kClaimWords words of the mark bitmap
-// (clearing them), lists the marked vertices in LDS, and scans each one's
-// out-edges with kClaimLanes lanes for the first attached head.  One exists:
-// the edge that marked it.  The vertex attaches with that edge (pi, layer =
-// k), joins anext and the next frontier.
+// Push round k, claim: the workgroup takes the mark bytes of its span
+// (clearing them), lists the marked vertices and finds each one's lowest
+// out-edge into the attached set.  One exists: the edge that marked it.  The
+// vertex attaches with it (pi, layer = k) and joins anext.
+template <int WPT>
 __global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __restrict__ row_ptr,
                                                     const int* __restrict__ col,
                                                     const unsigned* __restrict__ acur,
-                                                    unsigned* anext, unsigned* marks,
+                                                    unsigned* __restrict__ anext,
+                                                    unsigned char* __restrict__ marks,
                                                     int* __restrict__ pi, int* __restrict__ layer,
-                                                    int* __restrict__ fout, unsigned* fout_cnt,
-                                                    unsigned long long* cedges)
+                                                    Ctl* ctl, unsigned long long* cedges)
 {
-    __shared__ int todo[kClaimVerts];
-    __shared__ int obuf[kClaimVerts];   // at most one output per listed vertex
-    __shared__ unsigned ntodo, nout;
-    if (threadIdx.x == 0) ntodo = nout = 0;
-    __syncthreads();
+    __shared__ RoundLds L;
+    __shared__ unsigned nb[kWG * WPT];
     const int64_t words = ((int64_t)n + 31) / 32;
-    const int64_t wd = (int64_t)blockIdx.x * kClaimWords + threadIdx.x;
-    if (threadIdx.x < kClaimWords && wd < words) {
-        unsigned x = marks[wd];
-        if (x) {
-            marks[wd] = 0u;
-            const unsigned base = atomicAdd(&ntodo, (unsigned)__popc(x));
-            unsigned j = 0;
-            while (x) {
-                const int b = __ffs(x) - 1;
-                x &= x - 1;
-                todo[base + j++] = (int)(wd * 32 + b);
+    const int64_t wbase = (int64_t)blockIdx.x * kWG * WPT;
+    const int64_t w0 = wbase + (int64_t)threadIdx.x * WPT;
+    const int64_t v0 = w0 * 32;   // this thread's 32 * WPT mark bytes
+    unsigned long long mask = 0;
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) nb[threadIdx.x * WPT + j] = 0;
+    if (v0 + 32 * WPT <= n) {
+#pragma unroll
+        for (int q = 0; q < 2 * WPT; ++q) {
+            uint4 t = *(const uint4*)(marks + v0 + 16 * q);
+            if (t.x | t.y | t.z | t.w) *(uint4*)(marks + v0 + 16 * q) = make_uint4(0, 0, 0, 0);
+            const unsigned wd[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if ((wd[r >> 2] >> (8 * (r & 3))) & 0xffu) mask |= 1ull << (16 * q + r);
+        }
+    } else {
+        for (int q = 0; q < 32 * WPT && v0 + q < n; ++q) {
+            if (marks[v0 + q]) {
+                mask |= 1ull << q;
+                marks[v0 + q] = 0;
             }
         }
     }
-    __syncthreads();
-    const unsigned cnt = ntodo;
-    BlockList bl{obuf, &nout};
-    const int gl = threadIdx.x & (kClaimLanes - 1);
-    const int gshift = threadIdx.x & 63 & ~(kClaimLanes - 1);   // group's first lane in the wave
+    // marked tails that are already attached drop out
+    unsigned long long att = 0;
+#pragma unroll
+    for (int j = 0; j < WPT; ++j)
+        if (w0 + j < words) att |= (unsigned long long)acur[w0 + j] << (32 * j);
+    mask &= ~att;
+    unsigned total = 0;
+    const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
+    unsigned got = 0;
     unsigned long long scanned = 0;
-    for (unsigned ib = 0; ib < cnt; ib += kWG / kClaimLanes) {
-        const unsigned i = ib + threadIdx.x / kClaimLanes;
-        int u = 0, hit = -1;
-        if (i < cnt) {
-            u = todo[i];
-            for (int b = row_ptr[u], end = row_ptr[u + 1]; b < end && hit < 0; b += kClaimLanes) {
-                const int e = b + gl;
-                const bool h = e < end && attached(acur, col[e]);
-                const unsigned gm =
-                    (unsigned)(__ballot(h) >> gshift) & ((1u << kClaimLanes) - 1u);
-                if (gm) hit = b + __ffs(gm) - 1;
-                scanned += e < end ? 1 : 0;
-            }
-        }
-        const bool got = gl == 0 && hit >= 0;
-        if (got) {
-            pi[u] = hit;
-            layer[u] = k;
-            set_bit(anext, u);
-        }
-        blist_push(bl, got, u);
+    for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
+        emit_batch(mask, v0, rank, b0, L.todo);
+        __syncthreads();
+        const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
+        scanned += lowest_attached_edges(row_ptr, col, acur, L.todo, cnt, L.beg, L.off, L.best,
+                                         L.wsum);
+        got += attach_batch(k, L, cnt, wbase, nb, pi, layer);
+        __syncthreads();
     }
-    blist_flush(bl, fout, fout_cnt);
-    scanned = block_sum_u64(scanned);
-    if (threadIdx.x == 0 && scanned) atomicAdd(cedges, scanned);
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+        const unsigned x = nb[threadIdx.x * WPT + j];
+        if (x && w0 + j < words) anext[w0 + j] |= x;
+    }
+    const unsigned long long g = block_sum_u64(got);
+    if (threadIdx.x == 0) {
+        if (g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
+        if (cedges && scanned) atomicAdd(my_copy(cedges), scanned);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -745,16 +885,6 @@ __global__ __launch_bounds__(kWG) void k_rev_fill(int n, const int* __restrict__
 // scans, a single-block scan of the block totals, and the offsets added).
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = kWG * kScanItems;
-
-__device__ __forceinline__ unsigned wave_incl_scan(unsigned x)
-{
-    const int lane = threadIdx.x & 63;
-    for (int off = 1; off < 64; off <<= 1) {
-        const unsigned y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    return x;
-}
 
 __global__ __launch_bounds__(kWG) void k_scan_a(int64_t len, const unsigned* __restrict__ in,
                                                 unsigned* __restrict__ out,
@@ -861,7 +991,7 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
         Q[v] = q;
     }
     act = block_sum_u64(act);
-    if (threadIdx.x == 0 && act) atomicAdd(&ctl->active, (unsigned)act);
+    if (threadIdx.x == 0 && act) atomicAdd(&my_lane(ctl).active, (unsigned)act);
 }
 
 __device__ __forceinline__ Jmp jmp_combine(Jmp q, const Jmp& r)
@@ -907,7 +1037,7 @@ __global__ __launch_bounds__(kWG) void k_val_round(int n, int s, const Jmp* __re
         }
     }
     act = block_sum_u64(act);
-    if (threadIdx.x == 0 && act) atomicAdd(active, (unsigned)act);
+    if (threadIdx.x == 0 && act) atomicAdd(my_copy(active), (unsigned)act);
 }
 
 __global__ __launch_bounds__(kWG) void k_val_final(int n, const Jmp* __restrict__ Q,
@@ -922,7 +1052,7 @@ __global__ __launch_bounds__(kWG) void k_val_final(int n, const Jmp* __restrict_
         if (hop) hop[v] = (int)(q.H & ~kHopOverflow);
         if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
     }
-    if (__ballot(bad != 0) && (threadIdx.x & 63) == 0) atomicOr(&ctl->overflow, 1u);
+    if (__ballot(bad != 0) && (threadIdx.x & 63) == 0) atomicOr(&my_lane(ctl).overflow, 1u);
 }
 
 // Cycle C listed from the source: vertex c_j (j steps after s) is H = L - j
@@ -970,7 +1100,7 @@ __global__ __launch_bounds__(kWG) void k_tie_short_walk(SweepArgs a, const WT* _
         }
     }
     found = block_sum_u64(found);
-    if (threadIdx.x == 0 && found) atomicAdd(&a.ctl->certain, found);
+    if (threadIdx.x == 0 && found) atomicAdd(&my_lane(a.ctl).certain, found);
 }
 
 // ---------------------------------------------------------------------------
@@ -1115,36 +1245,43 @@ __global__ __launch_bounds__(kWG) void k_check_policy(int n, const int* __restri
     if (__ballot(b != 0) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
 }
 
+// Thread l < kLanes clears lane l; thread 0 also the header fields.
 __global__ void k_ctl_clear(Ctl* ctl, unsigned what)
 {
-    if (threadIdx.x != 0) return;
+    const int t = threadIdx.x;
     if (what & kClrAll) {
         unsigned* p = (unsigned*)ctl;
-        for (unsigned i = 0; i < sizeof(Ctl) / sizeof(unsigned); ++i) p[i] = 0;
+        for (unsigned i = t; i < sizeof(Ctl) / sizeof(unsigned); i += blockDim.x) p[i] = 0;
+        return;
     }
-    if (what & kClrChanged) {
-        ctl->changed = 0;
-        ctl->cbroken = 0;
-        ctl->tight = 0;
-        ctl->certain = 0;
-        ctl->nondec = 0;
-        ctl->xcnt = 0;
-        ctl->scnt = 0;
-        ctl->bad = 0;
+    if (t < kLanes) {
+        CtlLane& ln = ctl->lane[t];
+        if (what & kClrChanged) {
+            ln.changed = 0;
+            ln.cbroken = 0;
+            ln.tight = 0;
+            ln.certain = 0;
+            ln.nondec = 0;
+            ln.bad = 0;
+        }
+        if (what & kClrCount) {
+            ln.active = 0;
+            ln.active2 = 0;
+            ln.got = 0;
+            ln.left = 0;
+        }
+        if (what & kClrActive2) ln.active2 = 0;
     }
-    if (what & kClrCount) {
-        ctl->ncyc = 0;
-        ctl->ucnt[0] = ctl->ucnt[1] = 0;
-        ctl->fcnt[0] = ctl->fcnt[1] = 0;
-        ctl->active = 0;
-        ctl->active2 = 0;
-    }
-    if (what & kClrAll) {
-        ctl->pedges = 0;
-        ctl->ledges = 0;
-        ctl->err = 0;
-        ctl->maxabsw = 0;
-        ctl->overflow = 0;
+    if (t == 0) {
+        if (what & kClrChanged) {
+            ctl->xcnt = 0;
+            ctl->scnt = 0;
+        }
+        if (what & kClrCount) {
+            ctl->ncyc = 0;
+            ctl->ucnt[0] = ctl->ucnt[1] = 0;
+            ctl->fcnt[0] = ctl->fcnt[1] = 0;
+        }
     }
 }
 
@@ -1284,49 +1421,63 @@ void launch_select(const int* cyc_list, const long long* wsum, const unsigned* l
 }
 
 void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, int* layer,
-                      unsigned char* onC, int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt,
+                      unsigned char* onC, unsigned* a1, unsigned* a0, Ctl* ctl, hipStream_t st)
+{
+    k_conn_init<<<stride_grid(n), kWG, 0, st>>>(n, rep, onc, s, layer, onC, a1, a0, ctl);
+}
+
+// Words per thread of the round kernels: 2 when one word per thread would
+// need more than 1024 workgroups.
+static int round_wpt(int n)
+{
+    const int64_t words = ((int64_t)n + 31) / 32;
+    return words > (int64_t)1024 * kWG ? 2 : 1;
+}
+
+static unsigned round_grid(int n, int wpt)
+{
+    const int64_t words = ((int64_t)n + 31) / 32;
+    const int64_t per = (int64_t)kWG * wpt;
+    return (unsigned)((words + per - 1) / per);
+}
+
+void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
+                      unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
                       hipStream_t st)
 {
-    const unsigned per = list_per_block(n);
-    const unsigned grid = (unsigned)(((int64_t)n + per - 1) / per);
-    k_conn_init<<<grid, kWG, 0, st>>>(n, rep, onc, s, per, layer, onC, ulist, ucnt, flist, fcnt);
+    const int wpt = round_wpt(n);
+    if (wpt == 2)
+        k_conn_pull<2><<<round_grid(n, 2), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer,
+                                                         pi, ctl, ledges);
+    else
+        k_conn_pull<1><<<round_grid(n, 1), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer,
+                                                         pi, ctl, ledges);
 }
 
-void launch_conn_pull(int k, const int* row_ptr, const int* col, const unsigned* acur,
-                      unsigned* anext, int* layer, int* pi, const int* in_list, unsigned in_cnt,
-                      int* ulist, unsigned* ucnt, int* flist, unsigned* fcnt, const int* fin,
-                      unsigned f_cnt, unsigned long long* ledges, hipStream_t st)
+void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned* acur,
+                      unsigned* anext, unsigned char* marks, unsigned long long* pedges,
+                      hipStream_t st)
 {
-    if (in_cnt == 0 && f_cnt == 0) return;
-    const unsigned per = list_per_block(in_cnt > 0 ? in_cnt : 1);
-    unsigned grid = (unsigned)(((int64_t)in_cnt + per - 1) / per);
-    if (grid < 1) grid = 1;
-    k_conn_pull<<<grid, kWG, 0, st>>>(k, row_ptr, col, acur, anext, layer, pi, in_list, in_cnt,
-                                      per, ulist, ucnt, flist, fcnt, fin, f_cnt, ledges);
-}
-
-void launch_bits_from_layer(int n, const int* layer, unsigned* a0, unsigned* a1, hipStream_t st)
-{
-    k_bits_from_layer<<<stride_grid(n), kWG, 0, st>>>(n, layer, a0, a1);
-}
-
-void launch_conn_mark(const int* rin_ptr, const int* rin, const unsigned* acur, unsigned* anext,
-                      unsigned* marks, const int* fin, unsigned f_cnt, int add_front,
-                      unsigned long long* pedges, hipStream_t st)
-{
-    if (f_cnt == 0) return;
-    constexpr int G = 8;
-    k_conn_mark<G><<<stride_grid((int64_t)f_cnt * G), kWG, 0, st>>>(
-        rin_ptr, rin, acur, anext, marks, fin, f_cnt, add_front, pedges);
+    const int wpt = round_wpt(n);
+    if (wpt == 2)
+        k_conn_mark<2><<<round_grid(n, 2), kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks,
+                                                         pedges);
+    else
+        k_conn_mark<1><<<round_grid(n, 1), kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks,
+                                                         pedges);
 }
 
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
-                       unsigned* anext, unsigned* marks, int* pi, int* layer, int* fout,
-                       unsigned* fout_cnt, unsigned long long* cedges, hipStream_t st)
+                       unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
+                       unsigned long long* cedges, hipStream_t st)
 {
-    const unsigned grid = (unsigned)(((int64_t)n + kClaimVerts - 1) / kClaimVerts);
-    k_conn_claim<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer, fout,
-                                       fout_cnt, cedges);
+    const int wpt = round_wpt(n);
+    if (wpt == 2)
+        k_conn_claim<2><<<round_grid(n, 2), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks,
+                                                          pi, layer, ctl, cedges);
+    else
+        k_conn_claim<1><<<round_grid(n, 1), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks,
+                                                          pi, layer, ctl, cedges);
 }
 
 void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsigned* tot,
@@ -1339,7 +1490,7 @@ void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsig
 }
 
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
-                      unsigned* tot, int* rin_ptr, int* rin, unsigned* marks, hipStream_t st)
+                      unsigned* tot, int* rin_ptr, int* rin, unsigned char* marks, hipStream_t st)
 {
     const int64_t len = (int64_t)n + 1;
     k_fill_u32<<<stride_grid(len), kWG, 0, st>>>(len, deg, 0u);
@@ -1350,8 +1501,8 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
     k_scan_c<<<stride_grid(len), kWG, 0, st>>>(len, (unsigned*)rin_ptr, tot);
     k_copy_u32<<<stride_grid(n), kWG, 0, st>>>(n, (const unsigned*)rin_ptr, deg);
     k_rev_fill<<<stride_grid(n), kWG, 0, st>>>(n, row_ptr, col, deg, rin);
-    const int64_t words = ((int64_t)n + 31) / 32;
-    k_fill_u32<<<stride_grid(words), kWG, 0, st>>>(words, marks, 0u);
+    const int64_t words = ((int64_t)n + 3) / 4;
+    k_fill_u32<<<stride_grid(words), kWG, 0, st>>>(words, (unsigned*)marks, 0u);
 }
 
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
@@ -1488,6 +1639,20 @@ __global__ void k_post(const unsigned* __restrict__ src, int words, unsigned* ds
     }
 }
 
+// Folds the lanes of a control block into a snapshot and publishes it like
+// k_post.
+__global__ void k_post_ctl(const Ctl* __restrict__ c, CtlView* dst, unsigned* seq_slot,
+                           unsigned seq)
+{
+    if (threadIdx.x == 0) {
+        CtlView v;
+        fold_lanes(*c, v);
+        *dst = v;
+        __threadfence_system();
+        __hip_atomic_store(seq_slot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 namespace {
 struct Mailbox {
     unsigned* host = nullptr;   // kPostWords data words, then the sequence word
@@ -1497,38 +1662,56 @@ struct Mailbox {
     bool init = false;
 };
 thread_local Mailbox tl_mb;
+
+Mailbox& mailbox()
+{
+    Mailbox& mb = tl_mb;
+    if (mb.init) return mb;
+    mb.init = true;
+    const char* env = getenv("OCM_HOST_SYNC");
+    mb.stream_mode = env && env[0] == 's';
+    if (mb.stream_mode) return mb;
+    void* h = nullptr;
+    hipError_t e = hipHostMalloc(&h, 4 * (kPostWords + 16),
+                                 hipHostMallocMapped | hipHostMallocCoherent |
+                                     hipHostMallocPortable);
+    void* d = nullptr;
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&d, h, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        mb.stream_mode = true;
+        return mb;
+    }
+    // kept for the life of the process (a few hundred bytes per thread)
+    mb.host = (unsigned*)h;
+    mb.dev = (unsigned*)d;
+    __atomic_store_n(&mb.host[kPostWords], 0u, __ATOMIC_RELEASE);
+    return mb;
+}
+
+// Spins until the post with sequence number `want` lands.
+hipError_t wait_post(const Mailbox& mb, unsigned want, hipStream_t st)
+{
+    const unsigned* seq = mb.host + kPostWords;
+    for (uint64_t i = 1;; ++i) {
+        if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == want) return hipSuccess;
+        if ((i & 1023) == 0) {
+            // the stream may have failed or finished without the post landing
+            const hipError_t e = hipStreamQuery(st);
+            if (e == hipSuccess)
+                return __atomic_load_n(seq, __ATOMIC_ACQUIRE) == want ? hipSuccess
+                                                                      : hipErrorUnknown;
+            if (e != hipErrorNotReady) return e;
+        }
+        __builtin_ia32_pause();
+    }
+}
+
 }  // namespace
 
 hipError_t host_read(const void* dsrc, void* hdst, size_t bytes, hipStream_t st)
 {
-    Mailbox& mb = tl_mb;
-    if (!mb.init) {
-        mb.init = true;
-        const char* env = getenv("OCM_HOST_SYNC");
-        mb.stream_mode = env && env[0] == 's';
-        if (!mb.stream_mode) {
-            void* h = nullptr;
-            hipError_t e = hipHostMalloc(&h, 4 * (kPostWords + 16),
-                                         hipHostMallocMapped | hipHostMallocCoherent |
-                                             hipHostMallocPortable);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                mb.stream_mode = true;
-            } else {
-                void* d = nullptr;
-                e = hipHostGetDevicePointer(&d, h, 0);
-                if (e != hipSuccess) {
-                    (void)hipGetLastError();
-                    mb.stream_mode = true;
-                } else {
-                    // kept for the life of the thread's process (a few hundred bytes)
-                    mb.host = (unsigned*)h;
-                    mb.dev = (unsigned*)d;
-                    __atomic_store_n(&mb.host[kPostWords], 0u, __ATOMIC_RELEASE);
-                }
-            }
-        }
-    }
+    Mailbox& mb = mailbox();
     if (mb.stream_mode || bytes > 4 * kPostWords || (bytes & 3) != 0) {
         hipError_t e = hipMemcpyAsync(hdst, dsrc, bytes, hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return e;
@@ -1538,22 +1721,32 @@ hipError_t host_read(const void* dsrc, void* hdst, size_t bytes, hipStream_t st)
     k_post<<<1, 64, 0, st>>>((const unsigned*)dsrc, (int)(bytes / 4), mb.dev,
                              mb.dev + kPostWords, want);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = wait_post(mb, want, st);
     if (e != hipSuccess) return e;
-    const unsigned* seq = mb.host + kPostWords;
-    for (uint64_t i = 1;; ++i) {
-        if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == want) break;
-        if ((i & 1023) == 0) {
-            // the stream may have failed or finished without the post landing
-            e = hipStreamQuery(st);
-            if (e == hipSuccess) {
-                if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == want) break;
-                return hipErrorUnknown;
-            }
-            if (e != hipErrorNotReady) return e;
-        }
-        __builtin_ia32_pause();
-    }
     memcpy(hdst, mb.host, bytes);
+    return hipSuccess;
+}
+
+hipError_t host_read_ctl(const Ctl* ctl, CtlView* out, hipStream_t st)
+{
+    static_assert(sizeof(CtlView) <= 4 * kPostWords && sizeof(CtlView) % 4 == 0,
+                  "the snapshot fits the mailbox");
+    Mailbox& mb = mailbox();
+    if (mb.stream_mode) {
+        Ctl* h = (Ctl*)malloc(sizeof(Ctl));
+        if (!h) return hipErrorOutOfMemory;
+        hipError_t e = hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) fold_lanes(*h, *out);
+        free(h);
+        return e;
+    }
+    const unsigned want = ++mb.seq;
+    k_post_ctl<<<1, 64, 0, st>>>(ctl, (CtlView*)mb.dev, mb.dev + kPostWords, want);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = wait_post(mb, want, st);
+    if (e != hipSuccess) return e;
+    memcpy(out, mb.host, sizeof(CtlView));
     return hipSuccess;
 }
 

@@ -66,14 +66,13 @@ struct Ws {
     unsigned char* onc;  // on a policy-graph cycle
     unsigned char* onC;  // on the chosen cycle C
     int* layer;          // connect round of each vertex
-    int* list[2];        // connect: unattached vertices
-    int* flist[2];       // connect: frontier (last attached layer)
+    int* list[2];        // tie check: special-vertex list and jump pointers
     unsigned* rdeg;      // reverse CSR: in-degree, then fill cursor (n+1)
     unsigned* stot;      // prefix-sum block totals
     int* rin_ptr;        // reverse CSR offsets (n+1)
     int* rin;            // reverse CSR entries: the tail of each in-edge (m)
     unsigned* abits[2];  // connect: attached-vertex bitmaps (alternating by round)
-    unsigned* marks;     // push rounds: marked vertices (bitmap)
+    unsigned char* marks;  // push rounds: marked vertices (bytes)
     unsigned char* touched;  // tie check: special-vertex flags
     void* sel;           // select: per-block best candidates
     int* xs;             // tie check: tight non-policy edges (tail), xcap entries
@@ -109,8 +108,6 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.layer = (int*)take(4 * N);
     w.list[0] = (int*)take(4 * N);
     w.list[1] = (int*)take(4 * N);
-    w.flist[0] = (int*)take(4 * N);
-    w.flist[1] = (int*)take(4 * N);
     const size_t M = (size_t)m;
     w.rdeg = (unsigned*)take(4 * (N + 1));
     w.stot = (unsigned*)take(4 * ((N + 1) / 2048 + 2));
@@ -118,7 +115,7 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.rin = (int*)take(4 * M);
     w.abits[0] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.abits[1] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
-    w.marks = (unsigned*)take(4 * ((N + 31) / 32 + 1));
+    w.marks = (unsigned char*)take(N + 16);
     w.touched = (unsigned char*)take(N + 16);
     w.sel = take(32 * ocm::kSelectParts);
     w.xcap = (unsigned)(m < kTieListCap ? m : kTieListCap);
@@ -185,7 +182,7 @@ struct Ctx {
     int neg;
     hipStream_t st;
     Ws ws;
-    Ctl h;               // host copy of the control block
+    ocm::CtlView h;      // host snapshot of the control block
     Prof prof;
     int G;               // lanes per vertex in the sweep
     int sw;              // bytes per weight
@@ -205,7 +202,7 @@ constexpr unsigned kPushMinUnattached = 1u << 16;
 
 ocm_status read_ctl(Ctx& c)
 {
-    HIP_TRY(ocm::host_read(c.ws.ctl, &c.h, sizeof(Ctl), c.st));
+    HIP_TRY(ocm::host_read_ctl(c.ws.ctl, &c.h, c.st));
     return OCM_OK;
 }
 
@@ -344,7 +341,7 @@ ocm_status phase_cycles(Ctx& c, const int* pi, int* rep, unsigned char* onc)
     c.prof.begin(OCM_K_CYCLES);
     if (stop_test) ocm::launch_fill_u32((unsigned*)c.ws.layer, ((int64_t)c.n * 2 + 3) / 4, 0u, c.st);
     ocm::launch_pj_init(c.n, c.col, pi, c.ws.succ, P0, onc, stop_test ? tag[0] : nullptr,
-                        stop_test ? c.ws.ctl->pjc : nullptr, c.st);
+                        stop_test ? c.ws.ctl->lane[0].pjc : nullptr, c.st);
     c.prof.end();
     // pi, col[pi], succ, packed entry, on-cycle (+ tag clear and mark)
     c.prof.bytes(OCM_K_CYCLES, 21.0 * n + (stop_test ? 3.0 * n : 0.0));
@@ -356,7 +353,7 @@ ocm_status phase_cycles(Ctx& c, const int* pi, int* rep, unsigned char* onc)
         c.prof.begin(OCM_K_CYCLES);
         if (stop_test)
             ocm::launch_pj_round_tagged(c.n, r, P0, P1, tag[(r - 1) & 1], tag[r & 1],
-                                        c.ws.ctl->pjc, c.st);
+                                        c.ws.ctl->lane[0].pjc, c.st);
         else
             ocm::launch_pj_round(c.n, P0, P1, c.st);
         c.prof.end();
@@ -405,29 +402,27 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
     Ws& w = c.ws;
     ocm::launch_ctl_clear(w.ctl, ocm::kClrCount, c.st);
     c.prof.begin(OCM_K_CONN_PULL);
-    ocm::launch_conn_init(c.n, rep, onc, s, layer, onC, w.list[0], &w.ctl->ucnt[0], w.flist[0],
-                          &w.ctl->fcnt[0], c.st);
+    // round 1 reads abits[1] (C's component) and completes abits[0]
+    ocm::launch_conn_init(c.n, rep, onc, s, layer, onC, w.abits[1], w.abits[0], w.ctl, c.st);
     c.prof.end();
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
-    c.prof.bytes(OCM_K_CONN_PULL, 10.0 * c.n + 4.0 * ((double)c.h.ucnt[0] + c.h.fcnt[0]));
+    // rep, layer and on-C flags per vertex; the two bitmaps
+    c.prof.bytes(OCM_K_CONN_PULL, 6.25 * c.n);
     unsigned long long pe0 = c.h.pedges, le0 = c.h.ledges;
-    unsigned left = c.h.ucnt[0], ulen = left, front = c.h.fcnt[0];
-    if (left > 0) {
-        c.prof.begin(OCM_K_CONN_PULL);
-        ocm::launch_bits_from_layer(c.n, layer, w.abits[0], w.abits[1], c.st);
-        c.prof.end();
-        c.prof.bytes(OCM_K_CONN_PULL, 4.25 * c.n);
-    }
-    int ua = 0, fa = 0, k = 0;
+    unsigned left = c.h.left, front = c.h.got;
+    const double bitmaps = 0.125 * c.n;   // one attached-vertex bitmap
+    unsigned long long* pedges = &w.ctl->lane[0].pedges;
+    // the scanned-edge counts only feed the profile's byte figures
+    unsigned long long* ledges = c.prof.out ? &w.ctl->lane[0].ledges : nullptr;
+    int k = 0;
     ocm_status rc = OCM_OK;
     while (left > 0) {
         ++k;
-        const int ub = ua ^ 1, fb = fa ^ 1;
         bool push = false;
         if (c.connect_mode == 2) push = front > 0;
         else if (c.connect_mode == 0)
-            push = left >= kPushMinUnattached && (uint64_t)front * 4 < left;
+            push = left >= kPushMinUnattached && (uint64_t)front * 2 < left;
         if (push && !c.rev_built) {
             c.prof.begin(OCM_K_REVERSE);
             ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr, w.rin,
@@ -435,52 +430,47 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
             c.prof.end();
             // count: col + counter per edge; fill, scan and copy of the
             // counters; fill: row_ptr, col, cursor and the 4-byte tail per
-            // edge; mark bitmap reset
-            c.prof.bytes(OCM_K_REVERSE, 20.0 * c.m + 28.125 * c.n);
+            // edge; mark reset
+            c.prof.bytes(OCM_K_REVERSE, 20.0 * c.m + 29.0 * c.n);
             HIP_TRY(hipGetLastError());
             c.rev_built = true;
         }
         // round k reads abits[k&1] and completes abits[(k+1)&1]
         const unsigned* acur = w.abits[k & 1];
         unsigned* anext = w.abits[(k + 1) & 1];
-        const unsigned fadd = k > 1 ? front : 0u;   // round 1: the frontier is in both already
-        ocm::launch_zero2(&w.ctl->ucnt[ub], &w.ctl->fcnt[fb], c.st);
+        ocm::launch_ctl_clear(w.ctl, ocm::kClrCount, c.st);
         if (push) {
             c.prof.begin(OCM_K_CONN_MARK);
-            ocm::launch_conn_mark(w.rin_ptr, w.rin, acur, anext, w.marks, w.flist[fa], front,
-                                  k > 1, &w.ctl->pedges, c.st);
+            ocm::launch_conn_mark(c.n, w.rin_ptr, w.rin, acur, anext, w.marks, pedges, c.st);
             c.prof.end();
             c.prof.begin(OCM_K_CONN_CLAIM);
             ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, w.marks, pi, layer,
-                                   w.flist[fb], &w.ctl->fcnt[fb], &w.ctl->ledges, c.st);
+                                   w.ctl, ledges, c.st);
             c.prof.end();
             c.push_frontier += front;
         } else {
             c.prof.begin(OCM_K_CONN_PULL);
-            ocm::launch_conn_pull(k, c.row_ptr, c.col, acur, anext, layer, pi, w.list[ua], ulen,
-                                  w.list[ub], &w.ctl->ucnt[ub], w.flist[fb], &w.ctl->fcnt[fb],
-                                  w.flist[fa], fadd, &w.ctl->ledges, c.st);
+            ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, layer, pi, w.ctl, ledges,
+                                  c.st);
             c.prof.end();
         }
         HIP_TRY(hipGetLastError());
         OCM_TRY(read_ctl(c));
-        const unsigned got = c.h.fcnt[fb];
+        const unsigned got = c.h.got;
         const double S = (double)(c.h.ledges - le0);
         if (push) {
-            // mark: frontier entry, offsets and its bit; per in-edge the
-            // 4-byte tail and its bit, and a mark bit per attached vertex;
-            // claim: the mark words, then per attached vertex its offsets,
-            // pi, layer, list entry and bit, and per scanned out-edge col and
-            // a bit
+            // mark: both bitmaps, then per frontier vertex its offsets and
+            // per in-edge the 4-byte tail and its bit, and a mark byte per
+            // attached vertex; claim: the mark bytes, then per attached vertex
+            // its offsets, pi and layer, and per scanned out-edge col and a
+            // bit; the new bitmap words
             const double E = (double)(c.h.pedges - pe0);
-            c.prof.bytes(OCM_K_CONN_MARK, 12.125 * front + 4.125 * E + 0.125 * got);
-            c.prof.bytes(OCM_K_CONN_CLAIM, 0.25 * c.n + 20.125 * got + 4.125 * S);
+            c.prof.bytes(OCM_K_CONN_MARK, 2.0 * bitmaps + 8.0 * front + 4.125 * E + got);
+            c.prof.bytes(OCM_K_CONN_CLAIM, (double)c.n + 16.0 * got + 4.125 * S + bitmaps);
         } else {
-            // list entry, offsets and own bit per listed vertex; col and a bit
-            // per scanned edge; pi, layer, list entries and bits of the
-            // outcome; the previous frontier's bits
-            c.prof.bytes(OCM_K_CONN_PULL, 12.125 * ulen + 4.125 * S + 12.125 * got +
-                                              4.0 * c.h.ucnt[ub] + 4.125 * fadd);
+            // both bitmaps; per unattached vertex its offsets, per scanned
+            // out-edge col and a bit; pi and layer of the attached
+            c.prof.bytes(OCM_K_CONN_PULL, 3.0 * bitmaps + 8.0 * left + 4.125 * S + 8.0 * got);
         }
         pe0 = c.h.pedges;
         le0 = c.h.ledges;
@@ -488,15 +478,8 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
             rc = fail(OCM_E_NOT_STRONGLY_CONNECTED, "some vertex cannot reach the chosen cycle");
             break;
         }
-        if (push) {
-            left -= got;
-        } else {
-            ulen = c.h.ucnt[ub];
-            left = ulen;
-            ua = ub;
-        }
+        left -= got;
         front = got;
-        fa = fb;
     }
     if (rounds) *rounds = k;
     c.connect_rounds += k;
@@ -528,9 +511,9 @@ ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, 
         ++k;
         ++c.value_rounds;
         const int b = a ^ 1;
-        HIP_TRY(hipMemsetAsync(&c.ws.ctl->active2, 0, sizeof(unsigned), c.st));
+        ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrActive2, c.st);
         c.prof.begin(ph);
-        ocm::launch_val_round(c.n, s, c.ws.Q[a], c.ws.Q[b], &c.ws.ctl->active2, c.st);
+        ocm::launch_val_round(c.n, s, c.ws.Q[a], c.ws.Q[b], &c.ws.ctl->lane[0].active2, c.st);
         c.prof.end();
         c.prof.bytes(ph, 32.0 * c.n + 16.0 * act);   // own + new entry; gather if unfinished
         HIP_TRY(hipGetLastError());
@@ -724,7 +707,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     if (warm) {
         // warm start: the given policy replaces the first sweep
         ocm::launch_ctl_clear(w.ctl, ocm::kClrChanged, c.st);
-        ocm::launch_check_policy(c.n, c.row_ptr, o.init_policy, &w.ctl->bad, c.st);
+        ocm::launch_check_policy(c.n, c.row_ptr, o.init_policy, &w.ctl->lane[0].bad, c.st);
         HIP_TRY(hipGetLastError());
         OCM_TRY(read_ctl(c));
         if (c.h.bad) return fail(OCM_E_INVALID_ARG, "init_policy picks an edge of another vertex");
