@@ -846,6 +846,7 @@ struct BWs {
     unsigned* stot;
     int* rin_ptr;
     int* rin;
+    void* rscratch;
     unsigned* abits[2];
     unsigned char* marks;
     unsigned* bad;
@@ -910,6 +911,7 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m)
     w.stot = (unsigned*)take(4 * ((N + 1) / 2048 + 2));
     w.rin_ptr = (int*)take(4 * (N + 1));
     w.rin = (int*)take(4 * M);
+    w.rscratch = take(ocm::rev_scratch_bytes(n, m));
     w.abits[0] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.abits[1] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.marks = (unsigned char*)take(N + 16);
@@ -1169,7 +1171,7 @@ ocm_status host_connect(BCtx& c)
         const bool push = left >= (1u << 16) && (uint64_t)front * 2 < left;
         if (push && !c.rev_built) {
             ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, ws.rdeg, ws.stot, ws.rin_ptr, ws.rin,
-                                  ws.marks, c.st);
+                                  ws.marks, ws.rscratch, c.st);
             c.rev_built = true;
         }
         const unsigned* acur = ws.abits[k & 1];

@@ -185,8 +185,18 @@ void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned*
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                        unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
                        unsigned long long* cedges, hipStream_t st);
+// Reverse CSR (rin_ptr, rin) of the graph.  With `scratch` of
+// rev_scratch_bytes(n, m) bytes (0 when the plan does not apply) the build
+// is partitioned by head bucket; otherwise it counts and fills with global
+// atomics (deg and tot are its counters).  Also clears the mark bytes.
+struct RevPlan {
+    int64_t buckets, chunk, nblk, hist_len;
+    bool partition;
+};
+RevPlan rev_plan(int64_t n, int64_t m);
+size_t rev_scratch_bytes(int64_t n, int64_t m);
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
-                      unsigned* tot, int* rin_ptr, int* rin, unsigned char* marks,
+                      unsigned* tot, int* rin_ptr, int* rin, unsigned char* marks, void* scratch,
                       hipStream_t st);
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
                      int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl, hipStream_t st);

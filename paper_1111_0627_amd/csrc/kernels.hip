@@ -881,6 +881,168 @@ __global__ __launch_bounds__(kWG) void k_rev_fill(int n, const int* __restrict__
     }
 }
 
+// Partitioned build (no global atomics): edges are binned by head bucket
+// (8192 heads) in LDS, scattered bucket by bucket as (head, tail) pairs,
+// and each bucket then counts and places its pairs in LDS.  The order of a
+// vertex's in-edges is arbitrary; the rounds only test membership.
+constexpr int kRevBucketBits = 13;
+constexpr int kRevBucket = 1 << kRevBucketBits;
+constexpr int kRevMaxBuckets = 8192;
+
+__global__ __launch_bounds__(kWG) void k_rev_hist(int64_t m, const int* __restrict__ col,
+                                                  int64_t chunk, int nblk, int B,
+                                                  unsigned* __restrict__ hist)
+{
+    __shared__ unsigned h[kRevMaxBuckets];
+    for (int i = threadIdx.x; i < B; i += kWG) h[i] = 0;
+    __syncthreads();
+    const int64_t e0 = (int64_t)blockIdx.x * chunk;
+    const int64_t e1 = e0 + chunk < m ? e0 + chunk : m;
+    constexpr int U = 8;   // independent loads in flight per thread
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += U * kWG) {
+        int v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = e + j * kWG < e1 ? col[e + j * kWG] : -1;
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (v[j] >= 0) atomicAdd(&h[v[j] >> kRevBucketBits], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < B; i += kWG) hist[(int64_t)i * nblk + blockIdx.x] = h[i];
+}
+
+// last u in [0, n) with row_ptr[u] <= e
+__device__ __forceinline__ int source_of(const int* __restrict__ row_ptr, int n, int64_t e)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_ptr[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kWG) void k_rev_scatter(int n, const int* __restrict__ row_ptr,
+                                                     const int* __restrict__ col, int64_t m,
+                                                     int64_t chunk, int nblk, int B,
+                                                     const unsigned* __restrict__ hoff,
+                                                     int2* __restrict__ pairs)
+{
+    __shared__ unsigned cur[kRevMaxBuckets];
+    __shared__ int su[2];
+    const int64_t e0 = (int64_t)blockIdx.x * chunk;
+    const int64_t e1 = e0 + chunk < m ? e0 + chunk : m;
+    for (int i = threadIdx.x; i < B; i += kWG) cur[i] = hoff[(int64_t)i * nblk + blockIdx.x];
+    if (threadIdx.x == 0) su[0] = source_of(row_ptr, n, e0);
+    if (threadIdx.x == 64) su[1] = source_of(row_ptr, n, e1 - 1);
+    __syncthreads();
+    // G lanes per source, U sources per group in flight
+    constexpr int G = 8, U = 4;
+    const int lane = threadIdx.x & (G - 1);
+    constexpr int kGroups = kWG / G;
+    for (int ub = su[0] + threadIdx.x / G; ub <= su[1]; ub += U * kGroups) {
+        int lo[U], hi[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int u = ub + j * kGroups;
+            lo[j] = hi[j] = 0;
+            if (u <= su[1]) {
+                const int a = row_ptr[u], b = row_ptr[u + 1];
+                lo[j] = a > e0 ? a : (int)e0;
+                hi[j] = b < e1 ? b : (int)e1;
+            }
+        }
+        int v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = lo[j] + lane < hi[j] ? col[lo[j] + lane] : -1;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int u = ub + j * kGroups;
+            if (v[j] >= 0) {
+                const unsigned pos = atomicAdd(&cur[v[j] >> kRevBucketBits], 1u);
+                pairs[pos] = make_int2(v[j], u);
+            }
+            for (int e = lo[j] + lane + G; e < hi[j]; e += G) {   // out-degree above G
+                const int x = col[e];
+                const unsigned pos = atomicAdd(&cur[x >> kRevBucketBits], 1u);
+                pairs[pos] = make_int2(x, u);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_rev_place(int n, int64_t m, int B, int nblk,
+                                                   const unsigned* __restrict__ hoff,
+                                                   const int2* __restrict__ pairs,
+                                                   int* __restrict__ rin_ptr, int* __restrict__ rin)
+{
+    __shared__ unsigned cnt[kRevBucket];
+    __shared__ unsigned wsum[kWG / 64];
+    const int bkt = blockIdx.x;
+    const int64_t lo = (int64_t)bkt << kRevBucketBits;
+    const int64_t hi = lo + kRevBucket < n ? lo + kRevBucket : n;
+    const int64_t start = hoff[(int64_t)bkt * nblk];
+    const int64_t end = bkt + 1 < B ? (int64_t)hoff[(int64_t)(bkt + 1) * nblk] : m;
+    for (int i = threadIdx.x; i < kRevBucket; i += kWG) cnt[i] = 0;
+    __syncthreads();
+    constexpr int U = 8;   // independent loads in flight per thread
+    for (int64_t p = start + threadIdx.x; p < end; p += U * kWG) {
+        int h[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) h[j] = p + j * kWG < end ? pairs[p + j * kWG].x : -1;
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (h[j] >= 0) atomicAdd(&cnt[h[j] - lo], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of cnt: each thread owns a run of kRevBucket / kWG heads
+    constexpr int kRun = kRevBucket / kWG;
+    const int r0 = threadIdx.x * kRun;
+    unsigned run = 0;
+    for (int j = 0; j < kRun; ++j) run += cnt[r0 + j];
+    unsigned total = 0;
+    unsigned acc = block_rank(run, wsum, &total);
+    for (int j = 0; j < kRun; ++j) {
+        const unsigned d = cnt[r0 + j];
+        cnt[r0 + j] = acc;
+        acc += d;
+    }
+    __syncthreads();
+    for (int64_t v = lo + threadIdx.x; v < hi; v += kWG) rin_ptr[v] = (int)(start + cnt[v - lo]);
+    if (bkt == B - 1 && threadIdx.x == 0) rin_ptr[n] = (int)m;
+    __syncthreads();
+    for (int64_t p = start + threadIdx.x; p < end; p += U * kWG) {
+        int2 q[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) q[j] = p + j * kWG < end ? pairs[p + j * kWG] : make_int2(-1, 0);
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (q[j].x >= 0) rin[start + atomicAdd(&cnt[q[j].x - lo], 1u)] = q[j].y;
+    }
+}
+
+RevPlan rev_plan(int64_t n, int64_t m)
+{
+    RevPlan p;
+    p.buckets = (n + kRevBucket - 1) / kRevBucket;
+    int64_t chunk = 65536;
+    while ((m + chunk - 1) / chunk > 2048) chunk <<= 1;
+    p.chunk = chunk;
+    p.nblk = (m + chunk - 1) / chunk;
+    p.hist_len = p.buckets * p.nblk;
+    p.partition = p.buckets <= kRevMaxBuckets && m < (int64_t(1) << 31);
+    return p;
+}
+
+size_t rev_scratch_bytes(int64_t n, int64_t m)
+{
+    const RevPlan p = rev_plan(n, m);
+    if (!p.partition) return 0;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    return al(8 * (size_t)m) + 2 * al(4 * (size_t)p.hist_len) + al(4 * ((size_t)p.hist_len / 2048 + 2));
+}
+
 // Exclusive prefix sum of len unsigned values (three launches: per-block
 // scans, a single-block scan of the block totals, and the offsets added).
 constexpr int kScanItems = 8;
@@ -1490,17 +1652,35 @@ void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsig
 }
 
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
-                      unsigned* tot, int* rin_ptr, int* rin, unsigned char* marks, hipStream_t st)
+                      unsigned* tot, int* rin_ptr, int* rin, unsigned char* marks, void* scratch,
+                      hipStream_t st)
 {
-    const int64_t len = (int64_t)n + 1;
-    k_fill_u32<<<stride_grid(len), kWG, 0, st>>>(len, deg, 0u);
-    k_rev_count<<<stride_grid(m), kWG, 0, st>>>(n, row_ptr, col, deg);
-    const unsigned nb = (unsigned)((len + kScanBlock - 1) / kScanBlock);
-    k_scan_a<<<nb, kWG, 0, st>>>(len, deg, (unsigned*)rin_ptr, tot);
-    k_scan_b<<<1, 1024, 0, st>>>(nb, tot);
-    k_scan_c<<<stride_grid(len), kWG, 0, st>>>(len, (unsigned*)rin_ptr, tot);
-    k_copy_u32<<<stride_grid(n), kWG, 0, st>>>(n, (const unsigned*)rin_ptr, deg);
-    k_rev_fill<<<stride_grid(n), kWG, 0, st>>>(n, row_ptr, col, deg, rin);
+    const RevPlan p = rev_plan(n, m);
+    if (p.partition && scratch) {
+        auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+        char* sp = (char*)scratch;
+        int2* pairs = (int2*)sp;
+        unsigned* hist = (unsigned*)(sp + al(8 * (size_t)m));
+        unsigned* hoff = (unsigned*)((char*)hist + al(4 * (size_t)p.hist_len));
+        unsigned* htot = (unsigned*)((char*)hoff + al(4 * (size_t)p.hist_len));
+        k_rev_hist<<<(unsigned)p.nblk, kWG, 0, st>>>(m, col, p.chunk, (int)p.nblk, (int)p.buckets,
+                                                     hist);
+        launch_exclusive_scan(p.hist_len, hist, hoff, htot, st);
+        k_rev_scatter<<<(unsigned)p.nblk, kWG, 0, st>>>(n, row_ptr, col, m, p.chunk, (int)p.nblk,
+                                                        (int)p.buckets, hoff, pairs);
+        k_rev_place<<<(unsigned)p.buckets, kWG, 0, st>>>(n, m, (int)p.buckets, (int)p.nblk, hoff,
+                                                         pairs, rin_ptr, rin);
+    } else {
+        const int64_t len = (int64_t)n + 1;
+        k_fill_u32<<<stride_grid(len), kWG, 0, st>>>(len, deg, 0u);
+        k_rev_count<<<stride_grid(m), kWG, 0, st>>>(n, row_ptr, col, deg);
+        const unsigned nb = (unsigned)((len + kScanBlock - 1) / kScanBlock);
+        k_scan_a<<<nb, kWG, 0, st>>>(len, deg, (unsigned*)rin_ptr, tot);
+        k_scan_b<<<1, 1024, 0, st>>>(nb, tot);
+        k_scan_c<<<stride_grid(len), kWG, 0, st>>>(len, (unsigned*)rin_ptr, tot);
+        k_copy_u32<<<stride_grid(n), kWG, 0, st>>>(n, (const unsigned*)rin_ptr, deg);
+        k_rev_fill<<<stride_grid(n), kWG, 0, st>>>(n, row_ptr, col, deg, rin);
+    }
     const int64_t words = ((int64_t)n + 3) / 4;
     k_fill_u32<<<stride_grid(words), kWG, 0, st>>>(words, (unsigned*)marks, 0u);
 }

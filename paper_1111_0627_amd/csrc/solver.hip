@@ -71,6 +71,7 @@ struct Ws {
     unsigned* stot;      // prefix-sum block totals
     int* rin_ptr;        // reverse CSR offsets (n+1)
     int* rin;            // reverse CSR entries: the tail of each in-edge (m)
+    void* rscratch;      // reverse CSR build: partition scratch (pairs and histograms)
     unsigned* abits[2];  // connect: attached-vertex bitmaps (alternating by round)
     unsigned char* marks;  // push rounds: marked vertices (bytes)
     unsigned char* touched;  // tie check: special-vertex flags
@@ -113,6 +114,7 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.stot = (unsigned*)take(4 * ((N + 1) / 2048 + 2));
     w.rin_ptr = (int*)take(4 * (N + 1));
     w.rin = (int*)take(4 * M);
+    w.rscratch = take(ocm::rev_scratch_bytes(n, m));
     w.abits[0] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.abits[1] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.marks = (unsigned char*)take(N + 16);
@@ -426,7 +428,7 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
         if (push && !c.rev_built) {
             c.prof.begin(OCM_K_REVERSE);
             ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr, w.rin,
-                                  w.marks, c.st);
+                                  w.marks, w.rscratch, c.st);
             c.prof.end();
             // count: col + counter per edge; fill, scan and copy of the
             // counters; fill: row_ptr, col, cursor and the 4-byte tail per
