@@ -500,7 +500,7 @@ __global__ __launch_bounds__(kWG) void k_select_final(const Cand* __restrict__ p
 // words, i.e. 32 or 64 vertices, per thread), so one pass over its span has
 // a single load per thread; the items it finds (frontier, marked or
 // unattached vertices) are processed in LDS batches of kBatch.
-constexpr int kBatch = 2048;
+constexpr int kBatch = 1024;
 
 __device__ __forceinline__ bool attached(const unsigned* __restrict__ abits, int v)
 {
@@ -893,7 +893,7 @@ __global__ __launch_bounds__(kWG) void k_rev_hist(int64_t m, const int* __restri
                                                   int64_t chunk, int nblk, int B,
                                                   unsigned* __restrict__ hist)
 {
-    __shared__ unsigned h[kRevMaxBuckets];
+    extern __shared__ unsigned h[];   // B counters
     for (int i = threadIdx.x; i < B; i += kWG) h[i] = 0;
     __syncthreads();
     const int64_t e0 = (int64_t)blockIdx.x * chunk;
@@ -929,7 +929,7 @@ __global__ __launch_bounds__(kWG) void k_rev_scatter(int n, const int* __restric
                                                      const unsigned* __restrict__ hoff,
                                                      int2* __restrict__ pairs)
 {
-    __shared__ unsigned cur[kRevMaxBuckets];
+    extern __shared__ unsigned cur[];   // B cursors
     __shared__ int su[2];
     const int64_t e0 = (int64_t)blockIdx.x * chunk;
     const int64_t e1 = e0 + chunk < m ? e0 + chunk : m;
@@ -1663,11 +1663,12 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
         unsigned* hist = (unsigned*)(sp + al(8 * (size_t)m));
         unsigned* hoff = (unsigned*)((char*)hist + al(4 * (size_t)p.hist_len));
         unsigned* htot = (unsigned*)((char*)hoff + al(4 * (size_t)p.hist_len));
-        k_rev_hist<<<(unsigned)p.nblk, kWG, 0, st>>>(m, col, p.chunk, (int)p.nblk, (int)p.buckets,
-                                                     hist);
+        const size_t lds = 4 * (size_t)p.buckets;
+        k_rev_hist<<<(unsigned)p.nblk, kWG, lds, st>>>(m, col, p.chunk, (int)p.nblk,
+                                                       (int)p.buckets, hist);
         launch_exclusive_scan(p.hist_len, hist, hoff, htot, st);
-        k_rev_scatter<<<(unsigned)p.nblk, kWG, 0, st>>>(n, row_ptr, col, m, p.chunk, (int)p.nblk,
-                                                        (int)p.buckets, hoff, pairs);
+        k_rev_scatter<<<(unsigned)p.nblk, kWG, lds, st>>>(n, row_ptr, col, m, p.chunk,
+                                                          (int)p.nblk, (int)p.buckets, hoff, pairs);
         k_rev_place<<<(unsigned)p.buckets, kWG, 0, st>>>(n, m, (int)p.buckets, (int)p.nblk, hoff,
                                                          pairs, rin_ptr, rin);
     } else {
@@ -1821,12 +1822,61 @@ __global__ void k_post(const unsigned* __restrict__ src, int words, unsigned* ds
 
 // Folds the lanes of a control block into a snapshot and publishes it like
 // k_post.
+// lanes 0..kLanes-1 of the wave each hold one copy; fold over them
+__device__ __forceinline__ unsigned long long lane_sum(unsigned long long x)
+{
+    for (int o = kLanes / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kLanes);
+    return x;
+}
+__device__ __forceinline__ unsigned long long lane_max(unsigned long long x)
+{
+    for (int o = kLanes / 2; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(x, o, kLanes);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+__device__ __forceinline__ unsigned lane_or(unsigned x)
+{
+    for (int o = kLanes / 2; o > 0; o >>= 1) x |= __shfl_xor(x, o, kLanes);
+    return x;
+}
+
 __global__ void k_post_ctl(const Ctl* __restrict__ c, CtlView* dst, unsigned* seq_slot,
                            unsigned seq)
 {
+    // one wave; thread l < kLanes loads lane l (the others load lane 0 and
+    // take no part in the result)
+    const int l = threadIdx.x < kLanes ? threadIdx.x : 0;
+    const CtlLane& ln = c->lane[l];
+    CtlView v;
+    v.changed = lane_sum(ln.changed);
+    v.tight = lane_sum(ln.tight);
+    v.certain = lane_sum(ln.certain);
+    v.nondec = lane_sum(ln.nondec);
+    v.pedges = lane_sum(ln.pedges);
+    v.ledges = lane_sum(ln.ledges);
+    v.maxabsw = lane_max(ln.maxabsw);
+    v.active = (unsigned)lane_sum(ln.active);
+    v.active2 = (unsigned)lane_sum(ln.active2);
+    v.got = (unsigned)lane_sum(ln.got);
+    v.left = (unsigned)lane_sum(ln.left);
+    v.err = lane_or(ln.err);
+    v.cbroken = lane_or(ln.cbroken);
+    v.overflow = lane_or(ln.overflow);
+    v.bad = lane_or(ln.bad);
+    for (int j = 0; j < 4; ++j) v.pjc[j] = (unsigned)lane_sum(ln.pjc[j]);
     if (threadIdx.x == 0) {
-        CtlView v;
-        fold_lanes(*c, v);
+        v.W = c->W;
+        v.L = c->L;
+        v.s = c->s;
+        v.ncyc = c->ncyc;
+        for (int j = 0; j < 2; ++j) {
+            v.ucnt[j] = c->ucnt[j];
+            v.fcnt[j] = c->fcnt[j];
+        }
+        v.xcnt = c->xcnt;
+        v.scnt = c->scnt;
         *dst = v;
         __threadfence_system();
         __hip_atomic_store(seq_slot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
