@@ -44,6 +44,106 @@ KERNEL_NAMES = {
 }
 
 
+CSRC = os.path.join(ROOT, "paper_1111_0627_amd", "csrc")
+KERNEL_SYMBOL = {   # profile class -> the kernel whose counters give its traffic
+    "sweep": "k_sweep_u", "conn_mark": "k_conn_mark", "conn_claim": "k_conn_claim",
+    "conn_pull": "k_conn_pull", "values": "k_val_round", "fast": "k_val_round",
+    "cycles": "k_pj_round", "reverse": "k_rev_place",
+}
+
+
+def source_digest():
+    """sha256 over the HIP sources: counters taken from another build are not used."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def pmc_file(workload):
+    return os.path.join(ROOT, "profiles", f"pmc_{workload}.md")
+
+
+def load_pmc(workload):
+    """Per-kernel HBM counters (KiB per dispatch) and the copy calibration,
+    from the JSON block of profiles/pmc_<workload>.md; None if absent or
+    taken from other sources."""
+    path = pmc_file(workload)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    try:
+        blob = text.split("```json", 1)[1].split("```", 1)[0]
+        d = json.loads(blob)
+    except (IndexError, ValueError):
+        return None
+    if d.get("source_sha256") != source_digest():
+        return None
+    return d
+
+
+def traffic_per_launch(pmc, cls):
+    """Calibrated HBM bytes per launch of the class's kernel, or None."""
+    if not pmc or cls not in KERNEL_SYMBOL:
+        return None
+    k = pmc["kernels"].get(KERNEL_SYMBOL[cls])
+    if not k:
+        return None
+    cal = pmc["calibration"]
+    return 1024.0 * (k["fetch_kib"] * cal["fetch_factor"] + k["write_kib"] * cal["write_factor"])
+
+
+def summarize_pmc(fetch_dir, write_dir, out, workload, calib_mb, command):
+    """Writes profiles/pmc_<workload>.md from two rocprofv3 --pmc csv runs
+    (FETCH_SIZE, then WRITE_SIZE), each holding a device copy of calib_mb MiB."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        per = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"]
+                key = "copy" if "copyBuffer" in name else \
+                    name.replace("void ", "").split("(")[0].split("<")[0].split("::")[-1]
+                per.setdefault(key, []).append(float(r["Counter_Value"]))
+        return per
+
+    fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy_kib = calib_mb * 1024.0
+    cal = {"copy_bytes": calib_mb << 20, "fetch_kib": max(fe["copy"]), "write_kib": max(wr["copy"])}
+    cal["fetch_factor"] = copy_kib / cal["fetch_kib"]
+    cal["write_factor"] = copy_kib / cal["write_kib"]
+    kernels = {}
+    for k in sorted(set(fe) & set(wr)):
+        if k == "copy":
+            continue
+        kernels[k] = {"dispatches": len(fe[k]), "fetch_kib": sum(fe[k]) / len(fe[k]),
+                      "write_kib": sum(wr[k]) / len(wr[k])}
+    d = {"workload": workload, "source_sha256": source_digest(), "calibration": cal,
+         "kernels": kernels}
+    lines = [f"# HBM counters per dispatch: {workload}", "",
+             "Two `rocprofv3 --pmc` passes over the same run (`FETCH_SIZE`, then `WRITE_SIZE`).",
+             f"Each run first copies {calib_mb} MiB on the device; that copy calibrates the counters "
+             f"(fetch x{cal['fetch_factor']:.3f}, write x{cal['write_factor']:.3f}).", "",
+             "Command (one pass per counter):", "", "```", command, "```", "",
+             "| Kernel | Dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | Calibrated MB per dispatch |",
+             "|---|---:|---:|---:|---:|"]
+    for k, v in kernels.items():
+        mb = (v["fetch_kib"] * cal["fetch_factor"] + v["write_kib"] * cal["write_factor"]) / 1024
+        lines.append(f"| `{k}` | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} "
+                     f"| {mb:.1f} |")
+    lines += ["", "```json", json.dumps(d, indent=1), "```", ""]
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with open(out, "w") as f:
+        f.write("\n".join(lines))
+
+
 def roofline(cls, ms, launches, nbytes):
     """HBM roofline of one kernel class from the library's live hipEvent
     timings and its algorithmic bytes (both summed over the timed steps)."""
@@ -187,7 +287,14 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy one buffer of this many MiB (a plain copy "
                          "kernel of known size, to calibrate HBM byte counters)")
+    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/pmc_<workload>.md from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-command", default="", help="command line recorded with --pmc-summarize")
     args = ap.parse_args()
+    if args.pmc_summarize:
+        summarize_pmc(args.pmc_summarize[0], args.pmc_summarize[1], pmc_file(args.workload),
+                      args.workload, args.calib_copy_mb or 1024, args.pmc_command)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -288,9 +395,12 @@ def main():
         out["phase_launches_per_step"] = {k: v[1] / K for k, v in phase.items() if v[1]}
         out["phase_gbs"] = {k: v[2] / (v[0] / 1e3) / 1e9 for k, v in phase.items() if v[1] and v[0] > 0}
         dom = max((k for k, v in phase.items() if v[1]), key=lambda k: phase[k][0])
+        pmc = load_pmc(name)
         out["roofline"] = roofline(dom, *phase[dom])
         out["roofline"]["class"] = dom
+        out["roofline"]["traffic"] = traffic_per_launch(pmc, dom)
         out["roofline_sweep"] = roofline("sweep", *phase["sweep"])
+        out["roofline_sweep"]["traffic"] = traffic_per_launch(pmc, "sweep")
     if not args.no_adjoint:
         log("[bench] adjoint workload ...")
         out["adjoint"] = bench_adjoint(args.fd_edges)
