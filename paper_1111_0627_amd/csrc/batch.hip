@@ -67,7 +67,8 @@ struct GArrays {              // device arrays with one entry per graph
 struct BCtl {
     unsigned nchunks;
     unsigned nactive, nfast, ngeneral, ndone;
-    unsigned vrunning;
+    unsigned vrun_round[32];   // value phase: graphs still running in round r
+    unsigned nspans;           // rebuild: spans holding a rebuilt graph
     unsigned ncyc;
     unsigned overflow;
 };
@@ -83,6 +84,26 @@ __device__ __forceinline__ bool chunk_range(const int2* __restrict__ chunks, con
     const int64_t end = vptr[g + 1];
     v1 = v0 + T < end ? v0 + T : end;
     return true;
+}
+
+// Grid-stride over the chunk list: workgroup b takes chunks b, b + grid, ...,
+// so a launch needs no more workgroups than there are chunks to do, whatever
+// the list's capacity.  f(g, v0, v1) runs once per chunk; its `return` skips
+// to the next chunk.
+constexpr unsigned kChunkGrid = 2048;
+
+template <typename F>
+__device__ __forceinline__ void for_each_chunk(const int2* __restrict__ chunks, const unsigned* nch,
+                                               const long long* __restrict__ vptr, int T, F&& f)
+{
+    const unsigned nc = *nch;
+    for (unsigned ci = blockIdx.x; ci < nc; ci += gridDim.x) {
+        const int2 c = chunks[ci];
+        const int g = c.x;
+        const int64_t v0 = c.y;
+        const int64_t end = vptr[g + 1];
+        f(g, v0, v0 + T < end ? v0 + T : end);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -127,21 +148,20 @@ __global__ __launch_bounds__(kWG) void k_check_union(int G, const long long* __r
                                                      const unsigned* nch, int T,
                                                      unsigned* bad)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, vptr, T, g, v0, v1)) return;
-    unsigned err = 0;
-    const long long lo = vptr[g], hi = vptr[g + 1];
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-        const int a = row_ptr[v], b = row_ptr[v + 1];
-        if (v == lo && a != eptr[g]) err = 1;
-        if (v + 1 == hi && b != eptr[g + 1]) err = 1;
-        for (int e = a; e < b; ++e) {
-            const int c = col[e];
-            if (c < lo || c >= hi) err = 1;
+    for_each_chunk(chunks, nch, vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        unsigned err = 0;
+        const long long lo = vptr[g], hi = vptr[g + 1];
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+            const int a = row_ptr[v], b = row_ptr[v + 1];
+            if (v == lo && a != eptr[g]) err = 1;
+            if (v + 1 == hi && b != eptr[g + 1]) err = 1;
+            for (int e = a; e < b; ++e) {
+                const int c = col[e];
+                if (c < lo || c >= hi) err = 1;
+            }
         }
-    }
-    if (__ballot(err != 0) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+        if (__ballot(err != 0) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -159,74 +179,73 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
                                                const int* __restrict__ hop)
 {
     constexpr int VPB = kWG / G;
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    const bool first = !TIE && ga.iter[g] == 0;
-    const long long L = first ? 1 : ga.L[g];
-    const long long W = first ? 0 : ga.W[g];
-    const int lane = threadIdx.x & (G - 1);
-    unsigned long long cnt = 0, certain = 0, nondec = 0;
-    unsigned brk = 0;
-    for (int64_t vb = v0; vb < v1; vb += VPB) {
-        const int64_t v = vb + threadIdx.x / G;
-        const bool live = v < v1;
-        int beg = 0, end = 0, cur = -1;
-        long long own = 0;
-        if (live) {
-            beg = row_ptr[v];
-            end = row_ptr[v + 1];
-            if (!first) own = V[v];
-            if (TIE) cur = pi[v];
-        }
-        long long best = INT64_MAX;
-        int bpos = INT32_MAX;
-        for (int e = beg + lane; e < end; e += G) {
-            const long long we = wval(w, e, neg);
-            const long long key = first ? we : V[col[e]] + L * we - W;
-            if (TIE) {
-                if (key == own && e != cur) {
-                    cnt++;
-                    if (col[e] == v || onC[v]) certain++;
-                    if (hop[col[e]] >= hop[v]) nondec++;
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        const bool first = !TIE && ga.iter[g] == 0;
+        const long long L = first ? 1 : ga.L[g];
+        const long long W = first ? 0 : ga.W[g];
+        const int lane = threadIdx.x & (G - 1);
+        unsigned long long cnt = 0, certain = 0, nondec = 0;
+        unsigned brk = 0;
+        for (int64_t vb = v0; vb < v1; vb += VPB) {
+            const int64_t v = vb + threadIdx.x / G;
+            const bool live = v < v1;
+            int beg = 0, end = 0, cur = -1;
+            long long own = 0;
+            if (live) {
+                beg = row_ptr[v];
+                end = row_ptr[v + 1];
+                if (!first) own = V[v];
+                if (TIE) cur = pi[v];
+            }
+            long long best = INT64_MAX;
+            int bpos = INT32_MAX;
+            for (int e = beg + lane; e < end; e += G) {
+                const long long we = wval(w, e, neg);
+                const long long key = first ? we : V[col[e]] + L * we - W;
+                if (TIE) {
+                    if (key == own && e != cur) {
+                        cnt++;
+                        if (col[e] == v || onC[v]) certain++;
+                        if (hop[col[e]] >= hop[v]) nondec++;
+                    }
+                } else if (key < best) {
+                    best = key;
+                    bpos = e;
                 }
-            } else if (key < best) {
-                best = key;
-                bpos = e;
+            }
+            if (TIE) continue;
+    #pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+                const long long ob = __shfl_xor(best, off, G);
+                const int op = __shfl_xor(bpos, off, G);
+                if (ob < best || (ob == best && op < bpos)) {
+                    best = ob;
+                    bpos = op;
+                }
+            }
+            if (live && lane == 0 && (first || best < own)) {
+                pi[v] = bpos;
+                cnt++;
+                if (!first && onC[v]) brk = 1;
             }
         }
-        if (TIE) continue;
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) {
-            const long long ob = __shfl_xor(best, off, G);
-            const int op = __shfl_xor(bpos, off, G);
-            if (ob < best || (ob == best && op < bpos)) {
-                best = ob;
-                bpos = op;
+        cnt = block_sum_u64(cnt);
+        if (TIE) {
+            certain = block_sum_u64(certain);
+            nondec = block_sum_u64(nondec);
+            if (threadIdx.x == 0) {
+                if (cnt) atomicAdd(&ga.tight[g], cnt);
+                if (certain) atomicAdd(&ga.certain[g], certain);
+                if (nondec) atomicAdd(&ga.nondec[g], nondec);
+            }
+        } else {
+            const unsigned long long bb = block_sum_u64(brk);
+            if (threadIdx.x == 0) {
+                if (cnt) atomicAdd(&ga.changed[g], (unsigned)(cnt > 0xffffffffull ? 0xffffffffu : cnt));
+                if (bb) atomicOr(&ga.cbroken[g], 1u);
             }
         }
-        if (live && lane == 0 && (first || best < own)) {
-            pi[v] = bpos;
-            cnt++;
-            if (!first && onC[v]) brk = 1;
-        }
-    }
-    cnt = block_sum_u64(cnt);
-    if (TIE) {
-        certain = block_sum_u64(certain);
-        nondec = block_sum_u64(nondec);
-        if (threadIdx.x == 0) {
-            if (cnt) atomicAdd(&ga.tight[g], cnt);
-            if (certain) atomicAdd(&ga.certain[g], certain);
-            if (nondec) atomicAdd(&ga.nondec[g], nondec);
-        }
-    } else {
-        const unsigned long long bb = block_sum_u64(brk);
-        if (threadIdx.x == 0) {
-            if (cnt) atomicAdd(&ga.changed[g], (unsigned)(cnt > 0xffffffffull ? 0xffffffffu : cnt));
-            if (bb) atomicOr(&ga.cbroken[g], 1u);
-        }
-    }
+    });
 }
 
 // After the sweep: converged graphs retire; the others take the fast path
@@ -279,66 +298,65 @@ __global__ __launch_bounds__(kWG) void k_val_init(const int2* __restrict__ chunk
                                                   const WT* __restrict__ w, int neg,
                                                   int* __restrict__ succ, Jmp* __restrict__ Q)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    const int s = ga.s[g];
-    const long long W = ga.W[g], L = ga.L[g];
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-        const int e = pi[v];
-        const int t = col[e];
-        succ[v] = t;
-        Jmp q;
-        if (v == s) {
-            q.D = 0;
-            q.J = s;
-            q.H = 0;
-        } else {
-            q.D = L * wval(w, e, neg) - W;
-            q.J = t;
-            q.H = 1;
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        const int s = ga.s[g];
+        const long long W = ga.W[g], L = ga.L[g];
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+            const int e = pi[v];
+            const int t = col[e];
+            succ[v] = t;
+            Jmp q;
+            if (v == s) {
+                q.D = 0;
+                q.J = s;
+                q.H = 0;
+            } else {
+                q.D = L * wval(w, e, neg) - W;
+                q.J = t;
+                q.H = 1;
+            }
+            Q[v] = q;
         }
-        Q[v] = q;
-    }
-    if (threadIdx.x == 0) {
-        ga.vrun[g] = 1;
-        ga.ovf[g] = 0;
-    }
+        if (threadIdx.x == 0) {
+            ga.vrun[g] = 1;
+            ga.ovf[g] = 0;
+        }
+    });
 }
 
 __global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chunks,
                                                    const unsigned* nch, int T, GArrays ga,
                                                    const Jmp* __restrict__ Qin,
-                                                   Jmp* __restrict__ Qout)
+                                                   Jmp* __restrict__ Qout, const unsigned* running)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    if (!ga.vrun[g]) return;   // finished or stalled graph: its entries stay put
-    const int s = ga.s[g];
-    unsigned act = 0, prog = 0;
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-        Jmp q = Qin[v];
-        if (q.J != s) {
-            const Jmp r = Qin[q.J];
-            long long d;
-            if (__builtin_add_overflow(q.D, r.D, &d)) {
-                d = 0;
-                q.H |= kHopOverflow;
+    if (*running == 0) return;   // every graph of the phase has finished: nothing to do
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        if (!ga.vrun[g]) return;   // finished or stalled graph: its entries stay put
+        const int s = ga.s[g];
+        unsigned act = 0, prog = 0;
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+            Jmp q = Qin[v];
+            if (q.J != s) {
+                const Jmp r = Qin[q.J];
+                long long d;
+                if (__builtin_add_overflow(q.D, r.D, &d)) {
+                    d = 0;
+                    q.H |= kHopOverflow;
+                }
+                q.D = d;
+                q.J = r.J;
+                q.H = ((q.H & ~kHopOverflow) + (r.H & ~kHopOverflow)) | ((q.H | r.H) & kHopOverflow);
+                if (q.J == s) prog = 1;
+                else act = 1;
             }
-            q.D = d;
-            q.J = r.J;
-            q.H = ((q.H & ~kHopOverflow) + (r.H & ~kHopOverflow)) | ((q.H | r.H) & kHopOverflow);
-            if (q.J == s) prog = 1;
-            else act = 1;
+            Qout[v] = q;
         }
-        Qout[v] = q;
-    }
-    const unsigned long long a = block_sum_u64(act), p = block_sum_u64(prog);
-    if (threadIdx.x == 0) {
-        if (a) atomicOr(&ga.vact[g], 1u);
-        if (p) atomicOr(&ga.vprog[g], 1u);
-    }
+        const unsigned long long a = block_sum_u64(act), p = block_sum_u64(prog);
+        if (threadIdx.x == 0) {
+            if (a) atomicOr(&ga.vact[g], 1u);
+            if (p) atomicOr(&ga.vprog[g], 1u);
+        }
+    });
 }
 
 // After a value round: a graph is finished when no vertex is unfinished; a
@@ -368,7 +386,7 @@ __global__ __launch_bounds__(kWG) void k_val_update(int G, GArrays ga, int want,
         }
     }
     const unsigned long long r = block_sum_u64(running);
-    if (threadIdx.x == 0 && r) atomicAdd(&bc->vrunning, (unsigned)r);
+    if (threadIdx.x == 0 && r) atomicAdd(&bc->vrun_round[rounds], (unsigned)r);
 }
 
 // First-round bookkeeping: a graph may already be finished after init.
@@ -376,17 +394,16 @@ __global__ __launch_bounds__(kWG) void k_val_mark(const int2* __restrict__ chunk
                                                   const unsigned* nch, int T, GArrays ga,
                                                   const Jmp* __restrict__ Q)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    const int s = ga.s[g];
-    unsigned act = 0;
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) act |= Q[v].J != s;
-    const unsigned long long a = block_sum_u64(act);
-    if (threadIdx.x == 0) {
-        if (a) atomicOr(&ga.vact[g], 1u);
-        atomicOr(&ga.vprog[g], 1u);
-    }
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        const int s = ga.s[g];
+        unsigned act = 0;
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) act |= Q[v].J != s;
+        const unsigned long long a = block_sum_u64(act);
+        if (threadIdx.x == 0) {
+            if (a) atomicOr(&ga.vact[g], 1u);
+            atomicOr(&ga.vprog[g], 1u);
+        }
+    });
 }
 
 __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chunks,
@@ -395,32 +412,33 @@ __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chun
                                                    const Jmp* __restrict__ Q1,
                                                    long long* __restrict__ V, int* __restrict__ hop)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    if (ga.mode[g] != want) return;   // fell back or failed
-    if (ga.vrun[g]) {                 // did not finish within the rounds
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        // mode[g] may be changed by another workgroup of this launch: decide once
+        const int state = block_bcast(ga.mode[g] != want ? 0 : (ga.vrun[g] ? 1 : 2));
+        if (state == 0) return;   // fell back or failed
+        if (state == 1) {         // did not finish within the rounds
+            if (threadIdx.x == 0) {
+                ga.mode[g] = kDone;
+                ga.status[g] = OCM_E_HIP;
+            }
+            return;
+        }
+        const Jmp* __restrict__ Q = ga.fin[g] ? Q1 : Q0;
+        unsigned bad = 0;
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+            const Jmp q = Q[v];
+            V[v] = q.D;
+            hop[v] = (int)(q.H & ~kHopOverflow);
+            if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
+        }
+        const unsigned long long b = block_sum_u64(bad);
         if (threadIdx.x == 0) {
-            ga.mode[g] = kDone;
-            ga.status[g] = OCM_E_HIP;
+            if (b) {
+                ga.mode[g] = kDone;
+                ga.status[g] = OCM_E_OVERFLOW;
+            }
         }
-        return;
-    }
-    const Jmp* __restrict__ Q = ga.fin[g] ? Q1 : Q0;
-    unsigned bad = 0;
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-        const Jmp q = Q[v];
-        V[v] = q.D;
-        hop[v] = (int)(q.H & ~kHopOverflow);
-        if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
-    }
-    const unsigned long long b = block_sum_u64(bad);
-    if (threadIdx.x == 0) {
-        if (b) {
-            ga.mode[g] = kDone;
-            ga.status[g] = OCM_E_OVERFLOW;
-        }
-    }
+    });
 }
 
 // fast or general graph whose values are ready: back to sweeping
@@ -443,15 +461,14 @@ __global__ __launch_bounds__(kWG) void k_pj_init(const int2* __restrict__ chunks
                                                  unsigned long long* __restrict__ P,
                                                  unsigned char* __restrict__ onc)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-        const int s = col[pi[v]];
-        P[v] = ((unsigned long long)(unsigned)s << 32) | (unsigned)v;
-        onc[v] = 0;
-    }
-    if (threadIdx.x == 0) ga.best[g] = -1;
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+            const int s = col[pi[v]];
+            P[v] = ((unsigned long long)(unsigned)s << 32) | (unsigned)v;
+            onc[v] = 0;
+        }
+        if (threadIdx.x == 0) ga.best[g] = -1;
+    });
 }
 
 __global__ __launch_bounds__(kWG) void k_pj_round(const int2* __restrict__ chunks,
@@ -459,15 +476,14 @@ __global__ __launch_bounds__(kWG) void k_pj_round(const int2* __restrict__ chunk
                                                   const unsigned long long* __restrict__ Pin,
                                                   unsigned long long* __restrict__ Pout)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-        const unsigned long long p = Pin[v];
-        const unsigned long long q = Pin[(int)(p >> 32)];
-        const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
-        Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
-    }
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+            const unsigned long long p = Pin[v];
+            const unsigned long long q = Pin[(int)(p >> 32)];
+            const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
+            Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
+        }
+    });
 }
 
 __global__ __launch_bounds__(kWG) void k_pj_final(const int2* __restrict__ chunks,
@@ -476,14 +492,13 @@ __global__ __launch_bounds__(kWG) void k_pj_final(const int2* __restrict__ chunk
                                                   int* __restrict__ rep,
                                                   unsigned char* __restrict__ onc)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-        const int c = (int)(P[v] >> 32);
-        rep[v] = (int)(unsigned)P[c];
-        onc[c] = 1;
-    }
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+            const int c = (int)(P[v] >> 32);
+            rep[v] = (int)(unsigned)P[c];
+            onc[c] = 1;
+        }
+    });
 }
 
 // cycle heads of general graphs: zero their sums and list (rep, graph)
@@ -495,26 +510,25 @@ __global__ __launch_bounds__(kWG) void k_cyc_zero(const int2* __restrict__ chunk
                                                   unsigned* __restrict__ lcnt,
                                                   int2* __restrict__ heads, BCtl* bc)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    for (int64_t vb = v0; vb < v1; vb += kWG) {
-        const int64_t v = vb + threadIdx.x;
-        const bool head = v < v1 && onc[v] && rep[v] == v;
-        if (head) {
-            wsum[v] = 0;
-            lcnt[v] = 0;
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        for (int64_t vb = v0; vb < v1; vb += kWG) {
+            const int64_t v = vb + threadIdx.x;
+            const bool head = v < v1 && onc[v] && rep[v] == v;
+            if (head) {
+                wsum[v] = 0;
+                lcnt[v] = 0;
+            }
+            const unsigned long long mask = __ballot(head);
+            if (mask) {
+                const unsigned lane = threadIdx.x & 63;
+                const unsigned leader = (unsigned)__ffsll((long long)mask) - 1u;
+                unsigned base = 0;
+                if (lane == leader) base = atomicAdd(&bc->ncyc, (unsigned)__popcll(mask));
+                base = __shfl(base, (int)leader, 64);
+                if (head) heads[base + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2((int)v, g);
+            }
         }
-        const unsigned long long mask = __ballot(head);
-        if (mask) {
-            const unsigned lane = threadIdx.x & 63;
-            const unsigned leader = (unsigned)__ffsll((long long)mask) - 1u;
-            unsigned base = 0;
-            if (lane == leader) base = atomicAdd(&bc->ncyc, (unsigned)__popcll(mask));
-            base = __shfl(base, (int)leader, 64);
-            if (head) heads[base + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2((int)v, g);
-        }
-    }
+    });
 }
 
 template <typename WT>
@@ -527,15 +541,14 @@ __global__ __launch_bounds__(kWG) void k_cyc_sum(const int2* __restrict__ chunks
                                                  long long* __restrict__ wsum,
                                                  unsigned* __restrict__ lcnt)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-        if (!onc[v]) continue;
-        const int r = rep[v];
-        atomicAdd((unsigned long long*)&wsum[r], (unsigned long long)wval(w, pi[v], neg));
-        atomicAdd(&lcnt[r], 1u);
-    }
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+            if (!onc[v]) continue;
+            const int r = rep[v];
+            atomicAdd((unsigned long long*)&wsum[r], (unsigned long long)wval(w, pi[v], neg));
+            atomicAdd(&lcnt[r], 1u);
+        }
+    });
 }
 
 // a < b in the order (W/L, rep)
@@ -620,32 +633,30 @@ __global__ __launch_bounds__(kWG) void k_conn_init(const int2* __restrict__ chun
                                                    unsigned char* __restrict__ onC,
                                                    unsigned* a1, unsigned* a0, Ctl* cc)
 {
-    int g;
-    int64_t v0, v1;
-    const bool ok = chunk_range(chunks, nch, ga.vptr, T, g, v0, v1);
-    if (!ok) return;   // uniform per block
-    const int s = ga.s[g];
-    unsigned long long ncomp = 0, nleft = 0;
-    for (int64_t vb = v0 + (threadIdx.x & ~63); vb < v1; vb += kWG) {
-        const int64_t v = vb + (threadIdx.x & 63);
-        const bool live = v < v1;
-        bool comp = false;
-        if (live) {
-            comp = rep[v] == s;
-            layer[v] = comp ? 0 : -1;
-            onC[v] = (unsigned char)(comp && onc[v]);
-            ncomp += comp;
-            nleft += !comp;
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        const int s = ga.s[g];
+        unsigned long long ncomp = 0, nleft = 0;
+        for (int64_t vb = v0 + (threadIdx.x & ~63); vb < v1; vb += kWG) {
+            const int64_t v = vb + (threadIdx.x & 63);
+            const bool live = v < v1;
+            bool comp = false;
+            if (live) {
+                comp = rep[v] == s;
+                layer[v] = comp ? 0 : -1;
+                onC[v] = (unsigned char)(comp && onc[v]);
+                ncomp += comp;
+                nleft += !comp;
+            }
+            clear_wave_bits(a0, vb, live);
+            clear_wave_bits(a1, vb, live && !comp);
         }
-        clear_wave_bits(a0, vb, live);
-        clear_wave_bits(a1, vb, live && !comp);
-    }
-    ncomp = block_sum_u64(ncomp);
-    nleft = block_sum_u64(nleft);
-    if (threadIdx.x == 0) {
-        if (ncomp) atomicAdd(&my_lane(cc).got, (unsigned)ncomp);
-        if (nleft) atomicAdd(&my_lane(cc).left, (unsigned)nleft);
-    }
+        ncomp = block_sum_u64(ncomp);
+        nleft = block_sum_u64(nleft);
+        if (threadIdx.x == 0) {
+            if (ncomp) atomicAdd(&my_lane(cc).got, (unsigned)ncomp);
+            if (nleft) atomicAdd(&my_lane(cc).left, (unsigned)nleft);
+        }
+    });
 }
 
 // Graphs with a vertex that stays unattached (not in acur) are not strongly
@@ -673,6 +684,44 @@ __global__ __launch_bounds__(kWG) void k_conn_fail(int G, int n, const long long
     }
 }
 
+// Flags the round-kernel spans (vertices [i * span_verts, (i + 1) *
+// span_verts)) that hold a vertex of a listed chunk.
+__global__ __launch_bounds__(kWG) void k_span_flag(const int2* __restrict__ chunks,
+                                                   const unsigned* nch, int T, GArrays ga,
+                                                   int64_t span_verts,
+                                                   unsigned char* __restrict__ flags)
+{
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        for (int64_t sp = v0 / span_verts + threadIdx.x; sp <= (v1 - 1) / span_verts; sp += kWG)
+            flags[sp] = 1;
+    });
+}
+
+// Lists the flagged spans in order (and clears the flags); one workgroup.
+__global__ __launch_bounds__(kWG) void k_span_list(int64_t nall, unsigned char* __restrict__ flags,
+                                                   int* __restrict__ spans, unsigned* nspans)
+{
+    __shared__ unsigned wsum[kWG / 64];
+    unsigned base = 0;
+    for (int64_t s0 = 0; s0 < nall; s0 += kWG) {
+        const int64_t i = s0 + threadIdx.x;
+        const bool f = i < nall && flags[i];
+        if (i < nall && f) flags[i] = 0;
+        const unsigned incl = wave_incl_scan(f ? 1u : 0u);
+        if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        unsigned wbase = 0, tot = 0;
+        for (int w = 0; w < kWG / 64; ++w) {
+            if (w < (int)(threadIdx.x >> 6)) wbase += wsum[w];
+            tot += wsum[w];
+        }
+        if (f) spans[base + wbase + incl - 1] = (int)i;
+        base += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *nspans = base;
+}
+
 // ---------------------------------------------------------------------------
 // results
 // ---------------------------------------------------------------------------
@@ -684,17 +733,16 @@ __global__ __launch_bounds__(kWG) void k_cycle_list(const int2* __restrict__ chu
                                                     const int* __restrict__ hop,
                                                     int* __restrict__ out)
 {
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    if (ga.status[g] != OCM_OK) return;
-    const int s = ga.s[g];
-    const long long L = ga.L[g], base = cptr[g];
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-        if (!onC[v]) continue;
-        const long long j = v == s ? 0 : L - (long long)hop[v];
-        if (j >= 0 && j < L) out[base + j] = pi[v];
-    }
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        if (ga.status[g] != OCM_OK) return;
+        const int s = ga.s[g];
+        const long long L = ga.L[g], base = cptr[g];
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
+            if (!onC[v]) continue;
+            const long long j = v == s ? 0 : L - (long long)hop[v];
+            if (j >= 0 && j < L) out[base + j] = pi[v];
+        }
+    });
 }
 
 template <int G, typename WT>
@@ -709,30 +757,30 @@ __global__ __launch_bounds__(kWG) void k_short_walk(const int2* __restrict__ chu
                                                     const int* __restrict__ hop)
 {
     constexpr int VPB = kWG / G;
-    int g;
-    int64_t v0, v1;
-    if (!chunk_range(chunks, nch, ga.vptr, T, g, v0, v1)) return;
-    if (ga.status[g] != OCM_OK || ga.certain[g] || !ga.nondec[g]) return;   // uniform
-    const long long L = ga.L[g], W = ga.W[g];
-    const int lane = threadIdx.x & (G - 1);
-    unsigned long long found = 0;
-    for (int64_t vb = v0; vb < v1; vb += VPB) {
-        const int64_t v = vb + threadIdx.x / G;
-        if (v >= v1) continue;
-        const int beg = row_ptr[v], end = row_ptr[v + 1], cur = pi[v];
-        const long long own = V[v];
-        for (int e = beg + lane; e < end; e += G) {
-            if (e == cur) continue;
-            const int y = col[e];
-            if (hop[y] < hop[v]) continue;
-            if (V[y] + L * wval(w, e, neg) - W != own) continue;
-            int x = y;
-            for (int st = 0; st < kShortWalk && x != (int)v; ++st) x = succ[x];
-            found += x == (int)v;
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        // certain[g] grows during this launch: decide once for the workgroup
+        if (block_bcast(ga.status[g] != OCM_OK || ga.certain[g] || !ga.nondec[g])) return;
+        const long long L = ga.L[g], W = ga.W[g];
+        const int lane = threadIdx.x & (G - 1);
+        unsigned long long found = 0;
+        for (int64_t vb = v0; vb < v1; vb += VPB) {
+            const int64_t v = vb + threadIdx.x / G;
+            if (v >= v1) continue;
+            const int beg = row_ptr[v], end = row_ptr[v + 1], cur = pi[v];
+            const long long own = V[v];
+            for (int e = beg + lane; e < end; e += G) {
+                if (e == cur) continue;
+                const int y = col[e];
+                if (hop[y] < hop[v]) continue;
+                if (V[y] + L * wval(w, e, neg) - W != own) continue;
+                int x = y;
+                for (int st = 0; st < kShortWalk && x != (int)v; ++st) x = succ[x];
+                found += x == (int)v;
+            }
         }
-    }
-    found = block_sum_u64(found);
-    if (threadIdx.x == 0 && found) atomicAdd(&ga.certain[g], found);
+        found = block_sum_u64(found);
+        if (threadIdx.x == 0 && found) atomicAdd(&ga.certain[g], found);
+    });
 }
 
 __global__ void k_bctl_clear(BCtl* bc)
@@ -849,6 +897,8 @@ struct BWs {
     void* rscratch;
     unsigned* abits[2];
     unsigned char* marks;
+    unsigned char* span_flag;   // rebuild: spans holding a rebuilt graph (flags, then list)
+    int* spans;
     unsigned* bad;
     void* vctl;          // control block of the validation kernel
     size_t total;
@@ -915,6 +965,9 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m)
     w.abits[0] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.abits[1] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.marks = (unsigned char*)take(N + 16);
+    const size_t nsp = (size_t)ocm::round_spans((int)n) + 1;
+    w.span_flag = (unsigned char*)take(nsp);
+    w.spans = (int*)take(4 * nsp);
     w.bad = (unsigned*)take(256);
     w.vctl = take(sizeof(ocm::Ctl));
     w.total = off;
@@ -957,7 +1010,15 @@ ocm_status bread(BCtx& c)
     return OCM_OK;
 }
 
-unsigned max_chunks(const BCtx& c) { return (unsigned)(c.n / ocm::b::kMinChunk + c.G + 1); }
+// workgroups of a chunked launch: enough for the largest chunk list, at
+// most kChunkGrid (the kernels stride over the list)
+unsigned chunk_grid(const BCtx& c)
+{
+    const unsigned most = (unsigned)(c.n / ocm::b::kMinChunk + c.G + 1);
+    return most < ocm::b::kChunkGrid ? most : ocm::b::kChunkGrid;
+}
+
+unsigned chunk_grid(unsigned nch) { return nch < ocm::b::kChunkGrid ? nch : ocm::b::kChunkGrid; }
 
 // Chunk list of the graphs in `want` (a mode, -1 = every graph not done,
 // -2 = every graph), built on the device; kernels read the count from
@@ -992,11 +1053,11 @@ void launch_bsweep_t(BCtx& c, unsigned nch, bool tie)
 #define OCM_BSW(GG)                                                                              \
     case GG:                                                                                     \
         if (tie)                                                                                 \
-            ocm::b::k_sweep<GG, WT, true><<<nch, ocm::kWG, 0, c.st>>>(                            \
+            ocm::b::k_sweep<GG, WT, true><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(                            \
                 ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,   \
                 ws.onC, ws.hop);                                                                 \
         else                                                                                     \
-            ocm::b::k_sweep<GG, WT, false><<<nch, ocm::kWG, 0, c.st>>>(                           \
+            ocm::b::k_sweep<GG, WT, false><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(                           \
                 ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,   \
                 ws.onC, ws.hop);                                                                 \
         break;
@@ -1028,7 +1089,7 @@ void launch_bwalk_t(BCtx& c, unsigned nch)
     const int T = c.sch.chunk;
 #define OCM_BWK(GG)                                                                              \
     case GG:                                                                                     \
-        ocm::b::k_short_walk<GG, WT><<<nch, ocm::kWG, 0, c.st>>>(                                 \
+        ocm::b::k_short_walk<GG, WT><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(                                 \
             ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,       \
             ws.succ, ws.hop);                                                                    \
         break;
@@ -1068,7 +1129,7 @@ void enqueue_values(BCtx& c, int want)
     BWs& ws = c.ws;
     GArrays& a = ws.ga;
     const int T = c.sch.chunk;
-    const unsigned mc = max_chunks(c);
+    const unsigned mc = chunk_grid(c);
     enqueue_chunks(c, want);
     if (c.wtype == OCM_W_I64)
         ocm::b::k_val_init<long long><<<mc, ocm::kWG, 0, c.st>>>(
@@ -1078,13 +1139,15 @@ void enqueue_values(BCtx& c, int want)
         ocm::b::k_val_init<int><<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, c.col,
                                                            ws.pi, (const int*)c.w, c.neg, ws.succ,
                                                            ws.Q[0]);
-    ocm::b::k_val_mark<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.Q[0]);
+    ocm::b::k_val_mark<<<chunk_grid(c), ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.Q[0]);
     const int R = jump_rounds(c);
+    ocm::launch_fill_u32(ws.bc->vrun_round, 32, 0u, c.st);
     for (int r = 0; r < R; ++r) {
         ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, r,
                                                                          ws.bc);
-        ocm::b::k_val_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a,
-                                                       ws.Q[r & 1], ws.Q[(r + 1) & 1]);
+        ocm::b::k_val_round<<<chunk_grid(c), ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a,
+                                                                ws.Q[r & 1], ws.Q[(r + 1) & 1],
+                                                                &ws.bc->vrun_round[r]);
     }
     ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, R, ws.bc);
     ocm::b::k_val_final<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, want, ws.Q[0],
@@ -1098,7 +1161,7 @@ void enqueue_general_head(BCtx& c)
     BWs& ws = c.ws;
     GArrays& a = ws.ga;
     const int T = c.sch.chunk;
-    const unsigned mc = max_chunks(c);
+    const unsigned mc = chunk_grid(c);
     enqueue_chunks(c, ocm::b::kGeneral);
     auto* P0 = (unsigned long long*)ws.Q[0];
     auto* P1 = (unsigned long long*)ws.Q[1];
@@ -1136,6 +1199,12 @@ void enqueue_general_head(BCtx& c)
     ocm::launch_fill_u32(ws.abits[1], words, 0xffffffffu, c.st);
     ocm::b::k_conn_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep, ws.onc,
                                                    ws.layer, ws.onC, ws.abits[1], ws.abits[0], cc);
+    // the rounds visit only the spans that hold a rebuilt graph
+    const int64_t span_verts = (int64_t)32 * ocm::kWG * ocm::round_wpt(c.n);
+    ocm::b::k_span_flag<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, span_verts,
+                                                   ws.span_flag);
+    ocm::b::k_span_list<<<1, ocm::kWG, 0, c.st>>>(ocm::round_spans(c.n), ws.span_flag, ws.spans,
+                                                  &ws.bc->nspans);
 }
 
 // One iteration up to the rebuild rounds: sweep, retire converged graphs,
@@ -1145,7 +1214,7 @@ void enqueue_head(BCtx& c, int max_iters, bool fast_path)
     BWs& ws = c.ws;
     GArrays& a = ws.ga;
     enqueue_chunks(c, ocm::b::kActive);
-    launch_bsweep(c, max_chunks(c), false);
+    launch_bsweep(c, chunk_grid(c), false);
     ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->nactive, &ws.bc->nfast);
     ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ngeneral, nullptr);
     ocm::b::k_after_sweep<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, max_iters,
@@ -1178,12 +1247,13 @@ ocm_status host_connect(BCtx& c)
         unsigned* anext = ws.abits[(k + 1) & 1];
         ocm::launch_ctl_clear(cc, ocm::kClrCount, c.st);
         if (push) {
-            ocm::launch_conn_mark(c.n, ws.rin_ptr, ws.rin, acur, anext, ws.marks, nullptr, c.st);
+            ocm::launch_conn_mark(c.n, ws.rin_ptr, ws.rin, acur, anext, ws.marks, nullptr, ws.spans,
+                                  &ws.bc->nspans, c.st);
             ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, ws.marks, ws.pi, ws.layer,
-                                   cc, nullptr, c.st);
+                                   cc, nullptr, ws.spans, &ws.bc->nspans, c.st);
         } else {
             ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, ws.layer, ws.pi, cc,
-                                  nullptr, c.st);
+                                  nullptr, ws.spans, &ws.bc->nspans, c.st);
         }
         BHIP(hipGetLastError());
         BHIP(ocm::host_read_ctl(cc, &h, c.st));
@@ -1291,10 +1361,10 @@ ocm_status autotune(BCtx& c, Schedule* out, int* tuned)
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {
             BHIP(hipEventRecord(e0, c.st));
-            launch_bsweep(c, max_chunks(c), false);   // iteration 0: the first sweep
+            launch_bsweep(c, chunk_grid(c), false);   // iteration 0: the first sweep
             auto* P0 = (unsigned long long*)ws.Q[0];
             auto* P1 = (unsigned long long*)ws.Q[1];
-            const unsigned mc = max_chunks(c);
+            const unsigned mc = chunk_grid(c);
             ocm::b::k_pj_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
                                                          c.col, ws.pi, P0, ws.onc);
             ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
@@ -1391,6 +1461,7 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
     GArrays& a = ws.ga;
 
     ocm::b::k_bctl_clear<<<1, 64, 0, c.st>>>(ws.bc);
+    ocm::launch_fill_u8(ws.span_flag, ocm::round_spans(c.n) + 1, 0, c.st);
     BHIP(hipMemcpyAsync(a.vptr, vptr, 8 * (size_t)(G + 1), hipMemcpyHostToDevice, c.st));
     BHIP(hipMemcpyAsync(a.eptr, eptr, 8 * (size_t)(G + 1), hipMemcpyHostToDevice, c.st));
     ocm::b::k_graph_init<<<ocm::stride_grid(G), ocm::kWG, 0, c.st>>>((int)G, a);
@@ -1412,7 +1483,7 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
             unsigned nch = 0;
             BTRY(build_chunks(c, -1, &nch));
             ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->overflow, nullptr);
-            ocm::b::k_check_union<<<nch, ocm::kWG, 0, c.st>>>((int)G, a.vptr, a.eptr, c.row_ptr, c.col,
+            ocm::b::k_check_union<<<chunk_grid(nch), ocm::kWG, 0, c.st>>>((int)G, a.vptr, a.eptr, c.row_ptr, c.col,
                                                               ws.chunks, &ws.bc->nchunks,
                                                               c.sch.chunk, &ws.bc->overflow);
             BHIP(hipGetLastError());
@@ -1488,7 +1559,7 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
         unsigned nch = 0;
         BTRY(build_chunks(c, -2, &nch));
         if (nch == 0) nch = 1;
-        ocm::b::k_cycle_list<<<nch, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, c.sch.chunk, a,
+        ocm::b::k_cycle_list<<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, c.sch.chunk, a,
                                                          ws.cptr, ws.onC, ws.pi, ws.hop, cycle_edges);
         if (o.tie_check) {
             ocm::b::k_tie_init<<<ocm::stride_grid(G), ocm::kWG, 0, c.st>>>((int)G, a);

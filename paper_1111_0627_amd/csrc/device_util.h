@@ -70,6 +70,18 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long x
     return t;
 }
 
+// Thread 0's value, seen by the whole workgroup (for early exits that must be
+// uniform while other workgroups may change the value being read).  All
+// threads call it.
+__device__ __forceinline__ int block_bcast(int x)
+{
+    __shared__ int v;
+    __syncthreads();
+    if (threadIdx.x == 0) v = x;
+    __syncthreads();
+    return v;
+}
+
 // Workgroup-buffered list append: items go to an LDS buffer first and the
 // block reserves its slice of the global list with one atomic at the end.
 struct BlockList {

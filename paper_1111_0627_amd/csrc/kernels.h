@@ -176,15 +176,21 @@ void launch_select(const int* cyc_list, const long long* wsum, const unsigned* l
 // component) and left (unattached); every round -> got (attached in it).
 void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, int* layer,
                       unsigned char* onC, unsigned* a1, unsigned* a0, Ctl* ctl, hipStream_t st);
+// Round kernels work on spans of kWG * round_wpt(n) bitmap words; `spans`
+// (device list of span indices, *nspans of them) restricts a round to those
+// spans, nullptr means every span.
+int round_wpt(int n);
+int64_t round_spans(int n);
 void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                       unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
-                      hipStream_t st);
+                      const int* spans, const unsigned* nspans, hipStream_t st);
 void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned* acur,
                       unsigned* anext, unsigned char* marks, unsigned long long* pedges,
-                      hipStream_t st);
+                      const int* spans, const unsigned* nspans, hipStream_t st);
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                        unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
-                       unsigned long long* cedges, hipStream_t st);
+                       unsigned long long* cedges, const int* spans, const unsigned* nspans,
+                       hipStream_t st);
 // Reverse CSR (rin_ptr, rin) of the graph.  With `scratch` of
 // rev_scratch_bytes(n, m) bytes (0 when the plan does not apply) the build
 // is partitioned by head bucket; otherwise it counts and fills with global

@@ -681,7 +681,21 @@ __device__ __forceinline__ unsigned attach_batch(int k, const RoundLds& L, unsig
     return got;
 }
 
-// Pull round k: the workgroup's unattached vertices (~acur) scan their
+// Spans of the round kernels: span i covers bitmap words [i * kWG * WPT,
+// (i + 1) * kWG * WPT).  A workgroup strides over the spans (all of them, or
+// only those listed in `spans`, *nspans of them).
+template <typename F>
+__device__ __forceinline__ void for_each_span(const int* __restrict__ spans, const unsigned* nspans,
+                                              int64_t nall, F&& f)
+{
+    const int64_t cnt = spans ? (int64_t)*nspans : nall;
+    for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        f(spans ? (int64_t)spans[i] : i);
+        __syncthreads();   // the next span reuses the LDS
+    }
+}
+
+// Pull round k: the unattached vertices (~acur) of each span scan their
 // out-edges; anext becomes acur plus this round's attachments.
 template <int WPT>
 __global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __restrict__ row_ptr,
@@ -689,39 +703,44 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __re
                                                    const unsigned* __restrict__ acur,
                                                    unsigned* __restrict__ anext,
                                                    int* __restrict__ layer, int* __restrict__ pi,
-                                                   Ctl* ctl, unsigned long long* ledges)
+                                                   Ctl* ctl, unsigned long long* ledges,
+                                                   const int* __restrict__ spans,
+                                                   const unsigned* nspans)
 {
     __shared__ RoundLds L;
     __shared__ unsigned nb[kWG * WPT];
     const int64_t words = ((int64_t)n + 31) / 32;
-    const int64_t wbase = (int64_t)blockIdx.x * kWG * WPT;
-    const int64_t w0 = wbase + (int64_t)threadIdx.x * WPT;
-    unsigned a[WPT];
-    unsigned long long mask = 0;
-#pragma unroll
-    for (int j = 0; j < WPT; ++j) {
-        a[j] = 0;
-        nb[threadIdx.x * WPT + j] = 0;
-        if (w0 + j < words) {
-            a[j] = acur[w0 + j];
-            mask |= (unsigned long long)(~a[j] & valid_bits(w0 + j, n)) << (32 * j);
-        }
-    }
-    unsigned total = 0;
-    const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
+    const int64_t per = (int64_t)kWG * WPT;
     unsigned got = 0, scanned = 0;
-    for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
-        emit_batch(mask, w0 * 32, rank, b0, L.todo);
-        __syncthreads();
-        const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
-        scanned += lowest_attached_edges(row_ptr, col, acur, L.todo, cnt, L.beg, L.off, L.best,
-                                         L.wsum);
-        got += attach_batch(k, L, cnt, wbase, nb, pi, layer);
-        __syncthreads();
-    }
+    for_each_span(spans, nspans, (words + per - 1) / per, [&](int64_t span) {
+        const int64_t wbase = span * per;
+        const int64_t w0 = wbase + (int64_t)threadIdx.x * WPT;
+        unsigned a[WPT];
+        unsigned long long mask = 0;
 #pragma unroll
-    for (int j = 0; j < WPT; ++j)
-        if (w0 + j < words) anext[w0 + j] = a[j] | nb[threadIdx.x * WPT + j];
+        for (int j = 0; j < WPT; ++j) {
+            a[j] = 0;
+            nb[threadIdx.x * WPT + j] = 0;
+            if (w0 + j < words) {
+                a[j] = acur[w0 + j];
+                mask |= (unsigned long long)(~a[j] & valid_bits(w0 + j, n)) << (32 * j);
+            }
+        }
+        unsigned total = 0;
+        const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
+        for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
+            emit_batch(mask, w0 * 32, rank, b0, L.todo);
+            __syncthreads();
+            const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
+            scanned += lowest_attached_edges(row_ptr, col, acur, L.todo, cnt, L.beg, L.off, L.best,
+                                             L.wsum);
+            got += attach_batch(k, L, cnt, wbase, nb, pi, layer);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < WPT; ++j)
+            if (w0 + j < words) anext[w0 + j] = a[j] | nb[threadIdx.x * WPT + j];
+    });
     const unsigned long long g = block_sum_u64(got);
     if (threadIdx.x == 0) {
         if (g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
@@ -729,60 +748,64 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __re
     }
 }
 
-// Push round k, mark: the workgroup lists its frontier vertices
-// (acur & ~anext, folded into anext on the way) and spreads their in-edges
-// over its threads; every tail u gets marks[u] = 1 (plain byte store,
-// idempotent).  Attached tails are dropped by the claim, which reads its own
-// span of acur anyway.
+// Push round k, mark: each span lists its frontier vertices (acur & ~anext,
+// folded into anext on the way) and spreads their in-edges over the
+// workgroup; every tail u gets marks[u] = 1 (plain byte store, idempotent).
+// Attached tails are dropped by the claim, which reads its span of acur
+// anyway.
 template <int WPT>
 __global__ __launch_bounds__(kWG) void k_conn_mark(int n, const int* __restrict__ rin_ptr,
                                                    const int* __restrict__ rin,
                                                    const unsigned* __restrict__ acur,
                                                    unsigned* __restrict__ anext,
                                                    unsigned char* __restrict__ marks,
-                                                   unsigned long long* pedges)
+                                                   unsigned long long* pedges,
+                                                   const int* __restrict__ spans,
+                                                   const unsigned* nspans)
 {
     __shared__ RoundLds L;
     const int64_t words = ((int64_t)n + 31) / 32;
-    const int64_t wbase = (int64_t)blockIdx.x * kWG * WPT;
-    const int64_t w0 = wbase + (int64_t)threadIdx.x * WPT;
-    unsigned long long mask = 0;
-#pragma unroll
-    for (int j = 0; j < WPT; ++j) {
-        if (w0 + j < words) {
-            const unsigned a = acur[w0 + j];
-            const unsigned f = a & ~anext[w0 + j];
-            if (f) anext[w0 + j] = a;   // anext is a subset of acur
-            mask |= (unsigned long long)f << (32 * j);
-        }
-    }
-    unsigned total = 0;
-    const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
+    const int64_t per = (int64_t)kWG * WPT;
     unsigned long long scanned = 0;
-    for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
-        emit_batch(mask, w0 * 32, rank, b0, L.todo);
-        __syncthreads();
-        const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
-        for (unsigned i = threadIdx.x; i < cnt; i += kWG) {
-            const int x = L.todo[i];
-            const int b = rin_ptr[x];
-            L.beg[i] = b;
-            L.off[i] = (unsigned)(rin_ptr[x + 1] - b);
+    for_each_span(spans, nspans, (words + per - 1) / per, [&](int64_t span) {
+        const int64_t w0 = span * per + (int64_t)threadIdx.x * WPT;
+        unsigned long long mask = 0;
+#pragma unroll
+        for (int j = 0; j < WPT; ++j) {
+            if (w0 + j < words) {
+                const unsigned a = acur[w0 + j];
+                const unsigned f = a & ~anext[w0 + j];
+                if (f) anext[w0 + j] = a;   // anext is a subset of acur
+                mask |= (unsigned long long)f << (32 * j);
+            }
         }
-        __syncthreads();
-        const unsigned tot = block_excl_scan(L.off, cnt, L.wsum);
-        for (unsigned t = threadIdx.x; t < tot; t += kWG) {
-            const unsigned i = owner_of(L.off, cnt, t);
-            marks[rin[L.beg[i] + (int)(t - L.off[i])]] = 1;
+        unsigned total = 0;
+        const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
+        for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
+            emit_batch(mask, w0 * 32, rank, b0, L.todo);
+            __syncthreads();
+            const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
+            for (unsigned i = threadIdx.x; i < cnt; i += kWG) {
+                const int x = L.todo[i];
+                const int b = rin_ptr[x];
+                L.beg[i] = b;
+                L.off[i] = (unsigned)(rin_ptr[x + 1] - b);
+            }
+            __syncthreads();
+            const unsigned tot = block_excl_scan(L.off, cnt, L.wsum);
+            for (unsigned t = threadIdx.x; t < tot; t += kWG) {
+                const unsigned i = owner_of(L.off, cnt, t);
+                marks[rin[L.beg[i] + (int)(t - L.off[i])]] = 1;
+            }
+            scanned += tot;
+            __syncthreads();
         }
-        scanned += tot;
-        __syncthreads();
-    }
+    });
     if (pedges && threadIdx.x == 0 && scanned) atomicAdd(my_copy(pedges), scanned);
 }
 
-// Push round k, claim: the workgroup takes the mark bytes of its span
-// (clearing them), lists the marked vertices and finds each one's lowest
+// Push round k, claim: each span takes its mark bytes (clearing them), lists
+// the marked vertices that are not attached yet and finds each one's lowest
 // out-edge into the attached set.  One exists: the edge that marked it.  The
 // vertex attaches with it (pi, layer = k) and joins anext.
 template <int WPT>
@@ -792,59 +815,64 @@ __global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __r
                                                     unsigned* __restrict__ anext,
                                                     unsigned char* __restrict__ marks,
                                                     int* __restrict__ pi, int* __restrict__ layer,
-                                                    Ctl* ctl, unsigned long long* cedges)
+                                                    Ctl* ctl, unsigned long long* cedges,
+                                                    const int* __restrict__ spans,
+                                                    const unsigned* nspans)
 {
     __shared__ RoundLds L;
     __shared__ unsigned nb[kWG * WPT];
     const int64_t words = ((int64_t)n + 31) / 32;
-    const int64_t wbase = (int64_t)blockIdx.x * kWG * WPT;
-    const int64_t w0 = wbase + (int64_t)threadIdx.x * WPT;
-    const int64_t v0 = w0 * 32;   // this thread's 32 * WPT mark bytes
-    unsigned long long mask = 0;
-#pragma unroll
-    for (int j = 0; j < WPT; ++j) nb[threadIdx.x * WPT + j] = 0;
-    if (v0 + 32 * WPT <= n) {
-#pragma unroll
-        for (int q = 0; q < 2 * WPT; ++q) {
-            uint4 t = *(const uint4*)(marks + v0 + 16 * q);
-            if (t.x | t.y | t.z | t.w) *(uint4*)(marks + v0 + 16 * q) = make_uint4(0, 0, 0, 0);
-            const unsigned wd[4] = {t.x, t.y, t.z, t.w};
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if ((wd[r >> 2] >> (8 * (r & 3))) & 0xffu) mask |= 1ull << (16 * q + r);
-        }
-    } else {
-        for (int q = 0; q < 32 * WPT && v0 + q < n; ++q) {
-            if (marks[v0 + q]) {
-                mask |= 1ull << q;
-                marks[v0 + q] = 0;
-            }
-        }
-    }
-    // marked tails that are already attached drop out
-    unsigned long long att = 0;
-#pragma unroll
-    for (int j = 0; j < WPT; ++j)
-        if (w0 + j < words) att |= (unsigned long long)acur[w0 + j] << (32 * j);
-    mask &= ~att;
-    unsigned total = 0;
-    const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
+    const int64_t per = (int64_t)kWG * WPT;
     unsigned got = 0;
     unsigned long long scanned = 0;
-    for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
-        emit_batch(mask, v0, rank, b0, L.todo);
-        __syncthreads();
-        const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
-        scanned += lowest_attached_edges(row_ptr, col, acur, L.todo, cnt, L.beg, L.off, L.best,
-                                         L.wsum);
-        got += attach_batch(k, L, cnt, wbase, nb, pi, layer);
-        __syncthreads();
-    }
+    for_each_span(spans, nspans, (words + per - 1) / per, [&](int64_t span) {
+        const int64_t wbase = span * per;
+        const int64_t w0 = wbase + (int64_t)threadIdx.x * WPT;
+        const int64_t v0 = w0 * 32;   // this thread's 32 * WPT mark bytes
+        unsigned long long mask = 0;
 #pragma unroll
-    for (int j = 0; j < WPT; ++j) {
-        const unsigned x = nb[threadIdx.x * WPT + j];
-        if (x && w0 + j < words) anext[w0 + j] |= x;
-    }
+        for (int j = 0; j < WPT; ++j) nb[threadIdx.x * WPT + j] = 0;
+        if (v0 + 32 * WPT <= n) {
+#pragma unroll
+            for (int q = 0; q < 2 * WPT; ++q) {
+                uint4 t = *(const uint4*)(marks + v0 + 16 * q);
+                if (t.x | t.y | t.z | t.w) *(uint4*)(marks + v0 + 16 * q) = make_uint4(0, 0, 0, 0);
+                const unsigned wd[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if ((wd[r >> 2] >> (8 * (r & 3))) & 0xffu) mask |= 1ull << (16 * q + r);
+            }
+        } else {
+            for (int q = 0; q < 32 * WPT && v0 + q < n; ++q) {
+                if (marks[v0 + q]) {
+                    mask |= 1ull << q;
+                    marks[v0 + q] = 0;
+                }
+            }
+        }
+        // marked tails that are already attached drop out
+        unsigned long long att = 0;
+#pragma unroll
+        for (int j = 0; j < WPT; ++j)
+            if (w0 + j < words) att |= (unsigned long long)acur[w0 + j] << (32 * j);
+        mask &= ~att;
+        unsigned total = 0;
+        const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
+        for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
+            emit_batch(mask, v0, rank, b0, L.todo);
+            __syncthreads();
+            const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
+            scanned += lowest_attached_edges(row_ptr, col, acur, L.todo, cnt, L.beg, L.off, L.best,
+                                             L.wsum);
+            got += attach_batch(k, L, cnt, wbase, nb, pi, layer);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < WPT; ++j) {
+            const unsigned x = nb[threadIdx.x * WPT + j];
+            if (x && w0 + j < words) anext[w0 + j] |= x;
+        }
+    });
     const unsigned long long g = block_sum_u64(got);
     if (threadIdx.x == 0) {
         if (g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
@@ -1590,56 +1618,65 @@ void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, in
 
 // Words per thread of the round kernels: 2 when one word per thread would
 // need more than 1024 workgroups.
-static int round_wpt(int n)
+int round_wpt(int n)
 {
     const int64_t words = ((int64_t)n + 31) / 32;
     return words > (int64_t)1024 * kWG ? 2 : 1;
 }
 
-static unsigned round_grid(int n, int wpt)
+int64_t round_spans(int n)
 {
     const int64_t words = ((int64_t)n + 31) / 32;
-    const int64_t per = (int64_t)kWG * wpt;
-    return (unsigned)((words + per - 1) / per);
+    const int64_t per = (int64_t)kWG * round_wpt(n);
+    return (words + per - 1) / per;
+}
+
+// one workgroup per span (with a span list the ones past its length leave
+// at once)
+static unsigned round_grid(int n, const int* spans)
+{
+    (void)spans;
+    return (unsigned)round_spans(n);
 }
 
 void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                       unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
-                      hipStream_t st)
+                      const int* spans, const unsigned* nspans, hipStream_t st)
 {
-    const int wpt = round_wpt(n);
-    if (wpt == 2)
-        k_conn_pull<2><<<round_grid(n, 2), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer,
-                                                         pi, ctl, ledges);
+    const unsigned grid = round_grid(n, spans);
+    if (round_wpt(n) == 2)
+        k_conn_pull<2><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer, pi, ctl,
+                                             ledges, spans, nspans);
     else
-        k_conn_pull<1><<<round_grid(n, 1), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer,
-                                                         pi, ctl, ledges);
+        k_conn_pull<1><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer, pi, ctl,
+                                             ledges, spans, nspans);
 }
 
 void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned* acur,
                       unsigned* anext, unsigned char* marks, unsigned long long* pedges,
-                      hipStream_t st)
+                      const int* spans, const unsigned* nspans, hipStream_t st)
 {
-    const int wpt = round_wpt(n);
-    if (wpt == 2)
-        k_conn_mark<2><<<round_grid(n, 2), kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks,
-                                                         pedges);
+    const unsigned grid = round_grid(n, spans);
+    if (round_wpt(n) == 2)
+        k_conn_mark<2><<<grid, kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks, pedges, spans,
+                                             nspans);
     else
-        k_conn_mark<1><<<round_grid(n, 1), kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks,
-                                                         pedges);
+        k_conn_mark<1><<<grid, kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks, pedges, spans,
+                                             nspans);
 }
 
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                        unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
-                       unsigned long long* cedges, hipStream_t st)
+                       unsigned long long* cedges, const int* spans, const unsigned* nspans,
+                       hipStream_t st)
 {
-    const int wpt = round_wpt(n);
-    if (wpt == 2)
-        k_conn_claim<2><<<round_grid(n, 2), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks,
-                                                          pi, layer, ctl, cedges);
+    const unsigned grid = round_grid(n, spans);
+    if (round_wpt(n) == 2)
+        k_conn_claim<2><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
+                                              ctl, cedges, spans, nspans);
     else
-        k_conn_claim<1><<<round_grid(n, 1), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks,
-                                                          pi, layer, ctl, cedges);
+        k_conn_claim<1><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
+                                              ctl, cedges, spans, nspans);
 }
 
 void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsigned* tot,

@@ -443,17 +443,18 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
         ocm::launch_ctl_clear(w.ctl, ocm::kClrCount, c.st);
         if (push) {
             c.prof.begin(OCM_K_CONN_MARK);
-            ocm::launch_conn_mark(c.n, w.rin_ptr, w.rin, acur, anext, w.marks, pedges, c.st);
+            ocm::launch_conn_mark(c.n, w.rin_ptr, w.rin, acur, anext, w.marks, pedges, nullptr,
+                                  nullptr, c.st);
             c.prof.end();
             c.prof.begin(OCM_K_CONN_CLAIM);
             ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, w.marks, pi, layer,
-                                   w.ctl, ledges, c.st);
+                                   w.ctl, ledges, nullptr, nullptr, c.st);
             c.prof.end();
             c.push_frontier += front;
         } else {
             c.prof.begin(OCM_K_CONN_PULL);
             ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, layer, pi, w.ctl, ledges,
-                                  c.st);
+                                  nullptr, nullptr, c.st);
             c.prof.end();
         }
         HIP_TRY(hipGetLastError());
