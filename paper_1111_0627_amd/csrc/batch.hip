@@ -1248,12 +1248,12 @@ ocm_status host_connect(BCtx& c)
         ocm::launch_ctl_clear(cc, ocm::kClrCount, c.st);
         if (push) {
             ocm::launch_conn_mark(c.n, ws.rin_ptr, ws.rin, acur, anext, ws.marks, nullptr, ws.spans,
-                                  &ws.bc->nspans, c.st);
+                                  &ws.bc->nspans, nullptr, c.st);
             ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, ws.marks, ws.pi, ws.layer,
-                                   cc, nullptr, ws.spans, &ws.bc->nspans, c.st);
+                                   cc, nullptr, ws.spans, &ws.bc->nspans, nullptr, c.st);
         } else {
             ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, ws.layer, ws.pi, cc,
-                                  nullptr, ws.spans, &ws.bc->nspans, c.st);
+                                  nullptr, ws.spans, &ws.bc->nspans, nullptr, c.st);
         }
         BHIP(hipGetLastError());
         BHIP(ocm::host_read_ctl(cc, &h, c.st));

@@ -56,8 +56,11 @@ struct alignas(128) Ctl {
     long long W, L;                // current lambda, unreduced
     int s;                         // current source (min vertex of C)
     unsigned ncyc;                 // cycles found by the cycle phase
-    unsigned ucnt[2];              // connect: unattached-list sizes
-    unsigned fcnt[2];              // connect: frontier-list sizes
+    unsigned rmode;                // connect, device-driven rounds: 0 done, 1 push, 2 pull
+    unsigned rleft;                //   unattached vertices
+    unsigned rfront;               //   vertices attached by the last round
+    unsigned rerr;                 //   a round attached nobody while vertices were left
+    unsigned rk;                   //   rounds run
     unsigned xcnt;                 // tie scan: tight non-policy edges listed
     unsigned scnt;                 // tie check: special vertices
     CtlLane lane[kLanes];
@@ -68,7 +71,7 @@ struct CtlView {
     long long W, L;
     int s;
     unsigned ncyc;
-    unsigned ucnt[2], fcnt[2];
+    unsigned rmode, rleft, rfront, rerr, rk;
     unsigned xcnt, scnt;
     unsigned long long changed, tight, certain, nondec, pedges, ledges, maxabsw;
     unsigned active, active2, got, left, err, cbroken, overflow, bad;
@@ -81,10 +84,11 @@ __host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
     v.L = c.L;
     v.s = c.s;
     v.ncyc = c.ncyc;
-    for (int j = 0; j < 2; ++j) {
-        v.ucnt[j] = c.ucnt[j];
-        v.fcnt[j] = c.fcnt[j];
-    }
+    v.rmode = c.rmode;
+    v.rleft = c.rleft;
+    v.rfront = c.rfront;
+    v.rerr = c.rerr;
+    v.rk = c.rk;
     v.xcnt = c.xcnt;
     v.scnt = c.scnt;
     v.changed = v.tight = v.certain = v.nondec = v.pedges = v.ledges = v.maxabsw = 0;
@@ -181,16 +185,26 @@ void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, in
 // spans, nullptr means every span.
 int round_wpt(int n);
 int64_t round_spans(int n);
+// gate (optional): the round kernel runs only if *gate equals its direction
+// (1 push, 2 pull), as set by launch_round_begin.
 void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                       unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
-                      const int* spans, const unsigned* nspans, hipStream_t st);
+                      const int* spans, const unsigned* nspans, const unsigned* gate,
+                      hipStream_t st);
 void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned* acur,
                       unsigned* anext, unsigned char* marks, unsigned long long* pedges,
-                      const int* spans, const unsigned* nspans, hipStream_t st);
+                      const int* spans, const unsigned* nspans, const unsigned* gate,
+                      hipStream_t st);
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                        unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
                        unsigned long long* cedges, const int* spans, const unsigned* nspans,
-                       hipStream_t st);
+                       const unsigned* gate, hipStream_t st);
+// Device-driven rounds: setup stores the counts after the init; begin picks
+// a round's direction (policy 0: push while left >= push_min and 2 * front <
+// left, 1: pull, 2: push) or marks the rebuild done; end books the round.
+void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, hipStream_t st);
+void launch_round_begin(Ctl* ctl, int policy, unsigned push_min, hipStream_t st);
+void launch_round_end(Ctl* ctl, hipStream_t st);
 // Reverse CSR (rin_ptr, rin) of the graph.  With `scratch` of
 // rev_scratch_bytes(n, m) bytes (0 when the plan does not apply) the build
 // is partitioned by head bucket; otherwise it counts and fills with global

@@ -62,90 +62,6 @@ __global__ __launch_bounds__(kWG) void k_validate(int n, int m, const int* __res
 // ---------------------------------------------------------------------------
 // sweep (SPFPassIter): G lanes per vertex, segmented argmin over out-edges
 // ---------------------------------------------------------------------------
-template <int G, typename WT, bool FIRST, bool TIE>
-__global__ __launch_bounds__(kWG) void k_sweep(SweepArgs a, const WT* __restrict__ w)
-{
-    constexpr int VPB = kWG / G;             // vertices per block per step
-    const int64_t L = FIRST ? 1 : a.L;
-    const int64_t W = FIRST ? 0 : a.W;
-    const int lane = threadIdx.x & (G - 1);
-    const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t per = ((int64_t)a.n + gridDim.x - 1) / gridDim.x;
-    const int64_t v0 = (int64_t)b * per;
-    const int64_t v1 = v0 + per < a.n ? v0 + per : a.n;
-    unsigned long long cnt = 0, certain = 0, nondec = 0;
-    unsigned cbroken = 0;
-    for (int64_t vb = v0; vb < v1; vb += VPB) {
-        const int64_t v = vb + threadIdx.x / G;
-        const bool live = v < v1;
-        int beg = 0, end = 0;
-        int64_t own = 0;
-        int cur = -1;
-        if (live) {
-            beg = a.row_ptr[v];
-            end = a.row_ptr[v + 1];
-            if (!FIRST) own = a.V[v];
-            if (TIE) cur = a.pi[v];
-        }
-        int64_t best = INT64_MAX;
-        int bpos = INT32_MAX;
-        for (int e = beg + lane; e < end; e += G) {
-            const int64_t we = wval(w, e, a.neg);
-            const int64_t key = FIRST ? we : a.V[a.col[e]] + L * we - W;
-            if (TIE) {
-                // tie scan: tight edges other than the policy edge.  A tight
-                // self-loop, or a tight edge leaving C, certainly closes a
-                // second critical cycle (every vertex's policy path leads
-                // back to C).
-                const bool tight = key == own && e != cur;
-                if (tight) {
-                    cnt++;
-                    if (a.col[e] == v || (a.onC && a.onC[v])) certain++;
-                    if (a.hop && a.hop[a.col[e]] >= a.hop[v]) nondec++;
-                }
-                if (a.xs) {
-                    const unsigned slot = wave_append(tight, a.xcnt);
-                    if (tight && slot < a.xcap) {
-                        a.xs[slot] = (int)v;
-                        a.ys[slot] = a.col[e];
-                    }
-                }
-            } else if (key < best) {
-                best = key;
-                bpos = e;
-            }
-        }
-        if (TIE) continue;
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) {
-            const int64_t ob = __shfl_xor(best, off, G);
-            const int op = __shfl_xor(bpos, off, G);
-            if (ob < best || (ob == best && op < bpos)) {
-                best = ob;
-                bpos = op;
-            }
-        }
-        if (live && lane == 0 && (FIRST || best < own)) {
-            a.pi[v] = bpos;
-            cnt++;
-            if (!FIRST && a.onC && a.onC[v]) cbroken = 1;
-        }
-    }
-    cnt = block_sum_u64(cnt);
-    const unsigned long long brk = block_sum_u64(cbroken);
-    if (TIE) {
-        certain = block_sum_u64(certain);
-        nondec = block_sum_u64(nondec);
-    }
-    if (threadIdx.x == 0) {
-        CtlLane& ln = my_lane(a.ctl);
-        if (cnt) atomicAdd(TIE ? &ln.tight : &ln.changed, cnt);
-        if (brk) atomicOr(&ln.cbroken, 1u);
-        if (TIE && certain) atomicAdd(&ln.certain, certain);
-        if (TIE && nondec) atomicAdd(&ln.nondec, nondec);
-    }
-}
-
 #ifndef OCM_SWEEP_UNROLL
 #define OCM_SWEEP_UNROLL 2
 #endif
@@ -239,6 +155,95 @@ __global__ __launch_bounds__(kWG) void k_sweep_u(SweepArgs a, const WT* __restri
         CtlLane& ln = my_lane(a.ctl);
         if (cnt) atomicAdd(&ln.changed, cnt);
         if (brk) atomicOr(&ln.cbroken, 1u);
+    }
+}
+
+// Tie scan with U vertices in flight per lane group (as k_sweep_u): counts the
+// tight edges other than the policy edge, those that certainly close a
+// second critical cycle (a tight self-loop, or a tight edge leaving C: every
+// policy path leads back to C), and those whose head is not nearer the
+// source; optionally lists them.
+template <int G, typename WT, int U>
+__global__ __launch_bounds__(kWG) void k_tiescan_u(SweepArgs a, const WT* __restrict__ w)
+{
+    constexpr int VPB = kWG / G;
+    const int64_t L = a.L, W = a.W;
+    const int lane = threadIdx.x & (G - 1);
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t per = ((int64_t)a.n + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)b * per;
+    const int64_t v1 = v0 + per < a.n ? v0 + per : a.n;
+    unsigned long long cnt = 0, certain = 0, nondec = 0;
+    auto edge = [&](int64_t v, int e, int c, int64_t key, int64_t own, int cur, bool onc, int hv) {
+        const bool tight = key == own && e != cur;
+        if (tight) {
+            cnt++;
+            if (c == v || onc) certain++;
+            if (a.hop && a.hop[c] >= hv) nondec++;
+        }
+        if (a.xs) {
+            const unsigned slot = wave_append(tight, a.xcnt);
+            if (tight && slot < a.xcap) {
+                a.xs[slot] = (int)v;
+                a.ys[slot] = c;
+            }
+        }
+    };
+    for (int64_t vb = v0; vb < v1; vb += U * VPB) {
+        int64_t v[U], own[U], w0[U];
+        int beg[U], end[U], cur[U], c0[U], hv[U];
+        bool onc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[u] = vb + u * VPB + threadIdx.x / G;
+            beg[u] = end[u] = 0;
+            own[u] = 0;
+            cur[u] = -1;
+            onc[u] = false;
+            hv[u] = 0;
+            if (v[u] < v1) {
+                beg[u] = a.row_ptr[v[u]];
+                end[u] = a.row_ptr[v[u] + 1];
+                own[u] = a.V[v[u]];
+                cur[u] = a.pi[v[u]];
+                onc[u] = a.onC && a.onC[v[u]];
+                if (a.hop) hv[u] = a.hop[v[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = beg[u] + lane;
+            c0[u] = 0;
+            w0[u] = 0;
+            if (e < end[u]) {
+                w0[u] = wval(w, e, a.neg);
+                c0[u] = a.col[e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = beg[u] + lane;
+            const bool live = e < end[u];
+            const int64_t key = live ? a.V[c0[u]] + L * w0[u] - W : INT64_MAX;
+            // every lane takes part (the list append is a wave operation)
+            edge(v[u], live ? e : -2, c0[u], key, live ? own[u] : INT64_MIN, cur[u], onc[u], hv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            for (int e = beg[u] + lane + G; e < end[u]; e += G) {
+                const int c = a.col[e];
+                edge(v[u], e, c, a.V[c] + L * wval(w, e, a.neg) - W, own[u], cur[u], onc[u], hv[u]);
+            }
+        }
+    }
+    cnt = block_sum_u64(cnt);
+    certain = block_sum_u64(certain);
+    nondec = block_sum_u64(nondec);
+    if (threadIdx.x == 0) {
+        CtlLane& ln = my_lane(a.ctl);
+        if (cnt) atomicAdd(&ln.tight, cnt);
+        if (certain) atomicAdd(&ln.certain, certain);
+        if (nondec) atomicAdd(&ln.nondec, nondec);
     }
 }
 
@@ -705,8 +710,9 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __re
                                                    int* __restrict__ layer, int* __restrict__ pi,
                                                    Ctl* ctl, unsigned long long* ledges,
                                                    const int* __restrict__ spans,
-                                                   const unsigned* nspans)
+                                                   const unsigned* nspans, const unsigned* gate)
 {
+    if (gate && *gate != 2u) return;   // not a pull round (uniform)
     __shared__ RoundLds L;
     __shared__ unsigned nb[kWG * WPT];
     const int64_t words = ((int64_t)n + 31) / 32;
@@ -761,8 +767,9 @@ __global__ __launch_bounds__(kWG) void k_conn_mark(int n, const int* __restrict_
                                                    unsigned char* __restrict__ marks,
                                                    unsigned long long* pedges,
                                                    const int* __restrict__ spans,
-                                                   const unsigned* nspans)
+                                                   const unsigned* nspans, const unsigned* gate)
 {
+    if (gate && *gate != 1u) return;   // not a push round (uniform)
     __shared__ RoundLds L;
     const int64_t words = ((int64_t)n + 31) / 32;
     const int64_t per = (int64_t)kWG * WPT;
@@ -817,8 +824,9 @@ __global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __r
                                                     int* __restrict__ pi, int* __restrict__ layer,
                                                     Ctl* ctl, unsigned long long* cedges,
                                                     const int* __restrict__ spans,
-                                                    const unsigned* nspans)
+                                                    const unsigned* nspans, const unsigned* gate)
 {
+    if (gate && *gate != 1u) return;   // not a push round (uniform)
     __shared__ RoundLds L;
     __shared__ unsigned nb[kWG * WPT];
     const int64_t words = ((int64_t)n + 31) / 32;
@@ -1469,8 +1477,7 @@ __global__ void k_ctl_clear(Ctl* ctl, unsigned what)
         }
         if (what & kClrCount) {
             ctl->ncyc = 0;
-            ctl->ucnt[0] = ctl->ucnt[1] = 0;
-            ctl->fcnt[0] = ctl->fcnt[1] = 0;
+            ctl->rmode = ctl->rleft = ctl->rfront = ctl->rerr = ctl->rk = 0;
         }
     }
 }
@@ -1518,7 +1525,7 @@ static void launch_sweep_t(const SweepArgs& a, const void* w, int G, bool first,
     const WT* ww = (const WT*)w;
 #define OCM_SWEEP_CASE(GG)                                                                        \
     case GG:                                                                                      \
-        if (tie) k_sweep<GG, WT, false, true><<<grid, kWG, 0, st>>>(a, ww);                       \
+        if (tie) k_tiescan_u<GG, WT, OCM_SWEEP_UNROLL><<<grid, kWG, 0, st>>>(a, ww);            \
         else if (first)                                                                           \
             k_sweep_u<GG, WT, true, OCM_SWEEP_UNROLL><<<grid, kWG, 0, st>>>(a, ww);               \
         else k_sweep_u<GG, WT, false, OCM_SWEEP_UNROLL><<<grid, kWG, 0, st>>>(a, ww);             \
@@ -1641,43 +1648,100 @@ static unsigned round_grid(int n, const int* spans)
 
 void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                       unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
-                      const int* spans, const unsigned* nspans, hipStream_t st)
+                      const int* spans, const unsigned* nspans, const unsigned* gate,
+                      hipStream_t st)
 {
     const unsigned grid = round_grid(n, spans);
     if (round_wpt(n) == 2)
         k_conn_pull<2><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer, pi, ctl,
-                                             ledges, spans, nspans);
+                                             ledges, spans, nspans, gate);
     else
         k_conn_pull<1><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer, pi, ctl,
-                                             ledges, spans, nspans);
+                                             ledges, spans, nspans, gate);
 }
 
 void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned* acur,
                       unsigned* anext, unsigned char* marks, unsigned long long* pedges,
-                      const int* spans, const unsigned* nspans, hipStream_t st)
+                      const int* spans, const unsigned* nspans, const unsigned* gate,
+                      hipStream_t st)
 {
     const unsigned grid = round_grid(n, spans);
     if (round_wpt(n) == 2)
         k_conn_mark<2><<<grid, kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks, pedges, spans,
-                                             nspans);
+                                             nspans, gate);
     else
         k_conn_mark<1><<<grid, kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks, pedges, spans,
-                                             nspans);
+                                             nspans, gate);
 }
 
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                        unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
                        unsigned long long* cedges, const int* spans, const unsigned* nspans,
-                       hipStream_t st)
+                       const unsigned* gate, hipStream_t st)
 {
     const unsigned grid = round_grid(n, spans);
     if (round_wpt(n) == 2)
         k_conn_claim<2><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
-                                              ctl, cedges, spans, nspans);
+                                              ctl, cedges, spans, nspans, gate);
     else
         k_conn_claim<1><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
-                                              ctl, cedges, spans, nspans);
+                                              ctl, cedges, spans, nspans, gate);
 }
+
+// Device-driven rebuild rounds (one wave each).
+__global__ void k_round_setup(Ctl* c, unsigned left, unsigned front)
+{
+    if (threadIdx.x == 0) {
+        c->rleft = left;
+        c->rfront = front;
+        c->rerr = 0;
+        c->rk = 0;
+        c->rmode = 0;
+    }
+}
+
+__global__ void k_round_begin(Ctl* c, int policy, unsigned push_min)
+{
+    if (threadIdx.x < kLanes) c->lane[threadIdx.x].got = 0;
+    if (threadIdx.x == 0) {
+        unsigned mode = 0;
+        const unsigned left = c->rleft, front = c->rfront;
+        if (!c->rerr && left > 0) {
+            if (policy == 1) mode = 2;
+            else if (policy == 2) mode = front > 0 ? 1 : 2;
+            else mode = left >= push_min && 2ull * front < left ? 1 : 2;
+        }
+        c->rmode = mode;
+    }
+}
+
+__global__ void k_round_end(Ctl* c)
+{
+    if (threadIdx.x == 0 && c->rmode != 0) {
+        unsigned got = 0;
+        for (int l = 0; l < kLanes; ++l) got += c->lane[l].got;
+        c->rk += 1;
+        if (got == 0) {
+            c->rerr = 1;   // vertices are left that cannot reach C
+        } else {
+            c->rleft -= got;
+            c->rfront = got;
+        }
+        c->rmode = 0;
+    }
+}
+
+void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, hipStream_t st)
+{
+    k_round_setup<<<1, 64, 0, st>>>(ctl, left, front);
+}
+
+void launch_round_begin(Ctl* ctl, int policy, unsigned push_min, hipStream_t st)
+{
+    k_round_begin<<<1, 64, 0, st>>>(ctl, policy, push_min);
+}
+
+void launch_round_end(Ctl* ctl, hipStream_t st) { k_round_end<<<1, 64, 0, st>>>(ctl); }
 
 void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsigned* tot,
                            hipStream_t st)
@@ -1693,7 +1757,11 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
                       hipStream_t st)
 {
     const RevPlan p = rev_plan(n, m);
-    if (p.partition && scratch) {
+    // OCM_REV_BUILD=atomic selects the two-pass atomic build (it also serves
+    // graphs with too many head buckets); both give the same in-edge sets
+    const char* env = getenv("OCM_REV_BUILD");
+    const bool atomic_build = env && env[0] == 'a';
+    if (p.partition && scratch && !atomic_build) {
         auto al = [](size_t b) { return (b + 255) / 256 * 256; };
         char* sp = (char*)scratch;
         int2* pairs = (int2*)sp;
@@ -1908,10 +1976,11 @@ __global__ void k_post_ctl(const Ctl* __restrict__ c, CtlView* dst, unsigned* se
         v.L = c->L;
         v.s = c->s;
         v.ncyc = c->ncyc;
-        for (int j = 0; j < 2; ++j) {
-            v.ucnt[j] = c->ucnt[j];
-            v.fcnt[j] = c->fcnt[j];
-        }
+        v.rmode = c->rmode;
+        v.rleft = c->rleft;
+        v.rfront = c->rfront;
+        v.rerr = c->rerr;
+        v.rk = c->rk;
         v.xcnt = c->xcnt;
         v.scnt = c->scnt;
         *dst = v;

@@ -396,6 +396,56 @@ ocm_status phase_select(Ctx& c, const int* pi, const int* rep, const unsigned ch
     return OCM_OK;
 }
 
+// The rebuild rounds without a host round trip per round: each round's
+// direction is picked on the device (k_round_begin, same rule as the host
+// loop below), the kernels of the other direction leave at once, and the host
+// reads the state back every kRoundsPerRead rounds.  Rounds queued after the
+// last one do nothing.
+constexpr int kRoundsPerRead = 8;
+
+ocm_status connect_rounds_on_device(Ctx& c, int* pi, int* layer, unsigned left, unsigned front,
+                                    int* rounds)
+{
+    Ws& w = c.ws;
+    const int policy = c.connect_mode;   // 0 automatic, 1 pull, 2 push
+    const bool may_push = policy == 2 || (policy == 0 && left >= kPushMinUnattached);
+    if (may_push && !c.rev_built) {
+        ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr, w.rin,
+                              w.marks, w.rscratch, c.st);
+        HIP_TRY(hipGetLastError());
+        c.rev_built = true;
+    }
+    ocm::launch_round_setup(w.ctl, left, front, c.st);
+    const unsigned* gate = &w.ctl->rmode;
+    unsigned long long* pedges = &w.ctl->lane[0].pedges;
+    int k = 0;
+    for (;;) {
+        for (int j = 0; j < kRoundsPerRead; ++j) {
+            ++k;
+            const unsigned* acur = w.abits[k & 1];
+            unsigned* anext = w.abits[(k + 1) & 1];
+            ocm::launch_round_begin(w.ctl, policy, kPushMinUnattached, c.st);
+            if (may_push) {
+                ocm::launch_conn_mark(c.n, w.rin_ptr, w.rin, acur, anext, w.marks, pedges, nullptr,
+                                      nullptr, gate, c.st);
+                ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, w.marks, pi, layer,
+                                       w.ctl, nullptr, nullptr, nullptr, gate, c.st);
+            }
+            ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, layer, pi, w.ctl, nullptr,
+                                  nullptr, nullptr, gate, c.st);
+            ocm::launch_round_end(w.ctl, c.st);
+        }
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        if (c.h.rerr || c.h.rleft == 0) break;
+        if (k > c.n + kRoundsPerRead) return fail(OCM_E_HIP, "rebuild rounds did not finish");
+    }
+    if (rounds) *rounds = (int)c.h.rk;
+    c.connect_rounds += (int)c.h.rk;
+    if (c.h.rerr) return fail(OCM_E_NOT_STRONGLY_CONNECTED, "some vertex cannot reach the chosen cycle");
+    return OCM_OK;
+}
+
 // Rebuild around C: component of C keeps pi, the rest attaches breadth-first.
 // Each round is a pull or a push round (same result, see k_conn_claim).
 ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s, int* pi,
@@ -413,6 +463,7 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
     c.prof.bytes(OCM_K_CONN_PULL, 6.25 * c.n);
     unsigned long long pe0 = c.h.pedges, le0 = c.h.ledges;
     unsigned left = c.h.left, front = c.h.got;
+    if (!c.prof.out && left > 0) return connect_rounds_on_device(c, pi, layer, left, front, rounds);
     const double bitmaps = 0.125 * c.n;   // one attached-vertex bitmap
     unsigned long long* pedges = &w.ctl->lane[0].pedges;
     // the scanned-edge counts only feed the profile's byte figures
@@ -444,17 +495,17 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
         if (push) {
             c.prof.begin(OCM_K_CONN_MARK);
             ocm::launch_conn_mark(c.n, w.rin_ptr, w.rin, acur, anext, w.marks, pedges, nullptr,
-                                  nullptr, c.st);
+                                  nullptr, nullptr, c.st);
             c.prof.end();
             c.prof.begin(OCM_K_CONN_CLAIM);
             ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, w.marks, pi, layer,
-                                   w.ctl, ledges, nullptr, nullptr, c.st);
+                                   w.ctl, ledges, nullptr, nullptr, nullptr, c.st);
             c.prof.end();
             c.push_frontier += front;
         } else {
             c.prof.begin(OCM_K_CONN_PULL);
             ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, layer, pi, w.ctl, ledges,
-                                  nullptr, nullptr, c.st);
+                                  nullptr, nullptr, nullptr, c.st);
             c.prof.end();
         }
         HIP_TRY(hipGetLastError());

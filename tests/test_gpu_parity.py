@@ -219,6 +219,22 @@ def test_cycle_phase_on_functional_graphs(name, succ):
     assert np.array_equal(onc.cpu().numpy(), onc_ref), name
 
 
+@pytest.mark.parametrize("build", ["partitioned", "atomic"])
+def test_reverse_builds_give_identical_results(build, monkeypatch):
+    """Push rounds read in-edges from the reverse CSR; its two builds (head
+    buckets in LDS, or global atomics) must give the oracle's rebuild."""
+    if build == "atomic":
+        monkeypatch.setenv("OCM_REV_BUILD", "atomic")
+    else:
+        monkeypatch.delenv("OCM_REV_BUILD", raising=False)
+    for seed, n in ((3, 70001), (4, 140003)):
+        g = synth.random_digraph(n, 1, 9, 1, 1000, np.int32, seed)
+        sol = native.solve(g.row_ptr, g.col, g.w)
+        r = ocm.min_cycle_mean(*to_dev(g.row_ptr, g.col, g.w), connect="push")
+        assert (r.p, r.q, r.iterations, r.cycle_edges.cpu().tolist()) == \
+            (sol.p, sol.q, sol.iterations, sol.cycle.tolist())
+
+
 def test_phase_entry_points_ignore_stale_workspace_contents():
     """Every entry point starts from a clean control block, whatever the
     workspace held before (regression: a stale overflow flag)."""
