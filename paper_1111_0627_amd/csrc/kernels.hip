@@ -158,88 +158,94 @@ __global__ __launch_bounds__(kWG) void k_sweep_u(SweepArgs a, const WT* __restri
     }
 }
 
-// Tie scan with U vertices in flight per lane group (as k_sweep_u): counts the
-// tight edges other than the policy edge, those that certainly close a
-// second critical cycle (a tight self-loop, or a tight edge leaving C: every
-// policy path leads back to C), and those whose head is not nearer the
-// source; optionally lists them.
-template <int G, typename WT, int U>
-__global__ __launch_bounds__(kWG) void k_tiescan_u(SweepArgs a, const WT* __restrict__ w)
+// Tie scan over a tile: a workgroup takes kWG consecutive vertices, whose
+// out-edges form one contiguous CSR range.  Offsets, own values, policy
+// edges, hop counts and on-C flags go to LDS (one load per thread); the
+// range's edges are then streamed with independent, coalesced loads (each
+// thread every kWG-th edge, 4 in flight) and mapped to their vertex by
+// binary search over the tile's offsets.  Counts the tight edges other than
+// the policy edge, those that certainly close a second critical cycle (a
+// tight self-loop, or a tight edge leaving C: every policy path leads back
+// to C), and those whose head is not nearer the source; optionally lists
+// them.
+struct TileLds {
+    int beg[kWG + 1];
+    long long own[kWG];
+};
+
+__device__ __forceinline__ int tile_owner(const int* beg, int nv, int e)
 {
-    constexpr int VPB = kWG / G;
+    int lo = 0, hi = nv - 1;   // last i with beg[i] <= e
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (beg[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename WT>
+__global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __restrict__ w)
+{
+    __shared__ TileLds T;
+    __shared__ int cur[kWG], hv[kWG];
+    __shared__ unsigned char onc[kWG];
     const int64_t L = a.L, W = a.W;
-    const int lane = threadIdx.x & (G - 1);
-    const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t per = ((int64_t)a.n + gridDim.x - 1) / gridDim.x;
-    const int64_t v0 = (int64_t)b * per;
-    const int64_t v1 = v0 + per < a.n ? v0 + per : a.n;
+    const int64_t v0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWG;
+    const int nv = a.n - v0 < kWG ? (int)(a.n - v0) : kWG;
+    const int t = threadIdx.x;
+    if (t < nv) {
+        T.beg[t] = a.row_ptr[v0 + t];
+        T.own[t] = a.V[v0 + t];
+        cur[t] = a.pi[v0 + t];
+        hv[t] = a.hop ? a.hop[v0 + t] : 0;
+        onc[t] = a.onC ? a.onC[v0 + t] : 0;
+    }
+    if (t == 0) T.beg[nv] = a.row_ptr[v0 + nv];
+    __syncthreads();
+    const int e0 = T.beg[0], e1 = T.beg[nv];
     unsigned long long cnt = 0, certain = 0, nondec = 0;
-    auto edge = [&](int64_t v, int e, int c, int64_t key, int64_t own, int cur, bool onc, int hv) {
-        const bool tight = key == own && e != cur;
-        if (tight) {
-            cnt++;
-            if (c == v || onc) certain++;
-            if (a.hop && a.hop[c] >= hv) nondec++;
-        }
-        if (a.xs) {
-            const unsigned slot = wave_append(tight, a.xcnt);
-            if (tight && slot < a.xcap) {
-                a.xs[slot] = (int)v;
-                a.ys[slot] = c;
-            }
-        }
-    };
-    for (int64_t vb = v0; vb < v1; vb += U * VPB) {
-        int64_t v[U], own[U], w0[U];
-        int beg[U], end[U], cur[U], c0[U], hv[U];
-        bool onc[U];
+    constexpr int U = 4;
+    for (int eb = e0 + t; eb < e1 + 0; eb += U * kWG) {
+        long long key[U];
+        int c[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            v[u] = vb + u * VPB + threadIdx.x / G;
-            beg[u] = end[u] = 0;
-            own[u] = 0;
-            cur[u] = -1;
-            onc[u] = false;
-            hv[u] = 0;
-            if (v[u] < v1) {
-                beg[u] = a.row_ptr[v[u]];
-                end[u] = a.row_ptr[v[u] + 1];
-                own[u] = a.V[v[u]];
-                cur[u] = a.pi[v[u]];
-                onc[u] = a.onC && a.onC[v[u]];
-                if (a.hop) hv[u] = a.hop[v[u]];
+            const int e = eb + u * kWG;
+            key[u] = INT64_MAX;
+            c[u] = 0;
+            if (e < e1) {
+                c[u] = a.col[e];
+                key[u] = a.V[c[u]] + L * wval(w, e, a.neg) - W;
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = beg[u] + lane;
-            c0[u] = 0;
-            w0[u] = 0;
-            if (e < end[u]) {
-                w0[u] = wval(w, e, a.neg);
-                c0[u] = a.col[e];
+            const int e = eb + u * kWG;
+            bool tight = false;
+            int i = 0;
+            if (e < e1) {
+                i = tile_owner(T.beg, nv, e);
+                tight = key[u] == T.own[i] && e != cur[i];
             }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = beg[u] + lane;
-            const bool live = e < end[u];
-            const int64_t key = live ? a.V[c0[u]] + L * w0[u] - W : INT64_MAX;
-            // every lane takes part (the list append is a wave operation)
-            edge(v[u], live ? e : -2, c0[u], key, live ? own[u] : INT64_MIN, cur[u], onc[u], hv[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            for (int e = beg[u] + lane + G; e < end[u]; e += G) {
-                const int c = a.col[e];
-                edge(v[u], e, c, a.V[c] + L * wval(w, e, a.neg) - W, own[u], cur[u], onc[u], hv[u]);
+            if (tight) {
+                cnt++;
+                if (c[u] == v0 + i || onc[i]) certain++;
+                if (a.hop && a.hop[c[u]] >= hv[i]) nondec++;
+            }
+            if (a.xs) {
+                const unsigned slot = wave_append(tight, a.xcnt);
+                if (tight && slot < a.xcap) {
+                    a.xs[slot] = (int)(v0 + i);
+                    a.ys[slot] = c[u];
+                }
             }
         }
     }
     cnt = block_sum_u64(cnt);
     certain = block_sum_u64(certain);
     nondec = block_sum_u64(nondec);
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         CtlLane& ln = my_lane(a.ctl);
         if (cnt) atomicAdd(&ln.tight, cnt);
         if (certain) atomicAdd(&ln.certain, certain);
@@ -1525,8 +1531,7 @@ static void launch_sweep_t(const SweepArgs& a, const void* w, int G, bool first,
     const WT* ww = (const WT*)w;
 #define OCM_SWEEP_CASE(GG)                                                                        \
     case GG:                                                                                      \
-        if (tie) k_tiescan_u<GG, WT, OCM_SWEEP_UNROLL><<<grid, kWG, 0, st>>>(a, ww);            \
-        else if (first)                                                                           \
+        if (first)                                                                                \
             k_sweep_u<GG, WT, true, OCM_SWEEP_UNROLL><<<grid, kWG, 0, st>>>(a, ww);               \
         else k_sweep_u<GG, WT, false, OCM_SWEEP_UNROLL><<<grid, kWG, 0, st>>>(a, ww);             \
         break;
@@ -1558,6 +1563,12 @@ void launch_validate(int n, int m, const int* row_ptr, const int* col, const voi
 void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool first, bool tie,
                   unsigned grid, hipStream_t st)
 {
+    if (tie) {   // tie scan: one workgroup per kWG vertices
+        const unsigned tiles = blocks_for(a.n);
+        if (wtype == kWI64) k_tiescan_tile<long long><<<tiles, kWG, 0, st>>>(a, (const long long*)w);
+        else k_tiescan_tile<int><<<tiles, kWG, 0, st>>>(a, (const int*)w);
+        return;
+    }
     if (wtype == kWI64) launch_sweep_t<long long>(a, w, G, first, tie, grid, st);
     else launch_sweep_t<int>(a, w, G, first, tie, grid, st);
 }
