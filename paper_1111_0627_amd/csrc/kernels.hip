@@ -158,89 +158,163 @@ __global__ __launch_bounds__(kWG) void k_sweep_u(SweepArgs a, const WT* __restri
     }
 }
 
-// Tie scan over a tile: a workgroup takes kWG consecutive vertices, whose
-// out-edges form one contiguous CSR range.  Offsets, own values, policy
-// edges, hop counts and on-C flags go to LDS (one load per thread); the
-// range's edges are then streamed with independent, coalesced loads (each
-// thread every kWG-th edge, 4 in flight) and mapped to their vertex by
-// binary search over the tile's offsets.  Counts the tight edges other than
-// the policy edge, those that certainly close a second critical cycle (a
-// tight self-loop, or a tight edge leaving C: every policy path leads back
-// to C), and those whose head is not nearer the source; optionally lists
-// them.
-struct TileLds {
-    int beg[kWG + 1];
-    long long own[kWG];
-};
+// Sweep over a tile: a workgroup takes kWG consecutive vertices, whose
+// out-edges form one contiguous CSR range.  The range is processed in
+// batches of kTileEdges: every thread loads kTileEdges / kWG edges (col, w,
+// then the gathered V, all independent loads) and stores their keys in LDS;
+// then each thread walks its own vertex's part of the batch in CSR order,
+// keeping the minimum key at the lowest position.  Three dependent global
+// loads per batch instead of per vertex step; same result as k_sweep_u.
+constexpr int kTileEdges = 2048;
 
-__device__ __forceinline__ int tile_owner(const int* beg, int nv, int e)
+template <typename WT, bool FIRST>
+__global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __restrict__ w)
 {
-    int lo = 0, hi = nv - 1;   // last i with beg[i] <= e
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (beg[mid] <= e) lo = mid;
-        else hi = mid - 1;
+    __shared__ int beg[kWG + 1];
+    __shared__ long long key[kTileEdges];
+    const int64_t L = FIRST ? 1 : a.L;
+    const int64_t W = FIRST ? 0 : a.W;
+    const int64_t v0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWG;
+    const int nv = a.n - v0 < kWG ? (int)(a.n - v0) : kWG;
+    const int t = threadIdx.x;
+    long long own = 0, best = INT64_MAX;
+    int pos = INT32_MAX;
+    if (t < nv) {
+        beg[t] = a.row_ptr[v0 + t];
+        if (!FIRST) own = a.V[v0 + t];
     }
-    return lo;
+    if (t == 0) beg[nv] = a.row_ptr[v0 + nv];
+    __syncthreads();
+    const int e0 = beg[0], e1 = beg[nv];
+    const int mb = t < nv ? beg[t] : 0, me = t < nv ? beg[t + 1] : 0;
+    constexpr int U = kTileEdges / kWG;
+    for (int eb = e0; eb < e1; eb += kTileEdges) {
+        const int cnt = e1 - eb < kTileEdges ? e1 - eb : kTileEdges;
+        if (FIRST) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = t + u * kWG;
+                if (j < cnt) key[j] = wval(w, eb + j, a.neg);
+            }
+        } else {
+            int c[U];
+            long long wl[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = t + u * kWG;
+                c[u] = 0;
+                wl[u] = 0;
+                if (j < cnt) {
+                    c[u] = a.col[eb + j];
+                    wl[u] = wval(w, eb + j, a.neg);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = t + u * kWG;
+                if (j < cnt) key[j] = a.V[c[u]] + L * wl[u] - W;
+            }
+        }
+        __syncthreads();
+        // this vertex's edges inside the batch, in CSR order
+        const int lo = mb > eb ? mb : eb, hi = me < eb + cnt ? me : eb + cnt;
+        for (int e = lo; e < hi; ++e) {
+            const long long k = key[e - eb];
+            if (k < best) {
+                best = k;
+                pos = e;
+            }
+        }
+        __syncthreads();
+    }
+    unsigned long long changed = 0;
+    unsigned cbroken = 0;
+    if (t < nv && pos != INT32_MAX && (FIRST || best < own)) {
+        a.pi[v0 + t] = pos;
+        changed = 1;
+        if (!FIRST && a.onC && a.onC[v0 + t]) cbroken = 1;
+    }
+    changed = block_sum_u64(changed);
+    const unsigned long long brk = block_sum_u64(cbroken);
+    if (t == 0) {
+        CtlLane& ln = my_lane(a.ctl);
+        if (changed) atomicAdd(&ln.changed, changed);
+        if (brk) atomicOr(&ln.cbroken, 1u);
+    }
 }
 
+// Tie scan over a tile (batches as k_sweep_tile; the heads are kept in LDS
+// too).  Counts the tight edges other than the policy edge, those that
+// certainly close a second critical cycle (a tight self-loop, or a tight
+// edge leaving C: every policy path leads back to C), and those whose head
+// is not nearer the source; optionally lists them.
 template <typename WT>
 __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __restrict__ w)
 {
-    __shared__ TileLds T;
-    __shared__ int cur[kWG], hv[kWG];
-    __shared__ unsigned char onc[kWG];
+    __shared__ int beg[kWG + 1];
+    __shared__ long long key[kTileEdges];
+    __shared__ int head[kTileEdges];
     const int64_t L = a.L, W = a.W;
     const int64_t v0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWG;
     const int nv = a.n - v0 < kWG ? (int)(a.n - v0) : kWG;
     const int t = threadIdx.x;
+    long long own = 0;
+    int cur = -1, hv = 0;
+    bool onc = false;
     if (t < nv) {
-        T.beg[t] = a.row_ptr[v0 + t];
-        T.own[t] = a.V[v0 + t];
-        cur[t] = a.pi[v0 + t];
-        hv[t] = a.hop ? a.hop[v0 + t] : 0;
-        onc[t] = a.onC ? a.onC[v0 + t] : 0;
+        beg[t] = a.row_ptr[v0 + t];
+        own = a.V[v0 + t];
+        cur = a.pi[v0 + t];
+        if (a.hop) hv = a.hop[v0 + t];
+        onc = a.onC && a.onC[v0 + t];
     }
-    if (t == 0) T.beg[nv] = a.row_ptr[v0 + nv];
+    if (t == 0) beg[nv] = a.row_ptr[v0 + nv];
     __syncthreads();
-    const int e0 = T.beg[0], e1 = T.beg[nv];
+    const int e0 = beg[0], e1 = beg[nv];
+    const int mb = t < nv ? beg[t] : 0, me = t < nv ? beg[t + 1] : 0;
     unsigned long long cnt = 0, certain = 0, nondec = 0;
-    constexpr int U = 4;
-    for (int eb = e0 + t; eb < e1 + 0; eb += U * kWG) {
-        long long key[U];
+    constexpr int U = kTileEdges / kWG;
+    for (int eb = e0; eb < e1; eb += kTileEdges) {
+        const int n_e = e1 - eb < kTileEdges ? e1 - eb : kTileEdges;
         int c[U];
+        long long wl[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = eb + u * kWG;
-            key[u] = INT64_MAX;
+            const int j = t + u * kWG;
             c[u] = 0;
-            if (e < e1) {
-                c[u] = a.col[e];
-                key[u] = a.V[c[u]] + L * wval(w, e, a.neg) - W;
+            wl[u] = 0;
+            if (j < n_e) {
+                c[u] = a.col[eb + j];
+                wl[u] = wval(w, eb + j, a.neg);
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = eb + u * kWG;
-            bool tight = false;
-            int i = 0;
-            if (e < e1) {
-                i = tile_owner(T.beg, nv, e);
-                tight = key[u] == T.own[i] && e != cur[i];
+            const int j = t + u * kWG;
+            if (j < n_e) {
+                key[j] = a.V[c[u]] + L * wl[u] - W;
+                head[j] = c[u];
             }
+        }
+        __syncthreads();
+        const int lo = mb > eb ? mb : eb, hi = me < eb + n_e ? me : eb + n_e;
+        for (int e = lo; e < hi; ++e) {
+            const bool tight = key[e - eb] == own && e != cur;
+            const int h = head[e - eb];
             if (tight) {
                 cnt++;
-                if (c[u] == v0 + i || onc[i]) certain++;
-                if (a.hop && a.hop[c[u]] >= hv[i]) nondec++;
+                if (h == v0 + t || onc) certain++;
+                if (a.hop && a.hop[h] >= hv) nondec++;
             }
-            if (a.xs) {
+            if (a.xs) {   // one counter atomic per wave and step
                 const unsigned slot = wave_append(tight, a.xcnt);
                 if (tight && slot < a.xcap) {
-                    a.xs[slot] = (int)(v0 + i);
-                    a.ys[slot] = c[u];
+                    a.xs[slot] = (int)(v0 + t);
+                    a.ys[slot] = h;
                 }
             }
         }
+        __syncthreads();
     }
     cnt = block_sum_u64(cnt);
     certain = block_sum_u64(certain);
@@ -1563,7 +1637,22 @@ void launch_validate(int n, int m, const int* row_ptr, const int* col, const voi
 void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool first, bool tie,
                   unsigned grid, hipStream_t st)
 {
-    if (tie) {   // tie scan: one workgroup per kWG vertices
+    if (G == 0) {   // sweep over vertex tiles
+        const unsigned tiles = blocks_for(a.n);
+        if (wtype == kWI64) {
+            const long long* ww = (const long long*)w;
+            if (tie) k_tiescan_tile<long long><<<tiles, kWG, 0, st>>>(a, ww);
+            else if (first) k_sweep_tile<long long, true><<<tiles, kWG, 0, st>>>(a, ww);
+            else k_sweep_tile<long long, false><<<tiles, kWG, 0, st>>>(a, ww);
+        } else {
+            const int* ww = (const int*)w;
+            if (tie) k_tiescan_tile<int><<<tiles, kWG, 0, st>>>(a, ww);
+            else if (first) k_sweep_tile<int, true><<<tiles, kWG, 0, st>>>(a, ww);
+            else k_sweep_tile<int, false><<<tiles, kWG, 0, st>>>(a, ww);
+        }
+        return;
+    }
+    if (tie) {   // the tie scan always runs over vertex tiles
         const unsigned tiles = blocks_for(a.n);
         if (wtype == kWI64) k_tiescan_tile<long long><<<tiles, kWG, 0, st>>>(a, (const long long*)w);
         else k_tiescan_tile<int><<<tiles, kWG, 0, st>>>(a, (const int*)w);

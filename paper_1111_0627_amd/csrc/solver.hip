@@ -189,6 +189,7 @@ struct Ctx {
     int G;               // lanes per vertex in the sweep
     int sw;              // bytes per weight
     unsigned sweep_grid;
+    bool tile_sweep = true;   // schedule 0: sweeps over vertex tiles, else G lanes per vertex
     int jump_rounds = 0;
     int connect_rounds = 0;
     int connect_mode = 0;   // 0 auto, 1 pull only, 2 push only
@@ -285,7 +286,8 @@ ocm_status validate(Ctx& c, int check_csr)
 
 // Policy improvement sweep; afterwards c.h.changed / cbroken are current.
 ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long long W, long long L,
-                       int* pi, const unsigned char* onC, bool collect = false)
+                       int* pi, const unsigned char* onC, bool collect = false,
+                       bool with_hop = false)
 {
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrChanged, c.st);
     ocm::SweepArgs a;
@@ -299,7 +301,7 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     a.pi = pi;
     a.onC = onC;
     a.ctl = c.ws.ctl;
-    a.hop = tie ? c.ws.hop : nullptr;
+    a.hop = tie && with_hop ? c.ws.hop : nullptr;
     a.xs = a.ys = nullptr;
     a.xcnt = nullptr;
     a.xcap = 0;
@@ -311,7 +313,7 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     }
     const int cls = tie ? OCM_K_TIESCAN : OCM_K_SWEEP;
     c.prof.begin(cls);
-    ocm::launch_sweep(a, c.w, c.wtype, c.G, first, tie, c.sweep_grid, c.st);
+    ocm::launch_sweep(a, c.w, c.wtype, c.tile_sweep ? 0 : c.G, first, tie, c.sweep_grid, c.st);
     c.prof.end();
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
@@ -647,6 +649,8 @@ ocm_status tie_check(Ctx& c, long long W, long long L, ocm_result* out)
         out->flags |= OCM_F_TIE;
         return OCM_OK;
     }
+    // second scan, now with the hop test (a random read per tight edge)
+    OCM_TRY(phase_sweep(c, false, true, w.V, W, L, w.pi, w.onC, false, true));
     // With hop = policy hops to s, every policy edge lowers hop by one except
     // s's own; a cycle of tight edges other than C, with no tight edge
     // leaving C (certain == 0), needs a tight non-policy edge whose head is
@@ -682,7 +686,7 @@ ocm_status tie_check(Ctx& c, long long W, long long L, ocm_result* out)
         out->flags |= OCM_F_TIE_UNCHECKED;
         return OCM_OK;
     }
-    OCM_TRY(phase_sweep(c, false, true, w.V, W, L, w.pi, w.onC, true));
+    OCM_TRY(phase_sweep(c, false, true, w.V, W, L, w.pi, w.onC, true, true));
     const unsigned kx = c.h.xcnt;
     if (kx != k) return fail(OCM_E_HIP, "tie scan listed a different edge count");
     int* spid = w.layer;
@@ -750,6 +754,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     c.G = choose_lanes(c.n, c.m, o.schedule);
     if (!valid_lanes(c.G)) return fail(OCM_E_INVALID_ARG, "schedule must be a power of two <= 64");
     c.sweep_grid = sweep_grid(c.n, c.G);
+    c.tile_sweep = o.schedule <= 0;
     c.connect_mode = o.connect_mode;
     if (c.connect_mode < 0 || c.connect_mode > 2) return fail(OCM_E_INVALID_ARG, "bad connect_mode");
 
@@ -928,6 +933,7 @@ ocm_status ocm_phase_sweep(const ocm_graph* g, int32_t neg, int32_t first, const
     c.G = choose_lanes(c.n, c.m, schedule);
     if (!valid_lanes(c.G)) return fail(OCM_E_INVALID_ARG, "schedule must be a power of two <= 64");
     c.sweep_grid = sweep_grid(c.n, c.G);
+    c.tile_sweep = schedule <= 0;
     OCM_TRY(phase_sweep(c, first != 0, false, (const long long*)V, W, L, pi, nullptr));
     *changed = (int64_t)c.h.changed;
     return OCM_OK;
