@@ -30,21 +30,38 @@ __global__ __launch_bounds__(kWG) void k_validate(int n, int m, const int* __res
     unsigned err = 0;
     unsigned long long mx = 0;
     const int64_t total = (int64_t)(n > m ? n : m);
-    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * kWG) {
-        if (check_csr && i < n) {
-            int a = row_ptr[i], b = row_ptr[i + 1];
-            if (b < a) err |= kErrBadCsr;
-            if (b == a) err |= kErrNoOut;
-            if (i == 0 && (a != 0 || row_ptr[n] != m)) err |= kErrBadCsr;
-        }
-        if (i < m) {
-            if (check_csr) {
-                int c = col[i];
-                if (c < 0 || c >= n) err |= kErrBadCsr;
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    constexpr int U = 8;   // independent elements in flight per thread
+    for (int64_t ib = (int64_t)blockIdx.x * kWG + threadIdx.x; ib < total; ib += U * stride) {
+        int ra[U], rb[U], c[U];
+        WT wv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = ib + u * stride;
+            ra[u] = rb[u] = c[u] = 0;
+            wv[u] = 0;
+            if (check_csr && i < n) {
+                ra[u] = row_ptr[i];
+                rb[u] = row_ptr[i + 1];
             }
-            unsigned long long a = uabs64((int64_t)w[i]);
-            mx = a > mx ? a : mx;
+            if (i < m) {
+                if (check_csr) c[u] = col[i];
+                wv[u] = w[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = ib + u * stride;
+            if (check_csr && i < n) {
+                if (rb[u] < ra[u]) err |= kErrBadCsr;
+                if (rb[u] == ra[u]) err |= kErrNoOut;
+                if (i == 0 && (ra[u] != 0 || row_ptr[n] != m)) err |= kErrBadCsr;
+            }
+            if (i < m) {
+                if (check_csr && (c[u] < 0 || c[u] >= n)) err |= kErrBadCsr;
+                const unsigned long long a = uabs64((int64_t)wv[u]);
+                mx = a > mx ? a : mx;
+            }
         }
     }
     mx = block_max_u64(mx);
@@ -1250,23 +1267,44 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
                                                   Ctl* ctl)
 {
     unsigned long long act = 0;
-    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * kWG) {
-        Jmp q;
-        const int e = pi[v];
-        const int t = col[e];
-        succ[v] = t;
-        if (v == s) {
-            q.D = 0;
-            q.J = s;
-            q.H = 0;
-        } else {
-            q.D = L * wval(w, e, neg) - W;
-            q.J = t;
-            q.H = 1;
-            act += t != s;
+    constexpr int U = 4;   // independent vertices in flight per thread
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t vb = (int64_t)blockIdx.x * kWG + threadIdx.x; vb < n; vb += U * stride) {
+        int e[U], t[U];
+        long long wv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t v = vb + u * stride;
+            e[u] = v < n ? pi[v] : 0;
         }
-        Q[v] = q;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t v = vb + u * stride;
+            t[u] = 0;
+            wv[u] = 0;
+            if (v < n) {
+                t[u] = col[e[u]];
+                wv[u] = wval(w, e[u], neg);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t v = vb + u * stride;
+            if (v >= n) continue;
+            succ[v] = t[u];
+            Jmp q;
+            if (v == s) {
+                q.D = 0;
+                q.J = s;
+                q.H = 0;
+            } else {
+                q.D = L * wv[u] - W;
+                q.J = t[u];
+                q.H = 1;
+                act += t[u] != s;
+            }
+            Q[v] = q;
+        }
     }
     act = block_sum_u64(act);
     if (threadIdx.x == 0 && act) atomicAdd(&my_lane(ctl).active, (unsigned)act);
