@@ -642,7 +642,7 @@ __global__ __launch_bounds__(kWG) void k_conn_init(const int2* __restrict__ chun
             bool comp = false;
             if (live) {
                 comp = rep[v] == s;
-                layer[v] = comp ? 0 : -1;
+                if (layer) layer[v] = comp ? 0 : -1;
                 onC[v] = (unsigned char)(comp && onc[v]);
                 ncomp += comp;
                 nleft += !comp;
@@ -886,7 +886,6 @@ struct BWs {
     int* rep;
     unsigned char* onc;
     unsigned char* onC;
-    int* layer;
     long long* wsum;
     unsigned* lcnt;
     int2* heads;
@@ -953,7 +952,6 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m)
     w.rep = (int*)take(4 * N);
     w.onc = (unsigned char*)take(N);
     w.onC = (unsigned char*)take(N);
-    w.layer = (int*)take(4 * N);
     w.wsum = (long long*)take(8 * N);
     w.lcnt = (unsigned*)take(4 * N);
     w.heads = (int2*)take(8 * N);
@@ -1198,7 +1196,7 @@ void enqueue_general_head(BCtx& c)
     ocm::launch_fill_u32(ws.abits[0], words, 0xffffffffu, c.st);
     ocm::launch_fill_u32(ws.abits[1], words, 0xffffffffu, c.st);
     ocm::b::k_conn_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep, ws.onc,
-                                                   ws.layer, ws.onC, ws.abits[1], ws.abits[0], cc);
+                                                   nullptr, ws.onC, ws.abits[1], ws.abits[0], cc);
     // the rounds visit only the spans that hold a rebuilt graph
     const int64_t span_verts = (int64_t)32 * ocm::kWG * ocm::round_wpt(c.n);
     ocm::b::k_span_flag<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, span_verts,
@@ -1249,10 +1247,10 @@ ocm_status host_connect(BCtx& c)
         if (push) {
             ocm::launch_conn_mark(c.n, ws.rin_ptr, ws.rin, acur, anext, ws.marks, nullptr, ws.spans,
                                   &ws.bc->nspans, nullptr, c.st);
-            ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, ws.marks, ws.pi, ws.layer,
+            ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, ws.marks, ws.pi, nullptr,
                                    cc, nullptr, ws.spans, &ws.bc->nspans, nullptr, c.st);
         } else {
-            ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, ws.layer, ws.pi, cc,
+            ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, nullptr, ws.pi, cc,
                                   nullptr, ws.spans, &ws.bc->nspans, nullptr, c.st);
         }
         BHIP(hipGetLastError());

@@ -174,7 +174,8 @@ void launch_cyc_sum(int n, const int* rep, const unsigned char* onc, const int* 
 constexpr int kSelectParts = 512;
 void launch_select(const int* cyc_list, const long long* wsum, const unsigned* lcnt, Ctl* ctl,
                    void* scratch, hipStream_t st);
-// Rebuild (breadth-first attachment to C's component).  a[0], a[1]: the two
+// Rebuild (breadth-first attachment to C's component); layer (the round that
+// attached each vertex) may be null.  a[0], a[1]: the two
 // attached-vertex bitmaps (ceil(n/32) words each); marks: push-round mark
 // bytes (n + 16).  Counts go to the control block's lanes: init -> got (C's
 // component) and left (unattached); every round -> got (attached in it).

@@ -731,7 +731,7 @@ __global__ __launch_bounds__(kWG) void k_conn_init(int n, const int* __restrict_
         bool comp = false;
         if (v < n) {
             comp = rep[v] == s;
-            layer[v] = comp ? 0 : -1;
+            if (layer) layer[v] = comp ? 0 : -1;
             if (onC) onC[v] = (unsigned char)(comp && onc && onc[v]);
         }
         const unsigned long long b = __ballot(comp);
@@ -775,7 +775,7 @@ __device__ __forceinline__ unsigned attach_batch(int k, const RoundLds& L, unsig
         if (h != INT32_MAX) {
             const int u = L.todo[i];
             pi[u] = h;
-            layer[u] = k;
+            if (layer) layer[u] = k;
             atomicOr(&nb[(u >> 5) - wbase], 1u << (u & 31));
             ++got;
         }

@@ -809,7 +809,8 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
         s = c.h.s;
         W = c.h.W;
         L = c.h.L;
-        rc = phase_connect(c, w.rep, w.onc, s, w.pi, w.layer, w.onC, nullptr);
+        // the solve itself needs no layers, only the rewired policy
+        rc = phase_connect(c, w.rep, w.onc, s, w.pi, nullptr, w.onC, nullptr);
         if (rc != OCM_OK) break;
         rc = phase_values(c, w.pi, s, W, L, w.V, w.hop, false, nullptr, nullptr);
         if (rc != OCM_OK) break;
