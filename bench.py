@@ -46,7 +46,8 @@ KERNEL_NAMES = {
 
 CSRC = os.path.join(ROOT, "paper_1111_0627_amd", "csrc")
 KERNEL_SYMBOL = {   # profile class -> the kernel whose counters give its traffic
-    "sweep": "k_sweep_u", "conn_mark": "k_conn_mark", "conn_claim": "k_conn_claim",
+    "sweep": "k_sweep_tile", "tiescan": "k_tiescan_tile", "conn_mark": "k_conn_mark",
+    "conn_claim": "k_conn_claim",
     "conn_pull": "k_conn_pull", "values": "k_val_round", "fast": "k_val_round",
     "cycles": "k_pj_round", "reverse": "k_rev_place",
 }
