@@ -29,14 +29,14 @@ def log(*a):
 
 
 KERNEL_NAMES = {
-    "sweep": "k_sweep (policy improvement)",
-    "tiescan": "k_sweep<TIE> (tight-edge count)",
+    "sweep": "k_sweep_tile (policy improvement)",
+    "tiescan": "k_tiescan_tile (tight-edge count)",
     "cycles": "k_pj_init/round/final (policy-graph cycles)",
     "select": "k_cyc_zero/sum + k_select (minimum-mean cycle)",
     "conn_pull": "k_conn_init/pull (rebuild, pull rounds)",
     "conn_mark": "k_conn_mark (rebuild, push marks)",
     "conn_claim": "k_conn_claim (rebuild, push claims)",
-    "reverse": "k_rev_count/fill + scan (reverse CSR)",
+    "reverse": "k_rev_hist/scatter/place (reverse CSR)",
     "values": "k_val_init/round/final (values after a rebuild)",
     "fast": "k_val_init/round/final (values, fast path)",
     "result": "k_cycle_list",
@@ -45,12 +45,32 @@ KERNEL_NAMES = {
 
 
 CSRC = os.path.join(ROOT, "paper_1111_0627_amd", "csrc")
-KERNEL_SYMBOL = {   # profile class -> the kernel whose counters give its traffic
-    "sweep": "k_sweep_tile", "tiescan": "k_tiescan_tile", "conn_mark": "k_conn_mark",
-    "conn_claim": "k_conn_claim",
-    "conn_pull": "k_conn_pull", "values": "k_val_round", "fast": "k_val_round",
-    "cycles": "k_pj_round", "reverse": "k_rev_place",
+# profile class -> (kernel, instantiation suffix) whose counters give its
+# traffic.  The rebuild-round kernels exist twice: "true>" is the copy the
+# device-driven round loop queues (mostly empty launches past the last
+# round), "false>" the one the per-phase profile launches, so only the
+# latter matches the live per-launch timings.
+KERNEL_SYMBOL = {
+    "sweep": ("k_sweep_tile", ""), "tiescan": ("k_tiescan_tile", ""),
+    "conn_mark": ("k_conn_mark", ", false>"), "conn_claim": ("k_conn_claim", ", false>"),
+    "conn_pull": ("k_conn_pull", ", false>"), "values": ("k_val_round", ""),
+    "fast": ("k_val_round", ""), "cycles": ("k_pj_round", ""), "reverse": ("k_rev_place", ""),
 }
+
+
+def kernel_key(name):
+    """Kernel name without return type, namespace and argument list
+    ("k_conn_claim<2, false>")."""
+    name = name.replace("void ", "").split("(")[0].strip()
+    return name[len("ocm::"):] if name.startswith("ocm::") else name
+
+
+def class_kernels(table, cls):
+    """Entries of a per-kernel table that belong to the class's kernel."""
+    if cls not in KERNEL_SYMBOL:
+        return []
+    base, suffix = KERNEL_SYMBOL[cls]
+    return [v for k, v in table.items() if k.split("<")[0] == base and k.endswith(suffix)]
 
 
 def source_digest():
@@ -87,14 +107,70 @@ def load_pmc(workload):
 
 
 def traffic_per_launch(pmc, cls):
-    """Calibrated HBM bytes per launch of the class's kernel, or None."""
-    if not pmc or cls not in KERNEL_SYMBOL:
+    """Calibrated HBM bytes per launch of the class's kernel (averaged over
+    its dispatches), or None."""
+    if not pmc:
         return None
-    k = pmc["kernels"].get(KERNEL_SYMBOL[cls])
-    if not k:
+    ks = class_kernels(pmc["kernels"], cls)
+    if not ks:
         return None
     cal = pmc["calibration"]
-    return 1024.0 * (k["fetch_kib"] * cal["fetch_factor"] + k["write_kib"] * cal["write_factor"])
+    d = sum(k["dispatches"] for k in ks)
+    kib = sum(k["dispatches"] * (k["fetch_kib"] * cal["fetch_factor"] +
+                                 k["write_kib"] * cal["write_factor"]) for k in ks)
+    return 1024.0 * kib / d
+
+
+def load_trace(workload):
+    """Per-kernel calls and average duration from the JSON block of
+    profiles/<workload>_kernel_trace.md; None if absent or from other sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_kernel_trace.md")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.loads(open(path).read().split("```json", 1)[1].split("```", 1)[0])
+    except (IndexError, ValueError):
+        return None
+    return d if d.get("source_sha256") == source_digest() else None
+
+
+def trace_avg_us(trace, cls):
+    """Average duration of the class's kernel in the committed rocprofv3 trace."""
+    if not trace:
+        return None
+    ks = class_kernels(trace["kernels"], cls)
+    calls = sum(k["calls"] for k in ks)
+    return sum(k["total_ns"] for k in ks) / calls / 1e3 if calls else None
+
+
+def summarize_trace(db, out, workload, command, note):
+    """Writes profiles/<workload>_kernel_trace.md from a rocprofv3
+    --kernel-trace database (rocpd SQLite)."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, count(*), sum(end - start) from kernels group by name").fetchall()
+    con.close()
+    per = {}
+    for name, n, t in rows:
+        k = kernel_key(name)
+        a = per.setdefault(k, {"calls": 0, "total_ns": 0})
+        a["calls"] += n
+        a["total_ns"] += t
+    tot = sum(v["total_ns"] for v in per.values())
+    d = {"workload": workload, "source_sha256": source_digest(), "kernels": per}
+    lines = [f"# Kernel trace: {workload}", "", "Command (from the repository root, on one MI355X):",
+             "", "```", command, "```", "", note, "",
+             "| Kernel | Calls | Total (ms) | Average (us) | Share (%) |", "|---|---:|---:|---:|---:|"]
+    for k, v in sorted(per.items(), key=lambda kv: -kv[1]["total_ns"]):
+        if v["total_ns"] < 0.001 * tot:
+            continue
+        lines.append(f"| `{k}` | {v['calls']} | {v['total_ns'] / 1e6:.3f} | "
+                     f"{v['total_ns'] / v['calls'] / 1e3:.1f} | {100.0 * v['total_ns'] / tot:.2f} |")
+    lines += ["", f"All kernels: {tot / 1e6:.3f} ms. Kernels under 0.1 % of it are left out of the "
+              "table (not of the JSON block).", "", "```json", json.dumps(d, indent=1), "```", ""]
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with open(out, "w") as f:
+        f.write("\n".join(lines))
 
 
 def summarize_pmc(fetch_dir, write_dir, out, workload, calib_mb, command):
@@ -110,8 +186,7 @@ def summarize_pmc(fetch_dir, write_dir, out, workload, calib_mb, command):
                 if r["Counter_Name"] != counter:
                     continue
                 name = r["Kernel_Name"]
-                key = "copy" if "copyBuffer" in name else \
-                    name.replace("void ", "").split("(")[0].split("<")[0].split("::")[-1]
+                key = "copy" if "copyBuffer" in name else kernel_key(name)
                 per.setdefault(key, []).append(float(r["Counter_Value"]))
         return per
 
@@ -291,10 +366,20 @@ def main():
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/pmc_<workload>.md from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--pmc-command", default="", help="command line recorded with --pmc-summarize")
+    ap.add_argument("--trace-summarize", metavar="DB",
+                    help="write profiles/<workload>_kernel_trace.md from a rocprofv3 "
+                         "--kernel-trace database and exit")
+    ap.add_argument("--trace-command", default="", help="command line recorded with --trace-summarize")
+    ap.add_argument("--trace-note", default="", help="what the traced run did")
     args = ap.parse_args()
     if args.pmc_summarize:
         summarize_pmc(args.pmc_summarize[0], args.pmc_summarize[1], pmc_file(args.workload),
                       args.workload, args.calib_copy_mb or 1024, args.pmc_command)
+        return
+    if args.trace_summarize:
+        summarize_trace(args.trace_summarize,
+                        os.path.join(ROOT, "profiles", f"{args.workload}_kernel_trace.md"),
+                        args.workload, args.trace_command, args.trace_note)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1"}))
@@ -396,12 +481,14 @@ def main():
         out["phase_launches_per_step"] = {k: v[1] / K for k, v in phase.items() if v[1]}
         out["phase_gbs"] = {k: v[2] / (v[0] / 1e3) / 1e9 for k, v in phase.items() if v[1] and v[0] > 0}
         dom = max((k for k, v in phase.items() if v[1]), key=lambda k: phase[k][0])
-        pmc = load_pmc(name)
+        pmc, trace = load_pmc(name), load_trace(name)
         out["roofline"] = roofline(dom, *phase[dom])
         out["roofline"]["class"] = dom
         out["roofline"]["traffic"] = traffic_per_launch(pmc, dom)
+        out["roofline"]["trace_avg_launch_us"] = trace_avg_us(trace, dom)
         out["roofline_sweep"] = roofline("sweep", *phase["sweep"])
         out["roofline_sweep"]["traffic"] = traffic_per_launch(pmc, "sweep")
+        out["roofline_sweep"]["trace_avg_launch_us"] = trace_avg_us(trace, "sweep")
     if not args.no_adjoint:
         log("[bench] adjoint workload ...")
         out["adjoint"] = bench_adjoint(args.fd_edges)

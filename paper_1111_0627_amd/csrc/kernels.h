@@ -47,6 +47,8 @@ struct alignas(128) CtlLane {
     unsigned overflow;             // values: a value left [-2^62, 2^62]
     unsigned bad;                  // conversion / policy check failure
     unsigned pjc[4];               // cycles: per round parity, image size and M changes
+    unsigned long long rpack;      // connect: (workgroups done << 32) + their attachments,
+                                   //   for this copy, in the running round kernel
 };
 static_assert(sizeof(CtlLane) == 4 * kLaneWords, "one lane per 128-byte line");
 
@@ -61,6 +63,7 @@ struct alignas(128) Ctl {
     unsigned rfront;               //   vertices attached by the last round
     unsigned rerr;                 //   a round attached nobody while vertices were left
     unsigned rk;                   //   rounds run
+    unsigned long long rpack;      //   (lanes done << 32) + their attachments
     unsigned xcnt;                 // tie scan: tight non-policy edges listed
     unsigned scnt;                 // tie check: special vertices
     CtlLane lane[kLanes];
@@ -186,26 +189,29 @@ void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, in
 // spans, nullptr means every span.
 int round_wpt(int n);
 int64_t round_spans(int n);
-// gate (optional): the round kernel runs only if *gate equals its direction
-// (1 push, 2 pull), as set by launch_round_begin.
+// Host-driven round steps (the host picks each round's direction).
 void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                       unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
-                      const int* spans, const unsigned* nspans, const unsigned* gate,
-                      hipStream_t st);
+                      const int* spans, const unsigned* nspans, hipStream_t st);
 void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned* acur,
                       unsigned* anext, unsigned char* marks, unsigned long long* pedges,
-                      const int* spans, const unsigned* nspans, const unsigned* gate,
-                      hipStream_t st);
+                      const int* spans, const unsigned* nspans, hipStream_t st);
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                        unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
                        unsigned long long* cedges, const int* spans, const unsigned* nspans,
-                       const unsigned* gate, hipStream_t st);
-// Device-driven rounds: setup stores the counts after the init; begin picks
-// a round's direction (policy 0: push while left >= push_min and 2 * front <
-// left, 1: pull, 2: push) or marks the rebuild done; end books the round.
-void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, hipStream_t st);
-void launch_round_begin(Ctl* ctl, int policy, unsigned push_min, hipStream_t st);
-void launch_round_end(Ctl* ctl, hipStream_t st);
+                       hipStream_t st);
+// Device-driven rounds: setup stores the counts after the init and picks
+// round 1's direction (policy 0: push while left >= push_min and 2 * front <
+// left, 1: pull, 2: push); launch_round queues round k (a push or pull round
+// as the device decides, nothing once the rebuild is over).  Rounds are
+// queued in order k = 1, 2, ...; with may_push false (no reverse CSR) every
+// round must be a pull round.  Progress: rk, rleft, rerr, rmode.
+void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, int policy, unsigned push_min,
+                        hipStream_t st);
+void launch_round(int k, int n, const int* row_ptr, const int* col, const int* rin_ptr,
+                  const int* rin, const unsigned* acur, unsigned* anext, unsigned char* marks,
+                  int* pi, int* layer, Ctl* ctl, unsigned long long* pedges, int policy,
+                  unsigned push_min, bool may_push, hipStream_t st);
 // Reverse CSR (rin_ptr, rin) of the graph.  With `scratch` of
 // rev_scratch_bytes(n, m) bytes (0 when the plan does not apply) the build
 // is partitioned by head bucket; otherwise it counts and fills with global

@@ -683,6 +683,35 @@ __device__ __forceinline__ void emit_batch(unsigned long long mask, int64_t base
     }
 }
 
+// Edges (or in-edges) per thread in flight in the round kernels' expansions.
+constexpr int kExpand = 4;
+
+// beg[i], off[i] = first position and length of the row of todo[i] (i < cnt),
+// four rows per thread in flight.
+__device__ __forceinline__ void gather_rows(const int* __restrict__ ptr, const int* todo,
+                                            unsigned cnt, int* beg, unsigned* off)
+{
+    constexpr int R = 4;
+    for (unsigned i0 = threadIdx.x; i0 < cnt; i0 += R * kWG) {
+        int a[R], b[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const unsigned i = i0 + j * kWG;
+            const int u = i < cnt ? todo[i] : -1;
+            a[j] = u >= 0 ? ptr[u] : 0;
+            b[j] = u >= 0 ? ptr[u + 1] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const unsigned i = i0 + j * kWG;
+            if (i < cnt) {
+                beg[i] = a[j];
+                off[i] = (unsigned)(b[j] - a[j]);
+            }
+        }
+    }
+}
+
 // For each of the cnt listed vertices, the lowest out-edge whose head is
 // attached (INT32_MAX if none): out-edges spread evenly over the workgroup,
 // LDS atomicMin per vertex.  Returns the number of edges scanned.
@@ -692,19 +721,29 @@ __device__ __forceinline__ unsigned lowest_attached_edges(const int* __restrict_
                                                           const int* todo, unsigned cnt, int* beg,
                                                           unsigned* off, int* best, unsigned* wsum)
 {
-    for (unsigned i = threadIdx.x; i < cnt; i += kWG) {
-        const int u = todo[i];
-        const int b = row_ptr[u];
-        beg[i] = b;
-        off[i] = (unsigned)(row_ptr[u + 1] - b);
-        best[i] = INT32_MAX;
-    }
+    gather_rows(row_ptr, todo, cnt, beg, off);
+    for (unsigned i = threadIdx.x; i < cnt; i += kWG) best[i] = INT32_MAX;
     __syncthreads();
     const unsigned total = block_excl_scan(off, cnt, wsum);
-    for (unsigned t = threadIdx.x; t < total; t += kWG) {
-        const unsigned i = owner_of(off, cnt, t);
-        const int e = beg[i] + (int)(t - off[i]);
-        if (attached(acur, col[e])) atomicMin(&best[i], e);
+    // kExpand edges per thread in flight: their owners, heads and bitmap
+    // words are each fetched for all of them before any is used
+    for (unsigned t0 = threadIdx.x; t0 < total; t0 += kExpand * kWG) {
+        unsigned own[kExpand];
+        int e[kExpand], h[kExpand];
+#pragma unroll
+        for (int j = 0; j < kExpand; ++j) {
+            const unsigned t = t0 + j * kWG;
+            own[j] = t < total ? owner_of(off, cnt, t) : 0;
+            e[j] = beg[own[j]] + (int)(t - off[own[j]]);
+        }
+#pragma unroll
+        for (int j = 0; j < kExpand; ++j) h[j] = t0 + j * kWG < total ? col[e[j]] : -1;
+        unsigned a[kExpand];
+#pragma unroll
+        for (int j = 0; j < kExpand; ++j) a[j] = h[j] >= 0 ? acur[h[j] >> 5] : 0u;
+#pragma unroll
+        for (int j = 0; j < kExpand; ++j)
+            if ((a[j] >> (h[j] & 31)) & 1u) atomicMin(&best[own[j]], e[j]);
     }
     __syncthreads();
     return total;
@@ -799,19 +838,14 @@ __device__ __forceinline__ void for_each_span(const int* __restrict__ spans, con
 
 // Pull round k: the unattached vertices (~acur) of each span scan their
 // out-edges; anext becomes acur plus this round's attachments.
+// Returns the workgroup's attachment count.
 template <int WPT>
-__global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __restrict__ row_ptr,
-                                                   const int* __restrict__ col,
-                                                   const unsigned* __restrict__ acur,
-                                                   unsigned* __restrict__ anext,
-                                                   int* __restrict__ layer, int* __restrict__ pi,
-                                                   Ctl* ctl, unsigned long long* ledges,
-                                                   const int* __restrict__ spans,
-                                                   const unsigned* nspans, const unsigned* gate)
+__device__ __forceinline__ unsigned long long pull_body(
+    int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    const unsigned* __restrict__ acur, unsigned* __restrict__ anext, int* __restrict__ layer,
+    int* __restrict__ pi, unsigned long long* ledges, const int* __restrict__ spans,
+    const unsigned* nspans, RoundLds& L, unsigned* nb)
 {
-    if (gate && *gate != 2u) return;   // not a pull round (uniform)
-    __shared__ RoundLds L;
-    __shared__ unsigned nb[kWG * WPT];
     const int64_t words = ((int64_t)n + 31) / 32;
     const int64_t per = (int64_t)kWG * WPT;
     unsigned got = 0, scanned = 0;
@@ -845,10 +879,8 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __re
             if (w0 + j < words) anext[w0 + j] = a[j] | nb[threadIdx.x * WPT + j];
     });
     const unsigned long long g = block_sum_u64(got);
-    if (threadIdx.x == 0) {
-        if (g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
-        if (ledges && scanned) atomicAdd(my_copy(ledges), (unsigned long long)scanned);
-    }
+    if (threadIdx.x == 0 && ledges && scanned) atomicAdd(my_copy(ledges), (unsigned long long)scanned);
+    return g;
 }
 
 // Push round k, mark: each span lists its frontier vertices (acur & ~anext,
@@ -857,17 +889,14 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __re
 // Attached tails are dropped by the claim, which reads its span of acur
 // anyway.
 template <int WPT>
-__global__ __launch_bounds__(kWG) void k_conn_mark(int n, const int* __restrict__ rin_ptr,
-                                                   const int* __restrict__ rin,
-                                                   const unsigned* __restrict__ acur,
-                                                   unsigned* __restrict__ anext,
-                                                   unsigned char* __restrict__ marks,
-                                                   unsigned long long* pedges,
-                                                   const int* __restrict__ spans,
-                                                   const unsigned* nspans, const unsigned* gate)
+__device__ __forceinline__ void mark_body(int n, const int* __restrict__ rin_ptr,
+                                          const int* __restrict__ rin,
+                                          const unsigned* __restrict__ acur,
+                                          unsigned* __restrict__ anext,
+                                          unsigned char* __restrict__ marks,
+                                          unsigned long long* pedges, const int* __restrict__ spans,
+                                          const unsigned* nspans, RoundLds& L)
 {
-    if (gate && *gate != 1u) return;   // not a push round (uniform)
-    __shared__ RoundLds L;
     const int64_t words = ((int64_t)n + 31) / 32;
     const int64_t per = (int64_t)kWG * WPT;
     unsigned long long scanned = 0;
@@ -889,17 +918,23 @@ __global__ __launch_bounds__(kWG) void k_conn_mark(int n, const int* __restrict_
             emit_batch(mask, w0 * 32, rank, b0, L.todo);
             __syncthreads();
             const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
-            for (unsigned i = threadIdx.x; i < cnt; i += kWG) {
-                const int x = L.todo[i];
-                const int b = rin_ptr[x];
-                L.beg[i] = b;
-                L.off[i] = (unsigned)(rin_ptr[x + 1] - b);
-            }
+            gather_rows(rin_ptr, L.todo, cnt, L.beg, L.off);
             __syncthreads();
             const unsigned tot = block_excl_scan(L.off, cnt, L.wsum);
-            for (unsigned t = threadIdx.x; t < tot; t += kWG) {
-                const unsigned i = owner_of(L.off, cnt, t);
-                marks[rin[L.beg[i] + (int)(t - L.off[i])]] = 1;
+            constexpr int U = 2 * kExpand;
+            for (unsigned t0 = threadIdx.x; t0 < tot; t0 += U * kWG) {
+                int x[U];
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    const unsigned t = t0 + j * kWG;
+                    const unsigned i = t < tot ? owner_of(L.off, cnt, t) : 0;
+                    x[j] = t < tot ? L.beg[i] + (int)(t - L.off[i]) : -1;
+                }
+#pragma unroll
+                for (int j = 0; j < U; ++j) x[j] = x[j] >= 0 ? rin[x[j]] : -1;
+#pragma unroll
+                for (int j = 0; j < U; ++j)
+                    if (x[j] >= 0) marks[x[j]] = 1;
             }
             scanned += tot;
             __syncthreads();
@@ -912,20 +947,15 @@ __global__ __launch_bounds__(kWG) void k_conn_mark(int n, const int* __restrict_
 // the marked vertices that are not attached yet and finds each one's lowest
 // out-edge into the attached set.  One exists: the edge that marked it.  The
 // vertex attaches with it (pi, layer = k) and joins anext.
+// Returns the workgroup's attachment count.
 template <int WPT>
-__global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __restrict__ row_ptr,
-                                                    const int* __restrict__ col,
-                                                    const unsigned* __restrict__ acur,
-                                                    unsigned* __restrict__ anext,
-                                                    unsigned char* __restrict__ marks,
-                                                    int* __restrict__ pi, int* __restrict__ layer,
-                                                    Ctl* ctl, unsigned long long* cedges,
-                                                    const int* __restrict__ spans,
-                                                    const unsigned* nspans, const unsigned* gate)
+__device__ __forceinline__ unsigned long long claim_body(
+    int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    const unsigned* __restrict__ acur, unsigned* __restrict__ anext,
+    unsigned char* __restrict__ marks, int* __restrict__ pi, int* __restrict__ layer,
+    unsigned long long* cedges, const int* __restrict__ spans, const unsigned* nspans, RoundLds& L,
+    unsigned* nb)
 {
-    if (gate && *gate != 1u) return;   // not a push round (uniform)
-    __shared__ RoundLds L;
-    __shared__ unsigned nb[kWG * WPT];
     const int64_t words = ((int64_t)n + 31) / 32;
     const int64_t per = (int64_t)kWG * WPT;
     unsigned got = 0;
@@ -979,10 +1009,151 @@ __global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __r
         }
     });
     const unsigned long long g = block_sum_u64(got);
-    if (threadIdx.x == 0) {
-        if (g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
-        if (cedges && scanned) atomicAdd(my_copy(cedges), scanned);
+    if (threadIdx.x == 0 && cedges && scanned) atomicAdd(my_copy(cedges), scanned);
+    return g;
+}
+
+// Host-driven rounds: one kernel per step.
+template <int WPT>
+__global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __restrict__ row_ptr,
+                                                   const int* __restrict__ col,
+                                                   const unsigned* __restrict__ acur,
+                                                   unsigned* __restrict__ anext,
+                                                   int* __restrict__ layer, int* __restrict__ pi,
+                                                   Ctl* ctl, unsigned long long* ledges,
+                                                   const int* __restrict__ spans,
+                                                   const unsigned* nspans)
+{
+    __shared__ RoundLds L;
+    __shared__ unsigned nb[kWG * WPT];
+    const unsigned long long g =
+        pull_body<WPT>(k, n, row_ptr, col, acur, anext, layer, pi, ledges, spans, nspans, L, nb);
+    if (threadIdx.x == 0 && g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
+}
+
+template <int WPT>
+__global__ __launch_bounds__(kWG) void k_conn_mark(int n, const int* __restrict__ rin_ptr,
+                                                   const int* __restrict__ rin,
+                                                   const unsigned* __restrict__ acur,
+                                                   unsigned* __restrict__ anext,
+                                                   unsigned char* __restrict__ marks,
+                                                   unsigned long long* pedges,
+                                                   const int* __restrict__ spans,
+                                                   const unsigned* nspans)
+{
+    __shared__ RoundLds L;
+    mark_body<WPT>(n, rin_ptr, rin, acur, anext, marks, pedges, spans, nspans, L);
+}
+
+template <int WPT>
+__global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __restrict__ row_ptr,
+                                                    const int* __restrict__ col,
+                                                    const unsigned* __restrict__ acur,
+                                                    unsigned* __restrict__ anext,
+                                                    unsigned char* __restrict__ marks,
+                                                    int* __restrict__ pi, int* __restrict__ layer,
+                                                    Ctl* ctl, unsigned long long* cedges,
+                                                    const int* __restrict__ spans,
+                                                    const unsigned* nspans)
+{
+    __shared__ RoundLds L;
+    __shared__ unsigned nb[kWG * WPT];
+    const unsigned long long g = claim_body<WPT>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
+                                                 cedges, spans, nspans, L, nb);
+    if (threadIdx.x == 0 && g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
+}
+
+// Device-driven rounds.  The control block holds the rounds run (rk), the
+// direction of the next one (rmode: 1 push, 2 pull, 0 the rebuild is over)
+// and its counts; round k's kernels run only while rk + 1 == k and rmode
+// names them, so the host can queue rounds ahead and the ones past the end
+// return at once.  The last workgroup of a round's final kernel books the
+// round (round_close).
+
+// Direction of the next round: policy 0 pushes while many vertices are left
+// and the frontier is small against them, 1 always pulls, 2 always pushes.
+__device__ __forceinline__ unsigned round_mode(unsigned left, unsigned front, int policy,
+                                               unsigned push_min)
+{
+    if (left == 0) return 0;
+    if (policy == 1) return 2;
+    if (policy == 2) return front > 0 ? 1 : 2;
+    return left >= push_min && 2ull * front < left ? 1 : 2;
+}
+
+// Called by thread 0 of every workgroup of round k's final kernel with the
+// workgroup's attachment count g.  The last workgroup to arrive folds the
+// round's attachments, re-arms the counters and picks round k + 1's
+// direction (a round that attached nobody while vertices were left ends the
+// rebuild with rerr set).  Each arrival is one 64-bit atomic adding
+// (1 << 32) + g, so the count travels with the arrival and no fence is
+// needed; arrivals are counted per lane first (same-address atomics
+// serialise), then per lane.
+__device__ __forceinline__ void round_close(Ctl* c, int k, unsigned long long g, int policy,
+                                            unsigned push_min)
+{
+    constexpr unsigned long long kOne = 1ull << 32;
+    const unsigned lane = blockIdx.x & (kLanes - 1);
+    const unsigned in_lane = (gridDim.x - lane + kLanes - 1) / kLanes;
+    const unsigned lanes = gridDim.x < (unsigned)kLanes ? gridDim.x : (unsigned)kLanes;
+    const unsigned long long lp = atomicAdd(&c->lane[lane].rpack, kOne + g);
+    if ((unsigned)(lp >> 32) != in_lane - 1) return;
+    __hip_atomic_store(&c->lane[lane].rpack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long lane_got = (lp & 0xffffffffull) + g;
+    const unsigned long long tp = atomicAdd(&c->rpack, kOne + lane_got);
+    if ((unsigned)(tp >> 32) != lanes - 1) return;
+    __hip_atomic_store(&c->rpack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned got = (unsigned)((tp & 0xffffffffull) + lane_got);
+    c->rk = (unsigned)k;
+    if (got == 0) {
+        c->rerr = 1;
+        c->rmode = 0;
+        return;
     }
+    const unsigned left = c->rleft - got;
+    c->rleft = left;
+    c->rfront = got;
+    c->rmode = round_mode(left, got, policy, push_min);
+}
+
+__device__ __forceinline__ bool round_is(const Ctl* c, int k, unsigned mode)
+{
+    return c->rk + 1 == (unsigned)k && c->rmode == mode;
+}
+
+// Round k's first kernel: the marks of a push round, or a whole pull round.
+template <int WPT>
+__global__ __launch_bounds__(kWG) void k_round_mark_pull(
+    int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    const int* __restrict__ rin_ptr, const int* __restrict__ rin, const unsigned* __restrict__ acur,
+    unsigned* __restrict__ anext, unsigned char* __restrict__ marks, int* __restrict__ pi,
+    int* __restrict__ layer, Ctl* ctl, unsigned long long* pedges, int policy, unsigned push_min)
+{
+    __shared__ RoundLds L;
+    __shared__ unsigned nb[kWG * WPT];
+    if (round_is(ctl, k, 1u)) {
+        mark_body<WPT>(n, rin_ptr, rin, acur, anext, marks, pedges, nullptr, nullptr, L);
+    } else if (round_is(ctl, k, 2u)) {
+        const unsigned long long g = pull_body<WPT>(k, n, row_ptr, col, acur, anext, layer, pi,
+                                                    nullptr, nullptr, nullptr, L, nb);
+        if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min);
+    }
+}
+
+// Round k's second kernel: the claims of a push round.
+template <int WPT>
+__global__ __launch_bounds__(kWG) void k_round_claim(
+    int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    const unsigned* __restrict__ acur, unsigned* __restrict__ anext,
+    unsigned char* __restrict__ marks, int* __restrict__ pi, int* __restrict__ layer, Ctl* ctl,
+    int policy, unsigned push_min)
+{
+    if (!round_is(ctl, k, 1u)) return;
+    __shared__ RoundLds L;
+    __shared__ unsigned nb[kWG * WPT];
+    const unsigned long long g = claim_body<WPT>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
+                                                 nullptr, nullptr, nullptr, L, nb);
+    if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min);
 }
 
 // ---------------------------------------------------------------------------
@@ -1763,10 +1934,13 @@ void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, in
 
 // Words per thread of the round kernels: 2 when one word per thread would
 // need more than 1024 workgroups.
+// One bitmap word (32 vertices) per thread: on the 16.7M-vertex product
+// graph two words per thread (half the workgroups) made the push rounds
+// 20 % slower, the gathers there being latency-bound.
 int round_wpt(int n)
 {
-    const int64_t words = ((int64_t)n + 31) / 32;
-    return words > (int64_t)1024 * kWG ? 2 : 1;
+    (void)n;
+    return 1;
 }
 
 int64_t round_spans(int n)
@@ -1786,100 +1960,62 @@ static unsigned round_grid(int n, const int* spans)
 
 void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                       unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
-                      const int* spans, const unsigned* nspans, const unsigned* gate,
-                      hipStream_t st)
+                      const int* spans, const unsigned* nspans, hipStream_t st)
 {
-    const unsigned grid = round_grid(n, spans);
-    if (round_wpt(n) == 2)
-        k_conn_pull<2><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer, pi, ctl,
-                                             ledges, spans, nspans, gate);
-    else
-        k_conn_pull<1><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer, pi, ctl,
-                                             ledges, spans, nspans, gate);
+    k_conn_pull<1><<<round_grid(n, spans), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer,
+                                                         pi, ctl, ledges, spans, nspans);
 }
 
 void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned* acur,
                       unsigned* anext, unsigned char* marks, unsigned long long* pedges,
-                      const int* spans, const unsigned* nspans, const unsigned* gate,
-                      hipStream_t st)
+                      const int* spans, const unsigned* nspans, hipStream_t st)
 {
-    const unsigned grid = round_grid(n, spans);
-    if (round_wpt(n) == 2)
-        k_conn_mark<2><<<grid, kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks, pedges, spans,
-                                             nspans, gate);
-    else
-        k_conn_mark<1><<<grid, kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks, pedges, spans,
-                                             nspans, gate);
+    k_conn_mark<1><<<round_grid(n, spans), kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks,
+                                                         pedges, spans, nspans);
 }
 
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                        unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
                        unsigned long long* cedges, const int* spans, const unsigned* nspans,
-                       const unsigned* gate, hipStream_t st)
+                       hipStream_t st)
 {
-    const unsigned grid = round_grid(n, spans);
-    if (round_wpt(n) == 2)
-        k_conn_claim<2><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
-                                              ctl, cedges, spans, nspans, gate);
-    else
-        k_conn_claim<1><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
-                                              ctl, cedges, spans, nspans, gate);
+    k_conn_claim<1><<<round_grid(n, spans), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks,
+                                                          pi, layer, ctl, cedges, spans, nspans);
 }
 
 // Device-driven rebuild rounds (one wave each).
-__global__ void k_round_setup(Ctl* c, unsigned left, unsigned front)
+__global__ void k_round_setup(Ctl* c, unsigned left, unsigned front, int policy,
+                              unsigned push_min)
 {
+    if (threadIdx.x < kLanes) c->lane[threadIdx.x].rpack = 0;
     if (threadIdx.x == 0) {
         c->rleft = left;
         c->rfront = front;
         c->rerr = 0;
         c->rk = 0;
-        c->rmode = 0;
+        c->rpack = 0;
+        c->rmode = round_mode(left, front, policy, push_min);
     }
 }
 
-__global__ void k_round_begin(Ctl* c, int policy, unsigned push_min)
+void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, int policy, unsigned push_min,
+                        hipStream_t st)
 {
-    if (threadIdx.x < kLanes) c->lane[threadIdx.x].got = 0;
-    if (threadIdx.x == 0) {
-        unsigned mode = 0;
-        const unsigned left = c->rleft, front = c->rfront;
-        if (!c->rerr && left > 0) {
-            if (policy == 1) mode = 2;
-            else if (policy == 2) mode = front > 0 ? 1 : 2;
-            else mode = left >= push_min && 2ull * front < left ? 1 : 2;
-        }
-        c->rmode = mode;
-    }
+    k_round_setup<<<1, 64, 0, st>>>(ctl, left, front, policy, push_min);
 }
 
-__global__ void k_round_end(Ctl* c)
+void launch_round(int k, int n, const int* row_ptr, const int* col, const int* rin_ptr,
+                  const int* rin, const unsigned* acur, unsigned* anext, unsigned char* marks,
+                  int* pi, int* layer, Ctl* ctl, unsigned long long* pedges, int policy,
+                  unsigned push_min, bool may_push, hipStream_t st)
 {
-    if (threadIdx.x == 0 && c->rmode != 0) {
-        unsigned got = 0;
-        for (int l = 0; l < kLanes; ++l) got += c->lane[l].got;
-        c->rk += 1;
-        if (got == 0) {
-            c->rerr = 1;   // vertices are left that cannot reach C
-        } else {
-            c->rleft -= got;
-            c->rfront = got;
-        }
-        c->rmode = 0;
-    }
+    const unsigned grid = (unsigned)round_spans(n);
+    k_round_mark_pull<1><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, rin_ptr, rin, acur, anext,
+                                               marks, pi, layer, ctl, pedges, policy, push_min);
+    if (may_push)
+        k_round_claim<1><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
+                                               ctl, policy, push_min);
 }
-
-void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, hipStream_t st)
-{
-    k_round_setup<<<1, 64, 0, st>>>(ctl, left, front);
-}
-
-void launch_round_begin(Ctl* ctl, int policy, unsigned push_min, hipStream_t st)
-{
-    k_round_begin<<<1, 64, 0, st>>>(ctl, policy, push_min);
-}
-
-void launch_round_end(Ctl* ctl, hipStream_t st) { k_round_end<<<1, 64, 0, st>>>(ctl); }
 
 void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsigned* tot,
                            hipStream_t st)

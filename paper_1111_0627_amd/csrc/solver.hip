@@ -399,10 +399,10 @@ ocm_status phase_select(Ctx& c, const int* pi, const int* rep, const unsigned ch
 }
 
 // The rebuild rounds without a host round trip per round: each round's
-// direction is picked on the device (k_round_begin, same rule as the host
-// loop below), the kernels of the other direction leave at once, and the host
-// reads the state back every kRoundsPerRead rounds.  Rounds queued after the
-// last one do nothing.
+// direction is picked on the device by the round before it (same rule as the
+// host loop below), two kernels are queued per round (marks or a pull round,
+// then the claims), and the host reads the state back every kRoundsPerRead
+// rounds.  Rounds queued after the last one do nothing.
 constexpr int kRoundsPerRead = 8;
 
 ocm_status connect_rounds_on_device(Ctx& c, int* pi, int* layer, unsigned left, unsigned front,
@@ -417,25 +417,15 @@ ocm_status connect_rounds_on_device(Ctx& c, int* pi, int* layer, unsigned left, 
         HIP_TRY(hipGetLastError());
         c.rev_built = true;
     }
-    ocm::launch_round_setup(w.ctl, left, front, c.st);
-    const unsigned* gate = &w.ctl->rmode;
+    ocm::launch_round_setup(w.ctl, left, front, policy, kPushMinUnattached, c.st);
     unsigned long long* pedges = &w.ctl->lane[0].pedges;
     int k = 0;
     for (;;) {
         for (int j = 0; j < kRoundsPerRead; ++j) {
             ++k;
-            const unsigned* acur = w.abits[k & 1];
-            unsigned* anext = w.abits[(k + 1) & 1];
-            ocm::launch_round_begin(w.ctl, policy, kPushMinUnattached, c.st);
-            if (may_push) {
-                ocm::launch_conn_mark(c.n, w.rin_ptr, w.rin, acur, anext, w.marks, pedges, nullptr,
-                                      nullptr, gate, c.st);
-                ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, w.marks, pi, layer,
-                                       w.ctl, nullptr, nullptr, nullptr, gate, c.st);
-            }
-            ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, layer, pi, w.ctl, nullptr,
-                                  nullptr, nullptr, gate, c.st);
-            ocm::launch_round_end(w.ctl, c.st);
+            ocm::launch_round(k, c.n, c.row_ptr, c.col, w.rin_ptr, w.rin, w.abits[k & 1],
+                              w.abits[(k + 1) & 1], w.marks, pi, layer, w.ctl, pedges, policy,
+                              kPushMinUnattached, may_push, c.st);
         }
         HIP_TRY(hipGetLastError());
         OCM_TRY(read_ctl(c));
@@ -497,17 +487,17 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
         if (push) {
             c.prof.begin(OCM_K_CONN_MARK);
             ocm::launch_conn_mark(c.n, w.rin_ptr, w.rin, acur, anext, w.marks, pedges, nullptr,
-                                  nullptr, nullptr, c.st);
+                                  nullptr, c.st);
             c.prof.end();
             c.prof.begin(OCM_K_CONN_CLAIM);
             ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, w.marks, pi, layer,
-                                   w.ctl, ledges, nullptr, nullptr, nullptr, c.st);
+                                   w.ctl, ledges, nullptr, nullptr, c.st);
             c.prof.end();
             c.push_frontier += front;
         } else {
             c.prof.begin(OCM_K_CONN_PULL);
             ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, layer, pi, w.ctl, ledges,
-                                  nullptr, nullptr, nullptr, c.st);
+                                  nullptr, nullptr, c.st);
             c.prof.end();
         }
         HIP_TRY(hipGetLastError());
@@ -518,15 +508,15 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
             // mark: both bitmaps, then per frontier vertex its offsets and
             // per in-edge the 4-byte tail and its bit, and a mark byte per
             // attached vertex; claim: the mark bytes, then per attached vertex
-            // its offsets, pi and layer, and per scanned out-edge col and a
-            // bit; the new bitmap words
+            // its offsets, pi and (when requested) layer, and per scanned
+            // out-edge col and a bit; the new bitmap words
             const double E = (double)(c.h.pedges - pe0);
             c.prof.bytes(OCM_K_CONN_MARK, 2.0 * bitmaps + 8.0 * front + 4.125 * E + got);
-            c.prof.bytes(OCM_K_CONN_CLAIM, (double)c.n + 16.0 * got + 4.125 * S + bitmaps);
+            c.prof.bytes(OCM_K_CONN_CLAIM, (double)c.n + (layer ? 16.0 : 12.0) * got + 4.125 * S + bitmaps);
         } else {
             // both bitmaps; per unattached vertex its offsets, per scanned
-            // out-edge col and a bit; pi and layer of the attached
-            c.prof.bytes(OCM_K_CONN_PULL, 3.0 * bitmaps + 8.0 * left + 4.125 * S + 8.0 * got);
+            // out-edge col and a bit; pi (and layer) of the attached
+            c.prof.bytes(OCM_K_CONN_PULL, 3.0 * bitmaps + 8.0 * left + 4.125 * S + (layer ? 8.0 : 4.0) * got);
         }
         pe0 = c.h.pedges;
         le0 = c.h.ledges;
