@@ -218,6 +218,7 @@ void launch_round(int k, int n, const int* row_ptr, const int* col, const int* r
 // atomics (deg and tot are its counters).  Also clears the mark bytes.
 struct RevPlan {
     int64_t buckets, chunk, nblk, hist_len;
+    int bits;   // heads per bucket = 2^bits
     bool partition;
 };
 RevPlan rev_plan(int64_t n, int64_t m);

@@ -1186,15 +1186,20 @@ __global__ __launch_bounds__(kWG) void k_rev_fill(int n, const int* __restrict__
 }
 
 // Partitioned build (no global atomics): edges are binned by head bucket
-// (8192 heads) in LDS, scattered bucket by bucket as (head, tail) pairs,
-// and each bucket then counts and places its pairs in LDS.  The order of a
-// vertex's in-edges is arbitrary; the rounds only test membership.
-constexpr int kRevBucketBits = 13;
-constexpr int kRevBucket = 1 << kRevBucketBits;
+// (2^bits heads, bits = 12..14) in LDS, scattered bucket by bucket as
+// (head, tail) pairs, and one workgroup per bucket then counts its pairs per
+// head and places them.  When the bucket's in-edges fit in LDS they are
+// placed there and written out in order (scattered 4-byte stores over a
+// bucket's region in HBM cost several times their size in write traffic).
+// The order of a vertex's in-edges is arbitrary; the rounds only test
+// membership.
+constexpr int kRevMinBits = 12;
+constexpr int kRevMaxBits = 14;
 constexpr int kRevMaxBuckets = 8192;
+constexpr int kPlaceWG = 1024;
 
 __global__ __launch_bounds__(kWG) void k_rev_hist(int64_t m, const int* __restrict__ col,
-                                                  int64_t chunk, int nblk, int B,
+                                                  int64_t chunk, int nblk, int B, int bits,
                                                   unsigned* __restrict__ hist)
 {
     extern __shared__ unsigned h[];   // B counters
@@ -1209,7 +1214,7 @@ __global__ __launch_bounds__(kWG) void k_rev_hist(int64_t m, const int* __restri
         for (int j = 0; j < U; ++j) v[j] = e + j * kWG < e1 ? col[e + j * kWG] : -1;
 #pragma unroll
         for (int j = 0; j < U; ++j)
-            if (v[j] >= 0) atomicAdd(&h[v[j] >> kRevBucketBits], 1u);
+            if (v[j] >= 0) atomicAdd(&h[v[j] >> bits], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < B; i += kWG) hist[(int64_t)i * nblk + blockIdx.x] = h[i];
@@ -1229,7 +1234,7 @@ __device__ __forceinline__ int source_of(const int* __restrict__ row_ptr, int n,
 
 __global__ __launch_bounds__(kWG) void k_rev_scatter(int n, const int* __restrict__ row_ptr,
                                                      const int* __restrict__ col, int64_t m,
-                                                     int64_t chunk, int nblk, int B,
+                                                     int64_t chunk, int nblk, int B, int bits,
                                                      const unsigned* __restrict__ hoff,
                                                      int2* __restrict__ pairs)
 {
@@ -1264,72 +1269,98 @@ __global__ __launch_bounds__(kWG) void k_rev_scatter(int n, const int* __restric
         for (int j = 0; j < U; ++j) {
             const int u = ub + j * kGroups;
             if (v[j] >= 0) {
-                const unsigned pos = atomicAdd(&cur[v[j] >> kRevBucketBits], 1u);
+                const unsigned pos = atomicAdd(&cur[v[j] >> bits], 1u);
                 pairs[pos] = make_int2(v[j], u);
             }
             for (int e = lo[j] + lane + G; e < hi[j]; e += G) {   // out-degree above G
                 const int x = col[e];
-                const unsigned pos = atomicAdd(&cur[x >> kRevBucketBits], 1u);
+                const unsigned pos = atomicAdd(&cur[x >> bits], 1u);
                 pairs[pos] = make_int2(x, u);
             }
         }
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_rev_place(int n, int64_t m, int B, int nblk,
-                                                   const unsigned* __restrict__ hoff,
-                                                   const int2* __restrict__ pairs,
-                                                   int* __restrict__ rin_ptr, int* __restrict__ rin)
+// One workgroup per bucket.  Dynamic LDS: 2^bits head counters, then `cap`
+// staged entries (cap = 0: the bucket is placed straight into rin).
+__global__ __launch_bounds__(kPlaceWG) void k_rev_place(int n, int64_t m, int B, int nblk,
+                                                        int bits, int64_t cap,
+                                                        const unsigned* __restrict__ hoff,
+                                                        const int2* __restrict__ pairs,
+                                                        int* __restrict__ rin_ptr,
+                                                        int* __restrict__ rin)
 {
-    __shared__ unsigned cnt[kRevBucket];
-    __shared__ unsigned wsum[kWG / 64];
+    extern __shared__ unsigned lds[];
+    __shared__ unsigned wsum[kPlaceWG / 64];
+    const int H = 1 << bits;
+    unsigned* cnt = lds;
+    int* stage = (int*)(lds + H);
     const int bkt = blockIdx.x;
-    const int64_t lo = (int64_t)bkt << kRevBucketBits;
-    const int64_t hi = lo + kRevBucket < n ? lo + kRevBucket : n;
+    const int64_t lo = (int64_t)bkt << bits;
+    const int64_t hi = lo + H < n ? lo + H : n;
     const int64_t start = hoff[(int64_t)bkt * nblk];
     const int64_t end = bkt + 1 < B ? (int64_t)hoff[(int64_t)(bkt + 1) * nblk] : m;
-    for (int i = threadIdx.x; i < kRevBucket; i += kWG) cnt[i] = 0;
+    for (int i = threadIdx.x; i < H; i += kPlaceWG) cnt[i] = 0;
     __syncthreads();
-    constexpr int U = 8;   // independent loads in flight per thread
-    for (int64_t p = start + threadIdx.x; p < end; p += U * kWG) {
+    constexpr int U = 4;   // independent loads in flight per thread
+    for (int64_t p = start + threadIdx.x; p < end; p += U * kPlaceWG) {
         int h[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) h[j] = p + j * kWG < end ? pairs[p + j * kWG].x : -1;
+        for (int j = 0; j < U; ++j) h[j] = p + j * kPlaceWG < end ? pairs[p + j * kPlaceWG].x : -1;
 #pragma unroll
         for (int j = 0; j < U; ++j)
             if (h[j] >= 0) atomicAdd(&cnt[h[j] - lo], 1u);
     }
     __syncthreads();
-    // exclusive scan of cnt: each thread owns a run of kRevBucket / kWG heads
-    constexpr int kRun = kRevBucket / kWG;
-    const int r0 = threadIdx.x * kRun;
-    unsigned run = 0;
-    for (int j = 0; j < kRun; ++j) run += cnt[r0 + j];
-    unsigned total = 0;
-    unsigned acc = block_rank(run, wsum, &total);
-    for (int j = 0; j < kRun; ++j) {
+    // exclusive scan of cnt: each thread owns a run of H / kPlaceWG heads
+    const int run = H / kPlaceWG;
+    const int r0 = threadIdx.x * run;
+    unsigned sum = 0;
+    for (int j = 0; j < run; ++j) sum += cnt[r0 + j];
+    const unsigned incl = wave_incl_scan(sum);
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    unsigned acc = incl - sum;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) acc += wsum[w];
+    for (int j = 0; j < run; ++j) {
         const unsigned d = cnt[r0 + j];
         cnt[r0 + j] = acc;
         acc += d;
     }
     __syncthreads();
-    for (int64_t v = lo + threadIdx.x; v < hi; v += kWG) rin_ptr[v] = (int)(start + cnt[v - lo]);
+    for (int64_t v = lo + threadIdx.x; v < hi; v += kPlaceWG) rin_ptr[v] = (int)(start + cnt[v - lo]);
     if (bkt == B - 1 && threadIdx.x == 0) rin_ptr[n] = (int)m;
-    __syncthreads();
-    for (int64_t p = start + threadIdx.x; p < end; p += U * kWG) {
+    const bool staged = end - start <= cap;   // uniform
+    int* out = staged ? stage : rin + start;
+    for (int64_t p = start + threadIdx.x; p < end; p += U * kPlaceWG) {
         int2 q[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) q[j] = p + j * kWG < end ? pairs[p + j * kWG] : make_int2(-1, 0);
+        for (int j = 0; j < U; ++j)
+            q[j] = p + j * kPlaceWG < end ? pairs[p + j * kPlaceWG] : make_int2(-1, 0);
 #pragma unroll
         for (int j = 0; j < U; ++j)
-            if (q[j].x >= 0) rin[start + atomicAdd(&cnt[q[j].x - lo], 1u)] = q[j].y;
+            if (q[j].x >= 0) out[atomicAdd(&cnt[q[j].x - lo], 1u)] = q[j].y;
+    }
+    if (staged) {
+        __syncthreads();
+        const int len = (int)(end - start);
+        for (int i = threadIdx.x; i < len; i += kPlaceWG) rin[start + i] = stage[i];
     }
 }
 
 RevPlan rev_plan(int64_t n, int64_t m)
 {
     RevPlan p;
-    p.buckets = (n + kRevBucket - 1) / kRevBucket;
+    int bits = kRevMinBits;
+    while (bits < kRevMaxBits && ((n + (1 << bits) - 1) >> bits) > kRevMaxBuckets) ++bits;
+    // OCM_REV_BUCKET_BITS raises the bucket size (up to 2^kRevMaxBits heads),
+    // so that small graphs reach the placements of large ones
+    if (const char* env = getenv("OCM_REV_BUCKET_BITS")) {
+        const int b = atoi(env);
+        if (b > bits && b <= kRevMaxBits) bits = b;
+    }
+    p.bits = bits;
+    p.buckets = (n + (1 << bits) - 1) >> bits;
     int64_t chunk = 65536;
     while ((m + chunk - 1) / chunk > 2048) chunk <<= 1;
     p.chunk = chunk;
@@ -2044,12 +2075,26 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
         unsigned* htot = (unsigned*)((char*)hoff + al(4 * (size_t)p.hist_len));
         const size_t lds = 4 * (size_t)p.buckets;
         k_rev_hist<<<(unsigned)p.nblk, kWG, lds, st>>>(m, col, p.chunk, (int)p.nblk,
-                                                       (int)p.buckets, hist);
+                                                       (int)p.buckets, p.bits, hist);
         launch_exclusive_scan(p.hist_len, hist, hoff, htot, st);
         k_rev_scatter<<<(unsigned)p.nblk, kWG, lds, st>>>(n, row_ptr, col, m, p.chunk,
-                                                          (int)p.nblk, (int)p.buckets, hoff, pairs);
-        k_rev_place<<<(unsigned)p.buckets, kWG, 0, st>>>(n, m, (int)p.buckets, (int)p.nblk, hoff,
-                                                         pairs, rin_ptr, rin);
+                                                          (int)p.nblk, (int)p.buckets, p.bits,
+                                                          hoff, pairs);
+        // the placement's LDS: head counters, then as many staged entries as
+        // the device's per-workgroup limit leaves room for
+        const size_t counters = (size_t)4 << p.bits;
+        int limit = 65536, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            limit = 65536;
+        const size_t room = (size_t)limit - 1024;   // static LDS of the kernel
+        const int64_t cap = room > counters ? (int64_t)((room - counters) / 4) : 0;
+        const size_t place_lds = counters + 4 * (size_t)cap;
+        if (place_lds > 65536)
+            (void)hipFuncSetAttribute((const void*)k_rev_place,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)place_lds);
+        k_rev_place<<<(unsigned)p.buckets, kPlaceWG, place_lds, st>>>(
+            n, m, (int)p.buckets, (int)p.nblk, p.bits, cap, hoff, pairs, rin_ptr, rin);
     } else {
         const int64_t len = (int64_t)n + 1;
         k_fill_u32<<<stride_grid(len), kWG, 0, st>>>(len, deg, 0u);

@@ -219,18 +219,39 @@ def test_cycle_phase_on_functional_graphs(name, succ):
     assert np.array_equal(onc.cpu().numpy(), onc_ref), name
 
 
-@pytest.mark.parametrize("build", ["partitioned", "atomic"])
+def _hub_graph(n, seed):
+    """A ring, an edge from every vertex into vertex 0 and 0..3 random edges
+    per vertex: vertex 0's bucket holds more in-edges than LDS can stage."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for u in range(n):
+        extra = rng.integers(0, n, size=int(rng.integers(0, 4)))
+        rows.append(np.concatenate(([(u + 1) % n, 0], extra)).astype(np.int32))
+    deg = np.array([len(r) for r in rows], dtype=np.int64)
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum(deg)
+    col = np.concatenate(rows).astype(np.int32)
+    w = rng.integers(-1000, 1000, size=len(col)).astype(np.int32)
+    return row_ptr, col, w
+
+
+@pytest.mark.parametrize("build", ["partitioned", "bucket13", "bucket14", "atomic"])
 def test_reverse_builds_give_identical_results(build, monkeypatch):
-    """Push rounds read in-edges from the reverse CSR; its two builds (head
-    buckets in LDS, or global atomics) must give the oracle's rebuild."""
+    """Push rounds read in-edges from the reverse CSR; its builds (head
+    buckets of 2^12..2^14 heads placed in LDS or straight into HBM, or global
+    atomics) must all give the oracle's rebuild."""
+    monkeypatch.delenv("OCM_REV_BUILD", raising=False)
+    monkeypatch.delenv("OCM_REV_BUCKET_BITS", raising=False)
     if build == "atomic":
         monkeypatch.setenv("OCM_REV_BUILD", "atomic")
-    else:
-        monkeypatch.delenv("OCM_REV_BUILD", raising=False)
-    for seed, n in ((3, 70001), (4, 140003)):
-        g = synth.random_digraph(n, 1, 9, 1, 1000, np.int32, seed)
-        sol = native.solve(g.row_ptr, g.col, g.w)
-        r = ocm.min_cycle_mean(*to_dev(g.row_ptr, g.col, g.w), connect="push")
+    elif build.startswith("bucket"):
+        monkeypatch.setenv("OCM_REV_BUCKET_BITS", build[len("bucket"):])
+    cases = [synth.random_digraph(n, 1, 9, 1, 1000, np.int32, seed)
+             for seed, n in ((3, 70001), (4, 140003))]
+    cases = [(g.row_ptr, g.col, g.w) for g in cases] + [_hub_graph(70001, 5)]
+    for row_ptr, col, w in cases:
+        sol = native.solve(row_ptr, col, w)
+        r = ocm.min_cycle_mean(*to_dev(row_ptr, col, w), connect="push")
         assert (r.p, r.q, r.iterations, r.cycle_edges.cpu().tolist()) == \
             (sol.p, sol.q, sol.iterations, sol.cycle.tolist())
 
