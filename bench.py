@@ -46,15 +46,13 @@ KERNEL_NAMES = {
 
 CSRC = os.path.join(ROOT, "paper_1111_0627_amd", "csrc")
 # profile class -> (kernel, instantiation suffix) whose counters give its
-# traffic.  The rebuild-round kernels exist twice: "true>" is the copy the
-# device-driven round loop queues (mostly empty launches past the last
-# round), "false>" the one the per-phase profile launches, so only the
-# latter matches the live per-launch timings.
+# traffic: the kernels the per-phase profile launches (the device-driven
+# round loops use k_round_*, k_val_round_dev and k_pj_round_dev instead).
 KERNEL_SYMBOL = {
     "sweep": ("k_sweep_tile", ""), "tiescan": ("k_tiescan_tile", ""),
-    "conn_mark": ("k_conn_mark", ", false>"), "conn_claim": ("k_conn_claim", ", false>"),
-    "conn_pull": ("k_conn_pull", ", false>"), "values": ("k_val_round", ""),
-    "fast": ("k_val_round", ""), "cycles": ("k_pj_round", ""), "reverse": ("k_rev_place", ""),
+    "conn_mark": ("k_conn_mark", ""), "conn_claim": ("k_conn_claim", ""),
+    "conn_pull": ("k_conn_pull", ""), "values": ("k_val_round", ""),
+    "fast": ("k_val_round", ""), "cycles": ("k_pj_round_tagged", ""), "reverse": ("k_rev_place", ""),
 }
 
 

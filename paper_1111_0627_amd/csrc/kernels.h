@@ -47,8 +47,8 @@ struct alignas(128) CtlLane {
     unsigned overflow;             // values: a value left [-2^62, 2^62]
     unsigned bad;                  // conversion / policy check failure
     unsigned pjc[4];               // cycles: per round parity, image size and M changes
-    unsigned long long rpack;      // connect: (workgroups done << 32) + their attachments,
-                                   //   for this copy, in the running round kernel
+    unsigned long long rpack;      // device-driven rounds: this copy's workgroups done with
+                                   //   the running round kernel, and their counts
 };
 static_assert(sizeof(CtlLane) == 4 * kLaneWords, "one lane per 128-byte line");
 
@@ -63,7 +63,11 @@ struct alignas(128) Ctl {
     unsigned rfront;               //   vertices attached by the last round
     unsigned rerr;                 //   a round attached nobody while vertices were left
     unsigned rk;                   //   rounds run
-    unsigned long long rpack;      //   (lanes done << 32) + their attachments
+    unsigned long long rpack;      //   lanes done with a round kernel, and their counts
+    unsigned jk;                   // jump rounds on the device (values, cycles): rounds run
+    unsigned jmode;                //   1 while rounds are left, 0 once they are over
+    unsigned jlast;                //   the last round's count (unfinished vertices, image size)
+    unsigned jstall;               //   values: a round finished no vertex
     unsigned xcnt;                 // tie scan: tight non-policy edges listed
     unsigned scnt;                 // tie check: special vertices
     CtlLane lane[kLanes];
@@ -75,6 +79,7 @@ struct CtlView {
     int s;
     unsigned ncyc;
     unsigned rmode, rleft, rfront, rerr, rk;
+    unsigned jk, jmode, jlast, jstall;
     unsigned xcnt, scnt;
     unsigned long long changed, tight, certain, nondec, pedges, ledges, maxabsw;
     unsigned active, active2, got, left, err, cbroken, overflow, bad;
@@ -92,6 +97,10 @@ __host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
     v.rfront = c.rfront;
     v.rerr = c.rerr;
     v.rk = c.rk;
+    v.jk = c.jk;
+    v.jmode = c.jmode;
+    v.jlast = c.jlast;
+    v.jstall = c.jstall;
     v.xcnt = c.xcnt;
     v.scnt = c.scnt;
     v.changed = v.tight = v.certain = v.nondec = v.pedges = v.ledges = v.maxabsw = 0;
@@ -167,6 +176,20 @@ void launch_pj_round(int n, const unsigned long long* Pin, unsigned long long* P
 void launch_pj_round_tagged(int n, int r, const unsigned long long* Pin, unsigned long long* Pout,
                             const unsigned char* tprev, unsigned char* tcur, unsigned* cnt,
                             hipStream_t st);
+// Device-driven jump rounds (cycles and values): setup arms round 1 (for
+// values only if the init left unfinished vertices); round r runs only if it
+// is the next one and the rounds are not over; the final runs once they are,
+// on the buffer of the last round run (round r reads buffer (r-1)&1 and
+// writes r&1).  Progress: jk, jmode, jstall.
+void launch_jump_setup(Ctl* ctl, bool values, hipStream_t st);
+void launch_pj_round_dev(int n, int r, const unsigned long long* Pin, unsigned long long* Pout,
+                         const unsigned char* tprev, unsigned char* tcur, Ctl* ctl, hipStream_t st);
+void launch_pj_final_dev(int n, const unsigned long long* P0, const unsigned long long* P1, int K,
+                         int* rep, unsigned char* onc, const Ctl* ctl, hipStream_t st);
+void launch_val_round_dev(int n, int s, int r, const Jmp* Qin, Jmp* Qout, Ctl* ctl,
+                          hipStream_t st);
+void launch_val_final_dev(int n, const Jmp* Q0, const Jmp* Q1, long long* V, int* hop, Ctl* ctl,
+                          hipStream_t st);
 void launch_pj_final(int n, const unsigned long long* P, int* rep, unsigned char* onc,
                      hipStream_t st);
 void launch_cyc_zero(int n, const int* rep, const unsigned char* onc, long long* wsum,

@@ -345,6 +345,65 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
 }
 
 // ---------------------------------------------------------------------------
+// Device-driven rounds (rebuild, values, cycles): the host queues several
+// rounds ahead; a round kernel runs only while the control block says its
+// round is next, and the last of its workgroups to finish books the round.
+// Each workgroup's thread 0 arrives with one 64-bit atomic adding
+// (1 << 48) + (flag << 32) + count, so its counts travel with the arrival
+// and no fence is needed.  Arrivals are counted per lane first (same-address
+// atomics serialise), then per lane.  Counts must sum below 2^32, flags
+// below 2^16.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kArrive = 1ull << 48;
+
+__device__ __forceinline__ unsigned long long arrival_word(unsigned long long count, unsigned flag)
+{
+    return count + ((unsigned long long)flag << 32);
+}
+
+// True for the grid's last arrival, which gets the summed word (arrival
+// counts removed) in *total and leaves the counters at zero.
+__device__ __forceinline__ bool last_arrival(Ctl* c, unsigned long long word,
+                                             unsigned long long* total)
+{
+    const unsigned lane = blockIdx.x & (kLanes - 1);
+    const unsigned in_lane = (gridDim.x - lane + kLanes - 1) / kLanes;
+    const unsigned lanes = gridDim.x < (unsigned)kLanes ? gridDim.x : (unsigned)kLanes;
+    const unsigned long long lp = atomicAdd(&c->lane[lane].rpack, word + kArrive);
+    if ((unsigned)(lp >> 48) != in_lane - 1) return false;
+    __hip_atomic_store(&c->lane[lane].rpack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long lane_sum = lp + word + kArrive - (unsigned long long)in_lane * kArrive;
+    const unsigned long long tp = atomicAdd(&c->rpack, lane_sum + kArrive);
+    if ((unsigned)(tp >> 48) != lanes - 1) return false;
+    __hip_atomic_store(&c->rpack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *total = tp - (unsigned long long)(lanes - 1) * kArrive + lane_sum;
+    return true;
+}
+
+// Is round r of the device-driven jump rounds the next one?
+__device__ __forceinline__ bool jump_round_is(const Ctl* c, int r)
+{
+    return c->jk + 1 == (unsigned)r && c->jmode == 1u;
+}
+
+// Start of device-driven jump rounds.  values: round 1 runs if init left
+// unfinished vertices (their count, in the lanes' active, becomes jlast);
+// cycles: round 1 runs.
+__global__ void k_jump_setup(Ctl* c, int values)
+{
+    if (threadIdx.x < kLanes) c->lane[threadIdx.x].rpack = 0;
+    if (threadIdx.x == 0) {
+        unsigned act = 0;
+        for (int l = 0; l < kLanes; ++l) act += c->lane[l].active;
+        c->rpack = 0;
+        c->jk = 0;
+        c->jstall = 0;
+        c->jlast = values ? act : 0u;
+        c->jmode = values ? (act > 0 ? 1u : 0u) : 1u;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // cycles: pointer jumping over the policy graph.  Entry P[v] packs
 // (J = succ^(2^k)(v), M = min vertex among the first 2^k vertices of v's
 // policy path).  After K rounds with 2^K >= n, J is on v's cycle and M at a
@@ -387,28 +446,29 @@ __global__ __launch_bounds__(kWG) void k_pj_init(int n, const int* __restrict__ 
 
 constexpr int kJumpUnroll = 4;   // entries in flight per thread in grid-stride jump rounds
 
-// cnt = {image count, M changes} of this round; nxt = the next round's pair
 __global__ __launch_bounds__(kWG) void k_pj_round(int n, const unsigned long long* __restrict__ Pin,
-                                                  unsigned long long* __restrict__ Pout,
-                                                  const unsigned char* __restrict__ tprev,
-                                                  unsigned char* __restrict__ tcur,
-                                                  unsigned char tag_prev, unsigned char tag_cur,
-                                                  unsigned* cnt, unsigned* nxt)
+                                                  unsigned long long* __restrict__ Pout)
 {
-    if (tprev == nullptr) {
-        const int v = blockIdx.x * kWG + threadIdx.x;
-        if (v >= n) return;
-        const unsigned long long p = Pin[v];
-        const int j = (int)(p >> 32);
-        const unsigned long long q = Pin[j];
-        const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
-        Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
-        return;
-    }
-    if (blockIdx.x == 0 && threadIdx.x < kLanes) {
-        nxt[threadIdx.x * kLaneWords] = 0;
-        nxt[threadIdx.x * kLaneWords + 1] = 0;
-    }
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v >= n) return;
+    const unsigned long long p = Pin[v];
+    const int j = (int)(p >> 32);
+    const unsigned long long q = Pin[j];
+    const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
+    Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
+}
+
+// A jump round with the stop test's tags: image(J) of this round is tagged
+// tag_cur in tcur; returns (in thread 0) the vertices tagged tag_prev in
+// tprev (the previous image) and the M changes.
+__device__ __forceinline__ void pj_tagged_body(int n, const unsigned long long* __restrict__ Pin,
+                                               unsigned long long* __restrict__ Pout,
+                                               const unsigned char* __restrict__ tprev,
+                                               unsigned char* __restrict__ tcur,
+                                               unsigned char tag_prev, unsigned char tag_cur,
+                                               unsigned long long* img_out,
+                                               unsigned long long* chg_out)
+{
     unsigned long long img = 0, chg = 0;
     // grid-stride with kJumpUnroll independent entries in flight per thread
     const int64_t stride = (int64_t)gridDim.x * kWG;
@@ -439,8 +499,23 @@ __global__ __launch_bounds__(kWG) void k_pj_round(int n, const unsigned long lon
             }
         }
     }
-    img = block_sum_u64(img);
-    chg = block_sum_u64(chg);
+    *img_out = block_sum_u64(img);
+    *chg_out = block_sum_u64(chg);
+}
+
+// Host-driven: cnt = {image count, M changes} of this round; nxt = the next
+// round's pair (cleared here).
+__global__ __launch_bounds__(kWG) void k_pj_round_tagged(
+    int n, const unsigned long long* __restrict__ Pin, unsigned long long* __restrict__ Pout,
+    const unsigned char* __restrict__ tprev, unsigned char* __restrict__ tcur,
+    unsigned char tag_prev, unsigned char tag_cur, unsigned* cnt, unsigned* nxt)
+{
+    if (blockIdx.x == 0 && threadIdx.x < kLanes) {
+        nxt[threadIdx.x * kLaneWords] = 0;
+        nxt[threadIdx.x * kLaneWords + 1] = 0;
+    }
+    unsigned long long img, chg;
+    pj_tagged_body(n, Pin, Pout, tprev, tcur, tag_prev, tag_cur, &img, &chg);
     if (threadIdx.x == 0) {
         unsigned* mine = my_copy(cnt);
         if (img) atomicAdd(&mine[0], (unsigned)img);
@@ -448,10 +523,46 @@ __global__ __launch_bounds__(kWG) void k_pj_round(int n, const unsigned long lon
     }
 }
 
+// Device-driven round r: the last workgroup applies the stop test (the
+// image size repeated and no M changed) and ends the rounds when it holds.
+__global__ __launch_bounds__(kWG) void k_pj_round_dev(
+    int n, int r, const unsigned long long* __restrict__ Pin, unsigned long long* __restrict__ Pout,
+    const unsigned char* __restrict__ tprev, unsigned char* __restrict__ tcur, Ctl* ctl)
+{
+    if (!jump_round_is(ctl, r)) return;
+    unsigned long long img, chg;
+    pj_tagged_body(n, Pin, Pout, tprev, tcur, (unsigned char)r, (unsigned char)(r + 1), &img, &chg);
+    if (threadIdx.x != 0) return;
+    unsigned long long tot;
+    if (!last_arrival(ctl, arrival_word(img, chg != 0), &tot)) return;
+    const unsigned image = (unsigned)tot;
+    const bool changed = ((tot >> 32) & 0xffffu) != 0;
+    const bool stop = r >= 2 && image == ctl->jlast && !changed;
+    ctl->jlast = image;
+    ctl->jk = (unsigned)r;
+    if (stop) ctl->jmode = 0;
+}
+
 __global__ __launch_bounds__(kWG) void k_pj_final(int n, const unsigned long long* __restrict__ P,
                                                   int* __restrict__ rep,
                                                   unsigned char* __restrict__ onc)
 {
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v >= n) return;
+    const int c = (int)(P[v] >> 32);
+    rep[v] = (int)(unsigned)P[c];
+    onc[c] = 1;
+}
+
+// Device-driven: runs once the rounds are over (stopped, or all K run), on
+// the entries of the last round run.
+__global__ __launch_bounds__(kWG) void k_pj_final_dev(int n, const unsigned long long* __restrict__ P0,
+                                                      const unsigned long long* __restrict__ P1,
+                                                      int K, int* __restrict__ rep,
+                                                      unsigned char* __restrict__ onc, const Ctl* ctl)
+{
+    if (ctl->jmode != 0 && ctl->jk != (unsigned)K) return;
+    const unsigned long long* __restrict__ P = (ctl->jk & 1) ? P1 : P0;
     const int v = blockIdx.x * kWG + threadIdx.x;
     if (v >= n) return;
     const int c = (int)(P[v] >> 32);
@@ -1063,11 +1174,10 @@ __global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __r
     if (threadIdx.x == 0 && g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
 }
 
-// Device-driven rounds.  The control block holds the rounds run (rk), the
-// direction of the next one (rmode: 1 push, 2 pull, 0 the rebuild is over)
-// and its counts; round k's kernels run only while rk + 1 == k and rmode
-// names them, so the host can queue rounds ahead and the ones past the end
-// return at once.  The last workgroup of a round's final kernel books the
+// Device-driven rebuild rounds.  The control block holds the rounds run
+// (rk), the direction of the next one (rmode: 1 push, 2 pull, 0 the rebuild
+// is over) and its counts; round k's kernels run only while rk + 1 == k and
+// rmode names them.  The last workgroup of a round's final kernel books the
 // round (round_close).
 
 // Direction of the next round: policy 0 pushes while many vertices are left
@@ -1082,28 +1192,15 @@ __device__ __forceinline__ unsigned round_mode(unsigned left, unsigned front, in
 }
 
 // Called by thread 0 of every workgroup of round k's final kernel with the
-// workgroup's attachment count g.  The last workgroup to arrive folds the
-// round's attachments, re-arms the counters and picks round k + 1's
-// direction (a round that attached nobody while vertices were left ends the
-// rebuild with rerr set).  Each arrival is one 64-bit atomic adding
-// (1 << 32) + g, so the count travels with the arrival and no fence is
-// needed; arrivals are counted per lane first (same-address atomics
-// serialise), then per lane.
+// workgroup's attachment count g.  The last workgroup to arrive books the
+// round's attachments and picks round k + 1's direction (a round that
+// attached nobody while vertices were left ends the rebuild with rerr set).
 __device__ __forceinline__ void round_close(Ctl* c, int k, unsigned long long g, int policy,
                                             unsigned push_min)
 {
-    constexpr unsigned long long kOne = 1ull << 32;
-    const unsigned lane = blockIdx.x & (kLanes - 1);
-    const unsigned in_lane = (gridDim.x - lane + kLanes - 1) / kLanes;
-    const unsigned lanes = gridDim.x < (unsigned)kLanes ? gridDim.x : (unsigned)kLanes;
-    const unsigned long long lp = atomicAdd(&c->lane[lane].rpack, kOne + g);
-    if ((unsigned)(lp >> 32) != in_lane - 1) return;
-    __hip_atomic_store(&c->lane[lane].rpack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long lane_got = (lp & 0xffffffffull) + g;
-    const unsigned long long tp = atomicAdd(&c->rpack, kOne + lane_got);
-    if ((unsigned)(tp >> 32) != lanes - 1) return;
-    __hip_atomic_store(&c->rpack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned got = (unsigned)((tp & 0xffffffffull) + lane_got);
+    unsigned long long tot;
+    if (!last_arrival(c, arrival_word(g, 0), &tot)) return;
+    const unsigned got = (unsigned)tot;
     c->rk = (unsigned)k;
     if (got == 0) {
         c->rerr = 1;
@@ -1525,8 +1622,11 @@ __device__ __forceinline__ Jmp jmp_combine(Jmp q, const Jmp& r)
     return q;
 }
 
-__global__ __launch_bounds__(kWG) void k_val_round(int n, int s, const Jmp* __restrict__ Qin,
-                                                   Jmp* __restrict__ Qout, unsigned* active)
+// One jump round over all entries; returns (in thread 0) the vertices still
+// unfinished after it.
+__device__ __forceinline__ unsigned long long val_round_body(int n, int s,
+                                                             const Jmp* __restrict__ Qin,
+                                                             Jmp* __restrict__ Qout)
 {
     unsigned long long act = 0;
     // grid-stride with kJumpUnroll independent entries in flight per thread
@@ -1554,13 +1654,42 @@ __global__ __launch_bounds__(kWG) void k_val_round(int n, int s, const Jmp* __re
             Qout[v] = q[u];
         }
     }
-    act = block_sum_u64(act);
+    return block_sum_u64(act);
+}
+
+__global__ __launch_bounds__(kWG) void k_val_round(int n, int s, const Jmp* __restrict__ Qin,
+                                                   Jmp* __restrict__ Qout, unsigned* active)
+{
+    const unsigned long long act = val_round_body(n, s, Qin, Qout);
     if (threadIdx.x == 0 && act) atomicAdd(my_copy(active), (unsigned)act);
 }
 
-__global__ __launch_bounds__(kWG) void k_val_final(int n, const Jmp* __restrict__ Q,
-                                                   long long* __restrict__ V,
-                                                   int* __restrict__ hop, Ctl* ctl)
+// Device-driven round r: the last workgroup ends the rounds once no vertex
+// is unfinished, or with jstall once a round finished none.
+__global__ __launch_bounds__(kWG) void k_val_round_dev(int n, int s, int r,
+                                                       const Jmp* __restrict__ Qin,
+                                                       Jmp* __restrict__ Qout, Ctl* ctl)
+{
+    if (!jump_round_is(ctl, r)) return;
+    const unsigned long long act = val_round_body(n, s, Qin, Qout);
+    if (threadIdx.x != 0) return;
+    unsigned long long tot;
+    if (!last_arrival(ctl, arrival_word(act, 0), &tot)) return;
+    const unsigned now = (unsigned)tot;
+    ctl->jk = (unsigned)r;
+    if (now == 0) {
+        ctl->jmode = 0;
+    } else if (now == ctl->jlast) {
+        ctl->jstall = 1;
+        ctl->jmode = 0;
+    } else {
+        ctl->jlast = now;
+    }
+}
+
+__device__ __forceinline__ void val_final_body(int n, const Jmp* __restrict__ Q,
+                                               long long* __restrict__ V, int* __restrict__ hop,
+                                               Ctl* ctl)
 {
     const int v = blockIdx.x * kWG + threadIdx.x;
     unsigned bad = 0;
@@ -1571,6 +1700,24 @@ __global__ __launch_bounds__(kWG) void k_val_final(int n, const Jmp* __restrict_
         if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
     }
     if (__ballot(bad != 0) && (threadIdx.x & 63) == 0) atomicOr(&my_lane(ctl).overflow, 1u);
+}
+
+__global__ __launch_bounds__(kWG) void k_val_final(int n, const Jmp* __restrict__ Q,
+                                                   long long* __restrict__ V,
+                                                   int* __restrict__ hop, Ctl* ctl)
+{
+    val_final_body(n, Q, V, hop, ctl);
+}
+
+// Device-driven: runs once every vertex finished (not after a stall), on the
+// entries of the last round run.
+__global__ __launch_bounds__(kWG) void k_val_final_dev(int n, const Jmp* __restrict__ Q0,
+                                                       const Jmp* __restrict__ Q1,
+                                                       long long* __restrict__ V,
+                                                       int* __restrict__ hop, Ctl* ctl)
+{
+    if (ctl->jmode != 0 || ctl->jstall) return;
+    val_final_body(n, (ctl->jk & 1) ? Q1 : Q0, V, hop, ctl);
 }
 
 // Cycle C listed from the source: vertex c_j (j steps after s) is H = L - j
@@ -1908,20 +2055,48 @@ void launch_pj_init(int n, const int* col, const int* pi, int* succ, unsigned lo
     k_pj_init<<<blocks_for(n), kWG, 0, st>>>(n, col, pi, succ, P, onc, tag0, cnt);
 }
 
+void launch_jump_setup(Ctl* ctl, bool values, hipStream_t st)
+{
+    k_jump_setup<<<1, 64, 0, st>>>(ctl, values ? 1 : 0);
+}
+
+void launch_pj_round_dev(int n, int r, const unsigned long long* Pin, unsigned long long* Pout,
+                         const unsigned char* tprev, unsigned char* tcur, Ctl* ctl, hipStream_t st)
+{
+    k_pj_round_dev<<<stride_grid(n), kWG, 0, st>>>(n, r, Pin, Pout, tprev, tcur, ctl);
+}
+
+void launch_pj_final_dev(int n, const unsigned long long* P0, const unsigned long long* P1, int K,
+                         int* rep, unsigned char* onc, const Ctl* ctl, hipStream_t st)
+{
+    k_pj_final_dev<<<blocks_for(n), kWG, 0, st>>>(n, P0, P1, K, rep, onc, ctl);
+}
+
+void launch_val_round_dev(int n, int s, int r, const Jmp* Qin, Jmp* Qout, Ctl* ctl,
+                          hipStream_t st)
+{
+    k_val_round_dev<<<stride_grid(n), kWG, 0, st>>>(n, s, r, Qin, Qout, ctl);
+}
+
+void launch_val_final_dev(int n, const Jmp* Q0, const Jmp* Q1, long long* V, int* hop, Ctl* ctl,
+                          hipStream_t st)
+{
+    k_val_final_dev<<<blocks_for(n), kWG, 0, st>>>(n, Q0, Q1, V, hop, ctl);
+}
+
 void launch_pj_round(int n, const unsigned long long* Pin, unsigned long long* Pout,
                      hipStream_t st)
 {
-    k_pj_round<<<blocks_for(n), kWG, 0, st>>>(n, Pin, Pout, nullptr, nullptr, 0, 0, nullptr,
-                                              nullptr);
+    k_pj_round<<<blocks_for(n), kWG, 0, st>>>(n, Pin, Pout);
 }
 
 void launch_pj_round_tagged(int n, int r, const unsigned long long* Pin, unsigned long long* Pout,
                             const unsigned char* tprev, unsigned char* tcur, unsigned* cnt,
                             hipStream_t st)
 {
-    k_pj_round<<<stride_grid(n), kWG, 0, st>>>(n, Pin, Pout, tprev, tcur, (unsigned char)r,
-                                               (unsigned char)(r + 1), cnt + 2 * (r & 1),
-                                               cnt + 2 * ((r + 1) & 1));
+    k_pj_round_tagged<<<stride_grid(n), kWG, 0, st>>>(n, Pin, Pout, tprev, tcur, (unsigned char)r,
+                                                      (unsigned char)(r + 1), cnt + 2 * (r & 1),
+                                                      cnt + 2 * ((r + 1) & 1));
 }
 
 void launch_pj_final(int n, const unsigned long long* P, int* rep, unsigned char* onc,
@@ -2300,6 +2475,10 @@ __global__ void k_post_ctl(const Ctl* __restrict__ c, CtlView* dst, unsigned* se
         v.rfront = c->rfront;
         v.rerr = c->rerr;
         v.rk = c->rk;
+        v.jk = c->jk;
+        v.jmode = c->jmode;
+        v.jlast = c->jlast;
+        v.jstall = c->jstall;
         v.xcnt = c->xcnt;
         v.scnt = c->scnt;
         *dst = v;

@@ -332,6 +332,34 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
 // Cycles of the policy graph: rep and on_cycle for every vertex.  At most
 // K = ceil(log2 n) jump rounds; the stop test of k_pj_round ends the phase as
 // soon as every jump pointer is on its cycle and the window minima are fixed.
+// Rounds queued between two host reads of the control block when the device
+// decides when rounds end (rebuild, cycles, values).
+constexpr int kRoundsPerRead = 8;
+
+// Cycle rounds with the stop test decided on the device: K rounds at most,
+// queued kRoundsPerRead at a time with the final after each batch.
+ocm_status cycle_rounds_on_device(Ctx& c, int K, unsigned long long* P0, unsigned long long* P1,
+                                  unsigned char* const tag[2], int* rep, unsigned char* onc)
+{
+    unsigned long long* P[2] = {P0, P1};
+    ocm::launch_jump_setup(c.ws.ctl, false, c.st);
+    int r = 0;
+    for (;;) {
+        for (int j = 0; j < kRoundsPerRead && r < K; ++j) {
+            ++r;
+            ocm::launch_pj_round_dev(c.n, r, P[(r - 1) & 1], P[r & 1], tag[(r - 1) & 1], tag[r & 1],
+                                     c.ws.ctl, c.st);
+        }
+        ocm::launch_pj_final_dev(c.n, P0, P1, K, rep, onc, c.ws.ctl, c.st);
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        if (c.h.jmode == 0 || c.h.jk == (unsigned)K) break;
+        if (r >= K) return fail(OCM_E_HIP, "cycle rounds did not finish");
+    }
+    c.jump_rounds += (int)c.h.jk;
+    return OCM_OK;
+}
+
 ocm_status phase_cycles(Ctx& c, const int* pi, int* rep, unsigned char* onc)
 {
     auto* P0 = (unsigned long long*)c.ws.Q[0];
@@ -345,11 +373,12 @@ ocm_status phase_cycles(Ctx& c, const int* pi, int* rep, unsigned char* onc)
     c.prof.begin(OCM_K_CYCLES);
     if (stop_test) ocm::launch_fill_u32((unsigned*)c.ws.layer, ((int64_t)c.n * 2 + 3) / 4, 0u, c.st);
     ocm::launch_pj_init(c.n, c.col, pi, c.ws.succ, P0, onc, stop_test ? tag[0] : nullptr,
-                        stop_test ? c.ws.ctl->lane[0].pjc : nullptr, c.st);
+                        stop_test && c.prof.out ? c.ws.ctl->lane[0].pjc : nullptr, c.st);
     c.prof.end();
     // pi, col[pi], succ, packed entry, on-cycle (+ tag clear and mark)
     c.prof.bytes(OCM_K_CYCLES, 21.0 * n + (stop_test ? 3.0 * n : 0.0));
     HIP_TRY(hipGetLastError());
+    if (stop_test && !c.prof.out) return cycle_rounds_on_device(c, K, P0, P1, tag, rep, onc);
     long long img_prev = -1;
     int r = 0;
     while (r < K) {
@@ -403,7 +432,6 @@ ocm_status phase_select(Ctx& c, const int* pi, const int* rep, const unsigned ch
 // host loop below), two kernels are queued per round (marks or a pull round,
 // then the claims), and the host reads the state back every kRoundsPerRead
 // rounds.  Rounds queued after the last one do nothing.
-constexpr int kRoundsPerRead = 8;
 
 ocm_status connect_rounds_on_device(Ctx& c, int* pi, int* layer, unsigned left, unsigned front,
                                     int* rounds)
@@ -537,6 +565,41 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
 // finishes no vertex and reports *stalled = true (no values written).
 // Otherwise every vertex must reach s.  *qfinal is the buffer holding the
 // final entries (their hop counts list C).
+// Value rounds decided on the device after the init: kRoundsPerRead rounds
+// and the final per host read, until every vertex finished or a round
+// finished none (a stall: the policy graph does not reach s).
+ocm_status value_rounds_on_device(Ctx& c, int s, long long* V, int* hop, bool probe, bool* stalled,
+                                  int* rounds)
+{
+    ocm::launch_jump_setup(c.ws.ctl, true, c.st);
+    int r = 0;
+    for (;;) {
+        for (int j = 0; j < kRoundsPerRead; ++j) {
+            ++r;
+            ocm::launch_val_round_dev(c.n, s, r, c.ws.Q[(r - 1) & 1], c.ws.Q[r & 1], c.ws.ctl,
+                                      c.st);
+        }
+        ocm::launch_val_final_dev(c.n, c.ws.Q[0], c.ws.Q[1], V, hop, c.ws.ctl, c.st);
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        if (c.h.jmode == 0) break;
+        if (r > 64) return fail(OCM_E_HIP, "value propagation did not converge");
+    }
+    const int k = (int)c.h.jk;
+    c.jump_rounds += k;
+    c.value_rounds += k;
+    if (rounds) *rounds = k;
+    if (c.h.jstall) {
+        if (probe) {
+            if (stalled) *stalled = true;
+            return OCM_OK;
+        }
+        return fail(OCM_E_NOT_STRONGLY_CONNECTED, "policy graph does not reach the source");
+    }
+    if (c.h.overflow) return fail(OCM_E_OVERFLOW, "a value left [-2^62, 2^62]");
+    return OCM_OK;
+}
+
 ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, long long* V,
                         int* hop, bool probe, bool* stalled, int* rounds)
 {
@@ -549,6 +612,7 @@ ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, 
     c.prof.end();
     c.prof.bytes(ph, (28.0 + c.sw) * c.n);   // pi, col[pi], w[pi], succ, 16-byte entry
     HIP_TRY(hipGetLastError());
+    if (!c.prof.out) return value_rounds_on_device(c, s, V, hop, probe, stalled, rounds);
     OCM_TRY(read_ctl(c));
     unsigned act = c.h.active;
     int a = 0, k = 0;
