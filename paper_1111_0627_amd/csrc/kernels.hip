@@ -709,11 +709,18 @@ __global__ __launch_bounds__(kWG) void k_select_final(const Cand* __restrict__ p
 //         (k_conn_claim).
 // Both find, for every vertex that attaches, the same (lowest) edge; the host
 // picks the cheaper direction per round.
-// A round workgroup owns kWG * WPT consecutive bitmap words (WPT = 1 or 2
-// words, i.e. 32 or 64 vertices, per thread), so one pass over its span has
-// a single load per thread; the items it finds (frontier, marked or
-// unattached vertices) are processed in LDS batches of kBatch.
-constexpr int kBatch = 1024;
+// A round workgroup owns kWG consecutive bitmap words, one per thread (32
+// vertices).  Claims and pull rounds: each wave handles its 64 words on its
+// own: it ranks its candidates (marked or unattached vertices) in word order
+// and gives rank r to lane r % 64, so the lanes share the work evenly without
+// workgroup barriers; a lane scans its vertex's out-row itself, four entries
+// per step, and stops at the first attached head (the lowest one); rows
+// longer than kLaneRow are scanned by the whole wave, 64 entries per step.
+// Marks: the workgroup lists its frontier vertices in LDS batches and spreads
+// all their in-edges over its threads (every in-edge is visited, and spread
+// rows give coalesced loads; measured faster than the per-wave scheme here).
+constexpr int kLaneRow = 32;
+constexpr int kWaves = kWG / 64;
 
 __device__ __forceinline__ bool attached(const unsigned* __restrict__ abits, int v)
 {
@@ -725,6 +732,63 @@ __device__ __forceinline__ unsigned valid_bits(int64_t word, int n)
     const int64_t lo = word * 32;
     return lo + 32 <= n ? 0xffffffffu : (lo >= n ? 0u : (1u << (unsigned)(n - lo)) - 1u);
 }
+
+// Rebuild init: C's component (rep == s) keeps pi (layer 0), every other
+// vertex is unattached (layer -1).  Writes the round-1 bitmaps (a1 = layer
+// 0, a0 = empty) and counts both sets into the lanes (got, left).
+__global__ __launch_bounds__(kWG) void k_conn_init(int n, const int* __restrict__ rep,
+                                                   const unsigned char* __restrict__ onc, int s,
+                                                   int* __restrict__ layer,
+                                                   unsigned char* __restrict__ onC,
+                                                   unsigned* __restrict__ a1,
+                                                   unsigned* __restrict__ a0, Ctl* ctl)
+{
+    const int64_t words = ((int64_t)n + 31) / 32;
+    const int64_t span = (int64_t)gridDim.x * kWG;
+    const int lane = threadIdx.x & 63;
+    unsigned long long ncomp = 0, nleft = 0;
+    // 64 consecutive vertices per wave, two words per ballot
+    for (int64_t vb = ((int64_t)blockIdx.x * kWG + threadIdx.x) & ~(int64_t)63; vb < (int64_t)n;
+         vb += span) {
+        const int64_t v = vb + lane;
+        bool comp = false;
+        if (v < n) {
+            comp = rep[v] == s;
+            if (layer) layer[v] = comp ? 0 : -1;
+            if (onC) onC[v] = (unsigned char)(comp && onc && onc[v]);
+        }
+        const unsigned long long b = __ballot(comp);
+        const unsigned long long live = __ballot(v < n);
+        const int64_t wd = (vb >> 5) + (lane >> 5);
+        if ((lane & 31) == 0 && wd < words) {
+            a1[wd] = (unsigned)(b >> (lane & 32));
+            a0[wd] = 0u;
+        }
+        if (lane == 0) {
+            ncomp += (unsigned long long)__popcll(b);
+            nleft += (unsigned long long)__popcll(live & ~b);
+        }
+    }
+    ncomp = block_sum_u64(ncomp);
+    nleft = block_sum_u64(nleft);
+    if (threadIdx.x == 0) {
+        if (ncomp) atomicAdd(&my_lane(ctl).got, (unsigned)ncomp);
+        if (nleft) atomicAdd(&my_lane(ctl).left, (unsigned)nleft);
+    }
+}
+
+// LDS of the mark step: the frontier of a workgroup's words is processed
+// in batches of kBatch vertices whose in-edges are spread over all its
+// threads (the rows are short, so spreading keeps the loads coalesced).
+constexpr int kBatch = 1024;
+constexpr int kExpand = 4;   // in-edges per thread in flight: 2 * kExpand
+
+struct MarkLds {
+    int todo[kBatch];
+    int beg[kBatch];
+    unsigned off[kBatch];
+    unsigned wsum[kWG / 64];
+};
 
 // Exclusive rank of each thread's count c over the workgroup; *total = sum.
 // All threads call it.
@@ -794,9 +858,6 @@ __device__ __forceinline__ void emit_batch(unsigned long long mask, int64_t base
     }
 }
 
-// Edges (or in-edges) per thread in flight in the round kernels' expansions.
-constexpr int kExpand = 4;
-
 // beg[i], off[i] = first position and length of the row of todo[i] (i < cnt),
 // four rows per thread in flight.
 __device__ __forceinline__ void gather_rows(const int* __restrict__ ptr, const int* todo,
@@ -823,174 +884,171 @@ __device__ __forceinline__ void gather_rows(const int* __restrict__ ptr, const i
     }
 }
 
-// For each of the cnt listed vertices, the lowest out-edge whose head is
-// attached (INT32_MAX if none): out-edges spread evenly over the workgroup,
-// LDS atomicMin per vertex.  Returns the number of edges scanned.
-__device__ __forceinline__ unsigned lowest_attached_edges(const int* __restrict__ row_ptr,
-                                                          const int* __restrict__ col,
-                                                          const unsigned* __restrict__ acur,
-                                                          const int* todo, unsigned cnt, int* beg,
-                                                          unsigned* off, int* best, unsigned* wsum)
-{
-    gather_rows(row_ptr, todo, cnt, beg, off);
-    for (unsigned i = threadIdx.x; i < cnt; i += kWG) best[i] = INT32_MAX;
-    __syncthreads();
-    const unsigned total = block_excl_scan(off, cnt, wsum);
-    // kExpand edges per thread in flight: their owners, heads and bitmap
-    // words are each fetched for all of them before any is used
-    for (unsigned t0 = threadIdx.x; t0 < total; t0 += kExpand * kWG) {
-        unsigned own[kExpand];
-        int e[kExpand], h[kExpand];
-#pragma unroll
-        for (int j = 0; j < kExpand; ++j) {
-            const unsigned t = t0 + j * kWG;
-            own[j] = t < total ? owner_of(off, cnt, t) : 0;
-            e[j] = beg[own[j]] + (int)(t - off[own[j]]);
-        }
-#pragma unroll
-        for (int j = 0; j < kExpand; ++j) h[j] = t0 + j * kWG < total ? col[e[j]] : -1;
-        unsigned a[kExpand];
-#pragma unroll
-        for (int j = 0; j < kExpand; ++j) a[j] = h[j] >= 0 ? acur[h[j] >> 5] : 0u;
-#pragma unroll
-        for (int j = 0; j < kExpand; ++j)
-            if ((a[j] >> (h[j] & 31)) & 1u) atomicMin(&best[own[j]], e[j]);
-    }
-    __syncthreads();
-    return total;
-}
-
-// Rebuild init: C's component (rep == s) keeps pi (layer 0), every other
-// vertex is unattached (layer -1).  Writes the round-1 bitmaps (a1 = layer
-// 0, a0 = empty) and counts both sets into the lanes (got, left).
-__global__ __launch_bounds__(kWG) void k_conn_init(int n, const int* __restrict__ rep,
-                                                   const unsigned char* __restrict__ onc, int s,
-                                                   int* __restrict__ layer,
-                                                   unsigned char* __restrict__ onC,
-                                                   unsigned* __restrict__ a1,
-                                                   unsigned* __restrict__ a0, Ctl* ctl)
-{
-    const int64_t words = ((int64_t)n + 31) / 32;
-    const int64_t span = (int64_t)gridDim.x * kWG;
-    const int lane = threadIdx.x & 63;
-    unsigned long long ncomp = 0, nleft = 0;
-    // 64 consecutive vertices per wave, two words per ballot
-    for (int64_t vb = ((int64_t)blockIdx.x * kWG + threadIdx.x) & ~(int64_t)63; vb < (int64_t)n;
-         vb += span) {
-        const int64_t v = vb + lane;
-        bool comp = false;
-        if (v < n) {
-            comp = rep[v] == s;
-            if (layer) layer[v] = comp ? 0 : -1;
-            if (onC) onC[v] = (unsigned char)(comp && onc && onc[v]);
-        }
-        const unsigned long long b = __ballot(comp);
-        const unsigned long long live = __ballot(v < n);
-        const int64_t wd = (vb >> 5) + (lane >> 5);
-        if ((lane & 31) == 0 && wd < words) {
-            a1[wd] = (unsigned)(b >> (lane & 32));
-            a0[wd] = 0u;
-        }
-        if (lane == 0) {
-            ncomp += (unsigned long long)__popcll(b);
-            nleft += (unsigned long long)__popcll(live & ~b);
-        }
-    }
-    ncomp = block_sum_u64(ncomp);
-    nleft = block_sum_u64(nleft);
-    if (threadIdx.x == 0) {
-        if (ncomp) atomicAdd(&my_lane(ctl).got, (unsigned)ncomp);
-        if (nleft) atomicAdd(&my_lane(ctl).left, (unsigned)nleft);
-    }
-}
-
-// LDS of the round kernels
-struct RoundLds {
-    int todo[kBatch];
-    int beg[kBatch];
-    unsigned off[kBatch];
-    int best[kBatch];
-    unsigned wsum[kWG / 64];
+// Per-wave LDS of the round kernels.
+struct WaveLds {
+    unsigned pre[kWaves][64];   // exclusive rank of each word's first candidate
+    unsigned msk[kWaves][64];   // candidates of each word
+    unsigned nb[kWaves][64];    // vertices attached in the round, per word
 };
 
-// Attaches the batch's vertices that found an edge (pi, layer = k) and sets
-// their bits in nb (the workgroup's new words, first word wbase).
-__device__ __forceinline__ unsigned attach_batch(int k, const RoundLds& L, unsigned cnt,
-                                                 int64_t wbase, unsigned* nb, int* __restrict__ pi,
-                                                 int* __restrict__ layer)
+// LDS written by some lanes of a wave and read by others.
+__device__ __forceinline__ void wave_lds_sync()
 {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Position of the k-th (from 0) set bit of m; k < popcount(m).
+__device__ __forceinline__ int select_bit(unsigned m, unsigned k)
+{
+    int pos = 0;
+    unsigned c = __popc(m & 0xffffu);
+    if (k >= c) { k -= c; m >>= 16; pos += 16; }
+    c = __popc(m & 0xffu);
+    if (k >= c) { k -= c; m >>= 8; pos += 8; }
+    c = __popc(m & 0xfu);
+    if (k >= c) { k -= c; m >>= 4; pos += 4; }
+    c = __popc(m & 0x3u);
+    if (k >= c) { k -= c; m >>= 2; pos += 2; }
+    if (k >= (m & 1u)) pos += 1;
+    return pos;
+}
+
+// Publishes this lane's candidate mask; returns the wave's candidate count.
+__device__ __forceinline__ unsigned wave_rank(unsigned mask, unsigned* pre, unsigned* msk)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned c = __popc(mask);
+    const unsigned incl = wave_incl_scan(c);
+    pre[lane] = incl - c;
+    msk[lane] = mask;
+    wave_lds_sync();
+    return __shfl(incl, 63);
+}
+
+// Word (0..63, within the wave's words) and bit of the candidate of rank r.
+__device__ __forceinline__ void wave_candidate(const unsigned* pre, const unsigned* msk, unsigned r,
+                                               int* word, int* bit)
+{
+    int lo = 0, hi = 63;   // the last word whose first rank is <= r holds r
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    *word = lo;
+    *bit = select_bit(msk[lo], r - pre[lo]);
+}
+
+// Every candidate of the wave (v0: first vertex of the wave's words)
+// attaches with its lowest out-edge whose head is in acur, if it has one
+// (pi, layer = k, bit in nb).  Returns the lane's attachments; out-edges
+// examined are added to *scanned.
+__device__ __forceinline__ unsigned wave_attach(int k, int64_t v0, unsigned mask,
+                                                const int* __restrict__ row_ptr,
+                                                const int* __restrict__ col,
+                                                const unsigned* __restrict__ acur,
+                                                int* __restrict__ pi, int* __restrict__ layer,
+                                                unsigned* pre, unsigned* msk, unsigned* nb,
+                                                unsigned long long* scanned)
+{
+    const int lane = threadIdx.x & 63;
+    nb[lane] = 0;
+    const unsigned total = wave_rank(mask, pre, msk);
     unsigned got = 0;
-    for (unsigned i = threadIdx.x; i < cnt; i += kWG) {
-        const int h = L.best[i];
-        if (h != INT32_MAX) {
-            const int u = L.todo[i];
-            pi[u] = h;
+    for (unsigned r0 = 0; r0 < total; r0 += 64) {
+        const unsigned r = r0 + lane;
+        int word = 0, bit = 0, u = -1, b = 0, end = 0;
+        if (r < total) {
+            wave_candidate(pre, msk, r, &word, &bit);
+            u = (int)(v0 + 32 * word + bit);
+            b = row_ptr[u];
+            end = row_ptr[u + 1];
+        }
+        const bool heavy = end - b > kLaneRow;
+        int best = INT32_MAX;
+        if (u >= 0 && !heavy) {
+            for (int e = b; e < end; e += 4) {
+                int h[4];
+                unsigned a[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) h[j] = e + j < end ? col[e + j] : -1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[j] = h[j] >= 0 ? acur[h[j] >> 5] : 0u;
+                int hit = -1;
+#pragma unroll
+                for (int j = 3; j >= 0; --j)
+                    if ((a[j] >> (h[j] & 31)) & 1u) hit = j;
+                *scanned += (unsigned)(end - e < 4 ? end - e : 4);
+                if (hit >= 0) {
+                    best = e + hit;
+                    break;
+                }
+            }
+        }
+        // long rows, one at a time, by the whole wave
+        for (unsigned long long hv = __ballot(heavy); hv; hv &= hv - 1) {
+            const int src = __ffsll((long long)hv) - 1;
+            const int hb = __shfl(b, src), he = __shfl(end, src);
+            int found = INT32_MAX;
+            for (int e0 = hb; e0 < he; e0 += 64) {
+                const int e = e0 + lane;
+                const unsigned long long bal = __ballot(e < he && attached(acur, col[e]));
+                if (lane == src) *scanned += (unsigned)(he - e0 < 64 ? he - e0 : 64);
+                if (bal) {
+                    found = e0 + __ffsll((long long)bal) - 1;
+                    break;
+                }
+            }
+            if (lane == src) best = found;
+        }
+        if (best != INT32_MAX) {
+            pi[u] = best;
             if (layer) layer[u] = k;
-            atomicOr(&nb[(u >> 5) - wbase], 1u << (u & 31));
+            atomicOr(&nb[word], 1u << bit);
             ++got;
         }
     }
+    wave_lds_sync();
     return got;
 }
 
-// Spans of the round kernels: span i covers bitmap words [i * kWG * WPT,
-// (i + 1) * kWG * WPT).  A workgroup strides over the spans (all of them, or
-// only those listed in `spans`, *nspans of them).
+// Spans of the round kernels: span i covers bitmap words [i * kWG,
+// (i + 1) * kWG).  A workgroup strides over the spans (all of them, or only
+// those listed in `spans`, *nspans of them).
 template <typename F>
 __device__ __forceinline__ void for_each_span(const int* __restrict__ spans, const unsigned* nspans,
                                               int64_t nall, F&& f)
 {
     const int64_t cnt = spans ? (int64_t)*nspans : nall;
-    for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-        f(spans ? (int64_t)spans[i] : i);
-        __syncthreads();   // the next span reuses the LDS
-    }
+    for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) f(spans ? (int64_t)spans[i] : i);
 }
 
-// Pull round k: the unattached vertices (~acur) of each span scan their
-// out-edges; anext becomes acur plus this round's attachments.
-// Returns the workgroup's attachment count.
-template <int WPT>
+// Pull round k: the unattached vertices (~acur) scan their out-edges; anext
+// becomes acur plus this round's attachments.  Returns (in thread 0) the
+// workgroup's attachment count.
 __device__ __forceinline__ unsigned long long pull_body(
     int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
     const unsigned* __restrict__ acur, unsigned* __restrict__ anext, int* __restrict__ layer,
     int* __restrict__ pi, unsigned long long* ledges, const int* __restrict__ spans,
-    const unsigned* nspans, RoundLds& L, unsigned* nb)
+    const unsigned* nspans, WaveLds& L)
 {
     const int64_t words = ((int64_t)n + 31) / 32;
-    const int64_t per = (int64_t)kWG * WPT;
-    unsigned got = 0, scanned = 0;
-    for_each_span(spans, nspans, (words + per - 1) / per, [&](int64_t span) {
-        const int64_t wbase = span * per;
-        const int64_t w0 = wbase + (int64_t)threadIdx.x * WPT;
-        unsigned a[WPT];
-        unsigned long long mask = 0;
-#pragma unroll
-        for (int j = 0; j < WPT; ++j) {
-            a[j] = 0;
-            nb[threadIdx.x * WPT + j] = 0;
-            if (w0 + j < words) {
-                a[j] = acur[w0 + j];
-                mask |= (unsigned long long)(~a[j] & valid_bits(w0 + j, n)) << (32 * j);
-            }
-        }
-        unsigned total = 0;
-        const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
-        for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
-            emit_batch(mask, w0 * 32, rank, b0, L.todo);
-            __syncthreads();
-            const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
-            scanned += lowest_attached_edges(row_ptr, col, acur, L.todo, cnt, L.beg, L.off, L.best,
-                                             L.wsum);
-            got += attach_batch(k, L, cnt, wbase, nb, pi, layer);
-            __syncthreads();
-        }
-#pragma unroll
-        for (int j = 0; j < WPT; ++j)
-            if (w0 + j < words) anext[w0 + j] = a[j] | nb[threadIdx.x * WPT + j];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned got = 0;
+    unsigned long long scanned = 0;
+    for_each_span(spans, nspans, (words + kWG - 1) / kWG, [&](int64_t span) {
+        const int64_t w = span * kWG + threadIdx.x;
+        const unsigned a = w < words ? acur[w] : 0u;
+        const unsigned mask = w < words ? ~a & valid_bits(w, n) : 0u;
+        got += wave_attach(k, (w - lane) * 32, mask, row_ptr, col, acur, pi, layer, L.pre[wave],
+                           L.msk[wave], L.nb[wave], &scanned);
+        if (w < words) anext[w] = a | L.nb[wave][lane];
     });
     const unsigned long long g = block_sum_u64(got);
-    if (threadIdx.x == 0 && ledges && scanned) atomicAdd(my_copy(ledges), (unsigned long long)scanned);
+    scanned = block_sum_u64(scanned);
+    if (threadIdx.x == 0 && ledges && scanned) atomicAdd(my_copy(ledges), scanned);
     return g;
 }
 
@@ -999,29 +1057,24 @@ __device__ __forceinline__ unsigned long long pull_body(
 // workgroup; every tail u gets marks[u] = 1 (plain byte store, idempotent).
 // Attached tails are dropped by the claim, which reads its span of acur
 // anyway.
-template <int WPT>
 __device__ __forceinline__ void mark_body(int n, const int* __restrict__ rin_ptr,
                                           const int* __restrict__ rin,
                                           const unsigned* __restrict__ acur,
                                           unsigned* __restrict__ anext,
                                           unsigned char* __restrict__ marks,
                                           unsigned long long* pedges, const int* __restrict__ spans,
-                                          const unsigned* nspans, RoundLds& L)
+                                          const unsigned* nspans, MarkLds& L)
 {
     const int64_t words = ((int64_t)n + 31) / 32;
-    const int64_t per = (int64_t)kWG * WPT;
     unsigned long long scanned = 0;
-    for_each_span(spans, nspans, (words + per - 1) / per, [&](int64_t span) {
-        const int64_t w0 = span * per + (int64_t)threadIdx.x * WPT;
+    for_each_span(spans, nspans, (words + kWG - 1) / kWG, [&](int64_t span) {
+        const int64_t w0 = span * kWG + threadIdx.x;
         unsigned long long mask = 0;
-#pragma unroll
-        for (int j = 0; j < WPT; ++j) {
-            if (w0 + j < words) {
-                const unsigned a = acur[w0 + j];
-                const unsigned f = a & ~anext[w0 + j];
-                if (f) anext[w0 + j] = a;   // anext is a subset of acur
-                mask |= (unsigned long long)f << (32 * j);
-            }
+        if (w0 < words) {
+            const unsigned a = acur[w0];
+            const unsigned f = a & ~anext[w0];
+            if (f) anext[w0] = a;   // anext is a subset of acur
+            mask = f;
         }
         unsigned total = 0;
         const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
@@ -1054,78 +1107,64 @@ __device__ __forceinline__ void mark_body(int n, const int* __restrict__ rin_ptr
     if (pedges && threadIdx.x == 0 && scanned) atomicAdd(my_copy(pedges), scanned);
 }
 
-// Push round k, claim: each span takes its mark bytes (clearing them), lists
-// the marked vertices that are not attached yet and finds each one's lowest
-// out-edge into the attached set.  One exists: the edge that marked it.  The
-// vertex attaches with it (pi, layer = k) and joins anext.
-// Returns the workgroup's attachment count.
-template <int WPT>
+// The 32 mark bytes of word w as a bit mask, cleared on the way (marks are
+// 0 or 1).
+__device__ __forceinline__ unsigned take_marks(unsigned char* __restrict__ marks, int64_t w, int n)
+{
+    const int64_t v0 = w * 32;
+    unsigned mask = 0;
+    if (v0 + 32 <= n) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const uint4 t = *(const uint4*)(marks + v0 + 16 * q);
+            if (t.x | t.y | t.z | t.w) *(uint4*)(marks + v0 + 16 * q) = make_uint4(0, 0, 0, 0);
+            const unsigned wd[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)   // four 0/1 bytes -> four bits
+                mask |= (((wd[i] & 0x01010101u) * 0x01020408u) >> 24) << (16 * q + 4 * i);
+        }
+    } else {
+        for (int q = 0; q < 32 && v0 + q < n; ++q) {
+            if (marks[v0 + q]) {
+                mask |= 1u << q;
+                marks[v0 + q] = 0;
+            }
+        }
+    }
+    return mask;
+}
+
+// Push round k, claim: each word takes its mark bytes (clearing them); the
+// marked vertices not attached yet find their lowest out-edge into the
+// attached set.  One exists: the edge that marked the vertex.  The vertex
+// attaches with it (pi, layer = k) and joins anext.  Returns (in thread 0)
+// the workgroup's attachment count.
 __device__ __forceinline__ unsigned long long claim_body(
     int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
     const unsigned* __restrict__ acur, unsigned* __restrict__ anext,
     unsigned char* __restrict__ marks, int* __restrict__ pi, int* __restrict__ layer,
-    unsigned long long* cedges, const int* __restrict__ spans, const unsigned* nspans, RoundLds& L,
-    unsigned* nb)
+    unsigned long long* cedges, const int* __restrict__ spans, const unsigned* nspans, WaveLds& L)
 {
     const int64_t words = ((int64_t)n + 31) / 32;
-    const int64_t per = (int64_t)kWG * WPT;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     unsigned got = 0;
     unsigned long long scanned = 0;
-    for_each_span(spans, nspans, (words + per - 1) / per, [&](int64_t span) {
-        const int64_t wbase = span * per;
-        const int64_t w0 = wbase + (int64_t)threadIdx.x * WPT;
-        const int64_t v0 = w0 * 32;   // this thread's 32 * WPT mark bytes
-        unsigned long long mask = 0;
-#pragma unroll
-        for (int j = 0; j < WPT; ++j) nb[threadIdx.x * WPT + j] = 0;
-        if (v0 + 32 * WPT <= n) {
-#pragma unroll
-            for (int q = 0; q < 2 * WPT; ++q) {
-                uint4 t = *(const uint4*)(marks + v0 + 16 * q);
-                if (t.x | t.y | t.z | t.w) *(uint4*)(marks + v0 + 16 * q) = make_uint4(0, 0, 0, 0);
-                const unsigned wd[4] = {t.x, t.y, t.z, t.w};
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    if ((wd[r >> 2] >> (8 * (r & 3))) & 0xffu) mask |= 1ull << (16 * q + r);
-            }
-        } else {
-            for (int q = 0; q < 32 * WPT && v0 + q < n; ++q) {
-                if (marks[v0 + q]) {
-                    mask |= 1ull << q;
-                    marks[v0 + q] = 0;
-                }
-            }
-        }
+    for_each_span(spans, nspans, (words + kWG - 1) / kWG, [&](int64_t span) {
+        const int64_t w = span * kWG + threadIdx.x;
         // marked tails that are already attached drop out
-        unsigned long long att = 0;
-#pragma unroll
-        for (int j = 0; j < WPT; ++j)
-            if (w0 + j < words) att |= (unsigned long long)acur[w0 + j] << (32 * j);
-        mask &= ~att;
-        unsigned total = 0;
-        const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
-        for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
-            emit_batch(mask, v0, rank, b0, L.todo);
-            __syncthreads();
-            const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
-            scanned += lowest_attached_edges(row_ptr, col, acur, L.todo, cnt, L.beg, L.off, L.best,
-                                             L.wsum);
-            got += attach_batch(k, L, cnt, wbase, nb, pi, layer);
-            __syncthreads();
-        }
-#pragma unroll
-        for (int j = 0; j < WPT; ++j) {
-            const unsigned x = nb[threadIdx.x * WPT + j];
-            if (x && w0 + j < words) anext[w0 + j] |= x;
-        }
+        const unsigned mask = w < words ? take_marks(marks, w, n) & ~acur[w] : 0u;
+        got += wave_attach(k, (w - lane) * 32, mask, row_ptr, col, acur, pi, layer, L.pre[wave],
+                           L.msk[wave], L.nb[wave], &scanned);
+        const unsigned x = L.nb[wave][lane];
+        if (x && w < words) anext[w] |= x;
     });
     const unsigned long long g = block_sum_u64(got);
+    scanned = block_sum_u64(scanned);
     if (threadIdx.x == 0 && cedges && scanned) atomicAdd(my_copy(cedges), scanned);
     return g;
 }
 
 // Host-driven rounds: one kernel per step.
-template <int WPT>
 __global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __restrict__ row_ptr,
                                                    const int* __restrict__ col,
                                                    const unsigned* __restrict__ acur,
@@ -1135,14 +1174,12 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __re
                                                    const int* __restrict__ spans,
                                                    const unsigned* nspans)
 {
-    __shared__ RoundLds L;
-    __shared__ unsigned nb[kWG * WPT];
+    __shared__ WaveLds L;
     const unsigned long long g =
-        pull_body<WPT>(k, n, row_ptr, col, acur, anext, layer, pi, ledges, spans, nspans, L, nb);
+        pull_body(k, n, row_ptr, col, acur, anext, layer, pi, ledges, spans, nspans, L);
     if (threadIdx.x == 0 && g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
 }
 
-template <int WPT>
 __global__ __launch_bounds__(kWG) void k_conn_mark(int n, const int* __restrict__ rin_ptr,
                                                    const int* __restrict__ rin,
                                                    const unsigned* __restrict__ acur,
@@ -1152,11 +1189,10 @@ __global__ __launch_bounds__(kWG) void k_conn_mark(int n, const int* __restrict_
                                                    const int* __restrict__ spans,
                                                    const unsigned* nspans)
 {
-    __shared__ RoundLds L;
-    mark_body<WPT>(n, rin_ptr, rin, acur, anext, marks, pedges, spans, nspans, L);
+    __shared__ MarkLds L;
+    mark_body(n, rin_ptr, rin, acur, anext, marks, pedges, spans, nspans, L);
 }
 
-template <int WPT>
 __global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __restrict__ row_ptr,
                                                     const int* __restrict__ col,
                                                     const unsigned* __restrict__ acur,
@@ -1167,10 +1203,9 @@ __global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __r
                                                     const int* __restrict__ spans,
                                                     const unsigned* nspans)
 {
-    __shared__ RoundLds L;
-    __shared__ unsigned nb[kWG * WPT];
-    const unsigned long long g = claim_body<WPT>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
-                                                 cedges, spans, nspans, L, nb);
+    __shared__ WaveLds L;
+    const unsigned long long g = claim_body(k, n, row_ptr, col, acur, anext, marks, pi, layer,
+                                            cedges, spans, nspans, L);
     if (threadIdx.x == 0 && g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
 }
 
@@ -1219,26 +1254,26 @@ __device__ __forceinline__ bool round_is(const Ctl* c, int k, unsigned mode)
 }
 
 // Round k's first kernel: the marks of a push round, or a whole pull round.
-template <int WPT>
 __global__ __launch_bounds__(kWG) void k_round_mark_pull(
     int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
     const int* __restrict__ rin_ptr, const int* __restrict__ rin, const unsigned* __restrict__ acur,
     unsigned* __restrict__ anext, unsigned char* __restrict__ marks, int* __restrict__ pi,
     int* __restrict__ layer, Ctl* ctl, unsigned long long* pedges, int policy, unsigned push_min)
 {
-    __shared__ RoundLds L;
-    __shared__ unsigned nb[kWG * WPT];
+    __shared__ union {
+        MarkLds mark;
+        WaveLds pull;
+    } L;
     if (round_is(ctl, k, 1u)) {
-        mark_body<WPT>(n, rin_ptr, rin, acur, anext, marks, pedges, nullptr, nullptr, L);
+        mark_body(n, rin_ptr, rin, acur, anext, marks, pedges, nullptr, nullptr, L.mark);
     } else if (round_is(ctl, k, 2u)) {
-        const unsigned long long g = pull_body<WPT>(k, n, row_ptr, col, acur, anext, layer, pi,
-                                                    nullptr, nullptr, nullptr, L, nb);
+        const unsigned long long g = pull_body(k, n, row_ptr, col, acur, anext, layer, pi, nullptr,
+                                               nullptr, nullptr, L.pull);
         if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min);
     }
 }
 
 // Round k's second kernel: the claims of a push round.
-template <int WPT>
 __global__ __launch_bounds__(kWG) void k_round_claim(
     int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
     const unsigned* __restrict__ acur, unsigned* __restrict__ anext,
@@ -1246,10 +1281,9 @@ __global__ __launch_bounds__(kWG) void k_round_claim(
     int policy, unsigned push_min)
 {
     if (!round_is(ctl, k, 1u)) return;
-    __shared__ RoundLds L;
-    __shared__ unsigned nb[kWG * WPT];
-    const unsigned long long g = claim_body<WPT>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
-                                                 nullptr, nullptr, nullptr, L, nb);
+    __shared__ WaveLds L;
+    const unsigned long long g = claim_body(k, n, row_ptr, col, acur, anext, marks, pi, layer,
+                                            nullptr, nullptr, nullptr, L);
     if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min);
 }
 
@@ -2168,7 +2202,7 @@ void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const un
                       unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
                       const int* spans, const unsigned* nspans, hipStream_t st)
 {
-    k_conn_pull<1><<<round_grid(n, spans), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer,
+    k_conn_pull<<<round_grid(n, spans), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer,
                                                          pi, ctl, ledges, spans, nspans);
 }
 
@@ -2176,7 +2210,7 @@ void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned*
                       unsigned* anext, unsigned char* marks, unsigned long long* pedges,
                       const int* spans, const unsigned* nspans, hipStream_t st)
 {
-    k_conn_mark<1><<<round_grid(n, spans), kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks,
+    k_conn_mark<<<round_grid(n, spans), kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks,
                                                          pedges, spans, nspans);
 }
 
@@ -2185,7 +2219,7 @@ void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const u
                        unsigned long long* cedges, const int* spans, const unsigned* nspans,
                        hipStream_t st)
 {
-    k_conn_claim<1><<<round_grid(n, spans), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks,
+    k_conn_claim<<<round_grid(n, spans), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks,
                                                           pi, layer, ctl, cedges, spans, nspans);
 }
 
@@ -2216,11 +2250,11 @@ void launch_round(int k, int n, const int* row_ptr, const int* col, const int* r
                   unsigned push_min, bool may_push, hipStream_t st)
 {
     const unsigned grid = (unsigned)round_spans(n);
-    k_round_mark_pull<1><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, rin_ptr, rin, acur, anext,
-                                               marks, pi, layer, ctl, pedges, policy, push_min);
+    k_round_mark_pull<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, rin_ptr, rin, acur, anext, marks,
+                                            pi, layer, ctl, pedges, policy, push_min);
     if (may_push)
-        k_round_claim<1><<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer,
-                                               ctl, policy, push_min);
+        k_round_claim<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer, ctl,
+                                            policy, push_min);
 }
 
 void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsigned* tot,
