@@ -128,9 +128,10 @@ typedef struct {
 typedef struct {
     int32_t max_iters;         /* 0 = unlimited                                */
     int32_t validate;          /* 1 = check the CSR on the device first        */
-    int32_t schedule;          /* lanes per vertex in the sweep: 1..64 (power
-                                  of two), 0 = chosen from the mean degree
-                                  (batched calls: autotuned)                   */
+    int32_t schedule;          /* sweep schedule: 1..64 (power of two) lanes
+                                  per vertex; 0 = vertex tiles with their
+                                  edges staged in LDS (batched calls: lanes
+                                  autotuned); same results either way          */
     int32_t tie_check;         /* 1 = run the exact uniqueness test of C       */
     int32_t fast_path;         /* 1 = fuse cycle/value phases while the critical
                                   cycle is unchanged (same results)            */
