@@ -1248,10 +1248,11 @@ ocm_status host_connect(BCtx& c)
             ocm::launch_conn_mark(c.n, ws.rin_ptr, ws.rin, acur, anext, ws.marks, nullptr, ws.spans,
                                   &ws.bc->nspans, c.st);
             ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, ws.marks, ws.pi, nullptr,
-                                   cc, nullptr, ws.spans, &ws.bc->nspans, c.st);
+                                   cc, nullptr, ws.spans, &ws.bc->nspans, nullptr, nullptr,
+                                   nullptr, nullptr, c.st);
         } else {
             ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, nullptr, ws.pi, cc,
-                                  nullptr, ws.spans, &ws.bc->nspans, c.st);
+                                  nullptr, ws.spans, &ws.bc->nspans, nullptr, c.st);
         }
         BHIP(hipGetLastError());
         BHIP(ocm::host_read_ctl(cc, &h, c.st));

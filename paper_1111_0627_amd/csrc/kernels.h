@@ -63,6 +63,7 @@ struct alignas(128) Ctl {
     unsigned rfront;               //   vertices attached by the last round
     unsigned rerr;                 //   a round attached nobody while vertices were left
     unsigned rk;                   //   rounds run
+    unsigned rmarks;               //   the round whose marks a push round left
     unsigned long long rpack;      //   lanes done with a round kernel, and their counts
     unsigned jk;                   // jump rounds on the device (values, cycles): rounds run
     unsigned jmode;                //   1 while rounds are left, 0 once they are over
@@ -212,17 +213,24 @@ void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, in
 // spans, nullptr means every span.
 int round_wpt(int n);
 int64_t round_spans(int n);
-// Host-driven round steps (the host picks each round's direction).
+// Host-driven round steps (the host picks each round's direction).  Push
+// round k: the marks (frontier in-edges -> mark bytes), unless round k-1
+// left them, then the claims, which with marks_next also mark round k+1's
+// frontier there (the next round's mark array).  A pull round given `stale`
+// clears those mark bytes (marks a push round left for it).  Any superset
+// of the marked vertices gives the same attachments.
 void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                       unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
-                      const int* spans, const unsigned* nspans, hipStream_t st);
+                      const int* spans, const unsigned* nspans, unsigned char* stale,
+                      hipStream_t st);
 void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned* acur,
-                      unsigned* anext, unsigned char* marks, unsigned long long* pedges,
+                      const unsigned* anext, unsigned char* marks, unsigned long long* pedges,
                       const int* spans, const unsigned* nspans, hipStream_t st);
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                        unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
                        unsigned long long* cedges, const int* spans, const unsigned* nspans,
-                       hipStream_t st);
+                       const int* rin_ptr, const int* rin, unsigned char* marks_next,
+                       unsigned long long* pedges, hipStream_t st);
 // Device-driven rounds: setup stores the counts after the init and picks
 // round 1's direction (policy 0: push while left >= push_min and 2 * front <
 // left, 1: pull, 2: push); launch_round queues round k (a push or pull round
@@ -233,8 +241,9 @@ void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, int policy, uns
                         hipStream_t st);
 void launch_round(int k, int n, const int* row_ptr, const int* col, const int* rin_ptr,
                   const int* rin, const unsigned* acur, unsigned* anext, unsigned char* marks,
-                  int* pi, int* layer, Ctl* ctl, unsigned long long* pedges, int policy,
-                  unsigned push_min, bool may_push, hipStream_t st);
+                  unsigned char* marks_next, int* pi, int* layer, Ctl* ctl,
+                  unsigned long long* pedges, int policy, unsigned push_min, bool may_push,
+                  hipStream_t st);
 // Reverse CSR (rin_ptr, rin) of the graph.  With `scratch` of
 // rev_scratch_bytes(n, m) bytes (0 when the plan does not apply) the build
 // is partitioned by head bucket; otherwise it counts and fills with global

@@ -891,6 +891,12 @@ struct WaveLds {
     unsigned nb[kWaves][64];    // vertices attached in the round, per word
 };
 
+// LDS of a round kernel that claims and then marks (used one after the other).
+union RoundLds {
+    WaveLds wave;
+    MarkLds mark;
+};
+
 // LDS written by some lanes of a wave and read by others.
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -1025,88 +1031,6 @@ __device__ __forceinline__ void for_each_span(const int* __restrict__ spans, con
     for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) f(spans ? (int64_t)spans[i] : i);
 }
 
-// Pull round k: the unattached vertices (~acur) scan their out-edges; anext
-// becomes acur plus this round's attachments.  Returns (in thread 0) the
-// workgroup's attachment count.
-__device__ __forceinline__ unsigned long long pull_body(
-    int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
-    const unsigned* __restrict__ acur, unsigned* __restrict__ anext, int* __restrict__ layer,
-    int* __restrict__ pi, unsigned long long* ledges, const int* __restrict__ spans,
-    const unsigned* nspans, WaveLds& L)
-{
-    const int64_t words = ((int64_t)n + 31) / 32;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    unsigned got = 0;
-    unsigned long long scanned = 0;
-    for_each_span(spans, nspans, (words + kWG - 1) / kWG, [&](int64_t span) {
-        const int64_t w = span * kWG + threadIdx.x;
-        const unsigned a = w < words ? acur[w] : 0u;
-        const unsigned mask = w < words ? ~a & valid_bits(w, n) : 0u;
-        got += wave_attach(k, (w - lane) * 32, mask, row_ptr, col, acur, pi, layer, L.pre[wave],
-                           L.msk[wave], L.nb[wave], &scanned);
-        if (w < words) anext[w] = a | L.nb[wave][lane];
-    });
-    const unsigned long long g = block_sum_u64(got);
-    scanned = block_sum_u64(scanned);
-    if (threadIdx.x == 0 && ledges && scanned) atomicAdd(my_copy(ledges), scanned);
-    return g;
-}
-
-// Push round k, mark: each span lists its frontier vertices (acur & ~anext,
-// folded into anext on the way) and spreads their in-edges over the
-// workgroup; every tail u gets marks[u] = 1 (plain byte store, idempotent).
-// Attached tails are dropped by the claim, which reads its span of acur
-// anyway.
-__device__ __forceinline__ void mark_body(int n, const int* __restrict__ rin_ptr,
-                                          const int* __restrict__ rin,
-                                          const unsigned* __restrict__ acur,
-                                          unsigned* __restrict__ anext,
-                                          unsigned char* __restrict__ marks,
-                                          unsigned long long* pedges, const int* __restrict__ spans,
-                                          const unsigned* nspans, MarkLds& L)
-{
-    const int64_t words = ((int64_t)n + 31) / 32;
-    unsigned long long scanned = 0;
-    for_each_span(spans, nspans, (words + kWG - 1) / kWG, [&](int64_t span) {
-        const int64_t w0 = span * kWG + threadIdx.x;
-        unsigned long long mask = 0;
-        if (w0 < words) {
-            const unsigned a = acur[w0];
-            const unsigned f = a & ~anext[w0];
-            if (f) anext[w0] = a;   // anext is a subset of acur
-            mask = f;
-        }
-        unsigned total = 0;
-        const unsigned rank = block_rank((unsigned)__popcll(mask), L.wsum, &total);
-        for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
-            emit_batch(mask, w0 * 32, rank, b0, L.todo);
-            __syncthreads();
-            const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
-            gather_rows(rin_ptr, L.todo, cnt, L.beg, L.off);
-            __syncthreads();
-            const unsigned tot = block_excl_scan(L.off, cnt, L.wsum);
-            constexpr int U = 2 * kExpand;
-            for (unsigned t0 = threadIdx.x; t0 < tot; t0 += U * kWG) {
-                int x[U];
-#pragma unroll
-                for (int j = 0; j < U; ++j) {
-                    const unsigned t = t0 + j * kWG;
-                    const unsigned i = t < tot ? owner_of(L.off, cnt, t) : 0;
-                    x[j] = t < tot ? L.beg[i] + (int)(t - L.off[i]) : -1;
-                }
-#pragma unroll
-                for (int j = 0; j < U; ++j) x[j] = x[j] >= 0 ? rin[x[j]] : -1;
-#pragma unroll
-                for (int j = 0; j < U; ++j)
-                    if (x[j] >= 0) marks[x[j]] = 1;
-            }
-            scanned += tot;
-            __syncthreads();
-        }
-    });
-    if (pedges && threadIdx.x == 0 && scanned) atomicAdd(my_copy(pedges), scanned);
-}
-
 // The 32 mark bytes of word w as a bit mask, cleared on the way (marks are
 // 0 or 1).
 __device__ __forceinline__ unsigned take_marks(unsigned char* __restrict__ marks, int64_t w, int n)
@@ -1134,16 +1058,15 @@ __device__ __forceinline__ unsigned take_marks(unsigned char* __restrict__ marks
     return mask;
 }
 
-// Push round k, claim: each word takes its mark bytes (clearing them); the
-// marked vertices not attached yet find their lowest out-edge into the
-// attached set.  One exists: the edge that marked the vertex.  The vertex
-// attaches with it (pi, layer = k) and joins anext.  Returns (in thread 0)
-// the workgroup's attachment count.
-__device__ __forceinline__ unsigned long long claim_body(
+// Pull round k: the unattached vertices (~acur) scan their out-edges; anext
+// becomes acur plus this round's attachments.  With stale (marks left by a
+// push round before it for this round), their bytes are cleared.  Returns (in
+// thread 0) the workgroup's attachment count.
+__device__ __forceinline__ unsigned long long pull_body(
     int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
-    const unsigned* __restrict__ acur, unsigned* __restrict__ anext,
-    unsigned char* __restrict__ marks, int* __restrict__ pi, int* __restrict__ layer,
-    unsigned long long* cedges, const int* __restrict__ spans, const unsigned* nspans, WaveLds& L)
+    const unsigned* __restrict__ acur, unsigned* __restrict__ anext, int* __restrict__ layer,
+    int* __restrict__ pi, unsigned long long* ledges, const int* __restrict__ spans,
+    const unsigned* nspans, unsigned char* __restrict__ stale, WaveLds& L)
 {
     const int64_t words = ((int64_t)n + 31) / 32;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1151,16 +1074,121 @@ __device__ __forceinline__ unsigned long long claim_body(
     unsigned long long scanned = 0;
     for_each_span(spans, nspans, (words + kWG - 1) / kWG, [&](int64_t span) {
         const int64_t w = span * kWG + threadIdx.x;
-        // marked tails that are already attached drop out
-        const unsigned mask = w < words ? take_marks(marks, w, n) & ~acur[w] : 0u;
+        const unsigned a = w < words ? acur[w] : 0u;
+        const unsigned mask = w < words ? ~a & valid_bits(w, n) : 0u;
+        if (stale && w < words) (void)take_marks(stale, w, n);
         got += wave_attach(k, (w - lane) * 32, mask, row_ptr, col, acur, pi, layer, L.pre[wave],
                            L.msk[wave], L.nb[wave], &scanned);
-        const unsigned x = L.nb[wave][lane];
-        if (x && w < words) anext[w] |= x;
+        if (w < words) anext[w] = a | L.nb[wave][lane];
     });
     const unsigned long long g = block_sum_u64(got);
     scanned = block_sum_u64(scanned);
-    if (threadIdx.x == 0 && cedges && scanned) atomicAdd(my_copy(cedges), scanned);
+    if (threadIdx.x == 0 && ledges && scanned) atomicAdd(my_copy(ledges), scanned);
+    return g;
+}
+
+// Marks the tails of the in-edges of the workgroup's listed vertices (mask:
+// this thread's word w0) in marks: marks[u] = 1, a plain byte store
+// (idempotent).  The vertices go through LDS in batches of kBatch and their
+// in-edges are spread over the workgroup.  Returns the in-edges visited
+// (the same in every thread).  All threads call it; it ends with a barrier.
+__device__ __forceinline__ unsigned mark_in_edges(unsigned mask, int64_t w0,
+                                                  const int* __restrict__ rin_ptr,
+                                                  const int* __restrict__ rin,
+                                                  unsigned char* __restrict__ marks, MarkLds& L)
+{
+    unsigned total = 0, visited = 0;
+    const unsigned rank = block_rank((unsigned)__popc(mask), L.wsum, &total);
+    for (unsigned b0 = 0; b0 < total; b0 += kBatch) {
+        emit_batch(mask, w0 * 32, rank, b0, L.todo);
+        __syncthreads();
+        const unsigned cnt = total - b0 < kBatch ? total - b0 : kBatch;
+        gather_rows(rin_ptr, L.todo, cnt, L.beg, L.off);
+        __syncthreads();
+        const unsigned tot = block_excl_scan(L.off, cnt, L.wsum);
+        constexpr int U = 2 * kExpand;
+        for (unsigned t0 = threadIdx.x; t0 < tot; t0 += U * kWG) {
+            int x[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const unsigned t = t0 + j * kWG;
+                const unsigned i = t < tot ? owner_of(L.off, cnt, t) : 0;
+                x[j] = t < tot ? L.beg[i] + (int)(t - L.off[i]) : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) x[j] = x[j] >= 0 ? rin[x[j]] : -1;
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                if (x[j] >= 0) marks[x[j]] = 1;
+        }
+        visited += tot;
+        __syncthreads();
+    }
+    return visited;
+}
+
+// Push round k, mark: the frontier (acur & ~anext) marks the tails of its
+// in-edges.  Attached tails are dropped by the claim, which reads its words
+// of acur anyway.  Used for a push round whose marks the previous round did
+// not leave (the first one, or one after a pull round).
+__device__ __forceinline__ void mark_body(int n, const int* __restrict__ rin_ptr,
+                                          const int* __restrict__ rin,
+                                          const unsigned* __restrict__ acur,
+                                          const unsigned* __restrict__ anext,
+                                          unsigned char* __restrict__ marks,
+                                          unsigned long long* pedges, const int* __restrict__ spans,
+                                          const unsigned* nspans, MarkLds& L)
+{
+    const int64_t words = ((int64_t)n + 31) / 32;
+    unsigned long long scanned = 0;
+    for_each_span(spans, nspans, (words + kWG - 1) / kWG, [&](int64_t span) {
+        const int64_t w0 = span * kWG + threadIdx.x;
+        const unsigned f = w0 < words ? acur[w0] & ~anext[w0] : 0u;
+        scanned += mark_in_edges(f, w0, rin_ptr, rin, marks, L);
+    });
+    if (pedges && threadIdx.x == 0 && scanned) atomicAdd(my_copy(pedges), scanned);
+}
+
+// Push round k, claim: each word takes its mark bytes (clearing them); the
+// marked vertices not attached yet find their lowest out-edge into the
+// attached set.  One exists: the edge that marked the vertex.  The vertex
+// attaches with it (pi, layer = k); anext gets acur plus the attachments
+// (whole words).  With marks_next, the workgroup then marks the in-edge
+// tails of its attachments, the next round's frontier, in marks_next (the
+// next round's mark array; this round's is marks).  Returns (in thread 0)
+// the workgroup's attachment count.
+__device__ __forceinline__ unsigned long long claim_body(
+    int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
+    const unsigned* __restrict__ acur, unsigned* __restrict__ anext,
+    unsigned char* __restrict__ marks, int* __restrict__ pi, int* __restrict__ layer,
+    unsigned long long* cedges, const int* __restrict__ spans, const unsigned* nspans,
+    const int* __restrict__ rin_ptr, const int* __restrict__ rin,
+    unsigned char* __restrict__ marks_next, unsigned long long* pedges, RoundLds& L)
+{
+    const int64_t words = ((int64_t)n + 31) / 32;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned got = 0;
+    unsigned long long scanned = 0, marked = 0;
+    for_each_span(spans, nspans, (words + kWG - 1) / kWG, [&](int64_t span) {
+        const int64_t w = span * kWG + threadIdx.x;
+        const unsigned a = w < words ? acur[w] : 0u;
+        // marked tails that are already attached drop out
+        const unsigned mask = w < words ? take_marks(marks, w, n) & ~a : 0u;
+        got += wave_attach(k, (w - lane) * 32, mask, row_ptr, col, acur, pi, layer,
+                           L.wave.pre[wave], L.wave.msk[wave], L.wave.nb[wave], &scanned);
+        const unsigned x = L.wave.nb[wave][lane];
+        if (w < words) anext[w] = a | x;
+        if (marks_next) {
+            __syncthreads();   // the LDS turns into the mark step's
+            marked += mark_in_edges(x, w, rin_ptr, rin, marks_next, L.mark);
+        }
+    });
+    const unsigned long long g = block_sum_u64(got);
+    scanned = block_sum_u64(scanned);
+    if (threadIdx.x == 0) {
+        if (cedges && scanned) atomicAdd(my_copy(cedges), scanned);
+        if (pedges && marked) atomicAdd(my_copy(pedges), marked);
+    }
     return g;
 }
 
@@ -1172,18 +1200,19 @@ __global__ __launch_bounds__(kWG) void k_conn_pull(int k, int n, const int* __re
                                                    int* __restrict__ layer, int* __restrict__ pi,
                                                    Ctl* ctl, unsigned long long* ledges,
                                                    const int* __restrict__ spans,
-                                                   const unsigned* nspans)
+                                                   const unsigned* nspans,
+                                                   unsigned char* __restrict__ stale)
 {
     __shared__ WaveLds L;
     const unsigned long long g =
-        pull_body(k, n, row_ptr, col, acur, anext, layer, pi, ledges, spans, nspans, L);
+        pull_body(k, n, row_ptr, col, acur, anext, layer, pi, ledges, spans, nspans, stale, L);
     if (threadIdx.x == 0 && g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
 }
 
 __global__ __launch_bounds__(kWG) void k_conn_mark(int n, const int* __restrict__ rin_ptr,
                                                    const int* __restrict__ rin,
                                                    const unsigned* __restrict__ acur,
-                                                   unsigned* __restrict__ anext,
+                                                   const unsigned* __restrict__ anext,
                                                    unsigned char* __restrict__ marks,
                                                    unsigned long long* pedges,
                                                    const int* __restrict__ spans,
@@ -1201,11 +1230,16 @@ __global__ __launch_bounds__(kWG) void k_conn_claim(int k, int n, const int* __r
                                                     int* __restrict__ pi, int* __restrict__ layer,
                                                     Ctl* ctl, unsigned long long* cedges,
                                                     const int* __restrict__ spans,
-                                                    const unsigned* nspans)
+                                                    const unsigned* nspans,
+                                                    const int* __restrict__ rin_ptr,
+                                                    const int* __restrict__ rin,
+                                                    unsigned char* __restrict__ marks_next,
+                                                    unsigned long long* pedges)
 {
-    __shared__ WaveLds L;
+    __shared__ RoundLds L;
     const unsigned long long g = claim_body(k, n, row_ptr, col, acur, anext, marks, pi, layer,
-                                            cedges, spans, nspans, L);
+                                            cedges, spans, nspans, rin_ptr, rin, marks_next,
+                                            pedges, L);
     if (threadIdx.x == 0 && g) atomicAdd(&my_lane(ctl).got, (unsigned)g);
 }
 
@@ -1229,14 +1263,16 @@ __device__ __forceinline__ unsigned round_mode(unsigned left, unsigned front, in
 // Called by thread 0 of every workgroup of round k's final kernel with the
 // workgroup's attachment count g.  The last workgroup to arrive books the
 // round's attachments and picks round k + 1's direction (a round that
-// attached nobody while vertices were left ends the rebuild with rerr set).
+// attached nobody while vertices were left ends the rebuild with rerr set);
+// marked_next: the round left round k + 1's marks.
 __device__ __forceinline__ void round_close(Ctl* c, int k, unsigned long long g, int policy,
-                                            unsigned push_min)
+                                            unsigned push_min, bool marked_next)
 {
     unsigned long long tot;
     if (!last_arrival(c, arrival_word(g, 0), &tot)) return;
     const unsigned got = (unsigned)tot;
     c->rk = (unsigned)k;
+    if (marked_next) c->rmarks = (unsigned)k + 1;
     if (got == 0) {
         c->rerr = 1;
         c->rmode = 0;
@@ -1253,38 +1289,43 @@ __device__ __forceinline__ bool round_is(const Ctl* c, int k, unsigned mode)
     return c->rk + 1 == (unsigned)k && c->rmode == mode;
 }
 
-// Round k's first kernel: the marks of a push round, or a whole pull round.
+// Round k's first kernel: the marks of a push round (unless round k-1 left
+// them), or a whole pull round (clearing marks round k-1 left).  marks is
+// round k's mark array (marks[k & 1] of the pair).
 __global__ __launch_bounds__(kWG) void k_round_mark_pull(
     int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
     const int* __restrict__ rin_ptr, const int* __restrict__ rin, const unsigned* __restrict__ acur,
     unsigned* __restrict__ anext, unsigned char* __restrict__ marks, int* __restrict__ pi,
     int* __restrict__ layer, Ctl* ctl, unsigned long long* pedges, int policy, unsigned push_min)
 {
-    __shared__ union {
-        MarkLds mark;
-        WaveLds pull;
-    } L;
+    __shared__ RoundLds L;
+    const bool left_marks = ctl->rmarks == (unsigned)k;
     if (round_is(ctl, k, 1u)) {
-        mark_body(n, rin_ptr, rin, acur, anext, marks, pedges, nullptr, nullptr, L.mark);
+        if (!left_marks)
+            mark_body(n, rin_ptr, rin, acur, anext, marks, pedges, nullptr, nullptr, L.mark);
     } else if (round_is(ctl, k, 2u)) {
-        const unsigned long long g = pull_body(k, n, row_ptr, col, acur, anext, layer, pi, nullptr,
-                                               nullptr, nullptr, L.pull);
-        if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min);
+        const unsigned long long g =
+            pull_body(k, n, row_ptr, col, acur, anext, layer, pi, nullptr, nullptr, nullptr,
+                      left_marks ? marks : nullptr, L.wave);
+        if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min, false);
     }
 }
 
-// Round k's second kernel: the claims of a push round.
-__global__ __launch_bounds__(kWG) void k_round_claim(
+// Round k's second kernel: the claims of a push round, and the marks of
+// round k + 1 in marks_next.
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_round_claim(
     int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
-    const unsigned* __restrict__ acur, unsigned* __restrict__ anext,
-    unsigned char* __restrict__ marks, int* __restrict__ pi, int* __restrict__ layer, Ctl* ctl,
-    int policy, unsigned push_min)
+    const int* __restrict__ rin_ptr, const int* __restrict__ rin, const unsigned* __restrict__ acur,
+    unsigned* __restrict__ anext, unsigned char* __restrict__ marks,
+    unsigned char* __restrict__ marks_next, int* __restrict__ pi, int* __restrict__ layer, Ctl* ctl,
+    unsigned long long* pedges, int policy, unsigned push_min)
 {
     if (!round_is(ctl, k, 1u)) return;
-    __shared__ WaveLds L;
+    __shared__ RoundLds L;
     const unsigned long long g = claim_body(k, n, row_ptr, col, acur, anext, marks, pi, layer,
-                                            nullptr, nullptr, nullptr, L);
-    if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min);
+                                            nullptr, nullptr, nullptr, rin_ptr, rin, marks_next,
+                                            pedges, L);
+    if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -2200,14 +2241,15 @@ static unsigned round_grid(int n, const int* spans)
 
 void launch_conn_pull(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                       unsigned* anext, int* layer, int* pi, Ctl* ctl, unsigned long long* ledges,
-                      const int* spans, const unsigned* nspans, hipStream_t st)
+                      const int* spans, const unsigned* nspans, unsigned char* stale,
+                      hipStream_t st)
 {
-    k_conn_pull<<<round_grid(n, spans), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer,
-                                                         pi, ctl, ledges, spans, nspans);
+    k_conn_pull<<<round_grid(n, spans), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, layer, pi,
+                                                      ctl, ledges, spans, nspans, stale);
 }
 
 void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned* acur,
-                      unsigned* anext, unsigned char* marks, unsigned long long* pedges,
+                      const unsigned* anext, unsigned char* marks, unsigned long long* pedges,
                       const int* spans, const unsigned* nspans, hipStream_t st)
 {
     k_conn_mark<<<round_grid(n, spans), kWG, 0, st>>>(n, rin_ptr, rin, acur, anext, marks,
@@ -2217,10 +2259,12 @@ void launch_conn_mark(int n, const int* rin_ptr, const int* rin, const unsigned*
 void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const unsigned* acur,
                        unsigned* anext, unsigned char* marks, int* pi, int* layer, Ctl* ctl,
                        unsigned long long* cedges, const int* spans, const unsigned* nspans,
-                       hipStream_t st)
+                       const int* rin_ptr, const int* rin, unsigned char* marks_next,
+                       unsigned long long* pedges, hipStream_t st)
 {
-    k_conn_claim<<<round_grid(n, spans), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks,
-                                                          pi, layer, ctl, cedges, spans, nspans);
+    k_conn_claim<<<round_grid(n, spans), kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi,
+                                                       layer, ctl, cedges, spans, nspans, rin_ptr,
+                                                       rin, marks_next, pedges);
 }
 
 // Device-driven rebuild rounds (one wave each).
@@ -2233,6 +2277,7 @@ __global__ void k_round_setup(Ctl* c, unsigned left, unsigned front, int policy,
         c->rfront = front;
         c->rerr = 0;
         c->rk = 0;
+        c->rmarks = 0;
         c->rpack = 0;
         c->rmode = round_mode(left, front, policy, push_min);
     }
@@ -2246,15 +2291,16 @@ void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, int policy, uns
 
 void launch_round(int k, int n, const int* row_ptr, const int* col, const int* rin_ptr,
                   const int* rin, const unsigned* acur, unsigned* anext, unsigned char* marks,
-                  int* pi, int* layer, Ctl* ctl, unsigned long long* pedges, int policy,
-                  unsigned push_min, bool may_push, hipStream_t st)
+                  unsigned char* marks_next, int* pi, int* layer, Ctl* ctl,
+                  unsigned long long* pedges, int policy, unsigned push_min, bool may_push,
+                  hipStream_t st)
 {
     const unsigned grid = (unsigned)round_spans(n);
     k_round_mark_pull<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, rin_ptr, rin, acur, anext, marks,
                                             pi, layer, ctl, pedges, policy, push_min);
     if (may_push)
-        k_round_claim<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, acur, anext, marks, pi, layer, ctl,
-                                            policy, push_min);
+        k_round_claim<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, rin_ptr, rin, acur, anext, marks,
+                                            marks_next, pi, layer, ctl, pedges, policy, push_min);
 }
 
 void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsigned* tot,

@@ -73,7 +73,7 @@ struct Ws {
     int* rin;            // reverse CSR entries: the tail of each in-edge (m)
     void* rscratch;      // reverse CSR build: partition scratch (pairs and histograms)
     unsigned* abits[2];  // connect: attached-vertex bitmaps (alternating by round)
-    unsigned char* marks;  // push rounds: marked vertices (bytes)
+    unsigned char* marks[2];  // push rounds: marked vertices (bytes), by round parity
     unsigned char* touched;  // tie check: special-vertex flags
     void* sel;           // select: per-block best candidates
     int* xs;             // tie check: tight non-policy edges (tail), xcap entries
@@ -117,7 +117,8 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.rscratch = take(ocm::rev_scratch_bytes(n, m));
     w.abits[0] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.abits[1] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
-    w.marks = (unsigned char*)take(N + 16);
+    w.marks[0] = (unsigned char*)take(N + 16);
+    w.marks[1] = (unsigned char*)take(N + 16);
     w.touched = (unsigned char*)take(N + 16);
     w.sel = take(32 * ocm::kSelectParts);
     w.xcap = (unsigned)(m < kTieListCap ? m : kTieListCap);
@@ -430,8 +431,19 @@ ocm_status phase_select(Ctx& c, const int* pi, const int* rep, const unsigned ch
 // The rebuild rounds without a host round trip per round: each round's
 // direction is picked on the device by the round before it (same rule as the
 // host loop below), two kernels are queued per round (marks or a pull round,
-// then the claims), and the host reads the state back every kRoundsPerRead
-// rounds.  Rounds queued after the last one do nothing.
+// then the claims and the next round's marks), and the host reads the state
+// back every kRoundsPerRead rounds.  Rounds queued after the last one do
+// nothing.
+
+// Reverse CSR for push rounds, once per solve; both mark arrays start clear.
+void build_reverse(Ctx& c)
+{
+    Ws& w = c.ws;
+    ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr, w.rin,
+                          w.marks[0], w.rscratch, c.st);
+    ocm::launch_fill_u32((unsigned*)w.marks[1], ((int64_t)c.n + 3) / 4, 0u, c.st);
+    c.rev_built = true;
+}
 
 ocm_status connect_rounds_on_device(Ctx& c, int* pi, int* layer, unsigned left, unsigned front,
                                     int* rounds)
@@ -440,10 +452,8 @@ ocm_status connect_rounds_on_device(Ctx& c, int* pi, int* layer, unsigned left, 
     const int policy = c.connect_mode;   // 0 automatic, 1 pull, 2 push
     const bool may_push = policy == 2 || (policy == 0 && left >= kPushMinUnattached);
     if (may_push && !c.rev_built) {
-        ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr, w.rin,
-                              w.marks, w.rscratch, c.st);
+        build_reverse(c);
         HIP_TRY(hipGetLastError());
-        c.rev_built = true;
     }
     ocm::launch_round_setup(w.ctl, left, front, policy, kPushMinUnattached, c.st);
     unsigned long long* pedges = &w.ctl->lane[0].pedges;
@@ -452,8 +462,8 @@ ocm_status connect_rounds_on_device(Ctx& c, int* pi, int* layer, unsigned left, 
         for (int j = 0; j < kRoundsPerRead; ++j) {
             ++k;
             ocm::launch_round(k, c.n, c.row_ptr, c.col, w.rin_ptr, w.rin, w.abits[k & 1],
-                              w.abits[(k + 1) & 1], w.marks, pi, layer, w.ctl, pedges, policy,
-                              kPushMinUnattached, may_push, c.st);
+                              w.abits[(k + 1) & 1], w.marks[k & 1], w.marks[(k + 1) & 1], pi,
+                              layer, w.ctl, pedges, policy, kPushMinUnattached, may_push, c.st);
         }
         HIP_TRY(hipGetLastError());
         OCM_TRY(read_ctl(c));
@@ -489,6 +499,7 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
     // the scanned-edge counts only feed the profile's byte figures
     unsigned long long* ledges = c.prof.out ? &w.ctl->lane[0].ledges : nullptr;
     int k = 0;
+    int marked = 0;   // the round whose marks the last push round left
     ocm_status rc = OCM_OK;
     while (left > 0) {
         ++k;
@@ -498,34 +509,44 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
             push = left >= kPushMinUnattached && (uint64_t)front * 2 < left;
         if (push && !c.rev_built) {
             c.prof.begin(OCM_K_REVERSE);
-            ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr, w.rin,
-                                  w.marks, w.rscratch, c.st);
+            build_reverse(c);
             c.prof.end();
             // count: col + counter per edge; fill, scan and copy of the
             // counters; fill: row_ptr, col, cursor and the 4-byte tail per
             // edge; mark reset
             c.prof.bytes(OCM_K_REVERSE, 20.0 * c.m + 29.0 * c.n);
             HIP_TRY(hipGetLastError());
-            c.rev_built = true;
         }
         // round k reads abits[k&1] and completes abits[(k+1)&1]
         const unsigned* acur = w.abits[k & 1];
         unsigned* anext = w.abits[(k + 1) & 1];
         ocm::launch_ctl_clear(w.ctl, ocm::kClrCount, c.st);
+        const bool standalone = push && marked != k;
         if (push) {
-            c.prof.begin(OCM_K_CONN_MARK);
-            ocm::launch_conn_mark(c.n, w.rin_ptr, w.rin, acur, anext, w.marks, pedges, nullptr,
-                                  nullptr, c.st);
-            c.prof.end();
+            if (standalone) {
+                c.prof.begin(OCM_K_CONN_MARK);
+                ocm::launch_conn_mark(c.n, w.rin_ptr, w.rin, acur, anext, w.marks[k & 1], pedges,
+                                      nullptr, nullptr, c.st);
+                c.prof.end();
+                HIP_TRY(hipGetLastError());
+                OCM_TRY(read_ctl(c));
+                // both bitmaps; per frontier vertex its offsets, per in-edge
+                // the 4-byte tail (its mark bytes are booked below)
+                c.prof.bytes(OCM_K_CONN_MARK,
+                             2.0 * bitmaps + 8.0 * front + 4.0 * (double)(c.h.pedges - pe0));
+                pe0 = c.h.pedges;
+            }
             c.prof.begin(OCM_K_CONN_CLAIM);
-            ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, w.marks, pi, layer,
-                                   w.ctl, ledges, nullptr, nullptr, c.st);
+            ocm::launch_conn_claim(k, c.n, c.row_ptr, c.col, acur, anext, w.marks[k & 1], pi, layer,
+                                   w.ctl, ledges, nullptr, nullptr, w.rin_ptr, w.rin,
+                                   w.marks[(k + 1) & 1], pedges, c.st);
             c.prof.end();
+            marked = k + 1;
             c.push_frontier += front;
         } else {
             c.prof.begin(OCM_K_CONN_PULL);
             ocm::launch_conn_pull(k, c.n, c.row_ptr, c.col, acur, anext, layer, pi, w.ctl, ledges,
-                                  nullptr, nullptr, c.st);
+                                  nullptr, nullptr, marked == k ? w.marks[k & 1] : nullptr, c.st);
             c.prof.end();
         }
         HIP_TRY(hipGetLastError());
@@ -533,14 +554,17 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
         const unsigned got = c.h.got;
         const double S = (double)(c.h.ledges - le0);
         if (push) {
-            // mark: both bitmaps, then per frontier vertex its offsets and
-            // per in-edge the 4-byte tail and its bit, and a mark byte per
-            // attached vertex; claim: the mark bytes, then per attached vertex
-            // its offsets, pi and (when requested) layer, and per scanned
-            // out-edge col and a bit; the new bitmap words
+            // claims: the mark bytes and both bitmaps (acur read, anext
+            // written); per attached vertex its offsets, pi and (when
+            // requested) layer; per scanned out-edge col and a bit.  The
+            // next round's marks: per attached vertex its in-edge offsets,
+            // per in-edge the 4-byte tail.  This round's attachments are the
+            // vertices marked for it, a byte each, booked to the step that
+            // marked them
             const double E = (double)(c.h.pedges - pe0);
-            c.prof.bytes(OCM_K_CONN_MARK, 2.0 * bitmaps + 8.0 * front + 4.125 * E + got);
-            c.prof.bytes(OCM_K_CONN_CLAIM, (double)c.n + (layer ? 16.0 : 12.0) * got + 4.125 * S + bitmaps);
+            c.prof.bytes(OCM_K_CONN_CLAIM, (double)c.n + 2.0 * bitmaps + (layer ? 16.0 : 12.0) * got +
+                                               4.125 * S + 8.0 * got + 4.0 * E);
+            c.prof.bytes(standalone ? OCM_K_CONN_MARK : OCM_K_CONN_CLAIM, (double)got);
         } else {
             // both bitmaps; per unattached vertex its offsets, per scanned
             // out-edge col and a bit; pi (and layer) of the attached
