@@ -1359,8 +1359,8 @@ __global__ __launch_bounds__(kWG) void k_rev_fill(int n, const int* __restrict__
 
 // Partitioned build (no global atomics): edges are binned by head bucket
 // (2^bits heads, bits = 12..14) in LDS, scattered bucket by bucket as
-// (head, tail) pairs, and one workgroup per bucket then counts its pairs per
-// head and places them.  When the bucket's in-edges fit in LDS they are
+// (head offset in the bucket: 16 bits, tail: 32 bits) in two arrays, and one
+// workgroup per bucket then counts its edges per head and places them.  When the bucket's in-edges fit in LDS they are
 // placed there and written out in order (scattered 4-byte stores over a
 // bucket's region in HBM cost several times their size in write traffic).
 // The order of a vertex's in-edges is arbitrary; the rounds only test
@@ -1369,6 +1369,7 @@ constexpr int kRevMinBits = 12;
 constexpr int kRevMaxBits = 14;
 constexpr int kRevMaxBuckets = 8192;
 constexpr int kPlaceWG = 1024;
+constexpr int kPlaceUnroll = 16;
 
 __global__ __launch_bounds__(kWG) void k_rev_hist(int64_t m, const int* __restrict__ col,
                                                   int64_t chunk, int nblk, int B, int bits,
@@ -1408,7 +1409,8 @@ __global__ __launch_bounds__(kWG) void k_rev_scatter(int n, const int* __restric
                                                      const int* __restrict__ col, int64_t m,
                                                      int64_t chunk, int nblk, int B, int bits,
                                                      const unsigned* __restrict__ hoff,
-                                                     int2* __restrict__ pairs)
+                                                     unsigned short* __restrict__ hlo,
+                                                     int* __restrict__ tails)
 {
     extern __shared__ unsigned cur[];   // B cursors
     __shared__ int su[2];
@@ -1418,6 +1420,7 @@ __global__ __launch_bounds__(kWG) void k_rev_scatter(int n, const int* __restric
     if (threadIdx.x == 0) su[0] = source_of(row_ptr, n, e0);
     if (threadIdx.x == 64) su[1] = source_of(row_ptr, n, e1 - 1);
     __syncthreads();
+    const int hmask = (1 << bits) - 1;
     // G lanes per source, U sources per group in flight
     constexpr int G = 8, U = 4;
     const int lane = threadIdx.x & (G - 1);
@@ -1442,12 +1445,14 @@ __global__ __launch_bounds__(kWG) void k_rev_scatter(int n, const int* __restric
             const int u = ub + j * kGroups;
             if (v[j] >= 0) {
                 const unsigned pos = atomicAdd(&cur[v[j] >> bits], 1u);
-                pairs[pos] = make_int2(v[j], u);
+                hlo[pos] = (unsigned short)(v[j] & hmask);
+                tails[pos] = u;
             }
             for (int e = lo[j] + lane + G; e < hi[j]; e += G) {   // out-degree above G
                 const int x = col[e];
                 const unsigned pos = atomicAdd(&cur[x >> bits], 1u);
-                pairs[pos] = make_int2(x, u);
+                hlo[pos] = (unsigned short)(x & hmask);
+                tails[pos] = u;
             }
         }
     }
@@ -1458,7 +1463,8 @@ __global__ __launch_bounds__(kWG) void k_rev_scatter(int n, const int* __restric
 __global__ __launch_bounds__(kPlaceWG) void k_rev_place(int n, int64_t m, int B, int nblk,
                                                         int bits, int64_t cap,
                                                         const unsigned* __restrict__ hoff,
-                                                        const int2* __restrict__ pairs,
+                                                        const unsigned short* __restrict__ hlo,
+                                                        const int* __restrict__ tails,
                                                         int* __restrict__ rin_ptr,
                                                         int* __restrict__ rin)
 {
@@ -1474,14 +1480,15 @@ __global__ __launch_bounds__(kPlaceWG) void k_rev_place(int n, int64_t m, int B,
     const int64_t end = bkt + 1 < B ? (int64_t)hoff[(int64_t)(bkt + 1) * nblk] : m;
     for (int i = threadIdx.x; i < H; i += kPlaceWG) cnt[i] = 0;
     __syncthreads();
-    constexpr int U = 4;   // independent loads in flight per thread
+    // one workgroup per CU (the LDS): many loads in flight per thread
+    constexpr int U = kPlaceUnroll;
     for (int64_t p = start + threadIdx.x; p < end; p += U * kPlaceWG) {
         int h[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) h[j] = p + j * kPlaceWG < end ? pairs[p + j * kPlaceWG].x : -1;
+        for (int j = 0; j < U; ++j) h[j] = p + j * kPlaceWG < end ? (int)hlo[p + j * kPlaceWG] : -1;
 #pragma unroll
         for (int j = 0; j < U; ++j)
-            if (h[j] >= 0) atomicAdd(&cnt[h[j] - lo], 1u);
+            if (h[j] >= 0) atomicAdd(&cnt[h[j]], 1u);
     }
     __syncthreads();
     // exclusive scan of cnt: each thread owns a run of H / kPlaceWG heads
@@ -1505,13 +1512,16 @@ __global__ __launch_bounds__(kPlaceWG) void k_rev_place(int n, int64_t m, int B,
     const bool staged = end - start <= cap;   // uniform
     int* out = staged ? stage : rin + start;
     for (int64_t p = start + threadIdx.x; p < end; p += U * kPlaceWG) {
-        int2 q[U];
+        int h[U], t[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const bool in = p + j * kPlaceWG < end;
+            h[j] = in ? (int)hlo[p + j * kPlaceWG] : -1;
+            t[j] = in ? tails[p + j * kPlaceWG] : 0;
+        }
 #pragma unroll
         for (int j = 0; j < U; ++j)
-            q[j] = p + j * kPlaceWG < end ? pairs[p + j * kPlaceWG] : make_int2(-1, 0);
-#pragma unroll
-        for (int j = 0; j < U; ++j)
-            if (q[j].x >= 0) out[atomicAdd(&cnt[q[j].x - lo], 1u)] = q[j].y;
+            if (h[j] >= 0) out[atomicAdd(&cnt[h[j]], 1u)] = t[j];
     }
     if (staged) {
         __syncthreads();
@@ -1547,7 +1557,8 @@ size_t rev_scratch_bytes(int64_t n, int64_t m)
     const RevPlan p = rev_plan(n, m);
     if (!p.partition) return 0;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    return al(8 * (size_t)m) + 2 * al(4 * (size_t)p.hist_len) + al(4 * ((size_t)p.hist_len / 2048 + 2));
+    return al(4 * (size_t)m) + al(2 * (size_t)m) + 2 * al(4 * (size_t)p.hist_len) +
+           al(4 * ((size_t)p.hist_len / 2048 + 2));
 }
 
 // Exclusive prefix sum of len unsigned values (three launches: per-block
@@ -2324,8 +2335,9 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
     if (p.partition && scratch && !atomic_build) {
         auto al = [](size_t b) { return (b + 255) / 256 * 256; };
         char* sp = (char*)scratch;
-        int2* pairs = (int2*)sp;
-        unsigned* hist = (unsigned*)(sp + al(8 * (size_t)m));
+        int* tails = (int*)sp;
+        auto* hlo = (unsigned short*)(sp + al(4 * (size_t)m));
+        unsigned* hist = (unsigned*)((char*)hlo + al(2 * (size_t)m));
         unsigned* hoff = (unsigned*)((char*)hist + al(4 * (size_t)p.hist_len));
         unsigned* htot = (unsigned*)((char*)hoff + al(4 * (size_t)p.hist_len));
         const size_t lds = 4 * (size_t)p.buckets;
@@ -2334,7 +2346,7 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
         launch_exclusive_scan(p.hist_len, hist, hoff, htot, st);
         k_rev_scatter<<<(unsigned)p.nblk, kWG, lds, st>>>(n, row_ptr, col, m, p.chunk,
                                                           (int)p.nblk, (int)p.buckets, p.bits,
-                                                          hoff, pairs);
+                                                          hoff, hlo, tails);
         // the placement's LDS: head counters, then as many staged entries as
         // the device's per-workgroup limit leaves room for
         const size_t counters = (size_t)4 << p.bits;
@@ -2349,7 +2361,7 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
             (void)hipFuncSetAttribute((const void*)k_rev_place,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)place_lds);
         k_rev_place<<<(unsigned)p.buckets, kPlaceWG, place_lds, st>>>(
-            n, m, (int)p.buckets, (int)p.nblk, p.bits, cap, hoff, pairs, rin_ptr, rin);
+            n, m, (int)p.buckets, (int)p.nblk, p.bits, cap, hoff, hlo, tails, rin_ptr, rin);
     } else {
         const int64_t len = (int64_t)n + 1;
         k_fill_u32<<<stride_grid(len), kWG, 0, st>>>(len, deg, 0u);
