@@ -164,8 +164,12 @@ struct SweepArgs {
 
 void launch_validate(int n, int m, const int* row_ptr, const int* col, const void* w, int wtype,
                      int check_csr, Ctl* ctl, hipStream_t st);
+// G = 0: vertex tiles (k_sweep_tile, k_tiescan_tile), else G lanes per
+// vertex.  tie: the tie scan instead of a sweep.  count_tight (tiles, not
+// first): the sweep also counts tight and certain edges as the tie scan's
+// first pass does (valid as such when it changes nothing).
 void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool first, bool tie,
-                  unsigned grid, hipStream_t st);
+                  bool count_tight, unsigned grid, hipStream_t st);
 // tag0 (optional): byte array marked with 1 at every successor; cnt: the
 // four stop-test counters, cleared
 void launch_pj_init(int n, const int* col, const int* pi, int* succ, unsigned long long* P,

@@ -264,8 +264,11 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
 // too).  Counts the tight edges other than the policy edge, those that
 // certainly close a second critical cycle (a tight self-loop, or a tight
 // edge leaving C: every policy path leads back to C), and those whose head
-// is not nearer the source; optionally lists them.
-template <typename WT>
+// is not nearer the source; optionally lists them.  SWEEP: also the
+// improvement sweep of k_sweep_tile (not FIRST) in the same pass; when it
+// changes no policy edge its counts are the tie scan's (no hop test, no
+// list), so the solve's last sweep doubles as the tie check's first scan.
+template <typename WT, bool SWEEP>
 __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __restrict__ w)
 {
     __shared__ int beg[kWG + 1];
@@ -290,6 +293,8 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
     const int e0 = beg[0], e1 = beg[nv];
     const int mb = t < nv ? beg[t] : 0, me = t < nv ? beg[t + 1] : 0;
     unsigned long long cnt = 0, certain = 0, nondec = 0;
+    long long best = INT64_MAX;
+    int pos = INT32_MAX;
     constexpr int U = kTileEdges / kWG;
     for (int eb = e0; eb < e1; eb += kTileEdges) {
         const int n_e = e1 - eb < kTileEdges ? e1 - eb : kTileEdges;
@@ -316,7 +321,12 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
         __syncthreads();
         const int lo = mb > eb ? mb : eb, hi = me < eb + n_e ? me : eb + n_e;
         for (int e = lo; e < hi; ++e) {
-            const bool tight = key[e - eb] == own && e != cur;
+            const long long k = key[e - eb];
+            if (SWEEP && k < best) {
+                best = k;
+                pos = e;
+            }
+            const bool tight = k == own && e != cur;
             const int h = head[e - eb];
             if (tight) {
                 cnt++;
@@ -333,14 +343,27 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
         }
         __syncthreads();
     }
+    unsigned long long changed = 0;
+    unsigned cbroken = 0;
+    if (SWEEP && t < nv && pos != INT32_MAX && best < own) {
+        a.pi[v0 + t] = pos;
+        changed = 1;
+        if (onc) cbroken = 1;
+    }
     cnt = block_sum_u64(cnt);
     certain = block_sum_u64(certain);
     nondec = block_sum_u64(nondec);
+    if (SWEEP) {
+        changed = block_sum_u64(changed);
+        cbroken = (unsigned)block_sum_u64(cbroken);
+    }
     if (t == 0) {
         CtlLane& ln = my_lane(a.ctl);
         if (cnt) atomicAdd(&ln.tight, cnt);
         if (certain) atomicAdd(&ln.certain, certain);
         if (nondec) atomicAdd(&ln.nondec, nondec);
+        if (SWEEP && changed) atomicAdd(&ln.changed, changed);
+        if (SWEEP && cbroken) atomicOr(&ln.cbroken, 1u);
     }
 }
 
@@ -2108,18 +2131,21 @@ void launch_validate(int n, int m, const int* row_ptr, const int* col, const voi
 }
 
 void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool first, bool tie,
-                  unsigned grid, hipStream_t st)
+                  bool count_tight, unsigned grid, hipStream_t st)
 {
     if (G == 0) {   // sweep over vertex tiles
         const unsigned tiles = blocks_for(a.n);
+        const bool fused = !tie && !first && count_tight;
         if (wtype == kWI64) {
             const long long* ww = (const long long*)w;
-            if (tie) k_tiescan_tile<long long><<<tiles, kWG, 0, st>>>(a, ww);
+            if (tie) k_tiescan_tile<long long, false><<<tiles, kWG, 0, st>>>(a, ww);
+            else if (fused) k_tiescan_tile<long long, true><<<tiles, kWG, 0, st>>>(a, ww);
             else if (first) k_sweep_tile<long long, true><<<tiles, kWG, 0, st>>>(a, ww);
             else k_sweep_tile<long long, false><<<tiles, kWG, 0, st>>>(a, ww);
         } else {
             const int* ww = (const int*)w;
-            if (tie) k_tiescan_tile<int><<<tiles, kWG, 0, st>>>(a, ww);
+            if (tie) k_tiescan_tile<int, false><<<tiles, kWG, 0, st>>>(a, ww);
+            else if (fused) k_tiescan_tile<int, true><<<tiles, kWG, 0, st>>>(a, ww);
             else if (first) k_sweep_tile<int, true><<<tiles, kWG, 0, st>>>(a, ww);
             else k_sweep_tile<int, false><<<tiles, kWG, 0, st>>>(a, ww);
         }
@@ -2127,8 +2153,9 @@ void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool firs
     }
     if (tie) {   // the tie scan always runs over vertex tiles
         const unsigned tiles = blocks_for(a.n);
-        if (wtype == kWI64) k_tiescan_tile<long long><<<tiles, kWG, 0, st>>>(a, (const long long*)w);
-        else k_tiescan_tile<int><<<tiles, kWG, 0, st>>>(a, (const int*)w);
+        if (wtype == kWI64)
+            k_tiescan_tile<long long, false><<<tiles, kWG, 0, st>>>(a, (const long long*)w);
+        else k_tiescan_tile<int, false><<<tiles, kWG, 0, st>>>(a, (const int*)w);
         return;
     }
     if (wtype == kWI64) launch_sweep_t<long long>(a, w, G, first, tie, grid, st);

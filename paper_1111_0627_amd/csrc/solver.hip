@@ -191,6 +191,9 @@ struct Ctx {
     int sw;              // bytes per weight
     unsigned sweep_grid;
     bool tile_sweep = true;   // schedule 0: sweeps over vertex tiles, else G lanes per vertex
+    bool count_tight = false;   // sweeps also count tight edges (tie check requested)
+    bool swept_tie = false;     // the last sweep's counts are the tie scan's first pass
+    unsigned long long swept_tight = 0, swept_certain = 0;
     int jump_rounds = 0;
     int connect_rounds = 0;
     int connect_mode = 0;   // 0 auto, 1 pull only, 2 push only
@@ -313,19 +316,25 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
         a.xcap = c.ws.xcap;
     }
     const int cls = tie ? OCM_K_TIESCAN : OCM_K_SWEEP;
+    const bool fused = !tie && !first && c.tile_sweep && c.count_tight;
     c.prof.begin(cls);
-    ocm::launch_sweep(a, c.w, c.wtype, c.tile_sweep ? 0 : c.G, first, tie, c.sweep_grid, c.st);
+    ocm::launch_sweep(a, c.w, c.wtype, c.tile_sweep ? 0 : c.G, first, tie, fused, c.sweep_grid,
+                      c.st);
     c.prof.end();
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
+    c.swept_tie = fused;
+    c.swept_tight = c.h.tight;
+    c.swept_certain = c.h.certain;
     // col + w per edge, row_ptr per vertex; after the first sweep also the
-    // gathered V per edge and the own V per vertex; the tie scan reads pi;
-    // policy writes of changed vertices
+    // gathered V per edge and the own V per vertex; the tie scan (and a
+    // sweep that counts tight edges) reads pi; policy writes of changed
+    // vertices
     const double n = c.n, m = c.m;
     double b = m * (4.0 + c.sw) + 4.0 * (n + 1);
     if (!first) b += 8.0 * m + 8.0 * n;
-    if (tie) b += 4.0 * n;
-    else b += 4.0 * (double)c.h.changed;
+    if (tie || fused) b += 4.0 * n;
+    if (!tie) b += 4.0 * (double)c.h.changed;
     c.prof.bytes(cls, b);
     return OCM_OK;
 }
@@ -718,12 +727,16 @@ bool has_cycle(int N, const std::vector<int>& head, const std::vector<int>& next
 ocm_status tie_check(Ctx& c, long long W, long long L, ocm_result* out)
 {
     Ws& w = c.ws;
-    OCM_TRY(phase_sweep(c, false, true, w.V, W, L, w.pi, w.onC));
-    const unsigned long long k = c.h.tight;
+    // the solve's last sweep changed nothing; if it counted tight edges, its
+    // counts are this first scan's
+    if (!c.swept_tie) OCM_TRY(phase_sweep(c, false, true, w.V, W, L, w.pi, w.onC));
+    const unsigned long long k = c.swept_tie ? c.swept_tight : c.h.tight;
+    const unsigned long long certain = c.swept_tie ? c.swept_certain : c.h.certain;
+    c.swept_tie = false;
     out->tight_edges = (int64_t)k;
     if (k == 0) return OCM_OK;
     out->flags |= OCM_F_TIGHT_EDGES;
-    if (c.h.certain > 0) {
+    if (certain > 0) {
         out->flags |= OCM_F_TIE;
         return OCM_OK;
     }
@@ -833,6 +846,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     if (!valid_lanes(c.G)) return fail(OCM_E_INVALID_ARG, "schedule must be a power of two <= 64");
     c.sweep_grid = sweep_grid(c.n, c.G);
     c.tile_sweep = o.schedule <= 0;
+    c.count_tight = o.tie_check != 0;
     c.connect_mode = o.connect_mode;
     if (c.connect_mode < 0 || c.connect_mode > 2) return fail(OCM_E_INVALID_ARG, "bad connect_mode");
 
