@@ -29,7 +29,7 @@ def log(*a):
 
 
 KERNEL_NAMES = {
-    "sweep": "k_sweep_tile (policy improvement)",
+    "sweep": "k_sweep_tile / k_tiescan_tile<SWEEP> (policy improvement)",
     "tiescan": "k_tiescan_tile (tight-edge count)",
     "cycles": "k_pj_init/round/final (policy-graph cycles)",
     "select": "k_cyc_zero/sum + k_select (minimum-mean cycle)",
@@ -45,14 +45,18 @@ KERNEL_NAMES = {
 
 
 CSRC = os.path.join(ROOT, "paper_1111_0627_amd", "csrc")
-# profile class -> (kernel, instantiation suffix) whose counters give its
-# traffic: the kernels the per-phase profile launches (the device-driven
-# round loops use k_round_*, k_val_round_dev and k_pj_round_dev instead).
+# profile class -> the (kernel, instantiation suffix) pairs whose counters
+# give its traffic: the kernels the per-phase profile launches (the
+# device-driven round loops use k_round_*, k_val_round_dev and
+# k_pj_round_dev instead).  The first sweep is k_sweep_tile<.., true>; the
+# later ones also count tight edges (k_tiescan_tile<.., true>).
 KERNEL_SYMBOL = {
-    "sweep": ("k_sweep_tile", ""), "tiescan": ("k_tiescan_tile", ""),
-    "conn_mark": ("k_conn_mark", ""), "conn_claim": ("k_conn_claim", ""),
-    "conn_pull": ("k_conn_pull", ""), "values": ("k_val_round", ""),
-    "fast": ("k_val_round", ""), "cycles": ("k_pj_round_tagged", ""), "reverse": ("k_rev_place", ""),
+    "sweep": [("k_sweep_tile", ""), ("k_tiescan_tile", ", true>")],
+    "tiescan": [("k_tiescan_tile", ", false>")],
+    "conn_mark": [("k_conn_mark", "")], "conn_claim": [("k_conn_claim", "")],
+    "conn_pull": [("k_conn_pull", "")], "values": [("k_val_round", "")],
+    "fast": [("k_val_round", "")], "cycles": [("k_pj_round_tagged", "")],
+    "reverse": [("k_rev_place", "")],
 }
 
 
@@ -65,10 +69,9 @@ def kernel_key(name):
 
 def class_kernels(table, cls):
     """Entries of a per-kernel table that belong to the class's kernel."""
-    if cls not in KERNEL_SYMBOL:
-        return []
-    base, suffix = KERNEL_SYMBOL[cls]
-    return [v for k, v in table.items() if k.split("<")[0] == base and k.endswith(suffix)]
+    return [v for k, v in table.items()
+            if any(k.split("<")[0] == base and k.endswith(suffix)
+                   for base, suffix in KERNEL_SYMBOL.get(cls, []))]
 
 
 def source_digest():
