@@ -5,6 +5,8 @@
 
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -198,9 +200,28 @@ struct Ctx {
     int connect_rounds = 0;
     int connect_mode = 0;   // 0 auto, 1 pull only, 2 push only
     bool rev_built = false;
+    // reverse CSR built early on a side stream: rev_done is recorded there
+    // when it is complete; the solve's stream waits for it before use
+    bool rev_pending = false;
+    hipEvent_t rev_in = nullptr, rev_done = nullptr;
     int64_t push_frontier = 0;
     int general_iters = 0;
     int value_rounds = 0;
+
+    Ctx() = default;
+    Ctx(const Ctx&) = delete;
+    Ctx& operator=(const Ctx&) = delete;
+    ~Ctx()
+    {
+        // every exit path: the side stream's writes into the workspace end
+        // before the solve returns
+        if (rev_pending) {
+            (void)hipStreamWaitEvent(st, rev_done, 0);
+            (void)hipEventSynchronize(rev_done);
+        }
+        if (rev_in) (void)hipEventDestroy(rev_in);
+        if (rev_done) (void)hipEventDestroy(rev_done);
+    }
 };
 
 // Push rounds pay off once many vertices are unattached and the frontier is
@@ -444,14 +465,69 @@ ocm_status phase_select(Ctx& c, const int* pi, const int* rep, const unsigned ch
 // back every kRoundsPerRead rounds.  Rounds queued after the last one do
 // nothing.
 
-// Reverse CSR for push rounds, once per solve; both mark arrays start clear.
-void build_reverse(Ctx& c)
+// Reverse CSR for push rounds, once per solve, on stream st; both mark
+// arrays start clear.
+void launch_reverse(Ctx& c, hipStream_t st)
 {
     Ws& w = c.ws;
     ocm::launch_rev_build(c.n, c.m, c.row_ptr, c.col, w.rdeg, w.stot, w.rin_ptr, w.rin,
-                          w.marks[0], w.rscratch, c.st);
-    ocm::launch_fill_u32((unsigned*)w.marks[1], ((int64_t)c.n + 3) / 4, 0u, c.st);
+                          w.marks[0], w.rscratch, st);
+    ocm::launch_fill_u32((unsigned*)w.marks[1], ((int64_t)c.n + 3) / 4, 0u, st);
+}
+
+// The reverse CSR, ready on the solve's stream: the early build's (waited
+// for) or one built now.
+void build_reverse(Ctx& c)
+{
+    if (c.rev_pending) {
+        (void)hipStreamWaitEvent(c.st, c.rev_done, 0);
+        c.rev_pending = false;
+    } else {
+        launch_reverse(c, c.st);
+    }
     c.rev_built = true;
+}
+
+// One side stream per device (default priority, non-blocking), kept for
+// the life of the process.
+hipStream_t side_stream()
+{
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[dev] = s;
+    return s;
+}
+
+// A cold solve's first iteration always rebuilds; on a large graph that
+// rebuild pushes and needs the reverse CSR, which depends on the graph only.
+// Build it on a side stream right after validation, so that it overlaps the
+// first sweep and the cycle phase.  Not with the per-phase profile (its
+// timings stay per kernel), not for pull-only rebuilds.
+void start_reverse_early(Ctx& c)
+{
+    if (c.prof.out || c.rev_built || c.connect_mode == 1 || c.n < 2 * (int64_t)kPushMinUnattached)
+        return;
+    hipStream_t side = side_stream();
+    if (!side) return;
+    if (hipEventCreateWithFlags(&c.rev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c.rev_done, hipEventDisableTiming) != hipSuccess)
+        return;
+    if (hipEventRecord(c.rev_in, c.st) != hipSuccess || hipStreamWaitEvent(side, c.rev_in, 0) != hipSuccess)
+        return;
+    launch_reverse(c, side);
+    if (hipEventRecord(c.rev_done, side) != hipSuccess) {
+        // the build is queued; make the solve's stream wait for it anyway
+        (void)hipStreamSynchronize(side);
+        return;
+    }
+    c.rev_pending = true;
 }
 
 ocm_status connect_rounds_on_device(Ctx& c, int* pi, int* layer, unsigned left, unsigned front,
@@ -852,6 +928,8 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
 
     ocm_status rc = validate(c, o.validate != 0);
     if (rc != OCM_OK) { c.prof.finish(); return rc; }
+    start_reverse_early(c);
+    HIP_TRY(hipGetLastError());
 
     Ws& w = c.ws;
     const bool warm = o.init_policy != nullptr;
