@@ -333,6 +333,8 @@ def test_schedules_and_fast_path_give_identical_bytes():
 
 @pytest.mark.parametrize("kind", ["product", "random"])
 def test_connect_directions_give_identical_bytes(kind):
+    """Pull, push and automatic rebuild rounds, each with the rounds decided
+    on the device and (per-phase profile) by the host, give the same bytes."""
     if kind == "product":
         g = synth.product_graph(5, 16, 0.3, 1, 1000, 4)
     else:
@@ -341,13 +343,17 @@ def test_connect_directions_give_identical_bytes(kind):
     rp, cl, w = to_dev(g.row_ptr, g.col, g.w)
     ref = None
     for mode in ("pull", "push", "auto"):
-        res = ocm.min_cycle_mean(rp, cl, w, connect=mode, want_policy=True, want_potential=True)
-        assert_same(res, sol)
-        cur = (res.policy.cpu().numpy(), res.potential.cpu().numpy(), res.connect_rounds)
-        if ref is None:
-            ref = cur
-        assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1])
-        assert cur[2] == ref[2]
+        for profile in (False, True):
+            res = ocm.min_cycle_mean(rp, cl, w, connect=mode, want_policy=True,
+                                     want_potential=True, profile=profile)
+            assert_same(res, sol)
+            cur = (res.policy.cpu().numpy(), res.potential.cpu().numpy(), res.connect_rounds)
+            if ref is None:
+                ref = cur
+            assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1])
+            assert cur[2] == ref[2]
+            if profile:
+                assert res.profile["conn_claim"][1] > 0 or mode == "pull"
 
 
 def test_product_graph_small_against_closed_form():
