@@ -69,6 +69,7 @@ struct alignas(128) Ctl {
     unsigned jmode;                //   1 while rounds are left, 0 once they are over
     unsigned jlast;                //   the last round's count (unfinished vertices, image size)
     unsigned jstall;               //   values: a round finished no vertex
+    unsigned jgate;                //   values: 0 = the queued value phase is skipped
     unsigned xcnt;                 // tie scan: tight non-policy edges listed
     unsigned scnt;                 // tie check: special vertices
     CtlLane lane[kLanes];
@@ -186,7 +187,12 @@ void launch_pj_round_tagged(int n, int r, const unsigned long long* Pin, unsigne
 // is the next one and the rounds are not over; the final runs once they are,
 // on the buffer of the last round run (round r reads buffer (r-1)&1 and
 // writes r&1).  Progress: jk, jmode, jstall.
-void launch_jump_setup(Ctl* ctl, bool values, hipStream_t st);
+void launch_jump_setup(Ctl* ctl, bool values, bool gated, hipStream_t st);
+// Opens ctl->jgate iff the sweep just run changed a policy edge (or force)
+// and no vertex of C changed: the fast-path value phase queued behind the
+// sweep (init and jump setup gated) then runs only if the host would have
+// started it.
+void launch_fast_gate(Ctl* ctl, bool force, hipStream_t st);
 void launch_pj_round_dev(int n, int r, const unsigned long long* Pin, unsigned long long* Pout,
                          const unsigned char* tprev, unsigned char* tcur, Ctl* ctl, hipStream_t st);
 void launch_pj_final_dev(int n, const unsigned long long* P0, const unsigned long long* P1, int K,
@@ -262,8 +268,10 @@ size_t rev_scratch_bytes(int64_t n, int64_t m);
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
                       unsigned* tot, int* rin_ptr, int* rin, unsigned char* marks, void* scratch,
                       hipStream_t st);
+// gate (nullable): the init does nothing while *gate is 0.
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
-                     int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl, hipStream_t st);
+                     int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl,
+                     const unsigned* gate, hipStream_t st);
 void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st);
 void launch_val_final(int n, const Jmp* Q, long long* V, int* hop, Ctl* ctl, hipStream_t st);
 void launch_cycle_list(int n, int s, long long L, const unsigned char* onC, const int* pi,

@@ -415,18 +415,36 @@ __device__ __forceinline__ bool jump_round_is(const Ctl* c, int r)
 
 // Start of device-driven jump rounds.  values: round 1 runs if init left
 // unfinished vertices (their count, in the lanes' active, becomes jlast);
-// cycles: round 1 runs.
-__global__ void k_jump_setup(Ctl* c, int values)
+// cycles: round 1 runs.  gated (values): nothing runs unless jgate is open
+// (set by k_fast_gate); otherwise the gate is opened here.
+__global__ void k_jump_setup(Ctl* c, int values, int gated)
 {
     if (threadIdx.x < kLanes) c->lane[threadIdx.x].rpack = 0;
     if (threadIdx.x == 0) {
         unsigned act = 0;
         for (int l = 0; l < kLanes; ++l) act += c->lane[l].active;
+        if (!gated) c->jgate = 1;
+        const bool open = c->jgate != 0;
         c->rpack = 0;
         c->jk = 0;
         c->jstall = 0;
         c->jlast = values ? act : 0u;
-        c->jmode = values ? (act > 0 ? 1u : 0u) : 1u;
+        c->jmode = values ? (act > 0 && open ? 1u : 0u) : 1u;
+    }
+}
+
+// After a sweep whose value phase is queued behind it: open jgate only if
+// the sweep changed a policy edge (or force) and no vertex of C changed.
+__global__ void k_fast_gate(Ctl* c, int force)
+{
+    if (threadIdx.x == 0) {
+        unsigned long long changed = 0;
+        unsigned broken = 0;
+        for (int l = 0; l < kLanes; ++l) {
+            changed += c->lane[l].changed;
+            broken |= c->lane[l].cbroken;
+        }
+        c->jgate = !broken && (changed > 0 || force) ? 1u : 0u;
     }
 }
 
@@ -1570,7 +1588,9 @@ RevPlan rev_plan(int64_t n, int64_t m)
     }
     p.bits = bits;
     p.buckets = (n + (1 << bits) - 1) >> bits;
-    int64_t chunk = 65536;
+    // edges per histogram / scatter block: enough blocks to fill the chip
+    // (up to 2048), at least 4096 edges each
+    int64_t chunk = 4096;
     while ((m + chunk - 1) / chunk > 2048) chunk <<= 1;
     p.chunk = chunk;
     p.nblk = (m + chunk - 1) / chunk;
@@ -1676,8 +1696,9 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
                                                   const WT* __restrict__ w, int neg, int s,
                                                   long long W, long long L,
                                                   int* __restrict__ succ, Jmp* __restrict__ Q,
-                                                  Ctl* ctl)
+                                                  Ctl* ctl, const unsigned* gate)
 {
+    if (gate && *gate == 0u) return;   // the value phase is skipped (uniform)
     unsigned long long act = 0;
     constexpr int U = 4;   // independent vertices in flight per thread
     const int64_t stride = (int64_t)gridDim.x * kWG;
@@ -1829,7 +1850,7 @@ __global__ __launch_bounds__(kWG) void k_val_final_dev(int n, const Jmp* __restr
                                                        long long* __restrict__ V,
                                                        int* __restrict__ hop, Ctl* ctl)
 {
-    if (ctl->jmode != 0 || ctl->jstall) return;
+    if (ctl->jmode != 0 || ctl->jstall || !ctl->jgate) return;
     val_final_body(n, (ctl->jk & 1) ? Q1 : Q0, V, hop, ctl);
 }
 
@@ -2172,9 +2193,14 @@ void launch_pj_init(int n, const int* col, const int* pi, int* succ, unsigned lo
     k_pj_init<<<blocks_for(n), kWG, 0, st>>>(n, col, pi, succ, P, onc, tag0, cnt);
 }
 
-void launch_jump_setup(Ctl* ctl, bool values, hipStream_t st)
+void launch_jump_setup(Ctl* ctl, bool values, bool gated, hipStream_t st)
 {
-    k_jump_setup<<<1, 64, 0, st>>>(ctl, values ? 1 : 0);
+    k_jump_setup<<<1, 64, 0, st>>>(ctl, values ? 1 : 0, gated ? 1 : 0);
+}
+
+void launch_fast_gate(Ctl* ctl, bool force, hipStream_t st)
+{
+    k_fast_gate<<<1, 64, 0, st>>>(ctl, force ? 1 : 0);
 }
 
 void launch_pj_round_dev(int n, int r, const unsigned long long* Pin, unsigned long long* Pout,
@@ -2409,14 +2435,15 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
 }
 
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
-                     int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl, hipStream_t st)
+                     int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl,
+                     const unsigned* gate, hipStream_t st)
 {
     if (wtype == kWI64)
         k_val_init<long long><<<stride_grid(n), kWG, 0, st>>>(n, col, pi, (const long long*)w, neg,
-                                                             s, W, L, succ, Q, ctl);
+                                                             s, W, L, succ, Q, ctl, gate);
     else
         k_val_init<int><<<stride_grid(n), kWG, 0, st>>>(n, col, pi, (const int*)w, neg, s, W, L,
-                                                       succ, Q, ctl);
+                                                       succ, Q, ctl, gate);
 }
 
 void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st)

@@ -195,6 +195,7 @@ struct Ctx {
     bool tile_sweep = true;   // schedule 0: sweeps over vertex tiles, else G lanes per vertex
     bool count_tight = false;   // sweeps also count tight edges (tie check requested)
     bool swept_tie = false;     // the last sweep's counts are the tie scan's first pass
+    bool sweep_fused = false;   // the last sweep launched counts tight edges
     unsigned long long swept_tight = 0, swept_certain = 0;
     int jump_rounds = 0;
     int connect_rounds = 0;
@@ -310,9 +311,29 @@ ocm_status validate(Ctx& c, int check_csr)
 }
 
 // Policy improvement sweep; afterwards c.h.changed / cbroken are current.
+// The sweep's bookkeeping once c.h holds the control block after it.
+void sweep_done(Ctx& c, bool first, bool tie, bool fused)
+{
+    c.swept_tie = fused;
+    c.swept_tight = c.h.tight;
+    c.swept_certain = c.h.certain;
+    // col + w per edge, row_ptr per vertex; after the first sweep also the
+    // gathered V per edge and the own V per vertex; the tie scan (and a
+    // sweep that counts tight edges) reads pi; policy writes of changed
+    // vertices
+    const double n = c.n, m = c.m;
+    double b = m * (4.0 + c.sw) + 4.0 * (n + 1);
+    if (!first) b += 8.0 * m + 8.0 * n;
+    if (tie || fused) b += 4.0 * n;
+    if (!tie) b += 4.0 * (double)c.h.changed;
+    c.prof.bytes(tie ? OCM_K_TIESCAN : OCM_K_SWEEP, b);
+}
+
+// read = false: the caller reads the control block later (after more work
+// queued behind the sweep) and then calls sweep_done.
 ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long long W, long long L,
                        int* pi, const unsigned char* onC, bool collect = false,
-                       bool with_hop = false)
+                       bool with_hop = false, bool read = true)
 {
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrChanged, c.st);
     ocm::SweepArgs a;
@@ -343,20 +364,10 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
                       c.st);
     c.prof.end();
     HIP_TRY(hipGetLastError());
+    c.sweep_fused = fused;
+    if (!read) return OCM_OK;
     OCM_TRY(read_ctl(c));
-    c.swept_tie = fused;
-    c.swept_tight = c.h.tight;
-    c.swept_certain = c.h.certain;
-    // col + w per edge, row_ptr per vertex; after the first sweep also the
-    // gathered V per edge and the own V per vertex; the tie scan (and a
-    // sweep that counts tight edges) reads pi; policy writes of changed
-    // vertices
-    const double n = c.n, m = c.m;
-    double b = m * (4.0 + c.sw) + 4.0 * (n + 1);
-    if (!first) b += 8.0 * m + 8.0 * n;
-    if (tie || fused) b += 4.0 * n;
-    if (!tie) b += 4.0 * (double)c.h.changed;
-    c.prof.bytes(cls, b);
+    sweep_done(c, first, tie, fused);
     return OCM_OK;
 }
 
@@ -373,7 +384,7 @@ ocm_status cycle_rounds_on_device(Ctx& c, int K, unsigned long long* P0, unsigne
                                   unsigned char* const tag[2], int* rep, unsigned char* onc)
 {
     unsigned long long* P[2] = {P0, P1};
-    ocm::launch_jump_setup(c.ws.ctl, false, c.st);
+    ocm::launch_jump_setup(c.ws.ctl, false, false, c.st);
     int r = 0;
     for (;;) {
         for (int j = 0; j < kRoundsPerRead && r < K; ++j) {
@@ -678,9 +689,9 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
 // and the final per host read, until every vertex finished or a round
 // finished none (a stall: the policy graph does not reach s).
 ocm_status value_rounds_on_device(Ctx& c, int s, long long* V, int* hop, bool probe, bool* stalled,
-                                  int* rounds)
+                                  int* rounds, bool gated)
 {
-    ocm::launch_jump_setup(c.ws.ctl, true, c.st);
+    ocm::launch_jump_setup(c.ws.ctl, true, gated, c.st);
     int r = 0;
     for (;;) {
         for (int j = 0; j < kRoundsPerRead; ++j) {
@@ -709,19 +720,21 @@ ocm_status value_rounds_on_device(Ctx& c, int s, long long* V, int* hop, bool pr
     return OCM_OK;
 }
 
+// gated (rounds decided on the device only): the phase runs only if
+// ctl->jgate is open (k_fast_gate); a closed gate leaves V as it was.
 ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, long long* V,
-                        int* hop, bool probe, bool* stalled, int* rounds)
+                        int* hop, bool probe, bool* stalled, int* rounds, bool gated = false)
 {
     if (stalled) *stalled = false;
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrCount, c.st);
     const int ph = probe ? OCM_K_FAST : OCM_K_VALUES;
     c.prof.begin(ph);
     ocm::launch_val_init(c.n, c.col, pi, c.w, c.wtype, c.neg, s, W, L, c.ws.succ, c.ws.Q[0],
-                         c.ws.ctl, c.st);
+                         c.ws.ctl, gated ? &c.ws.ctl->jgate : nullptr, c.st);
     c.prof.end();
     c.prof.bytes(ph, (28.0 + c.sw) * c.n);   // pi, col[pi], w[pi], succ, 16-byte entry
     HIP_TRY(hipGetLastError());
-    if (!c.prof.out) return value_rounds_on_device(c, s, V, hop, probe, stalled, rounds);
+    if (!c.prof.out) return value_rounds_on_device(c, s, V, hop, probe, stalled, rounds, gated);
     OCM_TRY(read_ctl(c));
     unsigned act = c.h.active;
     int a = 0, k = 0;
@@ -947,9 +960,24 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     int s = -1;
     long long W = 0, L = 1;
     for (;;) {
+        // with the rounds decided on the device, the fast path's value phase
+        // is queued behind the sweep, gated on the sweep's outcome, and both
+        // are read back at once
+        const bool ahead = need_sweep && o.fast_path && have_c && !c.prof.out;
+        bool stalled = false;
         if (need_sweep) {
-            rc = phase_sweep(c, iter == 0 && !warm, false, w.V, W, L, w.pi, have_c ? w.onC : nullptr);
+            const bool first = iter == 0 && !warm;
+            rc = phase_sweep(c, first, false, w.V, W, L, w.pi, have_c ? w.onC : nullptr, false,
+                             false, !ahead);
             if (rc != OCM_OK) break;
+            if (ahead) {
+                // the sweep count test below only spares a warm start's first
+                // sweep, which never runs here (no C yet)
+                ocm::launch_fast_gate(w.ctl, false, c.st);
+                rc = phase_values(c, w.pi, s, W, L, w.V, w.hop, true, &stalled, nullptr, true);
+                if (rc != OCM_OK) break;
+                sweep_done(c, first, false, c.sweep_fused);
+            }
             ++iter;
             // no strict improvement left (a cold start's first sweep always changes)
             if (iter >= (warm ? 1 : 2) && c.h.changed == 0) break;
@@ -963,9 +991,10 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
             // C is still a cycle of the new policy.  If every vertex still
             // reaches s, C is the policy graph's only cycle: the cycle, select
             // and connect phases would change nothing, so only values remain.
-            bool stalled = false;
-            rc = phase_values(c, w.pi, s, W, L, w.V, w.hop, true, &stalled, nullptr);
-            if (rc != OCM_OK) break;
+            if (!ahead) {
+                rc = phase_values(c, w.pi, s, W, L, w.V, w.hop, true, &stalled, nullptr);
+                if (rc != OCM_OK) break;
+            }
             if (!stalled) {
                 ++fast;
                 continue;
