@@ -57,6 +57,28 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x
     return t;
 }
 
+// N sums over the workgroup in one pass (two barriers); the results are
+// valid in thread 0.
+template <int N>
+__device__ __forceinline__ void block_sums_u64(unsigned long long (&x)[N])
+{
+    __shared__ unsigned long long part[kWG / 64][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = wave_sum_u64(x[i]);
+    __syncthreads();   // part may still be read by an earlier call
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) part[threadIdx.x >> 6][i] = x[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            unsigned long long t = 0;
+            for (int w = 0; w < kWG / 64; ++w) t += part[w][i];
+            x[i] = t;
+        }
+}
+
 __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long x)
 {
     __shared__ unsigned long long part[kWG / 64];

@@ -251,12 +251,12 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
         changed = 1;
         if (!FIRST && a.onC && a.onC[v0 + t]) cbroken = 1;
     }
-    changed = block_sum_u64(changed);
-    const unsigned long long brk = block_sum_u64(cbroken);
+    unsigned long long sums[2] = {changed, cbroken};
+    block_sums_u64(sums);
     if (t == 0) {
         CtlLane& ln = my_lane(a.ctl);
-        if (changed) atomicAdd(&ln.changed, changed);
-        if (brk) atomicOr(&ln.cbroken, 1u);
+        if (sums[0]) atomicAdd(&ln.changed, sums[0]);
+        if (sums[1]) atomicOr(&ln.cbroken, 1u);
     }
 }
 
@@ -354,20 +354,15 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
         changed = 1;
         if (onc) cbroken = 1;
     }
-    cnt = block_sum_u64(cnt);
-    certain = block_sum_u64(certain);
-    nondec = block_sum_u64(nondec);
-    if (SWEEP) {
-        changed = block_sum_u64(changed);
-        cbroken = (unsigned)block_sum_u64(cbroken);
-    }
+    unsigned long long sums[5] = {cnt, certain, nondec, changed, cbroken};
+    block_sums_u64(sums);
     if (t == 0) {
         CtlLane& ln = my_lane(a.ctl);
-        if (cnt) atomicAdd(&ln.tight, cnt);
-        if (certain) atomicAdd(&ln.certain, certain);
-        if (nondec) atomicAdd(&ln.nondec, nondec);
-        if (SWEEP && changed) atomicAdd(&ln.changed, changed);
-        if (SWEEP && cbroken) atomicOr(&ln.cbroken, 1u);
+        if (sums[0]) atomicAdd(&ln.tight, sums[0]);
+        if (sums[1]) atomicAdd(&ln.certain, sums[1]);
+        if (sums[2]) atomicAdd(&ln.nondec, sums[2]);
+        if (SWEEP && sums[3]) atomicAdd(&ln.changed, sums[3]);
+        if (SWEEP && sums[4]) atomicOr(&ln.cbroken, 1u);
     }
 }
 
