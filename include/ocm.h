@@ -37,7 +37,11 @@
  *
  * Streams: `stream` is a hipStream_t passed as void* (NULL = null stream).
  * Every call enqueues its kernels on that stream and synchronises it before
- * returning (loop control reads small counters back to the host).
+ * returning (loop control reads small counters back to the host).  A cold
+ * ocm_min / ocm_max on a graph of at least 131072 vertices also builds the
+ * reverse CSR on a library-owned stream of the same device (created once,
+ * default priority), ordered after the call's earlier work by an event; the
+ * call waits for it before using it and before returning.
  *
  * Errors: functions return ocm_status; nothing aborts or throws across the
  * ABI.  ocm_last_error() returns a thread-local message for the last failure.
