@@ -967,9 +967,13 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
         bool stalled = false;
         if (need_sweep) {
             const bool first = iter == 0 && !warm;
+            // a cold start's first sweep decides nothing (the stop test needs a
+            // second sweep; the iteration cap is at least 2 then): no read
+            const bool blind = first && !c.prof.out && (o.max_iters <= 0 || o.max_iters > 1);
             rc = phase_sweep(c, first, false, w.V, W, L, w.pi, have_c ? w.onC : nullptr, false,
-                             false, !ahead);
+                             false, !ahead && !blind);
             if (rc != OCM_OK) break;
+            if (blind) c.h.changed = 1;   // FIRST always picks an edge per vertex
             if (ahead) {
                 // the sweep count test below only spares a warm start's first
                 // sweep, which never runs here (no C yet)
@@ -1022,7 +1026,8 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     out->general_iters = c.general_iters;
     out->value_rounds = c.value_rounds;
     out->push_frontier = c.push_frontier;
-    if (read_ctl(c) == OCM_OK) out->push_in_edges = (int64_t)c.h.pedges;
+    // the last read came after the last rebuild: its in-edge count is final
+    out->push_in_edges = (int64_t)c.h.pedges;
     if (rc != OCM_OK) {
         c.prof.finish();
         return rc;
