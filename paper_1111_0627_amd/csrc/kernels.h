@@ -154,6 +154,7 @@ struct SweepArgs {
     const long long* V;
     long long W, L;
     int* pi;
+    int* succ;                     // optional: col[pi] kept up to date where pi changes
     const unsigned char* onC;      // optional: flags vertices of the current C
     Ctl* ctl;
     const int* hop;                // tie scan: policy hops to the source, or null
@@ -173,8 +174,10 @@ void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool firs
                   bool count_tight, unsigned grid, hipStream_t st);
 // tag0 (optional): byte array marked with 1 at every successor; cnt: the
 // four stop-test counters, cleared
-void launch_pj_init(int n, const int* col, const int* pi, int* succ, unsigned long long* P,
-                    unsigned char* onc, unsigned char* tag0, unsigned* cnt, hipStream_t st);
+// have_succ: succ already holds col[pi]; otherwise it is written.
+void launch_pj_init(int n, const int* col, const int* pi, int* succ, bool have_succ,
+                    unsigned long long* P, unsigned char* onc, unsigned char* tag0, unsigned* cnt,
+                    hipStream_t st);
 void launch_pj_round(int n, const unsigned long long* Pin, unsigned long long* Pout,
                      hipStream_t st);
 // round r >= 1 with the stop-test counters: cnt[2*(r&1)] = size of
@@ -268,9 +271,10 @@ size_t rev_scratch_bytes(int64_t n, int64_t m);
 void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned* deg,
                       unsigned* tot, int* rin_ptr, int* rin, unsigned char* marks, void* scratch,
                       hipStream_t st);
-// gate (nullable): the init does nothing while *gate is 0.
+// gate (nullable): the init does nothing while *gate is 0.  have_succ: succ
+// already holds col[pi]; otherwise it is written.
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
-                     int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl,
+                     int s, long long W, long long L, int* succ, bool have_succ, Jmp* Q, Ctl* ctl,
                      const unsigned* gate, hipStream_t st);
 void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st);
 void launch_val_final(int n, const Jmp* Q, long long* V, int* hop, Ctl* ctl, hipStream_t st);

@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
     const int mb = t < nv ? beg[t] : 0, me = t < nv ? beg[t + 1] : 0;
     unsigned long long cnt = 0, certain = 0, nondec = 0;
     long long best = INT64_MAX;
-    int pos = INT32_MAX;
+    int pos = INT32_MAX, bhead = 0;
     constexpr int U = kTieTileEdges / kWG;
     for (int eb = e0; eb < e1; eb += kTieTileEdges) {
         const int n_e = e1 - eb < kTieTileEdges ? e1 - eb : kTieTileEdges;
@@ -326,12 +326,13 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
         const int lo = mb > eb ? mb : eb, hi = me < eb + n_e ? me : eb + n_e;
         for (int e = lo; e < hi; ++e) {
             const long long k = key[e - eb];
+            const int h = head[e - eb];
             if (SWEEP && k < best) {
                 best = k;
                 pos = e;
+                bhead = h;
             }
             const bool tight = k == own && e != cur;
-            const int h = head[e - eb];
             if (tight) {
                 cnt++;
                 if (h == v0 + t || onc) certain++;
@@ -351,6 +352,7 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
     unsigned cbroken = 0;
     if (SWEEP && t < nv && pos != INT32_MAX && best < own) {
         a.pi[v0 + t] = pos;
+        if (a.succ) a.succ[v0 + t] = bhead;
         changed = 1;
         if (onc) cbroken = 1;
     }
@@ -466,8 +468,11 @@ __device__ __forceinline__ unsigned long long pj_pack(int j, int mn)
     return ((unsigned long long)(unsigned)j << 32) | (unsigned)mn;
 }
 
+// have_succ: succ already holds col[pi] (kept up to date where pi changed);
+// otherwise it is written here.
 __global__ __launch_bounds__(kWG) void k_pj_init(int n, const int* __restrict__ col,
                                                  const int* __restrict__ pi, int* __restrict__ succ,
+                                                 int have_succ,
                                                  unsigned long long* __restrict__ P,
                                                  unsigned char* __restrict__ onc,
                                                  unsigned char* __restrict__ tag0, unsigned* cnt)
@@ -477,8 +482,13 @@ __global__ __launch_bounds__(kWG) void k_pj_init(int n, const int* __restrict__ 
         for (int l = 0; l < kLanes; ++l)
             for (int j = 0; j < 4; ++j) cnt[l * kLaneWords + j] = 0;
     if (v >= n) return;
-    const int s = col[pi[v]];
-    succ[v] = s;
+    int s;
+    if (have_succ) {
+        s = succ[v];
+    } else {
+        s = col[pi[v]];
+        succ[v] = s;
+    }
     P[v] = pj_pack(s, v);
     onc[v] = 0;
     if (tag0) tag0[s] = 1;
@@ -1690,8 +1700,9 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
                                                   const int* __restrict__ pi,
                                                   const WT* __restrict__ w, int neg, int s,
                                                   long long W, long long L,
-                                                  int* __restrict__ succ, Jmp* __restrict__ Q,
-                                                  Ctl* ctl, const unsigned* gate)
+                                                  int* __restrict__ succ, int have_succ,
+                                                  Jmp* __restrict__ Q, Ctl* ctl,
+                                                  const unsigned* gate)
 {
     if (gate && *gate == 0u) return;   // the value phase is skipped (uniform)
     unsigned long long act = 0;
@@ -1711,7 +1722,7 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
             t[u] = 0;
             wv[u] = 0;
             if (v < n) {
-                t[u] = col[e[u]];
+                t[u] = have_succ ? succ[v] : col[e[u]];
                 wv[u] = wval(w, e[u], neg);
             }
         }
@@ -1719,7 +1730,7 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
         for (int u = 0; u < U; ++u) {
             const int64_t v = vb + u * stride;
             if (v >= n) continue;
-            succ[v] = t[u];
+            if (!have_succ) succ[v] = t[u];
             Jmp q;
             if (v == s) {
                 q.D = 0;
@@ -2182,10 +2193,12 @@ void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool firs
     else launch_sweep_t<int>(a, w, G, first, tie, grid, st);
 }
 
-void launch_pj_init(int n, const int* col, const int* pi, int* succ, unsigned long long* P,
-                    unsigned char* onc, unsigned char* tag0, unsigned* cnt, hipStream_t st)
+void launch_pj_init(int n, const int* col, const int* pi, int* succ, bool have_succ,
+                    unsigned long long* P, unsigned char* onc, unsigned char* tag0, unsigned* cnt,
+                    hipStream_t st)
 {
-    k_pj_init<<<blocks_for(n), kWG, 0, st>>>(n, col, pi, succ, P, onc, tag0, cnt);
+    k_pj_init<<<blocks_for(n), kWG, 0, st>>>(n, col, pi, succ, have_succ ? 1 : 0, P, onc, tag0,
+                                             cnt);
 }
 
 void launch_jump_setup(Ctl* ctl, bool values, bool gated, hipStream_t st)
@@ -2430,15 +2443,16 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
 }
 
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
-                     int s, long long W, long long L, int* succ, Jmp* Q, Ctl* ctl,
+                     int s, long long W, long long L, int* succ, bool have_succ, Jmp* Q, Ctl* ctl,
                      const unsigned* gate, hipStream_t st)
 {
     if (wtype == kWI64)
         k_val_init<long long><<<stride_grid(n), kWG, 0, st>>>(n, col, pi, (const long long*)w, neg,
-                                                             s, W, L, succ, Q, ctl, gate);
+                                                             s, W, L, succ, have_succ ? 1 : 0, Q, ctl,
+                                                             gate);
     else
         k_val_init<int><<<stride_grid(n), kWG, 0, st>>>(n, col, pi, (const int*)w, neg, s, W, L,
-                                                       succ, Q, ctl, gate);
+                                                       succ, have_succ ? 1 : 0, Q, ctl, gate);
 }
 
 void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st)

@@ -195,6 +195,11 @@ struct Ctx {
     bool tile_sweep = true;   // schedule 0: sweeps over vertex tiles, else G lanes per vertex
     bool count_tight = false;   // sweeps also count tight edges (tie check requested)
     bool swept_tie = false;     // the last sweep's counts are the tie scan's first pass
+    // ws.succ holds col[pi] for every vertex of the workspace's policy: the
+    // cycle and value inits then read it instead of gathering col[pi]; the
+    // sweeps that count tight edges keep it so (the rebuild does not: its
+    // scattered stores cost more than the gather they save)
+    bool succ_ok = false;
     bool sweep_fused = false;   // the last sweep launched counts tight edges
     unsigned long long swept_tight = 0, swept_certain = 0;
     int jump_rounds = 0;
@@ -345,6 +350,7 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     a.W = W;
     a.L = L;
     a.pi = pi;
+    a.succ = nullptr;
     a.onC = onC;
     a.ctl = c.ws.ctl;
     a.hop = tie && with_hop ? c.ws.hop : nullptr;
@@ -359,6 +365,10 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     }
     const int cls = tie ? OCM_K_TIESCAN : OCM_K_SWEEP;
     const bool fused = !tie && !first && c.tile_sweep && c.count_tight;
+    // a sweep that changes pi without updating succ leaves it stale
+    const bool keep = fused && c.succ_ok && pi == c.ws.pi;
+    a.succ = keep ? c.ws.succ : nullptr;
+    if (!tie && !keep) c.succ_ok = false;
     c.prof.begin(cls);
     ocm::launch_sweep(a, c.w, c.wtype, c.tile_sweep ? 0 : c.G, first, tie, fused, c.sweep_grid,
                       c.st);
@@ -414,9 +424,11 @@ ocm_status phase_cycles(Ctx& c, const int* pi, int* rep, unsigned char* onc)
     const bool stop_test = K > 2;
     c.prof.begin(OCM_K_CYCLES);
     if (stop_test) ocm::launch_fill_u32((unsigned*)c.ws.layer, ((int64_t)c.n * 2 + 3) / 4, 0u, c.st);
-    ocm::launch_pj_init(c.n, c.col, pi, c.ws.succ, P0, onc, stop_test ? tag[0] : nullptr,
+    const bool have_succ = c.succ_ok && pi == c.ws.pi;
+    ocm::launch_pj_init(c.n, c.col, pi, c.ws.succ, have_succ, P0, onc, stop_test ? tag[0] : nullptr,
                         stop_test && c.prof.out ? c.ws.ctl->lane[0].pjc : nullptr, c.st);
     c.prof.end();
+    c.succ_ok = pi == c.ws.pi;
     // pi, col[pi], succ, packed entry, on-cycle (+ tag clear and mark)
     c.prof.bytes(OCM_K_CYCLES, 21.0 * n + (stop_test ? 3.0 * n : 0.0));
     HIP_TRY(hipGetLastError());
@@ -578,6 +590,7 @@ ocm_status phase_connect(Ctx& c, const int* rep, const unsigned char* onc, int s
                          int* layer, unsigned char* onC, int* rounds)
 {
     Ws& w = c.ws;
+    c.succ_ok = false;   // the rebuild rewires pi and leaves succ behind
     ocm::launch_ctl_clear(w.ctl, ocm::kClrCount, c.st);
     c.prof.begin(OCM_K_CONN_PULL);
     // round 1 reads abits[1] (C's component) and completes abits[0]
@@ -729,8 +742,11 @@ ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, 
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrCount, c.st);
     const int ph = probe ? OCM_K_FAST : OCM_K_VALUES;
     c.prof.begin(ph);
-    ocm::launch_val_init(c.n, c.col, pi, c.w, c.wtype, c.neg, s, W, L, c.ws.succ, c.ws.Q[0],
-                         c.ws.ctl, gated ? &c.ws.ctl->jgate : nullptr, c.st);
+    const bool have_succ = c.succ_ok && pi == c.ws.pi;
+    ocm::launch_val_init(c.n, c.col, pi, c.w, c.wtype, c.neg, s, W, L, c.ws.succ, have_succ,
+                         c.ws.Q[0], c.ws.ctl, gated ? &c.ws.ctl->jgate : nullptr, c.st);
+    // a gated init that does not run leaves succ as it was
+    if (!gated) c.succ_ok = pi == c.ws.pi;
     c.prof.end();
     c.prof.bytes(ph, (28.0 + c.sw) * c.n);   // pi, col[pi], w[pi], succ, 16-byte entry
     HIP_TRY(hipGetLastError());
