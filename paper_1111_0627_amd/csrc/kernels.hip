@@ -1644,24 +1644,36 @@ __global__ __launch_bounds__(kWG) void k_scan_a(int64_t len, const unsigned* __r
     if (threadIdx.x == kWG - 1) tot[blockIdx.x] = wbase + incl;
 }
 
+// One workgroup; kScanTotals consecutive totals per thread, so that up to
+// 1024 * kScanTotals block totals take a single pass.
+constexpr int kScanTotals = 4;
+
 __global__ __launch_bounds__(1024) void k_scan_b(unsigned nb, unsigned* __restrict__ tot)
 {
     __shared__ unsigned wt[16];
     __shared__ unsigned carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (unsigned b0 = 0; b0 < nb; b0 += 1024) {
-        const unsigned i = b0 + threadIdx.x;
-        const unsigned x = i < nb ? tot[i] : 0u;
-        const unsigned incl = wave_incl_scan(x);
+    for (unsigned b0 = 0; b0 < nb; b0 += 1024 * kScanTotals) {
+        const unsigned i0 = b0 + threadIdx.x * kScanTotals;
+        unsigned v[kScanTotals], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kScanTotals; ++j) {
+            const unsigned x = i0 + j < nb ? tot[i0 + j] : 0u;
+            v[j] = sum;
+            sum += x;
+        }
+        const unsigned incl = wave_incl_scan(sum);
         if ((threadIdx.x & 63) == 63) wt[threadIdx.x >> 6] = incl;
         __syncthreads();
         unsigned wbase = 0;
         for (int wv = 0; wv < (int)(threadIdx.x >> 6); ++wv) wbase += wt[wv];
-        const unsigned excl = carry + wbase + incl - x;
-        if (i < nb) tot[i] = excl;
+        const unsigned excl = carry + wbase + incl - sum;
+#pragma unroll
+        for (int j = 0; j < kScanTotals; ++j)
+            if (i0 + j < nb) tot[i0 + j] = excl + v[j];
         __syncthreads();
-        if (threadIdx.x == 1023) carry = excl + x;
+        if (threadIdx.x == 1023) carry = excl + sum;
         __syncthreads();
     }
 }
