@@ -1421,6 +1421,39 @@ constexpr int kRevMaxBuckets = 8192;
 constexpr int kPlaceWG = 1024;
 constexpr int kPlaceUnroll = 16;
 
+// Adds one to cnt[key] for every lane with key >= 0 and returns the lane's
+// old count.  Locality in a graph sends many of a wave's edges into one head
+// bucket, and such adds serialise in the LDS: for up to kClaimRounds keys,
+// the lanes that share the first remaining lane's key take one atomic
+// together; the rest add one each.
+constexpr int kClaimRounds = 1;
+
+__device__ __forceinline__ unsigned lds_claim(unsigned* cnt, int key)
+{
+    const unsigned lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    bool open = key >= 0;
+    unsigned pos = 0;
+#pragma unroll
+    for (int r = 0; r < kClaimRounds; ++r) {
+        const unsigned long long live = __ballot(open);
+        if (!live) break;
+        const int leader = __ffsll((long long)live) - 1;
+        const int k = __builtin_amdgcn_readlane(key, leader);
+        const bool grp = open && key == k;
+        const unsigned long long mask = __ballot(grp);
+        unsigned base = 0;
+        if ((int)lane == leader) base = atomicAdd(&cnt[k], (unsigned)__popcll(mask));
+        base = (unsigned)__builtin_amdgcn_readlane((int)base, leader);
+        if (grp) {
+            pos = base + (unsigned)__popcll(mask & below);
+            open = false;
+        }
+    }
+    if (open) pos = atomicAdd(&cnt[key], 1u);
+    return pos;
+}
+
 __global__ __launch_bounds__(kWG) void k_rev_hist(int64_t m, const int* __restrict__ col,
                                                   int64_t chunk, int nblk, int B, int bits,
                                                   unsigned* __restrict__ hist)
@@ -1436,8 +1469,7 @@ __global__ __launch_bounds__(kWG) void k_rev_hist(int64_t m, const int* __restri
 #pragma unroll
         for (int j = 0; j < U; ++j) v[j] = e + j * kWG < e1 ? col[e + j * kWG] : -1;
 #pragma unroll
-        for (int j = 0; j < U; ++j)
-            if (v[j] >= 0) atomicAdd(&h[v[j] >> bits], 1u);
+        for (int j = 0; j < U; ++j) (void)lds_claim(h, v[j] >= 0 ? v[j] >> bits : -1);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < B; i += kWG) hist[(int64_t)i * nblk + blockIdx.x] = h[i];
@@ -1493,8 +1525,8 @@ __global__ __launch_bounds__(kWG) void k_rev_scatter(int n, const int* __restric
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const int u = ub + j * kGroups;
+            const unsigned pos = lds_claim(cur, v[j] >= 0 ? v[j] >> bits : -1);
             if (v[j] >= 0) {
-                const unsigned pos = atomicAdd(&cur[v[j] >> bits], 1u);
                 hlo[pos] = (unsigned short)(v[j] & hmask);
                 tails[pos] = u;
             }
@@ -1593,10 +1625,12 @@ RevPlan rev_plan(int64_t n, int64_t m)
     }
     p.bits = bits;
     p.buckets = (n + (1 << bits) - 1) >> bits;
-    // edges per histogram / scatter block: enough blocks to fill the chip
-    // (up to 2048), at least 4096 edges each
+    // edges per histogram / scatter block: at least 4096, and at most 1024
+    // blocks (four per CU).  Longer chunks give longer per-bucket runs in the
+    // scatter's writes, and a build on a side stream leaves CUs to the solve
+    // it overlaps; 512 or fewer blocks no longer hide the loads.
     int64_t chunk = 4096;
-    while ((m + chunk - 1) / chunk > 2048) chunk <<= 1;
+    while ((m + chunk - 1) / chunk > 1024) chunk <<= 1;
     p.chunk = chunk;
     p.nblk = (m + chunk - 1) / chunk;
     p.hist_len = p.buckets * p.nblk;
