@@ -55,7 +55,7 @@ def lib():
         L.orc_karp.argtypes = [i64, i64, P, P, P, P, P]
         L.orc_karp.restype = C.c_int
         L.orc_solve.argtypes = [i64, i64, P, P, P, C.c_int, i32, C.c_int,
-                                C.POINTER(_Result), P, i64, P]
+                                C.POINTER(_Result), P, i64, P, P]
         L.orc_solve.restype = C.c_int
         L.orc_certify.argtypes = [i64, i64, P, P, P, C.c_int, i64, i64, P, i64, P, i64]
         L.orc_certify.restype = C.c_int
@@ -121,6 +121,7 @@ class Solution:
     L: int
     tight: int               # tight non-policy edges at the optimum
     V: np.ndarray | None     # potential scaled by L (int64), if requested
+    pi: np.ndarray | None = None   # final policy (CSR positions), if requested
 
     @property
     def value(self) -> Fraction:
@@ -128,20 +129,21 @@ class Solution:
 
 
 def solve(row_ptr, col, w, mode: str = "min", max_iters: int = 0,
-          tie: bool = True, want_V: bool = False) -> Solution:
+          tie: bool = True, want_V: bool = False, want_pi: bool = False) -> Solution:
     """Sequential policy iteration (Alg. 2 with readings R1-R10)."""
     rp, cl, ww = _csr(row_ptr, col, w)
     n, m = len(rp) - 1, len(cl)
     res = _Result()
     cyc = np.zeros(max(n, 1), np.int32)
     V = np.zeros(n, np.int64) if want_V else None
+    pi = np.zeros(n, np.int32) if want_pi else None
     rc = lib().orc_solve(n, m, _ptr(rp), _ptr(cl), _ptr(ww), int(mode == "max"),
                          max_iters, int(tie), C.byref(res), _ptr(cyc), n,
-                         _ptr(V) if want_V else None)
+                         _ptr(V) if want_V else None, _ptr(pi) if want_pi else None)
     if rc:
         raise OracleError(rc, "solve")
     return Solution(res.p, res.q, cyc[:res.cycle_len].copy(), res.source,
-                    res.iterations, res.tie, res.ncycles_first, res.W, res.L, res.tight, V)
+                    res.iterations, res.tie, res.ncycles_first, res.W, res.L, res.tight, V, pi)
 
 
 def certify(row_ptr, col, w, p, q, cycle, V, K, mode: str = "min") -> int:

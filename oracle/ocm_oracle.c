@@ -508,12 +508,12 @@ typedef struct {
 
 /* Full sequential solve.  cycle_edges (capacity cap) receives the critical
  * cycle as CSR positions from pi(s); val_out (n, may be NULL) receives the
- * final potential scaled by L.  max_iters = 0 means no limit.
- * do_tie = 1 runs the exact uniqueness test. */
+ * final potential scaled by L; pi_out (n, may be NULL) the final policy.
+ * max_iters = 0 means no limit.  do_tie = 1 runs the exact uniqueness test. */
 int orc_solve(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
               const int64_t *w64, int negate, int32_t max_iters, int do_tie,
               orc_result *res, int32_t *cycle_edges, int64_t cap,
-              int64_t *val_out)
+              int64_t *val_out, int32_t *pi_out)
 {
     int rc;
     orc_state *st = orc_state_new(n, m, row_ptr, col, w64, negate, &rc);
@@ -554,6 +554,7 @@ int orc_solve(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
         for (int64_t v = 0; v < n; ++v)
             for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
                 if (e != st->pi[v] && edge_value(st, e) == st->val[v]) res->tight++;
+        if (pi_out) orc_state_get_pi(st, pi_out);
         if (val_out) {
             rc = orc_state_get_val(st, val_out);
             if (rc) goto done;

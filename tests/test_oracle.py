@@ -42,8 +42,8 @@ def test_hand_traces_phase_by_phase(tr):
         assert st.get("val").tolist() == it["V"]
     r = tr["result"]
     sol = native.solve(rp, cl, w, want_V=True)
-    assert (sol.p, sol.q, sol.cycle.tolist(), sol.source, sol.iterations, sol.tie) == \
-        (r["p"], r["q"], r["cycle"], r["source"], r["iterations"], r["tie"])
+    assert (sol.p, sol.q, sol.cycle.tolist(), sol.source, sol.iterations, sol.tie, sol.tight) == \
+        (r["p"], r["q"], r["cycle"], r["source"], r["iterations"], r["tie"], r["tight"])
     val, crit = brute.optimum(rp, cl, w)
     assert val == Fraction(r["p"], r["q"]) == native.karp(rp, cl, w)
     assert tuple(r["cycle"]) in crit
@@ -64,10 +64,19 @@ def test_brute_enumerates_known_cycles():
 
 def _check_tiny(rp, cl, w, mode):
     val, crit = brute.optimum(rp, cl, w, mode)
-    sol = native.solve(rp, cl, w, mode=mode, want_V=True)
+    sol = native.solve(rp, cl, w, mode=mode, want_V=True, want_pi=True)
     assert sol.value == val
     assert tuple(sol.cycle.tolist()) in crit
     assert sol.tie == int(len(crit) > 1)
+    # Every edge of a critical cycle is tight at the optimum (its reduced
+    # costs are >= 0 under a feasible potential and sum to zero around it),
+    # so the tight non-policy count is at least the number of non-policy
+    # edges lying on some critical simple cycle; a second critical cycle
+    # needs at least one non-policy edge (the policy graph holds one cycle).
+    on_crit = set(e for c in crit for e in c)
+    assert sol.tight >= len(on_crit - set(sol.pi.tolist()))
+    if len(crit) > 1:
+        assert sol.tight >= 1
     assert sol.source == min(int(np.searchsorted(rp, e, side="right") - 1) for e in sol.cycle)
     assert native.certify(rp, cl, w, sol.p, sol.q, sol.cycle, sol.V, sol.L, mode) == 0
     kv = native.karp(rp, cl, w if mode == "min" else -w)
@@ -102,6 +111,36 @@ def test_tiny_graphs_without_ring_are_certified_or_rejected():
         assert sol.value == val and tuple(sol.cycle.tolist()) in crit
         assert native.certify(rp, cl, w, sol.p, sol.q, sol.cycle, sol.V, sol.L) == 0
     assert rejected > 100
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tight_count_closed_form(seed):
+    # A ring whose edges all weigh c plus chords weighing c or more.  The
+    # weight-c edges then form a strongly connected subgraph (it holds the
+    # ring), every weight-c edge lies on a cycle of mean c = the optimum, so
+    # all of them are tight and the potential is constant; a heavier edge has
+    # reduced cost L * (w - c) > 0.  Hence exactly (#weight-c edges) - n
+    # non-policy edges are tight, whatever trajectory the iteration took.
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 400))
+    c = int(rng.integers(-20, 20))
+    rp, cl, ww = [0], [], []
+    for v in range(n):
+        d = int(rng.integers(0, 5))
+        tg = [int(t) for t in rng.integers(0, n, d)]
+        wt = [c + (int(rng.integers(1, 4)) if rng.random() < 0.6 else 0) for _ in tg]
+        k = int(rng.integers(0, d + 1))
+        tg.insert(k, (v + 1) % n)
+        wt.insert(k, c)
+        cl.extend(tg)
+        ww.extend(wt)
+        rp.append(len(cl))
+    rp, cl, ww = np.array(rp), np.array(cl), np.array(ww)
+    for mode, sign in (("min", 1), ("max", -1)):
+        sol = native.solve(rp, cl, sign * ww, mode=mode, want_V=True, want_pi=True)
+        assert sol.value == sign * c
+        assert sol.tight == int((ww == c).sum()) - n
+        assert (sol.V == 0).all()
 
 
 def test_fig1_graph_not_strongly_connected():
