@@ -182,6 +182,33 @@ ocm_status ocm_max(const ocm_graph *g, const ocm_options *o, void *ws,
                    size_t ws_bytes, int32_t *cycle_edges, int64_t cycle_cap,
                    ocm_result *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ocm_min
+ * without a caller workspace.  Its scratch is a library-owned device array of
+ * OCM_NOALLOC_SCRATCH_BYTES (256 MiB) per GPU, part of the library's code
+ * object: every GPU the library is loaded on holds it until the process ends.
+ * Its address is looked up once per device (hipGetSymbolAddress), on the
+ * first call with that device current.
+ *   - Same arguments and results as ocm_min, minus the workspace; the caller
+ *     still owns the graph, cycle_edges and out.
+ *   - A graph whose workspace (ocm_workspace_size) exceeds the array gives
+ *     OCM_E_WORKSPACE with the sizes in ocm_last_error(); o->profile must be
+ *     NULL (OCM_E_INVALID_ARG).
+ *   - The call allocates no device memory and no pinned host memory, creates
+ *     no stream or event (control reads are synchronous copies into the
+ *     calling thread's stack) and calls no hipMalloc / hipFree.  The
+ *     uniqueness test's small host-side special-vertex graph, when that test
+ *     needs it, lives on the host heap.
+ *   - All calls on one GPU share that GPU's array, which keeps the last
+ *     call's contents (the solver initialises everything it reads).  Calls
+ *     on one device from threads of this process are serialised by a
+ *     per-device lock, and each call synchronises `stream` before returning;
+ *     work that another caller enqueues on the same array outside this entry
+ *     point would race with it. */
+#define OCM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+ocm_status ocm_min_noalloc(const ocm_graph *g, const ocm_options *o, int32_t *cycle_edges,
+                           int64_t cycle_cap, ocm_result *out, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Single phases of one policy-iteration step (Alg. 3), on caller arrays.  */
 /* They share the workspace layout of ocm_min and exist so that each phase */

@@ -294,6 +294,10 @@ void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsig
 hipError_t host_read(const void* dsrc, void* hdst, size_t bytes, hipStream_t st);
 // Folds a control block's lanes and reads the snapshot.
 hipError_t host_read_ctl(const Ctl* ctl, CtlView* out, hipStream_t st);
+// The same through a copy into the caller's stack and a stream
+// synchronisation: no pinned mailbox is created (used by the entry point
+// that allocates nothing).
+hipError_t host_read_ctl_copy(const Ctl* ctl, CtlView* out, hipStream_t st);
 
 // thread-local message returned by ocm_last_error()
 void set_last_error(const char* what);

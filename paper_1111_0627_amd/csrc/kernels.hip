@@ -2766,20 +2766,21 @@ hipError_t host_read(const void* dsrc, void* hdst, size_t bytes, hipStream_t st)
     return hipSuccess;
 }
 
+hipError_t host_read_ctl_copy(const Ctl* ctl, CtlView* out, hipStream_t st)
+{
+    Ctl h;   // on the caller's stack: this path allocates nothing
+    hipError_t e = hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) fold_lanes(h, *out);
+    return e;
+}
+
 hipError_t host_read_ctl(const Ctl* ctl, CtlView* out, hipStream_t st)
 {
     static_assert(sizeof(CtlView) <= 4 * kPostWords && sizeof(CtlView) % 4 == 0,
                   "the snapshot fits the mailbox");
     Mailbox& mb = mailbox();
-    if (mb.stream_mode) {
-        Ctl* h = (Ctl*)malloc(sizeof(Ctl));
-        if (!h) return hipErrorOutOfMemory;
-        hipError_t e = hipMemcpyAsync(h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e == hipSuccess) fold_lanes(*h, *out);
-        free(h);
-        return e;
-    }
+    if (mb.stream_mode) return host_read_ctl_copy(ctl, out, st);
     const unsigned want = ++mb.seq;
     k_post_ctl<<<1, 64, 0, st>>>(ctl, (CtlView*)mb.dev, mb.dev + kPostWords, want);
     hipError_t e = hipGetLastError();

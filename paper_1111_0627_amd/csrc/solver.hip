@@ -213,6 +213,9 @@ struct Ctx {
     int64_t push_frontier = 0;
     int general_iters = 0;
     int value_rounds = 0;
+    // the call may not allocate: control reads go through a stack copy
+    // instead of the pinned mailbox, and no side stream or event is created
+    bool noalloc = false;
 
     Ctx() = default;
     Ctx(const Ctx&) = delete;
@@ -236,6 +239,10 @@ constexpr unsigned kPushMinUnattached = 1u << 16;
 
 ocm_status read_ctl(Ctx& c)
 {
+    if (c.noalloc) {
+        HIP_TRY(ocm::host_read_ctl_copy(c.ws.ctl, &c.h, c.st));
+        return OCM_OK;
+    }
     HIP_TRY(ocm::host_read_ctl(c.ws.ctl, &c.h, c.st));
     return OCM_OK;
 }
@@ -535,7 +542,8 @@ hipStream_t side_stream()
 // timings stay per kernel), not for pull-only rebuilds.
 void start_reverse_early(Ctx& c)
 {
-    if (c.prof.out || c.rev_built || c.connect_mode == 1 || c.n < 2 * (int64_t)kPushMinUnattached)
+    if (c.noalloc || c.prof.out || c.rev_built || c.connect_mode == 1 ||
+        c.n < 2 * (int64_t)kPushMinUnattached)
         return;
     hipStream_t side = side_stream();
     if (!side) return;
@@ -936,7 +944,8 @@ long long gcd_ll(long long a, long long b)
 }
 
 ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t ws_bytes,
-                 int32_t* cycle_edges, int64_t cap, ocm_result* out, void* stream, int neg)
+                 int32_t* cycle_edges, int64_t cap, ocm_result* out, void* stream, int neg,
+                 bool noalloc = false)
 {
     if (!out) return fail(OCM_E_INVALID_ARG, "result pointer is null");
     memset(out, 0, sizeof *out);
@@ -945,6 +954,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     else ocm_default_options(&o);
     if (o.profile) memset(o.profile, 0, sizeof *o.profile);
     Ctx c;
+    c.noalloc = noalloc;
     OCM_TRY(setup(c, g, neg, wsp, ws_bytes, stream, o.profile));
     if (cap > 0 && !cycle_edges) return fail(OCM_E_INVALID_ARG, "cycle_edges is null");
     c.G = choose_lanes(c.n, c.m, o.schedule);
@@ -1083,9 +1093,70 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     return OCM_OK;
 }
 
+// Workspace of ocm_min_noalloc: one array per GPU (each device that loads
+// the library holds its own copy until the process ends).  Host code must
+// never pass `scratch` itself to a kernel (in host code it names a host-side
+// stand-in); it uses the device address from hipGetSymbolAddress instead.
+static __device__ __align__(256) unsigned char scratch[OCM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchSlot {
+    std::mutex call;           // serialises calls on this device within the process
+    void* ptr = nullptr;       // device address of this device's `scratch`
+    bool init = false;
+};
+ScratchSlot g_scratch[kMaxDevices];
+std::mutex g_scratch_init;
+
+// The calling thread's current device and the address of its `scratch`,
+// looked up once per device with that device current.
+ocm_status scratch_slot(ScratchSlot** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(OCM_E_INVALID_ARG, "device index out of range");
+    ScratchSlot& sl = g_scratch[dev];
+    std::lock_guard<std::mutex> lock(g_scratch_init);
+    if (!sl.init) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(OCM_E_HIP, "no device address for the static scratch array");
+        sl.ptr = p;
+        sl.init = true;
+    }
+    *out = &sl;
+    return OCM_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+ocm_status ocm_min_noalloc(const ocm_graph* g, const ocm_options* o, int32_t* cycle_edges,
+                           int64_t cycle_cap, ocm_result* out, void* stream)
+{
+    if (o && o->profile) return fail(OCM_E_INVALID_ARG, "ocm_min_noalloc takes no profile");
+    OCM_TRY(check_graph(g));
+    const size_t need = carve(nullptr, g->n, g->m).total;
+    if (need > (size_t)OCM_NOALLOC_SCRATCH_BYTES) {
+        char b[192];
+        snprintf(b, sizeof b,
+                 "graph needs %zu bytes of scratch; ocm_min_noalloc holds %zu (use ocm_min with a "
+                 "caller workspace)",
+                 need, (size_t)OCM_NOALLOC_SCRATCH_BYTES);
+        return fail(OCM_E_WORKSPACE, b);
+    }
+    ScratchSlot* sl = nullptr;
+    OCM_TRY(scratch_slot(&sl));
+    std::lock_guard<std::mutex> lock(sl->call);
+    const ocm_status rc = solve(g, o, sl->ptr, OCM_NOALLOC_SCRATCH_BYTES, cycle_edges, cycle_cap,
+                                out, stream, 0, true);
+    // the array is free for the next call only once this call's kernels end
+    const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (rc == OCM_OK && e != hipSuccess) return fail(OCM_E_HIP, hipGetErrorString(e));
+    return rc;
+}
 
 ocm_status ocm_weights_from_f64(int64_t m, const double* w_f64, int64_t* w_i64, void* ws,
                                 size_t ws_bytes, void* stream)

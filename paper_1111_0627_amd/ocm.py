@@ -94,6 +94,8 @@ def lib():
         for f in (L.ocm_min, L.ocm_max):
             f.argtypes = [G, O, P, C.c_size_t, P, i64, C.POINTER(_Result), P]
             f.restype = C.c_int
+        L.ocm_min_noalloc.argtypes = [G, O, P, i64, C.POINTER(_Result), P]
+        L.ocm_min_noalloc.restype = C.c_int
         L.ocm_phase_sweep.argtypes = [G, i32, i32, P, i64, i64, P, i32, P, C.c_size_t,
                                       C.POINTER(i64), P]
         L.ocm_phase_cycles.argtypes = [G, P, P, P, P, C.c_size_t, C.POINTER(i64), P]
@@ -250,6 +252,27 @@ def min_cycle_mean(row_ptr, col, w, *, want_policy=False, want_potential=False,
                    profile=False, **opt) -> Result:
     """Exact minimum cycle mean and one critical cycle (ocm_min)."""
     return _solve(lib().ocm_min, row_ptr, col, w, want_policy, want_potential, profile, **opt)
+
+
+# ocm_min_noalloc's scratch per GPU (OCM_NOALLOC_SCRATCH_BYTES in ocm.h)
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def min_cycle_mean_noalloc(row_ptr, col, w, cycle_out: torch.Tensor, **opt) -> Result:
+    """ocm_min without a workspace (ocm_min_noalloc): the library's static
+    per-GPU scratch array is used, so the call allocates no device memory.
+    ``cycle_out``: caller-owned int32 device tensor for the cycle's edges."""
+    g = make_graph(row_ptr, col, w)
+    _dev(cycle_out, (torch.int32,), "cycle_out")
+    o = options(**opt)
+    res = _Result()
+    _check(lib().ocm_min_noalloc(C.byref(g), C.byref(o), C.c_void_p(cycle_out.data_ptr()),
+                                 cycle_out.numel(), C.byref(res), _stream()))
+    counters = dict(push_frontier=res.push_frontier, push_in_edges=res.push_in_edges,
+                    general_iters=res.general_iters, value_rounds=res.value_rounds)
+    return Result(res.p, res.q, cycle_out[:res.cycle_len], res.source, res.iterations, res.flags,
+                  res.W, res.L, res.tight_edges, res.connect_rounds, res.jump_rounds,
+                  res.fast_iters, counters)
 
 
 def max_cycle_mean(row_ptr, col, w, *, want_policy=False, want_potential=False,
