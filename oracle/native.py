@@ -57,6 +57,14 @@ def lib():
         L.orc_solve.argtypes = [i64, i64, P, P, P, C.c_int, i32, C.c_int,
                                 C.POINTER(_Result), P, i64, P, P]
         L.orc_solve.restype = C.c_int
+        L.orc_solve_ratio.argtypes = [i64, i64, P, P, P, P, C.c_int, i32, C.c_int,
+                                      C.POINTER(_Result), P, i64, P, P]
+        L.orc_solve_ratio.restype = C.c_int
+        L.orc_certify_ratio.argtypes = [i64, i64, P, P, P, P, C.c_int, i64, i64, P, i64, P,
+                                        i64]
+        L.orc_certify_ratio.restype = C.c_int
+        L.orc_state_new_ratio.argtypes = [i64, i64, P, P, P, P, C.c_int, C.POINTER(C.c_int)]
+        L.orc_state_new_ratio.restype = P
         L.orc_certify.argtypes = [i64, i64, P, P, P, C.c_int, i64, i64, P, i64, P, i64]
         L.orc_certify.restype = C.c_int
         L.orc_state_new.argtypes = [i64, i64, P, P, P, C.c_int, C.POINTER(C.c_int)]
@@ -129,31 +137,38 @@ class Solution:
 
 
 def solve(row_ptr, col, w, mode: str = "min", max_iters: int = 0,
-          tie: bool = True, want_V: bool = False, want_pi: bool = False) -> Solution:
-    """Sequential policy iteration (Alg. 2 with readings R1-R10)."""
+          tie: bool = True, want_V: bool = False, want_pi: bool = False,
+          t=None) -> Solution:
+    """Sequential policy iteration (Alg. 2 with readings R1-R10).  With edge
+    times ``t`` (integers >= 1) it solves the optimal cycle ratio cost/time;
+    then ``L`` is the critical cycle's time and ``len(cycle)`` its length."""
     rp, cl, ww = _csr(row_ptr, col, w)
     n, m = len(rp) - 1, len(cl)
     res = _Result()
     cyc = np.zeros(max(n, 1), np.int32)
     V = np.zeros(n, np.int64) if want_V else None
     pi = np.zeros(n, np.int32) if want_pi else None
-    rc = lib().orc_solve(n, m, _ptr(rp), _ptr(cl), _ptr(ww), int(mode == "max"),
-                         max_iters, int(tie), C.byref(res), _ptr(cyc), n,
-                         _ptr(V) if want_V else None, _ptr(pi) if want_pi else None)
+    tt = None if t is None else np.ascontiguousarray(t, dtype=np.int64)
+    rc = lib().orc_solve_ratio(n, m, _ptr(rp), _ptr(cl), _ptr(ww),
+                               None if tt is None else _ptr(tt), int(mode == "max"),
+                               max_iters, int(tie), C.byref(res), _ptr(cyc), n,
+                               _ptr(V) if want_V else None, _ptr(pi) if want_pi else None)
     if rc:
         raise OracleError(rc, "solve")
     return Solution(res.p, res.q, cyc[:res.cycle_len].copy(), res.source,
                     res.iterations, res.tie, res.ncycles_first, res.W, res.L, res.tight, V, pi)
 
 
-def certify(row_ptr, col, w, p, q, cycle, V, K, mode: str = "min") -> int:
-    """Optimality certificate; returns ORC_OK (0) or a negative code."""
+def certify(row_ptr, col, w, p, q, cycle, V, K, mode: str = "min", t=None) -> int:
+    """Optimality certificate; returns ORC_OK (0) or a negative code.  With
+    edge times ``t`` it certifies the optimal cost-to-time ratio p/q."""
     rp, cl, ww = _csr(row_ptr, col, w)
     cy = np.ascontiguousarray(cycle, dtype=np.int32)
     VV = np.ascontiguousarray(V, dtype=np.int64)
-    return lib().orc_certify(len(rp) - 1, len(cl), _ptr(rp), _ptr(cl), _ptr(ww),
-                             int(mode == "max"), int(p), int(q), _ptr(cy), len(cy),
-                             _ptr(VV), int(K))
+    tt = None if t is None else np.ascontiguousarray(t, dtype=np.int64)
+    return lib().orc_certify_ratio(len(rp) - 1, len(cl), _ptr(rp), _ptr(cl), _ptr(ww),
+                                   None if tt is None else _ptr(tt), int(mode == "max"),
+                                   int(p), int(q), _ptr(cy), len(cy), _ptr(VV), int(K))
 
 
 class Stepper:
@@ -165,12 +180,15 @@ class Stepper:
     ``values`` (value update from the source).
     """
 
-    def __init__(self, row_ptr, col, w, mode: str = "min"):
+    def __init__(self, row_ptr, col, w, mode: str = "min", t=None):
         self.rp, self.cl, self.ww = _csr(row_ptr, col, w)
+        self.tt = None if t is None else np.ascontiguousarray(t, dtype=np.int64)
         self.n, self.m = len(self.rp) - 1, len(self.cl)
         rc = C.c_int()
-        self.h = lib().orc_state_new(self.n, self.m, _ptr(self.rp), _ptr(self.cl),
-                                     _ptr(self.ww), int(mode == "max"), C.byref(rc))
+        self.h = lib().orc_state_new_ratio(self.n, self.m, _ptr(self.rp), _ptr(self.cl),
+                                           _ptr(self.ww),
+                                           None if self.tt is None else _ptr(self.tt),
+                                           int(mode == "max"), C.byref(rc))
         if not self.h:
             raise OracleError(rc.value, "state")
 

@@ -20,6 +20,12 @@
  *   orc_certify   O(m) optimality certificate: a cycle of mean lambda plus a
  *                 potential feasible for w - lambda (Prop. 2.1 and the LP of
  *                 Eq. (1), Section 2.4) prove lambda is the optimum.
+ *   *_ratio       The optimal cycle ratio (Section 2.2: every transition
+ *                 carries a cost w and a time t, and the ratio of a cycle is
+ *                 its cost over its time), by the same policy iteration with
+ *                 lambda = W / T and edge values T * w - W * t; the cycle mean
+ *                 is the case t = 1 on every edge.  Times are integers >= 1,
+ *                 so every cycle has positive time.
  *
  * Readings where the paper leaves a choice open (Alg. 2 and Section 3.1):
  *   R1  the initial policy (pi = nil, val = 0, lambda = 0) picks, per vertex,
@@ -165,6 +171,8 @@ typedef struct orc_state {
     int64_t n, m;
     const int32_t *row_ptr, *col;
     int64_t *w;          /* weights, negated for the maximum (R10) */
+    int64_t *t;          /* times (ratio problem), NULL = 1 on every edge */
+    int64_t clen;        /* number of edges of the chosen cycle */
     int32_t *src;        /* source vertex of every edge */
     /* backward adjacency: for every vertex x, the edges entering x */
     int64_t *in_ptr;
@@ -172,7 +180,7 @@ typedef struct orc_state {
     /* Howard state */
     int32_t *pi;         /* policy: CSR position of the chosen out-edge, -1 = nil */
     i128 *val;           /* V, scaled by L */
-    int64_t W, L;        /* lambda = W / L, unreduced */
+    int64_t W, L;        /* lambda = W / L, unreduced (L = time of C for a ratio) */
     int32_t s;           /* source vertex */
     int32_t iter;        /* sweeps done */
     /* cycle phase outputs */
@@ -188,7 +196,7 @@ typedef struct orc_state {
 void orc_state_free(orc_state *st)
 {
     if (!st) return;
-    free(st->w); free(st->src); free(st->in_ptr); free(st->in_edge);
+    free(st->w); free(st->t); free(st->src); free(st->in_ptr); free(st->in_edge);
     free(st->pi); free(st->val); free(st->rep); free(st->on_cycle);
     free(st->layer); free(st->mark); free(st->stack); free(st->queue);
     free(st->cyc_of);
@@ -196,14 +204,18 @@ void orc_state_free(orc_state *st)
 }
 
 /* Creates a solver state.  w64 holds the weights as int64 (the caller widens
- * int32 weights); negate selects the maximum (R10).  The arrays must outlive
- * the state.  *rc receives the status. */
-orc_state *orc_state_new(int64_t n, int64_t m, const int32_t *row_ptr,
-                         const int32_t *col, const int64_t *w64, int negate,
-                         int *rc)
+ * int32 weights); t64 the times (NULL: the cycle mean, every time 1); negate
+ * selects the maximum (R10).  The arrays must outlive the state.  *rc
+ * receives the status. */
+orc_state *orc_state_new_ratio(int64_t n, int64_t m, const int32_t *row_ptr,
+                               const int32_t *col, const int64_t *w64,
+                               const int64_t *t64, int negate, int *rc)
 {
     *rc = check_csr(n, m, row_ptr, col);
     if (*rc) return NULL;
+    if (t64)
+        for (int64_t e = 0; e < m; ++e)
+            if (t64[e] < 1) { *rc = ORC_E_INVALID_ARG; return NULL; }
     orc_state *st = calloc(1, sizeof(orc_state));
     if (!st) { *rc = ORC_E_NOMEM; return NULL; }
     st->n = n; st->m = m; st->row_ptr = row_ptr; st->col = col;
@@ -226,6 +238,11 @@ orc_state *orc_state_new(int64_t n, int64_t m, const int32_t *row_ptr,
         orc_state_free(st); *rc = ORC_E_NOMEM; return NULL;
     }
     for (int64_t e = 0; e < m; ++e) st->w[e] = negate ? -w64[e] : w64[e];
+    if (t64) {
+        st->t = malloc(sizeof(int64_t) * m);
+        if (!st->t) { orc_state_free(st); *rc = ORC_E_NOMEM; return NULL; }
+        memcpy(st->t, t64, sizeof(int64_t) * m);
+    }
     for (int64_t v = 0; v < n; ++v)
         for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) st->src[e] = (int32_t)v;
     /* backward edges, the G^-1 of Alg. 3, stored explicitly as in Sec. 2.3 */
@@ -239,14 +256,28 @@ orc_state *orc_state_new(int64_t n, int64_t m, const int32_t *row_ptr,
         free(fill);
     }
     for (int64_t v = 0; v < n; ++v) st->pi[v] = -1;
-    st->W = 0; st->L = 1; st->s = -1; st->iter = 0; st->rounds = 0;
+    st->W = 0; st->L = 1; st->s = -1; st->iter = 0; st->rounds = 0; st->clen = 0;
     return st;
 }
 
-/* Value of edge e under the current lambda: V(target) + L * w(e) - W. */
+orc_state *orc_state_new(int64_t n, int64_t m, const int32_t *row_ptr,
+                         const int32_t *col, const int64_t *w64, int negate,
+                         int *rc)
+{
+    return orc_state_new_ratio(n, m, row_ptr, col, w64, NULL, negate, rc);
+}
+
+/* Time of edge e (1 for the cycle mean). */
+static int64_t edge_time(const orc_state *st, int64_t e)
+{
+    return st->t ? st->t[e] : 1;
+}
+
+/* Value of edge e under the current lambda = W / L:
+ * V(target) + L * w(e) - W * t(e). */
 static i128 edge_value(const orc_state *st, int64_t e)
 {
-    return st->val[st->col[e]] + (i128)st->L * st->w[e] - st->W;
+    return st->val[st->col[e]] + (i128)st->L * st->w[e] - (i128)st->W * edge_time(st, e);
 }
 
 /* Policy improvement: one pass of the main loop of Alg. 2.  For every vertex
@@ -315,29 +346,33 @@ int64_t orc_state_cycles(orc_state *st)
 }
 
 /* MinMeanWeightCycle and MinVertex of Alg. 2 (R3, R4): among the cycles of
- * the policy graph pick the smallest mean W/L, ties to the smallest rep. */
+ * the policy graph pick the smallest mean W/L (for a ratio: cost over time),
+ * ties to the smallest rep. */
 int orc_state_select(orc_state *st, int32_t *s, int64_t *W, int64_t *L)
 {
     int32_t best_r = -1;
-    i128 bw = 0;
-    int64_t bl = 1;
+    i128 bw = 0, bl = 1;
+    int64_t bc = 0;
     for (int64_t r = 0; r < st->n; ++r) {
         if (!st->on_cycle[r] || st->rep[r] != r) continue;
-        i128 cw = 0;
+        i128 cw = 0, ct = 0;
         int64_t cl = 0;
         int32_t y = (int32_t)r;
         do {
             cw += st->w[st->pi[y]];
+            ct += edge_time(st, st->pi[y]);
             ++cl;
             y = st->col[st->pi[y]];
         } while (y != r);
-        /* cw / cl < bw / bl, both denominators positive */
-        if (best_r < 0 || cw * bl < bw * cl) { best_r = (int32_t)r; bw = cw; bl = cl; }
+        /* cw / ct < bw / bl, both denominators positive */
+        if (best_r < 0 || cw * bl < bw * ct) { best_r = (int32_t)r; bw = cw; bl = ct; bc = cl; }
     }
-    if (bw > (i128)INT64_MAX || bw < (i128)INT64_MIN) return ORC_E_OVERFLOW;
+    if (bw > (i128)INT64_MAX || bw < (i128)INT64_MIN || bl > (i128)INT64_MAX)
+        return ORC_E_OVERFLOW;
     st->s = best_r;
     st->W = (int64_t)bw;
-    st->L = bl;
+    st->L = (int64_t)bl;
+    st->clen = bc;
     *s = best_r; *W = st->W; *L = st->L;
     return ORC_OK;
 }
@@ -391,7 +426,7 @@ void orc_state_values(orc_state *st)
             int32_t e = st->in_edge[i];
             int32_t u = st->src[e];
             if (u != st->s && st->pi[u] == e) {
-                st->val[u] = st->val[v] + (i128)st->L * st->w[e] - st->W;
+                st->val[u] = st->val[v] + (i128)st->L * st->w[e] - (i128)st->W * edge_time(st, e);
                 st->queue[tail++] = u;
             }
         }
@@ -509,14 +544,16 @@ typedef struct {
 /* Full sequential solve.  cycle_edges (capacity cap) receives the critical
  * cycle as CSR positions from pi(s); val_out (n, may be NULL) receives the
  * final potential scaled by L; pi_out (n, may be NULL) the final policy.
- * max_iters = 0 means no limit.  do_tie = 1 runs the exact uniqueness test. */
-int orc_solve(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
-              const int64_t *w64, int negate, int32_t max_iters, int do_tie,
-              orc_result *res, int32_t *cycle_edges, int64_t cap,
-              int64_t *val_out, int32_t *pi_out)
+ * max_iters = 0 means no limit.  do_tie = 1 runs the exact uniqueness test.
+ * t64 (may be NULL): edge times of the ratio problem; then p/q = W/L is the
+ * optimal cost-to-time ratio, L the time of C and cycle_len its edge count. */
+int orc_solve_ratio(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                    const int64_t *w64, const int64_t *t64, int negate, int32_t max_iters,
+                    int do_tie, orc_result *res, int32_t *cycle_edges, int64_t cap,
+                    int64_t *val_out, int32_t *pi_out)
 {
     int rc;
-    orc_state *st = orc_state_new(n, m, row_ptr, col, w64, negate, &rc);
+    orc_state *st = orc_state_new_ratio(n, m, row_ptr, col, w64, t64, negate, &rc);
     if (!st) return rc;
     memset(res, 0, sizeof(*res));
     for (;;) {
@@ -540,11 +577,11 @@ int orc_solve(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
         res->W = W; res->L = L;
         res->source = st->s;
         res->iterations = st->iter;
-        res->cycle_len = L;
+        res->cycle_len = st->clen;
         if (cycle_edges) {
-            if (cap < L) { rc = ORC_E_CAPACITY; goto done; }
+            if (cap < st->clen) { rc = ORC_E_CAPACITY; goto done; }
             int32_t y = st->s;
-            for (int64_t i = 0; i < L; ++i) {
+            for (int64_t i = 0; i < st->clen; ++i) {
                 cycle_edges[i] = st->pi[y];
                 y = st->col[st->pi[y]];
             }
@@ -566,19 +603,30 @@ done:
     return rc;
 }
 
+int orc_solve(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+              const int64_t *w64, int negate, int32_t max_iters, int do_tie,
+              orc_result *res, int32_t *cycle_edges, int64_t cap,
+              int64_t *val_out, int32_t *pi_out)
+{
+    return orc_solve_ratio(n, m, row_ptr, col, w64, NULL, negate, max_iters, do_tie, res,
+                           cycle_edges, cap, val_out, pi_out);
+}
+
 /* Optimality certificate.  Checks
  *   (a) cycle_edges is a closed walk over valid edges visiting no vertex twice,
- *   (b) its weight sum equals p/q times its length, and
+ *   (b) its weight sum equals p/q times its length (for a ratio: its time),
  *   (c) V, scaled by K > 0 with K*p/q = Wk an integer, satisfies
- *       V(v) <= V(u) + K*w(e) - Wk on every edge e = v->u
+ *       V(v) <= V(u) + K*w(e) - Wk*t(e) on every edge e = v->u (t = 1 for
+ *       the mean)
  * for the minimum (negate = 0) or the maximum (negate = 1, on -w and -p).
- * (c) says p/q is feasible, so p/q <= optimum (Prop. 2.1 and Eq. (1)); (a)+(b)
- * exhibit a cycle of mean p/q.  Together: p/q is the optimum.  The check is
- * O(m) in int128 and independent of how V was computed. */
-int orc_certify(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
-                const int64_t *w64, int negate, int64_t p, int64_t q,
-                const int32_t *cycle_edges, int64_t cycle_len,
-                const int64_t *V, int64_t K)
+ * (c) says p/q is feasible: summed around any cycle it gives
+ * K*(cost) - Wk*(time) >= 0, so p/q <= optimum (Prop. 2.1 and Eq. (1));
+ * (a)+(b) exhibit a cycle of value p/q.  Together: p/q is the optimum.  The
+ * check is O(m) in int128 and independent of how V was computed. */
+int orc_certify_ratio(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                      const int64_t *w64, const int64_t *t64, int negate, int64_t p,
+                      int64_t q, const int32_t *cycle_edges, int64_t cycle_len,
+                      const int64_t *V, int64_t K)
 {
     int rc = check_csr(n, m, row_ptr, col);
     if (rc) return rc;
@@ -589,7 +637,7 @@ int orc_certify(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col
     /* (a) + (b) */
     uint8_t *seen = calloc(n, 1);
     if (!seen) return ORC_E_NOMEM;
-    i128 sum = 0;
+    i128 sum = 0, tsum = 0;
     int32_t first_src = -1, at = -1;
     rc = ORC_OK;
     for (int64_t i = 0; i < cycle_len; ++i) {
@@ -607,17 +655,97 @@ int orc_certify(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col
         if (seen[v]) { rc = ORC_E_CERT_CYCLE; break; }
         seen[v] = 1;
         sum += negate ? -w64[e] : w64[e];
+        tsum += t64 ? t64[e] : 1;
         at = col[e];
     }
     free(seen);
     if (rc) return rc;
     if (at != first_src) return ORC_E_CERT_CYCLE;
-    if (sum * q != (i128)pm * cycle_len) return ORC_E_CERT_MEAN;
+    if (sum * q != (i128)pm * tsum) return ORC_E_CERT_MEAN;
     /* (c) */
     for (int64_t v = 0; v < n; ++v)
         for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
             i128 wv = negate ? -w64[e] : w64[e];
-            if ((i128)V[v] > (i128)V[col[e]] + (i128)K * wv - Wk) return ORC_E_CERT_POTENTIAL;
+            i128 tv = t64 ? t64[e] : 1;
+            if ((i128)V[v] > (i128)V[col[e]] + (i128)K * wv - Wk * tv) return ORC_E_CERT_POTENTIAL;
         }
     return ORC_OK;
+}
+
+int orc_certify(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                const int64_t *w64, int negate, int64_t p, int64_t q,
+                const int32_t *cycle_edges, int64_t cycle_len,
+                const int64_t *V, int64_t K)
+{
+    return orc_certify_ratio(n, m, row_ptr, col, w64, NULL, negate, p, q, cycle_edges,
+                             cycle_len, V, K);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Strongly connected components (Tarjan's algorithm, iterative), for inputs */
+/* that are not strongly connected: Prop. 2.2 makes the optimum of a graph   */
+/* the best optimum over its components that hold a cycle (Section 2.5       */
+/* names the SCC decomposition as the alternative to the Hamiltonian-cycle   */
+/* augmentation).  Vertices may have no out-edge.  comp_out[v] receives the  */
+/* smallest vertex index of v's component.  Returns ORC_OK or an error.      */
+/* ------------------------------------------------------------------------ */
+int orc_scc(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+            int32_t *comp_out)
+{
+    if (n < 1 || m < 0) return ORC_E_INVALID_ARG;
+    if (row_ptr[0] != 0 || (int64_t)row_ptr[n] != m) return ORC_E_BAD_CSR;
+    for (int64_t v = 0; v < n; ++v)
+        if (row_ptr[v + 1] < row_ptr[v]) return ORC_E_BAD_CSR;
+    for (int64_t e = 0; e < m; ++e)
+        if (col[e] < 0 || (int64_t)col[e] >= n) return ORC_E_BAD_CSR;
+    int32_t *index = malloc(sizeof(int32_t) * n), *low = malloc(sizeof(int32_t) * n);
+    int32_t *stk = malloc(sizeof(int32_t) * n), *cs_v = malloc(sizeof(int32_t) * n);
+    int64_t *cs_e = malloc(sizeof(int64_t) * n);
+    uint8_t *onstk = calloc(n, 1);
+    int rc = ORC_E_NOMEM;
+    if (!index || !low || !stk || !cs_v || !cs_e || !onstk) goto out;
+    for (int64_t v = 0; v < n; ++v) index[v] = -1;
+    int32_t counter = 0;
+    int64_t sp = 0, csp = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        if (index[r] != -1) continue;
+        cs_v[csp] = (int32_t)r; cs_e[csp] = row_ptr[r]; ++csp;
+        index[r] = low[r] = counter++;
+        stk[sp++] = (int32_t)r; onstk[r] = 1;
+        while (csp > 0) {
+            int32_t v = cs_v[csp - 1];
+            int64_t e = cs_e[csp - 1];
+            if (e < row_ptr[v + 1]) {
+                cs_e[csp - 1] = e + 1;
+                int32_t u = col[e];
+                if (index[u] == -1) {
+                    index[u] = low[u] = counter++;
+                    stk[sp++] = u; onstk[u] = 1;
+                    cs_v[csp] = u; cs_e[csp] = row_ptr[u]; ++csp;
+                } else if (onstk[u] && index[u] < low[v]) {
+                    low[v] = index[u];
+                }
+            } else {
+                --csp;
+                if (csp > 0) {
+                    int32_t p = cs_v[csp - 1];
+                    if (low[v] < low[p]) low[p] = low[v];
+                }
+                if (low[v] == index[v]) {
+                    /* pop the component; its id is its smallest vertex */
+                    int64_t top = sp;
+                    int32_t mn = v, x;
+                    do { x = stk[--sp]; if (x < mn) mn = x; } while (x != v);
+                    for (int64_t i = sp; i < top; ++i) {
+                        onstk[stk[i]] = 0;
+                        comp_out[stk[i]] = mn;
+                    }
+                }
+            }
+        }
+    }
+    rc = ORC_OK;
+out:
+    free(index); free(low); free(stk); free(cs_v); free(cs_e); free(onstk);
+    return rc;
 }
