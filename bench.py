@@ -231,6 +231,20 @@ def roofline(cls, ms, launches, nbytes):
             "avg_launch_us": ms * 1e3 / max(launches, 1)}
 
 
+def host_cpu():
+    """The host's CPU model and logical core count (the oracle uses one)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
 def cpu_baseline(g, mode, budget_s=30.0):
     """The C oracle (one thread) on the same workload: a full sequential
     policy-iteration solve; edges/s/iter = m * iterations / time."""
@@ -241,7 +255,104 @@ def cpu_baseline(g, mode, budget_s=30.0):
     return dict(value=g.m * sol.iterations / dt, unit="edges/s", cores=1, kind="oracle",
                 sample=f"one full sequential policy-iteration solve of the same workload "
                        f"({sol.iterations} iterations, {dt:.1f} s, single thread)",
-                seconds=round(dt, 2), iterations=sol.iterations, p=sol.p, q=sol.q)
+                seconds=round(dt, 2), iterations=sol.iterations, p=sol.p, q=sol.q,
+                host=host_cpu())
+
+
+def cpu_sample(g, mode, budget_s=10.0):
+    """The oracle's policy iteration, phase by phase, until it converges or
+    the budget is spent (whole iterations): edges/s/iter over what ran."""
+    from oracle import native
+    st = native.Stepper(g.row_ptr, g.col, g.w, mode=mode)
+    t0 = time.perf_counter()
+    it, done = 0, False
+    while time.perf_counter() - t0 < budget_s:
+        ch = st.sweep()
+        it += 1
+        if it >= 2 and ch == 0:
+            done = True
+            break
+        st.cycles()
+        st.select()
+        st.connect()
+        st.values()
+    dt = time.perf_counter() - t0
+    return dict(value=g.m * it / dt, unit="edges/s", cores=1, kind="oracle",
+                sample=(f"full sequential solve ({it} iterations)" if done else
+                        f"the first {it} iterations of the sequential solve (time budget)"),
+                seconds=round(dt, 2), iterations_run=it, converged=done)
+
+
+def bench_config(name, steps):
+    """One single-graph workload: time-to-exact-OCM (median of `steps` after a
+    warm-up), iterations, edges/s/iter, the sweep's HBM roofline, and the
+    oracle on the host (bounded sample; Karp on the small random graph)."""
+    from oracle import native
+    from paper_1111_0627_amd import ocm, synth
+    import torch
+    mode = synth.WORKLOADS[name]["mode"]
+    g = synth.workload(name)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    cl = torch.from_numpy(g.col).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    r = ocm.cycle_mean(rp, cl, w, mode=mode)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t = time.perf_counter()
+        r2 = ocm.cycle_mean(rp, cl, w, mode=mode)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1e3)
+        assert (r2.p, r2.q, r2.iterations) == (r.p, r.q, r.iterations)
+    med = float(np.median(ts))
+    phase = {}
+    for _ in range(max(1, steps // 2)):
+        rp_ = ocm.cycle_mean(rp, cl, w, mode=mode, profile=True)
+        for k, (pms, cnt, nbytes) in rp_.profile.items():
+            a = phase.setdefault(k, [0.0, 0, 0.0])
+            a[0] += pms
+            a[1] += cnt
+            a[2] += nbytes
+    out = {"n": g.n, "m": g.m, "mode": mode, "iterations": r.iterations,
+           "p": r.p, "q": r.q, "cycle_len": r.L, "fast_iters": r.fast_iters,
+           "time_to_exact_ocm_ms": {"median": med, "min": min(ts)},
+           "edges_per_s_per_iter": g.m * r.iterations / (med / 1e3),
+           "roofline_sweep": roofline("sweep", *phase["sweep"])}
+    gold = os.path.join(ROOT, "tests", "golden", "workloads.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            ex = json.load(f).get(name)
+        if ex:
+            out["matches_oracle_golden"] = (r.p, r.q, r.cycle_edges.cpu().tolist(), r.iterations) \
+                == (ex["p"], ex["q"], ex["cycle"], ex["iterations"])
+    cb = cpu_sample(g, mode)
+    if name == "rand1k":
+        t = time.perf_counter()
+        kv = native.karp(g.row_ptr, g.col, g.w)
+        cb["karp_seconds"] = round(time.perf_counter() - t, 4)
+        cb["karp_agrees"] = kv == r.value
+    out["cpu_oracle"] = cb
+    return out
+
+
+def batched_cpu_sample(gs, budget_s=12.0):
+    """The oracle over a spread sample of the batch's graphs (every k-th),
+    scaled to the whole batch by edges x iterations."""
+    from oracle import native
+    G = len(gs)
+    t0 = time.perf_counter()
+    done, em = 0, 0
+    for k in list(range(0, G, 16)) + list(range(8, G, 16)):
+        if time.perf_counter() - t0 > budget_s:
+            break
+        s = native.solve(gs[k].row_ptr, gs[k].col, gs[k].w, tie=False)
+        em += gs[k].m * s.iterations
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"graphs_sampled": done, "seconds": round(dt, 2), "value": em / dt,
+            "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"sequential solves of {done} of {G} graphs (every 16th first)"}
 
 
 def bench_batched(steps: int):
@@ -270,6 +381,7 @@ def bench_batched(steps: int):
     rps = [rp[int(vptr[k]):int(vptr[k + 1]) + 1] - int(eptr[k]) for k in range(len(gs))]
     plain_ms = 0.0
     agree = 0
+    cyc_all = r.cycle_edges.cpu().numpy()
     for k in range(len(gs)):
         e0, e1, v0, v1 = int(eptr[k]), int(eptr[k + 1]), int(vptr[k]), int(vptr[k + 1])
         rk = rps[k].contiguous()
@@ -280,16 +392,31 @@ def bench_batched(steps: int):
         x = ocm.min_cycle_mean(rk, ck, wk)
         torch.cuda.synchronize()
         plain_ms += (time.perf_counter() - t) * 1e3
-        agree += (x.p, x.q, x.iterations) == (r.p[k], r.q[k], r.iterations[k])
+        cyc = (cyc_all[r.cycle_ptr[k]:r.cycle_ptr[k + 1]] - int(eptr[k])).tolist()
+        agree += (x.p, x.q, x.iterations, x.cycle_edges.cpu().tolist(), x.tie) == \
+            (r.p[k], r.q[k], r.iterations[k], cyc, r.tie(k))
     its = np.array(r.iterations)
     med = float(np.median(times))
+    gold_ok = None
+    gold = os.path.join(ROOT, "tests", "golden", "batch4096.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            per = json.load(f)["per_graph"]
+        gold_ok = sum(int((r.p[k], r.q[k], r.iterations[k],
+                           (cyc_all[r.cycle_ptr[k]:r.cycle_ptr[k + 1]] - int(eptr[k])).tolist(),
+                           r.tie(k)) == (e["p"], e["q"], e["iterations"], e["cycle"],
+                                         bool(e["tie"])))
+                      for k, e in enumerate(per))
     return {"workload": "batch4096", "graphs": len(gs), "vertices": u.n, "edges": u.m,
             "batched_ms": {"median": med, "min": min(times)},
             "plain_calls_total_ms": plain_ms, "speedup_vs_plain_calls": plain_ms / med,
             "graphs_agreeing_with_plain": agree,
+            "graphs_matching_oracle_golden": gold_ok,
+            "ties_unchecked": int(sum(1 for f in r.flags if f & 2)),
             "iterations": {"min": int(its.min()), "median": float(np.median(its)),
                            "max": int(its.max()), "sum": int(its.sum())},
-            "edges_per_s_per_iter": float(sum(g.m * i for g, i in zip(gs, r.iterations)) / (med / 1e3))}
+            "edges_per_s_per_iter": float(sum(g.m * i for g, i in zip(gs, r.iterations)) / (med / 1e3)),
+            "cpu_oracle": batched_cpu_sample(gs)}
 
 
 def bench_adjoint(n_fd: int):
@@ -360,6 +487,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other single-graph workloads (rand1k, rand1m_max, rand4m_i64)")
     ap.add_argument("--fd-edges", type=int, default=1000)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy one buffer of this many MiB (a plain copy "
@@ -490,6 +619,13 @@ def main():
         out["roofline_sweep"] = roofline("sweep", *phase["sweep"])
         out["roofline_sweep"]["traffic"] = traffic_per_launch(pmc, "sweep")
         out["roofline_sweep"]["trace_avg_launch_us"] = trace_avg_us(trace, "sweep")
+    if not args.no_configs:
+        out["configs"] = {}
+        for cname in ("rand1k", "rand1m_max", "rand4m_i64"):
+            if cname == name:
+                continue
+            log(f"[bench] workload {cname} ...")
+            out["configs"][cname] = bench_config(cname, max(args.steps, 10))
     if not args.no_adjoint:
         log("[bench] adjoint workload ...")
         out["adjoint"] = bench_adjoint(args.fd_edges)

@@ -12,7 +12,8 @@
  * cycle detection in the one-successor policy graph, minimum-mean cycle
  * selection, rebuilding the policy graph around that cycle, and value
  * propagation from the cycle's smallest vertex.  All arithmetic is exact
- * (int64 values scaled by the cycle length, int128 comparisons of means), and
+ * (values scaled by the cycle length in int64, or in int128 once they leave
+ * the int64 range; int128 comparisons of means), and
  * every choice the paper leaves open is fixed deterministically:
  *   - a vertex changes policy only on strict improvement, to the lowest CSR
  *     position attaining the best value;
@@ -63,7 +64,9 @@ typedef enum {
     OCM_E_BAD_CSR = -2,                /* row_ptr not 0..m monotone, col outside [0,n) */
     OCM_E_NO_OUT_EDGE = -3,            /* a vertex without out-edges            */
     OCM_E_NOT_STRONGLY_CONNECTED = -4, /* some vertex cannot reach the chosen cycle */
-    OCM_E_OVERFLOW = -5,               /* a value would leave the int64 range   */
+    OCM_E_OVERFLOW = -5,               /* 2 n max|w| >= 2^62; or an int64 output
+                                          (potential_out, ocm_phase_values,
+                                          batched calls) cannot hold a value */
     OCM_E_CAPACITY = -6,               /* cycle_cap (or another cap) too small  */
     OCM_E_NOT_CONVERGED = -7,          /* max_iters reached with changes left   */
     OCM_E_WORKSPACE = -8,              /* workspace null or too small           */
@@ -76,7 +79,8 @@ enum { OCM_W_I32 = 0, OCM_W_I64 = 1 };
 enum {
     OCM_F_TIE = 1u,            /* another critical cycle exists (exact test)   */
     OCM_F_TIE_UNCHECKED = 2u,  /* the uniqueness test was not run              */
-    OCM_F_TIGHT_EDGES = 4u     /* some non-policy edge is tight at the optimum */
+    OCM_F_TIGHT_EDGES = 4u,    /* some non-policy edge is tight at the optimum */
+    OCM_F_INT128 = 8u          /* values were carried in int128 (see below)    */
 };
 
 typedef struct {
@@ -151,8 +155,16 @@ typedef struct {
                                   the cycle) may differ.  An entry outside its
                                   vertex's edge range gives OCM_E_INVALID_ARG. */
     int32_t *policy_out;       /* device int32[n] or NULL: final policy (edge positions) */
-    int64_t *potential_out;    /* device int64[n] or NULL: final values scaled by L */
+    int64_t *potential_out;    /* device int64[n] or NULL: final values scaled by L.
+                                  If they do not all fit int64 (OCM_F_INT128
+                                  solves only) the call fills the result and
+                                  returns OCM_E_OVERFLOW.                      */
     ocm_profile *profile;      /* host, or NULL                                */
+    int32_t int128_values;     /* 0: values in int64 until one would leave
+                                  [-2^62, 2^62], then int128 for the rest of
+                                  the solve; 1: int128 from the start.  Same
+                                  results either way (OCM_F_INT128 says which
+                                  ran).                                         */
 } ocm_options;
 
 /* Fills *o with the defaults: max_iters 0, validate 1, schedule 0,
@@ -181,6 +193,53 @@ ocm_status ocm_min(const ocm_graph *g, const ocm_options *o, void *ws,
 ocm_status ocm_max(const ocm_graph *g, const ocm_options *o, void *ws,
                    size_t ws_bytes, int32_t *cycle_edges, int64_t cycle_cap,
                    ocm_result *out, void *stream);
+
+/* Optimal cycle ratio (Section 2.2: every transition carries a cost and a
+ * time, and the ratio of a cycle is its total cost over its total time; the
+ * (v, w, t) edge record of Fig. 2).  The same policy iteration with
+ * lambda = W / T (cost and time of the chosen cycle) and edge values
+ * V[head] + T * w - W * t; the cycle mean is the case t = 1.
+ *   t        device int32[m]: the time of each edge (CSR order), >= 1, so
+ *            every cycle has positive time (OCM_E_INVALID_ARG otherwise);
+ *   out      p/q = the optimal ratio in lowest terms; W and L are the
+ *            critical cycle's cost and time; cycle_len its number of edges.
+ * Values stay exact under 2 n max|w| max t < 2^62 (OCM_E_OVERFLOW beyond);
+ * the workspace is ocm_workspace_size's.  Other arguments as ocm_min.
+ * ocm_ratio_max is the maximum: minus the minimum over negated costs. */
+ocm_status ocm_ratio_min(const ocm_graph *g, const int32_t *t, const ocm_options *o, void *ws,
+                         size_t ws_bytes, int32_t *cycle_edges, int64_t cycle_cap,
+                         ocm_result *out, void *stream);
+ocm_status ocm_ratio_max(const ocm_graph *g, const int32_t *t, const ocm_options *o, void *ws,
+                         size_t ws_bytes, int32_t *cycle_edges, int64_t cycle_cap,
+                         ocm_result *out, void *stream);
+
+/* Graphs that are not strongly connected (Prop. 2.2; Section 2.5 names the
+ * decomposition into strongly connected components as the alternative to
+ * augmenting the graph with a Hamiltonian cycle).  Every cycle lies inside
+ * one component, so the optimum is the best optimum among the components
+ * that hold a cycle.  The components are found on the device; those holding
+ * a cycle (two or more vertices, or a self-loop) are solved together as a
+ * batch (concurrent regions, Section 3.3).
+ *   - vertices may have no out-edge; the graph must hold a cycle
+ *     (OCM_E_NOT_STRONGLY_CONNECTED otherwise);
+ *   - each component is solved with the rules of ocm_min on its own
+ *     vertices, numbered in increasing original index, and its own edges in
+ *     original CSR order; the result comes from the best component, ties to
+ *     the one with the smallest vertex index;
+ *   - out: p/q, W, L, the cycle (original CSR positions, from its smallest
+ *     vertex), source (original vertex), iterations and flags of that
+ *     component's solve; OCM_F_TIE also when another component reaches the
+ *     same optimum; tight_edges = -1 (not counted);
+ *   - *components (may be NULL): the number of components holding a cycle;
+ *   - ws: ocm_general_workspace_size(g) bytes; o->init_policy, policy_out,
+ *     potential_out and profile must be NULL. */
+size_t ocm_general_workspace_size(const ocm_graph *g);
+ocm_status ocm_min_general(const ocm_graph *g, const ocm_options *o, void *ws, size_t ws_bytes,
+                           int32_t *cycle_edges, int64_t cycle_cap, ocm_result *out,
+                           int64_t *components, void *stream);
+ocm_status ocm_max_general(const ocm_graph *g, const ocm_options *o, void *ws, size_t ws_bytes,
+                           int32_t *cycle_edges, int64_t cycle_cap, ocm_result *out,
+                           int64_t *components, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): ocm_min

@@ -37,6 +37,7 @@ constexpr int kDone = 0;      // converged or failed
 constexpr int kActive = 1;    // next: a sweep
 constexpr int kFast = 2;      // next: values with the old cycle (fast path)
 constexpr int kGeneral = 3;   // next: cycles, select, rebuild, values
+constexpr int kTieList = 4;   // after the loop: tie left open by the quick tests
 
 struct GArrays {              // device arrays with one entry per graph
     long long* W;
@@ -71,6 +72,8 @@ struct BCtl {
     unsigned nspans;           // rebuild: spans holding a rebuilt graph
     unsigned ncyc;
     unsigned overflow;
+    unsigned xcnt;             // tie test: tight non-policy edges listed
+    unsigned scnt;             // tie test: special vertices
 };
 
 __device__ __forceinline__ bool chunk_range(const int2* __restrict__ chunks, const unsigned* nch,
@@ -176,7 +179,9 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
                                                const long long* __restrict__ V,
                                                int* __restrict__ pi,
                                                const unsigned char* __restrict__ onC,
-                                               const int* __restrict__ hop)
+                                               const int* __restrict__ hop,
+                                               int* __restrict__ xs, int* __restrict__ ys,
+                                               unsigned* xcnt, unsigned xcap)
 {
     constexpr int VPB = kWG / G;
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
@@ -207,6 +212,13 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
                         cnt++;
                         if (col[e] == v || onC[v]) certain++;
                         if (hop[col[e]] >= hop[v]) nondec++;
+                        if (xs) {   // list the tight non-policy edge (tie test)
+                            const unsigned slot = atomicAdd(xcnt, 1u);
+                            if (slot < xcap) {
+                                xs[slot] = (int)v;
+                                ys[slot] = col[e];
+                            }
+                        }
                     }
                 } else if (key < best) {
                     best = key;
@@ -828,6 +840,22 @@ __global__ __launch_bounds__(kWG) void k_fast_to_general(int G, GArrays ga)
         if (ga.mode[g] == kFast) ga.mode[g] = kGeneral;
 }
 
+// One graph of the union as a graph of its own: offsets, targets and policy
+// rebased to local numbering (weights are used in place).
+__global__ __launch_bounds__(kWG) void k_rebase(int n, int m, const int* __restrict__ row_ptr,
+                                                const int* __restrict__ col,
+                                                const int* __restrict__ pi, int voff, int eoff,
+                                                int* __restrict__ rp_out, int* __restrict__ col_out,
+                                                int* __restrict__ pi_out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i <= (int64_t)m;
+         i += (int64_t)gridDim.x * kWG) {
+        if (i <= n) rp_out[i] = row_ptr[i] - eoff;
+        if (i < n) pi_out[i] = pi[i] - eoff;
+        if (i < m) col_out[i] = col[i] - voff;
+    }
+}
+
 __global__ __launch_bounds__(kWG) void k_tie_init(int G, GArrays ga)
 {
     for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
@@ -900,10 +928,21 @@ struct BWs {
     int* spans;
     unsigned* bad;
     void* vctl;          // control block of the validation kernel
+    void* sub;           // exact tie test of one graph: its rebased CSR, policy and
+    size_t sub_bytes;    //   single-graph workspace (sized for the largest graph)
     size_t total;
 };
 
-BWs bcarve(void* base, int64_t G, int64_t n, int64_t m)
+// Bytes to solve the largest graph of the batch on its own (rebased CSR and
+// policy, then ocm_min's workspace).
+size_t sub_bytes_for(int64_t max_n, int64_t max_m)
+{
+    ocm_graph g{max_n, max_m, (const int32_t*)16, (const int32_t*)16, (const void*)16, OCM_W_I64};
+    const size_t ws = ocm_workspace_size(&g, nullptr);
+    return ws + 4 * (size_t)(max_n + 1) + 4 * (size_t)max_m + 8 * (size_t)max_n + 4 * 256;
+}
+
+BWs bcarve(void* base, int64_t G, int64_t n, int64_t m, size_t sub_bytes)
 {
     const int T = ocm::b::kMinChunk;
     char* b = (char*)base;
@@ -968,9 +1007,23 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m)
     w.spans = (int*)take(4 * nsp);
     w.bad = (unsigned*)take(256);
     w.vctl = take(sizeof(ocm::Ctl));
+    w.sub = take(sub_bytes);
+    w.sub_bytes = sub_bytes;
     w.total = off;
     return w;
 }
+
+}  // namespace
+
+// Workspace of a batched call with G graphs over n vertices and m edges
+// whose largest graph has at most max_n vertices and max_m edges (an upper
+// bound of ocm_batched_workspace_size for every such batch).
+size_t ocm::batched_ws_bound(int64_t G, int64_t n, int64_t m, int64_t max_n, int64_t max_m)
+{
+    return bcarve(nullptr, G, n, m, sub_bytes_for(max_n, max_m)).total;
+}
+
+namespace {
 
 // The batch schedule: lanes per vertex in the sweeps and vertices per chunk.
 struct Schedule {
@@ -1043,7 +1096,8 @@ ocm_status build_chunks(BCtx& c, int want, unsigned* nch_out)
 }
 
 template <typename WT>
-void launch_bsweep_t(BCtx& c, unsigned nch, bool tie)
+void launch_bsweep_t(BCtx& c, unsigned nch, bool tie, int* xs, int* ys, unsigned* xcnt,
+                     unsigned xcap)
 {
     const WT* w = (const WT*)c.w;
     BWs& ws = c.ws;
@@ -1053,11 +1107,11 @@ void launch_bsweep_t(BCtx& c, unsigned nch, bool tie)
         if (tie)                                                                                 \
             ocm::b::k_sweep<GG, WT, true><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(                            \
                 ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,   \
-                ws.onC, ws.hop);                                                                 \
+                ws.onC, ws.hop, xs, ys, xcnt, xcap);                                             \
         else                                                                                     \
             ocm::b::k_sweep<GG, WT, false><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(                           \
                 ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,   \
-                ws.onC, ws.hop);                                                                 \
+                ws.onC, ws.hop, nullptr, nullptr, nullptr, 0u);                                  \
         break;
     switch (c.sch.lanes) {
         OCM_BSW(1)
@@ -1072,11 +1126,14 @@ void launch_bsweep_t(BCtx& c, unsigned nch, bool tie)
 #undef OCM_BSW
 }
 
-void launch_bsweep(BCtx& c, unsigned nch, bool tie)
+// xs / ys / xcnt (tie scans only, may be null): list the tight non-policy
+// edges, at most xcap of them (xcnt counts all).
+void launch_bsweep(BCtx& c, unsigned nch, bool tie, int* xs = nullptr, int* ys = nullptr,
+                   unsigned* xcnt = nullptr, unsigned xcap = 0)
 {
     if (nch == 0) return;
-    if (c.wtype == OCM_W_I64) launch_bsweep_t<long long>(c, nch, tie);
-    else launch_bsweep_t<int>(c, nch, tie);
+    if (c.wtype == OCM_W_I64) launch_bsweep_t<long long>(c, nch, tie, xs, ys, xcnt, xcap);
+    else launch_bsweep_t<int>(c, nch, tie, xs, ys, xcnt, xcap);
 }
 
 template <typename WT>
@@ -1407,6 +1464,17 @@ long long bgcd(long long a, long long b)
     return a;
 }
 
+// Size of the largest graph's own solve (see sub_bytes_for).
+size_t batch_sub_bytes(int64_t G, const int64_t* vptr, const int64_t* eptr)
+{
+    int64_t mn = 1, mm = 1;
+    for (int64_t g = 0; g < G; ++g) {
+        mn = std::max<int64_t>(mn, vptr[g + 1] - vptr[g]);
+        mm = std::max<int64_t>(mm, eptr[g + 1] - eptr[g]);
+    }
+    return sub_bytes_for(mn, mm);
+}
+
 ocm_status check_batch(int64_t G, const int64_t* vptr, const int64_t* eptr, const ocm_graph* u)
 {
     if (G < 1 || !vptr || !eptr || !u) return bfail(OCM_E_INVALID_ARG, "null argument or G < 1");
@@ -1419,6 +1487,145 @@ ocm_status check_batch(int64_t G, const int64_t* vptr, const int64_t* eptr, cons
     for (int64_t g = 0; g < G; ++g)
         if (vptr[g + 1] <= vptr[g] || eptr[g + 1] <= eptr[g])
             return bfail(OCM_E_BAD_CSR, "every graph needs at least one vertex and edge");
+    return OCM_OK;
+}
+
+// Exact uniqueness of the critical cycles of every graph flagged
+// OCM_F_TIE_UNCHECKED, together: their tight non-policy edges are listed by
+// one more tie scan over their chunks, each endpoint becomes a special vertex
+// that learns the next special vertex (or its graph's C) on its policy path,
+// and the host looks for cycles in that small graph (one node c*_g per
+// graph; no edge joins two graphs, so a cycle decides its own graph).
+// *listed = false when the edges do not fit the list (nothing decided).
+ocm_status union_tie(BCtx& c, const int64_t* vptr, uint32_t* flags, bool* listed)
+{
+    BWs& ws = c.ws;
+    GArrays& a = ws.ga;
+    const int64_t G = c.G;
+    *listed = false;
+    std::vector<int> mode(G, ocm::b::kDone);
+    for (int64_t g = 0; g < G; ++g)
+        if (flags[g] & OCM_F_TIE_UNCHECKED) mode[g] = ocm::b::kTieList;
+    BHIP(hipMemcpyAsync(a.mode, mode.data(), 4 * (size_t)G, hipMemcpyHostToDevice, c.st));
+    // lists in the (now free) jump buffers
+    const unsigned xcap = (unsigned)std::min<int64_t>(int64_t(1) << 20, 2 * (int64_t)c.n);
+    int* xs = (int*)ws.Q[0];
+    int* ys = xs + xcap;
+    ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->xcnt, &ws.bc->scnt);
+    unsigned nch = 0;
+    BTRY(build_chunks(c, ocm::b::kTieList, &nch));
+    launch_bsweep(c, nch, true, xs, ys, &ws.bc->xcnt, xcap);
+    BHIP(hipGetLastError());
+    BTRY(bread(c));
+    const unsigned kx = c.h.xcnt;
+    if (kx > xcap) return OCM_OK;
+    // special vertices: endpoints of the listed edges (marks, rep, heads and
+    // lcnt are free after the loop)
+    unsigned char* sp = ws.marks;
+    int* spid = ws.rep;
+    int* slist = (int*)ws.heads;
+    int* P = (int*)ws.lcnt;
+    ocm::launch_tie_special(c.n, kx, xs, ys, ws.succ, ws.onC, sp, spid, slist, &ws.bc->scnt, c.st);
+    BHIP(hipGetLastError());
+    BTRY(bread(c));
+    const unsigned ns = c.h.scnt;
+    std::vector<int> hx(kx), hy(kx), hs(ns), hp(ns);
+    if (kx) {
+        BHIP(hipMemcpyAsync(hx.data(), xs, 4 * (size_t)kx, hipMemcpyDeviceToHost, c.st));
+        BHIP(hipMemcpyAsync(hy.data(), ys, 4 * (size_t)kx, hipMemcpyDeviceToHost, c.st));
+    }
+    // the walk's own endpoint conversion is not used (xs / ys stay vertices)
+    ocm::launch_tie_walk(c.n, ns, slist, ws.succ, sp, ws.onC, spid, P, 0, nullptr, nullptr, c.st);
+    if (ns) {
+        BHIP(hipMemcpyAsync(hs.data(), slist, 4 * (size_t)ns, hipMemcpyDeviceToHost, c.st));
+        BHIP(hipMemcpyAsync(hp.data(), P, 4 * (size_t)ns, hipMemcpyDeviceToHost, c.st));
+    }
+    BHIP(hipStreamSynchronize(c.st));
+    auto graph_of = [&](int v) {
+        return (int64_t)(std::upper_bound(vptr, vptr + G + 1, (int64_t)v) - vptr) - 1;
+    };
+    std::map<int, int> id;   // special vertex -> index
+    for (unsigned i = 0; i < ns; ++i) id[hs[i]] = (int)i;
+    // nodes: special vertices 0..ns-1 (one on C stands for its graph's c*),
+    // then c*_g = ns + g
+    auto node = [&](int v) -> int64_t {
+        const auto it = id.find(v);
+        if (it == id.end()) return -1;
+        const int i = it->second;
+        return hp[i] == -2 ? (int64_t)ns + graph_of(v) : (int64_t)i;
+    };
+    const int64_t N = (int64_t)ns + G;
+    std::vector<std::vector<int64_t>> adj(N);
+    for (unsigned i = 0; i < ns; ++i) {
+        if (hp[i] == -2) continue;
+        if (hp[i] == -3) return bfail(OCM_E_HIP, "policy path does not reach the critical cycle");
+        adj[i].push_back(hp[i] == -1 ? (int64_t)ns + graph_of(hs[i]) : node(hs[hp[i]]));
+    }
+    for (unsigned i = 0; i < kx; ++i) {
+        const int64_t x = node(hx[i]), y = node(hy[i]);
+        if (x < 0 || y < 0) return bfail(OCM_E_HIP, "tie list endpoint without a special index");
+        adj[x].push_back(y);
+    }
+    // three-colour depth-first search; a back edge marks its graph
+    std::vector<unsigned char> colr(N, 0);
+    std::vector<unsigned char> tie(G, 0);
+    std::vector<std::pair<int64_t, size_t>> st;
+    auto graph_of_node = [&](int64_t x) { return x >= (int64_t)ns ? x - (int64_t)ns : graph_of(hs[x]); };
+    for (int64_t r = 0; r < N; ++r) {
+        if (colr[r]) continue;
+        colr[r] = 1;
+        st.push_back({r, 0});
+        while (!st.empty()) {
+            auto& top = st.back();
+            if (top.second == adj[top.first].size()) {
+                colr[top.first] = 2;
+                st.pop_back();
+                continue;
+            }
+            const int64_t u = adj[top.first][top.second++];
+            if (colr[u] == 1) tie[graph_of_node(u)] = 1;
+            else if (colr[u] == 0) {
+                colr[u] = 1;
+                st.push_back({u, 0});
+            }
+        }
+    }
+    for (int64_t g = 0; g < G; ++g)
+        if (flags[g] & OCM_F_TIE_UNCHECKED)
+            flags[g] = (flags[g] & ~(uint32_t)OCM_F_TIE_UNCHECKED) | (tie[g] ? OCM_F_TIE : 0u);
+    *listed = true;
+    return OCM_OK;
+}
+
+// Exact uniqueness of graph g's critical cycle: graph g rebased into the
+// workspace's sub region and solved alone from its final policy; *f gets
+// that solve's OCM_F_TIE / OCM_F_TIE_UNCHECKED.
+ocm_status exact_tie(BCtx& c, int64_t g, const int64_t* vptr, const int64_t* eptr, long long W,
+                     long long L, uint32_t* f)
+{
+    const int64_t v0 = vptr[g], e0 = eptr[g];
+    const int n = (int)(vptr[g + 1] - v0), m = (int)(eptr[g + 1] - e0);
+    char* b = (char*)c.ws.sub;
+    int* rp = (int*)b;
+    int* cl = (int*)(b + bal(4 * (size_t)(n + 1)));
+    int* pol = (int*)((char*)cl + bal(4 * (size_t)m));
+    int32_t* cyc = (int32_t*)((char*)pol + bal(4 * (size_t)n));
+    char* ws = (char*)cyc + bal(4 * (size_t)n);
+    const size_t ws_bytes = c.ws.sub_bytes - (size_t)(ws - b);
+    ocm::b::k_rebase<<<ocm::stride_grid(m + 1), ocm::kWG, 0, c.st>>>(
+        n, m, c.row_ptr + v0, c.col + e0, c.ws.pi + v0, (int)v0, (int)e0, rp, cl, pol);
+    BHIP(hipGetLastError());
+    ocm_graph sg{n, m, rp, cl, (const char*)c.w + (size_t)c.sw * (size_t)e0, c.wtype};
+    ocm_options o;
+    ocm_default_options(&o);
+    o.validate = 0;
+    o.init_policy = pol;
+    ocm_result r;
+    const ocm_status rc = (c.neg ? ocm_max : ocm_min)(&sg, &o, ws, ws_bytes, cyc, n, &r, c.st);
+    if (rc != OCM_OK) return rc;
+    // the same optimum (W, L), from the same policy
+    if (r.W != (c.neg ? -W : W) || r.L != L) return bfail(OCM_E_HIP, "tie test solved another optimum");
+    *f = r.flags & (OCM_F_TIE | OCM_F_TIE_UNCHECKED);
     return OCM_OK;
 }
 
@@ -1453,9 +1660,10 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
           c.sch.lanes == 16 || c.sch.lanes == 32 || c.sch.lanes == 64))
         return bfail(OCM_E_INVALID_ARG, "schedule must be a power of two <= 64");
     for (int64_t g = 0; g < G; ++g) c.max_n = (int)std::max<int64_t>(c.max_n, vptr[g + 1] - vptr[g]);
-    c.ws = bcarve(nullptr, G, u->n, u->m);
+    const size_t sub = batch_sub_bytes(G, vptr, eptr);
+    c.ws = bcarve(nullptr, G, u->n, u->m, sub);
     if (!wsp || ws_bytes < c.ws.total) return bfail(OCM_E_WORKSPACE, "workspace missing or too small");
-    c.ws = bcarve(wsp, G, u->n, u->m);
+    c.ws = bcarve(wsp, G, u->n, u->m, sub);
     BWs& ws = c.ws;
     GArrays& a = ws.ga;
 
@@ -1575,6 +1783,21 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
                 if (hc[g]) flags[g] |= OCM_F_TIE;
                 else if (hn[g]) flags[g] |= OCM_F_TIE_UNCHECKED;
             }
+            // graphs the quick tests left open: the special-vertex test over
+            // all of them at once; if their tight edges do not fit the list,
+            // each is solved again on its own (warm started from its final
+            // policy), whose full test decides
+            bool open = false;
+            for (int64_t g = 0; g < G; ++g) open |= (flags[g] & OCM_F_TIE_UNCHECKED) != 0;
+            bool listed = false;
+            if (open) BTRY(union_tie(c, vptr, flags, &listed));
+            if (open && !listed)
+                for (int64_t g = 0; g < G; ++g)
+                    if (flags[g] & OCM_F_TIE_UNCHECKED) {
+                        uint32_t f = 0;
+                        BTRY(exact_tie(c, g, vptr, eptr, hW[g], hL[g], &f));
+                        flags[g] = (flags[g] & ~(uint32_t)OCM_F_TIE_UNCHECKED) | f;
+                    }
         } else {
             for (int64_t g = 0; g < G; ++g) flags[g] |= OCM_F_TIE_UNCHECKED;
         }
@@ -1594,7 +1817,7 @@ size_t ocm_batched_workspace_size(int64_t G, const int64_t* vptr, const int64_t*
 {
     (void)o;
     if (check_batch(G, vptr, eptr, u) != OCM_OK) return 0;
-    return bcarve(nullptr, G, u->n, u->m).total;
+    return bcarve(nullptr, G, u->n, u->m, batch_sub_bytes(G, vptr, eptr)).total;
 }
 
 ocm_status ocm_min_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, const ocm_graph* u,

@@ -143,6 +143,38 @@ __device__ __forceinline__ unsigned wave_incl_scan(unsigned x)
     return x;
 }
 
+// Values of the int128 fallback live in two int64 arrays, lo and hi:
+// value = hi * 2^64 + (unsigned) lo.  ValT<false> is the plain int64 value.
+template <bool WIDE>
+struct ValT {
+    using type = long long;
+};
+template <>
+struct ValT<true> {
+    using type = __int128;
+};
+
+template <bool WIDE>
+__device__ __forceinline__ typename ValT<WIDE>::type load_val(const long long* __restrict__ lo,
+                                                              const long long* __restrict__ hi,
+                                                              int64_t i)
+{
+    if constexpr (WIDE)
+        return (__int128)(((unsigned __int128)(unsigned long long)hi[i] << 64) |
+                          (unsigned long long)lo[i]);
+    else
+        return lo[i];
+}
+
+template <typename KT>
+__device__ __forceinline__ KT val_max()
+{
+    if constexpr (sizeof(KT) == 16)
+        return (KT)(~((unsigned __int128)1 << 127));
+    else
+        return (KT)INT64_MAX;
+}
+
 // |x| as unsigned, defined for INT64_MIN too.
 __device__ __forceinline__ unsigned long long uabs64(int64_t x)
 {

@@ -72,6 +72,7 @@ struct alignas(128) Ctl {
     unsigned jgate;                //   values: 0 = the queued value phase is skipped
     unsigned xcnt;                 // tie scan: tight non-policy edges listed
     unsigned scnt;                 // tie check: special vertices
+    unsigned clen;                 // select: edges of the chosen cycle (its L for a mean)
     CtlLane lane[kLanes];
 };
 
@@ -82,7 +83,7 @@ struct CtlView {
     unsigned ncyc;
     unsigned rmode, rleft, rfront, rerr, rk;
     unsigned jk, jmode, jlast, jstall;
-    unsigned xcnt, scnt;
+    unsigned xcnt, scnt, clen;
     unsigned long long changed, tight, certain, nondec, pedges, ledges, maxabsw;
     unsigned active, active2, got, left, err, cbroken, overflow, bad;
     unsigned pjc[4];
@@ -105,6 +106,7 @@ __host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
     v.jstall = c.jstall;
     v.xcnt = c.xcnt;
     v.scnt = c.scnt;
+    v.clen = c.clen;
     v.changed = v.tight = v.certain = v.nondec = v.pedges = v.ledges = v.maxabsw = 0;
     v.active = v.active2 = v.got = v.left = v.err = v.cbroken = v.overflow = v.bad = 0;
     for (int j = 0; j < 4; ++j) v.pjc[j] = 0;
@@ -152,6 +154,8 @@ struct SweepArgs {
     const int* row_ptr;
     const int* col;
     const long long* V;
+    const long long* Vhi;          // int128 values: high words of V (else null)
+    const int* t;                  // cycle ratio: edge times (else null: the mean)
     long long W, L;
     int* pi;
     int* succ;                     // optional: col[pi] kept up to date where pi changes
@@ -200,20 +204,31 @@ void launch_pj_round_dev(int n, int r, const unsigned long long* Pin, unsigned l
                          const unsigned char* tprev, unsigned char* tcur, Ctl* ctl, hipStream_t st);
 void launch_pj_final_dev(int n, const unsigned long long* P0, const unsigned long long* P1, int K,
                          int* rep, unsigned char* onc, const Ctl* ctl, hipStream_t st);
+// int128 values (hin/hout, h0/h1 non-null): the entries' high words live in
+// parallel arrays and Vhi receives the values' high words.
 void launch_val_round_dev(int n, int s, int r, const Jmp* Qin, Jmp* Qout, Ctl* ctl,
-                          hipStream_t st);
+                          hipStream_t st, const long long* hin = nullptr,
+                          long long* hout = nullptr);
 void launch_val_final_dev(int n, const Jmp* Q0, const Jmp* Q1, long long* V, int* hop, Ctl* ctl,
-                          hipStream_t st);
+                          hipStream_t st, const long long* h0 = nullptr,
+                          const long long* h1 = nullptr, long long* Vhi = nullptr);
 void launch_pj_final(int n, const unsigned long long* P, int* rep, unsigned char* onc,
                      hipStream_t st);
+// Cycle ratio (t non-null): tsum receives each cycle's time, and the order
+// is cost over time; ctl->clen gets the chosen cycle's edge count.
 void launch_cyc_zero(int n, const int* rep, const unsigned char* onc, long long* wsum,
-                     unsigned* lcnt, int* cyc_list, Ctl* ctl, hipStream_t st);
+                     unsigned* lcnt, int* cyc_list, Ctl* ctl, hipStream_t st,
+                     long long* tsum = nullptr);
 void launch_cyc_sum(int n, const int* rep, const unsigned char* onc, const int* pi, const void* w,
-                    int wtype, int neg, long long* wsum, unsigned* lcnt, hipStream_t st);
+                    int wtype, int neg, long long* wsum, unsigned* lcnt, hipStream_t st,
+                    const int* t = nullptr, long long* tsum = nullptr);
 // scratch: kSelectParts * 32 bytes of device memory
 constexpr int kSelectParts = 512;
 void launch_select(const int* cyc_list, const long long* wsum, const unsigned* lcnt, Ctl* ctl,
-                   void* scratch, hipStream_t st);
+                   void* scratch, hipStream_t st, const long long* tsum = nullptr);
+// Edge times of a cycle ratio: lane bad |= some t < 1, lane maxabsw = max t
+// (the caller clears both first).
+void launch_validate_t(int m, const int* t, Ctl* ctl, hipStream_t st);
 // Rebuild (breadth-first attachment to C's component); layer (the round that
 // attached each vertex) may be null.  a[0], a[1]: the two
 // attached-vertex bitmaps (ceil(n/32) words each); marks: push-round mark
@@ -273,11 +288,19 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
                       hipStream_t st);
 // gate (nullable): the init does nothing while *gate is 0.  have_succ: succ
 // already holds col[pi]; otherwise it is written.
+// Dhi (nullable): int128 entries, whose high words start sign-extended.
+// t (nullable): cycle ratio, the entries start at L * w - W * t.
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
                      int s, long long W, long long L, int* succ, bool have_succ, Jmp* Q, Ctl* ctl,
-                     const unsigned* gate, hipStream_t st);
-void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st);
-void launch_val_final(int n, const Jmp* Q, long long* V, int* hop, Ctl* ctl, hipStream_t st);
+                     const unsigned* gate, hipStream_t st, long long* Dhi = nullptr,
+                     const int* t = nullptr);
+void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st,
+                      const long long* hin = nullptr, long long* hout = nullptr);
+void launch_val_final(int n, const Jmp* Q, long long* V, int* hop, Ctl* ctl, hipStream_t st,
+                      const long long* hin = nullptr, long long* Vhi = nullptr);
+// *bad |= some int128 value (lo, hi) does not fit int64.
+void launch_fits64(int n, const long long* lo, const long long* hi, unsigned* bad,
+                   hipStream_t st);
 void launch_cycle_list(int n, int s, long long L, const unsigned char* onC, const int* pi,
                        const int* hop, int* out, hipStream_t st);
 void launch_tie_short_walk(const SweepArgs& a, const void* w, int wtype, int G, const int* succ,
@@ -298,6 +321,10 @@ hipError_t host_read_ctl(const Ctl* ctl, CtlView* out, hipStream_t st);
 // synchronisation: no pinned mailbox is created (used by the entry point
 // that allocates nothing).
 hipError_t host_read_ctl_copy(const Ctl* ctl, CtlView* out, hipStream_t st);
+
+// Upper bound of the batched workspace for G graphs over n vertices and m
+// edges, the largest graph at most max_n vertices and max_m edges.
+size_t batched_ws_bound(int64_t G, int64_t n, int64_t m, int64_t max_n, int64_t max_m);
 
 // thread-local message returned by ocm_last_error()
 void set_last_error(const char* what);

@@ -184,21 +184,24 @@ __global__ __launch_bounds__(kWG) void k_sweep_u(SweepArgs a, const WT* __restri
 // loads per batch instead of per vertex step; same result as k_sweep_u.
 constexpr int kTileEdges = 2048;
 
-template <typename WT, bool FIRST>
+// WIDE: int128 values (lo in a.V, hi in a.Vhi), keys compared in int128.
+// RATIO: cycle ratio, the key is V[head] + L * w - W * t (a.t: edge times).
+template <typename WT, bool FIRST, bool WIDE = false, bool RATIO = false>
 __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __restrict__ w)
 {
+    using KT = typename ValT<WIDE>::type;
     __shared__ int beg[kWG + 1];
-    __shared__ long long key[kTileEdges];
+    __shared__ KT key[kTileEdges];
     const int64_t L = FIRST ? 1 : a.L;
     const int64_t W = FIRST ? 0 : a.W;
     const int64_t v0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWG;
     const int nv = a.n - v0 < kWG ? (int)(a.n - v0) : kWG;
     const int t = threadIdx.x;
-    long long own = 0, best = INT64_MAX;
+    KT own = 0, best = val_max<KT>();
     int pos = INT32_MAX;
     if (t < nv) {
         beg[t] = a.row_ptr[v0 + t];
-        if (!FIRST) own = a.V[v0 + t];
+        if (!FIRST) own = load_val<WIDE>(a.V, a.Vhi, v0 + t);
     }
     if (t == 0) beg[nv] = a.row_ptr[v0 + nv];
     __syncthreads();
@@ -215,28 +218,32 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
             }
         } else {
             int c[U];
-            long long wl[U];
+            long long wl[U], tl[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = t + u * kWG;
                 c[u] = 0;
                 wl[u] = 0;
+                tl[u] = 1;
                 if (j < cnt) {
                     c[u] = a.col[eb + j];
                     wl[u] = wval(w, eb + j, a.neg);
+                    if (RATIO) tl[u] = a.t[eb + j];
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = t + u * kWG;
-                if (j < cnt) key[j] = a.V[c[u]] + L * wl[u] - W;
+                if (j < cnt)
+                    key[j] = load_val<WIDE>(a.V, a.Vhi, c[u]) +
+                             (KT)(L * wl[u] - (RATIO ? W * tl[u] : W));
             }
         }
         __syncthreads();
         // this vertex's edges inside the batch, in CSR order
         const int lo = mb > eb ? mb : eb, hi = me < eb + cnt ? me : eb + cnt;
         for (int e = lo; e < hi; ++e) {
-            const long long k = key[e - eb];
+            const KT k = key[e - eb];
             if (k < best) {
                 best = k;
                 pos = e;
@@ -272,22 +279,23 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
 // 1536 keeps 8 workgroups per CU (measured 13 % faster than 2048 here).
 constexpr int kTieTileEdges = 1536;
 
-template <typename WT, bool SWEEP>
+template <typename WT, bool SWEEP, bool WIDE = false, bool RATIO = false>
 __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __restrict__ w)
 {
+    using KT = typename ValT<WIDE>::type;
     __shared__ int beg[kWG + 1];
-    __shared__ long long key[kTieTileEdges];
+    __shared__ KT key[kTieTileEdges];
     __shared__ int head[kTieTileEdges];
     const int64_t L = a.L, W = a.W;
     const int64_t v0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWG;
     const int nv = a.n - v0 < kWG ? (int)(a.n - v0) : kWG;
     const int t = threadIdx.x;
-    long long own = 0;
+    KT own = 0;
     int cur = -1, hv = 0;
     bool onc = false;
     if (t < nv) {
         beg[t] = a.row_ptr[v0 + t];
-        own = a.V[v0 + t];
+        own = load_val<WIDE>(a.V, a.Vhi, v0 + t);
         cur = a.pi[v0 + t];
         if (a.hop) hv = a.hop[v0 + t];
         onc = a.onC && a.onC[v0 + t];
@@ -297,35 +305,38 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
     const int e0 = beg[0], e1 = beg[nv];
     const int mb = t < nv ? beg[t] : 0, me = t < nv ? beg[t + 1] : 0;
     unsigned long long cnt = 0, certain = 0, nondec = 0;
-    long long best = INT64_MAX;
+    KT best = val_max<KT>();
     int pos = INT32_MAX, bhead = 0;
     constexpr int U = kTieTileEdges / kWG;
     for (int eb = e0; eb < e1; eb += kTieTileEdges) {
         const int n_e = e1 - eb < kTieTileEdges ? e1 - eb : kTieTileEdges;
         int c[U];
-        long long wl[U];
+        long long wl[U], tl[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = t + u * kWG;
             c[u] = 0;
             wl[u] = 0;
+            tl[u] = 1;
             if (j < n_e) {
                 c[u] = a.col[eb + j];
                 wl[u] = wval(w, eb + j, a.neg);
+                if (RATIO) tl[u] = a.t[eb + j];
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = t + u * kWG;
             if (j < n_e) {
-                key[j] = a.V[c[u]] + L * wl[u] - W;
+                key[j] = load_val<WIDE>(a.V, a.Vhi, c[u]) +
+                         (KT)(L * wl[u] - (RATIO ? W * tl[u] : W));
                 head[j] = c[u];
             }
         }
         __syncthreads();
         const int lo = mb > eb ? mb : eb, hi = me < eb + n_e ? me : eb + n_e;
         for (int e = lo; e < hi; ++e) {
-            const long long k = key[e - eb];
+            const KT k = key[e - eb];
             const int h = head[e - eb];
             if (SWEEP && k < best) {
                 best = k;
@@ -627,7 +638,8 @@ __global__ __launch_bounds__(kWG) void k_cyc_zero(int n, const int* __restrict__
                                                   const unsigned char* __restrict__ onc,
                                                   unsigned per, long long* __restrict__ wsum,
                                                   unsigned* __restrict__ lcnt,
-                                                  int* __restrict__ cyc_list, Ctl* ctl)
+                                                  int* __restrict__ cyc_list, Ctl* ctl,
+                                                  long long* __restrict__ tsum)
 {
     __shared__ int hbuf[kListItems];
     __shared__ unsigned nh;
@@ -642,6 +654,7 @@ __global__ __launch_bounds__(kWG) void k_cyc_zero(int n, const int* __restrict__
         if (head) {
             wsum[v] = 0;
             lcnt[v] = 0;
+            if (tsum) tsum[v] = 0;
         }
         blist_push(bl, head, (int)v);
     }
@@ -654,13 +667,17 @@ __global__ __launch_bounds__(kWG) void k_cyc_sum(int n, const int* __restrict__ 
                                                  const int* __restrict__ pi,
                                                  const WT* __restrict__ w, int neg,
                                                  long long* __restrict__ wsum,
-                                                 unsigned* __restrict__ lcnt)
+                                                 unsigned* __restrict__ lcnt,
+                                                 const int* __restrict__ tm,
+                                                 long long* __restrict__ tsum)
 {
     const int v = blockIdx.x * kWG + threadIdx.x;
     if (v >= n || !onc[v]) return;
     const int r = rep[v];
-    atomicAdd((unsigned long long*)&wsum[r], (unsigned long long)wval(w, pi[v], neg));
+    const int e = pi[v];
+    atomicAdd((unsigned long long*)&wsum[r], (unsigned long long)wval(w, e, neg));
     atomicAdd(&lcnt[r], 1u);
+    if (tsum) atomicAdd((unsigned long long*)&tsum[r], (unsigned long long)tm[e]);
 }
 
 struct Cand {
@@ -704,16 +721,18 @@ __device__ __forceinline__ Cand block_best(Cand best)
     return best;
 }
 
+// tsum (cycle ratio): a cycle's denominator is its time, not its length.
 __global__ __launch_bounds__(kWG) void k_select_part(const int* __restrict__ cyc_list,
                                                      const long long* __restrict__ wsum,
                                                      const unsigned* __restrict__ lcnt,
+                                                     const long long* __restrict__ tsum,
                                                      const Ctl* ctl, Cand* __restrict__ part)
 {
     const unsigned nc = ctl->ncyc;
     Cand best{0, 1, -1};
     for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < nc; i += gridDim.x * kWG) {
         const int r = cyc_list[i];
-        const Cand c{wsum[r], (long long)lcnt[r], r};
+        const Cand c{wsum[r], tsum ? tsum[r] : (long long)lcnt[r], r};
         if (cand_less(c, best)) best = c;
     }
     best = block_best(best);
@@ -721,7 +740,7 @@ __global__ __launch_bounds__(kWG) void k_select_part(const int* __restrict__ cyc
 }
 
 __global__ __launch_bounds__(kWG) void k_select_final(const Cand* __restrict__ part, int nparts,
-                                                      Ctl* ctl)
+                                                      const unsigned* __restrict__ lcnt, Ctl* ctl)
 {
     Cand best{0, 1, -1};
     for (int i = threadIdx.x; i < nparts; i += kWG)
@@ -731,6 +750,27 @@ __global__ __launch_bounds__(kWG) void k_select_final(const Cand* __restrict__ p
         ctl->s = best.r;
         ctl->W = best.W;
         ctl->L = best.L;
+        ctl->clen = best.r >= 0 ? lcnt[best.r] : 0u;
+    }
+}
+
+// Edge times of a cycle ratio must be >= 1; their maximum bounds the values.
+__global__ __launch_bounds__(kWG) void k_validate_t(int m, const int* __restrict__ t, Ctl* ctl)
+{
+    unsigned bad = 0;
+    unsigned long long mx = 0;
+    for (int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * kWG) {
+        const int x = t[e];
+        bad |= x < 1 ? 1u : 0u;
+        mx = (unsigned long long)x > mx ? (unsigned long long)x : mx;
+    }
+    mx = block_max_u64(mx);
+    const unsigned anybad = (unsigned)block_sum_u64(bad);
+    if (threadIdx.x == 0) {
+        CtlLane& ln = my_lane(ctl);
+        if (mx) atomicMax(&ln.maxabsw, mx);
+        if (anybad) atomicOr(&ln.bad, 1u);
     }
 }
 
@@ -1748,7 +1788,8 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
                                                   long long W, long long L,
                                                   int* __restrict__ succ, int have_succ,
                                                   Jmp* __restrict__ Q, Ctl* ctl,
-                                                  const unsigned* gate)
+                                                  const unsigned* gate, long long* __restrict__ Dhi,
+                                                  const int* __restrict__ tm)
 {
     if (gate && *gate == 0u) return;   // the value phase is skipped (uniform)
     unsigned long long act = 0;
@@ -1756,7 +1797,7 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t vb = (int64_t)blockIdx.x * kWG + threadIdx.x; vb < n; vb += U * stride) {
         int e[U], t[U];
-        long long wv[U];
+        long long wv[U], tv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t v = vb + u * stride;
@@ -1767,9 +1808,11 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
             const int64_t v = vb + u * stride;
             t[u] = 0;
             wv[u] = 0;
+            tv[u] = 1;
             if (v < n) {
                 t[u] = have_succ ? succ[v] : col[e[u]];
                 wv[u] = wval(w, e[u], neg);
+                if (tm) tv[u] = tm[e[u]];
             }
         }
 #pragma unroll
@@ -1783,12 +1826,13 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
                 q.J = s;
                 q.H = 0;
             } else {
-                q.D = L * wv[u] - W;
+                q.D = L * wv[u] - W * tv[u];
                 q.J = t[u];
                 q.H = 1;
                 act += t[u] != s;
             }
             Q[v] = q;
+            if (Dhi) Dhi[v] = q.D < 0 ? -1ll : 0ll;   // int128 entries: sign-extended
         }
     }
     act = block_sum_u64(act);
@@ -1808,11 +1852,29 @@ __device__ __forceinline__ Jmp jmp_combine(Jmp q, const Jmp& r)
     return q;
 }
 
+// int128 entries: the sum's low word stays in the Jmp entry, its high word in
+// a parallel array (hin / hout); no overflow is possible (|sum| < n * 2^62).
+__device__ __forceinline__ void jmp_combine_wide(Jmp& q, long long& qh, const Jmp& r, long long rh)
+{
+    const unsigned __int128 a = ((unsigned __int128)(unsigned long long)qh << 64) |
+                                (unsigned long long)q.D;
+    const unsigned __int128 b = ((unsigned __int128)(unsigned long long)rh << 64) |
+                                (unsigned long long)r.D;
+    const unsigned __int128 d = a + b;
+    q.D = (long long)(unsigned long long)d;
+    qh = (long long)(unsigned long long)(d >> 64);
+    q.J = r.J;
+    q.H = q.H + r.H;
+}
+
 // One jump round over all entries; returns (in thread 0) the vertices still
 // unfinished after it.
+template <bool WIDE = false>
 __device__ __forceinline__ unsigned long long val_round_body(int n, int s,
                                                              const Jmp* __restrict__ Qin,
-                                                             Jmp* __restrict__ Qout)
+                                                             Jmp* __restrict__ Qout,
+                                                             const long long* __restrict__ hin = nullptr,
+                                                             long long* __restrict__ hout = nullptr)
 {
     unsigned long long act = 0;
     // grid-stride with kJumpUnroll independent entries in flight per thread
@@ -1820,44 +1882,61 @@ __device__ __forceinline__ unsigned long long val_round_body(int n, int s,
     for (int64_t v0 = (int64_t)blockIdx.x * kWG + threadIdx.x; v0 < n;
          v0 += kJumpUnroll * stride) {
         Jmp q[kJumpUnroll], r[kJumpUnroll];
+        long long qh[kJumpUnroll], rh[kJumpUnroll];
 #pragma unroll
         for (int u = 0; u < kJumpUnroll; ++u) {
             const int64_t v = v0 + u * stride;
-            if (v < n) q[u] = Qin[v];
-            else q[u].J = s;
+            qh[u] = rh[u] = 0;
+            if (v < n) {
+                q[u] = Qin[v];
+                if (WIDE) qh[u] = hin[v];
+            } else {
+                q[u].J = s;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kJumpUnroll; ++u)
-            if (q[u].J != s) r[u] = Qin[q[u].J];
+            if (q[u].J != s) {
+                r[u] = Qin[q[u].J];
+                if (WIDE) rh[u] = hin[q[u].J];
+            }
 #pragma unroll
         for (int u = 0; u < kJumpUnroll; ++u) {
             const int64_t v = v0 + u * stride;
             if (v >= n) continue;
             if (q[u].J != s) {
-                q[u] = jmp_combine(q[u], r[u]);
+                if (WIDE) jmp_combine_wide(q[u], qh[u], r[u], rh[u]);
+                else q[u] = jmp_combine(q[u], r[u]);
                 act += q[u].J != s;
             }
             Qout[v] = q[u];
+            if (WIDE) hout[v] = qh[u];
         }
     }
     return block_sum_u64(act);
 }
 
+template <bool WIDE>
 __global__ __launch_bounds__(kWG) void k_val_round(int n, int s, const Jmp* __restrict__ Qin,
-                                                   Jmp* __restrict__ Qout, unsigned* active)
+                                                   Jmp* __restrict__ Qout, unsigned* active,
+                                                   const long long* __restrict__ hin,
+                                                   long long* __restrict__ hout)
 {
-    const unsigned long long act = val_round_body(n, s, Qin, Qout);
+    const unsigned long long act = val_round_body<WIDE>(n, s, Qin, Qout, hin, hout);
     if (threadIdx.x == 0 && act) atomicAdd(my_copy(active), (unsigned)act);
 }
 
 // Device-driven round r: the last workgroup ends the rounds once no vertex
 // is unfinished, or with jstall once a round finished none.
+template <bool WIDE>
 __global__ __launch_bounds__(kWG) void k_val_round_dev(int n, int s, int r,
                                                        const Jmp* __restrict__ Qin,
-                                                       Jmp* __restrict__ Qout, Ctl* ctl)
+                                                       Jmp* __restrict__ Qout, Ctl* ctl,
+                                                       const long long* __restrict__ hin,
+                                                       long long* __restrict__ hout)
 {
     if (!jump_round_is(ctl, r)) return;
-    const unsigned long long act = val_round_body(n, s, Qin, Qout);
+    const unsigned long long act = val_round_body<WIDE>(n, s, Qin, Qout, hin, hout);
     if (threadIdx.x != 0) return;
     unsigned long long tot;
     if (!last_arrival(ctl, arrival_word(act, 0), &tot)) return;
@@ -1873,9 +1952,13 @@ __global__ __launch_bounds__(kWG) void k_val_round_dev(int n, int s, int r,
     }
 }
 
+// WIDE: V gets the low words, Vhi the high words (hin: the entries' high
+// words); int128 values cannot overflow.
+template <bool WIDE>
 __device__ __forceinline__ void val_final_body(int n, const Jmp* __restrict__ Q,
                                                long long* __restrict__ V, int* __restrict__ hop,
-                                               Ctl* ctl)
+                                               Ctl* ctl, const long long* __restrict__ hin,
+                                               long long* __restrict__ Vhi)
 {
     const int v = blockIdx.x * kWG + threadIdx.x;
     unsigned bad = 0;
@@ -1883,27 +1966,37 @@ __device__ __forceinline__ void val_final_body(int n, const Jmp* __restrict__ Q,
         const Jmp q = Q[v];
         V[v] = q.D;
         if (hop) hop[v] = (int)(q.H & ~kHopOverflow);
-        if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
+        if (WIDE) Vhi[v] = hin[v];
+        else if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
     }
-    if (__ballot(bad != 0) && (threadIdx.x & 63) == 0) atomicOr(&my_lane(ctl).overflow, 1u);
+    if (!WIDE && __ballot(bad != 0) && (threadIdx.x & 63) == 0)
+        atomicOr(&my_lane(ctl).overflow, 1u);
 }
 
+template <bool WIDE>
 __global__ __launch_bounds__(kWG) void k_val_final(int n, const Jmp* __restrict__ Q,
                                                    long long* __restrict__ V,
-                                                   int* __restrict__ hop, Ctl* ctl)
+                                                   int* __restrict__ hop, Ctl* ctl,
+                                                   const long long* __restrict__ hin,
+                                                   long long* __restrict__ Vhi)
 {
-    val_final_body(n, Q, V, hop, ctl);
+    val_final_body<WIDE>(n, Q, V, hop, ctl, hin, Vhi);
 }
 
 // Device-driven: runs once every vertex finished (not after a stall), on the
 // entries of the last round run.
+template <bool WIDE>
 __global__ __launch_bounds__(kWG) void k_val_final_dev(int n, const Jmp* __restrict__ Q0,
                                                        const Jmp* __restrict__ Q1,
                                                        long long* __restrict__ V,
-                                                       int* __restrict__ hop, Ctl* ctl)
+                                                       int* __restrict__ hop, Ctl* ctl,
+                                                       const long long* __restrict__ h0,
+                                                       const long long* __restrict__ h1,
+                                                       long long* __restrict__ Vhi)
 {
     if (ctl->jmode != 0 || ctl->jstall || !ctl->jgate) return;
-    val_final_body(n, (ctl->jk & 1) ? Q1 : Q0, V, hop, ctl);
+    const bool odd = (ctl->jk & 1) != 0;
+    val_final_body<WIDE>(n, odd ? Q1 : Q0, V, hop, ctl, odd ? h1 : h0, Vhi);
 }
 
 // Cycle C listed from the source: vertex c_j (j steps after s) is H = L - j
@@ -1924,10 +2017,11 @@ __global__ __launch_bounds__(kWG) void k_cycle_list(int n, int s, long long L,
 // nearer the source (hop[y] >= hop[x]), follow y's policy path for at most
 // kShortWalk steps; meeting x closes a cycle of tight edges other than C.
 
-template <int G, typename WT>
+template <int G, typename WT, bool WIDE = false>
 __global__ __launch_bounds__(kWG) void k_tie_short_walk(SweepArgs a, const WT* __restrict__ w,
                                                         const int* __restrict__ succ)
 {
+    using KT = typename ValT<WIDE>::type;
     constexpr int VPB = kWG / G;
     const int lane = threadIdx.x & (G - 1);
     const int64_t per = ((int64_t)a.n + gridDim.x - 1) / gridDim.x;
@@ -1938,13 +2032,15 @@ __global__ __launch_bounds__(kWG) void k_tie_short_walk(SweepArgs a, const WT* _
         const int64_t v = vb + threadIdx.x / G;
         if (v >= v1) continue;
         const int beg = a.row_ptr[v], end = a.row_ptr[v + 1];
-        const int64_t own = a.V[v];
+        const KT own = load_val<WIDE>(a.V, a.Vhi, v);
         const int cur = a.pi[v];
         for (int e = beg + lane; e < end; e += G) {
             if (e == cur) continue;
             const int y = a.col[e];
             if (a.hop[y] < a.hop[v]) continue;
-            if (a.V[y] + a.L * wval(w, e, a.neg) - a.W != own) continue;
+            const long long te = a.t ? a.t[e] : 1;
+            if (load_val<WIDE>(a.V, a.Vhi, y) + (KT)(a.L * wval(w, e, a.neg) - a.W * te) != own)
+                continue;
             int x = y;
             for (int st = 0; st < kShortWalk && x != (int)v; ++st) x = succ[x];
             found += x == (int)v;
@@ -2096,6 +2192,17 @@ __global__ __launch_bounds__(kWG) void k_check_policy(int n, const int* __restri
     if (__ballot(b != 0) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
 }
 
+// Does every int128 value (lo, hi) fit int64, i.e. is hi the sign of lo?
+__global__ __launch_bounds__(kWG) void k_fits64(int n, const long long* __restrict__ lo,
+                                                const long long* __restrict__ hi, unsigned* bad)
+{
+    unsigned b = 0;
+    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kWG)
+        b |= hi[v] != (lo[v] < 0 ? -1ll : 0ll) ? 1u : 0u;
+    if (__ballot(b != 0) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
 // Thread l < kLanes clears lane l; thread 0 also the header fields.
 __global__ void k_ctl_clear(Ctl* ctl, unsigned what)
 {
@@ -2120,6 +2227,7 @@ __global__ void k_ctl_clear(Ctl* ctl, unsigned what)
             ln.active2 = 0;
             ln.got = 0;
             ln.left = 0;
+            ln.overflow = 0;
         }
         if (what & kClrActive2) ln.active2 = 0;
     }
@@ -2207,9 +2315,39 @@ void launch_validate(int n, int m, const int* row_ptr, const int* col, const voi
         k_validate<int><<<grid, kWG, 0, st>>>(n, m, row_ptr, col, (const int*)w, check_csr, ctl);
 }
 
+// Sweeps after the first with int128 values or edge times: always over
+// vertex tiles.
+template <typename WT, bool WIDE, bool RATIO>
+static void launch_sweep_tiles(const SweepArgs& a, const WT* ww, bool tie, bool fused,
+                               hipStream_t st)
+{
+    const unsigned tiles = blocks_for(a.n);
+    if (tie) k_tiescan_tile<WT, false, WIDE, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
+    else if (fused) k_tiescan_tile<WT, true, WIDE, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
+    else k_sweep_tile<WT, false, WIDE, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
+}
+
+template <typename WT>
+static void launch_sweep_general(const SweepArgs& a, const WT* ww, bool tie, bool fused,
+                                 hipStream_t st)
+{
+    if (a.Vhi) {
+        if (a.t) launch_sweep_tiles<WT, true, true>(a, ww, tie, fused, st);
+        else launch_sweep_tiles<WT, true, false>(a, ww, tie, fused, st);
+    } else {
+        launch_sweep_tiles<WT, false, true>(a, ww, tie, fused, st);
+    }
+}
+
 void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool first, bool tie,
                   bool count_tight, unsigned grid, hipStream_t st)
 {
+    if ((a.Vhi || a.t) && !first) {
+        const bool fused = !tie && count_tight;
+        if (wtype == kWI64) launch_sweep_general(a, (const long long*)w, tie, fused, st);
+        else launch_sweep_general(a, (const int*)w, tie, fused, st);
+        return;
+    }
     if (G == 0) {   // sweep over vertex tiles
         const unsigned tiles = blocks_for(a.n);
         const bool fused = !tie && !first && count_tight;
@@ -2270,15 +2408,24 @@ void launch_pj_final_dev(int n, const unsigned long long* P0, const unsigned lon
 }
 
 void launch_val_round_dev(int n, int s, int r, const Jmp* Qin, Jmp* Qout, Ctl* ctl,
-                          hipStream_t st)
+                          hipStream_t st, const long long* hin, long long* hout)
 {
-    k_val_round_dev<<<stride_grid(n), kWG, 0, st>>>(n, s, r, Qin, Qout, ctl);
+    if (hin)
+        k_val_round_dev<true><<<stride_grid(n), kWG, 0, st>>>(n, s, r, Qin, Qout, ctl, hin, hout);
+    else
+        k_val_round_dev<false><<<stride_grid(n), kWG, 0, st>>>(n, s, r, Qin, Qout, ctl, nullptr,
+                                                               nullptr);
 }
 
 void launch_val_final_dev(int n, const Jmp* Q0, const Jmp* Q1, long long* V, int* hop, Ctl* ctl,
-                          hipStream_t st)
+                          hipStream_t st, const long long* h0, const long long* h1,
+                          long long* Vhi)
 {
-    k_val_final_dev<<<blocks_for(n), kWG, 0, st>>>(n, Q0, Q1, V, hop, ctl);
+    if (Vhi)
+        k_val_final_dev<true><<<blocks_for(n), kWG, 0, st>>>(n, Q0, Q1, V, hop, ctl, h0, h1, Vhi);
+    else
+        k_val_final_dev<false><<<blocks_for(n), kWG, 0, st>>>(n, Q0, Q1, V, hop, ctl, nullptr,
+                                                              nullptr, nullptr);
 }
 
 void launch_pj_round(int n, const unsigned long long* Pin, unsigned long long* Pout,
@@ -2303,30 +2450,36 @@ void launch_pj_final(int n, const unsigned long long* P, int* rep, unsigned char
 }
 
 void launch_cyc_zero(int n, const int* rep, const unsigned char* onc, long long* wsum,
-                     unsigned* lcnt, int* cyc_list, Ctl* ctl, hipStream_t st)
+                     unsigned* lcnt, int* cyc_list, Ctl* ctl, hipStream_t st, long long* tsum)
 {
     const unsigned per = list_per_block(n);
     const unsigned grid = (unsigned)(((int64_t)n + per - 1) / per);
-    k_cyc_zero<<<grid, kWG, 0, st>>>(n, rep, onc, per, wsum, lcnt, cyc_list, ctl);
+    k_cyc_zero<<<grid, kWG, 0, st>>>(n, rep, onc, per, wsum, lcnt, cyc_list, ctl, tsum);
 }
 
 void launch_cyc_sum(int n, const int* rep, const unsigned char* onc, const int* pi, const void* w,
-                    int wtype, int neg, long long* wsum, unsigned* lcnt, hipStream_t st)
+                    int wtype, int neg, long long* wsum, unsigned* lcnt, hipStream_t st,
+                    const int* t, long long* tsum)
 {
     if (wtype == kWI64)
         k_cyc_sum<long long><<<blocks_for(n), kWG, 0, st>>>(n, rep, onc, pi, (const long long*)w,
-                                                            neg, wsum, lcnt);
+                                                            neg, wsum, lcnt, t, tsum);
     else
         k_cyc_sum<int><<<blocks_for(n), kWG, 0, st>>>(n, rep, onc, pi, (const int*)w, neg, wsum,
-                                                      lcnt);
+                                                      lcnt, t, tsum);
 }
 
 void launch_select(const int* cyc_list, const long long* wsum, const unsigned* lcnt, Ctl* ctl,
-                   void* scratch, hipStream_t st)
+                   void* scratch, hipStream_t st, const long long* tsum)
 {
     Cand* part = (Cand*)scratch;
-    k_select_part<<<kSelectParts, kWG, 0, st>>>(cyc_list, wsum, lcnt, ctl, part);
-    k_select_final<<<1, kWG, 0, st>>>(part, kSelectParts, ctl);
+    k_select_part<<<kSelectParts, kWG, 0, st>>>(cyc_list, wsum, lcnt, tsum, ctl, part);
+    k_select_final<<<1, kWG, 0, st>>>(part, kSelectParts, lcnt, ctl);
+}
+
+void launch_validate_t(int m, const int* t, Ctl* ctl, hipStream_t st)
+{
+    k_validate_t<<<stride_grid(m), kWG, 0, st>>>(m, t, ctl);
 }
 
 void launch_conn_init(int n, const int* rep, const unsigned char* onc, int s, int* layer,
@@ -2490,25 +2643,33 @@ void launch_rev_build(int n, int m, const int* row_ptr, const int* col, unsigned
 
 void launch_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
                      int s, long long W, long long L, int* succ, bool have_succ, Jmp* Q, Ctl* ctl,
-                     const unsigned* gate, hipStream_t st)
+                     const unsigned* gate, hipStream_t st, long long* Dhi, const int* t)
 {
     if (wtype == kWI64)
         k_val_init<long long><<<stride_grid(n), kWG, 0, st>>>(n, col, pi, (const long long*)w, neg,
                                                              s, W, L, succ, have_succ ? 1 : 0, Q, ctl,
-                                                             gate);
+                                                             gate, Dhi, t);
     else
         k_val_init<int><<<stride_grid(n), kWG, 0, st>>>(n, col, pi, (const int*)w, neg, s, W, L,
-                                                       succ, have_succ ? 1 : 0, Q, ctl, gate);
+                                                       succ, have_succ ? 1 : 0, Q, ctl, gate, Dhi,
+                                                       t);
 }
 
-void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st)
+void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st,
+                      const long long* hin, long long* hout)
 {
-    k_val_round<<<stride_grid(n), kWG, 0, st>>>(n, s, Qin, Qout, active);
+    if (hin)
+        k_val_round<true><<<stride_grid(n), kWG, 0, st>>>(n, s, Qin, Qout, active, hin, hout);
+    else
+        k_val_round<false><<<stride_grid(n), kWG, 0, st>>>(n, s, Qin, Qout, active, nullptr,
+                                                           nullptr);
 }
 
-void launch_val_final(int n, const Jmp* Q, long long* V, int* hop, Ctl* ctl, hipStream_t st)
+void launch_val_final(int n, const Jmp* Q, long long* V, int* hop, Ctl* ctl, hipStream_t st,
+                      const long long* hin, long long* Vhi)
 {
-    k_val_final<<<blocks_for(n), kWG, 0, st>>>(n, Q, V, hop, ctl);
+    if (Vhi) k_val_final<true><<<blocks_for(n), kWG, 0, st>>>(n, Q, V, hop, ctl, hin, Vhi);
+    else k_val_final<false><<<blocks_for(n), kWG, 0, st>>>(n, Q, V, hop, ctl, nullptr, nullptr);
 }
 
 void launch_cycle_list(int n, int s, long long L, const unsigned char* onC, const int* pi,
@@ -2522,6 +2683,10 @@ static void launch_short_walk_t(const SweepArgs& a, const void* w, int G, const 
                                 unsigned grid, hipStream_t st)
 {
     const WT* ww = (const WT*)w;
+    if (a.Vhi) {   // int128 values: one lane group size (a rare fallback)
+        k_tie_short_walk<8, WT, true><<<grid, kWG, 0, st>>>(a, ww, succ);
+        return;
+    }
     switch (G) {
         case 1: k_tie_short_walk<1, WT><<<grid, kWG, 0, st>>>(a, ww, succ); break;
         case 2: k_tie_short_walk<2, WT><<<grid, kWG, 0, st>>>(a, ww, succ); break;
@@ -2572,6 +2737,11 @@ void launch_adjoint_scatter(int64_t m, const int* cyc, int64_t len, const double
 void launch_w_from_f64(int64_t m, const double* w, long long* out, unsigned* bad, hipStream_t st)
 {
     k_w_from_f64<<<stride_grid(m), kWG, 0, st>>>(m, w, out, bad);
+}
+
+void launch_fits64(int n, const long long* lo, const long long* hi, unsigned* bad, hipStream_t st)
+{
+    k_fits64<<<stride_grid(n), kWG, 0, st>>>(n, lo, hi, bad);
 }
 
 void launch_check_policy(int n, const int* row_ptr, const int* pi, unsigned* bad, hipStream_t st)
@@ -2686,6 +2856,7 @@ __global__ void k_post_ctl(const Ctl* __restrict__ c, CtlView* dst, unsigned* se
         v.jstall = c->jstall;
         v.xcnt = c->xcnt;
         v.scnt = c->scnt;
+        v.clen = c->clen;
         *dst = v;
         __threadfence_system();
         __hip_atomic_store(seq_slot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);

@@ -59,7 +59,9 @@ constexpr int64_t kTieListCap = 1 << 20;
 // Workspace carved into the solver's device arrays.
 struct Ws {
     Ctl* ctl;
-    long long* V;        // values scaled by L
+    long long* V;        // values scaled by L (int128 values: their low words)
+    long long* Vhi;      // int128 values: high words
+    long long* Dhi[2];   // int128 value rounds: high words of the jump entries' sums
     int* pi;             // policy: CSR position of each vertex's edge
     int* succ;           // policy successor
     int* hop;            // policy hops to the source (value phase)
@@ -83,6 +85,7 @@ struct Ws {
     unsigned xcap;
     long long* wsum;     // per-cycle weight sums, keyed by rep
     unsigned* lcnt;      // per-cycle lengths, keyed by rep
+    long long* tsum;     // cycle ratio: per-cycle times, keyed by rep
     int* cyc;            // cycle heads
     size_t total;
 };
@@ -100,6 +103,9 @@ Ws carve(void* base, int64_t n, int64_t m)
     const size_t N = (size_t)n;
     w.ctl = (Ctl*)take(sizeof(Ctl));
     w.V = (long long*)take(8 * N);
+    w.Vhi = (long long*)take(8 * N);
+    w.Dhi[0] = (long long*)take(8 * N);
+    w.Dhi[1] = (long long*)take(8 * N);
     w.pi = (int*)take(4 * N);
     w.succ = (int*)take(4 * N);
     w.hop = (int*)take(4 * N);
@@ -128,6 +134,7 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.ys = (int*)take(4 * (size_t)w.xcap);
     w.wsum = (long long*)take(8 * N);
     w.lcnt = (unsigned*)take(4 * N);
+    w.tsum = (long long*)take(8 * N);
     w.cyc = (int*)take(4 * N);
     w.total = off;
     return w;
@@ -183,6 +190,7 @@ struct Ctx {
     const int* row_ptr;
     const int* col;
     const void* w;
+    const int* t = nullptr;   // cycle ratio: edge times (>= 1); null for the mean
     int wtype;
     int neg;
     hipStream_t st;
@@ -216,6 +224,10 @@ struct Ctx {
     // the call may not allocate: control reads go through a stack copy
     // instead of the pinned mailbox, and no side stream or event is created
     bool noalloc = false;
+    // values are int128 (split lo / hi): set once a value leaves the int64
+    // range (or on request), for the rest of the solve
+    bool wide = false;
+    bool allow_wide = false;
 
     Ctx() = default;
     Ctx(const Ctx&) = delete;
@@ -317,7 +329,18 @@ ocm_status validate(Ctx& c, int check_csr)
     OCM_TRY(read_ctl(c));
     if (c.h.err & ocm::kErrBadCsr) return fail(OCM_E_BAD_CSR, "malformed CSR");
     if (c.h.err & ocm::kErrNoOut) return fail(OCM_E_NO_OUT_EDGE, "a vertex has no out-edge");
-    const unsigned __int128 bound = (unsigned __int128)2 * (unsigned)c.n * c.h.maxabsw;
+    const unsigned long long maxw = c.h.maxabsw;
+    unsigned long long maxt = 1;
+    if (c.t) {
+        // |T w - W t| <= 2 n max|w| max t for a cycle's (W, T)
+        ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrAll, c.st);
+        ocm::launch_validate_t(c.m, c.t, c.ws.ctl, c.st);
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        if (c.h.bad) return fail(OCM_E_INVALID_ARG, "edge times must be integers >= 1");
+        maxt = c.h.maxabsw;
+    }
+    const unsigned __int128 bound = (unsigned __int128)2 * (unsigned)c.n * maxw * maxt;
     if (bound >= ((unsigned __int128)1 << 62)) return fail(OCM_E_OVERFLOW, "weights too large for int64 values");
     return OCM_OK;
 }
@@ -354,6 +377,8 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     a.row_ptr = c.row_ptr;
     a.col = c.col;
     a.V = V;
+    a.Vhi = c.wide && V == c.ws.V ? c.ws.Vhi : nullptr;
+    a.t = first ? nullptr : c.t;
     a.W = W;
     a.L = L;
     a.pi = pi;
@@ -477,9 +502,11 @@ ocm_status phase_select(Ctx& c, const int* pi, const int* rep, const unsigned ch
 {
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrCount, c.st);
     c.prof.begin(OCM_K_SELECT);
-    ocm::launch_cyc_zero(c.n, rep, onc, c.ws.wsum, c.ws.lcnt, c.ws.cyc, c.ws.ctl, c.st);
-    ocm::launch_cyc_sum(c.n, rep, onc, pi, c.w, c.wtype, c.neg, c.ws.wsum, c.ws.lcnt, c.st);
-    ocm::launch_select(c.ws.cyc, c.ws.wsum, c.ws.lcnt, c.ws.ctl, c.ws.sel, c.st);
+    long long* tsum = c.t ? c.ws.tsum : nullptr;
+    ocm::launch_cyc_zero(c.n, rep, onc, c.ws.wsum, c.ws.lcnt, c.ws.cyc, c.ws.ctl, c.st, tsum);
+    ocm::launch_cyc_sum(c.n, rep, onc, pi, c.w, c.wtype, c.neg, c.ws.wsum, c.ws.lcnt, c.st, c.t,
+                        tsum);
+    ocm::launch_select(c.ws.cyc, c.ws.wsum, c.ws.lcnt, c.ws.ctl, c.ws.sel, c.st, tsum);
     c.prof.end();
     c.prof.bytes(OCM_K_SELECT, 6.0 * c.n);   // rep and on-cycle flags, twice
     HIP_TRY(hipGetLastError());
@@ -713,14 +740,22 @@ ocm_status value_rounds_on_device(Ctx& c, int s, long long* V, int* hop, bool pr
                                   int* rounds, bool gated)
 {
     ocm::launch_jump_setup(c.ws.ctl, true, gated, c.st);
+    Ws& w = c.ws;
     int r = 0;
     for (;;) {
         for (int j = 0; j < kRoundsPerRead; ++j) {
             ++r;
-            ocm::launch_val_round_dev(c.n, s, r, c.ws.Q[(r - 1) & 1], c.ws.Q[r & 1], c.ws.ctl,
-                                      c.st);
+            if (c.wide)
+                ocm::launch_val_round_dev(c.n, s, r, w.Q[(r - 1) & 1], w.Q[r & 1], w.ctl, c.st,
+                                          w.Dhi[(r - 1) & 1], w.Dhi[r & 1]);
+            else
+                ocm::launch_val_round_dev(c.n, s, r, w.Q[(r - 1) & 1], w.Q[r & 1], w.ctl, c.st);
         }
-        ocm::launch_val_final_dev(c.n, c.ws.Q[0], c.ws.Q[1], V, hop, c.ws.ctl, c.st);
+        if (c.wide)
+            ocm::launch_val_final_dev(c.n, w.Q[0], w.Q[1], V, hop, w.ctl, c.st, w.Dhi[0], w.Dhi[1],
+                                      w.Vhi);
+        else
+            ocm::launch_val_final_dev(c.n, w.Q[0], w.Q[1], V, hop, w.ctl, c.st);
         HIP_TRY(hipGetLastError());
         OCM_TRY(read_ctl(c));
         if (c.h.jmode == 0) break;
@@ -743,8 +778,8 @@ ocm_status value_rounds_on_device(Ctx& c, int s, long long* V, int* hop, bool pr
 
 // gated (rounds decided on the device only): the phase runs only if
 // ctl->jgate is open (k_fast_gate); a closed gate leaves V as it was.
-ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, long long* V,
-                        int* hop, bool probe, bool* stalled, int* rounds, bool gated = false)
+ocm_status phase_values_once(Ctx& c, const int* pi, int s, long long W, long long L, long long* V,
+                             int* hop, bool probe, bool* stalled, int* rounds, bool gated)
 {
     if (stalled) *stalled = false;
     ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrCount, c.st);
@@ -752,7 +787,8 @@ ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, 
     c.prof.begin(ph);
     const bool have_succ = c.succ_ok && pi == c.ws.pi;
     ocm::launch_val_init(c.n, c.col, pi, c.w, c.wtype, c.neg, s, W, L, c.ws.succ, have_succ,
-                         c.ws.Q[0], c.ws.ctl, gated ? &c.ws.ctl->jgate : nullptr, c.st);
+                         c.ws.Q[0], c.ws.ctl, gated ? &c.ws.ctl->jgate : nullptr, c.st,
+                         c.wide ? c.ws.Dhi[0] : nullptr, c.t);
     // a gated init that does not run leaves succ as it was
     if (!gated) c.succ_ok = pi == c.ws.pi;
     c.prof.end();
@@ -769,7 +805,11 @@ ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, 
         const int b = a ^ 1;
         ocm::launch_ctl_clear(c.ws.ctl, ocm::kClrActive2, c.st);
         c.prof.begin(ph);
-        ocm::launch_val_round(c.n, s, c.ws.Q[a], c.ws.Q[b], &c.ws.ctl->lane[0].active2, c.st);
+        if (c.wide)
+            ocm::launch_val_round(c.n, s, c.ws.Q[a], c.ws.Q[b], &c.ws.ctl->lane[0].active2, c.st,
+                                  c.ws.Dhi[a], c.ws.Dhi[b]);
+        else
+            ocm::launch_val_round(c.n, s, c.ws.Q[a], c.ws.Q[b], &c.ws.ctl->lane[0].active2, c.st);
         c.prof.end();
         c.prof.bytes(ph, 32.0 * c.n + 16.0 * act);   // own + new entry; gather if unfinished
         HIP_TRY(hipGetLastError());
@@ -790,13 +830,27 @@ ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, 
     c.jump_rounds += k;
     if (rounds) *rounds = k;
     c.prof.begin(ph);
-    ocm::launch_val_final(c.n, c.ws.Q[a], V, hop, c.ws.ctl, c.st);
+    if (c.wide) ocm::launch_val_final(c.n, c.ws.Q[a], V, hop, c.ws.ctl, c.st, c.ws.Dhi[a], c.ws.Vhi);
+    else ocm::launch_val_final(c.n, c.ws.Q[a], V, hop, c.ws.ctl, c.st);
     c.prof.end();
     c.prof.bytes(ph, 24.0 * c.n);
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
     if (c.h.overflow) return fail(OCM_E_OVERFLOW, "a value left [-2^62, 2^62]");
     return OCM_OK;
+}
+
+// Value phase; when a value leaves the int64 range (only int64 values are
+// checked), the phase is run again with int128 values, which the rest of the
+// solve keeps (sweeps and the tie check read them).  The overflowing phase's
+// V is discarded: its inputs (pi, s, W, L) are unchanged.
+ocm_status phase_values(Ctx& c, const int* pi, int s, long long W, long long L, long long* V,
+                        int* hop, bool probe, bool* stalled, int* rounds, bool gated = false)
+{
+    const ocm_status rc = phase_values_once(c, pi, s, W, L, V, hop, probe, stalled, rounds, gated);
+    if (rc != OCM_E_OVERFLOW || c.wide || !c.allow_wide || V != c.ws.V) return rc;
+    c.wide = true;
+    return phase_values_once(c, pi, s, W, L, V, hop, probe, stalled, rounds, false);
 }
 
 // Does the small graph (nodes 0..N-1, edges from adjacency lists) hold a
@@ -867,6 +921,8 @@ ocm_status tie_check(Ctx& c, long long W, long long L, ocm_result* out)
         a.row_ptr = c.row_ptr;
         a.col = c.col;
         a.V = w.V;
+        a.Vhi = c.wide ? w.Vhi : nullptr;
+        a.t = c.t;
         a.W = W;
         a.L = L;
         a.pi = w.pi;
@@ -943,9 +999,10 @@ long long gcd_ll(long long a, long long b)
     return a;
 }
 
+// t (nullable): edge times, the optimal cycle ratio instead of the mean.
 ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t ws_bytes,
                  int32_t* cycle_edges, int64_t cap, ocm_result* out, void* stream, int neg,
-                 bool noalloc = false)
+                 bool noalloc = false, const int32_t* t = nullptr)
 {
     if (!out) return fail(OCM_E_INVALID_ARG, "result pointer is null");
     memset(out, 0, sizeof *out);
@@ -955,6 +1012,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     if (o.profile) memset(o.profile, 0, sizeof *o.profile);
     Ctx c;
     c.noalloc = noalloc;
+    c.t = t;
     OCM_TRY(setup(c, g, neg, wsp, ws_bytes, stream, o.profile));
     if (cap > 0 && !cycle_edges) return fail(OCM_E_INVALID_ARG, "cycle_edges is null");
     c.G = choose_lanes(c.n, c.m, o.schedule);
@@ -963,6 +1021,8 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     c.tile_sweep = o.schedule <= 0;
     c.count_tight = o.tie_check != 0;
     c.connect_mode = o.connect_mode;
+    c.allow_wide = true;
+    c.wide = o.int128_values != 0;
     if (c.connect_mode < 0 || c.connect_mode > 2) return fail(OCM_E_INVALID_ARG, "bad connect_mode");
 
     ocm_status rc = validate(c, o.validate != 0);
@@ -985,6 +1045,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     bool have_c = false, need_sweep = !warm;
     int s = -1;
     long long W = 0, L = 1;
+    long long clen = 1;   // edges of C (L itself for the mean; L is C's time for a ratio)
     for (;;) {
         // with the rounds decided on the device, the fast path's value phase
         // is queued behind the sweep, gated on the sweep's outcome, and both
@@ -1038,6 +1099,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
         s = c.h.s;
         W = c.h.W;
         L = c.h.L;
+        clen = c.h.clen;
         // the solve itself needs no layers, only the rewired policy
         rc = phase_connect(c, w.rep, w.onc, s, w.pi, nullptr, w.onC, nullptr);
         if (rc != OCM_OK) break;
@@ -1046,6 +1108,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
         have_c = true;
     }
     out->iterations = iter;
+    if (c.wide) out->flags |= OCM_F_INT128;
     out->connect_rounds = c.connect_rounds;
     out->jump_rounds = c.jump_rounds;
     out->fast_iters = fast;
@@ -1064,15 +1127,15 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     out->W = neg ? -W : W;
     out->L = L;
     out->source = s;
-    out->cycle_len = L;
-    if (cap < L) {
+    out->cycle_len = clen;
+    if (cap < clen) {
         c.prof.finish();
         return fail(OCM_E_CAPACITY, "cycle_cap smaller than the critical cycle");
     }
     c.prof.begin(OCM_K_RESULT);
-    ocm::launch_cycle_list(c.n, s, L, w.onC, w.pi, w.hop, cycle_edges, c.st);
+    ocm::launch_cycle_list(c.n, s, clen, w.onC, w.pi, w.hop, cycle_edges, c.st);
     c.prof.end();
-    c.prof.bytes(OCM_K_RESULT, (double)c.n + 28.0 * L);
+    c.prof.bytes(OCM_K_RESULT, (double)c.n + 28.0 * clen);
     HIP_TRY(hipGetLastError());
     if (o.tie_check) {
         rc = tie_check(c, W, L, out);
@@ -1086,6 +1149,17 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     }
     if (o.policy_out)
         HIP_TRY(hipMemcpyAsync(o.policy_out, w.pi, 4 * (size_t)c.n, hipMemcpyDeviceToDevice, c.st));
+    if (o.potential_out && c.wide) {
+        // int128 values: exported only if every one fits int64
+        ocm::launch_ctl_clear(w.ctl, ocm::kClrChanged, c.st);
+        ocm::launch_fits64(c.n, w.V, w.Vhi, &w.ctl->lane[0].bad, c.st);
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        if (c.h.bad) {
+            c.prof.finish();
+            return fail(OCM_E_OVERFLOW, "the optimum's values need int128; potential_out holds int64");
+        }
+    }
     if (o.potential_out)
         HIP_TRY(hipMemcpyAsync(o.potential_out, w.V, 8 * (size_t)c.n, hipMemcpyDeviceToDevice, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
@@ -1212,6 +1286,22 @@ ocm_status ocm_max(const ocm_graph* g, const ocm_options* o, void* ws, size_t ws
                    int32_t* cycle_edges, int64_t cycle_cap, ocm_result* out, void* stream)
 {
     return solve(g, o, ws, ws_bytes, cycle_edges, cycle_cap, out, stream, 1);
+}
+
+ocm_status ocm_ratio_min(const ocm_graph* g, const int32_t* t, const ocm_options* o, void* ws,
+                         size_t ws_bytes, int32_t* cycle_edges, int64_t cycle_cap,
+                         ocm_result* out, void* stream)
+{
+    if (!t) return fail(OCM_E_INVALID_ARG, "edge times are null");
+    return solve(g, o, ws, ws_bytes, cycle_edges, cycle_cap, out, stream, 0, false, t);
+}
+
+ocm_status ocm_ratio_max(const ocm_graph* g, const int32_t* t, const ocm_options* o, void* ws,
+                         size_t ws_bytes, int32_t* cycle_edges, int64_t cycle_cap,
+                         ocm_result* out, void* stream)
+{
+    if (!t) return fail(OCM_E_INVALID_ARG, "edge times are null");
+    return solve(g, o, ws, ws_bytes, cycle_edges, cycle_cap, out, stream, 1, false, t);
 }
 
 ocm_status ocm_phase_sweep(const ocm_graph* g, int32_t neg, int32_t first, const int64_t* V,

@@ -30,7 +30,7 @@ OCM_E_WORKSPACE = -8
 OCM_E_HIP = -9
 
 OCM_W_I32, OCM_W_I64 = 0, 1
-OCM_F_TIE, OCM_F_TIE_UNCHECKED, OCM_F_TIGHT_EDGES = 1, 2, 4
+OCM_F_TIE, OCM_F_TIE_UNCHECKED, OCM_F_TIGHT_EDGES, OCM_F_INT128 = 1, 2, 4, 8
 
 PHASES = ("validate", "sweep", "tiescan", "cycles", "select", "conn_pull", "conn_mark",
           "conn_claim", "reverse", "values", "fast", "result")
@@ -72,7 +72,7 @@ class Options(C.Structure):
                 ("tie_check", C.c_int32), ("fast_path", C.c_int32),
                 ("connect_mode", C.c_int32), ("tile", C.c_int32), ("init_policy", C.c_void_p),
                 ("policy_out", C.c_void_p), ("potential_out", C.c_void_p),
-                ("profile", C.POINTER(Profile))]
+                ("profile", C.POINTER(Profile)), ("int128_values", C.c_int32)]
 
 
 _lib = None
@@ -96,6 +96,14 @@ def lib():
             f.restype = C.c_int
         L.ocm_min_noalloc.argtypes = [G, O, P, i64, C.POINTER(_Result), P]
         L.ocm_min_noalloc.restype = C.c_int
+        for f in (L.ocm_ratio_min, L.ocm_ratio_max):
+            f.argtypes = [G, P, O, P, C.c_size_t, P, i64, C.POINTER(_Result), P]
+            f.restype = C.c_int
+        L.ocm_general_workspace_size.argtypes = [G]
+        L.ocm_general_workspace_size.restype = C.c_size_t
+        for f in (L.ocm_min_general, L.ocm_max_general):
+            f.argtypes = [G, O, P, C.c_size_t, P, i64, C.POINTER(_Result), C.POINTER(i64), P]
+            f.restype = C.c_int
         L.ocm_phase_sweep.argtypes = [G, i32, i32, P, i64, i64, P, i32, P, C.c_size_t,
                                       C.POINTER(i64), P]
         L.ocm_phase_cycles.argtypes = [G, P, P, P, P, C.c_size_t, C.POINTER(i64), P]
@@ -173,6 +181,7 @@ def workspace(g: Graph, device) -> torch.Tensor:
 def release_workspace():
     _ws_cache.clear()
     _bws_cache.clear()
+    _gws_cache.clear()
 
 
 @dataclasses.dataclass
@@ -199,6 +208,11 @@ class Result:
         return Fraction(self.p, self.q)
 
     @property
+    def int128(self) -> bool:
+        """True when the solve carried its values in int128."""
+        return bool(self.flags & OCM_F_INT128)
+
+    @property
     def tie(self):
         """True / False, or None when the uniqueness test did not decide."""
         if self.flags & OCM_F_TIE:
@@ -212,10 +226,11 @@ CONNECT_MODES = {"auto": 0, "pull": 1, "push": 2}
 
 
 def options(max_iters=0, validate=True, schedule=0, tie_check=True, fast_path=True,
-            connect="auto", init_policy=None, tile=0) -> Options:
+            connect="auto", init_policy=None, tile=0, int128=False) -> Options:
     o = Options()
     lib().ocm_default_options(C.byref(o))
     o.max_iters, o.validate, o.schedule, o.tile = max_iters, int(validate), schedule, tile
+    o.int128_values = int(int128)
     o.tie_check, o.fast_path = int(tie_check), int(fast_path)
     o.connect_mode = CONNECT_MODES[connect]
     if init_policy is not None:
@@ -224,8 +239,13 @@ def options(max_iters=0, validate=True, schedule=0, tie_check=True, fast_path=Tr
     return o
 
 
-def _solve(fn, row_ptr, col, w, want_policy, want_potential, profile, **opt) -> Result:
+def _solve(fn, row_ptr, col, w, want_policy, want_potential, profile, times=None,
+           **opt) -> Result:
     g = make_graph(row_ptr, col, w)
+    if times is not None:
+        _dev(times, (torch.int32,), "t")
+        if times.numel() != g.m:
+            raise ValueError("t and col must have the same length")
     dev = col.device
     o = options(**opt)
     pol = torch.empty(g.n, dtype=torch.int32, device=dev) if want_policy else None
@@ -238,8 +258,13 @@ def _solve(fn, row_ptr, col, w, want_policy, want_potential, profile, **opt) -> 
     ws = workspace(g, dev)
     cyc = torch.empty(g.n, dtype=torch.int32, device=dev)
     res = _Result()
-    _check(fn(C.byref(g), C.byref(o), C.c_void_p(ws.data_ptr()), ws.numel(),
-              C.c_void_p(cyc.data_ptr()), g.n, C.byref(res), _stream()))
+    if times is None:
+        _check(fn(C.byref(g), C.byref(o), C.c_void_p(ws.data_ptr()), ws.numel(),
+                  C.c_void_p(cyc.data_ptr()), g.n, C.byref(res), _stream()))
+    else:
+        _check(fn(C.byref(g), C.c_void_p(times.data_ptr()), C.byref(o),
+                  C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(cyc.data_ptr()), g.n,
+                  C.byref(res), _stream()))
     counters = dict(push_frontier=res.push_frontier, push_in_edges=res.push_in_edges,
                     general_iters=res.general_iters, value_rounds=res.value_rounds)
     return Result(res.p, res.q, cyc[:res.cycle_len], res.source, res.iterations, res.flags,
@@ -279,6 +304,54 @@ def max_cycle_mean(row_ptr, col, w, *, want_policy=False, want_potential=False,
                    profile=False, **opt) -> Result:
     """Exact maximum cycle mean and one critical cycle (ocm_max)."""
     return _solve(lib().ocm_max, row_ptr, col, w, want_policy, want_potential, profile, **opt)
+
+
+def min_cycle_ratio(row_ptr, col, w, t, *, want_policy=False, want_potential=False,
+                    profile=False, **opt) -> Result:
+    """Exact minimum cycle ratio cost/time and one critical cycle
+    (ocm_ratio_min); ``t``: int32 edge times >= 1.  ``W`` and ``L`` of the
+    result are the critical cycle's cost and time."""
+    return _solve(lib().ocm_ratio_min, row_ptr, col, w, want_policy, want_potential, profile,
+                  times=t, **opt)
+
+
+def max_cycle_ratio(row_ptr, col, w, t, *, want_policy=False, want_potential=False,
+                    profile=False, **opt) -> Result:
+    """Exact maximum cycle ratio (ocm_ratio_max)."""
+    return _solve(lib().ocm_ratio_max, row_ptr, col, w, want_policy, want_potential, profile,
+                  times=t, **opt)
+
+
+_gws_cache: dict = {}
+
+
+def cycle_mean_general(row_ptr, col, w, mode: str = "min", **opt) -> Result:
+    """Optimum of a graph that need not be strongly connected (its vertices
+    may even lack out-edges): the best optimum over its strongly connected
+    components (ocm_min_general / ocm_max_general).  ``counters["components"]``
+    is the number of components that hold a cycle."""
+    if mode not in ("min", "max"):
+        raise ValueError("mode must be 'min' or 'max'")
+    g = make_graph(row_ptr, col, w)
+    need = lib().ocm_general_workspace_size(C.byref(g))
+    if need == 0:
+        _check(OCM_E_INVALID_ARG)
+    key = torch.device(col.device)
+    ws = _gws_cache.get(key)
+    if ws is None or ws.numel() < need:
+        _gws_cache.pop(key, None)
+        ws = torch.empty(need, dtype=torch.uint8, device=col.device)
+        _gws_cache[key] = ws
+    o = options(**opt)
+    cyc = torch.empty(g.n, dtype=torch.int32, device=col.device)
+    res = _Result()
+    nc = C.c_int64()
+    fn = lib().ocm_min_general if mode == "min" else lib().ocm_max_general
+    _check(fn(C.byref(g), C.byref(o), C.c_void_p(ws.data_ptr()), ws.numel(),
+              C.c_void_p(cyc.data_ptr()), g.n, C.byref(res), C.byref(nc), _stream()))
+    return Result(res.p, res.q, cyc[:res.cycle_len], res.source, res.iterations, res.flags,
+                  res.W, res.L, res.tight_edges, res.connect_rounds, res.jump_rounds,
+                  res.fast_iters, {"components": nc.value})
 
 
 def cycle_mean(row_ptr, col, w, mode: str = "min", **kw) -> Result:

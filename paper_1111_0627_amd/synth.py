@@ -22,6 +22,23 @@ Recipes
        duplicate targets are kept.
     4. ``w = integers(wlo, whi + 1, m)`` in final CSR order, cast to wdtype.
 
+``deep_tail_graph(ring, tail, extra, wlight, hlo, hhi, seed)``
+    A light ring 0 .. ring-1 fed by a long heavy tail, so that the optimum's
+    values grow like tail * ring * hhi (beyond int64 for large weights) while
+    every single weight stays small.
+    1. ``xt = integers(max(j - 8, 0), tail)`` for tail index j, ``extra``
+       draws per tail vertex in one call (shape (tail, extra)): extra targets
+       at most 8 steps nearer the ring, so every way to the ring crosses at
+       least tail / 8 heavy edges;
+    2. out-edges, in CSR order: ring vertex i -> (i + 1) mod ring, and ring
+       vertex 0 also -> ring + tail - 1 (the tail's far end); tail vertex
+       ring + j -> ring + j - 1 (ring vertex 0 for j = 0), then its extra
+       targets ring + xt[j];
+    3. ``w = integers(hlo, hhi + 1, m)`` in CSR order, then the ring edges'
+       weights are redrawn as ``integers(0, wlight + 1, ring)`` (int64).
+    Strongly connected; the minimum cycle mean is the ring's mean whenever
+    hlo exceeds wlight.
+
 ``product_graph(procs, states, p2, wlo, whi, seed)``
     Interleaving product of ``procs`` local automata with ``states`` local
     states each, the shape of a model checker's state space (Section 4).
@@ -87,6 +104,34 @@ def random_digraph(n: int, dlo: int, dhi: int, wlo: int, whi: int,
     col[~is_ring] = tgt.astype(np.int32)
     col[ring_pos] = ((np.arange(n, dtype=np.int64) + 1) % n).astype(np.int32)
     w = rng.integers(wlo, whi + 1, m).astype(wdtype)
+    return Graph(row_ptr.astype(np.int32), col, w, name)
+
+
+def deep_tail_graph(ring: int, tail: int, extra: int = 2, wlight: int = 10,
+                    hlo: int = 2**47, hhi: int = 2**48, seed=0, name: str = "") -> Graph:
+    """Light ring fed by a long heavy tail; recipe in the module docstring."""
+    if ring < 1 or tail < 1:
+        raise ValueError("ring and tail must be >= 1")
+    rng = _rng(seed)
+    xt = rng.integers(np.maximum(np.arange(tail) - 8, 0)[:, None], tail, (tail, extra))
+    n = ring + tail
+    deg = np.ones(n, np.int64)
+    deg[0] += 1
+    deg[ring:] += extra
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    m = int(row_ptr[-1])
+    col = np.empty(m, np.int32)
+    rs = row_ptr[:ring]
+    col[rs] = (np.arange(ring) + 1) % ring
+    col[rs[0] + 1] = ring + tail - 1
+    ts = row_ptr[ring:n]
+    j = np.arange(tail)
+    col[ts] = np.where(j == 0, 0, ring + j - 1)
+    for k in range(extra):
+        col[ts + 1 + k] = ring + xt[:, k]
+    w = rng.integers(hlo, hhi + 1, m).astype(np.int64)
+    w[rs] = rng.integers(0, wlight + 1, ring)
     return Graph(row_ptr.astype(np.int32), col, w, name)
 
 

@@ -70,7 +70,7 @@ def test_struct_layouts_match_header(tmp_path, libpath):
 #include "ocm.h"
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(ocm_graph), sizeof(ocm_result), sizeof(ocm_options), sizeof(ocm_profile));
-  printf("%zu %zu %zu %zu\n", offsetof(ocm_result, flags), offsetof(ocm_result, W), offsetof(ocm_result, tight_edges), offsetof(ocm_options, profile));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(ocm_result, flags), offsetof(ocm_result, W), offsetof(ocm_result, tight_edges), offsetof(ocm_options, profile), offsetof(ocm_options, int128_values));
   return 0;
 }
 ''')
@@ -82,7 +82,8 @@ int main(void) {
     assert sizes[:4] == [C.sizeof(ocm.Graph), C.sizeof(ocm._Result), C.sizeof(ocm.Options),
                          C.sizeof(ocm.Profile)]
     assert sizes[4:] == [ocm._Result.flags.offset, ocm._Result.W.offset,
-                         ocm._Result.tight_edges.offset, ocm.Options.profile.offset]
+                         ocm._Result.tight_edges.offset, ocm.Options.profile.offset,
+                         ocm.Options.int128_values.offset]
 
 
 def test_product_path_has_no_oracle_dependency():

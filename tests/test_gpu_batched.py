@@ -47,9 +47,8 @@ def test_batched_equals_oracle_per_graph(mode, seed):
         cyc = (res.cycle(k).cpu().numpy() - eptr[k]).tolist()
         assert (res.p[k], res.q[k], cyc, res.iterations[k]) == \
             (sol.p, sol.q, sol.cycle.tolist(), sol.iterations), k
-        t = res.tie(k)
-        if t is not None:
-            assert t == bool(sol.tie), k
+        assert res.tie(k) == bool(sol.tie), k
+        assert bool(res.flags[k] & ocm.OCM_F_TIGHT_EDGES) == (sol.tight > 0), k
 
 
 def test_batched_equals_plain_gpu_calls():
@@ -61,9 +60,8 @@ def test_batched_equals_plain_gpu_calls():
         cyc = (res.cycle(k).cpu().numpy() - eptr[k]).tolist()
         assert (res.p[k], res.q[k], cyc, res.iterations[k]) == \
             (r.p, r.q, r.cycle_edges.cpu().tolist(), r.iterations)
-        flag_bits = ocm.OCM_F_TIE | ocm.OCM_F_TIGHT_EDGES
-        if res.tie(k) is not None:
-            assert res.flags[k] & flag_bits == r.flags & flag_bits
+        flag_bits = ocm.OCM_F_TIE | ocm.OCM_F_TIE_UNCHECKED | ocm.OCM_F_TIGHT_EDGES
+        assert res.flags[k] & flag_bits == r.flags & flag_bits
 
 
 def test_batched_schedules_and_fast_path_agree():
@@ -142,3 +140,53 @@ def test_batched_single_graph_and_tiny_graphs():
     for k, g in enumerate(gs):
         sol = native.solve(g.row_ptr, g.col, g.w)
         assert (res.p[k], res.q[k], res.iterations[k]) == (sol.p, sol.q, sol.iterations)
+
+
+def test_batch4096_full_size_against_oracle_golden():
+    """The batched workload at full size (4,096 graphs, n log-uniform in
+    [100, 10^5]): every graph's value, critical cycle, iteration count and
+    tight-edge flag equal the sequential oracle's (stored by
+    tests/golden/make_golden.py), and no tie is left undecided."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "batch4096.json")
+    with open(path) as f:
+        gold = json.load(f)["per_graph"]
+    gs = synth.batch_graphs()
+    assert len(gs) == len(gold) == 4096
+    u, vptr, eptr = synth.disjoint_union(gs)
+    res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr)
+    assert all(s == ocm.OCM_OK for s in res.status)
+    cyc_all = res.cycle_edges.cpu().numpy()
+    bad = []
+    for k, ex in enumerate(gold):
+        assert (gs[k].n, gs[k].m) == (ex["n"], ex["m"])
+        cyc = (cyc_all[res.cycle_ptr[k]:res.cycle_ptr[k + 1]] - eptr[k]).tolist()
+        got = (res.p[k], res.q[k], cyc, res.iterations[k],
+               bool(res.flags[k] & ocm.OCM_F_TIGHT_EDGES), res.tie(k))
+        exp = (ex["p"], ex["q"], ex["cycle"], ex["iterations"], ex["tight"] > 0, bool(ex["tie"]))
+        if got != exp:
+            bad.append((k, got, exp))
+    assert not bad, bad[:3]
+
+
+@pytest.mark.parametrize("mode", ["min", "max"])
+def test_batched_ties_resolved_exactly(mode):
+    """Equal weights make tight edges and second critical cycles common;
+    every graph's tie flag must still be decided and equal the oracle's
+    (Tarjan on the tight subgraph)."""
+    rng = np.random.default_rng(17)
+    gs = [synth.random_digraph(int(rng.integers(2, 3000)), 1, 4, 0, 2, np.int32, seed=[17, k])
+          for k in range(80)]
+    u, vptr, eptr = synth.disjoint_union(gs)
+    res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr, mode=mode)
+    assert all(s == ocm.OCM_OK for s in res.status)
+    ties = 0
+    for k, g in enumerate(gs):
+        sol = native.solve(g.row_ptr, g.col, g.w, mode=mode)
+        cyc = (res.cycle(k).cpu().numpy() - eptr[k]).tolist()
+        assert (res.p[k], res.q[k], cyc, res.iterations[k]) == \
+            (sol.p, sol.q, sol.cycle.tolist(), sol.iterations), k
+        assert res.tie(k) == bool(sol.tie), k
+        ties += sol.tie
+    assert ties > 10

@@ -1,0 +1,98 @@
+"""int128 values: instances whose optimum needs values beyond int64 (a light
+ring fed by a long heavy tail) are solved exactly, with OCM_F_INT128 set, and
+equal the oracle (which keeps its values in int128 throughout); forcing
+int128 values from the start changes no result on ordinary graphs."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import native
+from paper_1111_0627_amd import ocm, synth
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    ocm.lib()
+    yield
+    ocm.release_workspace()
+
+
+def dev(g):
+    return (torch.from_numpy(np.ascontiguousarray(g.row_ptr, np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(g.col, np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(g.w)).cuda())
+
+
+def same(res, sol):
+    got = (res.p, res.q, res.cycle_edges.cpu().tolist(), res.source, res.iterations,
+           res.tight_edges, res.tie)
+    exp = (sol.p, sol.q, sol.cycle.tolist(), sol.source, sol.iterations, sol.tight,
+           bool(sol.tie))
+    assert got == exp
+
+
+CASES = [(700, 800, 2, 2**47, 2**48, 1), (128, 3000, 3, 2**47, 2**48, 2),
+         (3000, 20000, 2, 2**40, 2**41, 3), (300, 3000, 1, 2**46, 2**47, 4)]
+
+
+@pytest.mark.parametrize("ring,tail,extra,hlo,hhi,seed", CASES)
+def test_deep_tail_needs_int128_and_matches_oracle(ring, tail, extra, hlo, hhi, seed):
+    g = synth.deep_tail_graph(ring, tail, extra, 10, hlo, hhi, seed)
+    sol = native.solve(g.row_ptr, g.col, g.w)
+    for mode_kw in ({}, {"int128": True}, {"fast_path": False}, {"connect": "push"}):
+        res = ocm.min_cycle_mean(*dev(g), **mode_kw)
+        same(res, sol)
+        assert res.int128
+    # the maximum over negated weights: the same instance, mirrored
+    neg = synth.Graph(g.row_ptr, g.col, -g.w)
+    solm = native.solve(neg.row_ptr, neg.col, neg.w, mode="max")
+    resm = ocm.max_cycle_mean(*dev(neg))
+    same(resm, solm)
+    assert resm.int128
+
+
+def test_potential_out_refuses_int128_values():
+    g = synth.deep_tail_graph(700, 800, 2, 10, 2**47, 2**48, 1)
+    with pytest.raises(ocm.OCMError) as ei:
+        ocm.min_cycle_mean(*dev(g), want_potential=True)
+    assert ei.value.status == ocm.OCM_E_OVERFLOW
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_forced_int128_equals_int64_path(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(50, 5000))
+    g = synth.random_digraph(n, 1, 5, -30, 30, np.int32, seed=seed)
+    sol = native.solve(g.row_ptr, g.col, g.w)
+    r64 = ocm.min_cycle_mean(*dev(g), want_potential=True)
+    r128 = ocm.min_cycle_mean(*dev(g), int128=True, want_potential=True)
+    same(r64, sol)
+    same(r128, sol)
+    assert not r64.int128 and r128.int128
+    assert torch.equal(r64.potential, r128.potential)
+
+
+def test_forced_int128_on_hand_traces_and_ties():
+    with open(os.path.join(GOLD, "hand_traces.json")) as f:
+        traces = json.load(f)["traces"]
+    for tr in traces:
+        rp, cl, w = (np.array(tr[k]) for k in ("row_ptr", "col", "w"))
+        g = synth.Graph(rp.astype(np.int32), cl.astype(np.int32), w.astype(np.int64))
+        r = tr["result"]
+        res = ocm.min_cycle_mean(*dev(g), int128=True)
+        assert (res.p, res.q, res.cycle_edges.cpu().tolist(), res.source, res.iterations,
+                res.tie) == (r["p"], r["q"], r["cycle"], r["source"], r["iterations"],
+                             bool(r["tie"]))
+    # many equal weights: tight edges and ties everywhere
+    for seed in range(4):
+        g = synth.random_digraph(3000, 1, 4, 0, 2, np.int32, seed=seed)
+        sol = native.solve(g.row_ptr, g.col, g.w)
+        same(ocm.min_cycle_mean(*dev(g), int128=True), sol)

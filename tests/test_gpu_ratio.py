@@ -1,0 +1,122 @@
+"""Optimal cycle ratio (cost over time per cycle, Section 2.2) on the GPU
+through the C ABI, against the ratio oracle: the rational optimum, the
+critical cycle, source, iteration count, tight-edge count and tie flag must
+be identical, and the GPU's own potential must certify the result."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import brute, native
+from paper_1111_0627_amd import ocm, synth
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    ocm.lib()
+    yield
+    ocm.release_workspace()
+
+
+def dev(rp, cl, w, t):
+    w = np.asarray(w)
+    if w.dtype not in (np.int32, np.int64):
+        w = w.astype(np.int64)
+    return (torch.from_numpy(np.ascontiguousarray(rp, np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(cl, np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(w)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(t, np.int32)).cuda())
+
+
+def solve(rp, cl, w, t, mode="min", **kw):
+    fn = ocm.min_cycle_ratio if mode == "min" else ocm.max_cycle_ratio
+    return fn(*dev(rp, cl, w, t), **kw)
+
+
+def same(res, sol):
+    got = (res.p, res.q, res.L, res.cycle_edges.cpu().tolist(), res.source, res.iterations,
+           res.tight_edges, res.tie)
+    exp = (sol.p, sol.q, sol.L, sol.cycle.tolist(), sol.source, sol.iterations, sol.tight,
+           bool(sol.tie))
+    assert got == exp
+
+
+def test_ratio_hand_traces():
+    with open(os.path.join(GOLD, "ratio_traces.json")) as f:
+        for tr in json.load(f)["traces"]:
+            r = tr["result"]
+            res = solve(tr["row_ptr"], tr["col"], tr["w"], tr["t"])
+            assert (res.p, res.q, res.L, res.cycle_edges.cpu().tolist(), res.source,
+                    res.iterations, res.tie) == (r["p"], r["q"], r["T"], r["cycle"], r["source"],
+                                                 r["iterations"], bool(r["tie"]))
+
+
+def test_ratio_tiny_graphs_against_oracle_and_brute_force():
+    rng = np.random.default_rng(21)
+    for it in range(150):
+        n = int(rng.integers(1, 8))
+        rp, cl, w = brute.random_tiny(rng, n, 3, -6, 6)
+        t = rng.integers(1, 6, len(cl))
+        mode = "max" if it % 4 == 0 else "min"
+        sol = native.solve(rp, cl, w, mode=mode, t=t)
+        res = solve(rp, cl, w, t, mode)
+        same(res, sol)
+        assert res.value == brute.optimum(rp, cl, w, mode, t=t)[0]
+
+
+@pytest.mark.parametrize("n,seed,wdt", [(3000, 0, np.int32), (70000, 1, np.int32),
+                                        (200000, 2, np.int64), (1 << 20, 3, np.int32)])
+def test_ratio_random_graphs(n, seed, wdt):
+    g = synth.random_digraph(n, 1, 6, 1, 10000, wdt, seed=seed)
+    t = np.random.default_rng(seed).integers(1, 100, g.m)
+    sol = native.solve(g.row_ptr, g.col, g.w, t=t)
+    for kw in ({}, {"fast_path": False}, {"connect": "push"}, {"int128": True}):
+        res = solve(g.row_ptr, g.col, g.w, t, want_potential=True, **kw)
+        same(res, sol)
+        assert native.certify(g.row_ptr, g.col, g.w, res.p, res.q, res.cycle_edges.cpu().numpy(),
+                              res.potential.cpu().numpy(), res.L, t=t) == 0
+    # max mode
+    solm = native.solve(g.row_ptr, g.col, g.w, mode="max", t=t)
+    same(solve(g.row_ptr, g.col, g.w, t, "max"), solm)
+
+
+def test_ratio_with_unit_times_is_the_mean():
+    g = synth.random_digraph(50000, 1, 5, -500, 500, np.int32, seed=4)
+    t = np.ones(g.m, np.int32)
+    r = solve(g.row_ptr, g.col, g.w, t)
+    m = ocm.min_cycle_mean(*dev(g.row_ptr, g.col, g.w, t)[:3])
+    assert (r.p, r.q, r.cycle_edges.cpu().tolist(), r.iterations, r.tight_edges, r.tie) == \
+        (m.p, m.q, m.cycle_edges.cpu().tolist(), m.iterations, m.tight_edges, m.tie)
+
+
+def test_ratio_ties_and_product_graph_times():
+    # many equal costs and times: ties everywhere
+    for seed in range(3):
+        g = synth.random_digraph(5000, 1, 4, 0, 3, np.int32, seed=seed)
+        t = np.random.default_rng(seed).integers(1, 3, g.m)
+        same(solve(g.row_ptr, g.col, g.w, t), native.solve(g.row_ptr, g.col, g.w, t=t))
+    # a state-space-shaped graph with per-transition times
+    g = synth.product_graph(4, 8, 0.3, 1, 1000, seed=2)
+    t = np.random.default_rng(2).integers(1, 50, g.m)
+    same(solve(g.row_ptr, g.col, g.w, t), native.solve(g.row_ptr, g.col, g.w, t=t))
+
+
+def test_ratio_rejects_bad_times():
+    g = synth.random_digraph(100, 1, 3, 1, 9, np.int32, seed=1)
+    t = np.ones(g.m, np.int32)
+    t[5] = 0
+    with pytest.raises(ocm.OCMError) as ei:
+        solve(g.row_ptr, g.col, g.w, t)
+    assert ei.value.status == ocm.OCM_E_INVALID_ARG
+    t[5] = 1 << 30
+    w = np.full(g.m, 1 << 27, np.int64)   # 2 n max|w| max t = 2^63.6
+    with pytest.raises(ocm.OCMError) as ei:
+        solve(g.row_ptr, g.col, w, t)
+    assert ei.value.status == ocm.OCM_E_OVERFLOW

@@ -298,3 +298,23 @@ def test_max_iters_and_bounds():
     full = native.solve(g.row_ptr, g.col, g.w)
     ok = native.solve(g.row_ptr, g.col, g.w, max_iters=full.iterations)
     assert ok.value == full.value
+
+
+@pytest.mark.parametrize("ring,tail,extra,hlo,hhi,seed",
+                         [(700, 800, 2, 2**47, 2**48, 1), (128, 3000, 3, 2**47, 2**48, 2),
+                          (300, 3000, 1, 2**46, 2**47, 4)])
+def test_deep_tail_values_leave_int64(ring, tail, extra, hlo, hhi, seed):
+    """The int128 instances: the optimum is the light ring's mean (closed form,
+    and Karp's value), every weight passes the 2 n max|w| < 2^62 bound, yet the
+    optimum's potential does not fit int64 (the oracle keeps it in int128 and
+    refuses to export it as int64)."""
+    g = synth.deep_tail_graph(ring, tail, extra, 10, hlo, hhi, seed)
+    assert 2 * g.n * int(np.abs(g.w).max()) < 2**62
+    ring_w = g.w[g.row_ptr[:ring]]
+    want = Fraction(int(ring_w.sum()), ring)
+    sol = native.solve(g.row_ptr, g.col, g.w)
+    assert sol.value == want == native.karp(g.row_ptr, g.col, g.w)
+    assert sorted(int(e) for e in sol.cycle) == sorted(int(e) for e in g.row_ptr[:ring])
+    with pytest.raises(native.OracleError) as ei:
+        native.solve(g.row_ptr, g.col, g.w, want_V=True)
+    assert ei.value.code == native.ORC_E_OVERFLOW
