@@ -351,9 +351,11 @@ ocm_status ocm_max_batched(int64_t G, const int64_t *vptr, const int64_t *eptr,
 
 /* The schedule the last batched call on this thread used: sweep lanes per
  * vertex, chunk size, and whether it was timed now (1) or taken from the
- * autotuner's per-size-class cache (0).  The batched loop runs each
- * iteration as two captured hipGraphs around the rebuild rounds; setting the
- * environment variable OCM_BATCH_GRAPH=0 enqueues the same kernels directly. */
+ * autotuner's per-size-class cache (0).  The batched loop runs its first
+ * iteration as two captured hipGraphs around host-driven rebuild rounds and
+ * every later iteration as one captured hipGraph (device-driven rounds, one
+ * host read per iteration); setting the environment variable
+ * OCM_BATCH_GRAPH=0 enqueues the same kernels directly. */
 void ocm_batched_last_schedule(int32_t *lanes, int32_t *tile, int32_t *tuned);
 
 /* ---------------------------------------------------------------------- */

@@ -74,6 +74,7 @@ struct BCtl {
     unsigned overflow;
     unsigned xcnt;             // tie test: tight non-policy edges listed
     unsigned scnt;             // tie test: special vertices
+    unsigned rounds_open;      // device-driven rebuild rounds of the iteration left unfinished
 };
 
 __device__ __forceinline__ bool chunk_range(const int2* __restrict__ chunks, const unsigned* nch,
@@ -95,12 +96,24 @@ __device__ __forceinline__ bool chunk_range(const int2* __restrict__ chunks, con
 // to the next chunk.
 constexpr unsigned kChunkGrid = 2048;
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2: when the grid is a multiple of 8, XCD x takes the x-th eighth of the
+// list (consecutive chunks, i.e. the same few graphs), so a graph's gathered
+// values stay in one L2 instead of being fetched by all eight.
 template <typename F>
 __device__ __forceinline__ void for_each_chunk(const int2* __restrict__ chunks, const unsigned* nch,
                                                const long long* __restrict__ vptr, int T, F&& f)
 {
     const unsigned nc = *nch;
-    for (unsigned ci = blockIdx.x; ci < nc; ci += gridDim.x) {
+    unsigned lo = 0, hi = nc, first = blockIdx.x, step = gridDim.x;
+    if ((gridDim.x & 7u) == 0u) {
+        const unsigned x = blockIdx.x & 7u;
+        lo = (unsigned)((unsigned long long)nc * x / 8u);
+        hi = (unsigned)((unsigned long long)nc * (x + 1u) / 8u);
+        first = lo + (blockIdx.x >> 3);
+        step = gridDim.x >> 3;
+    }
+    for (unsigned ci = first; ci < hi; ci += step) {
         const int2 c = chunks[ci];
         const int g = c.x;
         const int64_t v0 = c.y;
@@ -112,12 +125,16 @@ __device__ __forceinline__ void for_each_chunk(const int2* __restrict__ chunks, 
 // ---------------------------------------------------------------------------
 // chunk lists
 // ---------------------------------------------------------------------------
+// halt (nullable): while *halt is non-zero every count is 0 (the list is
+// empty and the kernels that take it do nothing).
 __global__ __launch_bounds__(kWG) void k_chunk_count(int G, const int* __restrict__ mode, int want,
                                                      const long long* __restrict__ vptr, int T,
-                                                     unsigned* __restrict__ cnt)
+                                                     unsigned* __restrict__ cnt,
+                                                     const unsigned* halt)
 {
+    const bool off = halt && *halt != 0u;
     for (int g = blockIdx.x * kWG + threadIdx.x; g <= G; g += gridDim.x * kWG) {
-        if (g == G) {
+        if (g == G || off) {
             cnt[g] = 0;
             continue;
         }
@@ -260,6 +277,92 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
     });
 }
 
+// The same sweep over vertex tiles: a workgroup takes its chunk 256 vertices
+// at a time; their out-edges form one contiguous CSR range, streamed through
+// LDS in batches of kBTileEdges (col and w loaded coalesced, the gathered V
+// and the key computed per edge), then each thread walks its own vertex's
+// keys in CSR order for the lowest-position minimum.  Same results as
+// k_sweep (strict "<" in CSR order).
+constexpr int kBTileEdges = 2048;
+
+template <typename WT>
+__global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chunks,
+                                                    const unsigned* nch, int T, GArrays ga,
+                                                    const int* __restrict__ row_ptr,
+                                                    const int* __restrict__ col,
+                                                    const WT* __restrict__ w, int neg,
+                                                    const long long* __restrict__ V,
+                                                    int* __restrict__ pi,
+                                                    const unsigned char* __restrict__ onC)
+{
+    __shared__ int beg[kWG + 1];
+    __shared__ long long key[kBTileEdges];
+    constexpr int U = kBTileEdges / kWG;
+    const int t = threadIdx.x;
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t c0, int64_t c1) {
+        const bool first = ga.iter[g] == 0;
+        const long long L = first ? 1 : ga.L[g];
+        const long long W = first ? 0 : ga.W[g];
+        unsigned long long cnt = 0;
+        unsigned brk = 0;
+        for (int64_t v0 = c0; v0 < c1; v0 += kWG) {
+            const int nv = c1 - v0 < kWG ? (int)(c1 - v0) : kWG;
+            long long own = 0, best = INT64_MAX;
+            int pos = INT32_MAX;
+            __syncthreads();   // beg / key of the previous tile are read
+            if (t < nv) {
+                beg[t] = row_ptr[v0 + t];
+                if (!first) own = V[v0 + t];
+            }
+            if (t == 0) beg[nv] = row_ptr[v0 + nv];
+            __syncthreads();
+            const int e0 = beg[0], e1 = beg[nv];
+            const int mb = t < nv ? beg[t] : 0, me = t < nv ? beg[t + 1] : 0;
+            for (int eb = e0; eb < e1; eb += kBTileEdges) {
+                const int ne = e1 - eb < kBTileEdges ? e1 - eb : kBTileEdges;
+                int c[U];
+                long long wl[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = t + u * kWG;
+                    c[u] = 0;
+                    wl[u] = 0;
+                    if (j < ne) {
+                        c[u] = col[eb + j];
+                        wl[u] = wval(w, eb + j, neg);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int j = t + u * kWG;
+                    if (j < ne) key[j] = first ? wl[u] : V[c[u]] + L * wl[u] - W;
+                }
+                __syncthreads();
+                const int lo = mb > eb ? mb : eb, hi = me < eb + ne ? me : eb + ne;
+                for (int e = lo; e < hi; ++e) {
+                    const long long k = key[e - eb];
+                    if (k < best) {
+                        best = k;
+                        pos = e;
+                    }
+                }
+                __syncthreads();
+            }
+            if (t < nv && pos != INT32_MAX && (first || best < own)) {
+                pi[v0 + t] = pos;
+                cnt++;
+                if (!first && onC[v0 + t]) brk = 1;
+            }
+        }
+        cnt = block_sum_u64(cnt);
+        const unsigned long long bb = block_sum_u64(brk);
+        if (threadIdx.x == 0) {
+            if (cnt) atomicAdd(&ga.changed[g], (unsigned)(cnt > 0xffffffffull ? 0xffffffffu : cnt));
+            if (bb) atomicOr(&ga.cbroken[g], 1u);
+        }
+    });
+}
+
 // After the sweep: converged graphs retire; the others take the fast path
 // (C intact) or the general phases.
 __global__ __launch_bounds__(kWG) void k_after_sweep(int G, GArrays ga, int max_iters,
@@ -346,22 +449,38 @@ __global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chun
         if (!ga.vrun[g]) return;   // finished or stalled graph: its entries stay put
         const int s = ga.s[g];
         unsigned act = 0, prog = 0;
-        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-            Jmp q = Qin[v];
-            if (q.J != s) {
-                const Jmp r = Qin[q.J];
-                long long d;
-                if (__builtin_add_overflow(q.D, r.D, &d)) {
-                    d = 0;
-                    q.H |= kHopOverflow;
-                }
-                q.D = d;
-                q.J = r.J;
-                q.H = ((q.H & ~kHopOverflow) + (r.H & ~kHopOverflow)) | ((q.H | r.H) & kHopOverflow);
-                if (q.J == s) prog = 1;
-                else act = 1;
+        // four entries in flight per thread: loads, then the dependent gathers
+        constexpr int U = 4;
+        for (int64_t vb = v0 + threadIdx.x; vb < v1; vb += U * kWG) {
+            Jmp q[U], r[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t v = vb + u * kWG;
+                if (v < v1) q[u] = Qin[v];
+                else q[u].J = s;
             }
-            Qout[v] = q;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (q[u].J != s) r[u] = Qin[q[u].J];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t v = vb + u * kWG;
+                if (v >= v1) continue;
+                if (q[u].J != s) {
+                    long long d;
+                    if (__builtin_add_overflow(q[u].D, r[u].D, &d)) {
+                        d = 0;
+                        q[u].H |= kHopOverflow;
+                    }
+                    q[u].D = d;
+                    q[u].J = r[u].J;
+                    q[u].H = ((q[u].H & ~kHopOverflow) + (r[u].H & ~kHopOverflow)) |
+                             ((q[u].H | r[u].H) & kHopOverflow);
+                    if (q[u].J == s) prog = 1;
+                    else act = 1;
+                }
+                Qout[v] = q[u];
+            }
         }
         const unsigned long long a = block_sum_u64(act), p = block_sum_u64(prog);
         if (threadIdx.x == 0) {
@@ -375,8 +494,9 @@ __global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chun
 // graph whose round finished nothing while vertices remain never reaches s
 // (fast path: C is no longer the only cycle).
 __global__ __launch_bounds__(kWG) void k_val_update(int G, GArrays ga, int want, int rounds,
-                                                    BCtl* bc)
+                                                    BCtl* bc, const unsigned* halt)
 {
+    if (halt && *halt != 0u) return;
     unsigned running = 0;
     for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
         if (ga.mode[g] != want || !ga.vrun[g]) continue;
@@ -453,9 +573,18 @@ __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chun
     });
 }
 
-// fast or general graph whose values are ready: back to sweeping
-__global__ __launch_bounds__(kWG) void k_values_done(int G, GArrays ga, int want)
+// The iteration's rebuild rounds did not all run (more than the captured
+// number were needed): the host finishes them.
+__global__ void k_rounds_open(BCtl* bc, const Ctl* ctl)
 {
+    if (threadIdx.x == 0) bc->rounds_open = ctl->rmode != 0u ? 1u : 0u;
+}
+
+// fast or general graph whose values are ready: back to sweeping
+__global__ __launch_bounds__(kWG) void k_values_done(int G, GArrays ga, int want,
+                                                     const unsigned* halt)
+{
+    if (halt && *halt != 0u) return;
     for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
         if (ga.mode[g] != want) continue;
         ga.mode[g] = kActive;
@@ -489,11 +618,24 @@ __global__ __launch_bounds__(kWG) void k_pj_round(const int2* __restrict__ chunk
                                                   unsigned long long* __restrict__ Pout)
 {
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
-        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-            const unsigned long long p = Pin[v];
-            const unsigned long long q = Pin[(int)(p >> 32)];
-            const unsigned m0 = (unsigned)p, m1 = (unsigned)q;
-            Pout[v] = (q & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
+        constexpr int U = 4;   // entries in flight per thread
+        for (int64_t vb = v0 + threadIdx.x; vb < v1; vb += U * kWG) {
+            unsigned long long p[U], q[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t v = vb + u * kWG;
+                p[u] = v < v1 ? Pin[v] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (vb + u * kWG < v1) q[u] = Pin[(int)(p[u] >> 32)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t v = vb + u * kWG;
+                if (v >= v1) continue;
+                const unsigned m0 = (unsigned)p[u], m1 = (unsigned)q[u];
+                Pout[v] = (q[u] & 0xffffffff00000000ull) | (m0 < m1 ? m0 : m1);
+            }
         }
     });
 }
@@ -672,10 +814,17 @@ __global__ __launch_bounds__(kWG) void k_conn_init(const int2* __restrict__ chun
 }
 
 // Graphs with a vertex that stays unattached (not in acur) are not strongly
-// connected.
+// connected.  Device-driven rounds (ctl non-null): only after a round that
+// attached nobody (rerr), on that round's bitmap (a0 / a1 by its parity).
 __global__ __launch_bounds__(kWG) void k_conn_fail(int G, int n, const long long* __restrict__ vptr,
-                                                   const unsigned* __restrict__ acur, GArrays ga)
+                                                   const unsigned* __restrict__ acur, GArrays ga,
+                                                   const unsigned* __restrict__ a1 = nullptr,
+                                                   const Ctl* ctl = nullptr)
 {
+    if (ctl) {
+        if (!ctl->rerr) return;
+        if (ctl->rk & 1u) acur = a1;
+    }
     const int64_t words = ((int64_t)n + 31) / 32;
     for (int64_t w = (int64_t)blockIdx.x * kWG + threadIdx.x; w < words;
          w += (int64_t)gridDim.x * kWG) {
@@ -924,6 +1073,7 @@ struct BWs {
     void* rscratch;
     unsigned* abits[2];
     unsigned char* marks;
+    unsigned char* marks2;      // device-driven rounds: the other round parity's marks
     unsigned char* span_flag;   // rebuild: spans holding a rebuilt graph (flags, then list)
     int* spans;
     unsigned* bad;
@@ -1002,6 +1152,7 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m, size_t sub_bytes)
     w.abits[0] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.abits[1] = (unsigned*)take(4 * ((N + 31) / 32 + 1));
     w.marks = (unsigned char*)take(N + 16);
+    w.marks2 = (unsigned char*)take(N + 16);
     const size_t nsp = (size_t)ocm::round_spans((int)n) + 1;
     w.span_flag = (unsigned char*)take(nsp);
     w.spans = (int*)take(4 * nsp);
@@ -1052,6 +1203,8 @@ struct BCtx {
     Schedule sch;
     ocm_profile* prof = nullptr;
     bool rev_built = false;
+    bool tile_sweep = true;   // improvement sweeps over vertex tiles (else lanes per vertex)
+    bool device_rounds = true;   // iterations after the first decide their rounds on the device
     int max_n = 1;
 };
 
@@ -1071,15 +1224,51 @@ unsigned chunk_grid(const BCtx& c)
 
 unsigned chunk_grid(unsigned nch) { return nch < ocm::b::kChunkGrid ? nch : ocm::b::kChunkGrid; }
 
+// Workgroups of `kernel` that are resident on the device at once, rounded
+// down to a multiple of 8 (one per XCD slot): a grid-stride chunk kernel
+// launched with at most this many runs in a single wave of workgroups, with
+// no tail of late ones (2048 workgroups of a kernel that fits 6 per CU would
+// run as 1536 plus a third-full second wave).
+unsigned resident_grid(const void* kernel)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, unsigned> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(dev, kernel);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, ocm::kWG, 0) != hipSuccess ||
+        per < 1)
+        per = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 8;
+    (void)hipGetLastError();
+    unsigned g = (unsigned)(per * cus) & ~7u;
+    if (g < 8) g = 8;
+    cache[key] = g;
+    return g;
+}
+
+// Grid of a chunk kernel: the chunk bound, at most one resident wave.
+unsigned kgrid(unsigned most, const void* kernel)
+{
+    const unsigned r = resident_grid(kernel);
+    return most < r ? most : r;
+}
+
 // Chunk list of the graphs in `want` (a mode, -1 = every graph not done,
 // -2 = every graph), built on the device; kernels read the count from
 // device memory, so nothing here waits for the host.
-void enqueue_chunks(BCtx& c, int want)
+void enqueue_chunks(BCtx& c, int want, const unsigned* halt = nullptr)
 {
     GArrays& a = c.ws.ga;
     const int T = c.sch.chunk;
     ocm::b::k_chunk_count<<<ocm::stride_grid(c.G + 1), ocm::kWG, 0, c.st>>>((int)c.G, a.mode, want,
-                                                                          a.vptr, T, a.ccnt);
+                                                                          a.vptr, T, a.ccnt, halt);
     ocm::launch_exclusive_scan(c.G + 1, a.ccnt, a.coff, a.ctot, c.st);
     ocm::b::k_chunk_fill<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a.ccnt, a.coff,
                                                                      a.vptr, T, c.ws.chunks,
@@ -1132,6 +1321,21 @@ void launch_bsweep(BCtx& c, unsigned nch, bool tie, int* xs = nullptr, int* ys =
                    unsigned* xcnt = nullptr, unsigned xcap = 0)
 {
     if (nch == 0) return;
+    if (!tie && c.tile_sweep) {   // improvement sweeps over vertex tiles
+        BWs& ws = c.ws;
+        if (c.wtype == OCM_W_I64)
+            ocm::b::k_sweep_tile<long long><<<
+                kgrid(chunk_grid(nch), (const void*)ocm::b::k_sweep_tile<long long>), ocm::kWG, 0,
+                c.st>>>(
+                ws.chunks, &ws.bc->nchunks, c.sch.chunk, ws.ga, c.row_ptr, c.col,
+                (const long long*)c.w, c.neg, ws.V, ws.pi, ws.onC);
+        else
+            ocm::b::k_sweep_tile<int><<<kgrid(chunk_grid(nch), (const void*)ocm::b::k_sweep_tile<int>),
+                                        ocm::kWG, 0, c.st>>>(
+                ws.chunks, &ws.bc->nchunks, c.sch.chunk, ws.ga, c.row_ptr, c.col, (const int*)c.w,
+                c.neg, ws.V, ws.pi, ws.onC);
+        return;
+    }
     if (c.wtype == OCM_W_I64) launch_bsweep_t<long long>(c, nch, tie, xs, ys, xcnt, xcap);
     else launch_bsweep_t<int>(c, nch, tie, xs, ys, xcnt, xcap);
 }
@@ -1179,13 +1383,14 @@ int jump_rounds(const BCtx& c)
 // policy path has fewer than max_n edges, so K = ceil(log2 max_n) rounds
 // finish every graph that reaches its source.  kFast graphs that stop
 // progressing fall back to the general phases; kGeneral ones fail.
-void enqueue_values(BCtx& c, int want)
+// halt (nullable): nothing runs while *halt is non-zero.
+void enqueue_values(BCtx& c, int want, const unsigned* halt = nullptr)
 {
     BWs& ws = c.ws;
     GArrays& a = ws.ga;
     const int T = c.sch.chunk;
     const unsigned mc = chunk_grid(c);
-    enqueue_chunks(c, want);
+    enqueue_chunks(c, want, halt);
     if (c.wtype == OCM_W_I64)
         ocm::b::k_val_init<long long><<<mc, ocm::kWG, 0, c.st>>>(
             ws.chunks, &ws.bc->nchunks, T, a, c.col, ws.pi, (const long long*)c.w, c.neg, ws.succ,
@@ -1199,15 +1404,16 @@ void enqueue_values(BCtx& c, int want)
     ocm::launch_fill_u32(ws.bc->vrun_round, 32, 0u, c.st);
     for (int r = 0; r < R; ++r) {
         ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, r,
-                                                                         ws.bc);
+                                                                         ws.bc, halt);
         ocm::b::k_val_round<<<chunk_grid(c), ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a,
                                                                 ws.Q[r & 1], ws.Q[(r + 1) & 1],
                                                                 &ws.bc->vrun_round[r]);
     }
-    ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, R, ws.bc);
+    ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, R, ws.bc,
+                                                                     halt);
     ocm::b::k_val_final<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, want, ws.Q[0],
                                                    ws.Q[1], ws.V, ws.hop);
-    ocm::b::k_values_done<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want);
+    ocm::b::k_values_done<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, halt);
 }
 
 // Cycles, exact vote and the start of the rebuild for kGeneral graphs.
@@ -1327,14 +1533,76 @@ ocm_status host_connect(BCtx& c)
     return OCM_OK;
 }
 
-// The two fixed parts of an iteration as captured hipGraphs.
+// Rebuild rounds decided on the device (as ocm_min's), over the whole union:
+// graphs that are not rebuilt count as attached in both bitmaps.  Round k
+// reads abits[k & 1] and completes abits[(k + 1) & 1]; the marks alternate
+// the same way.  Pull only (policy 1) while no reverse CSR exists.
+constexpr int kLoopRounds = 16;   // rounds captured in each iteration
+constexpr unsigned kBPushMin = 1u << 16;
+
+void enqueue_rounds(BCtx& c, int k0, int k1)
+{
+    BWs& ws = c.ws;
+    ocm::Ctl* cc = (ocm::Ctl*)ws.vctl;
+    unsigned char* mk[2] = {ws.marks, ws.marks2};
+    for (int k = k0; k <= k1; ++k)
+        ocm::launch_round(k, c.n, c.row_ptr, c.col, ws.rin_ptr, ws.rin, ws.abits[k & 1],
+                          ws.abits[(k + 1) & 1], mk[k & 1], mk[(k + 1) & 1], ws.pi, nullptr, cc,
+                          &cc->lane[0].pedges, c.rev_built ? 0 : 1, kBPushMin, c.rev_built, c.st);
+}
+
+// One whole iteration without a host read: sweep, retirement, fast-path
+// values, cycles, vote, rebuild init, kLoopRounds device-driven rounds, the
+// failure marks of a round that attached nobody, then the general graphs'
+// values -- these only once the rounds are over (the host finishes them
+// otherwise, flagged in rounds_open).
+void enqueue_iteration(BCtx& c, int max_iters, bool fast_path)
+{
+    BWs& ws = c.ws;
+    ocm::Ctl* cc = (ocm::Ctl*)ws.vctl;
+    enqueue_head(c, max_iters, fast_path);
+    ocm::launch_round_setup_dev(cc, c.rev_built ? 0 : 1, kBPushMin, c.st);
+    enqueue_rounds(c, 1, kLoopRounds);
+    ocm::b::k_conn_fail<<<ocm::stride_grid((c.n + 31) / 32), ocm::kWG, 0, c.st>>>(
+        (int)c.G, c.n, ws.ga.vptr, ws.abits[0], ws.ga, ws.abits[1], cc);
+    ocm::b::k_rounds_open<<<1, 64, 0, c.st>>>(ws.bc, cc);
+    enqueue_values(c, ocm::b::kGeneral, &cc->rmode);
+}
+
+// Rounds left open by an iteration: queued in batches of 8 until the device
+// says the rebuild is over, then the failure marks and the values.
+ocm_status finish_rounds(BCtx& c)
+{
+    BWs& ws = c.ws;
+    ocm::Ctl* cc = (ocm::Ctl*)ws.vctl;
+    ocm::CtlView h;
+    int k = kLoopRounds;
+    for (;;) {
+        enqueue_rounds(c, k + 1, k + 8);
+        k += 8;
+        BHIP(hipGetLastError());
+        BHIP(ocm::host_read_ctl(cc, &h, c.st));
+        if (h.rmode == 0) break;
+        if (k > c.n + 8) return bfail(OCM_E_HIP, "rebuild rounds did not finish");
+    }
+    ocm::b::k_conn_fail<<<ocm::stride_grid((c.n + 31) / 32), ocm::kWG, 0, c.st>>>(
+        (int)c.G, c.n, ws.ga.vptr, ws.abits[0], ws.ga, ws.abits[1], cc);
+    enqueue_values(c, ocm::b::kGeneral);
+    BHIP(hipGetLastError());
+    return OCM_OK;
+}
+
+// The fixed parts of an iteration as captured hipGraphs: head and tail
+// around the host-driven rounds of the first iteration, then whole
+// iterations with device-driven rounds.
 struct Loop {
     hipStream_t cs = nullptr;
-    hipGraphExec_t head = nullptr, tail = nullptr;
+    hipGraphExec_t head = nullptr, tail = nullptr, iter = nullptr;
     ~Loop()
     {
         if (head) (void)hipGraphExecDestroy(head);
         if (tail) (void)hipGraphExecDestroy(tail);
+        if (iter) (void)hipGraphExecDestroy(iter);
         if (cs) (void)hipStreamDestroy(cs);
     }
 };
@@ -1655,6 +1923,7 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
     c.neg = neg;
     c.st = (hipStream_t)stream;
     c.sch.lanes = o.schedule > 0 ? o.schedule : default_lanes(u->n, u->m);
+    c.tile_sweep = o.schedule <= 0;
     c.sch.chunk = 1024;
     if (!(c.sch.lanes == 1 || c.sch.lanes == 2 || c.sch.lanes == 4 || c.sch.lanes == 8 ||
           c.sch.lanes == 16 || c.sch.lanes == 32 || c.sch.lanes == 64))
@@ -1669,6 +1938,8 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
 
     ocm::b::k_bctl_clear<<<1, 64, 0, c.st>>>(ws.bc);
     ocm::launch_fill_u8(ws.span_flag, ocm::round_spans(c.n) + 1, 0, c.st);
+    ocm::launch_fill_u8(ws.marks, (int64_t)c.n + 16, 0, c.st);
+    ocm::launch_fill_u8(ws.marks2, (int64_t)c.n + 16, 0, c.st);
     BHIP(hipMemcpyAsync(a.vptr, vptr, 8 * (size_t)(G + 1), hipMemcpyHostToDevice, c.st));
     BHIP(hipMemcpyAsync(a.eptr, eptr, 8 * (size_t)(G + 1), hipMemcpyHostToDevice, c.st));
     ocm::b::k_graph_init<<<ocm::stride_grid(G), ocm::kWG, 0, c.st>>>((int)G, a);
@@ -1720,17 +1991,31 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
         BTRY(capture(c, lp, &lp.head, [&] { enqueue_head(c, o.max_iters, o.fast_path != 0); }));
         BTRY(capture(c, lp, &lp.tail, [&] { enqueue_values(c, ocm::b::kGeneral); }));
     }
+    // the first iteration (every graph rebuilds) with host-driven rounds,
+    // which build the reverse CSR when push rounds pay; then whole
+    // iterations with device-driven rounds, one host read each
     for (int guard = 0;; ++guard) {
         if (guard > (1 << 20)) return bfail(OCM_E_NOT_CONVERGED, "iteration guard");
-        if (use_graph) BHIP(hipGraphLaunch(lp.head, c.st));
-        else enqueue_head(c, o.max_iters, o.fast_path != 0);
+        if (guard == 0 || !c.device_rounds) {
+            if (use_graph) BHIP(hipGraphLaunch(lp.head, c.st));
+            else enqueue_head(c, o.max_iters, o.fast_path != 0);
+            BHIP(hipGetLastError());
+            BTRY(bread(c));
+            if (c.h.nactive == 0) break;   // every graph converged or failed
+            BTRY(host_connect(c));
+            if (use_graph) BHIP(hipGraphLaunch(lp.tail, c.st));
+            else enqueue_values(c, ocm::b::kGeneral);
+            BHIP(hipGetLastError());
+            continue;
+        }
+        if (use_graph && !lp.iter)
+            BTRY(capture(c, lp, &lp.iter, [&] { enqueue_iteration(c, o.max_iters, o.fast_path != 0); }));
+        if (use_graph) BHIP(hipGraphLaunch(lp.iter, c.st));
+        else enqueue_iteration(c, o.max_iters, o.fast_path != 0);
         BHIP(hipGetLastError());
         BTRY(bread(c));
-        if (c.h.nactive == 0) break;   // every graph converged or failed
-        BTRY(host_connect(c));
-        if (use_graph) BHIP(hipGraphLaunch(lp.tail, c.st));
-        else enqueue_values(c, ocm::b::kGeneral);
-        BHIP(hipGetLastError());
+        if (c.h.nactive == 0) break;
+        if (c.h.rounds_open) BTRY(finish_rounds(c));
     }
 
     // per-graph results

@@ -267,6 +267,9 @@ void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const u
 // round must be a pull round.  Progress: rk, rleft, rerr, rmode.
 void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, int policy, unsigned push_min,
                         hipStream_t st);
+// launch_round_setup with left / front taken on the device from the lanes'
+// counts of the rebuild init (ctl cleared with kClrCount before the init).
+void launch_round_setup_dev(Ctl* ctl, int policy, unsigned push_min, hipStream_t st);
 void launch_round(int k, int n, const int* row_ptr, const int* col, const int* rin_ptr,
                   const int* rin, const unsigned* acur, unsigned* anext, unsigned char* marks,
                   unsigned char* marks_next, int* pi, int* layer, Ctl* ctl,

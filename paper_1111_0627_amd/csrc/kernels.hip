@@ -2558,6 +2558,35 @@ __global__ void k_round_setup(Ctl* c, unsigned left, unsigned front, int policy,
     }
 }
 
+// The same start, from the counts the rebuild init left in the lanes (got:
+// C's component, left: unattached), with no host read in between (one wave).
+__global__ void k_round_setup_dev(Ctl* c, int policy, unsigned push_min)
+{
+    const int l = threadIdx.x;
+    unsigned long long got = 0, left = 0;
+    if (l < kLanes) {
+        got = c->lane[l].got;
+        left = c->lane[l].left;
+        c->lane[l].rpack = 0;
+    }
+    got = wave_sum_u64(got);
+    left = wave_sum_u64(left);
+    if (l == 0) {
+        c->rleft = (unsigned)left;
+        c->rfront = (unsigned)got;
+        c->rerr = 0;
+        c->rk = 0;
+        c->rmarks = 0;
+        c->rpack = 0;
+        c->rmode = round_mode((unsigned)left, (unsigned)got, policy, push_min);
+    }
+}
+
+void launch_round_setup_dev(Ctl* ctl, int policy, unsigned push_min, hipStream_t st)
+{
+    k_round_setup_dev<<<1, 64, 0, st>>>(ctl, policy, push_min);
+}
+
 void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, int policy, unsigned push_min,
                         hipStream_t st)
 {

@@ -190,3 +190,41 @@ def test_batched_ties_resolved_exactly(mode):
         assert res.tie(k) == bool(sol.tie), k
         ties += sol.tie
     assert ties > 10
+
+
+@pytest.mark.parametrize("graph", ["1", "0"])
+def test_batched_deep_rebuilds_on_device(monkeypatch, graph):
+    """Sparse graphs (out-degree 0-1 plus the ring) whose later rebuilds need
+    more than the 16 rounds captured per iteration: the host finishes them;
+    results equal the oracle's, with and without graph capture."""
+    monkeypatch.setenv("OCM_BATCH_GRAPH", graph)
+    gs = [synth.random_digraph(3000, 0, 1, 1, 10000, np.int32, seed=[9, s])
+          for s in (2, 6, 13, 17, 38)]
+    gs += [synth.random_digraph(n, 1, 6, 1, 100, np.int32, seed=[4, n]) for n in (50, 900, 20000)]
+    u, vptr, eptr = synth.disjoint_union(gs)
+    res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr)
+    assert all(s == ocm.OCM_OK for s in res.status)
+    for k, g in enumerate(gs):
+        sol = native.solve(g.row_ptr, g.col, g.w)
+        cyc = (res.cycle(k).cpu().numpy() - eptr[k]).tolist()
+        assert (res.p[k], res.q[k], cyc, res.iterations[k], res.tie(k)) == \
+            (sol.p, sol.q, sol.cycle.tolist(), sol.iterations, bool(sol.tie)), k
+
+
+def test_batched_failure_in_a_later_rebuild():
+    """A graph whose first rebuild succeeds (its first cycle is in a sink
+    component) but whose second one cannot attach every vertex: it fails
+    with OCM_E_NOT_STRONGLY_CONNECTED in a device-driven rebuild, alone."""
+    # a1 <-> a2 (weight 5 each, mean 5), a1 -> b and a2 -> b (weight 1), b -> b (10)
+    bad = synth.Graph(np.array([0, 2, 4, 5], np.int32), np.array([2, 1, 2, 0, 2], np.int32),
+                      np.array([1, 5, 1, 5, 10], np.int32))
+    with pytest.raises(native.OracleError) as ei:
+        native.solve(bad.row_ptr, bad.col, bad.w)
+    assert ei.value.code == native.ORC_E_NOT_STRONGLY_CONNECTED
+    good = [synth.random_digraph(n, 1, 4, 1, 50, np.int32, seed=[6, n]) for n in (400, 5000)]
+    u, vptr, eptr = synth.disjoint_union([good[0], bad, good[1]])
+    res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr)
+    assert res.status == [ocm.OCM_OK, ocm.OCM_E_NOT_STRONGLY_CONNECTED, ocm.OCM_OK]
+    for k, g in ((0, good[0]), (2, good[1])):
+        sol = native.solve(g.row_ptr, g.col, g.w)
+        assert (res.p[k], res.q[k], res.iterations[k]) == (sol.p, sol.q, sol.iterations)
