@@ -60,6 +60,9 @@ def lib():
         L.orc_solve_ratio.argtypes = [i64, i64, P, P, P, P, C.c_int, i32, C.c_int,
                                       C.POINTER(_Result), P, i64, P, P]
         L.orc_solve_ratio.restype = C.c_int
+        L.orc_solve_mc.argtypes = [i64, i64, P, P, P, C.c_int, i32, C.c_int,
+                                   C.POINTER(_Result), P, i64, P, P]
+        L.orc_solve_mc.restype = C.c_int
         L.orc_certify_ratio.argtypes = [i64, i64, P, P, P, P, C.c_int, i64, i64, P, i64, P,
                                         i64]
         L.orc_certify_ratio.restype = C.c_int
@@ -157,6 +160,24 @@ def solve(row_ptr, col, w, mode: str = "min", max_iters: int = 0,
         raise OracleError(rc, "solve")
     return Solution(res.p, res.q, cyc[:res.cycle_len].copy(), res.source,
                     res.iterations, res.tie, res.ncycles_first, res.W, res.L, res.tight, V, pi)
+
+
+def solve_multichain(row_ptr, col, w, mode: str = "min", max_iters: int = 0,
+                     tie: bool = True, want_pi: bool = False) -> Solution:
+    """Multichain policy iteration (every policy cycle keeps its own gain; no
+    rebuild): same optimum, its own trajectory and critical cycle."""
+    rp, cl, ww = _csr(row_ptr, col, w)
+    n, m = len(rp) - 1, len(cl)
+    res = _Result()
+    cyc = np.zeros(max(n, 1), np.int32)
+    pi = np.zeros(n, np.int32) if want_pi else None
+    rc = lib().orc_solve_mc(n, m, _ptr(rp), _ptr(cl), _ptr(ww), int(mode == "max"), max_iters,
+                            int(tie), C.byref(res), _ptr(cyc), n, None,
+                            _ptr(pi) if want_pi else None)
+    if rc:
+        raise OracleError(rc, "solve_multichain")
+    return Solution(res.p, res.q, cyc[:res.cycle_len].copy(), res.source, res.iterations,
+                    res.tie, res.ncycles_first, res.W, res.L, res.tight, None, pi)
 
 
 def certify(row_ptr, col, w, p, q, cycle, V, K, mode: str = "min", t=None) -> int:

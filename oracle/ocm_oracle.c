@@ -749,3 +749,241 @@ out:
     free(index); free(low); free(stk); free(cs_v); free(cs_e); free(onstk);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Multichain policy iteration (not in the paper: the variant that skips the */
+/* rebuild of Alg. 2).  Every cycle of the policy graph keeps its own gain   */
+/* lambda_r = W_r / L_r (weight and length of the cycle with smallest vertex */
+/* r); a vertex's gain is that of the cycle its policy path reaches, and its */
+/* value V is scaled by that cycle's L: V(r) = 0 at each cycle's smallest    */
+/* vertex, V(v) = V(succ v) + L_r * w(pi v) - W_r.  An edge v->u offers the  */
+/* pair (gain of u, bias (V(u) + L_u * w - W_u) / L_u); a vertex moves to the */
+/* lowest-position edge with the lexicographically smallest pair when that   */
+/* pair is strictly below its own (gain, V(v) / L_v).  The first sweep is   */
+/* R1's, and the stop rule R8's.  At the end the optimum is the smallest     */
+/* gain, C the policy cycle attaining it with the smallest vertex.           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t *cw, *cl;      /* per cycle rep: weight and length (0 elsewhere) */
+} orc_mc;
+
+/* gain of vertex v: (cw, cl) of its cycle */
+#define MC_GW(st, mc, v) ((mc)->cw[(st)->rep[v]])
+#define MC_GL(st, mc, v) ((mc)->cl[(st)->rep[v]])
+
+static int64_t mc_sweep(orc_state *st, const orc_mc *mc)
+{
+    int64_t changed = 0;
+    for (int64_t v = 0; v < st->n; ++v) {
+        int64_t e0 = st->row_ptr[v], e1 = st->row_ptr[v + 1];
+        if (st->pi[v] < 0) {   /* R1 */
+            int32_t arg = -1;
+            int64_t best = 0;
+            for (int64_t e = e0; e < e1; ++e)
+                if (arg < 0 || st->w[e] < best) { best = st->w[e]; arg = (int32_t)e; }
+            st->pi[v] = arg;
+            ++changed;
+            continue;
+        }
+        /* best (gain bw/bl, bias bb/bl) over the out-edges, CSR order, strict < */
+        int32_t arg = -1;
+        i128 bw = 0, bl = 1, bb = 0;
+        for (int64_t e = e0; e < e1; ++e) {
+            int32_t u = st->col[e];
+            i128 wu = MC_GW(st, mc, u), lu = MC_GL(st, mc, u);
+            i128 nb = st->val[u] + lu * st->w[e] - wu;     /* bias numerator over lu */
+            int less;
+            if (arg < 0) less = 1;
+            else if (wu * bl != bw * lu) less = wu * bl < bw * lu;
+            else less = nb * bl < bb * lu;
+            if (less) { arg = (int32_t)e; bw = wu; bl = lu; bb = nb; }
+        }
+        /* own pair: (gain of v, V(v) / L_v) */
+        i128 ow = MC_GW(st, mc, v), ol = MC_GL(st, mc, v), ob = st->val[v];
+        int better;
+        if (bw * ol != ow * bl) better = bw * ol < ow * bl;
+        else better = bb * ol < ob * bl;
+        if (better) { st->pi[v] = arg; ++changed; }
+    }
+    st->iter++;
+    return changed;
+}
+
+/* Per-cycle sums and the values toward every cycle's smallest vertex. */
+static void mc_values(orc_state *st, orc_mc *mc)
+{
+    const int64_t n = st->n;
+    for (int64_t v = 0; v < n; ++v) { mc->cw[v] = 0; mc->cl[v] = 0; }
+    for (int64_t r = 0; r < n; ++r) {
+        if (!st->on_cycle[r] || st->rep[r] != r) continue;
+        int32_t y = (int32_t)r;
+        do {
+            mc->cw[r] += st->w[st->pi[y]];
+            mc->cl[r] += 1;
+            y = st->col[st->pi[y]];
+        } while (y != r);
+    }
+    /* backward breadth-first search from every cycle's smallest vertex */
+    int64_t head = 0, tail = 0;
+    for (int64_t r = 0; r < n; ++r)
+        if (st->on_cycle[r] && st->rep[r] == r) { st->val[r] = 0; st->queue[tail++] = (int32_t)r; }
+    while (head < tail) {
+        int32_t v = st->queue[head++];
+        for (int64_t i = st->in_ptr[v]; i < st->in_ptr[v + 1]; ++i) {
+            int32_t e = st->in_edge[i];
+            int32_t u = st->src[e];
+            if (st->pi[u] != e) continue;
+            if (st->on_cycle[u] && st->rep[u] == u) continue;   /* a cycle's own source */
+            int32_t r = st->rep[u];
+            st->val[u] = st->val[v] + (i128)mc->cl[r] * st->w[e] - mc->cw[r];
+            st->queue[tail++] = u;
+        }
+    }
+}
+
+/* Exact uniqueness of C for the multichain result: another policy cycle
+ * with the optimal mean, or a tight non-policy edge inside a strongly
+ * connected component of the tight subgraph among vertices of optimal gain
+ * (an edge v->u is tight when u has the same gain and its bias equals
+ * V(v) / L_v). */
+static int mc_tight(const orc_state *st, const orc_mc *mc, int64_t e, int32_t v)
+{
+    int32_t u = st->col[e];
+    i128 wu = MC_GW(st, mc, u), lu = MC_GL(st, mc, u);
+    i128 wv = MC_GW(st, mc, v), lv = MC_GL(st, mc, v);
+    if (wu * lv != wv * lu) return 0;
+    i128 nb = st->val[u] + lu * st->w[e] - wu;
+    return nb * lv == st->val[v] * lu;
+}
+
+static int mc_tie(orc_state *st, const orc_mc *mc, int64_t W, int64_t L, int64_t *tight)
+{
+    const int64_t n = st->n;
+    int ncrit = 0;
+    for (int64_t r = 0; r < n; ++r)
+        if (st->on_cycle[r] && st->rep[r] == r && (i128)mc->cw[r] * L == (i128)W * mc->cl[r]) ++ncrit;
+    *tight = 0;
+    for (int64_t v = 0; v < n; ++v)
+        for (int64_t e = st->row_ptr[v]; e < st->row_ptr[v + 1]; ++e)
+            if (e != st->pi[v] && mc_tight(st, mc, e, (int32_t)v)) ++*tight;
+    if (ncrit > 1) return 1;
+    /* Tarjan over the tight subgraph of the optimal-gain vertices */
+    int32_t *index = malloc(sizeof(int32_t) * n), *low = malloc(sizeof(int32_t) * n);
+    int32_t *comp = malloc(sizeof(int32_t) * n), *stk = malloc(sizeof(int32_t) * n);
+    int32_t *cs_v = malloc(sizeof(int32_t) * n);
+    int64_t *cs_e = malloc(sizeof(int64_t) * n);
+    uint8_t *onstk = calloc(n, 1), *opt = calloc(n, 1);
+    int tie = -1;
+    if (!index || !low || !comp || !stk || !cs_v || !cs_e || !onstk || !opt) goto out;
+    for (int64_t v = 0; v < n; ++v) {
+        index[v] = -1; comp[v] = -1;
+        opt[v] = (i128)MC_GW(st, mc, v) * L == (i128)W * MC_GL(st, mc, v);
+    }
+    int32_t counter = 0, ncomp = 0;
+    int64_t sp = 0, csp = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        if (index[r] != -1 || !opt[r]) continue;
+        cs_v[csp] = (int32_t)r; cs_e[csp] = st->row_ptr[r]; ++csp;
+        index[r] = low[r] = counter++;
+        stk[sp++] = (int32_t)r; onstk[r] = 1;
+        while (csp > 0) {
+            int32_t v = cs_v[csp - 1];
+            int64_t e = cs_e[csp - 1];
+            if (e < st->row_ptr[v + 1]) {
+                cs_e[csp - 1] = e + 1;
+                int32_t u = st->col[e];
+                if (!opt[u]) continue;
+                if (!(st->pi[v] == e || mc_tight(st, mc, e, v))) continue;
+                if (index[u] == -1) {
+                    index[u] = low[u] = counter++;
+                    stk[sp++] = u; onstk[u] = 1;
+                    cs_v[csp] = u; cs_e[csp] = st->row_ptr[u]; ++csp;
+                } else if (onstk[u] && index[u] < low[v]) {
+                    low[v] = index[u];
+                }
+            } else {
+                --csp;
+                if (csp > 0) {
+                    int32_t p = cs_v[csp - 1];
+                    if (low[v] < low[p]) low[p] = low[v];
+                }
+                if (low[v] == index[v]) {
+                    int32_t x;
+                    do { x = stk[--sp]; onstk[x] = 0; comp[x] = ncomp; } while (x != v);
+                    ++ncomp;
+                }
+            }
+        }
+    }
+    tie = 0;
+    for (int64_t v = 0; v < n && !tie; ++v) {
+        if (!opt[v]) continue;
+        for (int64_t e = st->row_ptr[v]; e < st->row_ptr[v + 1]; ++e) {
+            if (st->pi[v] == e || !opt[st->col[e]] || !mc_tight(st, mc, e, (int32_t)v)) continue;
+            if (comp[v] == comp[st->col[e]]) { tie = 1; break; }
+        }
+    }
+out:
+    free(index); free(low); free(comp); free(stk); free(cs_v); free(cs_e); free(onstk); free(opt);
+    return tie;
+}
+
+int orc_solve_mc(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                 const int64_t *w64, int negate, int32_t max_iters, int do_tie,
+                 orc_result *res, int32_t *cycle_edges, int64_t cap, int64_t *val_out,
+                 int32_t *pi_out)
+{
+    int rc;
+    orc_state *st = orc_state_new(n, m, row_ptr, col, w64, negate, &rc);
+    if (!st) return rc;
+    orc_mc mc;
+    mc.cw = calloc(n, sizeof(int64_t));
+    mc.cl = calloc(n, sizeof(int64_t));
+    memset(res, 0, sizeof(*res));
+    if (!mc.cw || !mc.cl) { rc = ORC_E_NOMEM; goto done; }
+    for (;;) {
+        int64_t changed = mc_sweep(st, &mc);
+        if (st->iter >= 2 && changed == 0) break;               /* R8 */
+        if (max_iters > 0 && st->iter >= max_iters) { rc = ORC_E_NOT_CONVERGED; goto done; }
+        int64_t nc = orc_state_cycles(st);
+        if (st->iter == 1) res->ncycles_first = (int32_t)nc;
+        mc_values(st, &mc);
+    }
+    {
+        /* C: the smallest gain, then the smallest rep */
+        int32_t s = -1;
+        for (int64_t r = 0; r < n; ++r) {
+            if (!st->on_cycle[r] || st->rep[r] != r) continue;
+            if (s < 0 || (i128)mc.cw[r] * mc.cl[s] < (i128)mc.cw[s] * mc.cl[r]) s = (int32_t)r;
+        }
+        int64_t W = mc.cw[s], L = mc.cl[s];
+        int64_t g = gcd64(W, L);
+        res->p = (negate ? -W : W) / g;
+        res->q = L / g;
+        res->W = W; res->L = L;
+        res->source = s;
+        res->iterations = st->iter;
+        res->cycle_len = L;
+        if (cycle_edges) {
+            if (cap < L) { rc = ORC_E_CAPACITY; goto done; }
+            int32_t y = s;
+            for (int64_t i = 0; i < L; ++i) {
+                cycle_edges[i] = st->pi[y];
+                y = st->col[st->pi[y]];
+            }
+        }
+        int64_t tight = 0;
+        res->tie = do_tie ? mc_tie(st, &mc, W, L, &tight) : -1;
+        res->tight = tight;
+        if (pi_out) orc_state_get_pi(st, pi_out);
+        if (val_out) {
+            rc = orc_state_get_val(st, val_out);
+            if (rc) goto done;
+        }
+        rc = ORC_OK;
+    }
+done:
+    free(mc.cw); free(mc.cl);
+    orc_state_free(st);
+    return rc;
+}
