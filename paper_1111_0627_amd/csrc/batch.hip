@@ -75,6 +75,7 @@ struct BCtl {
     unsigned xcnt;             // tie test: tight non-policy edges listed
     unsigned scnt;             // tie test: special vertices
     unsigned rounds_open;      // device-driven rebuild rounds of the iteration left unfinished
+    unsigned wide32;           // some value left int32: sweeps gather V, not its int32 copy
 };
 
 __device__ __forceinline__ bool chunk_range(const int2* __restrict__ chunks, const unsigned* nch,
@@ -293,12 +294,15 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
                                                     const WT* __restrict__ w, int neg,
                                                     const long long* __restrict__ V,
                                                     int* __restrict__ pi,
-                                                    const unsigned char* __restrict__ onC)
+                                                    const unsigned char* __restrict__ onC,
+                                                    const int* __restrict__ V32, const BCtl* bc)
 {
     __shared__ int beg[kWG + 1];
     __shared__ long long key[kBTileEdges];
     constexpr int U = kBTileEdges / kWG;
     const int t = threadIdx.x;
+    // every value written so far fits int32: gather the 4-byte copy
+    const bool use32 = bc->wide32 == 0u;
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t c0, int64_t c1) {
         const bool first = ga.iter[g] == 0;
         const long long L = first ? 1 : ga.L[g];
@@ -312,7 +316,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
             __syncthreads();   // beg / key of the previous tile are read
             if (t < nv) {
                 beg[t] = row_ptr[v0 + t];
-                if (!first) own = V[v0 + t];
+                if (!first) own = use32 ? (long long)V32[v0 + t] : V[v0 + t];
             }
             if (t == 0) beg[nv] = row_ptr[v0 + nv];
             __syncthreads();
@@ -335,7 +339,9 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int j = t + u * kWG;
-                    if (j < ne) key[j] = first ? wl[u] : V[c[u]] + L * wl[u] - W;
+                    if (j < ne)
+                        key[j] = first ? wl[u]
+                                       : (use32 ? (long long)V32[c[u]] : V[c[u]]) + L * wl[u] - W;
                 }
                 __syncthreads();
                 const int lo = mb > eb ? mb : eb, hi = me < eb + ne ? me : eb + ne;
@@ -542,7 +548,8 @@ __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chun
                                                    const unsigned* nch, int T, GArrays ga,
                                                    int want, const Jmp* __restrict__ Q0,
                                                    const Jmp* __restrict__ Q1,
-                                                   long long* __restrict__ V, int* __restrict__ hop)
+                                                   long long* __restrict__ V, int* __restrict__ hop,
+                                                   int* __restrict__ V32, BCtl* bc)
 {
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
         // mode[g] may be changed by another workgroup of this launch: decide once
@@ -556,19 +563,24 @@ __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chun
             return;
         }
         const Jmp* __restrict__ Q = ga.fin[g] ? Q1 : Q0;
-        unsigned bad = 0;
+        unsigned bad = 0, big = 0;
         for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
             const Jmp q = Q[v];
             V[v] = q.D;
+            V32[v] = (int)q.D;
             hop[v] = (int)(q.H & ~kHopOverflow);
             if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
+            big |= q.D > INT32_MAX || q.D < INT32_MIN ? 1u : 0u;
         }
         const unsigned long long b = block_sum_u64(bad);
+        const unsigned long long bg = block_sum_u64(big);
         if (threadIdx.x == 0) {
             if (b) {
                 ga.mode[g] = kDone;
                 ga.status[g] = OCM_E_OVERFLOW;
             }
+            // sticky: from now on the sweeps gather the int64 values
+            if (bg) atomicOr(&bc->wide32, 1u);
         }
     });
 }
@@ -1056,6 +1068,7 @@ struct BWs {
     int2* chunks;
     long long* cptr;     // G+1 cycle offsets
     long long* V;
+    int* V32;            // int32 copy of V (used while every value fits)
     int* pi;
     int* succ;
     int* hop;
@@ -1133,6 +1146,7 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m, size_t sub_bytes)
     w.chunks = (int2*)take(8 * maxch);
     w.cptr = (long long*)take(8 * (Gs + 1));
     w.V = (long long*)take(8 * N);
+    w.V32 = (int*)take(4 * N);
     w.pi = (int*)take(4 * N);
     w.succ = (int*)take(4 * N);
     w.hop = (int*)take(4 * N);
@@ -1328,12 +1342,12 @@ void launch_bsweep(BCtx& c, unsigned nch, bool tie, int* xs = nullptr, int* ys =
                 kgrid(chunk_grid(nch), (const void*)ocm::b::k_sweep_tile<long long>), ocm::kWG, 0,
                 c.st>>>(
                 ws.chunks, &ws.bc->nchunks, c.sch.chunk, ws.ga, c.row_ptr, c.col,
-                (const long long*)c.w, c.neg, ws.V, ws.pi, ws.onC);
+                (const long long*)c.w, c.neg, ws.V, ws.pi, ws.onC, ws.V32, ws.bc);
         else
             ocm::b::k_sweep_tile<int><<<kgrid(chunk_grid(nch), (const void*)ocm::b::k_sweep_tile<int>),
                                         ocm::kWG, 0, c.st>>>(
                 ws.chunks, &ws.bc->nchunks, c.sch.chunk, ws.ga, c.row_ptr, c.col, (const int*)c.w,
-                c.neg, ws.V, ws.pi, ws.onC);
+                c.neg, ws.V, ws.pi, ws.onC, ws.V32, ws.bc);
         return;
     }
     if (c.wtype == OCM_W_I64) launch_bsweep_t<long long>(c, nch, tie, xs, ys, xcnt, xcap);
@@ -1412,7 +1426,7 @@ void enqueue_values(BCtx& c, int want, const unsigned* halt = nullptr)
     ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, R, ws.bc,
                                                                      halt);
     ocm::b::k_val_final<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, want, ws.Q[0],
-                                                   ws.Q[1], ws.V, ws.hop);
+                                                   ws.Q[1], ws.V, ws.hop, ws.V32, ws.bc);
     ocm::b::k_values_done<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, halt);
 }
 

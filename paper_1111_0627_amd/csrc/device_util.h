@@ -143,25 +143,32 @@ __device__ __forceinline__ unsigned wave_incl_scan(unsigned x)
     return x;
 }
 
-// Values of the int128 fallback live in two int64 arrays, lo and hi:
-// value = hi * 2^64 + (unsigned) lo.  ValT<false> is the plain int64 value.
-template <bool WIDE>
+// How the sweeps read the values V (value mode VM):
+//   0  int64 values;
+//   1  int128 values in two int64 arrays, lo and hi: value = hi * 2^64 +
+//      (unsigned) lo (the fallback once a value leaves int64);
+//   2  an int32 copy, written by the value phase when every value fits
+//      int32 (half the gathered bytes; the keys are still formed in int64).
+// ValT<VM>::type is the type keys are compared in.
+template <int VM>
 struct ValT {
     using type = long long;
 };
 template <>
-struct ValT<true> {
+struct ValT<1> {
     using type = __int128;
 };
 
-template <bool WIDE>
-__device__ __forceinline__ typename ValT<WIDE>::type load_val(const long long* __restrict__ lo,
-                                                              const long long* __restrict__ hi,
-                                                              int64_t i)
+template <int VM>
+__device__ __forceinline__ typename ValT<VM>::type load_val(const long long* __restrict__ lo,
+                                                            const long long* __restrict__ hi,
+                                                            const int* __restrict__ v32, int64_t i)
 {
-    if constexpr (WIDE)
+    if constexpr (VM == 1)
         return (__int128)(((unsigned __int128)(unsigned long long)hi[i] << 64) |
                           (unsigned long long)lo[i]);
+    else if constexpr (VM == 2)
+        return (long long)v32[i];
     else
         return lo[i];
 }

@@ -49,6 +49,8 @@ struct alignas(128) CtlLane {
     unsigned pjc[4];               // cycles: per round parity, image size and M changes
     unsigned long long rpack;      // device-driven rounds: this copy's workgroups done with
                                    //   the running round kernel, and their counts
+    unsigned wide32;               // values: some value does not fit int32 (no int32 copy)
+    unsigned pad_[3];
 };
 static_assert(sizeof(CtlLane) == 4 * kLaneWords, "one lane per 128-byte line");
 
@@ -87,6 +89,7 @@ struct CtlView {
     unsigned long long changed, tight, certain, nondec, pedges, ledges, maxabsw;
     unsigned active, active2, got, left, err, cbroken, overflow, bad;
     unsigned pjc[4];
+    unsigned wide32;
 };
 
 __host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
@@ -109,6 +112,7 @@ __host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
     v.clen = c.clen;
     v.changed = v.tight = v.certain = v.nondec = v.pedges = v.ledges = v.maxabsw = 0;
     v.active = v.active2 = v.got = v.left = v.err = v.cbroken = v.overflow = v.bad = 0;
+    v.wide32 = 0;
     for (int j = 0; j < 4; ++j) v.pjc[j] = 0;
     for (int l = 0; l < kLanes; ++l) {
         const CtlLane& ln = c.lane[l];
@@ -127,6 +131,7 @@ __host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
         v.cbroken |= ln.cbroken;
         v.overflow |= ln.overflow;
         v.bad |= ln.bad;
+        v.wide32 |= ln.wide32;
         for (int j = 0; j < 4; ++j) v.pjc[j] += ln.pjc[j];
     }
 }
@@ -155,6 +160,7 @@ struct SweepArgs {
     const int* col;
     const long long* V;
     const long long* Vhi;          // int128 values: high words of V (else null)
+    const int* V32;                // int32 copy of V when every value fits (else null)
     const int* t;                  // cycle ratio: edge times (else null: the mean)
     long long W, L;
     int* pi;
@@ -209,9 +215,12 @@ void launch_pj_final_dev(int n, const unsigned long long* P0, const unsigned lon
 void launch_val_round_dev(int n, int s, int r, const Jmp* Qin, Jmp* Qout, Ctl* ctl,
                           hipStream_t st, const long long* hin = nullptr,
                           long long* hout = nullptr);
+// V32 (nullable, int64 values only): also the int32 copy of V; the lanes'
+// wide32 flag says some value did not fit.
 void launch_val_final_dev(int n, const Jmp* Q0, const Jmp* Q1, long long* V, int* hop, Ctl* ctl,
                           hipStream_t st, const long long* h0 = nullptr,
-                          const long long* h1 = nullptr, long long* Vhi = nullptr);
+                          const long long* h1 = nullptr, long long* Vhi = nullptr,
+                          int* V32 = nullptr);
 void launch_pj_final(int n, const unsigned long long* P, int* rep, unsigned char* onc,
                      hipStream_t st);
 // Cycle ratio (t non-null): tsum receives each cycle's time, and the order
@@ -300,7 +309,8 @@ void launch_val_init(int n, const int* col, const int* pi, const void* w, int wt
 void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active, hipStream_t st,
                       const long long* hin = nullptr, long long* hout = nullptr);
 void launch_val_final(int n, const Jmp* Q, long long* V, int* hop, Ctl* ctl, hipStream_t st,
-                      const long long* hin = nullptr, long long* Vhi = nullptr);
+                      const long long* hin = nullptr, long long* Vhi = nullptr,
+                      int* V32 = nullptr);
 // *bad |= some int128 value (lo, hi) does not fit int64.
 void launch_fits64(int n, const long long* lo, const long long* hi, unsigned* bad,
                    hipStream_t st);

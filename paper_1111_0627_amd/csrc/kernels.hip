@@ -184,12 +184,13 @@ __global__ __launch_bounds__(kWG) void k_sweep_u(SweepArgs a, const WT* __restri
 // loads per batch instead of per vertex step; same result as k_sweep_u.
 constexpr int kTileEdges = 2048;
 
-// WIDE: int128 values (lo in a.V, hi in a.Vhi), keys compared in int128.
-// RATIO: cycle ratio, the key is V[head] + L * w - W * t (a.t: edge times).
-template <typename WT, bool FIRST, bool WIDE = false, bool RATIO = false>
+// VM: how V is read (0 int64, 1 int128 in a.V / a.Vhi with int128 keys, 2
+// the int32 copy a.V32).  RATIO: cycle ratio, the key is
+// V[head] + L * w - W * t (a.t: edge times).
+template <typename WT, bool FIRST, int VM = 0, bool RATIO = false>
 __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __restrict__ w)
 {
-    using KT = typename ValT<WIDE>::type;
+    using KT = typename ValT<VM>::type;
     __shared__ int beg[kWG + 1];
     __shared__ KT key[kTileEdges];
     const int64_t L = FIRST ? 1 : a.L;
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
     int pos = INT32_MAX;
     if (t < nv) {
         beg[t] = a.row_ptr[v0 + t];
-        if (!FIRST) own = load_val<WIDE>(a.V, a.Vhi, v0 + t);
+        if (!FIRST) own = load_val<VM>(a.V, a.Vhi, a.V32, v0 + t);
     }
     if (t == 0) beg[nv] = a.row_ptr[v0 + nv];
     __syncthreads();
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
             for (int u = 0; u < U; ++u) {
                 const int j = t + u * kWG;
                 if (j < cnt)
-                    key[j] = load_val<WIDE>(a.V, a.Vhi, c[u]) +
+                    key[j] = load_val<VM>(a.V, a.Vhi, a.V32, c[u]) +
                              (KT)(L * wl[u] - (RATIO ? W * tl[u] : W));
             }
         }
@@ -279,10 +280,10 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
 // 1536 keeps 8 workgroups per CU (measured 13 % faster than 2048 here).
 constexpr int kTieTileEdges = 1536;
 
-template <typename WT, bool SWEEP, bool WIDE = false, bool RATIO = false>
+template <typename WT, bool SWEEP, int VM = 0, bool RATIO = false>
 __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __restrict__ w)
 {
-    using KT = typename ValT<WIDE>::type;
+    using KT = typename ValT<VM>::type;
     __shared__ int beg[kWG + 1];
     __shared__ KT key[kTieTileEdges];
     __shared__ int head[kTieTileEdges];
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
     bool onc = false;
     if (t < nv) {
         beg[t] = a.row_ptr[v0 + t];
-        own = load_val<WIDE>(a.V, a.Vhi, v0 + t);
+        own = load_val<VM>(a.V, a.Vhi, a.V32, v0 + t);
         cur = a.pi[v0 + t];
         if (a.hop) hv = a.hop[v0 + t];
         onc = a.onC && a.onC[v0 + t];
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
         for (int u = 0; u < U; ++u) {
             const int j = t + u * kWG;
             if (j < n_e) {
-                key[j] = load_val<WIDE>(a.V, a.Vhi, c[u]) +
+                key[j] = load_val<VM>(a.V, a.Vhi, a.V32, c[u]) +
                          (KT)(L * wl[u] - (RATIO ? W * tl[u] : W));
                 head[j] = c[u];
             }
@@ -1954,23 +1955,32 @@ __global__ __launch_bounds__(kWG) void k_val_round_dev(int n, int s, int r,
 
 // WIDE: V gets the low words, Vhi the high words (hin: the entries' high
 // words); int128 values cannot overflow.
+// V32 (int64 values only, nullable): the int32 copy, with wide32 flagged
+// when some value does not fit it.
 template <bool WIDE>
 __device__ __forceinline__ void val_final_body(int n, const Jmp* __restrict__ Q,
                                                long long* __restrict__ V, int* __restrict__ hop,
                                                Ctl* ctl, const long long* __restrict__ hin,
-                                               long long* __restrict__ Vhi)
+                                               long long* __restrict__ Vhi,
+                                               int* __restrict__ V32)
 {
     const int v = blockIdx.x * kWG + threadIdx.x;
-    unsigned bad = 0;
+    unsigned bad = 0, big = 0;
     if (v < n) {
         const Jmp q = Q[v];
         V[v] = q.D;
         if (hop) hop[v] = (int)(q.H & ~kHopOverflow);
         if (WIDE) Vhi[v] = hin[v];
         else if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
+        if (!WIDE && V32) {
+            V32[v] = (int)q.D;
+            big = q.D > INT32_MAX || q.D < INT32_MIN;
+        }
     }
     if (!WIDE && __ballot(bad != 0) && (threadIdx.x & 63) == 0)
         atomicOr(&my_lane(ctl).overflow, 1u);
+    if (!WIDE && __ballot(big != 0) && (threadIdx.x & 63) == 0)
+        atomicOr(&my_lane(ctl).wide32, 1u);
 }
 
 template <bool WIDE>
@@ -1978,9 +1988,10 @@ __global__ __launch_bounds__(kWG) void k_val_final(int n, const Jmp* __restrict_
                                                    long long* __restrict__ V,
                                                    int* __restrict__ hop, Ctl* ctl,
                                                    const long long* __restrict__ hin,
-                                                   long long* __restrict__ Vhi)
+                                                   long long* __restrict__ Vhi,
+                                                   int* __restrict__ V32)
 {
-    val_final_body<WIDE>(n, Q, V, hop, ctl, hin, Vhi);
+    val_final_body<WIDE>(n, Q, V, hop, ctl, hin, Vhi, V32);
 }
 
 // Device-driven: runs once every vertex finished (not after a stall), on the
@@ -1992,11 +2003,12 @@ __global__ __launch_bounds__(kWG) void k_val_final_dev(int n, const Jmp* __restr
                                                        int* __restrict__ hop, Ctl* ctl,
                                                        const long long* __restrict__ h0,
                                                        const long long* __restrict__ h1,
-                                                       long long* __restrict__ Vhi)
+                                                       long long* __restrict__ Vhi,
+                                                       int* __restrict__ V32)
 {
     if (ctl->jmode != 0 || ctl->jstall || !ctl->jgate) return;
     const bool odd = (ctl->jk & 1) != 0;
-    val_final_body<WIDE>(n, odd ? Q1 : Q0, V, hop, ctl, odd ? h1 : h0, Vhi);
+    val_final_body<WIDE>(n, odd ? Q1 : Q0, V, hop, ctl, odd ? h1 : h0, Vhi, V32);
 }
 
 // Cycle C listed from the source: vertex c_j (j steps after s) is H = L - j
@@ -2017,11 +2029,11 @@ __global__ __launch_bounds__(kWG) void k_cycle_list(int n, int s, long long L,
 // nearer the source (hop[y] >= hop[x]), follow y's policy path for at most
 // kShortWalk steps; meeting x closes a cycle of tight edges other than C.
 
-template <int G, typename WT, bool WIDE = false>
+template <int G, typename WT, int VM = 0>
 __global__ __launch_bounds__(kWG) void k_tie_short_walk(SweepArgs a, const WT* __restrict__ w,
                                                         const int* __restrict__ succ)
 {
-    using KT = typename ValT<WIDE>::type;
+    using KT = typename ValT<VM>::type;
     constexpr int VPB = kWG / G;
     const int lane = threadIdx.x & (G - 1);
     const int64_t per = ((int64_t)a.n + gridDim.x - 1) / gridDim.x;
@@ -2032,14 +2044,14 @@ __global__ __launch_bounds__(kWG) void k_tie_short_walk(SweepArgs a, const WT* _
         const int64_t v = vb + threadIdx.x / G;
         if (v >= v1) continue;
         const int beg = a.row_ptr[v], end = a.row_ptr[v + 1];
-        const KT own = load_val<WIDE>(a.V, a.Vhi, v);
+        const KT own = load_val<VM>(a.V, a.Vhi, a.V32, v);
         const int cur = a.pi[v];
         for (int e = beg + lane; e < end; e += G) {
             if (e == cur) continue;
             const int y = a.col[e];
             if (a.hop[y] < a.hop[v]) continue;
             const long long te = a.t ? a.t[e] : 1;
-            if (load_val<WIDE>(a.V, a.Vhi, y) + (KT)(a.L * wval(w, e, a.neg) - a.W * te) != own)
+            if (load_val<VM>(a.V, a.Vhi, a.V32, y) + (KT)(a.L * wval(w, e, a.neg) - a.W * te) != own)
                 continue;
             int x = y;
             for (int st = 0; st < kShortWalk && x != (int)v; ++st) x = succ[x];
@@ -2228,6 +2240,7 @@ __global__ void k_ctl_clear(Ctl* ctl, unsigned what)
             ln.got = 0;
             ln.left = 0;
             ln.overflow = 0;
+            ln.wide32 = 0;
         }
         if (what & kClrActive2) ln.active2 = 0;
     }
@@ -2315,34 +2328,38 @@ void launch_validate(int n, int m, const int* row_ptr, const int* col, const voi
         k_validate<int><<<grid, kWG, 0, st>>>(n, m, row_ptr, col, (const int*)w, check_csr, ctl);
 }
 
-// Sweeps after the first with int128 values or edge times: always over
-// vertex tiles.
-template <typename WT, bool WIDE, bool RATIO>
+// Sweeps after the first with int128 values, an int32 copy of V or edge
+// times: always over vertex tiles.
+template <typename WT, int VM, bool RATIO>
 static void launch_sweep_tiles(const SweepArgs& a, const WT* ww, bool tie, bool fused,
                                hipStream_t st)
 {
     const unsigned tiles = blocks_for(a.n);
-    if (tie) k_tiescan_tile<WT, false, WIDE, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
-    else if (fused) k_tiescan_tile<WT, true, WIDE, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
-    else k_sweep_tile<WT, false, WIDE, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
+    if (tie) k_tiescan_tile<WT, false, VM, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
+    else if (fused) k_tiescan_tile<WT, true, VM, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
+    else k_sweep_tile<WT, false, VM, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
+}
+
+template <typename WT, int VM>
+static void launch_sweep_vm(const SweepArgs& a, const WT* ww, bool tie, bool fused, hipStream_t st)
+{
+    if (a.t) launch_sweep_tiles<WT, VM, true>(a, ww, tie, fused, st);
+    else launch_sweep_tiles<WT, VM, false>(a, ww, tie, fused, st);
 }
 
 template <typename WT>
 static void launch_sweep_general(const SweepArgs& a, const WT* ww, bool tie, bool fused,
                                  hipStream_t st)
 {
-    if (a.Vhi) {
-        if (a.t) launch_sweep_tiles<WT, true, true>(a, ww, tie, fused, st);
-        else launch_sweep_tiles<WT, true, false>(a, ww, tie, fused, st);
-    } else {
-        launch_sweep_tiles<WT, false, true>(a, ww, tie, fused, st);
-    }
+    if (a.Vhi) launch_sweep_vm<WT, 1>(a, ww, tie, fused, st);
+    else if (a.V32) launch_sweep_vm<WT, 2>(a, ww, tie, fused, st);
+    else launch_sweep_vm<WT, 0>(a, ww, tie, fused, st);
 }
 
 void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool first, bool tie,
                   bool count_tight, unsigned grid, hipStream_t st)
 {
-    if ((a.Vhi || a.t) && !first) {
+    if ((a.Vhi || a.t || (a.V32 && (G == 0 || tie))) && !first) {
         const bool fused = !tie && count_tight;
         if (wtype == kWI64) launch_sweep_general(a, (const long long*)w, tie, fused, st);
         else launch_sweep_general(a, (const int*)w, tie, fused, st);
@@ -2419,13 +2436,14 @@ void launch_val_round_dev(int n, int s, int r, const Jmp* Qin, Jmp* Qout, Ctl* c
 
 void launch_val_final_dev(int n, const Jmp* Q0, const Jmp* Q1, long long* V, int* hop, Ctl* ctl,
                           hipStream_t st, const long long* h0, const long long* h1,
-                          long long* Vhi)
+                          long long* Vhi, int* V32)
 {
     if (Vhi)
-        k_val_final_dev<true><<<blocks_for(n), kWG, 0, st>>>(n, Q0, Q1, V, hop, ctl, h0, h1, Vhi);
+        k_val_final_dev<true><<<blocks_for(n), kWG, 0, st>>>(n, Q0, Q1, V, hop, ctl, h0, h1, Vhi,
+                                                             nullptr);
     else
         k_val_final_dev<false><<<blocks_for(n), kWG, 0, st>>>(n, Q0, Q1, V, hop, ctl, nullptr,
-                                                              nullptr, nullptr);
+                                                              nullptr, nullptr, V32);
 }
 
 void launch_pj_round(int n, const unsigned long long* Pin, unsigned long long* Pout,
@@ -2695,10 +2713,12 @@ void launch_val_round(int n, int s, const Jmp* Qin, Jmp* Qout, unsigned* active,
 }
 
 void launch_val_final(int n, const Jmp* Q, long long* V, int* hop, Ctl* ctl, hipStream_t st,
-                      const long long* hin, long long* Vhi)
+                      const long long* hin, long long* Vhi, int* V32)
 {
-    if (Vhi) k_val_final<true><<<blocks_for(n), kWG, 0, st>>>(n, Q, V, hop, ctl, hin, Vhi);
-    else k_val_final<false><<<blocks_for(n), kWG, 0, st>>>(n, Q, V, hop, ctl, nullptr, nullptr);
+    if (Vhi) k_val_final<true><<<blocks_for(n), kWG, 0, st>>>(n, Q, V, hop, ctl, hin, Vhi, nullptr);
+    else
+        k_val_final<false><<<blocks_for(n), kWG, 0, st>>>(n, Q, V, hop, ctl, nullptr, nullptr,
+                                                          V32);
 }
 
 void launch_cycle_list(int n, int s, long long L, const unsigned char* onC, const int* pi,
@@ -2713,7 +2733,7 @@ static void launch_short_walk_t(const SweepArgs& a, const void* w, int G, const 
 {
     const WT* ww = (const WT*)w;
     if (a.Vhi) {   // int128 values: one lane group size (a rare fallback)
-        k_tie_short_walk<8, WT, true><<<grid, kWG, 0, st>>>(a, ww, succ);
+        k_tie_short_walk<8, WT, 1><<<grid, kWG, 0, st>>>(a, ww, succ);
         return;
     }
     switch (G) {
@@ -2868,6 +2888,7 @@ __global__ void k_post_ctl(const Ctl* __restrict__ c, CtlView* dst, unsigned* se
     v.cbroken = lane_or(ln.cbroken);
     v.overflow = lane_or(ln.overflow);
     v.bad = lane_or(ln.bad);
+    v.wide32 = lane_or(ln.wide32);
     for (int j = 0; j < 4; ++j) v.pjc[j] = (unsigned)lane_sum(ln.pjc[j]);
     if (threadIdx.x == 0) {
         v.W = c->W;

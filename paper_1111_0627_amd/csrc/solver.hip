@@ -61,6 +61,7 @@ struct Ws {
     Ctl* ctl;
     long long* V;        // values scaled by L (int128 values: their low words)
     long long* Vhi;      // int128 values: high words
+    int* V32;            // int32 copy of V (valid while every value fits int32)
     long long* Dhi[2];   // int128 value rounds: high words of the jump entries' sums
     int* pi;             // policy: CSR position of each vertex's edge
     int* succ;           // policy successor
@@ -104,6 +105,7 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.ctl = (Ctl*)take(sizeof(Ctl));
     w.V = (long long*)take(8 * N);
     w.Vhi = (long long*)take(8 * N);
+    w.V32 = (int*)take(4 * N);
     w.Dhi[0] = (long long*)take(8 * N);
     w.Dhi[1] = (long long*)take(8 * N);
     w.pi = (int*)take(4 * N);
@@ -209,6 +211,7 @@ struct Ctx {
     // scattered stores cost more than the gather they save)
     bool succ_ok = false;
     bool sweep_fused = false;   // the last sweep launched counts tight edges
+    double sweep_vbytes = 8.0;  // bytes per value the last sweep gathered
     unsigned long long swept_tight = 0, swept_certain = 0;
     int jump_rounds = 0;
     int connect_rounds = 0;
@@ -228,6 +231,9 @@ struct Ctx {
     // range (or on request), for the rest of the solve
     bool wide = false;
     bool allow_wide = false;
+    // ws.V32 holds V as int32 (every value of the last value phase fit):
+    // sweeps then gather 4-byte values
+    bool v32 = false;
 
     Ctx() = default;
     Ctx(const Ctx&) = delete;
@@ -358,7 +364,9 @@ void sweep_done(Ctx& c, bool first, bool tie, bool fused)
     // vertices
     const double n = c.n, m = c.m;
     double b = m * (4.0 + c.sw) + 4.0 * (n + 1);
-    if (!first) b += 8.0 * m + 8.0 * n;
+    // values gathered as int64, int128 (two words) or from the int32 copy
+    const double sv = c.sweep_vbytes;
+    if (!first) b += sv * m + sv * n;
     if (tie || fused) b += 4.0 * n;
     if (!tie) b += 4.0 * (double)c.h.changed;
     c.prof.bytes(tie ? OCM_K_TIESCAN : OCM_K_SWEEP, b);
@@ -378,6 +386,7 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     a.col = c.col;
     a.V = V;
     a.Vhi = c.wide && V == c.ws.V ? c.ws.Vhi : nullptr;
+    a.V32 = !c.wide && c.v32 && V == c.ws.V && !first ? c.ws.V32 : nullptr;
     a.t = first ? nullptr : c.t;
     a.W = W;
     a.L = L;
@@ -407,6 +416,7 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     c.prof.end();
     HIP_TRY(hipGetLastError());
     c.sweep_fused = fused;
+    c.sweep_vbytes = a.Vhi ? 16.0 : a.V32 ? 4.0 : 8.0;
     if (!read) return OCM_OK;
     OCM_TRY(read_ctl(c));
     sweep_done(c, first, tie, fused);
@@ -755,7 +765,8 @@ ocm_status value_rounds_on_device(Ctx& c, int s, long long* V, int* hop, bool pr
             ocm::launch_val_final_dev(c.n, w.Q[0], w.Q[1], V, hop, w.ctl, c.st, w.Dhi[0], w.Dhi[1],
                                       w.Vhi);
         else
-            ocm::launch_val_final_dev(c.n, w.Q[0], w.Q[1], V, hop, w.ctl, c.st);
+            ocm::launch_val_final_dev(c.n, w.Q[0], w.Q[1], V, hop, w.ctl, c.st, nullptr, nullptr,
+                                      nullptr, V == w.V ? w.V32 : nullptr);
         HIP_TRY(hipGetLastError());
         OCM_TRY(read_ctl(c));
         if (c.h.jmode == 0) break;
@@ -765,6 +776,11 @@ ocm_status value_rounds_on_device(Ctx& c, int s, long long* V, int* hop, bool pr
     c.jump_rounds += k;
     c.value_rounds += k;
     if (rounds) *rounds = k;
+    // the int32 copy is current when the phase ran to its end (a gated phase
+    // runs iff the sweep queued before it changed a policy edge and no
+    // vertex of C)
+    if (V == c.ws.V && !c.h.jstall && (!gated || (!c.h.cbroken && c.h.changed > 0)))
+        c.v32 = !c.wide && !c.h.wide32;
     if (c.h.jstall) {
         if (probe) {
             if (stalled) *stalled = true;
@@ -831,11 +847,14 @@ ocm_status phase_values_once(Ctx& c, const int* pi, int s, long long W, long lon
     if (rounds) *rounds = k;
     c.prof.begin(ph);
     if (c.wide) ocm::launch_val_final(c.n, c.ws.Q[a], V, hop, c.ws.ctl, c.st, c.ws.Dhi[a], c.ws.Vhi);
-    else ocm::launch_val_final(c.n, c.ws.Q[a], V, hop, c.ws.ctl, c.st);
+    else
+        ocm::launch_val_final(c.n, c.ws.Q[a], V, hop, c.ws.ctl, c.st, nullptr, nullptr,
+                              V == c.ws.V ? c.ws.V32 : nullptr);
     c.prof.end();
     c.prof.bytes(ph, 24.0 * c.n);
     HIP_TRY(hipGetLastError());
     OCM_TRY(read_ctl(c));
+    if (V == c.ws.V) c.v32 = !c.wide && !c.h.wide32;
     if (c.h.overflow) return fail(OCM_E_OVERFLOW, "a value left [-2^62, 2^62]");
     return OCM_OK;
 }
@@ -922,6 +941,7 @@ ocm_status tie_check(Ctx& c, long long W, long long L, ocm_result* out)
         a.col = c.col;
         a.V = w.V;
         a.Vhi = c.wide ? w.Vhi : nullptr;
+        a.V32 = !c.wide && c.v32 ? w.V32 : nullptr;
         a.t = c.t;
         a.W = W;
         a.L = L;

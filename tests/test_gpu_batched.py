@@ -228,3 +228,20 @@ def test_batched_failure_in_a_later_rebuild():
     for k, g in ((0, good[0]), (2, good[1])):
         sol = native.solve(g.row_ptr, g.col, g.w)
         assert (res.p[k], res.q[k], res.iterations[k]) == (sol.p, sol.q, sol.iterations)
+
+
+def test_batched_values_beyond_int32():
+    """One graph with weights near 2^30 pushes its values past int32 (the
+    sweeps then gather the int64 values for the rest of the call); every
+    graph still equals the oracle."""
+    gs = [synth.random_digraph(n, 1, 5, 1, 1000, np.int64, seed=[8, n]) for n in (300, 7000)]
+    gs.append(synth.random_digraph(5000, 1, 5, 2**30, 2**31, np.int64, seed=[8, 1]))
+    gs.append(synth.random_digraph(9000, 1, 5, 1, 1000, np.int64, seed=[8, 2]))
+    u, vptr, eptr = synth.disjoint_union(gs)
+    res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr)
+    assert all(s == ocm.OCM_OK for s in res.status)
+    for k, g in enumerate(gs):
+        sol = native.solve(g.row_ptr, g.col, g.w)
+        cyc = (res.cycle(k).cpu().numpy() - eptr[k]).tolist()
+        assert (res.p[k], res.q[k], cyc, res.iterations[k]) == \
+            (sol.p, sol.q, sol.cycle.tolist(), sol.iterations), k

@@ -96,3 +96,19 @@ def test_forced_int128_on_hand_traces_and_ties():
         g = synth.random_digraph(3000, 1, 4, 0, 2, np.int32, seed=seed)
         sol = native.solve(g.row_ptr, g.col, g.w)
         same(ocm.min_cycle_mean(*dev(g), int128=True), sol)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_values_beyond_int32_use_int64_gathers(seed):
+    """Weights near 2^30: the optimum's values leave int32 (the sweeps must
+    not use the int32 copy) while staying in int64; a second graph of small
+    weights afterwards uses the copy again.  Both equal the oracle."""
+    g = synth.random_digraph(20000, 1, 5, 2**30, 2**31, np.int64, seed=seed)
+    sol = native.solve(g.row_ptr, g.col, g.w, want_V=True)
+    assert np.abs(sol.V).max() > 2**31
+    res = ocm.min_cycle_mean(*dev(g), want_potential=True)
+    same(res, sol)
+    assert not res.int128
+    assert np.array_equal(res.potential.cpu().numpy(), sol.V)
+    h = synth.random_digraph(20000, 1, 5, 1, 1000, np.int64, seed=seed)
+    same(ocm.min_cycle_mean(*dev(h)), native.solve(h.row_ptr, h.col, h.w))
