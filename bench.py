@@ -283,6 +283,25 @@ def cpu_sample(g, mode, budget_s=10.0):
                 seconds=round(dt, 2), iterations_run=it, converged=done)
 
 
+def bench_multichain(rp, cl, w, mode, steps, ref):
+    """The multichain variant (every policy cycle keeps its own gain, no
+    rebuild) on the same resident graph: median time to the exact optimum,
+    its sweep count, and whether it reaches the same optimum as Alg. 2."""
+    from paper_1111_0627_amd import ocm
+    import torch
+    r = ocm.cycle_mean(rp, cl, w, mode=mode, multichain=True)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t = time.perf_counter()
+        r = ocm.cycle_mean(rp, cl, w, mode=mode, multichain=True)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1e3)
+    return {"time_to_exact_ocm_ms": {"median": float(np.median(ts)), "min": min(ts)},
+            "iterations": r.iterations, "jump_rounds": r.jump_rounds,
+            "same_optimum": (r.p, r.q) == (ref.p, ref.q)}
+
+
 def bench_config(name, steps):
     """One single-graph workload: time-to-exact-OCM (median of `steps` after a
     warm-up), iterations, edges/s/iter, the sweep's HBM roofline, and the
@@ -326,6 +345,7 @@ def bench_config(name, steps):
         if ex:
             out["matches_oracle_golden"] = (r.p, r.q, r.cycle_edges.cpu().tolist(), r.iterations) \
                 == (ex["p"], ex["q"], ex["cycle"], ex["iterations"])
+    out["multichain"] = bench_multichain(rp, cl, w, mode, steps, r)
     cb = cpu_sample(g, mode)
     if name == "rand1k":
         t = time.perf_counter()
@@ -619,6 +639,7 @@ def main():
         out["roofline_sweep"] = roofline("sweep", *phase["sweep"])
         out["roofline_sweep"]["traffic"] = traffic_per_launch(pmc, "sweep")
         out["roofline_sweep"]["trace_avg_launch_us"] = trace_avg_us(trace, "sweep")
+    out["multichain"] = bench_multichain(rp, cl, w, mode, args.steps, r)
     if not args.no_configs:
         out["configs"] = {}
         for cname in ("rand1k", "rand1m_max", "rand4m_i64"):

@@ -165,6 +165,20 @@ typedef struct {
                                   the solve; 1: int128 from the start.  Same
                                   results either way (OCM_F_INT128 says which
                                   ran).                                         */
+    int32_t multichain;        /* 0: Alg. 2 (one gain; the rebuild attaches
+                                  every vertex to C).  1: multichain policy
+                                  iteration, an alternative not in the paper:
+                                  every policy cycle keeps its own gain W_r/L_r,
+                                  a vertex's value is scaled by the length of
+                                  the cycle it reaches, and the sweep compares
+                                  (gain, bias) pairs; no rebuild.  Same optimum;
+                                  its own trajectory and, among tied cycles, its
+                                  own C (the policy cycle of smallest gain, then
+                                  smallest vertex); potential_out holds those
+                                  per-cycle scaled values.  ocm_min / ocm_max /
+                                  ocm_min_noalloc only, without init_policy or
+                                  int128_values; values stay int64 (one beyond
+                                  2^62 gives OCM_E_OVERFLOW).                    */
 } ocm_options;
 
 /* Fills *o with the defaults: max_iters 0, validate 1, schedule 0,

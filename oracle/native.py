@@ -163,21 +163,24 @@ def solve(row_ptr, col, w, mode: str = "min", max_iters: int = 0,
 
 
 def solve_multichain(row_ptr, col, w, mode: str = "min", max_iters: int = 0,
-                     tie: bool = True, want_pi: bool = False) -> Solution:
+                     tie: bool = True, want_V: bool = False,
+                     want_pi: bool = False) -> Solution:
     """Multichain policy iteration (every policy cycle keeps its own gain; no
-    rebuild): same optimum, its own trajectory and critical cycle."""
+    rebuild): same optimum, its own trajectory and critical cycle.  ``V``:
+    each vertex's value scaled by the length of the cycle it reaches."""
     rp, cl, ww = _csr(row_ptr, col, w)
     n, m = len(rp) - 1, len(cl)
     res = _Result()
     cyc = np.zeros(max(n, 1), np.int32)
+    V = np.zeros(n, np.int64) if want_V else None
     pi = np.zeros(n, np.int32) if want_pi else None
     rc = lib().orc_solve_mc(n, m, _ptr(rp), _ptr(cl), _ptr(ww), int(mode == "max"), max_iters,
-                            int(tie), C.byref(res), _ptr(cyc), n, None,
-                            _ptr(pi) if want_pi else None)
+                            int(tie), C.byref(res), _ptr(cyc), n,
+                            _ptr(V) if want_V else None, _ptr(pi) if want_pi else None)
     if rc:
         raise OracleError(rc, "solve_multichain")
     return Solution(res.p, res.q, cyc[:res.cycle_len].copy(), res.source, res.iterations,
-                    res.tie, res.ncycles_first, res.W, res.L, res.tight, None, pi)
+                    res.tie, res.ncycles_first, res.W, res.L, res.tight, V, pi)
 
 
 def certify(row_ptr, col, w, p, q, cycle, V, K, mode: str = "min", t=None) -> int:

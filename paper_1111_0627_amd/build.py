@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libocm.so")
-SOURCES = ["kernels.hip", "solver.hip", "batch.hip", "general.hip"]
+SOURCES = ["kernels.hip", "solver.hip", "batch.hip", "general.hip", "multichain.hip"]
 ARCH = os.environ.get("OCM_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are switched off for all device code.

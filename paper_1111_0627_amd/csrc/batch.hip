@@ -345,11 +345,32 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
                 }
                 __syncthreads();
                 const int lo = mb > eb ? mb : eb, hi = me < eb + ne ? me : eb + ne;
-                for (int e = lo; e < hi; ++e) {
-                    const long long k = key[e - eb];
-                    if (k < best) {
-                        best = k;
-                        pos = e;
+                const bool long_row = hi - lo > kLongRow;
+                if (!long_row)
+                    for (int e = lo; e < hi; ++e) {
+                        const long long k = key[e - eb];
+                        if (k < best) {
+                            best = k;
+                            pos = e;
+                        }
+                    }
+                // the wave's long rows, one after the other, by all its lanes
+                for (unsigned long long lm = __ballot(long_row); lm; lm &= lm - 1) {
+                    const int l = __ffsll((long long)lm) - 1;
+                    const int rlo = __shfl(lo, l, 64), rhi = __shfl(hi, l, 64);
+                    long long rb = INT64_MAX;
+                    int rp = INT32_MAX, rh = 0;
+                    for (int e = rlo + (t & 63); e < rhi; e += 64) {
+                        const long long k = key[e - eb];
+                        if (k < rb) {
+                            rb = k;
+                            rp = e;
+                        }
+                    }
+                    wave_argmin<long long, false>(rb, rp, rh);
+                    if ((t & 63) == l && rb < best) {
+                        best = rb;
+                        pos = rp;
                     }
                 }
                 __syncthreads();
@@ -1922,6 +1943,7 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
     if (o_in) o = *o_in;
     else ocm_default_options(&o);
     if (o.init_policy) return bfail(OCM_E_INVALID_ARG, "warm start is not supported in batches");
+    if (o.multichain) return bfail(OCM_E_INVALID_ARG, "multichain is not supported in batches");
     // a chunk's vertices are listed through an LDS buffer of kListItems
     if (o.tile != 0 && (o.tile < ocm::b::kMinChunk || o.tile > ocm::kListItems))
         return bfail(OCM_E_INVALID_ARG, "tile must be 0 or in [512, 4096]");

@@ -203,5 +203,110 @@ __device__ __forceinline__ unsigned wave_append(bool want, unsigned* counter)
     return base + before;
 }
 
+// ---------------------------------------------------------------------------
+// Device-driven rounds (rebuild, values, cycles): the host queues several
+// rounds ahead; a round kernel runs only while the control block says its
+// round is next, and the last of its workgroups to finish books the round.
+// Each workgroup's thread 0 arrives with one 64-bit atomic adding
+// (1 << 48) + (flag << 32) + count, so its counts travel with the arrival
+// and no fence is needed.  Arrivals are counted per lane first (same-address
+// atomics serialise), then per lane.  Counts must sum below 2^32, flags
+// below 2^16.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kArrive = 1ull << 48;
+
+__device__ __forceinline__ unsigned long long arrival_word(unsigned long long count, unsigned flag)
+{
+    return count + ((unsigned long long)flag << 32);
+}
+
+// True for the grid's last arrival, which gets the summed word (arrival
+// counts removed) in *total and leaves the counters at zero.
+__device__ __forceinline__ bool last_arrival(Ctl* c, unsigned long long word,
+                                             unsigned long long* total)
+{
+    const unsigned lane = blockIdx.x & (kLanes - 1);
+    const unsigned in_lane = (gridDim.x - lane + kLanes - 1) / kLanes;
+    const unsigned lanes = gridDim.x < (unsigned)kLanes ? gridDim.x : (unsigned)kLanes;
+    const unsigned long long lp = atomicAdd(&c->lane[lane].rpack, word + kArrive);
+    if ((unsigned)(lp >> 48) != in_lane - 1) return false;
+    __hip_atomic_store(&c->lane[lane].rpack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long lane_sum = lp + word + kArrive - (unsigned long long)in_lane * kArrive;
+    const unsigned long long tp = atomicAdd(&c->rpack, lane_sum + kArrive);
+    if ((unsigned)(tp >> 48) != lanes - 1) return false;
+    __hip_atomic_store(&c->rpack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *total = tp - (unsigned long long)(lanes - 1) * kArrive + lane_sum;
+    return true;
+}
+
+// Is round r of the device-driven jump rounds the next one?
+__device__ __forceinline__ bool jump_round_is(const Ctl* c, int r)
+{
+    return c->jk + 1 == (unsigned)r && c->jmode == 1u;
+}
+
+// Jump entries: q followed by r (sums add, hops add; bit 31 of H flags an
+// int64 overflow of the sum).
+__device__ __forceinline__ Jmp jmp_combine(Jmp q, const Jmp& r)
+{
+    long long d;
+    if (__builtin_add_overflow(q.D, r.D, &d)) {
+        d = 0;
+        q.H |= kHopOverflow;
+    }
+    q.D = d;
+    q.J = r.J;
+    q.H = ((q.H & ~kHopOverflow) + (r.H & ~kHopOverflow)) | ((q.H | r.H) & kHopOverflow);
+    return q;
+}
+
+// Rows with more than kLongRow keys in a batch are walked by the vertex's
+// whole wave (64 lanes striding over the keys, then a wave minimum with
+// ties to the lower position) instead of by its own thread alone: a hub's
+// row then costs its length / 64 steps, not its length, while rows of
+// ordinary degree keep the one-thread walk.
+constexpr int kLongRow = 32;
+
+template <typename KT>
+__device__ __forceinline__ KT shfl_kt(KT x, int src)
+{
+    if constexpr (sizeof(KT) == 16) {
+        const unsigned long long lo = __shfl((unsigned long long)x, src, 64);
+        const long long hi = __shfl((long long)(x >> 64), src, 64);
+        return (KT)(((unsigned __int128)(unsigned long long)hi << 64) | lo);
+    } else {
+        return __shfl(x, src, 64);
+    }
+}
+
+template <typename KT>
+__device__ __forceinline__ KT shfl_xor_kt(KT x, int off)
+{
+    if constexpr (sizeof(KT) == 16) {
+        const unsigned long long lo = __shfl_xor((unsigned long long)x, off, 64);
+        const long long hi = __shfl_xor((long long)(x >> 64), off, 64);
+        return (KT)(((unsigned __int128)(unsigned long long)hi << 64) | lo);
+    } else {
+        return __shfl_xor(x, off, 64);
+    }
+}
+
+// Minimum key over the wave, ties to the lower position; every lane gets it
+// (with the head when H is set).
+template <typename KT, bool H>
+__device__ __forceinline__ void wave_argmin(KT& k, int& p, int& h)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const KT ok = shfl_xor_kt(k, off);
+        const int op = __shfl_xor(p, off, 64);
+        const int oh = H ? __shfl_xor(h, off, 64) : 0;
+        if (ok < k || (ok == k && op < p)) {
+            k = ok;
+            p = op;
+            if (H) h = oh;
+        }
+    }
+}
 
 }  // namespace ocm

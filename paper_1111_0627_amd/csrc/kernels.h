@@ -50,7 +50,8 @@ struct alignas(128) CtlLane {
     unsigned long long rpack;      // device-driven rounds: this copy's workgroups done with
                                    //   the running round kernel, and their counts
     unsigned wide32;               // values: some value does not fit int32 (no int32 copy)
-    unsigned pad_[3];
+    unsigned ncrit;                // multichain tie check: policy cycles of optimal gain
+    unsigned pad_[2];
 };
 static_assert(sizeof(CtlLane) == 4 * kLaneWords, "one lane per 128-byte line");
 
@@ -89,7 +90,7 @@ struct CtlView {
     unsigned long long changed, tight, certain, nondec, pedges, ledges, maxabsw;
     unsigned active, active2, got, left, err, cbroken, overflow, bad;
     unsigned pjc[4];
-    unsigned wide32;
+    unsigned wide32, ncrit;
 };
 
 __host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
@@ -112,7 +113,7 @@ __host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
     v.clen = c.clen;
     v.changed = v.tight = v.certain = v.nondec = v.pedges = v.ledges = v.maxabsw = 0;
     v.active = v.active2 = v.got = v.left = v.err = v.cbroken = v.overflow = v.bad = 0;
-    v.wide32 = 0;
+    v.wide32 = v.ncrit = 0;
     for (int j = 0; j < 4; ++j) v.pjc[j] = 0;
     for (int l = 0; l < kLanes; ++l) {
         const CtlLane& ln = c.lane[l];
@@ -132,6 +133,7 @@ __host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
         v.overflow |= ln.overflow;
         v.bad |= ln.bad;
         v.wide32 |= ln.wide32;
+        v.ncrit += ln.ncrit;
         for (int j = 0; j < 4; ++j) v.pjc[j] += ln.pjc[j];
     }
 }
@@ -334,6 +336,58 @@ hipError_t host_read_ctl(const Ctl* ctl, CtlView* out, hipStream_t st);
 // synchronisation: no pinned mailbox is created (used by the entry point
 // that allocates nothing).
 hipError_t host_read_ctl_copy(const Ctl* ctl, CtlView* out, hipStream_t st);
+
+// Multichain policy iteration (every policy cycle keeps its own gain).
+// Value entries are Jmp: D sums L_r * w - W_r over the first H policy edges
+// of v's path, where r is the smallest vertex of the cycle that path reaches
+// and W_r, L_r are that cycle's weight and length; J is the vertex reached,
+// or ~r once the path has reached r.  After the final the entries are the
+// records the sweep gathers: D = V(v), J = r, H = hops from v to r.
+struct McArgs {
+    int n;
+    int neg;
+    const int* row_ptr;
+    const int* col;
+    const Jmp* R;                  // per-vertex records (value, cycle, hops)
+    const long long* wsum;         // per cycle (keyed by r): weight
+    const unsigned* lcnt;          //                         length
+    int* pi;
+    int* succ;                     // col[pi], kept up to date where pi changes
+    Ctl* ctl;
+    // tie scan only: the optimal gain W / L, C's flags, hops, list of the
+    // tight non-policy edges between vertices of optimal gain
+    long long W, L;
+    const unsigned char* onC;
+    int* xs;
+    int* ys;
+    unsigned* xcnt;
+    unsigned xcap;
+};
+// Entries of every vertex: roots (the smallest vertex of each policy cycle)
+// finished with D = 0; succ gets col[pi] unless have_succ; lanes' active =
+// unfinished vertices.
+void launch_mc_val_init(int n, const int* col, const int* pi, const void* w, int wtype, int neg,
+                        const int* rep, const unsigned char* onc, const long long* wsum,
+                        const unsigned* lcnt, int* succ, bool have_succ, Jmp* Q, Ctl* ctl,
+                        hipStream_t st);
+// Device-driven rounds as launch_val_round_dev (jump setup with values).
+void launch_mc_round_dev(int n, int r, const Jmp* Qin, Jmp* Qout, Ctl* ctl, hipStream_t st);
+// After the rounds: V, hop, the lanes' overflow flag, and the records in
+// place (buffer jk & 1).
+void launch_mc_final_dev(int n, Jmp* Q0, Jmp* Q1, long long* V, int* hop, Ctl* ctl,
+                         hipStream_t st);
+// G lanes per vertex (power of two <= 64).  Not tie: the improvement sweep
+// (lanes' changed) that also counts every tight non-policy edge (lanes'
+// tight).  tie: counts (tight), and lists when a.xs is set, the tight
+// non-policy edges whose tail has the optimal gain a.W / a.L, with certain
+// (a tight self-loop or a tail on C) and nondec (head not nearer its root).
+void launch_mc_sweep(const McArgs& a, const void* w, int wtype, int G, bool tie, hipStream_t st);
+// Lanes' ncrit = policy cycles whose gain equals W / L.
+void launch_mc_ncrit(const int* cyc_list, const long long* wsum, const unsigned* lcnt, long long W,
+                     long long L, Ctl* ctl, hipStream_t st);
+// onC = vertices of the policy cycle whose smallest vertex is s.
+void launch_mc_mark_c(int n, const int* rep, const unsigned char* onc, int s, unsigned char* onC,
+                      hipStream_t st);
 
 // Upper bound of the batched workspace for G graphs over n vertices and m
 // edges, the largest graph at most max_n vertices and max_m edges.

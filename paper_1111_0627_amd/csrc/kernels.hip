@@ -243,11 +243,32 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
         __syncthreads();
         // this vertex's edges inside the batch, in CSR order
         const int lo = mb > eb ? mb : eb, hi = me < eb + cnt ? me : eb + cnt;
-        for (int e = lo; e < hi; ++e) {
-            const KT k = key[e - eb];
-            if (k < best) {
-                best = k;
-                pos = e;
+        const bool long_row = hi - lo > kLongRow;
+        if (!long_row)
+            for (int e = lo; e < hi; ++e) {
+                const KT k = key[e - eb];
+                if (k < best) {
+                    best = k;
+                    pos = e;
+                }
+            }
+        // the wave's long rows, one after the other, by all its lanes
+        for (unsigned long long lm = __ballot(long_row); lm; lm &= lm - 1) {
+            const int l = __ffsll((long long)lm) - 1;
+            const int rlo = __shfl(lo, l, 64), rhi = __shfl(hi, l, 64);
+            KT rb = val_max<KT>();
+            int rp = INT32_MAX, rh = 0;
+            for (int e = rlo + (t & 63); e < rhi; e += 64) {
+                const KT k = key[e - eb];
+                if (k < rb) {
+                    rb = k;
+                    rp = e;
+                }
+            }
+            wave_argmin<KT, false>(rb, rp, rh);
+            if ((t & 63) == l && rb < best) {   // earlier batches hold lower positions
+                best = rb;
+                pos = rp;
             }
         }
         __syncthreads();
@@ -336,7 +357,8 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
         }
         __syncthreads();
         const int lo = mb > eb ? mb : eb, hi = me < eb + n_e ? me : eb + n_e;
-        for (int e = lo; e < hi; ++e) {
+        const bool long_row = hi - lo > kLongRow;
+        for (int e = lo; e < (long_row ? lo : hi); ++e) {
             const KT k = key[e - eb];
             const int h = head[e - eb];
             if (SWEEP && k < best) {
@@ -355,6 +377,47 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
                 if (tight && slot < a.xcap) {
                     a.xs[slot] = (int)(v0 + t);
                     a.ys[slot] = h;
+                }
+            }
+        }
+        // the wave's long rows, one after the other, by all its lanes
+        for (unsigned long long lm = __ballot(long_row); lm; lm &= lm - 1) {
+            const int l = __ffsll((long long)lm) - 1;
+            const int rlo = __shfl(lo, l, 64), rhi = __shfl(hi, l, 64);
+            const KT rown = shfl_kt(own, l);
+            const int rcur = __shfl(cur, l, 64), rhv = __shfl(hv, l, 64);
+            const bool ronc = __shfl((int)onc, l, 64) != 0;
+            const int rv = (int)(v0 + (t & ~63) + l);
+            KT rb = val_max<KT>();
+            int rp = INT32_MAX, rh = 0;
+            for (int e = rlo + (t & 63); e < rhi; e += 64) {
+                const KT k = key[e - eb];
+                const int h = head[e - eb];
+                if (SWEEP && k < rb) {
+                    rb = k;
+                    rp = e;
+                    rh = h;
+                }
+                const bool tight = k == rown && e != rcur;
+                if (tight) {
+                    cnt++;
+                    if (h == rv || ronc) certain++;
+                    if (a.hop && a.hop[h] >= rhv) nondec++;
+                }
+                if (a.xs) {
+                    const unsigned slot = wave_append(tight, a.xcnt);
+                    if (tight && slot < a.xcap) {
+                        a.xs[slot] = rv;
+                        a.ys[slot] = h;
+                    }
+                }
+            }
+            if (SWEEP) {
+                wave_argmin<KT, true>(rb, rp, rh);
+                if ((t & 63) == l && rb < best) {   // earlier batches hold lower positions
+                    best = rb;
+                    pos = rp;
+                    bhead = rh;
                 }
             }
         }
@@ -378,48 +441,6 @@ __global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __r
         if (SWEEP && sums[3]) atomicAdd(&ln.changed, sums[3]);
         if (SWEEP && sums[4]) atomicOr(&ln.cbroken, 1u);
     }
-}
-
-// ---------------------------------------------------------------------------
-// Device-driven rounds (rebuild, values, cycles): the host queues several
-// rounds ahead; a round kernel runs only while the control block says its
-// round is next, and the last of its workgroups to finish books the round.
-// Each workgroup's thread 0 arrives with one 64-bit atomic adding
-// (1 << 48) + (flag << 32) + count, so its counts travel with the arrival
-// and no fence is needed.  Arrivals are counted per lane first (same-address
-// atomics serialise), then per lane.  Counts must sum below 2^32, flags
-// below 2^16.
-// ---------------------------------------------------------------------------
-constexpr unsigned long long kArrive = 1ull << 48;
-
-__device__ __forceinline__ unsigned long long arrival_word(unsigned long long count, unsigned flag)
-{
-    return count + ((unsigned long long)flag << 32);
-}
-
-// True for the grid's last arrival, which gets the summed word (arrival
-// counts removed) in *total and leaves the counters at zero.
-__device__ __forceinline__ bool last_arrival(Ctl* c, unsigned long long word,
-                                             unsigned long long* total)
-{
-    const unsigned lane = blockIdx.x & (kLanes - 1);
-    const unsigned in_lane = (gridDim.x - lane + kLanes - 1) / kLanes;
-    const unsigned lanes = gridDim.x < (unsigned)kLanes ? gridDim.x : (unsigned)kLanes;
-    const unsigned long long lp = atomicAdd(&c->lane[lane].rpack, word + kArrive);
-    if ((unsigned)(lp >> 48) != in_lane - 1) return false;
-    __hip_atomic_store(&c->lane[lane].rpack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long lane_sum = lp + word + kArrive - (unsigned long long)in_lane * kArrive;
-    const unsigned long long tp = atomicAdd(&c->rpack, lane_sum + kArrive);
-    if ((unsigned)(tp >> 48) != lanes - 1) return false;
-    __hip_atomic_store(&c->rpack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *total = tp - (unsigned long long)(lanes - 1) * kArrive + lane_sum;
-    return true;
-}
-
-// Is round r of the device-driven jump rounds the next one?
-__device__ __forceinline__ bool jump_round_is(const Ctl* c, int r)
-{
-    return c->jk + 1 == (unsigned)r && c->jmode == 1u;
 }
 
 // Start of device-driven jump rounds.  values: round 1 runs if init left
@@ -1840,19 +1861,6 @@ __global__ __launch_bounds__(kWG) void k_val_init(int n, const int* __restrict__
     if (threadIdx.x == 0 && act) atomicAdd(&my_lane(ctl).active, (unsigned)act);
 }
 
-__device__ __forceinline__ Jmp jmp_combine(Jmp q, const Jmp& r)
-{
-    long long d;
-    if (__builtin_add_overflow(q.D, r.D, &d)) {
-        d = 0;
-        q.H |= kHopOverflow;
-    }
-    q.D = d;
-    q.J = r.J;
-    q.H = ((q.H & ~kHopOverflow) + (r.H & ~kHopOverflow)) | ((q.H | r.H) & kHopOverflow);
-    return q;
-}
-
 // int128 entries: the sum's low word stays in the Jmp entry, its high word in
 // a parallel array (hin / hout); no overflow is possible (|sum| < n * 2^62).
 __device__ __forceinline__ void jmp_combine_wide(Jmp& q, long long& qh, const Jmp& r, long long rh)
@@ -2233,6 +2241,7 @@ __global__ void k_ctl_clear(Ctl* ctl, unsigned what)
             ln.certain = 0;
             ln.nondec = 0;
             ln.bad = 0;
+            ln.ncrit = 0;
         }
         if (what & kClrCount) {
             ln.active = 0;
@@ -2889,6 +2898,7 @@ __global__ void k_post_ctl(const Ctl* __restrict__ c, CtlView* dst, unsigned* se
     v.overflow = lane_or(ln.overflow);
     v.bad = lane_or(ln.bad);
     v.wide32 = lane_or(ln.wide32);
+    v.ncrit = (unsigned)lane_sum(ln.ncrit);
     for (int j = 0; j < 4; ++j) v.pjc[j] = (unsigned)lane_sum(ln.pjc[j]);
     if (threadIdx.x == 0) {
         v.W = c->W;

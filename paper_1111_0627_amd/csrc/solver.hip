@@ -910,6 +910,8 @@ bool has_cycle(int N, const std::vector<int>& head, const std::vector<int>& next
 // the tight subgraph.  Quick exact answers first (no such edge; a tight
 // self-loop; a tight edge leaving C), then the compressed special-vertex
 // graph described at k_tie_mark.
+ocm_status tie_from_list(Ctx& c, unsigned kx, ocm_result* out);
+
 ocm_status tie_check(Ctx& c, long long W, long long L, ocm_result* out)
 {
     Ws& w = c.ws;
@@ -969,6 +971,15 @@ ocm_status tie_check(Ctx& c, long long W, long long L, ocm_result* out)
     OCM_TRY(phase_sweep(c, false, true, w.V, W, L, w.pi, w.onC, true, true));
     const unsigned kx = c.h.xcnt;
     if (kx != k) return fail(OCM_E_HIP, "tie scan listed a different edge count");
+    return tie_from_list(c, kx, out);
+}
+
+// The tie decision from the listed tight non-policy edges (w.xs, w.ys; kx of
+// them) whose tails have the optimal gain: the special-vertex graph below.
+// Every policy path from such a vertex reaches C.
+ocm_status tie_from_list(Ctx& c, unsigned kx, ocm_result* out)
+{
+    Ws& w = c.ws;
     int* spid = w.layer;
     int* slist = w.list[1];
     int* P = w.list[0];
@@ -1019,6 +1030,192 @@ long long gcd_ll(long long a, long long b)
     return a;
 }
 
+// Multichain policy iteration (ocm_options.multichain): every policy cycle
+// keeps its own gain and no rebuild runs.  The first sweep is R1's, the stop
+// rule R8's; each later iteration finds the policy graph's cycles, sums them,
+// propagates every vertex's value toward the smallest vertex of the cycle it
+// reaches, and sweeps with (gain, bias) pairs.  At the end C is the policy
+// cycle with the smallest gain (ties: the smallest vertex), the same order as
+// the select of Alg. 2.
+struct McRun {
+    const Jmp* R = nullptr;   // records of the last value phase
+};
+
+ocm_status mc_values(Ctx& c, McRun& run)
+{
+    Ws& w = c.ws;
+    ocm::launch_ctl_clear(w.ctl, ocm::kClrCount, c.st);
+    c.prof.begin(OCM_K_SELECT);
+    ocm::launch_cyc_zero(c.n, w.rep, w.onc, w.wsum, w.lcnt, w.cyc, w.ctl, c.st);
+    ocm::launch_cyc_sum(c.n, w.rep, w.onc, w.pi, c.w, c.wtype, c.neg, w.wsum, w.lcnt, c.st);
+    c.prof.end();
+    c.prof.bytes(OCM_K_SELECT, 6.0 * c.n);
+    c.prof.begin(OCM_K_VALUES);
+    const bool have_succ = c.succ_ok;
+    ocm::launch_mc_val_init(c.n, c.col, w.pi, c.w, c.wtype, c.neg, w.rep, w.onc, w.wsum, w.lcnt,
+                            w.succ, have_succ, w.Q[0], w.ctl, c.st);
+    c.succ_ok = true;
+    c.prof.end();
+    // pi, succ, rep, on-cycle flag, w[pi], the entry
+    c.prof.bytes(OCM_K_VALUES, (29.0 + c.sw) * c.n);
+    HIP_TRY(hipGetLastError());
+    ocm::launch_jump_setup(w.ctl, true, false, c.st);
+    int r = 0;
+    for (;;) {
+        c.prof.begin(OCM_K_VALUES);
+        for (int j = 0; j < kRoundsPerRead; ++j) {
+            ++r;
+            ocm::launch_mc_round_dev(c.n, r, w.Q[(r - 1) & 1], w.Q[r & 1], w.ctl, c.st);
+        }
+        ocm::launch_mc_final_dev(c.n, w.Q[0], w.Q[1], w.V, w.hop, w.ctl, c.st);
+        c.prof.end();
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        if (c.h.jmode == 0) break;
+        if (r > 64) return fail(OCM_E_HIP, "value propagation did not converge");
+    }
+    const int k = (int)c.h.jk;
+    c.jump_rounds += k;
+    c.value_rounds += k;
+    // own entry, gathered entry, new entry per round; the final's record
+    c.prof.bytes(OCM_K_VALUES, 48.0 * c.n * k + 44.0 * c.n);
+    if (c.h.jstall) return fail(OCM_E_HIP, "a policy path reaches no cycle");
+    if (c.h.overflow)
+        return fail(OCM_E_OVERFLOW, "a multichain value left [-2^62, 2^62] (int64 only)");
+    run.R = w.Q[k & 1];
+    return OCM_OK;
+}
+
+ocm_status mc_sweep(Ctx& c, const McRun& run, bool tie, long long W, long long L, bool list)
+{
+    Ws& w = c.ws;
+    ocm::launch_ctl_clear(w.ctl, ocm::kClrChanged, c.st);
+    ocm::McArgs a;
+    a.n = c.n;
+    a.neg = c.neg;
+    a.row_ptr = c.row_ptr;
+    a.col = c.col;
+    a.R = run.R;
+    a.wsum = w.wsum;
+    a.lcnt = w.lcnt;
+    a.pi = w.pi;
+    a.succ = w.succ;
+    a.ctl = w.ctl;
+    a.W = W;
+    a.L = L;
+    a.onC = w.onC;
+    a.xs = list ? w.xs : nullptr;
+    a.ys = list ? w.ys : nullptr;
+    a.xcnt = &w.ctl->xcnt;
+    a.xcap = w.xcap;
+    const int cls = tie ? OCM_K_TIESCAN : OCM_K_SWEEP;
+    c.prof.begin(cls);
+    ocm::launch_mc_sweep(a, c.w, c.wtype, c.G, tie, c.st);
+    c.prof.end();
+    // row_ptr, own record + gain; per edge col, w, the head's record and gain
+    c.prof.bytes(cls, 28.0 * c.n + (4.0 + c.sw + 28.0) * c.m);
+    HIP_TRY(hipGetLastError());
+    return read_ctl(c);
+}
+
+ocm_status solve_mc(Ctx& c, const ocm_options& o, int32_t* cycle_edges, int64_t cap,
+                    ocm_result* out)
+{
+    Ws& w = c.ws;
+    McRun run;
+    ocm_status rc = phase_sweep(c, true, false, w.V, 0, 1, w.pi, nullptr, false, false, false);
+    int iter = 1;
+    unsigned long long tight = 0;
+    while (rc == OCM_OK) {
+        if ((o.max_iters > 0 && iter >= o.max_iters) || iter >= kIterCap) {
+            rc = fail(OCM_E_NOT_CONVERGED, "max_iters reached");
+            break;
+        }
+        ++c.general_iters;
+        rc = phase_cycles(c, w.pi, w.rep, w.onc);
+        if (rc != OCM_OK) break;
+        rc = mc_values(c, run);
+        if (rc != OCM_OK) break;
+        rc = mc_sweep(c, run, false, 0, 1, false);
+        if (rc != OCM_OK) break;
+        ++iter;
+        tight = c.h.tight;
+        if (c.h.changed == 0) break;   // no strict improvement left
+    }
+    out->iterations = iter;
+    out->jump_rounds = c.jump_rounds;
+    out->general_iters = c.general_iters;
+    out->value_rounds = c.value_rounds;
+    if (rc != OCM_OK) {
+        c.prof.finish();
+        return rc;
+    }
+    // C: the last policy's cycle of smallest gain (the sums are recomputed)
+    rc = phase_select(c, w.pi, w.rep, w.onc);
+    if (rc != OCM_OK) {
+        c.prof.finish();
+        return rc;
+    }
+    const int s = c.h.s;
+    const long long W = c.h.W, L = c.h.L, clen = c.h.clen;
+    const long long gg = gcd_ll(W, L);
+    out->p = (c.neg ? -W : W) / gg;
+    out->q = L / gg;
+    out->W = c.neg ? -W : W;
+    out->L = L;
+    out->source = s;
+    out->cycle_len = clen;
+    if (cap < clen) {
+        c.prof.finish();
+        return fail(OCM_E_CAPACITY, "cycle_cap smaller than the critical cycle");
+    }
+    c.prof.begin(OCM_K_RESULT);
+    ocm::launch_mc_mark_c(c.n, w.rep, w.onc, s, w.onC, c.st);
+    ocm::launch_cycle_list(c.n, s, clen, w.onC, w.pi, w.hop, cycle_edges, c.st);
+    c.prof.end();
+    c.prof.bytes(OCM_K_RESULT, 7.0 * c.n + 28.0 * clen);
+    HIP_TRY(hipGetLastError());
+    if (o.tie_check) {
+        // tight edges: those of the last sweep (it changed nothing)
+        out->tight_edges = (int64_t)tight;
+        if (tight > 0) out->flags |= OCM_F_TIGHT_EDGES;
+        // a second policy cycle of optimal gain is a second critical cycle;
+        // otherwise every vertex of optimal gain reaches C, and the
+        // single-gain test applies to the tight edges among them
+        ocm::launch_ctl_clear(w.ctl, ocm::kClrChanged, c.st);
+        ocm::launch_mc_ncrit(w.cyc, w.wsum, w.lcnt, W, L, w.ctl, c.st);
+        HIP_TRY(hipGetLastError());
+        OCM_TRY(read_ctl(c));
+        if (c.h.ncrit > 1) {
+            out->flags |= OCM_F_TIE;
+        } else if (tight > 0) {
+            OCM_TRY(mc_sweep(c, run, true, W, L, false));
+            const unsigned long long k = c.h.tight;
+            if (c.h.certain > 0) {
+                out->flags |= OCM_F_TIE;
+            } else if (k > 0 && c.h.nondec > 0) {
+                if (k > w.xcap) {
+                    out->flags |= OCM_F_TIE_UNCHECKED;
+                } else {
+                    OCM_TRY(mc_sweep(c, run, true, W, L, true));
+                    if (c.h.xcnt != k) return fail(OCM_E_HIP, "tie scan listed a different edge count");
+                    OCM_TRY(tie_from_list(c, (unsigned)k, out));
+                }
+            }
+        }
+    } else {
+        out->flags |= OCM_F_TIE_UNCHECKED;
+        out->tight_edges = -1;
+    }
+    if (o.policy_out)
+        HIP_TRY(hipMemcpyAsync(o.policy_out, w.pi, 4 * (size_t)c.n, hipMemcpyDeviceToDevice, c.st));
+    if (o.potential_out)
+        HIP_TRY(hipMemcpyAsync(o.potential_out, w.V, 8 * (size_t)c.n, hipMemcpyDeviceToDevice, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    c.prof.finish();
+    return OCM_OK;
+}
+
 // t (nullable): edge times, the optimal cycle ratio instead of the mean.
 ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t ws_bytes,
                  int32_t* cycle_edges, int64_t cap, ocm_result* out, void* stream, int neg,
@@ -1045,8 +1242,12 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
     c.wide = o.int128_values != 0;
     if (c.connect_mode < 0 || c.connect_mode > 2) return fail(OCM_E_INVALID_ARG, "bad connect_mode");
 
+    if (o.multichain && (o.init_policy || t || o.int128_values))
+        return fail(OCM_E_INVALID_ARG,
+                    "multichain runs without init_policy, edge times or int128 values");
     ocm_status rc = validate(c, o.validate != 0);
     if (rc != OCM_OK) { c.prof.finish(); return rc; }
+    if (o.multichain) return solve_mc(c, o, cycle_edges, cap, out);
     start_reverse_early(c);
     HIP_TRY(hipGetLastError());
 

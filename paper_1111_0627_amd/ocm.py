@@ -72,7 +72,8 @@ class Options(C.Structure):
                 ("tie_check", C.c_int32), ("fast_path", C.c_int32),
                 ("connect_mode", C.c_int32), ("tile", C.c_int32), ("init_policy", C.c_void_p),
                 ("policy_out", C.c_void_p), ("potential_out", C.c_void_p),
-                ("profile", C.POINTER(Profile)), ("int128_values", C.c_int32)]
+                ("profile", C.POINTER(Profile)), ("int128_values", C.c_int32),
+                ("multichain", C.c_int32)]
 
 
 _lib = None
@@ -226,11 +227,13 @@ CONNECT_MODES = {"auto": 0, "pull": 1, "push": 2}
 
 
 def options(max_iters=0, validate=True, schedule=0, tie_check=True, fast_path=True,
-            connect="auto", init_policy=None, tile=0, int128=False) -> Options:
+            connect="auto", init_policy=None, tile=0, int128=False,
+            multichain=False) -> Options:
     o = Options()
     lib().ocm_default_options(C.byref(o))
     o.max_iters, o.validate, o.schedule, o.tile = max_iters, int(validate), schedule, tile
     o.int128_values = int(int128)
+    o.multichain = int(multichain)
     o.tie_check, o.fast_path = int(tie_check), int(fast_path)
     o.connect_mode = CONNECT_MODES[connect]
     if init_policy is not None:

@@ -107,6 +107,38 @@ def random_digraph(n: int, dlo: int, dhi: int, wlo: int, whi: int,
     return Graph(row_ptr.astype(np.int32), col, w, name)
 
 
+def hub_graph(n: int, hubs: int, hub_deg: int, dlo: int, dhi: int, wlo: int, whi: int,
+              wdtype=np.int64, seed=0, name: str = "") -> Graph:
+    """random_digraph(n, dlo, dhi, ...) whose vertices 0, n/hubs, 2n/hubs, ...
+    (``hubs`` of them) get ``hub_deg`` extra out-edges to uniform targets: a
+    few rows far longer than the rest (power-law-like hubs)."""
+    base = random_digraph(n, dlo, dhi, wlo, whi, wdtype, seed)
+    rng = _rng([seed, 1] if isinstance(seed, int) else [*seed, 1])
+    deg = np.diff(base.row_ptr.astype(np.int64))
+    hub_ids = (np.arange(hubs, dtype=np.int64) * n) // max(hubs, 1)
+    extra = np.zeros(n, np.int64)
+    extra[hub_ids] = hub_deg
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(deg + extra, out=row_ptr[1:])
+    m = int(row_ptr[-1])
+    if m >= 2**31:
+        raise ValueError("edge count must stay below 2^31")
+    col = np.empty(m, np.int32)
+    w = np.empty(m, wdtype)
+    # each row: its base edges (ring edge last), then the hub's extra edges
+    src_base = np.repeat(np.arange(n), deg)
+    off_base = np.arange(base.row_ptr[-1]) - np.repeat(base.row_ptr[:-1].astype(np.int64), deg)
+    pos_base = row_ptr[:-1][src_base] + off_base
+    col[pos_base] = base.col
+    w[pos_base] = base.w
+    src_x = np.repeat(np.arange(n), extra)
+    off_x = np.arange(int(extra.sum())) - np.repeat(np.cumsum(extra) - extra, extra)
+    pos_x = row_ptr[:-1][src_x] + deg[src_x] + off_x
+    col[pos_x] = rng.integers(0, n, len(pos_x)).astype(np.int32)
+    w[pos_x] = rng.integers(wlo, whi + 1, len(pos_x)).astype(wdtype)
+    return Graph(row_ptr.astype(np.int32), col, w, name)
+
+
 def deep_tail_graph(ring: int, tail: int, extra: int = 2, wlight: int = 10,
                     hlo: int = 2**47, hhi: int = 2**48, seed=0, name: str = "") -> Graph:
     """Light ring fed by a long heavy tail; recipe in the module docstring."""

@@ -70,7 +70,7 @@ def test_struct_layouts_match_header(tmp_path, libpath):
 #include "ocm.h"
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(ocm_graph), sizeof(ocm_result), sizeof(ocm_options), sizeof(ocm_profile));
-  printf("%zu %zu %zu %zu %zu\n", offsetof(ocm_result, flags), offsetof(ocm_result, W), offsetof(ocm_result, tight_edges), offsetof(ocm_options, profile), offsetof(ocm_options, int128_values));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(ocm_result, flags), offsetof(ocm_result, W), offsetof(ocm_result, tight_edges), offsetof(ocm_options, profile), offsetof(ocm_options, int128_values), offsetof(ocm_options, multichain));
   return 0;
 }
 ''')
@@ -83,7 +83,7 @@ int main(void) {
                          C.sizeof(ocm.Profile)]
     assert sizes[4:] == [ocm._Result.flags.offset, ocm._Result.W.offset,
                          ocm._Result.tight_edges.offset, ocm.Options.profile.offset,
-                         ocm.Options.int128_values.offset]
+                         ocm.Options.int128_values.offset, ocm.Options.multichain.offset]
 
 
 def test_product_path_has_no_oracle_dependency():

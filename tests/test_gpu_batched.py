@@ -245,3 +245,21 @@ def test_batched_values_beyond_int32():
         cyc = (res.cycle(k).cpu().numpy() - eptr[k]).tolist()
         assert (res.p[k], res.q[k], cyc, res.iterations[k]) == \
             (sol.p, sol.q, sol.cycle.tolist(), sol.iterations), k
+
+
+def test_batched_hub_rows():
+    """Graphs with hub rows (walked by the whole wave in the batched tile
+    sweep) next to ordinary graphs; every graph equals the oracle."""
+    gs = [synth.hub_graph(n, h, d, 1, 4, 0, 5, np.int64, seed=[9, n])
+          for n, h, d in ((3000, 2, 20000), (500, 1, 3000), (12000, 30, 900))]
+    gs.insert(1, synth.random_digraph(4000, 1, 5, 1, 1000, np.int64, seed=[9, 1]))
+    u, vptr, eptr = synth.disjoint_union(gs)
+    for mode in ("min", "max"):
+        res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr, mode=mode)
+        assert all(s == ocm.OCM_OK for s in res.status)
+        for k, g in enumerate(gs):
+            sol = native.solve(g.row_ptr, g.col, g.w, mode=mode)
+            cyc = (res.cycle(k).cpu().numpy() - eptr[k]).tolist()
+            assert (res.p[k], res.q[k], cyc, res.iterations[k]) == \
+                (sol.p, sol.q, sol.cycle.tolist(), sol.iterations), k
+            assert res.tie(k) == bool(sol.tie), k

@@ -331,6 +331,28 @@ def test_schedules_and_fast_path_give_identical_bytes():
             assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1])
 
 
+@pytest.mark.parametrize("hubs,hub_deg,wlo,whi,seed", [
+    (3, 50000, 0, 3, 1), (40, 2000, -20, 20, 2), (1, 300000, 1, 1000, 3), (200, 70, 0, 1, 4)])
+def test_hub_rows_walked_by_their_wave(hubs, hub_deg, wlo, whi, seed):
+    """Rows far longer than the rest (hubs) are walked by the whole wave in
+    the tile sweeps and tie scans; every schedule, value mode and tie path
+    must still match the oracle byte for byte (small weight ranges make many
+    tight edges on the hub rows)."""
+    g = synth.hub_graph(20000, hubs, hub_deg, 1, 4, wlo, whi, np.int64, seed=[21, seed])
+    for mode in ("min", "max"):
+        sol = native.solve(g.row_ptr, g.col, g.w, mode=mode)
+        rp, cl, w = to_dev(g.row_ptr, g.col, g.w)
+        ref = None
+        for kw in ({}, {"schedule": 64}, {"int128": True}, {"fast_path": False}):
+            res = ocm.cycle_mean(rp, cl, w, mode=mode, want_policy=True, want_potential=True,
+                                 **kw)
+            assert_same(res, sol)
+            cur = (res.policy.cpu().numpy(), res.potential.cpu().numpy())
+            if ref is None:
+                ref = cur
+            assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1])
+
+
 @pytest.mark.parametrize("kind", ["product", "random", "random_long_chunks"])
 def test_connect_directions_give_identical_bytes(kind):
     """Pull, push and automatic rebuild rounds, each with the rounds decided

@@ -21,13 +21,43 @@ def test_multichain_hand_trace():
     for tr in traces:
         rp, cl, w = (np.array(tr[k]) for k in ("row_ptr", "col", "w"))
         r = tr["multichain"]
-        s = native.solve_multichain(rp, cl, w)
+        s = native.solve_multichain(rp, cl, w, want_V=True, want_pi=True)
         assert (s.p, s.q, s.cycle.tolist(), s.source, s.iterations, s.tie, s.tight) == \
             (r["p"], r["q"], r["cycle"], r["source"], r["iterations"], r["tie"], r["tight"])
+        assert s.V.tolist() == r["V"] and s.pi.tolist() == r["pi"]
         u = tr["unichain"]
         su = native.solve(rp, cl, w)
         assert (su.p, su.q, su.cycle.tolist(), su.source, su.iterations) == \
             (u["p"], u["q"], u["cycle"], u["source"], u["iterations"])
+
+
+def test_multichain_tight_edges_closed_form():
+    """Equal weights: every cycle is critical, every value is 0 and every
+    non-policy edge is tight (m - n of them)."""
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        n = int(rng.integers(1, 40))
+        rp, cl, w = brute.random_tiny(rng, n, 4, 0, 0)
+        w = np.full(len(cl), 7, np.int64)
+        s = native.solve_multichain(rp, cl, w, want_V=True)
+        assert s.value == 7 and s.tight == len(cl) - n
+        assert not s.V.any()
+
+
+def test_multichain_tight_edges_cover_critical_cycles():
+    """Every edge of every critical cycle is tight at the optimum (reduced
+    costs are non-negative and sum to zero around it), so the tight
+    non-policy edges number at least the critical cycles' edges outside the
+    policy."""
+    rng = np.random.default_rng(31)
+    for it in range(2000):
+        n = int(rng.integers(1, 7))
+        rp, cl, w = brute.random_tiny(rng, n, 3, -3, 3)
+        best, crit = brute.optimum(rp, cl, w)
+        s = native.solve_multichain(rp, cl, w, want_pi=True)
+        pol = set(s.pi.tolist())
+        on_crit = {e for c in crit for e in c} - pol
+        assert s.tight >= len(on_crit), it
 
 
 def test_multichain_against_brute_force():
