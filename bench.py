@@ -50,13 +50,15 @@ CSRC = os.path.join(ROOT, "paper_1111_0627_amd", "csrc")
 # device-driven round loops use k_round_*, k_val_round_dev and
 # k_pj_round_dev instead).  The first sweep is k_sweep_tile<.., true>; the
 # later ones also count tight edges (k_tiescan_tile<.., true>).
+# (kernel, (template argument index, value) or None): the tie scan's second
+# template argument says whether it is also the improvement sweep
 KERNEL_SYMBOL = {
-    "sweep": [("k_sweep_tile", ""), ("k_tiescan_tile", ", true>")],
-    "tiescan": [("k_tiescan_tile", ", false>")],
-    "conn_mark": [("k_conn_mark", "")], "conn_claim": [("k_conn_claim", "")],
-    "conn_pull": [("k_conn_pull", "")], "values": [("k_val_round", "")],
-    "fast": [("k_val_round", "")], "cycles": [("k_pj_round_tagged", "")],
-    "reverse": [("k_rev_place", "")],
+    "sweep": [("k_sweep_tile", None), ("k_tiescan_tile", (1, "true"))],
+    "tiescan": [("k_tiescan_tile", (1, "false"))],
+    "conn_mark": [("k_conn_mark", None)], "conn_claim": [("k_conn_claim", None)],
+    "conn_pull": [("k_conn_pull", None)], "values": [("k_val_round", None)],
+    "fast": [("k_val_round", None)], "cycles": [("k_pj_round_tagged", None)],
+    "reverse": [("k_rev_place", None)],
 }
 
 
@@ -67,21 +69,41 @@ def kernel_key(name):
     return name[len("ocm::"):] if name.startswith("ocm::") else name
 
 
+def template_args(key):
+    """Template arguments of a kernel key ("k_x<int, true, 0>" -> ["int", "true", "0"])."""
+    if "<" not in key:
+        return []
+    return [a.strip() for a in key[key.index("<") + 1:key.rindex(">")].split(",")]
+
+
 def class_kernels(table, cls):
     """Entries of a per-kernel table that belong to the class's kernel."""
+    def match(k, base, arg):
+        if k.split("<")[0] != base:
+            return False
+        if arg is None:
+            return True
+        a = template_args(k)
+        return len(a) > arg[0] and a[arg[0]] == arg[1]
     return [v for k, v in table.items()
-            if any(k.split("<")[0] == base and k.endswith(suffix)
-                   for base, suffix in KERNEL_SYMBOL.get(cls, []))]
+            if any(match(k, base, arg) for base, arg in KERNEL_SYMBOL.get(cls, []))]
+
+
+# The sources the single-graph solve is built from (the batched, general and
+# multichain files do not change its kernels).
+DIGEST_FILES = ("include/ocm.h", "paper_1111_0627_amd/csrc/kernels.h",
+                "paper_1111_0627_amd/csrc/device_util.h", "paper_1111_0627_amd/csrc/kernels.hip",
+                "paper_1111_0627_amd/csrc/solver.hip")
 
 
 def source_digest():
-    """sha256 over the HIP sources: counters taken from another build are not used."""
+    """sha256 over the single-graph solve's sources: counters and traces taken
+    from another build of its kernels are not used."""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for rel in DIGEST_FILES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
@@ -221,6 +243,60 @@ def summarize_pmc(fetch_dir, write_dir, out, workload, calib_mb, command):
         f.write("\n".join(lines))
 
 
+def summarize_l2(pmc_dir, out, workload, command):
+    """Writes profiles/<workload>_l2_hits.md from a rocprofv3 --pmc
+    TCC_HIT_sum TCC_MISS_sum csv run: L2 requests, hit rate and missed lines
+    per launch of every kernel."""
+    import csv
+    import glob
+    per = {}
+    for f in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] not in ("TCC_HIT_sum", "TCC_MISS_sum"):
+                continue
+            k = kernel_key(r["Kernel_Name"])
+            a = per.setdefault(k, {"TCC_HIT_sum": [], "TCC_MISS_sum": []})
+            a[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    rows = []
+    for k, v in per.items():
+        if not v["TCC_HIT_sum"] or not v["TCC_MISS_sum"]:
+            continue
+        n = len(v["TCC_HIT_sum"])
+        hit = sum(v["TCC_HIT_sum"]) / n
+        miss = sum(v["TCC_MISS_sum"]) / len(v["TCC_MISS_sum"])
+        rows.append((k, n, hit + miss, hit / (hit + miss) if hit + miss else 0.0, miss * 128 / 1e6))
+    rows.sort(key=lambda r: -r[2])
+    d = {"workload": workload, "source_sha256": source_digest(),
+         "kernels": {r[0]: {"launches": r[1], "requests": r[2], "hit_rate": r[3],
+                            "miss_mb": r[4]} for r in rows}}
+    lines = [f"# L2 hits and misses per launch, {workload}", "",
+             "Command (from the repository root):", "", "```", command, "```", "",
+             "L2 requests are counted after the wave's own coalescing (lanes that read one line make "
+             "one request). A miss, read or write, moves a 128-byte line.", "",
+             "| Kernel | Launches | L2 requests per launch | Hit rate | Misses × 128 B per launch |",
+             "|---|---:|---:|---:|---:|"]
+    for k, n, req, hr, mb in rows:
+        if req < 1e5:
+            continue
+        lines.append(f"| `{k}` | {n} | {req / 1e6:.2f}M | {hr:.3f} | {mb:.0f} MB |")
+    lines += ["", "```json", json.dumps(d, indent=1), "```", ""]
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with open(out, "w") as f:
+        f.write("\n".join(lines))
+
+
+def with_traffic(rf, traffic):
+    """Adds the counter-measured HBM bytes per launch and the rate they move
+    at (traffic over the live average launch time) beside the algorithmic
+    figures."""
+    rf["traffic"] = traffic
+    if traffic:
+        gbs = traffic / (rf["avg_launch_us"] / 1e6) / 1e9
+        rf["traffic_gbs"] = gbs
+        rf["traffic_frac"] = gbs / PEAK_HBM_GBS
+    return rf
+
+
 def roofline(cls, ms, launches, nbytes):
     """HBM roofline of one kernel class from the library's live hipEvent
     timings and its algorithmic bytes (both summed over the timed steps)."""
@@ -338,6 +414,7 @@ def bench_config(name, steps):
            "time_to_exact_ocm_ms": {"median": med, "min": min(ts)},
            "edges_per_s_per_iter": g.m * r.iterations / (med / 1e3),
            "roofline_sweep": roofline("sweep", *phase["sweep"])}
+    with_traffic(out["roofline_sweep"], traffic_per_launch(load_pmc(name), "sweep"))
     gold = os.path.join(ROOT, "tests", "golden", "workloads.json")
     if os.path.exists(gold):
         with open(gold) as f:
@@ -507,8 +584,11 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-multichain", action="store_true",
+                    help="skip the multichain variant's timing on the headline workload")
     ap.add_argument("--no-configs", action="store_true",
-                    help="skip the other single-graph workloads (rand1k, rand1m_max, rand4m_i64)")
+                    help="skip the other single-graph workloads (rand1k, rand1m_max, rand4m_i64, "
+                         "hub1m)")
     ap.add_argument("--fd-edges", type=int, default=1000)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy one buffer of this many MiB (a plain copy "
@@ -520,11 +600,20 @@ def main():
                     help="write profiles/<workload>_kernel_trace.md from a rocprofv3 "
                          "--kernel-trace database and exit")
     ap.add_argument("--trace-command", default="", help="command line recorded with --trace-summarize")
+    ap.add_argument("--l2-summarize", metavar="PMC_DIR",
+                    help="write profiles/<workload>_l2_hits.md from a rocprofv3 --pmc "
+                         "TCC_HIT_sum TCC_MISS_sum run and exit")
+    ap.add_argument("--l2-command", default="", help="command line recorded with --l2-summarize")
     ap.add_argument("--trace-note", default="", help="what the traced run did")
     args = ap.parse_args()
     if args.pmc_summarize:
         summarize_pmc(args.pmc_summarize[0], args.pmc_summarize[1], pmc_file(args.workload),
                       args.workload, args.calib_copy_mb or 1024, args.pmc_command)
+        return
+    if args.l2_summarize:
+        summarize_l2(args.l2_summarize,
+                     os.path.join(ROOT, "profiles", f"{args.workload}_l2_hits.md"),
+                     args.workload, args.l2_command)
         return
     if args.trace_summarize:
         summarize_trace(args.trace_summarize,
@@ -634,15 +723,17 @@ def main():
         pmc, trace = load_pmc(name), load_trace(name)
         out["roofline"] = roofline(dom, *phase[dom])
         out["roofline"]["class"] = dom
-        out["roofline"]["traffic"] = traffic_per_launch(pmc, dom)
+        with_traffic(out["roofline"], traffic_per_launch(pmc, dom))
         out["roofline"]["trace_avg_launch_us"] = trace_avg_us(trace, dom)
         out["roofline_sweep"] = roofline("sweep", *phase["sweep"])
-        out["roofline_sweep"]["traffic"] = traffic_per_launch(pmc, "sweep")
+        with_traffic(out["roofline_sweep"], traffic_per_launch(pmc, "sweep"))
         out["roofline_sweep"]["trace_avg_launch_us"] = trace_avg_us(trace, "sweep")
-    out["multichain"] = bench_multichain(rp, cl, w, mode, args.steps, r)
+    if not args.no_multichain:
+        log("[bench] multichain variant ...")
+        out["multichain"] = bench_multichain(rp, cl, w, mode, args.steps, r)
     if not args.no_configs:
         out["configs"] = {}
-        for cname in ("rand1k", "rand1m_max", "rand4m_i64"):
+        for cname in ("rand1k", "rand1m_max", "rand4m_i64", "hub1m"):
             if cname == name:
                 continue
             log(f"[bench] workload {cname} ...")

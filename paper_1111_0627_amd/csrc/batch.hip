@@ -1047,6 +1047,352 @@ __global__ __launch_bounds__(kWG) void k_tie_init(int G, GArrays ga)
     }
 }
 
+// ---------------------------------------------------------------------------
+// The small-graph class: a graph of at most kSmallN vertices and kSmallM
+// edges is solved whole by one workgroup, every per-vertex array in LDS
+// (vertex ids local, 16 bits), its CSR read from global memory (it stays in
+// L2 across the iterations).  The phases and rules are the single-graph
+// solver's (R1-R10): first sweep, then per iteration the policy graph's
+// cycles by pointer jumping, the minimum-mean select, the breadth-first
+// rebuild rounds, values by pointer jumping and the improvement sweep.
+// There is no fast path (it changes no result).  The graph's final policy,
+// successors, values, hops and C flags go to the batch arrays, so the
+// cycle listing and tie tests after the loop treat it like any other graph.
+// ---------------------------------------------------------------------------
+constexpr int kSmallN = 2048;
+constexpr int kSmallM = 32768;
+constexpr int kSmallWG = 512;
+constexpr int kSmallVPT = kSmallN / kSmallWG;   // vertices per thread
+constexpr int kSmallIterCap = 1 << 20;
+
+struct SmallLds {
+    long long V[kSmallN];       // values scaled by L
+    int pi[kSmallN];            // policy: global edge positions
+    short succ[kSmallN];        // local successor
+    short rep[kSmallN];         // smallest vertex of the reached cycle
+    short layer[kSmallN];       // rebuild round, -1 unattached
+    unsigned char onc[kSmallN]; // on a policy cycle
+    union {
+        struct {
+            short J[kSmallN];   // 2^k-th successor
+            short M[kSmallN];   // minimum over the next 2^k vertices
+        } cyc;
+        struct {
+            long long wsum[kSmallN];
+            int lcnt[kSmallN];
+        } sel;
+        struct {
+            long long D[kSmallN];   // sum of (L*w - W) over the first H policy edges
+            short J[kSmallN];
+            short H[kSmallN];
+        } val;
+    } u;
+    unsigned long long red[kSmallWG / 64];
+    long long cw[kSmallWG / 64], cl[kSmallWG / 64];
+    int cr[kSmallWG / 64];
+};
+
+// Sum over the workgroup, returned to every thread.
+__device__ __forceinline__ unsigned long long small_sum(unsigned long long x, SmallLds& S)
+{
+    x = wave_sum_u64(x);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) S.red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (int i = 0; i < kSmallWG / 64; ++i) t += S.red[i];
+    return t;
+}
+
+// (a.W / a.L, a.r) < (b.W / b.L, b.r); r < 0: none.
+__device__ __forceinline__ bool small_less(long long aw, long long al, int ar, long long bw,
+                                           long long bl, int br)
+{
+    if (br < 0) return ar >= 0;
+    if (ar < 0) return false;
+    const __int128 x = (__int128)aw * bl, y = (__int128)bw * al;
+    if (x != y) return x < y;
+    return ar < br;
+}
+
+template <typename WT>
+__global__ __launch_bounds__(kSmallWG) void k_small_solve(
+    const int* __restrict__ list, int nlist, GArrays ga, const int* __restrict__ row_ptr,
+    const int* __restrict__ col, const WT* __restrict__ w, int neg, int max_iters,
+    int* __restrict__ pi_out, int* __restrict__ succ_out, long long* __restrict__ V_out,
+    int* __restrict__ hop_out, unsigned char* __restrict__ onC_out)
+{
+    __shared__ SmallLds S;
+    const int t = threadIdx.x;
+    for (int li = blockIdx.x; li < nlist; li += gridDim.x) {
+        const int g = list[li];
+        const int v0 = (int)ga.vptr[g];
+        const int n = (int)(ga.vptr[g + 1] - v0);
+        // R1: the lowest-position minimum-weight out-edge
+        for (int v = t; v < n; v += kSmallWG) {
+            const int b = row_ptr[v0 + v], e1 = row_ptr[v0 + v + 1];
+            long long best = 0;
+            int arg = -1;
+            for (int e = b; e < e1; ++e) {
+                const long long x = wval(w, e, neg);
+                if (arg < 0 || x < best) {
+                    best = x;
+                    arg = e;
+                }
+            }
+            S.pi[v] = arg;
+            S.succ[v] = (short)(col[arg] - v0);
+        }
+        int iter = 1, status = OCM_OK, s = 0;
+        long long W = 0, L = 1;
+        __syncthreads();
+        for (;;) {
+            if ((max_iters > 0 && iter >= max_iters) || iter >= kSmallIterCap) {
+                status = OCM_E_NOT_CONVERGED;
+                break;
+            }
+            // cycles: after K rounds (2^K >= n) J(v) lies on v's cycle and
+            // M(J(v)) is that cycle's smallest vertex; the image of J is the
+            // set of cycle vertices
+            for (int v = t; v < n; v += kSmallWG) {
+                S.u.cyc.J[v] = S.succ[v];
+                S.u.cyc.M[v] = (short)v;
+                S.onc[v] = 0;
+            }
+            __syncthreads();
+            for (int span = 1; span < n; span <<= 1) {
+                short nj[kSmallVPT], nm[kSmallVPT];
+#pragma unroll
+                for (int i = 0; i < kSmallVPT; ++i) {
+                    const int v = t + i * kSmallWG;
+                    if (v < n) {
+                        const int j = S.u.cyc.J[v];
+                        nj[i] = S.u.cyc.J[j];
+                        const short a = S.u.cyc.M[v], b = S.u.cyc.M[j];
+                        nm[i] = a < b ? a : b;
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < kSmallVPT; ++i) {
+                    const int v = t + i * kSmallWG;
+                    if (v < n) {
+                        S.u.cyc.J[v] = nj[i];
+                        S.u.cyc.M[v] = nm[i];
+                    }
+                }
+                __syncthreads();
+            }
+            for (int v = t; v < n; v += kSmallWG) {
+                const int x = S.u.cyc.J[v];
+                S.onc[x] = 1;
+                S.rep[v] = S.u.cyc.M[x];
+            }
+            __syncthreads();
+            // select: per-cycle (W, L) keyed by the smallest vertex, then
+            // the order (W / L, rep)
+            for (int v = t; v < n; v += kSmallWG) {
+                S.u.sel.wsum[v] = 0;
+                S.u.sel.lcnt[v] = 0;
+            }
+            __syncthreads();
+            for (int v = t; v < n; v += kSmallWG)
+                if (S.onc[v]) {
+                    atomicAdd((unsigned long long*)&S.u.sel.wsum[S.rep[v]],
+                              (unsigned long long)wval(w, S.pi[v], neg));
+                    atomicAdd(&S.u.sel.lcnt[S.rep[v]], 1);
+                }
+            __syncthreads();
+            {
+                long long bw = 0, bl = 1;
+                int br = -1;
+                for (int v = t; v < n; v += kSmallWG)
+                    if (S.onc[v] && S.rep[v] == v &&
+                        small_less(S.u.sel.wsum[v], S.u.sel.lcnt[v], v, bw, bl, br)) {
+                        bw = S.u.sel.wsum[v];
+                        bl = S.u.sel.lcnt[v];
+                        br = v;
+                    }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const long long ow = __shfl_xor(bw, off, 64), ol = __shfl_xor(bl, off, 64);
+                    const int orr = __shfl_xor(br, off, 64);
+                    if (small_less(ow, ol, orr, bw, bl, br)) {
+                        bw = ow;
+                        bl = ol;
+                        br = orr;
+                    }
+                }
+                if ((t & 63) == 0) {
+                    S.cw[t >> 6] = bw;
+                    S.cl[t >> 6] = bl;
+                    S.cr[t >> 6] = br;
+                }
+                __syncthreads();
+                bw = S.cw[0];
+                bl = S.cl[0];
+                br = S.cr[0];
+                for (int i = 1; i < kSmallWG / 64; ++i)
+                    if (small_less(S.cw[i], S.cl[i], S.cr[i], bw, bl, br)) {
+                        bw = S.cw[i];
+                        bl = S.cl[i];
+                        br = S.cr[i];
+                    }
+                s = br;
+                W = bw;
+                L = bl;
+            }
+            // rebuild (R5, R6): C's component keeps its edges; round k
+            // attaches every other vertex with an out-edge into the vertices
+            // attached before round k, by its lowest such edge.  A vertex
+            // attached in round k is written at once: the others' test
+            // (0 <= layer < k) ignores it either way.
+            unsigned long long left = 0;
+            for (int v = t; v < n; v += kSmallWG) {
+                const bool keep = S.rep[v] == s;
+                S.layer[v] = keep ? 0 : -1;
+                left += !keep;
+            }
+            left = small_sum(left, S);
+            for (int k = 1; left > 0; ++k) {
+                unsigned long long got = 0;
+                for (int v = t; v < n; v += kSmallWG) {
+                    if (S.layer[v] != -1) continue;
+                    const int b = row_ptr[v0 + v], e1 = row_ptr[v0 + v + 1];
+                    for (int e = b; e < e1; ++e) {
+                        const int x = col[e] - v0;
+                        const int ly = S.layer[x];
+                        if (ly >= 0 && ly < k) {
+                            S.pi[v] = e;
+                            S.succ[v] = (short)x;
+                            S.layer[v] = (short)k;
+                            ++got;
+                            break;
+                        }
+                    }
+                }
+                got = small_sum(got, S);
+                if (got == 0) break;
+                left -= got;
+            }
+            if (left > 0) {
+                status = OCM_E_NOT_STRONGLY_CONNECTED;
+                break;
+            }
+            // values (R7) by pointer jumping toward s, one buffer: each
+            // round reads into registers, then writes
+            for (int v = t; v < n; v += kSmallWG) {
+                if (v == s) {
+                    S.u.val.D[v] = 0;
+                    S.u.val.J[v] = (short)s;
+                    S.u.val.H[v] = 0;
+                } else {
+                    S.u.val.D[v] = L * wval(w, S.pi[v], neg) - W;
+                    S.u.val.J[v] = S.succ[v];
+                    S.u.val.H[v] = 1;
+                }
+            }
+            unsigned long long ovf = 0;
+            bool stuck = false;
+            for (int r = 0;; ++r) {
+                // every vertex reaches s after the rebuild: ceil(log2 n) + 1
+                // rounds suffice; the bound only guarantees an exit
+                if (r > 32) {
+                    stuck = true;
+                    break;
+                }
+                __syncthreads();
+                long long nd[kSmallVPT];
+                short nj[kSmallVPT], nh[kSmallVPT];
+                unsigned long long act = 0;
+#pragma unroll
+                for (int i = 0; i < kSmallVPT; ++i) {
+                    const int v = t + i * kSmallWG;
+                    nj[i] = -1;
+                    if (v < n && S.u.val.J[v] != s) {
+                        const int j = S.u.val.J[v];
+                        long long d;
+                        if (__builtin_add_overflow(S.u.val.D[v], S.u.val.D[j], &d)) {
+                            d = 0;
+                            ovf = 1;
+                        }
+                        nd[i] = d;
+                        nj[i] = S.u.val.J[j];
+                        nh[i] = (short)(S.u.val.H[v] + S.u.val.H[j]);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < kSmallVPT; ++i) {
+                    const int v = t + i * kSmallWG;
+                    if (nj[i] >= 0) {
+                        S.u.val.D[v] = nd[i];
+                        S.u.val.J[v] = nj[i];
+                        S.u.val.H[v] = nh[i];
+                        act += nj[i] != s;
+                    }
+                }
+                if (small_sum(act, S) == 0) break;
+            }
+            if (stuck) {
+                status = OCM_E_NOT_STRONGLY_CONNECTED;
+                break;
+            }
+            for (int v = t; v < n; v += kSmallWG) {
+                const long long d = S.u.val.D[v];
+                if (d > kValLimit || d < -kValLimit) ovf = 1;
+                S.V[v] = d;
+            }
+            if (small_sum(ovf, S) != 0) {
+                status = OCM_E_OVERFLOW;
+                break;
+            }
+            // improvement sweep (R2): strict improvement, lowest position
+            unsigned long long changed = 0;
+            for (int v = t; v < n; v += kSmallWG) {
+                const int b = row_ptr[v0 + v], e1 = row_ptr[v0 + v + 1];
+                long long best = INT64_MAX;
+                int arg = -1, bh = 0;
+                for (int e = b; e < e1; ++e) {
+                    const int x = col[e] - v0;
+                    const long long key = S.V[x] + L * wval(w, e, neg) - W;
+                    if (key < best) {
+                        best = key;
+                        arg = e;
+                        bh = x;
+                    }
+                }
+                if (best < S.V[v]) {
+                    S.pi[v] = arg;
+                    S.succ[v] = (short)bh;
+                    ++changed;
+                }
+            }
+            ++iter;
+            if (small_sum(changed, S) == 0) break;
+        }
+        // the last value phase's results (the final sweep changed nothing)
+        const bool ok = status == OCM_OK;
+        for (int v = t; v < n; v += kSmallWG) {
+            pi_out[v0 + v] = S.pi[v];
+            succ_out[v0 + v] = v0 + S.succ[v];
+            if (ok) {
+                V_out[v0 + v] = S.V[v];
+                hop_out[v0 + v] = S.u.val.H[v];
+                onC_out[v0 + v] = (unsigned char)(S.onc[v] && S.rep[v] == s);
+            }
+        }
+        if (t == 0) {
+            ga.W[g] = W;
+            ga.L[g] = L;
+            ga.s[g] = v0 + s;
+            ga.iter[g] = iter;
+            ga.status[g] = status;
+            ga.mode[g] = kDone;
+        }
+        __syncthreads();   // S is reused by the next graph
+    }
+}
+
 }  // namespace b
 }  // namespace ocm
 
@@ -1111,6 +1457,7 @@ struct BWs {
     unsigned char* span_flag;   // rebuild: spans holding a rebuilt graph (flags, then list)
     int* spans;
     unsigned* bad;
+    int* small;          // graphs of the small class (solved one per workgroup in LDS)
     void* vctl;          // control block of the validation kernel
     void* sub;           // exact tie test of one graph: its rebased CSR, policy and
     size_t sub_bytes;    //   single-graph workspace (sized for the largest graph)
@@ -1192,6 +1539,7 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m, size_t sub_bytes)
     w.span_flag = (unsigned char*)take(nsp);
     w.spans = (int*)take(4 * nsp);
     w.bad = (unsigned*)take(256);
+    w.small = (int*)take(4 * Gs);
     w.vctl = take(sizeof(ocm::Ctl));
     w.sub = take(sub_bytes);
     w.sub_bytes = sub_bytes;
@@ -1241,6 +1589,7 @@ struct BCtx {
     bool tile_sweep = true;   // improvement sweeps over vertex tiles (else lanes per vertex)
     bool device_rounds = true;   // iterations after the first decide their rounds on the device
     int max_n = 1;
+    int64_t loop_G = 0, loop_n = 0;   // graphs and vertices the loop solves (not the small class)
 };
 
 ocm_status bread(BCtx& c)
@@ -1694,7 +2043,9 @@ int bits_of(int64_t x)
 ocm_status autotune(BCtx& c, Schedule* out, int* tuned)
 {
     const int l0 = default_lanes(c.n, c.m);
-    const TuneKey key{c.wtype, bits_of(c.G), bits_of(c.n / std::max<int64_t>(c.G, 1)), l0};
+    // the size class of the graphs the loop solves
+    const TuneKey key{c.wtype, bits_of(c.loop_G), bits_of(c.loop_n / std::max<int64_t>(c.loop_G, 1)),
+                      l0};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -2006,9 +2357,28 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
         }
     }
 
-    // schedule: given (lanes, tile), or autotuned and cached per size class
+    // size classes: graphs of at most kSmallN vertices and kSmallM edges are
+    // solved one per workgroup in LDS (OCM_BATCH_SMALL=0 sends them through
+    // the loop too; same results), the others by the loop
+    std::vector<int> small;
+    {
+        const char* se = getenv("OCM_BATCH_SMALL");
+        const bool use_small = !(se && se[0] == '0');
+        for (int64_t g = 0; g < G; ++g) {
+            const int64_t ng = vptr[g + 1] - vptr[g];
+            if (use_small && ng <= ocm::b::kSmallN && eptr[g + 1] - eptr[g] <= ocm::b::kSmallM) {
+                small.push_back((int)g);
+            } else {
+                ++c.loop_G;
+                c.loop_n += ng;
+            }
+        }
+    }
+
+    // schedule of the loop: given (lanes, tile), or autotuned and cached per
+    // size class
     int tuned = 0;
-    if (o.schedule <= 0 || o.tile <= 0) {
+    if ((o.schedule <= 0 || o.tile <= 0) && c.loop_G > 0) {
         Schedule t;
         BTRY(autotune(c, &t, &tuned));
         if (o.schedule <= 0) c.sch.lanes = t.lanes;
@@ -2017,6 +2387,34 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
     if (o.tile > 0) c.sch.chunk = o.tile;
     g_last_sched = {c.sch.lanes, c.sch.chunk};
     g_last_tuned = tuned;
+
+    // the small class, before the loop (which then leaves them alone: they
+    // are done)
+    if (!small.empty()) {
+        const int ns = (int)small.size();
+        BHIP(hipMemcpyAsync(ws.small, small.data(), 4 * (size_t)ns, hipMemcpyHostToDevice, c.st));
+        const void* kern = c.wtype == OCM_W_I64 ? (const void*)ocm::b::k_small_solve<long long>
+                                                : (const void*)ocm::b::k_small_solve<int>;
+        int per = 0, cus = 0, dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, ocm::b::kSmallWG, 0) != hipSuccess ||
+            per < 1)
+            per = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1)
+            cus = 8;
+        (void)hipGetLastError();
+        const unsigned grid = (unsigned)std::min<int64_t>(ns, (int64_t)per * cus);
+        if (c.wtype == OCM_W_I64)
+            ocm::b::k_small_solve<long long><<<grid, ocm::b::kSmallWG, 0, c.st>>>(
+                ws.small, ns, a, c.row_ptr, c.col, (const long long*)c.w, neg, o.max_iters, ws.pi,
+                ws.succ, ws.V, ws.hop, ws.onC);
+        else
+            ocm::b::k_small_solve<int><<<grid, ocm::b::kSmallWG, 0, c.st>>>(
+                ws.small, ns, a, c.row_ptr, c.col, (const int*)c.w, neg, o.max_iters, ws.pi,
+                ws.succ, ws.V, ws.hop, ws.onC);
+        BHIP(hipGetLastError());
+    }
 
     // iterations: [head graph] -> host rebuild rounds -> [tail graph]
     const char* env = getenv("OCM_BATCH_GRAPH");

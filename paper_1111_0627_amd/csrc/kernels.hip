@@ -301,8 +301,12 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
 // 1536 keeps 8 workgroups per CU (measured 13 % faster than 2048 here).
 constexpr int kTieTileEdges = 1536;
 
+// The mean with int64 or int32 values is held to 64 VGPRs (8 waves per
+// SIMD, as many as its LDS allows); left alone, the long-row walk would take
+// it to 72 VGPRs and 7 waves.
 template <typename WT, bool SWEEP, int VM = 0, bool RATIO = false>
-__global__ __launch_bounds__(kWG) void k_tiescan_tile(SweepArgs a, const WT* __restrict__ w)
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(RATIO || VM == 1 ? 4 : 8, 8)))
+void k_tiescan_tile(SweepArgs a, const WT* __restrict__ w)
 {
     using KT = typename ValT<VM>::type;
     __shared__ int beg[kWG + 1];

@@ -286,6 +286,8 @@ def workload(name: str) -> Graph:
         return product_graph(6, 16, 0.3, 1, 1000, 0, name)
     if name == "rand4m_i64":
         return random_digraph(2**22, 2, 6, 1, 2**20, np.int64, 0, name)
+    if name == "hub1m":
+        return hub_graph(2**20, 8, 2**20, 2, 6, 1, 1000, np.int64, 0, name)
     raise KeyError(name)
 
 
@@ -295,4 +297,6 @@ WORKLOADS = {
     "product16x6": dict(mode="min", desc="interleaving product of 6 automata x 16 states (n=16^6), p2=0.3, w int32 in [1,1000], seed 0"),
     "batch4096": dict(mode="min", desc="4096 random digraphs, n log-uniform in [100,1e5], deg 1-8 + ring, w int32 in [1,10000]"),
     "rand4m_i64": dict(mode="min", desc="random digraph n=2^22, deg 2-6 + ring, w int64 in [1,2^20], seed 0"),
+    "hub1m": dict(mode="min", desc="random digraph n=2^20, deg 2-6 + ring, plus 8 hubs of 2^20 extra out-edges, "
+                                   "w int64 in [1,1000], seed 0"),
 }

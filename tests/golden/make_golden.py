@@ -20,7 +20,7 @@ from paper_1111_0627_amd import synth  # noqa: E402
 
 OUT = os.path.join(HERE, "workloads.json")
 BATCH_OUT = os.path.join(HERE, "batch4096.json")
-NAMES = ["rand1k", "rand1m_max", "product16x6", "rand4m_i64", "batch4096"]
+NAMES = ["rand1k", "rand1m_max", "product16x6", "rand4m_i64", "hub1m", "batch4096"]
 
 
 def _batch_one(k):

@@ -263,3 +263,69 @@ def test_batched_hub_rows():
             assert (res.p[k], res.q[k], cyc, res.iterations[k]) == \
                 (sol.p, sol.q, sol.cycle.tolist(), sol.iterations), k
             assert res.tie(k) == bool(sol.tie), k
+
+
+def _small_class_batch(seed):
+    """Small graphs (the LDS class: n <= 2048) of every kind next to larger
+    ones: random weights, equal weights (ties), two disjoint rings (not
+    strongly connected), one vertex, and a light ring under a heavy tail
+    whose values leave int64 (OCM_E_OVERFLOW in the batched form); the
+    largest graph keeps 2 n max|w| below 2^62."""
+    rng = np.random.default_rng(seed)
+    gs = []
+    for k in range(40):
+        n = int(rng.integers(1, 2100))
+        lo = int(rng.integers(-50, 50))
+        gs.append(synth.random_digraph(n, 1, int(rng.integers(1, 9)), lo,
+                                       lo + int(rng.integers(0, 3) if k % 4 == 0 else 1000),
+                                       np.int64, seed=[seed, k]))
+    gs.insert(5, synth.Graph(np.array([0, 1, 2, 3, 4], np.int32), np.array([1, 0, 3, 2], np.int32),
+                             np.array([1, 1, 5, 5], np.int64)))
+    gs.insert(9, synth.deep_tail_graph(700, 800, 2, 10, 2**47, 2**48, seed=1))
+    gs.insert(12, synth.random_digraph(3000, 1, 5, 1, 100, np.int64, seed=[seed, 99]))
+    gs.insert(20, synth.Graph(np.array([0, 1], np.int32), np.array([0], np.int32),
+                              np.array([-7], np.int64)))
+    return gs
+
+
+@pytest.mark.parametrize("mode", ["min", "max"])
+def test_small_class_equals_loop_and_oracle(monkeypatch, mode):
+    """Graphs of at most 2048 vertices are solved one per workgroup in LDS;
+    with that class switched off (OCM_BATCH_SMALL=0) every graph goes
+    through the batched loop.  Both give identical bytes, every status
+    included, and every graph that succeeds equals the oracle."""
+    gs = _small_class_batch(41)
+    u, vptr, eptr = synth.disjoint_union(gs)
+    dev = to_dev(u)
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("OCM_BATCH_SMALL", flag)
+        r = ocm.cycle_mean_batched(*dev, vptr, eptr, mode=mode)
+        outs.append((r.p, r.q, r.iterations, r.cycle_ptr, r.cycle_edges.cpu().tolist(), r.flags,
+                     r.status))
+    assert outs[0] == outs[1]
+    p, q, iters, cptr, cyc_all, flags, status = outs[0]
+    assert status[5] == ocm.OCM_E_NOT_STRONGLY_CONNECTED
+    if mode == "min":
+        assert status[9] == ocm.OCM_E_OVERFLOW
+    for k, g in enumerate(gs):
+        if status[k] != ocm.OCM_OK:
+            continue
+        sol = native.solve(g.row_ptr, g.col, g.w, mode=mode)
+        cyc = [c - eptr[k] for c in cyc_all[cptr[k]:cptr[k + 1]]]
+        assert (p[k], q[k], cyc, iters[k]) == (sol.p, sol.q, sol.cycle.tolist(), sol.iterations), k
+        assert bool(flags[k] & ocm.OCM_F_TIE) == bool(sol.tie), k
+        assert bool(flags[k] & ocm.OCM_F_TIGHT_EDGES) == (sol.tight > 0), k
+
+
+def test_small_class_iteration_cap(monkeypatch):
+    gs = [synth.random_digraph(n, 1, 6, -100, 100, np.int64, seed=[42, n]) for n in (50, 900, 2000)]
+    u, vptr, eptr = synth.disjoint_union(gs)
+    dev = to_dev(u)
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("OCM_BATCH_SMALL", flag)
+        r = ocm.cycle_mean_batched(*dev, vptr, eptr, max_iters=3)
+        outs.append((r.p, r.q, r.iterations, r.status))
+    assert outs[0] == outs[1]
+    assert ocm.OCM_E_NOT_CONVERGED in outs[0][3]

@@ -511,7 +511,7 @@ def _golden():
         return json.load(f)
 
 
-@pytest.mark.parametrize("name", ["rand1m_max", "product16x6", "rand4m_i64"])
+@pytest.mark.parametrize("name", ["rand1m_max", "product16x6", "rand4m_i64", "hub1m"])
 def test_full_workloads_against_oracle_results(name):
     gold = _golden()[name]
     g = synth.workload(name)
