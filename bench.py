@@ -44,7 +44,9 @@ KERNEL_NAMES = {
 }
 
 
-CSRC = os.path.join(ROOT, "paper_1111_0627_amd", "csrc")
+# the sources whose digest marks profiles as current (not moved by tests that
+# point ROOT at a scratch directory)
+SRC_ROOT = ROOT
 # profile class -> the (kernel, instantiation suffix) pairs whose counters
 # give its traffic: the kernels the per-phase profile launches (the
 # device-driven round loops use k_round_*, k_val_round_dev and
@@ -102,7 +104,7 @@ def source_digest():
     import hashlib
     h = hashlib.sha256()
     for rel in DIGEST_FILES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
+        with open(os.path.join(SRC_ROOT, rel), "rb") as f:
             h.update(rel.encode() + b"\0" + f.read())
     return h.hexdigest()
 
