@@ -47,13 +47,12 @@ KERNEL_NAMES = {
 # the sources whose digest marks profiles as current (not moved by tests that
 # point ROOT at a scratch directory)
 SRC_ROOT = ROOT
-# profile class -> the (kernel, instantiation suffix) pairs whose counters
-# give its traffic: the kernels the per-phase profile launches (the
-# device-driven round loops use k_round_*, k_val_round_dev and
-# k_pj_round_dev instead).  The first sweep is k_sweep_tile<.., true>; the
-# later ones also count tight edges (k_tiescan_tile<.., true>).
-# (kernel, (template argument index, value) or None): the tie scan's second
-# template argument says whether it is also the improvement sweep
+# profile class -> the kernels whose counters give its traffic: the kernels
+# the per-phase profile launches (the device-driven round loops use
+# k_round_*, k_val_round_dev and k_pj_round_dev instead).  Each entry is
+# (kernel, (template argument index, value) or None): the first sweep is
+# k_sweep_tile, the later ones also count tight edges (k_tiescan_tile whose
+# second template argument, SWEEP, is true).
 KERNEL_SYMBOL = {
     "sweep": [("k_sweep_tile", None), ("k_tiescan_tile", (1, "true"))],
     "tiescan": [("k_tiescan_tile", (1, "false"))],
@@ -518,6 +517,49 @@ def bench_batched(steps: int):
             "cpu_oracle": batched_cpu_sample(gs)}
 
 
+def bench_small_class(steps: int):
+    """Many small graphs (16,384 random digraphs, n log-uniform in [64, 2048],
+    deg 1-8 + ring): the batched call with its small-graph class (one graph
+    per workgroup in LDS) against the same call with every graph sent
+    through the batched loop (OCM_BATCH_SMALL=0, identical results)."""
+    import torch
+    from paper_1111_0627_amd import ocm, synth
+    gs = synth.batch_graphs(G=16384, lo=64, hi=2048, seed=7)
+    u, vptr, eptr = synth.disjoint_union(gs)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(u.row_ptr).to(dev)
+    cl = torch.from_numpy(u.col).to(dev)
+    w = torch.from_numpy(u.w).to(dev)
+    out = {"workload": "16384 random digraphs, n log-uniform in [64, 2048], deg 1-8 + ring, "
+                       "w int32 in [1,10000]", "graphs": len(gs), "vertices": u.n, "edges": u.m}
+    res = {}
+    old = os.environ.get("OCM_BATCH_SMALL")
+    try:
+        for key, flag in (("small_class", "1"), ("loop_only", "0")):
+            os.environ["OCM_BATCH_SMALL"] = flag
+            r = ocm.cycle_mean_batched(rp, cl, w, vptr, eptr)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(steps):
+                t = time.perf_counter()
+                r = ocm.cycle_mean_batched(rp, cl, w, vptr, eptr)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t) * 1e3)
+            res[key] = r
+            out[key + "_ms"] = {"median": float(np.median(ts)), "min": min(ts)}
+    finally:
+        if old is None:
+            os.environ.pop("OCM_BATCH_SMALL", None)
+        else:
+            os.environ["OCM_BATCH_SMALL"] = old
+    a, b = res["small_class"], res["loop_only"]
+    out["identical"] = (a.p, a.q, a.iterations, a.cycle_ptr, a.flags, a.status) == \
+        (b.p, b.q, b.iterations, b.cycle_ptr, b.flags, b.status) and \
+        bool(torch.equal(a.cycle_edges, b.cycle_edges))
+    out["speedup"] = out["loop_only_ms"]["median"] / out["small_class_ms"]["median"]
+    return out
+
+
 def bench_adjoint(n_fd: int):
     """The adjoint workload: n = 2^22 random digraph with int64 weights;
     forward through the autograd Function, backward (adjoint scatter), and the
@@ -746,6 +788,8 @@ def main():
     if not args.no_batched:
         log("[bench] batched workload ...")
         out["batched"] = bench_batched(max(2, min(args.steps, 5)))
+        log("[bench] many small graphs ...")
+        out["batched_small"] = bench_small_class(max(2, min(args.steps, 5)))
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle ...")
         cb = cpu_baseline(g, mode)
