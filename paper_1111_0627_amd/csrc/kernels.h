@@ -18,6 +18,7 @@ constexpr unsigned kClrChanged = 1u;
 constexpr unsigned kClrCount = 2u;
 constexpr unsigned kClrAll = 4u;
 constexpr unsigned kClrActive2 = 8u;
+constexpr unsigned kClrGiant = 16u;
 
 // |V| must stay within 2^62 so that V[u] + (L*w - W) cannot leave int64 when
 // |L*w - W| < 2^62 as well.
@@ -76,6 +77,7 @@ struct alignas(128) Ctl {
     unsigned xcnt;                 // tie scan: tight non-policy edges listed
     unsigned scnt;                 // tie check: special vertices
     unsigned clen;                 // select: edges of the chosen cycle (its L for a mean)
+    unsigned ngiant;               // rows longer than kGiantRow
     CtlLane lane[kLanes];
 };
 
@@ -86,7 +88,7 @@ struct CtlView {
     unsigned ncyc;
     unsigned rmode, rleft, rfront, rerr, rk;
     unsigned jk, jmode, jlast, jstall;
-    unsigned xcnt, scnt, clen;
+    unsigned xcnt, scnt, clen, ngiant;
     unsigned long long changed, tight, certain, nondec, pedges, ledges, maxabsw;
     unsigned active, active2, got, left, err, cbroken, overflow, bad;
     unsigned pjc[4];
@@ -111,6 +113,7 @@ __host__ __device__ inline void fold_lanes(const Ctl& c, CtlView& v)
     v.xcnt = c.xcnt;
     v.scnt = c.scnt;
     v.clen = c.clen;
+    v.ngiant = c.ngiant;
     v.changed = v.tight = v.certain = v.nondec = v.pedges = v.ledges = v.maxabsw = 0;
     v.active = v.active2 = v.got = v.left = v.err = v.cbroken = v.overflow = v.bad = 0;
     v.wide32 = v.ncrit = 0;
@@ -155,6 +158,25 @@ struct alignas(16) Jmp {
     unsigned H;
 };
 
+// Rows of more than kGiantRow edges are swept by several workgroups: one per
+// chunk of at most kGiantChunk consecutive edges (k_giant_part), then one
+// merge per row in chunk order (k_giant_merge); the tile kernels skip them.
+// Built once per solve; ngiant = 0 leaves every row to the tile kernels.
+constexpr int kGiantRow = 8192;
+constexpr int kGiantChunk = 8192;
+
+struct GiantTab {
+    const int* cv = nullptr;       // chunk: its row's vertex,
+    const int* cs = nullptr;       //        first edge position
+    const int* ce = nullptr;       //        and end
+    int nchunks = 0;
+    const int* gv = nullptr;       // giant rows: vertex,
+    const int* gc0 = nullptr;      //             first chunk
+    const int* gc1 = nullptr;      //             and end chunk
+    int ngiant = 0;
+    void* parts = nullptr;         // per chunk: its best key, position and head (32 bytes)
+};
+
 struct SweepArgs {
     int n;
     int neg;
@@ -174,7 +196,14 @@ struct SweepArgs {
     int* ys;                       //           and head
     unsigned* xcnt;
     unsigned xcap;
+    GiantTab giant;                // rows swept by several workgroups (tile sweeps only)
 };
+
+// Giant rows: (vertex, first, end) triples of every row longer than
+// kGiantRow edges, appended in any order (at most cap; ctl->ngiant counts
+// them all).
+void launch_giant_list(int n, const int* row_ptr, int* triples, unsigned cap, Ctl* ctl,
+                       hipStream_t st);
 
 void launch_validate(int n, int m, const int* row_ptr, const int* col, const void* w, int wtype,
                      int check_csr, Ctl* ctl, hipStream_t st);
@@ -362,6 +391,7 @@ struct McArgs {
     int* ys;
     unsigned* xcnt;
     unsigned xcap;
+    GiantTab giant;                // rows swept by several workgroups (as in the tile sweeps)
 };
 // Entries of every vertex: roots (the smallest vertex of each policy cycle)
 // finished with D = 0; succ gets col[pi] unless have_succ; lanes' active =

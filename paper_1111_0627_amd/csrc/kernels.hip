@@ -184,6 +184,23 @@ __global__ __launch_bounds__(kWG) void k_sweep_u(SweepArgs a, const WT* __restri
 // loads per batch instead of per vertex step; same result as k_sweep_u.
 constexpr int kTileEdges = 2048;
 
+// First position at or after eb (below e1) outside the tile's giant rows
+// (beg: the tile's nv + 1 row offsets).  The same in every thread.
+__device__ __forceinline__ int skip_giant(const int* beg, int nv, int eb, int e1)
+{
+    while (eb < e1) {
+        int lo = 0, hi = nv - 1;   // the row holding eb: the last x with beg[x] <= eb
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (beg[mid] <= eb) lo = mid;
+            else hi = mid - 1;
+        }
+        if (beg[lo + 1] - beg[lo] <= kGiantRow) break;
+        eb = beg[lo + 1];
+    }
+    return eb;
+}
+
 // VM: how V is read (0 int64, 1 int128 in a.V / a.Vhi with int128 keys, 2
 // the int32 copy a.V32).  RATIO: cycle ratio, the key is
 // V[head] + L * w - W * t (a.t: edge times).
@@ -207,9 +224,12 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
     if (t == 0) beg[nv] = a.row_ptr[v0 + nv];
     __syncthreads();
     const int e0 = beg[0], e1 = beg[nv];
-    const int mb = t < nv ? beg[t] : 0, me = t < nv ? beg[t + 1] : 0;
+    // giant rows are left to k_giant_part / k_giant_merge
+    const bool giant = a.giant.ngiant > 0 && t < nv && beg[t + 1] - beg[t] > kGiantRow;
+    const bool skip = a.giant.ngiant > 0 && __syncthreads_or(giant);
+    const int mb = t < nv && !giant ? beg[t] : 0, me = t < nv && !giant ? beg[t + 1] : 0;
     constexpr int U = kTileEdges / kWG;
-    for (int eb = e0; eb < e1; eb += kTileEdges) {
+    for (int eb = skip ? skip_giant(beg, nv, e0, e1) : e0; eb < e1;) {
         const int cnt = e1 - eb < kTileEdges ? e1 - eb : kTileEdges;
         if (FIRST) {
 #pragma unroll
@@ -272,6 +292,8 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
             }
         }
         __syncthreads();
+        eb += cnt;
+        if (skip) eb = skip_giant(beg, nv, eb, e1);
     }
     unsigned long long changed = 0;
     unsigned cbroken = 0;
@@ -329,12 +351,15 @@ void k_tiescan_tile(SweepArgs a, const WT* __restrict__ w)
     if (t == 0) beg[nv] = a.row_ptr[v0 + nv];
     __syncthreads();
     const int e0 = beg[0], e1 = beg[nv];
-    const int mb = t < nv ? beg[t] : 0, me = t < nv ? beg[t + 1] : 0;
+    // giant rows are left to k_giant_part / k_giant_merge
+    const bool giant = a.giant.ngiant > 0 && t < nv && beg[t + 1] - beg[t] > kGiantRow;
+    const bool skip = a.giant.ngiant > 0 && __syncthreads_or(giant);
+    const int mb = t < nv && !giant ? beg[t] : 0, me = t < nv && !giant ? beg[t + 1] : 0;
     unsigned long long cnt = 0, certain = 0, nondec = 0;
     KT best = val_max<KT>();
     int pos = INT32_MAX, bhead = 0;
     constexpr int U = kTieTileEdges / kWG;
-    for (int eb = e0; eb < e1; eb += kTieTileEdges) {
+    for (int eb = skip ? skip_giant(beg, nv, e0, e1) : e0; eb < e1;) {
         const int n_e = e1 - eb < kTieTileEdges ? e1 - eb : kTieTileEdges;
         int c[U];
         long long wl[U], tl[U];
@@ -426,6 +451,8 @@ void k_tiescan_tile(SweepArgs a, const WT* __restrict__ w)
             }
         }
         __syncthreads();
+        eb += n_e;
+        if (skip) eb = skip_giant(beg, nv, eb, e1);
     }
     unsigned long long changed = 0;
     unsigned cbroken = 0;
@@ -444,6 +471,160 @@ void k_tiescan_tile(SweepArgs a, const WT* __restrict__ w)
         if (sums[2]) atomicAdd(&ln.nondec, sums[2]);
         if (SWEEP && sums[3]) atomicAdd(&ln.changed, sums[3]);
         if (SWEEP && sums[4]) atomicOr(&ln.cbroken, 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// giant rows: several workgroups per row
+// ---------------------------------------------------------------------------
+struct alignas(16) GiantPart {
+    __int128 key;   // the chunk's smallest key (any value mode, widened)
+    int pos;        // its lowest position (INT32_MAX: none)
+    int head;
+    int pad[2];
+};
+
+__global__ __launch_bounds__(kWG) void k_giant_list(int n, const int* __restrict__ row_ptr,
+                                                    int* __restrict__ triples, unsigned cap,
+                                                    Ctl* ctl)
+{
+    for (int64_t v = (int64_t)blockIdx.x * kWG + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kWG) {
+        const int b = row_ptr[v], e = row_ptr[v + 1];
+        if (e - b <= kGiantRow) continue;
+        const unsigned i = atomicAdd(&ctl->ngiant, 1u);
+        if (i < cap) {
+            triples[3 * i] = (int)v;
+            triples[3 * i + 1] = b;
+            triples[3 * i + 2] = e;
+        }
+    }
+}
+
+// One workgroup per chunk (grid-stride over the chunks).  MODE 0: the first
+// sweep (keys are the weights); 1: an improvement sweep (COUNT: it also
+// counts tight edges, as k_tiescan_tile<SWEEP> does); 2: the tie scan
+// (counts, and lists when a.xs is set; no best).  The chunk's best key at its
+// lowest position goes to parts[c] (modes 0 and 1).
+template <typename WT, int MODE, bool COUNT, int VM, bool RATIO>
+__global__ __launch_bounds__(kWG) void k_giant_part(SweepArgs a, const WT* __restrict__ w)
+{
+    using KT = typename ValT<VM>::type;
+    __shared__ KT sk[kWG / 64];
+    __shared__ int sp[kWG / 64], sh[kWG / 64];
+    const GiantTab& g = a.giant;
+    GiantPart* parts = (GiantPart*)g.parts;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    unsigned long long cnt = 0, certain = 0, nondec = 0;
+    for (int c = blockIdx.x; c < g.nchunks; c += gridDim.x) {
+        const int v = g.cv[c], c0 = g.cs[c], c1 = g.ce[c];
+        const KT own = MODE == 0 ? (KT)0 : load_val<VM>(a.V, a.Vhi, a.V32, v);
+        int cur = -1, hv = 0;
+        bool onc = false;
+        if (COUNT) {
+            cur = a.pi[v];
+            if (a.hop) hv = a.hop[v];
+            onc = a.onC && a.onC[v];
+        }
+        KT best = val_max<KT>();
+        int pos = INT32_MAX, bh = 0;
+        // lanes stride over the chunk: each keeps its lowest position among
+        // equal keys
+        for (int e = c0 + t; e < c1; e += kWG) {
+            const int h = a.col[e];
+            const long long wl = wval(w, e, a.neg);
+            KT k;
+            if (MODE == 0) k = (KT)wl;
+            else
+                k = load_val<VM>(a.V, a.Vhi, a.V32, h) +
+                    (KT)(a.L * wl - (RATIO ? a.W * (long long)a.t[e] : a.W));
+            if (MODE != 2 && k < best) {
+                best = k;
+                pos = e;
+                bh = h;
+            }
+            if (COUNT) {
+                const bool tight = k == own && e != cur;
+                if (tight) {
+                    ++cnt;
+                    if (h == v || onc) ++certain;
+                    if (a.hop && a.hop[h] >= hv) ++nondec;
+                }
+                if (MODE == 2 && a.xs) {   // one counter atomic per wave and step
+                    const unsigned slot = wave_append(tight, a.xcnt);
+                    if (tight && slot < a.xcap) {
+                        a.xs[slot] = v;
+                        a.ys[slot] = h;
+                    }
+                }
+            }
+        }
+        if (MODE != 2) {
+            wave_argmin<KT, true>(best, pos, bh);
+            if (lane == 0) {
+                sk[wave] = best;
+                sp[wave] = pos;
+                sh[wave] = bh;
+            }
+            __syncthreads();
+            if (t == 0) {
+                // the best wave by index (not a running record: see
+                // k_mc_giant_part)
+                int bi = 0;
+                for (int i = 1; i < kWG / 64; ++i)
+                    if (sk[i] < sk[bi] || (sk[i] == sk[bi] && sp[i] < sp[bi])) bi = i;
+                GiantPart p;
+                p.key = (__int128)sk[bi];
+                p.pos = sp[bi];
+                p.head = sh[bi];
+                p.pad[0] = p.pad[1] = 0;
+                parts[c] = p;
+            }
+            __syncthreads();   // sk is reused by the next chunk
+        }
+    }
+    if (COUNT) {
+        unsigned long long sums[3] = {cnt, certain, nondec};
+        block_sums_u64(sums);
+        if (t == 0) {
+            CtlLane& ln = my_lane(a.ctl);
+            if (sums[0]) atomicAdd(&ln.tight, sums[0]);
+            if (sums[1]) atomicAdd(&ln.certain, sums[1]);
+            if (sums[2]) atomicAdd(&ln.nondec, sums[2]);
+        }
+    }
+}
+
+// Each giant row's best over its chunks (in position order: a strict
+// compare keeps the lowest position), then the sweep's write rule.
+template <int VM, bool FIRST>
+__global__ __launch_bounds__(kWG) void k_giant_merge(SweepArgs a)
+{
+    using KT = typename ValT<VM>::type;
+    const GiantTab& g = a.giant;
+    const GiantPart* parts = (const GiantPart*)g.parts;
+    unsigned long long changed = 0, cbroken = 0;
+    for (int i = blockIdx.x * kWG + threadIdx.x; i < g.ngiant; i += gridDim.x * kWG) {
+        const int v = g.gv[i];
+        // the best chunk by index, position order (strict keeps the lowest)
+        int bi = -1;
+        for (int c = g.gc0[i]; c < g.gc1[i]; ++c)
+            if (parts[c].pos != INT32_MAX && (bi < 0 || (KT)parts[c].key < (KT)parts[bi].key))
+                bi = c;
+        if (bi < 0) continue;
+        const KT best = (KT)parts[bi].key;
+        if (!FIRST && !(best < load_val<VM>(a.V, a.Vhi, a.V32, v))) continue;
+        a.pi[v] = parts[bi].pos;
+        if (a.succ) a.succ[v] = parts[bi].head;
+        ++changed;
+        if (!FIRST && a.onC && a.onC[v]) cbroken = 1;
+    }
+    unsigned long long sums[2] = {changed, cbroken};
+    block_sums_u64(sums);
+    if (threadIdx.x == 0) {
+        CtlLane& ln = my_lane(a.ctl);
+        if (sums[0]) atomicAdd(&ln.changed, sums[0]);
+        if (sums[1]) atomicOr(&ln.cbroken, 1u);
     }
 }
 
@@ -2056,6 +2237,7 @@ __global__ __launch_bounds__(kWG) void k_tie_short_walk(SweepArgs a, const WT* _
         const int64_t v = vb + threadIdx.x / G;
         if (v >= v1) continue;
         const int beg = a.row_ptr[v], end = a.row_ptr[v + 1];
+        if (a.giant.ngiant > 0 && end - beg > kGiantRow) continue;   // k_giant_short_walk
         const KT own = load_val<VM>(a.V, a.Vhi, a.V32, v);
         const int cur = a.pi[v];
         for (int e = beg + lane; e < end; e += G) {
@@ -2068,6 +2250,34 @@ __global__ __launch_bounds__(kWG) void k_tie_short_walk(SweepArgs a, const WT* _
             int x = y;
             for (int st = 0; st < kShortWalk && x != (int)v; ++st) x = succ[x];
             found += x == (int)v;
+        }
+    }
+    found = block_sum_u64(found);
+    if (threadIdx.x == 0 && found) atomicAdd(&my_lane(a.ctl).certain, found);
+}
+
+// The same test on the giant rows, one workgroup per chunk.
+template <typename WT, int VM>
+__global__ __launch_bounds__(kWG) void k_giant_short_walk(SweepArgs a, const WT* __restrict__ w,
+                                                          const int* __restrict__ succ)
+{
+    using KT = typename ValT<VM>::type;
+    const GiantTab& g = a.giant;
+    unsigned long long found = 0;
+    for (int c = blockIdx.x; c < g.nchunks; c += gridDim.x) {
+        const int v = g.cv[c];
+        const KT own = load_val<VM>(a.V, a.Vhi, a.V32, v);
+        const int cur = a.pi[v], hv = a.hop[v];
+        for (int e = g.cs[c] + (int)threadIdx.x; e < g.ce[c]; e += kWG) {
+            if (e == cur) continue;
+            const int y = a.col[e];
+            if (a.hop[y] < hv) continue;
+            const long long te = a.t ? a.t[e] : 1;
+            if (load_val<VM>(a.V, a.Vhi, a.V32, y) + (KT)(a.L * wval(w, e, a.neg) - a.W * te) != own)
+                continue;
+            int x = y;
+            for (int st = 0; st < kShortWalk && x != v; ++st) x = succ[x];
+            found += x == v;
         }
     }
     found = block_sum_u64(found);
@@ -2258,6 +2468,7 @@ __global__ void k_ctl_clear(Ctl* ctl, unsigned what)
         if (what & kClrActive2) ln.active2 = 0;
     }
     if (t == 0) {
+        if (what & kClrGiant) ctl->ngiant = 0;
         if (what & kClrChanged) {
             ctl->xcnt = 0;
             ctl->scnt = 0;
@@ -2343,6 +2554,27 @@ void launch_validate(int n, int m, const int* row_ptr, const int* col, const voi
 
 // Sweeps after the first with int128 values, an int32 copy of V or edge
 // times: always over vertex tiles.
+// The giant rows' part of a tile sweep (after the tile kernel, on the same
+// stream): chunk bests, then one merge per row (not for the tie scan).
+template <typename WT, int VM, bool RATIO>
+static void launch_giant(const SweepArgs& a, const WT* ww, bool first, bool tie, bool fused,
+                         hipStream_t st)
+{
+    if (a.giant.ngiant <= 0) return;
+    const unsigned grid = a.giant.nchunks < 2048 ? (unsigned)a.giant.nchunks : 2048u;
+    const unsigned mgrid = blocks_for(a.giant.ngiant);
+    if (first) {
+        k_giant_part<WT, 0, false, 0, false><<<grid, kWG, 0, st>>>(a, ww);
+        k_giant_merge<0, true><<<mgrid, kWG, 0, st>>>(a);
+    } else if (tie) {
+        k_giant_part<WT, 2, true, VM, RATIO><<<grid, kWG, 0, st>>>(a, ww);
+    } else {
+        if (fused) k_giant_part<WT, 1, true, VM, RATIO><<<grid, kWG, 0, st>>>(a, ww);
+        else k_giant_part<WT, 1, false, VM, RATIO><<<grid, kWG, 0, st>>>(a, ww);
+        k_giant_merge<VM, false><<<mgrid, kWG, 0, st>>>(a);
+    }
+}
+
 template <typename WT, int VM, bool RATIO>
 static void launch_sweep_tiles(const SweepArgs& a, const WT* ww, bool tie, bool fused,
                                hipStream_t st)
@@ -2351,6 +2583,7 @@ static void launch_sweep_tiles(const SweepArgs& a, const WT* ww, bool tie, bool 
     if (tie) k_tiescan_tile<WT, false, VM, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
     else if (fused) k_tiescan_tile<WT, true, VM, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
     else k_sweep_tile<WT, false, VM, RATIO><<<tiles, kWG, 0, st>>>(a, ww);
+    launch_giant<WT, VM, RATIO>(a, ww, false, tie, fused, st);
 }
 
 template <typename WT, int VM>
@@ -2387,24 +2620,36 @@ void launch_sweep(const SweepArgs& a, const void* w, int wtype, int G, bool firs
             else if (fused) k_tiescan_tile<long long, true><<<tiles, kWG, 0, st>>>(a, ww);
             else if (first) k_sweep_tile<long long, true><<<tiles, kWG, 0, st>>>(a, ww);
             else k_sweep_tile<long long, false><<<tiles, kWG, 0, st>>>(a, ww);
+            launch_giant<long long, 0, false>(a, ww, first, tie, fused, st);
         } else {
             const int* ww = (const int*)w;
             if (tie) k_tiescan_tile<int, false><<<tiles, kWG, 0, st>>>(a, ww);
             else if (fused) k_tiescan_tile<int, true><<<tiles, kWG, 0, st>>>(a, ww);
             else if (first) k_sweep_tile<int, true><<<tiles, kWG, 0, st>>>(a, ww);
             else k_sweep_tile<int, false><<<tiles, kWG, 0, st>>>(a, ww);
+            launch_giant<int, 0, false>(a, ww, first, tie, fused, st);
         }
         return;
     }
     if (tie) {   // the tie scan always runs over vertex tiles
         const unsigned tiles = blocks_for(a.n);
-        if (wtype == kWI64)
+        if (wtype == kWI64) {
             k_tiescan_tile<long long, false><<<tiles, kWG, 0, st>>>(a, (const long long*)w);
-        else k_tiescan_tile<int, false><<<tiles, kWG, 0, st>>>(a, (const int*)w);
+            launch_giant<long long, 0, false>(a, (const long long*)w, false, true, false, st);
+        } else {
+            k_tiescan_tile<int, false><<<tiles, kWG, 0, st>>>(a, (const int*)w);
+            launch_giant<int, 0, false>(a, (const int*)w, false, true, false, st);
+        }
         return;
     }
     if (wtype == kWI64) launch_sweep_t<long long>(a, w, G, first, tie, grid, st);
     else launch_sweep_t<int>(a, w, G, first, tie, grid, st);
+}
+
+void launch_giant_list(int n, const int* row_ptr, int* triples, unsigned cap, Ctl* ctl,
+                       hipStream_t st)
+{
+    k_giant_list<<<stride_grid(n), kWG, 0, st>>>(n, row_ptr, triples, cap, ctl);
 }
 
 void launch_pj_init(int n, const int* col, const int* pi, int* succ, bool have_succ,
@@ -2745,6 +2990,11 @@ static void launch_short_walk_t(const SweepArgs& a, const void* w, int G, const 
                                 unsigned grid, hipStream_t st)
 {
     const WT* ww = (const WT*)w;
+    if (a.giant.ngiant > 0) {
+        const unsigned gg = a.giant.nchunks < 2048 ? (unsigned)a.giant.nchunks : 2048u;
+        if (a.Vhi) k_giant_short_walk<WT, 1><<<gg, kWG, 0, st>>>(a, ww, succ);
+        else k_giant_short_walk<WT, 0><<<gg, kWG, 0, st>>>(a, ww, succ);
+    }
     if (a.Vhi) {   // int128 values: one lane group size (a rare fallback)
         k_tie_short_walk<8, WT, 1><<<grid, kWG, 0, st>>>(a, ww, succ);
         return;
@@ -2921,6 +3171,7 @@ __global__ void k_post_ctl(const Ctl* __restrict__ c, CtlView* dst, unsigned* se
         v.xcnt = c->xcnt;
         v.scnt = c->scnt;
         v.clen = c->clen;
+        v.ngiant = c->ngiant;
         *dst = v;
         __threadfence_system();
         __hip_atomic_store(seq_slot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);

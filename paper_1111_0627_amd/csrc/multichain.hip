@@ -20,13 +20,14 @@ namespace {
 
 // Sign of (gw / gl, b / gl) - (hw / hl, c / hl) in lexicographic order; gl,
 // hl > 0.
+// Branch-free: both cross products are formed, then selected.
 __device__ __forceinline__ int mc_cmp(long long gw, long long gl, long long b, long long hw,
                                       long long hl, long long c)
 {
     const __int128 x = (__int128)gw * hl, y = (__int128)hw * gl;
-    if (x != y) return x < y ? -1 : 1;
     const __int128 p = (__int128)b * hl, q = (__int128)c * gl;
-    return p < q ? -1 : (p > q ? 1 : 0);
+    const int sg = (int)(x > y) - (int)(x < y), sb = (int)(p > q) - (int)(p < q);
+    return sg != 0 ? sg : sb;
 }
 
 template <typename WT>
@@ -172,7 +173,9 @@ __global__ __launch_bounds__(kWG) void k_mc_sweep(McArgs a, const WT* __restrict
             cur = a.pi[v];
             const bool opt = !TIE || (__int128)ow * a.L == (__int128)a.W * ol;
             const bool on_c = TIE && a.onC[v];
-            for (int e = opt ? e0 + lane : e1; e < e1; e += G) {
+            // giant rows are left to k_mc_giant_part / k_mc_giant_merge
+            const bool giant = a.giant.ngiant > 0 && e1 - e0 > kGiantRow;
+            for (int e = opt && !giant ? e0 + lane : e1; e < e1; e += G) {
                 const int u = a.col[e];
                 const Jmp ru = a.R[u];
                 const long long gw = a.wsum[ru.J], gl = (long long)a.lcnt[ru.J];
@@ -233,6 +236,133 @@ __global__ __launch_bounds__(kWG) void k_mc_sweep(McArgs a, const WT* __restrict
         if (sums[2]) atomicAdd(&ln.nondec, sums[2]);
         if (sums[3]) atomicAdd(&ln.changed, sums[3]);
     }
+}
+
+// Giant rows of the multichain sweep: one workgroup per chunk keeps the
+// chunk's smallest pair at its lowest position (and, for the tie scan, the
+// counts and the list), then one thread per row merges its chunks in
+// position order and applies the strict-improvement rule.
+struct alignas(16) McPart {
+    long long gw, gl, nb;   // the chunk's best pair: gain W / L and bias numerator
+    int pos, head;          // its lowest position (INT_MAX: none) and head
+};
+static_assert(sizeof(McPart) == 32, "one 32-byte slot per chunk");
+
+template <typename WT, bool TIE>
+__global__ __launch_bounds__(kWG) void k_mc_giant_part(McArgs a, const WT* __restrict__ w)
+{
+    __shared__ McPart sp[kWG / 64];
+    const GiantTab& g = a.giant;
+    McPart* parts = (McPart*)g.parts;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    unsigned long long cnt = 0, certain = 0, nondec = 0;
+    for (int c = blockIdx.x; c < g.nchunks; c += gridDim.x) {
+        const int v = g.cv[c];
+        const Jmp own = a.R[v];
+        const long long ow = a.wsum[own.J], ol = (long long)a.lcnt[own.J], od = own.D;
+        const int cur = a.pi[v];
+        const bool opt = !TIE || (__int128)ow * a.L == (__int128)a.W * ol;
+        const bool on_c = TIE && a.onC[v];
+        long long bw = 0, bl = 1, bb = 0;
+        int pos = INT_MAX, bh = 0;
+        for (int e = opt ? g.cs[c] + t : g.ce[c]; e < g.ce[c]; e += kWG) {
+            const int u = a.col[e];
+            const Jmp ru = a.R[u];
+            const long long gw = a.wsum[ru.J], gl = (long long)a.lcnt[ru.J];
+            const long long nb = ru.D + gl * wval(w, e, a.neg) - gw;
+            if (!TIE && (pos == INT_MAX || mc_cmp(gw, gl, nb, bw, bl, bb) < 0)) {
+                bw = gw;
+                bl = gl;
+                bb = nb;
+                pos = e;
+                bh = u;
+            }
+            const bool tight = e != cur && mc_cmp(gw, gl, nb, ow, ol, od) == 0;
+            if (tight) {
+                ++cnt;
+                if (TIE) {
+                    if (u == v || on_c) ++certain;
+                    if ((int)ru.H >= (int)own.H) ++nondec;
+                }
+            }
+            if (TIE && a.xs) {
+                const unsigned slot = wave_append(tight, a.xcnt);
+                if (tight && slot < a.xcap) {
+                    a.xs[slot] = v;
+                    a.ys[slot] = u;
+                }
+            }
+        }
+        if (TIE) continue;
+        for (int off = 32; off > 0; off >>= 1) {
+            const long long xw = __shfl_xor(bw, off, 64), xl = __shfl_xor(bl, off, 64);
+            const long long xb = __shfl_xor(bb, off, 64);
+            const int xp = __shfl_xor(pos, off, 64), xh = __shfl_xor(bh, off, 64);
+            if (xp == INT_MAX) continue;
+            const int k = pos == INT_MAX ? -1 : mc_cmp(xw, xl, xb, bw, bl, bb);
+            if (k < 0 || (k == 0 && xp < pos)) {
+                bw = xw;
+                bl = xl;
+                bb = xb;
+                pos = xp;
+                bh = xh;
+            }
+        }
+        if (lane == 0) sp[wave] = McPart{bw, bl, bb, pos, bh};
+        __syncthreads();
+        if (t == 0) {
+            // the best wave by index: a record assigned under this condition
+            // lost its head in the generated code (its position was taken)
+            int bi = 0;
+            for (int i = 1; i < kWG / 64; ++i) {
+                if (sp[i].pos == INT_MAX) continue;
+                const int k = sp[bi].pos == INT_MAX
+                                  ? -1
+                                  : mc_cmp(sp[i].gw, sp[i].gl, sp[i].nb, sp[bi].gw, sp[bi].gl,
+                                           sp[bi].nb);
+                if (k < 0 || (k == 0 && sp[i].pos < sp[bi].pos)) bi = i;
+            }
+            parts[c] = sp[bi];
+        }
+        __syncthreads();   // sp is reused by the next chunk
+    }
+    unsigned long long sums[3] = {cnt, certain, nondec};
+    block_sums_u64(sums);
+    if (t == 0) {
+        CtlLane& ln = my_lane(a.ctl);
+        if (sums[0]) atomicAdd(&ln.tight, sums[0]);
+        if (sums[1]) atomicAdd(&ln.certain, sums[1]);
+        if (sums[2]) atomicAdd(&ln.nondec, sums[2]);
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_mc_giant_merge(McArgs a)
+{
+    const GiantTab& g = a.giant;
+    const McPart* parts = (const McPart*)g.parts;
+    unsigned long long changed = 0;
+    for (int i = blockIdx.x * kWG + threadIdx.x; i < g.ngiant; i += gridDim.x * kWG) {
+        const int v = g.gv[i];
+        // the best chunk by index (position order: strict keeps the lowest);
+        // see k_mc_giant_part for why not a running record
+        int bi = -1;
+        for (int c = g.gc0[i]; c < g.gc1[i]; ++c) {
+            if (parts[c].pos == INT_MAX) continue;
+            if (bi < 0 || mc_cmp(parts[c].gw, parts[c].gl, parts[c].nb, parts[bi].gw, parts[bi].gl,
+                                 parts[bi].nb) < 0)
+                bi = c;
+        }
+        if (bi < 0) continue;
+        const McPart b = parts[bi];
+        const Jmp own = a.R[v];
+        if (mc_cmp(b.gw, b.gl, b.nb, a.wsum[own.J], (long long)a.lcnt[own.J], own.D) < 0) {
+            a.pi[v] = b.pos;
+            a.succ[v] = b.head;
+            ++changed;
+        }
+    }
+    changed = block_sum_u64(changed);
+    if (threadIdx.x == 0 && changed) atomicAdd(&my_lane(a.ctl).changed, changed);
 }
 
 __global__ __launch_bounds__(kWG) void k_mc_ncrit(const int* __restrict__ cyc_list,
@@ -312,10 +442,28 @@ void launch_mc_final_dev(int n, Jmp* Q0, Jmp* Q1, long long* V, int* hop, Ctl* c
     k_mc_final_dev<<<blocks_for(n), kWG, 0, st>>>(n, Q0, Q1, V, hop, ctl);
 }
 
+template <typename WT>
+void mc_giant(const McArgs& a, const WT* w, bool tie, hipStream_t st)
+{
+    if (a.giant.ngiant <= 0) return;
+    const unsigned grid = a.giant.nchunks < 2048 ? (unsigned)a.giant.nchunks : 2048u;
+    if (tie) {
+        k_mc_giant_part<WT, true><<<grid, kWG, 0, st>>>(a, w);
+    } else {
+        k_mc_giant_part<WT, false><<<grid, kWG, 0, st>>>(a, w);
+        k_mc_giant_merge<<<blocks_for(a.giant.ngiant), kWG, 0, st>>>(a);
+    }
+}
+
 void launch_mc_sweep(const McArgs& a, const void* w, int wtype, int G, bool tie, hipStream_t st)
 {
-    if (wtype == kWI64) mc_sweep_t(a, (const long long*)w, G, tie, st);
-    else mc_sweep_t(a, (const int*)w, G, tie, st);
+    if (wtype == kWI64) {
+        mc_sweep_t(a, (const long long*)w, G, tie, st);
+        mc_giant(a, (const long long*)w, tie, st);
+    } else {
+        mc_sweep_t(a, (const int*)w, G, tie, st);
+        mc_giant(a, (const int*)w, tie, st);
+    }
 }
 
 void launch_mc_ncrit(const int* cyc_list, const long long* wsum, const unsigned* lcnt, long long W,

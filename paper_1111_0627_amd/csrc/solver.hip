@@ -3,6 +3,7 @@
 // C ABI declared in include/ocm.h.
 #include "ocm.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -88,6 +89,17 @@ struct Ws {
     unsigned* lcnt;      // per-cycle lengths, keyed by rep
     long long* tsum;     // cycle ratio: per-cycle times, keyed by rep
     int* cyc;            // cycle heads
+    // giant rows (more than kGiantRow edges): the listed triples, the chunk
+    // table, the rows' chunk ranges and the chunks' partial results
+    unsigned gcap, ccap;
+    int* gtri;
+    int* cv;
+    int* cs;
+    int* ce;
+    int* gv;
+    int* gc0;
+    int* gc1;
+    void* gparts;
     size_t total;
 };
 
@@ -138,6 +150,16 @@ Ws carve(void* base, int64_t n, int64_t m)
     w.lcnt = (unsigned*)take(4 * N);
     w.tsum = (long long*)take(8 * N);
     w.cyc = (int*)take(4 * N);
+    w.gcap = (unsigned)(M / ocm::kGiantRow + 1);
+    w.ccap = (unsigned)(M / ocm::kGiantChunk + w.gcap + 1);
+    w.gtri = (int*)take(12 * (size_t)w.gcap);
+    w.cv = (int*)take(4 * (size_t)w.ccap);
+    w.cs = (int*)take(4 * (size_t)w.ccap);
+    w.ce = (int*)take(4 * (size_t)w.ccap);
+    w.gv = (int*)take(4 * (size_t)w.gcap);
+    w.gc0 = (int*)take(4 * (size_t)w.gcap);
+    w.gc1 = (int*)take(4 * (size_t)w.gcap);
+    w.gparts = take(32 * (size_t)w.ccap);
     w.total = off;
     return w;
 }
@@ -234,6 +256,9 @@ struct Ctx {
     // ws.V32 holds V as int32 (every value of the last value phase fit):
     // sweeps then gather 4-byte values
     bool v32 = false;
+    // rows of more than kGiantRow edges, swept by several workgroups each
+    // (tile sweeps only; empty when there are none)
+    ocm::GiantTab giant;
 
     Ctx() = default;
     Ctx(const Ctx&) = delete;
@@ -394,6 +419,7 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     a.succ = nullptr;
     a.onC = onC;
     a.ctl = c.ws.ctl;
+    a.giant = c.tile_sweep ? c.giant : ocm::GiantTab{};
     a.hop = tie && with_hop ? c.ws.hop : nullptr;
     a.xs = a.ys = nullptr;
     a.xcnt = nullptr;
@@ -420,6 +446,61 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     if (!read) return OCM_OK;
     OCM_TRY(read_ctl(c));
     sweep_done(c, first, tie, fused);
+    return OCM_OK;
+}
+
+// Giant rows: listed on the device; their chunk table is built on the host
+// (rows by vertex, each row's chunks in position order, so that the merge
+// keeps the lowest position among equal keys) and copied to the workspace.
+// Only the tile sweeps use it.
+ocm_status build_giant(Ctx& c)
+{
+    Ws& w = c.ws;
+    c.giant = ocm::GiantTab{};
+    if (!c.tile_sweep || c.m <= ocm::kGiantRow) return OCM_OK;
+    ocm::launch_ctl_clear(w.ctl, ocm::kClrGiant, c.st);
+    ocm::launch_giant_list(c.n, c.row_ptr, w.gtri, w.gcap, w.ctl, c.st);
+    HIP_TRY(hipGetLastError());
+    OCM_TRY(read_ctl(c));
+    const unsigned ng = c.h.ngiant;
+    if (ng == 0) return OCM_OK;
+    if (ng > w.gcap) return fail(OCM_E_HIP, "more giant rows than the edges allow");
+    std::vector<int> tri(3 * (size_t)ng);
+    HIP_TRY(hipMemcpyAsync(tri.data(), w.gtri, 12 * (size_t)ng, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    std::vector<int> order(ng);
+    for (unsigned i = 0; i < ng; ++i) order[i] = (int)i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return tri[3 * x] < tri[3 * y]; });
+    std::vector<int> cv, cs, ce, gv(ng), gc0(ng), gc1(ng);
+    for (unsigned k = 0; k < ng; ++k) {
+        const int i = order[k], v = tri[3 * i], b = tri[3 * i + 1], e = tri[3 * i + 2];
+        gv[k] = v;
+        gc0[k] = (int)cv.size();
+        for (int x = b; x < e; x += ocm::kGiantChunk) {
+            cv.push_back(v);
+            cs.push_back(x);
+            ce.push_back(e - x > ocm::kGiantChunk ? x + ocm::kGiantChunk : e);
+        }
+        gc1[k] = (int)cv.size();
+    }
+    const size_t nc = cv.size();
+    if (nc > w.ccap) return fail(OCM_E_HIP, "more giant-row chunks than the workspace holds");
+    HIP_TRY(hipMemcpyAsync(w.cv, cv.data(), 4 * nc, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(w.cs, cs.data(), 4 * nc, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(w.ce, ce.data(), 4 * nc, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(w.gv, gv.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(w.gc0, gc0.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(w.gc1, gc1.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));   // the host vectors end here
+    c.giant.cv = w.cv;
+    c.giant.cs = w.cs;
+    c.giant.ce = w.ce;
+    c.giant.nchunks = (int)nc;
+    c.giant.gv = w.gv;
+    c.giant.gc0 = w.gc0;
+    c.giant.gc1 = w.gc1;
+    c.giant.ngiant = (int)ng;
+    c.giant.parts = w.gparts;
     return OCM_OK;
 }
 
@@ -954,6 +1035,7 @@ ocm_status tie_check(Ctx& c, long long W, long long L, ocm_result* out)
         a.xs = a.ys = nullptr;
         a.xcnt = nullptr;
         a.xcap = 0;
+        a.giant = c.tile_sweep ? c.giant : ocm::GiantTab{};
         c.prof.begin(OCM_K_TIESCAN);
         ocm::launch_tie_short_walk(a, c.w, c.wtype, c.G, w.succ, c.sweep_grid, c.st);
         c.prof.end();
@@ -1108,6 +1190,7 @@ ocm_status mc_sweep(Ctx& c, const McRun& run, bool tie, long long W, long long L
     a.ys = list ? w.ys : nullptr;
     a.xcnt = &w.ctl->xcnt;
     a.xcap = w.xcap;
+    a.giant = c.giant;
     const int cls = tie ? OCM_K_TIESCAN : OCM_K_SWEEP;
     c.prof.begin(cls);
     ocm::launch_mc_sweep(a, c.w, c.wtype, c.G, tie, c.st);
@@ -1246,6 +1329,7 @@ ocm_status solve(const ocm_graph* g, const ocm_options* o_in, void* wsp, size_t 
         return fail(OCM_E_INVALID_ARG,
                     "multichain runs without init_policy, edge times or int128 values");
     ocm_status rc = validate(c, o.validate != 0);
+    if (rc == OCM_OK) rc = build_giant(c);
     if (rc != OCM_OK) { c.prof.finish(); return rc; }
     if (o.multichain) return solve_mc(c, o, cycle_edges, cap, out);
     start_reverse_early(c);

@@ -130,3 +130,11 @@ def test_noalloc_entry_point():
     assert (a.p, a.q, a.iterations, a.tight_edges, a.tie) == \
         (b.p, b.q, b.iterations, b.tight_edges, b.tie)
     assert a.cycle_edges.cpu().tolist() == b.cycle_edges.cpu().tolist()
+
+
+def test_giant_rows():
+    """The first sweep takes giant rows (more than 8192 edges) through the
+    multi-workgroup path; the later sweeps use lanes per vertex."""
+    g = synth.hub_graph(5000, 3, 20000, 1, 4, -10, 10, np.int64, seed=[19, 0])
+    check(g.row_ptr, g.col, g.w)
+    check(g.row_ptr, g.col, g.w, "max")

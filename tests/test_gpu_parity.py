@@ -332,12 +332,14 @@ def test_schedules_and_fast_path_give_identical_bytes():
 
 
 @pytest.mark.parametrize("hubs,hub_deg,wlo,whi,seed", [
-    (3, 50000, 0, 3, 1), (40, 2000, -20, 20, 2), (1, 300000, 1, 1000, 3), (200, 70, 0, 1, 4)])
+    (3, 50000, 0, 3, 1), (40, 2000, -20, 20, 2), (1, 300000, 1, 1000, 3), (200, 70, 0, 1, 4),
+    (12, 8193, 0, 2, 5), (5, 16384, -3, 3, 6)])
 def test_hub_rows_walked_by_their_wave(hubs, hub_deg, wlo, whi, seed):
     """Rows far longer than the rest (hubs) are walked by the whole wave in
-    the tile sweeps and tie scans; every schedule, value mode and tie path
-    must still match the oracle byte for byte (small weight ranges make many
-    tight edges on the hub rows)."""
+    the tile sweeps and tie scans, and rows of more than 8192 edges by
+    several workgroups (chunks of 8192, then a merge); every schedule, value
+    mode and tie path must still match the oracle byte for byte (small
+    weight ranges make many tight edges on the hub rows)."""
     g = synth.hub_graph(20000, hubs, hub_deg, 1, 4, wlo, whi, np.int64, seed=[21, seed])
     for mode in ("min", "max"):
         sol = native.solve(g.row_ptr, g.col, g.w, mode=mode)

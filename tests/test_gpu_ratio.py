@@ -120,3 +120,15 @@ def test_ratio_rejects_bad_times():
     with pytest.raises(ocm.OCMError) as ei:
         solve(g.row_ptr, g.col, w, t)
     assert ei.value.status == ocm.OCM_E_OVERFLOW
+
+
+@pytest.mark.parametrize("hubs,hub_deg,seed", [(2, 40000, 1), (1, 100000, 2), (30, 9000, 3)])
+def test_ratio_with_giant_rows(hubs, hub_deg, seed):
+    """Rows longer than 8192 edges are swept by several workgroups (chunk
+    bests, then a merge in position order); with edge times the keys carry
+    W * t, and the result must still equal the ratio oracle's."""
+    g = synth.hub_graph(6000, hubs, hub_deg, 1, 4, -20, 20, np.int64, seed=[61, seed])
+    t = np.random.default_rng(seed).integers(1, 6, g.m).astype(np.int64)
+    for mode in ("min", "max"):
+        sol = native.solve(g.row_ptr, g.col, g.w, mode=mode, t=t)
+        same(solve(g.row_ptr, g.col, g.w, t, mode=mode), sol)
