@@ -380,7 +380,6 @@ ocm_status solve_general(const ocm_graph* g, const ocm_options* o_in, void* wsp,
     if (o.init_policy || o.policy_out || o.potential_out || o.profile)
         return gfail(OCM_E_INVALID_ARG, "general graphs take no policy, potential or profile");
     const int n = (int)g->n, m = (int)g->m;
-    const int sw = g->wtype == OCM_W_I64 ? 8 : 4;
     hipStream_t st = (hipStream_t)stream;
     GWs w = gcarve(nullptr, n, m);
     if (!wsp || ws_bytes < w.total) return gfail(OCM_E_WORKSPACE, "workspace missing or too small");
