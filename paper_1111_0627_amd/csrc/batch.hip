@@ -76,7 +76,34 @@ struct BCtl {
     unsigned scnt;             // tie test: special vertices
     unsigned rounds_open;      // device-driven rebuild rounds of the iteration left unfinished
     unsigned wide32;           // some value left int32: sweeps gather V, not its int32 copy
+    unsigned hop_act[34];      // hop phase: entries short of s after round r - 1 (r = 0: 1)
 };
+
+// Value-round entry of the loop: the sum D of (L * w - W) over the policy
+// path from v to J, as two 32-bit words so that an entry takes 12 bytes
+// (hop counts are not carried: they are needed only after the loop, which
+// computes them once).  A sum that leaves int64 becomes kDOverflow, which
+// every later sum keeps.
+struct VJ {
+    unsigned lo, hi;
+    int J;
+};
+
+constexpr long long kDOverflow = (long long)(1ull << 63);
+
+__device__ __forceinline__ long long vj_d(const VJ& q)
+{
+    return (long long)(((unsigned long long)q.hi << 32) | q.lo);
+}
+
+__device__ __forceinline__ VJ vj_make(long long d, int j)
+{
+    VJ q;
+    q.lo = (unsigned)(unsigned long long)d;
+    q.hi = (unsigned)((unsigned long long)d >> 32);
+    q.J = j;
+    return q;
+}
 
 __device__ __forceinline__ bool chunk_range(const int2* __restrict__ chunks, const unsigned* nch,
                                             const long long* __restrict__ vptr, int T, int& g,
@@ -128,6 +155,56 @@ __device__ __forceinline__ void for_each_chunk(const int2* __restrict__ chunks, 
 // ---------------------------------------------------------------------------
 // halt (nullable): while *halt is non-zero every count is 0 (the list is
 // empty and the kernels that take it do nothing).
+// Chunk count of graph g for the selection `want`: a mode, -1 = every graph
+// not done, -2 = every graph.
+__device__ __forceinline__ unsigned chunk_count(int g, const int* __restrict__ mode, int want,
+                                                const long long* __restrict__ vptr, int T)
+{
+    const bool sel = want == -2 ? true : want == -1 ? mode[g] != kDone : mode[g] == want;
+    const long long n = vptr[g + 1] - vptr[g];
+    return sel ? (unsigned)((n + T - 1) / T) : 0u;
+}
+
+// The whole list in one workgroup when the batch is small enough
+// (G <= kChunkListOne): each thread takes a run of consecutive graphs, a
+// workgroup scan of the runs' chunk counts gives every run its offset, and
+// the runs are written in order: the same list as k_chunk_count, a scan and
+// k_chunk_fill, in one launch instead of five.
+constexpr int kChunkListWG = 1024;
+constexpr int kChunkListOne = 16 * kChunkListWG;
+
+__global__ __launch_bounds__(kChunkListWG) void k_chunk_list(int G, const int* __restrict__ mode,
+                                                             int want,
+                                                             const long long* __restrict__ vptr,
+                                                             int T, int2* __restrict__ chunks,
+                                                             unsigned* nch, const unsigned* halt)
+{
+    __shared__ unsigned wsum[kChunkListWG / 64];
+    const int per = (G + kChunkListWG - 1) / kChunkListWG;
+    const int g0 = (int)threadIdx.x * per;
+    const int g1 = g0 + per < G ? g0 + per : G;
+    const bool off = halt && *halt != 0u;
+    unsigned mine = 0;
+    if (!off)
+        for (int g = g0; g < g1; ++g) mine += chunk_count(g, mode, want, vptr, T);
+    const unsigned incl = wave_incl_scan(mine);
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    unsigned o = incl - mine, total = 0;
+    for (int i = 0; i < kChunkListWG / 64; ++i) {
+        if (i < (int)(threadIdx.x >> 6)) o += wsum[i];
+        total += wsum[i];
+    }
+    if (!off)
+        for (int g = g0; g < g1; ++g) {
+            const unsigned c = chunk_count(g, mode, want, vptr, T);
+            const long long v0 = vptr[g];
+            for (unsigned i = 0; i < c; ++i) chunks[o + i] = make_int2(g, (int)(v0 + (long long)i * T));
+            o += c;
+        }
+    if (threadIdx.x == 0) *nch = total;
+}
+
 __global__ __launch_bounds__(kWG) void k_chunk_count(int G, const int* __restrict__ mode, int want,
                                                      const long long* __restrict__ vptr, int T,
                                                      unsigned* __restrict__ cnt,
@@ -139,10 +216,7 @@ __global__ __launch_bounds__(kWG) void k_chunk_count(int G, const int* __restric
             cnt[g] = 0;
             continue;
         }
-        // want: a mode, -1 = every graph not done, -2 = every graph
-        const bool sel = want == -2 ? true : want == -1 ? mode[g] != kDone : mode[g] == want;
-        const long long n = vptr[g + 1] - vptr[g];
-        cnt[g] = sel ? (unsigned)((n + T - 1) / T) : 0u;
+        cnt[g] = chunk_count(g, mode, want, vptr, T);
     }
 }
 
@@ -187,6 +261,13 @@ __global__ __launch_bounds__(kWG) void k_check_union(int G, const long long* __r
 
 // ---------------------------------------------------------------------------
 // sweep over the chunks of active graphs (SPFPassIter per region)
+//
+// A vertex whose edge changes also gets the edge's head in succ and its raw
+// weight in wsel.  Outside a rebuild (which rewrites pi alone) both then hold
+// col[pi] and w[pi] for every vertex: the value init after a rebuild writes
+// them for the whole graph, the sweeps keep them, so the fast path's value
+// init and the cycle init read them instead of one col and one w line per
+// few rows.
 // ---------------------------------------------------------------------------
 template <int G, typename WT, bool TIE>
 __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
@@ -199,7 +280,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
                                                const unsigned char* __restrict__ onC,
                                                const int* __restrict__ hop,
                                                int* __restrict__ xs, int* __restrict__ ys,
-                                               unsigned* xcnt, unsigned xcap)
+                                               unsigned* xcnt, unsigned xcap,
+                                               int* __restrict__ succ, WT* __restrict__ wsel)
 {
     constexpr int VPB = kWG / G;
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
@@ -255,6 +337,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
             }
             if (live && lane == 0 && (first || best < own)) {
                 pi[v] = bpos;
+                succ[v] = col[bpos];
+                wsel[v] = w[bpos];
                 cnt++;
                 if (!first && onC[v]) brk = 1;
             }
@@ -295,7 +379,9 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
                                                     const long long* __restrict__ V,
                                                     int* __restrict__ pi,
                                                     const unsigned char* __restrict__ onC,
-                                                    const int* __restrict__ V32, const BCtl* bc)
+                                                    const int* __restrict__ V32, const BCtl* bc,
+                                                    int* __restrict__ succ,
+                                                    WT* __restrict__ wsel)
 {
     __shared__ int beg[kWG + 1];
     __shared__ long long key[kBTileEdges];
@@ -325,23 +411,25 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
             for (int eb = e0; eb < e1; eb += kBTileEdges) {
                 const int ne = e1 - eb < kBTileEdges ? e1 - eb : kBTileEdges;
                 int c[U];
-                long long wl[U];
+                WT wr[U];   // raw weights: half the registers of int64 ones for int32 w
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int j = t + u * kWG;
                     c[u] = 0;
-                    wl[u] = 0;
+                    wr[u] = 0;
                     if (j < ne) {
                         c[u] = col[eb + j];
-                        wl[u] = wval(w, eb + j, neg);
+                        wr[u] = w[eb + j];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int j = t + u * kWG;
-                    if (j < ne)
-                        key[j] = first ? wl[u]
-                                       : (use32 ? (long long)V32[c[u]] : V[c[u]]) + L * wl[u] - W;
+                    if (j < ne) {
+                        const long long wl = wval(&wr[u], 0, neg);
+                        key[j] = first ? wl
+                                       : (use32 ? (long long)V32[c[u]] : V[c[u]]) + L * wl - W;
+                    }
                 }
                 __syncthreads();
                 const int lo = mb > eb ? mb : eb, hi = me < eb + ne ? me : eb + ne;
@@ -377,6 +465,8 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
             }
             if (t < nv && pos != INT32_MAX && (first || best < own)) {
                 pi[v0 + t] = pos;
+                succ[v0 + t] = col[pos];
+                wsel[v0 + t] = w[pos];
                 cnt++;
                 if (!first && onC[v0 + t]) brk = 1;
             }
@@ -432,54 +522,67 @@ __global__ __launch_bounds__(kWG) void k_after_sweep(int G, GArrays ga, int max_
 // ---------------------------------------------------------------------------
 // values: pointer jumping toward each graph's source
 // ---------------------------------------------------------------------------
-template <typename WT>
+// Value init.  SEL (fast path): each vertex's successor and edge weight come
+// from succ and wsel; otherwise (after a rebuild) from pi, col and w, and
+// succ and wsel are written.  It also books the first round: a graph none of
+// whose vertices has an entry short of s is finished (vact stays clear).
+template <typename WT, bool SEL>
 __global__ __launch_bounds__(kWG) void k_val_init(const int2* __restrict__ chunks,
                                                   const unsigned* nch, int T, GArrays ga,
                                                   const int* __restrict__ col,
                                                   const int* __restrict__ pi,
                                                   const WT* __restrict__ w, int neg,
-                                                  int* __restrict__ succ, Jmp* __restrict__ Q)
+                                                  int* __restrict__ succ, WT* __restrict__ wsel,
+                                                  VJ* __restrict__ Q)
 {
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
         const int s = ga.s[g];
         const long long W = ga.W[g], L = ga.L[g];
+        unsigned act = 0;
         for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-            const int e = pi[v];
-            const int t = col[e];
-            succ[v] = t;
-            Jmp q;
-            if (v == s) {
-                q.D = 0;
-                q.J = s;
-                q.H = 0;
+            int t;
+            long long we;
+            if (SEL) {
+                t = succ[v];
+                we = wval(wsel, v, neg);
             } else {
-                q.D = L * wval(w, e, neg) - W;
-                q.J = t;
-                q.H = 1;
+                const int e = pi[v];
+                const WT x = w[e];
+                t = col[e];
+                succ[v] = t;
+                wsel[v] = x;
+                we = wval(&x, 0, neg);
             }
-            Q[v] = q;
+            const int j = v == s ? s : t;
+            act |= j != s ? 1u : 0u;
+            Q[v] = vj_make(v == s ? 0 : L * we - W, j);
         }
+        const unsigned long long a = block_sum_u64(act);
         if (threadIdx.x == 0) {
             ga.vrun[g] = 1;
             ga.ovf[g] = 0;
+            if (a) atomicOr(&ga.vact[g], 1u);
+            atomicOr(&ga.vprog[g], 1u);
         }
     });
 }
 
+constexpr int kValRoundU = 8;
+
 __global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chunks,
                                                    const unsigned* nch, int T, GArrays ga,
-                                                   const Jmp* __restrict__ Qin,
-                                                   Jmp* __restrict__ Qout, const unsigned* running)
+                                                   const VJ* __restrict__ Qin,
+                                                   VJ* __restrict__ Qout, const unsigned* running)
 {
     if (*running == 0) return;   // every graph of the phase has finished: nothing to do
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
         if (!ga.vrun[g]) return;   // finished or stalled graph: its entries stay put
         const int s = ga.s[g];
         unsigned act = 0, prog = 0;
-        // four entries in flight per thread: loads, then the dependent gathers
-        constexpr int U = 4;
+        // kValRoundU entries in flight per thread: loads, then the dependent gathers
+        constexpr int U = kValRoundU;
         for (int64_t vb = v0 + threadIdx.x; vb < v1; vb += U * kWG) {
-            Jmp q[U], r[U];
+            VJ q[U], r[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t v = vb + u * kWG;
@@ -494,15 +597,11 @@ __global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chun
                 const int64_t v = vb + u * kWG;
                 if (v >= v1) continue;
                 if (q[u].J != s) {
+                    const long long a = vj_d(q[u]), b = vj_d(r[u]);
                     long long d;
-                    if (__builtin_add_overflow(q[u].D, r[u].D, &d)) {
-                        d = 0;
-                        q[u].H |= kHopOverflow;
-                    }
-                    q[u].D = d;
-                    q[u].J = r[u].J;
-                    q[u].H = ((q[u].H & ~kHopOverflow) + (r[u].H & ~kHopOverflow)) |
-                             ((q[u].H | r[u].H) & kHopOverflow);
+                    if (a == kDOverflow || b == kDOverflow || __builtin_add_overflow(a, b, &d))
+                        d = kDOverflow;
+                    q[u] = vj_make(d, r[u].J);
                     if (q[u].J == s) prog = 1;
                     else act = 1;
                 }
@@ -548,28 +647,11 @@ __global__ __launch_bounds__(kWG) void k_val_update(int G, GArrays ga, int want,
     if (threadIdx.x == 0 && r) atomicAdd(&bc->vrun_round[rounds], (unsigned)r);
 }
 
-// First-round bookkeeping: a graph may already be finished after init.
-__global__ __launch_bounds__(kWG) void k_val_mark(const int2* __restrict__ chunks,
-                                                  const unsigned* nch, int T, GArrays ga,
-                                                  const Jmp* __restrict__ Q)
-{
-    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
-        const int s = ga.s[g];
-        unsigned act = 0;
-        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) act |= Q[v].J != s;
-        const unsigned long long a = block_sum_u64(act);
-        if (threadIdx.x == 0) {
-            if (a) atomicOr(&ga.vact[g], 1u);
-            atomicOr(&ga.vprog[g], 1u);
-        }
-    });
-}
-
 __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chunks,
                                                    const unsigned* nch, int T, GArrays ga,
-                                                   int want, const Jmp* __restrict__ Q0,
-                                                   const Jmp* __restrict__ Q1,
-                                                   long long* __restrict__ V, int* __restrict__ hop,
+                                                   int want, const VJ* __restrict__ Q0,
+                                                   const VJ* __restrict__ Q1,
+                                                   long long* __restrict__ V,
                                                    int* __restrict__ V32, BCtl* bc)
 {
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
@@ -583,15 +665,14 @@ __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chun
             }
             return;
         }
-        const Jmp* __restrict__ Q = ga.fin[g] ? Q1 : Q0;
+        const VJ* __restrict__ Q = ga.fin[g] ? Q1 : Q0;
         unsigned bad = 0, big = 0;
         for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-            const Jmp q = Q[v];
-            V[v] = q.D;
-            V32[v] = (int)q.D;
-            hop[v] = (int)(q.H & ~kHopOverflow);
-            if ((q.H & kHopOverflow) || q.D > kValLimit || q.D < -kValLimit) bad = 1;
-            big |= q.D > INT32_MAX || q.D < INT32_MIN ? 1u : 0u;
+            const long long d = vj_d(Q[v]);   // kDOverflow lies below -kValLimit
+            V[v] = d;
+            V32[v] = (int)d;
+            if (d > kValLimit || d < -kValLimit) bad = 1;
+            big |= d > INT32_MAX || d < INT32_MIN ? 1u : 0u;
         }
         const unsigned long long b = block_sum_u64(bad);
         const unsigned long long bg = block_sum_u64(big);
@@ -603,6 +684,83 @@ __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chun
             // sticky: from now on the sweeps gather the int64 values
             if (bg) atomicOr(&bc->wide32, 1u);
         }
+    });
+}
+
+// Hops to the source after the loop (the policy edges from v to s, which
+// the tie tests and the cycle listing use), by pointer jumping on entries
+// (J in the high word, H in the low word).  Graphs that failed are skipped.
+__global__ __launch_bounds__(kWG) void k_hop_init(const int2* __restrict__ chunks,
+                                                  const unsigned* nch, int T, GArrays ga,
+                                                  const int* __restrict__ succ,
+                                                  unsigned long long* __restrict__ P)
+{
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        if (ga.status[g] != OCM_OK) return;
+        const int s = ga.s[g];
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG)
+            P[v] = v == s ? (unsigned long long)(unsigned)s << 32
+                          : ((unsigned long long)(unsigned)succ[v] << 32) | 1u;
+    });
+}
+
+// running: some entry of the last round had not reached s (round 0: set
+// by the host); act: this round's.
+__global__ __launch_bounds__(kWG) void k_hop_round(const int2* __restrict__ chunks,
+                                                   const unsigned* nch, int T, GArrays ga,
+                                                   const unsigned long long* __restrict__ Pin,
+                                                   unsigned long long* __restrict__ Pout,
+                                                   const unsigned* running, unsigned* act_out)
+{
+    if (*running == 0) return;
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        if (ga.status[g] != OCM_OK) return;
+        const unsigned s = (unsigned)ga.s[g];
+        unsigned act = 0;
+        constexpr int U = 8;
+        for (int64_t vb = v0 + threadIdx.x; vb < v1; vb += U * kWG) {
+            unsigned long long p[U], q[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t v = vb + u * kWG;
+                p[u] = v < v1 ? Pin[v] : (unsigned long long)s << 32;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if ((unsigned)(p[u] >> 32) != s) q[u] = Pin[(unsigned)(p[u] >> 32)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t v = vb + u * kWG;
+                if (v >= v1) continue;
+                if ((unsigned)(p[u] >> 32) != s) {
+                    p[u] = (q[u] & 0xffffffff00000000ull) |
+                           (unsigned)((unsigned)p[u] + (unsigned)q[u]);
+                    act |= (unsigned)(p[u] >> 32) != s ? 1u : 0u;
+                }
+                Pout[v] = p[u];
+            }
+        }
+        const unsigned long long a = block_sum_u64(act);
+        if (threadIdx.x == 0 && a) atomicOr(act_out, 1u);
+    });
+}
+
+// Round r reads P0 when r is even and writes the other buffer; a round
+// whose running flag is clear writes nothing, so the entries are in the
+// output of the last round that ran (P0 if none did).
+__global__ __launch_bounds__(kWG) void k_hop_final(const int2* __restrict__ chunks,
+                                                   const unsigned* nch, int T, GArrays ga,
+                                                   const unsigned long long* __restrict__ P0,
+                                                   const unsigned long long* __restrict__ P1,
+                                                   const unsigned* hop_act, int R,
+                                                   int* __restrict__ hop)
+{
+    int ran = 0;
+    while (ran < R && hop_act[ran] != 0u) ++ran;
+    const unsigned long long* __restrict__ P = ran == 0 ? P0 : ((ran - 1) & 1 ? P0 : P1);
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        if (ga.status[g] != OCM_OK) return;
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) hop[v] = (int)(unsigned)P[v];
     });
 }
 
@@ -628,16 +786,16 @@ __global__ __launch_bounds__(kWG) void k_values_done(int G, GArrays ga, int want
 // ---------------------------------------------------------------------------
 // cycles of the policy graph (pointer jumping), per-cycle sums, vote
 // ---------------------------------------------------------------------------
+// succ holds col[pi] here (a sweep, never a rebuild, changed pi last)
 __global__ __launch_bounds__(kWG) void k_pj_init(const int2* __restrict__ chunks,
                                                  const unsigned* nch, int T, GArrays ga,
-                                                 const int* __restrict__ col,
-                                                 const int* __restrict__ pi,
+                                                 const int* __restrict__ succ,
                                                  unsigned long long* __restrict__ P,
                                                  unsigned char* __restrict__ onc)
 {
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
         for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
-            const int s = col[pi[v]];
+            const int s = succ[v];
             P[v] = ((unsigned long long)(unsigned)s << 32) | (unsigned)v;
             onc[v] = 0;
         }
@@ -651,7 +809,7 @@ __global__ __launch_bounds__(kWG) void k_pj_round(const int2* __restrict__ chunk
                                                   unsigned long long* __restrict__ Pout)
 {
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
-        constexpr int U = 4;   // entries in flight per thread
+        constexpr int U = 8;   // entries in flight per thread
         for (int64_t vb = v0 + threadIdx.x; vb < v1; vb += U * kWG) {
             unsigned long long p[U], q[U];
 #pragma unroll
@@ -1401,7 +1559,6 @@ __global__ __launch_bounds__(kSmallWG) void k_small_solve(
 // ===========================================================================
 namespace {
 
-using ocm::Jmp;
 using ocm::b::BCtl;
 using ocm::b::GArrays;
 
@@ -1438,8 +1595,9 @@ struct BWs {
     int* V32;            // int32 copy of V (used while every value fits)
     int* pi;
     int* succ;
+    void* wsel;          // raw weight of each vertex's policy edge (WT)
     int* hop;
-    Jmp* Q[2];
+    ocm::b::VJ* Q[2];    // value rounds (the cycle and hop rounds alias them)
     int* rep;
     unsigned char* onc;
     unsigned char* onC;
@@ -1517,9 +1675,11 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m, size_t sub_bytes)
     w.V32 = (int*)take(4 * N);
     w.pi = (int*)take(4 * N);
     w.succ = (int*)take(4 * N);
+    w.wsel = take(8 * N);
     w.hop = (int*)take(4 * N);
-    w.Q[0] = (Jmp*)take(sizeof(Jmp) * N);
-    w.Q[1] = (Jmp*)take(sizeof(Jmp) * N);
+    static_assert(sizeof(ocm::b::VJ) >= 8, "the 8-byte jump entries alias Q");
+    w.Q[0] = (ocm::b::VJ*)take(sizeof(ocm::b::VJ) * N);
+    w.Q[1] = (ocm::b::VJ*)take(sizeof(ocm::b::VJ) * N);
     w.rep = (int*)take(4 * N);
     w.onc = (unsigned char*)take(N);
     w.onC = (unsigned char*)take(N);
@@ -1651,6 +1811,12 @@ void enqueue_chunks(BCtx& c, int want, const unsigned* halt = nullptr)
 {
     GArrays& a = c.ws.ga;
     const int T = c.sch.chunk;
+    if (c.G <= ocm::b::kChunkListOne) {
+        ocm::b::k_chunk_list<<<1, ocm::b::kChunkListWG, 0, c.st>>>((int)c.G, a.mode, want, a.vptr, T,
+                                                                  c.ws.chunks, &c.ws.bc->nchunks,
+                                                                  halt);
+        return;
+    }
     ocm::b::k_chunk_count<<<ocm::stride_grid(c.G + 1), ocm::kWG, 0, c.st>>>((int)c.G, a.mode, want,
                                                                           a.vptr, T, a.ccnt, halt);
     ocm::launch_exclusive_scan(c.G + 1, a.ccnt, a.coff, a.ctot, c.st);
@@ -1678,13 +1844,13 @@ void launch_bsweep_t(BCtx& c, unsigned nch, bool tie, int* xs, int* ys, unsigned
 #define OCM_BSW(GG)                                                                              \
     case GG:                                                                                     \
         if (tie)                                                                                 \
-            ocm::b::k_sweep<GG, WT, true><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(                            \
+            ocm::b::k_sweep<GG, WT, true><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(          \
                 ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,   \
-                ws.onC, ws.hop, xs, ys, xcnt, xcap);                                             \
+                ws.onC, ws.hop, xs, ys, xcnt, xcap, nullptr, nullptr);                           \
         else                                                                                     \
-            ocm::b::k_sweep<GG, WT, false><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(                           \
+            ocm::b::k_sweep<GG, WT, false><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(         \
                 ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,   \
-                ws.onC, ws.hop, nullptr, nullptr, nullptr, 0u);                                  \
+                ws.onC, ws.hop, nullptr, nullptr, nullptr, 0u, ws.succ, (WT*)ws.wsel);           \
         break;
     switch (c.sch.lanes) {
         OCM_BSW(1)
@@ -1712,12 +1878,13 @@ void launch_bsweep(BCtx& c, unsigned nch, bool tie, int* xs = nullptr, int* ys =
                 kgrid(chunk_grid(nch), (const void*)ocm::b::k_sweep_tile<long long>), ocm::kWG, 0,
                 c.st>>>(
                 ws.chunks, &ws.bc->nchunks, c.sch.chunk, ws.ga, c.row_ptr, c.col,
-                (const long long*)c.w, c.neg, ws.V, ws.pi, ws.onC, ws.V32, ws.bc);
+                (const long long*)c.w, c.neg, ws.V, ws.pi, ws.onC, ws.V32, ws.bc, ws.succ,
+                (long long*)ws.wsel);
         else
             ocm::b::k_sweep_tile<int><<<kgrid(chunk_grid(nch), (const void*)ocm::b::k_sweep_tile<int>),
                                         ocm::kWG, 0, c.st>>>(
                 ws.chunks, &ws.bc->nchunks, c.sch.chunk, ws.ga, c.row_ptr, c.col, (const int*)c.w,
-                c.neg, ws.V, ws.pi, ws.onC, ws.V32, ws.bc);
+                c.neg, ws.V, ws.pi, ws.onC, ws.V32, ws.bc, ws.succ, (int*)ws.wsel);
         return;
     }
     if (c.wtype == OCM_W_I64) launch_bsweep_t<long long>(c, nch, tie, xs, ys, xcnt, xcap);
@@ -1775,15 +1942,21 @@ void enqueue_values(BCtx& c, int want, const unsigned* halt = nullptr)
     const int T = c.sch.chunk;
     const unsigned mc = chunk_grid(c);
     enqueue_chunks(c, want, halt);
-    if (c.wtype == OCM_W_I64)
-        ocm::b::k_val_init<long long><<<mc, ocm::kWG, 0, c.st>>>(
-            ws.chunks, &ws.bc->nchunks, T, a, c.col, ws.pi, (const long long*)c.w, c.neg, ws.succ,
-            ws.Q[0]);
-    else
-        ocm::b::k_val_init<int><<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, c.col,
-                                                           ws.pi, (const int*)c.w, c.neg, ws.succ,
-                                                           ws.Q[0]);
-    ocm::b::k_val_mark<<<chunk_grid(c), ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.Q[0]);
+    // the fast path's graphs keep succ and wsel from their sweeps; the
+    // general path's were rebuilt
+    const bool sel = want == ocm::b::kFast;
+#define OCM_BVI(WT, SEL)                                                                        \
+    ocm::b::k_val_init<WT, SEL><<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a,     \
+                                                          c.col, ws.pi, (const WT*)c.w, c.neg,  \
+                                                          ws.succ, (WT*)ws.wsel, ws.Q[0])
+    if (c.wtype == OCM_W_I64) {
+        if (sel) OCM_BVI(long long, true);
+        else OCM_BVI(long long, false);
+    } else {
+        if (sel) OCM_BVI(int, true);
+        else OCM_BVI(int, false);
+    }
+#undef OCM_BVI
     const int R = jump_rounds(c);
     ocm::launch_fill_u32(ws.bc->vrun_round, 32, 0u, c.st);
     for (int r = 0; r < R; ++r) {
@@ -1796,7 +1969,7 @@ void enqueue_values(BCtx& c, int want, const unsigned* halt = nullptr)
     ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, R, ws.bc,
                                                                      halt);
     ocm::b::k_val_final<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, want, ws.Q[0],
-                                                   ws.Q[1], ws.V, ws.hop, ws.V32, ws.bc);
+                                                   ws.Q[1], ws.V, ws.V32, ws.bc);
     ocm::b::k_values_done<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, halt);
 }
 
@@ -1811,7 +1984,7 @@ void enqueue_general_head(BCtx& c)
     auto* P0 = (unsigned long long*)ws.Q[0];
     auto* P1 = (unsigned long long*)ws.Q[1];
     const int K = jump_rounds(c);
-    ocm::b::k_pj_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, c.col, ws.pi, P0,
+    ocm::b::k_pj_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.succ, P0,
                                                  ws.onc);
     for (int k = 0; k < K; ++k) {
         ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0, P1);
@@ -2076,7 +2249,7 @@ ocm_status autotune(BCtx& c, Schedule* out, int* tuned)
             auto* P1 = (unsigned long long*)ws.Q[1];
             const unsigned mc = chunk_grid(c);
             ocm::b::k_pj_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
-                                                         c.col, ws.pi, P0, ws.onc);
+                                                         ws.succ, P0, ws.onc);
             ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
                                                           P0, P1);
             ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
@@ -2452,7 +2625,30 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
         if (c.h.rounds_open) BTRY(finish_rounds(c));
     }
 
-    // per-graph results
+    // hops to the source for every solved graph (the small class's are
+    // recomputed, equal), then the per-graph results
+    {
+        unsigned nch = 0;
+        BTRY(build_chunks(c, -2, &nch));
+        if (nch > 0) {
+            const int T = c.sch.chunk;
+            const unsigned mc = chunk_grid(nch);
+            auto* P0 = (unsigned long long*)ws.Q[0];
+            auto* P1 = (unsigned long long*)ws.Q[1];
+            const int R = jump_rounds(c);
+            ocm::launch_fill_u32(ws.bc->hop_act, 34, 0u, c.st);
+            ocm::launch_fill_u32(ws.bc->hop_act, 1, 1u, c.st);
+            ocm::b::k_hop_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.succ,
+                                                          P0);
+            for (int r = 0; r < R; ++r)
+                ocm::b::k_hop_round<<<mc, ocm::kWG, 0, c.st>>>(
+                    ws.chunks, &ws.bc->nchunks, T, a, r & 1 ? P1 : P0, r & 1 ? P0 : P1,
+                    &ws.bc->hop_act[r], &ws.bc->hop_act[r + 1]);
+            ocm::b::k_hop_final<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0,
+                                                           P1, ws.bc->hop_act, R, ws.hop);
+            BHIP(hipGetLastError());
+        }
+    }
     std::vector<long long> hW(G), hL(G);
     std::vector<int> hs(G), hit(G), hst(G);
     BHIP(hipMemcpyAsync(hW.data(), a.W, 8 * (size_t)G, hipMemcpyDeviceToHost, c.st));
