@@ -180,13 +180,18 @@ __global__ __launch_bounds__(kChunkListWG) void k_chunk_list(int G, const int* _
                                                              unsigned* nch, const unsigned* halt)
 {
     __shared__ unsigned wsum[kChunkListWG / 64];
-    const int per = (G + kChunkListWG - 1) / kChunkListWG;
+    constexpr int kPer = kChunkListOne / kChunkListWG;
+    const int per = (G + kChunkListWG - 1) / kChunkListWG;   // <= kPer
     const int g0 = (int)threadIdx.x * per;
-    const int g1 = g0 + per < G ? g0 + per : G;
     const bool off = halt && *halt != 0u;
+    unsigned cnt[kPer];
     unsigned mine = 0;
-    if (!off)
-        for (int g = g0; g < g1; ++g) mine += chunk_count(g, mode, want, vptr, T);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int g = g0 + i;
+        cnt[i] = !off && i < per && g < G ? chunk_count(g, mode, want, vptr, T) : 0u;
+        mine += cnt[i];
+    }
     const unsigned incl = wave_incl_scan(mine);
     if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = incl;
     __syncthreads();
@@ -195,13 +200,14 @@ __global__ __launch_bounds__(kChunkListWG) void k_chunk_list(int G, const int* _
         if (i < (int)(threadIdx.x >> 6)) o += wsum[i];
         total += wsum[i];
     }
-    if (!off)
-        for (int g = g0; g < g1; ++g) {
-            const unsigned c = chunk_count(g, mode, want, vptr, T);
-            const long long v0 = vptr[g];
-            for (unsigned i = 0; i < c; ++i) chunks[o + i] = make_int2(g, (int)(v0 + (long long)i * T));
-            o += c;
-        }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        if (cnt[i] == 0) continue;
+        const int g = g0 + i;
+        const long long v0 = vptr[g];
+        for (unsigned j = 0; j < cnt[i]; ++j) chunks[o + j] = make_int2(g, (int)(v0 + (long long)j * T));
+        o += cnt[i];
+    }
     if (threadIdx.x == 0) *nch = total;
 }
 
@@ -369,8 +375,13 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
 // keys in CSR order for the lowest-position minimum.  Same results as
 // k_sweep (strict "<" in CSR order).
 constexpr int kBTileEdges = 2048;
+constexpr bool kSweepOneTile = true;
 
-template <typename WT>
+// ONE: a workgroup per tile (blockIdx.x -> chunk, tile of the chunk; the
+// grid covers the list's capacity and idle workgroups leave at once), so the
+// dispatcher overlaps one tile's loads with another's; otherwise a resident
+// grid strides over the chunks and walks their tiles in order.
+template <typename WT, bool ONE>
 __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chunks,
                                                     const unsigned* nch, int T, GArrays ga,
                                                     const int* __restrict__ row_ptr,
@@ -389,94 +400,117 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
     const int t = threadIdx.x;
     // every value written so far fits int32: gather the 4-byte copy
     const bool use32 = bc->wide32 == 0u;
-    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t c0, int64_t c1) {
-        const bool first = ga.iter[g] == 0;
-        const long long L = first ? 1 : ga.L[g];
-        const long long W = first ? 0 : ga.W[g];
-        unsigned long long cnt = 0;
-        unsigned brk = 0;
-        for (int64_t v0 = c0; v0 < c1; v0 += kWG) {
-            const int nv = c1 - v0 < kWG ? (int)(c1 - v0) : kWG;
-            long long own = 0, best = INT64_MAX;
-            int pos = INT32_MAX;
-            __syncthreads();   // beg / key of the previous tile are read
-            if (t < nv) {
-                beg[t] = row_ptr[v0 + t];
-                if (!first) own = use32 ? (long long)V32[v0 + t] : V[v0 + t];
-            }
-            if (t == 0) beg[nv] = row_ptr[v0 + nv];
-            __syncthreads();
-            const int e0 = beg[0], e1 = beg[nv];
-            const int mb = t < nv ? beg[t] : 0, me = t < nv ? beg[t + 1] : 0;
-            for (int eb = e0; eb < e1; eb += kBTileEdges) {
-                const int ne = e1 - eb < kBTileEdges ? e1 - eb : kBTileEdges;
-                int c[U];
-                WT wr[U];   // raw weights: half the registers of int64 ones for int32 w
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int j = t + u * kWG;
-                    c[u] = 0;
-                    wr[u] = 0;
-                    if (j < ne) {
-                        c[u] = col[eb + j];
-                        wr[u] = w[eb + j];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int j = t + u * kWG;
-                    if (j < ne) {
-                        const long long wl = wval(&wr[u], 0, neg);
-                        key[j] = first ? wl
-                                       : (use32 ? (long long)V32[c[u]] : V[c[u]]) + L * wl - W;
-                    }
-                }
-                __syncthreads();
-                const int lo = mb > eb ? mb : eb, hi = me < eb + ne ? me : eb + ne;
-                const bool long_row = hi - lo > kLongRow;
-                if (!long_row)
-                    for (int e = lo; e < hi; ++e) {
-                        const long long k = key[e - eb];
-                        if (k < best) {
-                            best = k;
-                            pos = e;
-                        }
-                    }
-                // the wave's long rows, one after the other, by all its lanes
-                for (unsigned long long lm = __ballot(long_row); lm; lm &= lm - 1) {
-                    const int l = __ffsll((long long)lm) - 1;
-                    const int rlo = __shfl(lo, l, 64), rhi = __shfl(hi, l, 64);
-                    long long rb = INT64_MAX;
-                    int rp = INT32_MAX, rh = 0;
-                    for (int e = rlo + (t & 63); e < rhi; e += 64) {
-                        const long long k = key[e - eb];
-                        if (k < rb) {
-                            rb = k;
-                            rp = e;
-                        }
-                    }
-                    wave_argmin<long long, false>(rb, rp, rh);
-                    if ((t & 63) == l && rb < best) {
-                        best = rb;
-                        pos = rp;
-                    }
-                }
-                __syncthreads();
-            }
-            if (t < nv && pos != INT32_MAX && (first || best < own)) {
-                pi[v0 + t] = pos;
-                succ[v0 + t] = col[pos];
-                wsel[v0 + t] = w[pos];
-                cnt++;
-                if (!first && onC[v0 + t]) brk = 1;
-            }
+    // one tile of nv <= kWG vertices from v0; counts into cnt / brk
+    auto tile = [&](int64_t v0, int nv, bool first, long long L, long long W,
+                    unsigned long long& cnt, unsigned& brk) {
+        long long own = 0, best = INT64_MAX;
+        int pos = INT32_MAX;
+        __syncthreads();   // beg / key of the previous tile are read
+        if (t < nv) {
+            beg[t] = row_ptr[v0 + t];
+            if (!first) own = use32 ? (long long)V32[v0 + t] : V[v0 + t];
         }
+        if (t == 0) beg[nv] = row_ptr[v0 + nv];
+        __syncthreads();
+        const int e0 = beg[0], e1 = beg[nv];
+        const int mb = t < nv ? beg[t] : 0, me = t < nv ? beg[t + 1] : 0;
+        for (int eb = e0; eb < e1; eb += kBTileEdges) {
+            const int ne = e1 - eb < kBTileEdges ? e1 - eb : kBTileEdges;
+            int c[U];
+            WT wr[U];   // raw weights: half the registers of int64 ones for int32 w
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = t + u * kWG;
+                c[u] = 0;
+                wr[u] = 0;
+                if (j < ne) {
+                    c[u] = col[eb + j];
+                    wr[u] = w[eb + j];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = t + u * kWG;
+                if (j < ne) {
+                    const long long wl = wval(&wr[u], 0, neg);
+                    key[j] = first ? wl : (use32 ? (long long)V32[c[u]] : V[c[u]]) + L * wl - W;
+                }
+            }
+            __syncthreads();
+            const int lo = mb > eb ? mb : eb, hi = me < eb + ne ? me : eb + ne;
+            const bool long_row = hi - lo > kLongRow;
+            if (!long_row)
+                for (int e = lo; e < hi; ++e) {
+                    const long long k = key[e - eb];
+                    if (k < best) {
+                        best = k;
+                        pos = e;
+                    }
+                }
+            // the wave's long rows, one after the other, by all its lanes
+            for (unsigned long long lm = __ballot(long_row); lm; lm &= lm - 1) {
+                const int l = __ffsll((long long)lm) - 1;
+                const int rlo = __shfl(lo, l, 64), rhi = __shfl(hi, l, 64);
+                long long rb = INT64_MAX;
+                int rp = INT32_MAX, rh = 0;
+                for (int e = rlo + (t & 63); e < rhi; e += 64) {
+                    const long long k = key[e - eb];
+                    if (k < rb) {
+                        rb = k;
+                        rp = e;
+                    }
+                }
+                wave_argmin<long long, false>(rb, rp, rh);
+                if ((t & 63) == l && rb < best) {
+                    best = rb;
+                    pos = rp;
+                }
+            }
+            __syncthreads();
+        }
+        if (t < nv && pos != INT32_MAX && (first || best < own)) {
+            pi[v0 + t] = pos;
+            succ[v0 + t] = col[pos];
+            wsel[v0 + t] = w[pos];
+            cnt++;
+            if (!first && onC[v0 + t]) brk = 1;
+        }
+    };
+    auto book = [&](int g, unsigned long long cnt, unsigned brk) {
         cnt = block_sum_u64(cnt);
         const unsigned long long bb = block_sum_u64(brk);
         if (threadIdx.x == 0) {
             if (cnt) atomicAdd(&ga.changed[g], (unsigned)(cnt > 0xffffffffull ? 0xffffffffu : cnt));
             if (bb) atomicOr(&ga.cbroken[g], 1u);
         }
+    };
+    if (ONE) {
+        const unsigned per = (unsigned)((T + kWG - 1) / kWG);
+        const unsigned ci = blockIdx.x / per;
+        if (ci >= *nch) return;
+        const int2 ch = chunks[ci];
+        const int g = ch.x;
+        const int64_t end = ga.vptr[g + 1];
+        const int64_t c1 = ch.y + (int64_t)T < end ? ch.y + (int64_t)T : end;
+        const int64_t v0 = ch.y + (int64_t)(blockIdx.x % per) * kWG;
+        if (v0 >= c1) return;
+        const bool first = ga.iter[g] == 0;
+        unsigned long long cnt = 0;
+        unsigned brk = 0;
+        tile(v0, c1 - v0 < kWG ? (int)(c1 - v0) : kWG, first, first ? 1 : ga.L[g],
+             first ? 0 : ga.W[g], cnt, brk);
+        book(g, cnt, brk);
+        return;
+    }
+    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t c0, int64_t c1) {
+        const bool first = ga.iter[g] == 0;
+        const long long L = first ? 1 : ga.L[g];
+        const long long W = first ? 0 : ga.W[g];
+        unsigned long long cnt = 0;
+        unsigned brk = 0;
+        for (int64_t v0 = c0; v0 < c1; v0 += kWG)
+            tile(v0, c1 - v0 < kWG ? (int)(c1 - v0) : kWG, first, L, W, cnt, brk);
+        book(g, cnt, brk);
     });
 }
 
@@ -522,9 +556,13 @@ __global__ __launch_bounds__(kWG) void k_after_sweep(int G, GArrays ga, int max_
 // ---------------------------------------------------------------------------
 // values: pointer jumping toward each graph's source
 // ---------------------------------------------------------------------------
+constexpr bool kFastInitTwo = true;
+
 // Value init.  SEL (fast path): each vertex's successor and edge weight come
-// from succ and wsel; otherwise (after a rebuild) from pi, col and w, and
-// succ and wsel are written.  It also books the first round: a graph none of
+// from succ and wsel, and the entry already spans two policy edges (succ
+// and wsel of the successor are gathered); otherwise (after a rebuild) they
+// come from pi, col and w, the entry spans one edge, and succ and wsel are
+// written.  It also books the first round: a graph none of
 // whose vertices has an entry short of s is finished (vact stays clear).
 template <typename WT, bool SEL>
 __global__ __launch_bounds__(kWG) void k_val_init(const int2* __restrict__ chunks,
@@ -553,9 +591,16 @@ __global__ __launch_bounds__(kWG) void k_val_init(const int2* __restrict__ chunk
                 wsel[v] = x;
                 we = wval(&x, 0, neg);
             }
-            const int j = v == s ? s : t;
+            int j = v == s ? s : t;
+            long long d = v == s ? 0 : L * we - W;
+            if (SEL && kFastInitTwo && j != s) {
+                // two policy edges (the first jump round's work); each term
+                // is below 2^62 in magnitude (the weight bound): no overflow
+                d += L * wval(wsel, t, neg) - W;
+                j = succ[t];
+            }
             act |= j != s ? 1u : 0u;
-            Q[v] = vj_make(v == s ? 0 : L * we - W, j);
+            Q[v] = vj_make(d, j);
         }
         const unsigned long long a = block_sum_u64(act);
         if (threadIdx.x == 0) {
@@ -803,12 +848,23 @@ __global__ __launch_bounds__(kWG) void k_pj_init(const int2* __restrict__ chunks
     });
 }
 
+// Rounds a graph of n vertices needs: ceil(log2 n) (2^K >= n covers every
+// policy path and cycle in it).
+__device__ __forceinline__ int graph_rounds(const long long* __restrict__ vptr, int g)
+{
+    const long long n = vptr[g + 1] - vptr[g];
+    return n <= 1 ? 0 : 64 - __clzll((unsigned long long)(n - 1));
+}
+
+// Round k reads P[k & 1] and writes P[(k + 1) & 1]; a graph takes part only
+// in its first graph_rounds rounds, so its entries end in P[rounds & 1].
 __global__ __launch_bounds__(kWG) void k_pj_round(const int2* __restrict__ chunks,
-                                                  const unsigned* nch, int T, GArrays ga,
+                                                  const unsigned* nch, int T, GArrays ga, int k,
                                                   const unsigned long long* __restrict__ Pin,
                                                   unsigned long long* __restrict__ Pout)
 {
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        if (k >= graph_rounds(ga.vptr, g)) return;
         constexpr int U = 8;   // entries in flight per thread
         for (int64_t vb = v0 + threadIdx.x; vb < v1; vb += U * kWG) {
             unsigned long long p[U], q[U];
@@ -833,11 +889,13 @@ __global__ __launch_bounds__(kWG) void k_pj_round(const int2* __restrict__ chunk
 
 __global__ __launch_bounds__(kWG) void k_pj_final(const int2* __restrict__ chunks,
                                                   const unsigned* nch, int T, GArrays ga,
-                                                  const unsigned long long* __restrict__ P,
+                                                  const unsigned long long* __restrict__ P0,
+                                                  const unsigned long long* __restrict__ P1,
                                                   int* __restrict__ rep,
                                                   unsigned char* __restrict__ onc)
 {
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        const unsigned long long* __restrict__ P = graph_rounds(ga.vptr, g) & 1 ? P1 : P0;
         for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) {
             const int c = (int)(P[v] >> 32);
             rep[v] = (int)(unsigned)P[c];
@@ -1873,18 +1931,24 @@ void launch_bsweep(BCtx& c, unsigned nch, bool tie, int* xs = nullptr, int* ys =
     if (nch == 0) return;
     if (!tie && c.tile_sweep) {   // improvement sweeps over vertex tiles
         BWs& ws = c.ws;
-        if (c.wtype == OCM_W_I64)
-            ocm::b::k_sweep_tile<long long><<<
-                kgrid(chunk_grid(nch), (const void*)ocm::b::k_sweep_tile<long long>), ocm::kWG, 0,
-                c.st>>>(
-                ws.chunks, &ws.bc->nchunks, c.sch.chunk, ws.ga, c.row_ptr, c.col,
-                (const long long*)c.w, c.neg, ws.V, ws.pi, ws.onC, ws.V32, ws.bc, ws.succ,
-                (long long*)ws.wsel);
-        else
-            ocm::b::k_sweep_tile<int><<<kgrid(chunk_grid(nch), (const void*)ocm::b::k_sweep_tile<int>),
-                                        ocm::kWG, 0, c.st>>>(
-                ws.chunks, &ws.bc->nchunks, c.sch.chunk, ws.ga, c.row_ptr, c.col, (const int*)c.w,
-                c.neg, ws.V, ws.pi, ws.onC, ws.V32, ws.bc, ws.succ, (int*)ws.wsel);
+        const int T = c.sch.chunk;
+        const unsigned per = (unsigned)((T + ocm::kWG - 1) / ocm::kWG);
+        // one workgroup per tile: the list's capacity in tiles
+        const unsigned one = (unsigned)(c.n / T + c.G + 1) * per;
+#define OCM_BST(WT)                                                                              \
+    if (ocm::b::kSweepOneTile)                                                                   \
+        ocm::b::k_sweep_tile<WT, true><<<one, ocm::kWG, 0, c.st>>>(                              \
+            ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, (const WT*)c.w, c.neg, ws.V, \
+            ws.pi, ws.onC, ws.V32, ws.bc, ws.succ, (WT*)ws.wsel);                                \
+    else                                                                                         \
+        ocm::b::k_sweep_tile<WT, false><<<kgrid(chunk_grid(nch),                                 \
+                                                (const void*)ocm::b::k_sweep_tile<WT, false>),   \
+                                          ocm::kWG, 0, c.st>>>(                                  \
+            ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, (const WT*)c.w, c.neg, ws.V, \
+            ws.pi, ws.onC, ws.V32, ws.bc, ws.succ, (WT*)ws.wsel)
+        if (c.wtype == OCM_W_I64) OCM_BST(long long);
+        else OCM_BST(int);
+#undef OCM_BST
         return;
     }
     if (c.wtype == OCM_W_I64) launch_bsweep_t<long long>(c, nch, tie, xs, ys, xcnt, xcap);
@@ -1958,13 +2022,15 @@ void enqueue_values(BCtx& c, int want, const unsigned* halt = nullptr)
     }
 #undef OCM_BVI
     const int R = jump_rounds(c);
+    // one resident wave of round workgroups (its registers allow fewer than
+    // the chunk grid)
+    const unsigned vg = kgrid(chunk_grid(c), (const void*)ocm::b::k_val_round);
     ocm::launch_fill_u32(ws.bc->vrun_round, 32, 0u, c.st);
     for (int r = 0; r < R; ++r) {
         ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, r,
                                                                          ws.bc, halt);
-        ocm::b::k_val_round<<<chunk_grid(c), ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a,
-                                                                ws.Q[r & 1], ws.Q[(r + 1) & 1],
-                                                                &ws.bc->vrun_round[r]);
+        ocm::b::k_val_round<<<vg, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.Q[r & 1],
+                                                     ws.Q[(r + 1) & 1], &ws.bc->vrun_round[r]);
     }
     ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, R, ws.bc,
                                                                      halt);
@@ -1986,11 +2052,10 @@ void enqueue_general_head(BCtx& c)
     const int K = jump_rounds(c);
     ocm::b::k_pj_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.succ, P0,
                                                  ws.onc);
-    for (int k = 0; k < K; ++k) {
-        ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0, P1);
-        std::swap(P0, P1);
-    }
-    ocm::b::k_pj_final<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0, ws.rep,
+    for (int k = 0; k < K; ++k)
+        ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, k,
+                                                      k & 1 ? P1 : P0, k & 1 ? P0 : P1);
+    ocm::b::k_pj_final<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, P0, P1, ws.rep,
                                                   ws.onc);
     ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->ncyc, nullptr);
     ocm::b::k_cyc_zero<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.rep, ws.onc,
@@ -2251,9 +2316,9 @@ ocm_status autotune(BCtx& c, Schedule* out, int* tuned)
             ocm::b::k_pj_init<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
                                                          ws.succ, P0, ws.onc);
             ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
-                                                          P0, P1);
+                                                          0, P0, P1);
             ocm::b::k_pj_round<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, s.chunk, ws.ga,
-                                                          P1, P0);
+                                                          1, P1, P0);
             BHIP(hipEventRecord(e1, c.st));
             BHIP(hipEventSynchronize(e1));
             float t = 0.f;
