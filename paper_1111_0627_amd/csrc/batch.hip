@@ -373,8 +373,9 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
 // LDS in batches of kBTileEdges (col and w loaded coalesced, the gathered V
 // and the key computed per edge), then each thread walks its own vertex's
 // keys in CSR order for the lowest-position minimum.  Same results as
-// k_sweep (strict "<" in CSR order).
-constexpr int kBTileEdges = 2048;
+// k_sweep (strict "<" in CSR order).  Batches of 1024 keys measured faster
+// than 2048 or 1536 on the 4096-graph batch (more workgroups resident).
+constexpr int kBTileEdges = 1024;
 constexpr bool kSweepOneTile = true;
 
 // ONE: a workgroup per tile (blockIdx.x -> chunk, tile of the chunk; the
@@ -734,14 +735,21 @@ __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chun
 
 // Hops to the source after the loop (the policy edges from v to s, which
 // the tie tests and the cycle listing use), by pointer jumping on entries
-// (J in the high word, H in the low word).  Graphs that failed are skipped.
+// (J in the high word, H in the low word).  Graphs that failed are skipped,
+// and so are those of the small class (never in the loop, so have_c is
+// clear), which wrote their hops themselves.
+__device__ __forceinline__ bool hop_graph(const GArrays& ga, int g)
+{
+    return ga.status[g] == OCM_OK && ga.have_c[g];
+}
+
 __global__ __launch_bounds__(kWG) void k_hop_init(const int2* __restrict__ chunks,
                                                   const unsigned* nch, int T, GArrays ga,
                                                   const int* __restrict__ succ,
                                                   unsigned long long* __restrict__ P)
 {
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
-        if (ga.status[g] != OCM_OK) return;
+        if (!hop_graph(ga, g)) return;
         const int s = ga.s[g];
         for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG)
             P[v] = v == s ? (unsigned long long)(unsigned)s << 32
@@ -759,7 +767,7 @@ __global__ __launch_bounds__(kWG) void k_hop_round(const int2* __restrict__ chun
 {
     if (*running == 0) return;
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
-        if (ga.status[g] != OCM_OK) return;
+        if (!hop_graph(ga, g)) return;
         const unsigned s = (unsigned)ga.s[g];
         unsigned act = 0;
         constexpr int U = 8;
@@ -804,7 +812,7 @@ __global__ __launch_bounds__(kWG) void k_hop_final(const int2* __restrict__ chun
     while (ran < R && hop_act[ran] != 0u) ++ran;
     const unsigned long long* __restrict__ P = ran == 0 ? P0 : ((ran - 1) & 1 ? P0 : P1);
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
-        if (ga.status[g] != OCM_OK) return;
+        if (!hop_graph(ga, g)) return;
         for (int64_t v = v0 + threadIdx.x; v < v1; v += kWG) hop[v] = (int)(unsigned)P[v];
     });
 }
