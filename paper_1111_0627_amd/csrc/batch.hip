@@ -376,13 +376,12 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
 // k_sweep (strict "<" in CSR order).  Batches of 1024 keys measured faster
 // than 2048 or 1536 on the 4096-graph batch (more workgroups resident).
 constexpr int kBTileEdges = 1024;
-constexpr bool kSweepOneTile = true;
 
-// ONE: a workgroup per tile (blockIdx.x -> chunk, tile of the chunk; the
-// grid covers the list's capacity and idle workgroups leave at once), so the
-// dispatcher overlaps one tile's loads with another's; otherwise a resident
-// grid strides over the chunks and walks their tiles in order.
-template <typename WT, bool ONE>
+// A workgroup per tile (blockIdx.x -> chunk, tile of the chunk; the grid
+// covers the list's capacity and idle workgroups leave at once), so that
+// the dispatcher overlaps one tile's loads with another's (measured faster
+// than a resident grid that walks its chunks' tiles in order).
+template <typename WT>
 __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chunks,
                                                     const unsigned* nch, int T, GArrays ga,
                                                     const int* __restrict__ row_ptr,
@@ -401,12 +400,11 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
     const int t = threadIdx.x;
     // every value written so far fits int32: gather the 4-byte copy
     const bool use32 = bc->wide32 == 0u;
-    // one tile of nv <= kWG vertices from v0; counts into cnt / brk
+    // the tile of nv <= kWG vertices from v0; counts into cnt / brk
     auto tile = [&](int64_t v0, int nv, bool first, long long L, long long W,
                     unsigned long long& cnt, unsigned& brk) {
         long long own = 0, best = INT64_MAX;
         int pos = INT32_MAX;
-        __syncthreads();   // beg / key of the previous tile are read
         if (t < nv) {
             beg[t] = row_ptr[v0 + t];
             if (!first) own = use32 ? (long long)V32[v0 + t] : V[v0 + t];
@@ -485,34 +483,21 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
             if (bb) atomicOr(&ga.cbroken[g], 1u);
         }
     };
-    if (ONE) {
-        const unsigned per = (unsigned)((T + kWG - 1) / kWG);
-        const unsigned ci = blockIdx.x / per;
-        if (ci >= *nch) return;
-        const int2 ch = chunks[ci];
-        const int g = ch.x;
-        const int64_t end = ga.vptr[g + 1];
-        const int64_t c1 = ch.y + (int64_t)T < end ? ch.y + (int64_t)T : end;
-        const int64_t v0 = ch.y + (int64_t)(blockIdx.x % per) * kWG;
-        if (v0 >= c1) return;
-        const bool first = ga.iter[g] == 0;
-        unsigned long long cnt = 0;
-        unsigned brk = 0;
-        tile(v0, c1 - v0 < kWG ? (int)(c1 - v0) : kWG, first, first ? 1 : ga.L[g],
-             first ? 0 : ga.W[g], cnt, brk);
-        book(g, cnt, brk);
-        return;
-    }
-    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t c0, int64_t c1) {
-        const bool first = ga.iter[g] == 0;
-        const long long L = first ? 1 : ga.L[g];
-        const long long W = first ? 0 : ga.W[g];
-        unsigned long long cnt = 0;
-        unsigned brk = 0;
-        for (int64_t v0 = c0; v0 < c1; v0 += kWG)
-            tile(v0, c1 - v0 < kWG ? (int)(c1 - v0) : kWG, first, L, W, cnt, brk);
-        book(g, cnt, brk);
-    });
+    const unsigned per = (unsigned)((T + kWG - 1) / kWG);
+    const unsigned ci = blockIdx.x / per;
+    if (ci >= *nch) return;
+    const int2 ch = chunks[ci];
+    const int g = ch.x;
+    const int64_t end = ga.vptr[g + 1];
+    const int64_t c1 = ch.y + (int64_t)T < end ? ch.y + (int64_t)T : end;
+    const int64_t v0 = ch.y + (int64_t)(blockIdx.x % per) * kWG;
+    if (v0 >= c1) return;
+    const bool first = ga.iter[g] == 0;
+    unsigned long long cnt = 0;
+    unsigned brk = 0;
+    tile(v0, c1 - v0 < kWG ? (int)(c1 - v0) : kWG, first, first ? 1 : ga.L[g],
+         first ? 0 : ga.W[g], cnt, brk);
+    book(g, cnt, brk);
 }
 
 // After the sweep: converged graphs retire; the others take the fast path
@@ -557,8 +542,6 @@ __global__ __launch_bounds__(kWG) void k_after_sweep(int G, GArrays ga, int max_
 // ---------------------------------------------------------------------------
 // values: pointer jumping toward each graph's source
 // ---------------------------------------------------------------------------
-constexpr bool kFastInitTwo = true;
-
 // Value init.  SEL (fast path): each vertex's successor and edge weight come
 // from succ and wsel, and the entry already spans two policy edges (succ
 // and wsel of the successor are gathered); otherwise (after a rebuild) they
@@ -594,7 +577,7 @@ __global__ __launch_bounds__(kWG) void k_val_init(const int2* __restrict__ chunk
             }
             int j = v == s ? s : t;
             long long d = v == s ? 0 : L * we - W;
-            if (SEL && kFastInitTwo && j != s) {
+            if (SEL && j != s) {
                 // two policy edges (the first jump round's work); each term
                 // is below 2^62 in magnitude (the weight bound): no overflow
                 d += L * wval(wsel, t, neg) - W;
@@ -1944,16 +1927,9 @@ void launch_bsweep(BCtx& c, unsigned nch, bool tie, int* xs = nullptr, int* ys =
         // one workgroup per tile: the list's capacity in tiles
         const unsigned one = (unsigned)(c.n / T + c.G + 1) * per;
 #define OCM_BST(WT)                                                                              \
-    if (ocm::b::kSweepOneTile)                                                                   \
-        ocm::b::k_sweep_tile<WT, true><<<one, ocm::kWG, 0, c.st>>>(                              \
-            ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, (const WT*)c.w, c.neg, ws.V, \
-            ws.pi, ws.onC, ws.V32, ws.bc, ws.succ, (WT*)ws.wsel);                                \
-    else                                                                                         \
-        ocm::b::k_sweep_tile<WT, false><<<kgrid(chunk_grid(nch),                                 \
-                                                (const void*)ocm::b::k_sweep_tile<WT, false>),   \
-                                          ocm::kWG, 0, c.st>>>(                                  \
-            ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, (const WT*)c.w, c.neg, ws.V, \
-            ws.pi, ws.onC, ws.V32, ws.bc, ws.succ, (WT*)ws.wsel)
+    ocm::b::k_sweep_tile<WT><<<one, ocm::kWG, 0, c.st>>>(                                        \
+        ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, (const WT*)c.w, c.neg, ws.V,     \
+        ws.pi, ws.onC, ws.V32, ws.bc, ws.succ, (WT*)ws.wsel)
         if (c.wtype == OCM_W_I64) OCM_BST(long long);
         else OCM_BST(int);
 #undef OCM_BST

@@ -329,3 +329,32 @@ def test_small_class_iteration_cap(monkeypatch):
         outs.append((r.p, r.q, r.iterations, r.status))
     assert outs[0] == outs[1]
     assert ocm.OCM_E_NOT_CONVERGED in outs[0][3]
+
+
+def test_more_graphs_than_one_workgroup_lists(monkeypatch):
+    """Above 16,384 graphs the chunk lists come from the count, scan and
+    fill launches instead of one workgroup.  Small class on and off give
+    identical bytes, and sampled graphs (the two that take the loop
+    included) equal the oracle."""
+    rng = np.random.default_rng(51)
+    sizes = rng.integers(2, 40, 17000)
+    gs = [synth.random_digraph(int(n), 1, 4, 1, 50, np.int32, seed=[51, k])
+          for k, n in enumerate(sizes)]
+    gs += [synth.random_digraph(n, 1, 6, -50, 50, np.int32, seed=[52, n]) for n in (3000, 9000)]
+    u, vptr, eptr = synth.disjoint_union(gs)
+    dev = to_dev(u)
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("OCM_BATCH_SMALL", flag)
+        r = ocm.cycle_mean_batched(*dev, vptr, eptr)
+        outs.append((r.p, r.q, r.iterations, r.cycle_ptr, r.cycle_edges.cpu().tolist(), r.flags,
+                     r.status))
+    assert outs[0] == outs[1]
+    p, q, iters, cptr, cyc_all, flags, status = outs[0]
+    assert all(s == ocm.OCM_OK for s in status)
+    for k in list(range(0, len(gs), 97)) + [len(gs) - 2, len(gs) - 1]:
+        g = gs[k]
+        sol = native.solve(g.row_ptr, g.col, g.w)
+        cyc = [c - eptr[k] for c in cyc_all[cptr[k]:cptr[k + 1]]]
+        assert (p[k], q[k], cyc, iters[k]) == (sol.p, sol.q, sol.cycle.tolist(), sol.iterations), k
+        assert bool(flags[k] & ocm.OCM_F_TIE) == bool(sol.tie), k
