@@ -2155,7 +2155,8 @@ void enqueue_rounds(BCtx& c, int k0, int k1)
     for (int k = k0; k <= k1; ++k)
         ocm::launch_round(k, c.n, c.row_ptr, c.col, ws.rin_ptr, ws.rin, ws.abits[k & 1],
                           ws.abits[(k + 1) & 1], mk[k & 1], mk[(k + 1) & 1], ws.pi, nullptr, cc,
-                          &cc->lane[0].pedges, c.rev_built ? 0 : 1, kBPushMin, c.rev_built, c.st);
+                          &cc->lane[0].pedges, c.rev_built ? 0 : 1, kBPushMin, c.rev_built,
+                          false, c.st);
 }
 
 // One whole iteration without a host read: sweep, retirement, fast-path

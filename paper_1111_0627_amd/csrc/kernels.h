@@ -304,7 +304,10 @@ void launch_conn_claim(int k, int n, const int* row_ptr, const int* col, const u
 // left, 1: pull, 2: push); launch_round queues round k (a push or pull round
 // as the device decides, nothing once the rebuild is over).  Rounds are
 // queued in order k = 1, 2, ...; with may_push false (no reverse CSR) every
-// round must be a pull round.  Progress: rk, rleft, rerr, rmode.
+// round must be a pull round.  single (k > 1, may_push): one kernel for the
+// round instead of two, for rounds the host expects to push with the marks
+// the round before left; any other round then runs as a pull round (same
+// attachments).  Progress: rk, rleft, rerr, rmode.
 void launch_round_setup(Ctl* ctl, unsigned left, unsigned front, int policy, unsigned push_min,
                         hipStream_t st);
 // launch_round_setup with left / front taken on the device from the lanes'
@@ -314,7 +317,7 @@ void launch_round(int k, int n, const int* row_ptr, const int* col, const int* r
                   const int* rin, const unsigned* acur, unsigned* anext, unsigned char* marks,
                   unsigned char* marks_next, int* pi, int* layer, Ctl* ctl,
                   unsigned long long* pedges, int policy, unsigned push_min, bool may_push,
-                  hipStream_t st);
+                  bool single, hipStream_t st);
 // Reverse CSR (rin_ptr, rin) of the graph.  With `scratch` of
 // rev_scratch_bytes(n, m) bytes (0 when the plan does not apply) the build
 // is partitioned by head bucket; otherwise it counts and fills with global

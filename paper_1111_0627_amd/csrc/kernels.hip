@@ -1588,7 +1588,8 @@ __device__ __forceinline__ bool round_is(const Ctl* c, int k, unsigned mode)
 
 // Round k's first kernel: the marks of a push round (unless round k-1 left
 // them), or a whole pull round (clearing marks round k-1 left).  marks is
-// round k's mark array (marks[k & 1] of the pair).
+// round k's mark array (marks[k & 1] of the pair).  Not launched when the
+// host expects pushes with their marks left (single, below).
 __global__ __launch_bounds__(kWG) void k_round_mark_pull(
     int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
     const int* __restrict__ rin_ptr, const int* __restrict__ rin, const unsigned* __restrict__ acur,
@@ -1609,20 +1610,33 @@ __global__ __launch_bounds__(kWG) void k_round_mark_pull(
 }
 
 // Round k's second kernel: the claims of a push round, and the marks of
-// round k + 1 in marks_next.
+// round k + 1 in marks_next.  single: k_round_mark_pull was not launched
+// for round k (the host expected a push with its marks left by round k - 1);
+// this kernel then runs a pull round itself, and a push round that finds no
+// marks left (a pull came first) as a pull round too, which attaches the
+// same vertices by the same edges.
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_round_claim(
     int k, int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
     const int* __restrict__ rin_ptr, const int* __restrict__ rin, const unsigned* __restrict__ acur,
     unsigned* __restrict__ anext, unsigned char* __restrict__ marks,
     unsigned char* __restrict__ marks_next, int* __restrict__ pi, int* __restrict__ layer, Ctl* ctl,
-    unsigned long long* pedges, int policy, unsigned push_min)
+    unsigned long long* pedges, int policy, unsigned push_min, int single)
 {
-    if (!round_is(ctl, k, 1u)) return;
+    const bool push = round_is(ctl, k, 1u);
+    if (!push && !(single && round_is(ctl, k, 2u))) return;
     __shared__ RoundLds L;
-    const unsigned long long g = claim_body(k, n, row_ptr, col, acur, anext, marks, pi, layer,
-                                            nullptr, nullptr, nullptr, rin_ptr, rin, marks_next,
-                                            pedges, L);
-    if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min, true);
+    const bool left_marks = ctl->rmarks == (unsigned)k;
+    if (push && (!single || left_marks)) {
+        const unsigned long long g = claim_body(k, n, row_ptr, col, acur, anext, marks, pi, layer,
+                                                nullptr, nullptr, nullptr, rin_ptr, rin,
+                                                marks_next, pedges, L);
+        if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min, true);
+    } else {
+        const unsigned long long g =
+            pull_body(k, n, row_ptr, col, acur, anext, layer, pi, nullptr, nullptr, nullptr,
+                      left_marks ? marks : nullptr, L.wave);
+        if (threadIdx.x == 0) round_close(ctl, k, g, policy, push_min, false);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2873,14 +2887,17 @@ void launch_round(int k, int n, const int* row_ptr, const int* col, const int* r
                   const int* rin, const unsigned* acur, unsigned* anext, unsigned char* marks,
                   unsigned char* marks_next, int* pi, int* layer, Ctl* ctl,
                   unsigned long long* pedges, int policy, unsigned push_min, bool may_push,
-                  hipStream_t st)
+                  bool single, hipStream_t st)
 {
     const unsigned grid = (unsigned)round_spans(n);
-    k_round_mark_pull<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, rin_ptr, rin, acur, anext, marks,
-                                            pi, layer, ctl, pedges, policy, push_min);
+    const bool one = single && may_push;
+    if (!one)
+        k_round_mark_pull<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, rin_ptr, rin, acur, anext,
+                                                marks, pi, layer, ctl, pedges, policy, push_min);
     if (may_push)
         k_round_claim<<<grid, kWG, 0, st>>>(k, n, row_ptr, col, rin_ptr, rin, acur, anext, marks,
-                                            marks_next, pi, layer, ctl, pedges, policy, push_min);
+                                            marks_next, pi, layer, ctl, pedges, policy, push_min,
+                                            one ? 1 : 0);
 }
 
 void launch_exclusive_scan(int64_t len, const unsigned* in, unsigned* out, unsigned* tot,

@@ -691,18 +691,25 @@ ocm_status connect_rounds_on_device(Ctx& c, int* pi, int* layer, unsigned left, 
     }
     ocm::launch_round_setup(w.ctl, left, front, policy, kPushMinUnattached, c.st);
     unsigned long long* pedges = &w.ctl->lane[0].pedges;
+    // the host's guess of the next rounds' direction (the device's rule on
+    // the counts it last read): while it says push, rounds after the first
+    // take one kernel each; a wrong guess costs time, not results
+    bool guess_push = left > 0 && (policy == 2 || (policy == 0 && left >= kPushMinUnattached &&
+                                                   2ull * front < left));
     int k = 0;
     for (;;) {
         for (int j = 0; j < kRoundsPerRead; ++j) {
             ++k;
             ocm::launch_round(k, c.n, c.row_ptr, c.col, w.rin_ptr, w.rin, w.abits[k & 1],
                               w.abits[(k + 1) & 1], w.marks[k & 1], w.marks[(k + 1) & 1], pi,
-                              layer, w.ctl, pedges, policy, kPushMinUnattached, may_push, c.st);
+                              layer, w.ctl, pedges, policy, kPushMinUnattached, may_push,
+                              k > 1 && guess_push, c.st);
         }
         HIP_TRY(hipGetLastError());
         OCM_TRY(read_ctl(c));
         if (c.h.rerr || c.h.rleft == 0) break;
         if (k > c.n + kRoundsPerRead) return fail(OCM_E_HIP, "rebuild rounds did not finish");
+        guess_push = c.h.rmode == 1u;
     }
     if (rounds) *rounds = (int)c.h.rk;
     c.connect_rounds += (int)c.h.rk;
