@@ -299,6 +299,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(SweepArgs a, const WT* __res
     unsigned cbroken = 0;
     if (t < nv && pos != INT32_MAX && (FIRST || best < own)) {
         a.pi[v0 + t] = pos;
+        if (a.succ) a.succ[v0 + t] = a.col[pos];   // the batch just read it
         changed = 1;
         if (!FIRST && a.onC && a.onC[v0 + t]) cbroken = 1;
     }

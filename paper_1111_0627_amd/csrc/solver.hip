@@ -432,10 +432,12 @@ ocm_status phase_sweep(Ctx& c, bool first, bool tie, const long long* V, long lo
     }
     const int cls = tie ? OCM_K_TIESCAN : OCM_K_SWEEP;
     const bool fused = !tie && !first && c.tile_sweep && c.count_tight;
-    // a sweep that changes pi without updating succ leaves it stale
-    const bool keep = fused && c.succ_ok && pi == c.ws.pi;
+    // a sweep that changes pi without updating succ leaves it stale; the
+    // first tile sweep writes every vertex's, so succ is whole after it
+    const bool keep = pi == c.ws.pi && (first ? c.tile_sweep : fused && c.succ_ok);
     a.succ = keep ? c.ws.succ : nullptr;
     if (!tie && !keep) c.succ_ok = false;
+    if (keep && first) c.succ_ok = true;
     c.prof.begin(cls);
     ocm::launch_sweep(a, c.w, c.wtype, c.tile_sweep ? 0 : c.G, first, tie, fused, c.sweep_grid,
                       c.st);
