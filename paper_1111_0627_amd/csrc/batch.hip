@@ -291,6 +291,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
 {
     constexpr int VPB = kWG / G;
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
+        if (TIE && ga.status[g] != OCM_OK) return;
         const bool first = !TIE && ga.iter[g] == 0;
         const long long L = first ? 1 : ga.L[g];
         const long long W = first ? 0 : ga.W[g];
@@ -316,8 +317,19 @@ __global__ __launch_bounds__(kWG) void k_sweep(const int2* __restrict__ chunks,
                 if (TIE) {
                     if (key == own && e != cur) {
                         cnt++;
-                        if (col[e] == v || onC[v]) certain++;
-                        if (hop[col[e]] >= hop[v]) nondec++;
+                        const int y = col[e];
+                        const bool sure = y == v || onC[v];
+                        if (sure) certain++;
+                        if (hop[y] >= hop[v]) {
+                            nondec++;
+                            // the short walk (few such edges: walked here,
+                            // unless the graph is already known to tie)
+                            if (succ && !sure && ga.certain[g] == 0) {
+                                int x = y;
+                                for (int st = 0; st < kShortWalk && x != (int)v; ++st) x = succ[x];
+                                certain += x == (int)v;
+                            }
+                        }
                         if (xs) {   // list the tight non-policy edge (tie test)
                             const unsigned slot = atomicAdd(xcnt, 1u);
                             if (slot < xcap) {
@@ -1146,49 +1158,35 @@ __global__ __launch_bounds__(kWG) void k_cycle_list(const int2* __restrict__ chu
     });
 }
 
-template <int G, typename WT>
-__global__ __launch_bounds__(kWG) void k_short_walk(const int2* __restrict__ chunks,
-                                                    const unsigned* nch, int T, GArrays ga,
-                                                    const int* __restrict__ row_ptr,
-                                                    const int* __restrict__ col,
-                                                    const WT* __restrict__ w, int neg,
-                                                    const long long* __restrict__ V,
-                                                    const int* __restrict__ pi,
-                                                    const int* __restrict__ succ,
-                                                    const int* __restrict__ hop)
-{
-    constexpr int VPB = kWG / G;
-    for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
-        // certain[g] grows during this launch: decide once for the workgroup
-        if (block_bcast(ga.status[g] != OCM_OK || ga.certain[g] || !ga.nondec[g])) return;
-        const long long L = ga.L[g], W = ga.W[g];
-        const int lane = threadIdx.x & (G - 1);
-        unsigned long long found = 0;
-        for (int64_t vb = v0; vb < v1; vb += VPB) {
-            const int64_t v = vb + threadIdx.x / G;
-            if (v >= v1) continue;
-            const int beg = row_ptr[v], end = row_ptr[v + 1], cur = pi[v];
-            const long long own = V[v];
-            for (int e = beg + lane; e < end; e += G) {
-                if (e == cur) continue;
-                const int y = col[e];
-                if (hop[y] < hop[v]) continue;
-                if (V[y] + L * wval(w, e, neg) - W != own) continue;
-                int x = y;
-                for (int st = 0; st < kShortWalk && x != (int)v; ++st) x = succ[x];
-                found += x == (int)v;
-            }
-        }
-        found = block_sum_u64(found);
-        if (threadIdx.x == 0 && found) atomicAdd(&ga.certain[g], found);
-    });
-}
-
 __global__ void k_bctl_clear(BCtl* bc)
 {
     if (threadIdx.x == 0) {
         unsigned* p = (unsigned*)bc;
         for (unsigned i = 0; i < sizeof(BCtl) / sizeof(unsigned); ++i) p[i] = 0;
+    }
+}
+
+// The tie list's edges whose graph is in mode kTieList, appended to xo / yo
+// (their graph found by a binary search over vptr).
+__global__ __launch_bounds__(kWG) void k_list_open(unsigned k, const int* __restrict__ xs,
+                                                   const int* __restrict__ ys, int G,
+                                                   const long long* __restrict__ vptr,
+                                                   const int* __restrict__ mode,
+                                                   int* __restrict__ xo, int* __restrict__ yo,
+                                                   unsigned* cnt)
+{
+    for (unsigned i = blockIdx.x * kWG + threadIdx.x; i < k; i += gridDim.x * kWG) {
+        const long long v = xs[i];
+        int lo = 0, hi = G;   // vptr[lo] <= v < vptr[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (vptr[mid] <= v) lo = mid;
+            else hi = mid;
+        }
+        if (mode[lo] != kTieList) continue;
+        const unsigned slot = atomicAdd(cnt, 1u);
+        xo[slot] = (int)v;
+        yo[slot] = ys[i];
     }
 }
 
@@ -1885,7 +1883,7 @@ ocm_status build_chunks(BCtx& c, int want, unsigned* nch_out)
 
 template <typename WT>
 void launch_bsweep_t(BCtx& c, unsigned nch, bool tie, int* xs, int* ys, unsigned* xcnt,
-                     unsigned xcap)
+                     unsigned xcap, bool walk)
 {
     const WT* w = (const WT*)c.w;
     BWs& ws = c.ws;
@@ -1895,7 +1893,7 @@ void launch_bsweep_t(BCtx& c, unsigned nch, bool tie, int* xs, int* ys, unsigned
         if (tie)                                                                                 \
             ocm::b::k_sweep<GG, WT, true><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(          \
                 ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,   \
-                ws.onC, ws.hop, xs, ys, xcnt, xcap, nullptr, nullptr);                           \
+                ws.onC, ws.hop, xs, ys, xcnt, xcap, walk ? ws.succ : nullptr, nullptr);          \
         else                                                                                     \
             ocm::b::k_sweep<GG, WT, false><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(         \
                 ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,   \
@@ -1915,9 +1913,10 @@ void launch_bsweep_t(BCtx& c, unsigned nch, bool tie, int* xs, int* ys, unsigned
 }
 
 // xs / ys / xcnt (tie scans only, may be null): list the tight non-policy
-// edges, at most xcap of them (xcnt counts all).
+// edges, at most xcap of them (xcnt counts all).  walk (tie scans only):
+// also take the short walk from every tight edge that does not lower hop.
 void launch_bsweep(BCtx& c, unsigned nch, bool tie, int* xs = nullptr, int* ys = nullptr,
-                   unsigned* xcnt = nullptr, unsigned xcap = 0)
+                   unsigned* xcnt = nullptr, unsigned xcap = 0, bool walk = false)
 {
     if (nch == 0) return;
     if (!tie && c.tile_sweep) {   // improvement sweeps over vertex tiles
@@ -1935,41 +1934,10 @@ void launch_bsweep(BCtx& c, unsigned nch, bool tie, int* xs = nullptr, int* ys =
 #undef OCM_BST
         return;
     }
-    if (c.wtype == OCM_W_I64) launch_bsweep_t<long long>(c, nch, tie, xs, ys, xcnt, xcap);
-    else launch_bsweep_t<int>(c, nch, tie, xs, ys, xcnt, xcap);
+    if (c.wtype == OCM_W_I64) launch_bsweep_t<long long>(c, nch, tie, xs, ys, xcnt, xcap, walk);
+    else launch_bsweep_t<int>(c, nch, tie, xs, ys, xcnt, xcap, walk);
 }
 
-template <typename WT>
-void launch_bwalk_t(BCtx& c, unsigned nch)
-{
-    const WT* w = (const WT*)c.w;
-    BWs& ws = c.ws;
-    const int T = c.sch.chunk;
-#define OCM_BWK(GG)                                                                              \
-    case GG:                                                                                     \
-        ocm::b::k_short_walk<GG, WT><<<chunk_grid(nch), ocm::kWG, 0, c.st>>>(                                 \
-            ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, w, c.neg, ws.V, ws.pi,       \
-            ws.succ, ws.hop);                                                                    \
-        break;
-    switch (c.sch.lanes) {
-        OCM_BWK(1)
-        OCM_BWK(2)
-        OCM_BWK(4)
-        OCM_BWK(8)
-        OCM_BWK(16)
-        OCM_BWK(32)
-        OCM_BWK(64)
-        default: break;
-    }
-#undef OCM_BWK
-}
-
-void launch_bwalk(BCtx& c, unsigned nch)
-{
-    if (nch == 0) return;
-    if (c.wtype == OCM_W_I64) launch_bwalk_t<long long>(c, nch);
-    else launch_bwalk_t<int>(c, nch);
-}
 
 int jump_rounds(const BCtx& c)
 {
@@ -2370,14 +2338,24 @@ ocm_status check_batch(int64_t G, const int64_t* vptr, const int64_t* eptr, cons
     return OCM_OK;
 }
 
+// Capacity of the first tie scan's edge list: its two arrays and the open
+// graphs' copy (four arrays of int32) fit the two jump buffers (24 bytes per
+// vertex).
+unsigned tie_cap1(const BCtx& c)
+{
+    return (unsigned)std::min<int64_t>(int64_t(1) << 20, (int64_t)c.n);
+}
+
 // Exact uniqueness of the critical cycles of every graph flagged
-// OCM_F_TIE_UNCHECKED, together: their tight non-policy edges are listed by
-// one more tie scan over their chunks, each endpoint becomes a special vertex
-// that learns the next special vertex (or its graph's C) on its policy path,
-// and the host looks for cycles in that small graph (one node c*_g per
-// graph; no edge joins two graphs, so a cycle decides its own graph).
-// *listed = false when the edges do not fit the list (nothing decided).
-ocm_status union_tie(BCtx& c, const int64_t* vptr, uint32_t* flags, bool* listed)
+// OCM_F_TIE_UNCHECKED, together: their tight non-policy edges (taken from the
+// first tie scan's list when all of it fit, kx1 <= tie_cap1(c), else listed
+// by one more tie scan over their chunks) each give two special vertices;
+// each special vertex learns the next special vertex (or its graph's C) on
+// its policy path, and the host looks for cycles in that small graph (one
+// node c*_g per graph; no edge joins two graphs, so a cycle decides its own
+// graph).  *listed = false when the edges do not fit the list (nothing
+// decided).
+ocm_status union_tie(BCtx& c, const int64_t* vptr, uint32_t* flags, unsigned kx1, bool* listed)
 {
     BWs& ws = c.ws;
     GArrays& a = ws.ga;
@@ -2387,14 +2365,29 @@ ocm_status union_tie(BCtx& c, const int64_t* vptr, uint32_t* flags, bool* listed
     for (int64_t g = 0; g < G; ++g)
         if (flags[g] & OCM_F_TIE_UNCHECKED) mode[g] = ocm::b::kTieList;
     BHIP(hipMemcpyAsync(a.mode, mode.data(), 4 * (size_t)G, hipMemcpyHostToDevice, c.st));
-    // lists in the (now free) jump buffers
-    const unsigned xcap = (unsigned)std::min<int64_t>(int64_t(1) << 20, 2 * (int64_t)c.n);
-    int* xs = (int*)ws.Q[0];
-    int* ys = xs + xcap;
     ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->xcnt, &ws.bc->scnt);
-    unsigned nch = 0;
-    BTRY(build_chunks(c, ocm::b::kTieList, &nch));
-    launch_bsweep(c, nch, true, xs, ys, &ws.bc->xcnt, xcap);
+    // lists in the (now free) jump buffers
+    int* xs;
+    int* ys;
+    unsigned xcap;
+    const unsigned cap1 = tie_cap1(c);
+    if (kx1 <= cap1) {
+        // the open graphs' share of the first list, behind it
+        const int* xs1 = (const int*)ws.Q[0];
+        xs = (int*)ws.Q[0] + 2 * (size_t)cap1;
+        ys = xs + cap1;
+        xcap = cap1;
+        if (kx1)
+            ocm::b::k_list_open<<<ocm::stride_grid(kx1), ocm::kWG, 0, c.st>>>(
+                kx1, xs1, xs1 + cap1, (int)G, a.vptr, a.mode, xs, ys, &ws.bc->xcnt);
+    } else {
+        xcap = (unsigned)std::min<int64_t>(int64_t(1) << 20, 2 * (int64_t)c.n);
+        xs = (int*)ws.Q[0];
+        ys = xs + xcap;
+        unsigned nch = 0;
+        BTRY(build_chunks(c, ocm::b::kTieList, &nch));
+        launch_bsweep(c, nch, true, xs, ys, &ws.bc->xcnt, xcap);
+    }
     BHIP(hipGetLastError());
     BTRY(bread(c));
     const unsigned kx = c.h.xcnt;
@@ -2738,8 +2731,11 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
                                                          ws.cptr, ws.onC, ws.pi, ws.hop, cycle_edges);
         if (o.tie_check) {
             ocm::b::k_tie_init<<<ocm::stride_grid(G), ocm::kWG, 0, c.st>>>((int)G, a);
-            launch_bsweep(c, nch, true);
-            launch_bwalk(c, nch);
+            ocm::b::k_bctl_zero<<<1, 64, 0, c.st>>>(&ws.bc->xcnt, nullptr);
+            const unsigned cap1 = tie_cap1(c);
+            launch_bsweep(c, nch, true, (int*)ws.Q[0], (int*)ws.Q[0] + cap1, &ws.bc->xcnt, cap1, true);
+            unsigned kx1 = 0;
+            BHIP(hipMemcpyAsync(&kx1, &ws.bc->xcnt, 4, hipMemcpyDeviceToHost, c.st));
             std::vector<unsigned long long> ht(G), hc(G), hn(G);
             BHIP(hipMemcpyAsync(ht.data(), a.tight, 8 * (size_t)G, hipMemcpyDeviceToHost, c.st));
             BHIP(hipMemcpyAsync(hc.data(), a.certain, 8 * (size_t)G, hipMemcpyDeviceToHost, c.st));
@@ -2758,7 +2754,7 @@ ocm_status solve_batched(int64_t G, const int64_t* vptr, const int64_t* eptr, co
             bool open = false;
             for (int64_t g = 0; g < G; ++g) open |= (flags[g] & OCM_F_TIE_UNCHECKED) != 0;
             bool listed = false;
-            if (open) BTRY(union_tie(c, vptr, flags, &listed));
+            if (open) BTRY(union_tie(c, vptr, flags, kx1, &listed));
             if (open && !listed)
                 for (int64_t g = 0; g < G; ++g)
                     if (flags[g] & OCM_F_TIE_UNCHECKED) {

@@ -192,6 +192,27 @@ def test_batched_ties_resolved_exactly(mode):
     assert ties > 10
 
 
+def test_batched_ties_when_the_first_list_overflows():
+    """Graphs of equal weights have more tight non-policy edges than the
+    batch has vertices, so the list of the first tie scan overflows and the
+    open graphs' edges are listed again; the tie flags must still be the
+    oracle's."""
+    rng = np.random.default_rng(18)
+    gs = [synth.random_digraph(int(rng.integers(500, 4000)), 4, 8, 5, 5, np.int32, seed=[18, k])
+          for k in range(6)]
+    gs += [synth.random_digraph(int(rng.integers(2, 3000)), 1, 4, 0, 2, np.int32, seed=[17, k])
+           for k in range(40)]
+    u, vptr, eptr = synth.disjoint_union(gs)
+    res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr)
+    assert all(s == ocm.OCM_OK for s in res.status)
+    sols = [native.solve(g.row_ptr, g.col, g.w) for g in gs]
+    assert sum(s.tight for s in sols) > u.n   # the first list cannot hold them
+    for k, sol in enumerate(sols):
+        assert (res.p[k], res.q[k], res.iterations[k]) == (sol.p, sol.q, sol.iterations), k
+        assert res.tie(k) == bool(sol.tie), k
+    assert sum(s.tie for s in sols) > 10
+
+
 @pytest.mark.parametrize("graph", ["1", "0"])
 def test_batched_deep_rebuilds_on_device(monkeypatch, graph):
     """Sparse graphs (out-degree 0-1 plus the ring) whose later rebuilds need
