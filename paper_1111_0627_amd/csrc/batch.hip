@@ -393,7 +393,12 @@ constexpr int kBTileEdges = 1024;
 // covers the list's capacity and idle workgroups leave at once), so that
 // the dispatcher overlaps one tile's loads with another's (measured faster
 // than a resident grid that walks its chunks' tiles in order).
-template <typename WT>
+//
+// TIE: the tie scan after the loop instead (no policy change), with the
+// counts, the short walk (succ non-null) and the edge list of k_sweep's
+// tie form; graphs whose solve failed are skipped, and V is read in full
+// (the small class writes no int32 copy).
+template <typename WT, bool TIE>
 __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chunks,
                                                     const unsigned* nch, int T, GArrays ga,
                                                     const int* __restrict__ row_ptr,
@@ -404,22 +409,57 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
                                                     const unsigned char* __restrict__ onC,
                                                     const int* __restrict__ V32, const BCtl* bc,
                                                     int* __restrict__ succ,
-                                                    WT* __restrict__ wsel)
+                                                    WT* __restrict__ wsel,
+                                                    const int* __restrict__ hop,
+                                                    int* __restrict__ xs, int* __restrict__ ys,
+                                                    unsigned* xcnt, unsigned xcap)
 {
     __shared__ int beg[kWG + 1];
     __shared__ long long key[kBTileEdges];
     constexpr int U = kBTileEdges / kWG;
     const int t = threadIdx.x;
+    const unsigned per = (unsigned)((T + kWG - 1) / kWG);
+    const unsigned ci = blockIdx.x / per;
+    if (ci >= *nch) return;
+    const int2 ch = chunks[ci];
+    const int g = ch.x;
+    if (TIE && ga.status[g] != OCM_OK) return;
     // every value written so far fits int32: gather the 4-byte copy
-    const bool use32 = bc->wide32 == 0u;
-    // the tile of nv <= kWG vertices from v0; counts into cnt / brk
-    auto tile = [&](int64_t v0, int nv, bool first, long long L, long long W,
-                    unsigned long long& cnt, unsigned& brk) {
+    const bool use32 = !TIE && bc->wide32 == 0u;
+    unsigned long long cnt = 0, certain = 0, nondec = 0;
+    unsigned brk = 0;
+    // tie form: the tight non-policy edge e of vertex v
+    auto tight_edge = [&](int64_t v, int e) {
+        cnt++;
+        const int y = col[e];
+        const bool sure = y == v || onC[v];
+        if (sure) certain++;
+        if (hop[y] >= hop[v]) {
+            nondec++;
+            // the short walk (few such edges: walked here, unless the graph
+            // is already known to tie)
+            if (succ && !sure && ga.certain[g] == 0) {
+                int x = y;
+                for (int st = 0; st < kShortWalk && x != (int)v; ++st) x = succ[x];
+                certain += x == (int)v;
+            }
+        }
+        if (xs) {
+            const unsigned slot = atomicAdd(xcnt, 1u);
+            if (slot < xcap) {
+                xs[slot] = (int)v;
+                ys[slot] = y;
+            }
+        }
+    };
+    // the tile of nv <= kWG vertices from v0
+    auto tile = [&](int64_t v0, int nv, bool first, long long L, long long W) {
         long long own = 0, best = INT64_MAX;
-        int pos = INT32_MAX;
+        int pos = INT32_MAX, cur = -1;
         if (t < nv) {
             beg[t] = row_ptr[v0 + t];
             if (!first) own = use32 ? (long long)V32[v0 + t] : V[v0 + t];
+            if (TIE) cur = pi[v0 + t];
         }
         if (t == 0) beg[nv] = row_ptr[v0 + nv];
         __syncthreads();
@@ -453,7 +493,9 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
             if (!long_row)
                 for (int e = lo; e < hi; ++e) {
                     const long long k = key[e - eb];
-                    if (k < best) {
+                    if (TIE) {
+                        if (k == own && e != cur) tight_edge(v0 + t, e);
+                    } else if (k < best) {
                         best = k;
                         pos = e;
                     }
@@ -462,6 +504,14 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
             for (unsigned long long lm = __ballot(long_row); lm; lm &= lm - 1) {
                 const int l = __ffsll((long long)lm) - 1;
                 const int rlo = __shfl(lo, l, 64), rhi = __shfl(hi, l, 64);
+                if (TIE) {
+                    const long long rown = __shfl(own, l, 64);
+                    const int rcur = __shfl(cur, l, 64);
+                    const int64_t rv = v0 + (t & ~63) + l;
+                    for (int e = rlo + (t & 63); e < rhi; e += 64)
+                        if (key[e - eb] == rown && e != rcur) tight_edge(rv, e);
+                    continue;
+                }
                 long long rb = INT64_MAX;
                 int rp = INT32_MAX, rh = 0;
                 for (int e = rlo + (t & 63); e < rhi; e += 64) {
@@ -479,7 +529,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
             }
             __syncthreads();
         }
-        if (t < nv && pos != INT32_MAX && (first || best < own)) {
+        if (!TIE && t < nv && pos != INT32_MAX && (first || best < own)) {
             pi[v0 + t] = pos;
             succ[v0 + t] = col[pos];
             wsel[v0 + t] = w[pos];
@@ -487,29 +537,29 @@ __global__ __launch_bounds__(kWG) void k_sweep_tile(const int2* __restrict__ chu
             if (!first && onC[v0 + t]) brk = 1;
         }
     };
-    auto book = [&](int g, unsigned long long cnt, unsigned brk) {
-        cnt = block_sum_u64(cnt);
+    const int64_t end = ga.vptr[g + 1];
+    const int64_t c1 = ch.y + (int64_t)T < end ? ch.y + (int64_t)T : end;
+    const int64_t v0 = ch.y + (int64_t)(blockIdx.x % per) * kWG;
+    if (v0 >= c1) return;
+    const bool first = !TIE && ga.iter[g] == 0;
+    tile(v0, c1 - v0 < kWG ? (int)(c1 - v0) : kWG, first, first ? 1 : ga.L[g],
+         first ? 0 : ga.W[g]);
+    cnt = block_sum_u64(cnt);
+    if (TIE) {
+        certain = block_sum_u64(certain);
+        nondec = block_sum_u64(nondec);
+        if (threadIdx.x == 0) {
+            if (cnt) atomicAdd(&ga.tight[g], cnt);
+            if (certain) atomicAdd(&ga.certain[g], certain);
+            if (nondec) atomicAdd(&ga.nondec[g], nondec);
+        }
+    } else {
         const unsigned long long bb = block_sum_u64(brk);
         if (threadIdx.x == 0) {
             if (cnt) atomicAdd(&ga.changed[g], (unsigned)(cnt > 0xffffffffull ? 0xffffffffu : cnt));
             if (bb) atomicOr(&ga.cbroken[g], 1u);
         }
-    };
-    const unsigned per = (unsigned)((T + kWG - 1) / kWG);
-    const unsigned ci = blockIdx.x / per;
-    if (ci >= *nch) return;
-    const int2 ch = chunks[ci];
-    const int g = ch.x;
-    const int64_t end = ga.vptr[g + 1];
-    const int64_t c1 = ch.y + (int64_t)T < end ? ch.y + (int64_t)T : end;
-    const int64_t v0 = ch.y + (int64_t)(blockIdx.x % per) * kWG;
-    if (v0 >= c1) return;
-    const bool first = ga.iter[g] == 0;
-    unsigned long long cnt = 0;
-    unsigned brk = 0;
-    tile(v0, c1 - v0 < kWG ? (int)(c1 - v0) : kWG, first, first ? 1 : ga.L[g],
-         first ? 0 : ga.W[g], cnt, brk);
-    book(g, cnt, brk);
+    }
 }
 
 // After the sweep: converged graphs retire; the others take the fast path
@@ -1919,18 +1969,24 @@ void launch_bsweep(BCtx& c, unsigned nch, bool tie, int* xs = nullptr, int* ys =
                    unsigned* xcnt = nullptr, unsigned xcap = 0, bool walk = false)
 {
     if (nch == 0) return;
-    if (!tie && c.tile_sweep) {   // improvement sweeps over vertex tiles
+    if (c.tile_sweep) {   // improvement sweeps and tie scans over vertex tiles
         BWs& ws = c.ws;
         const int T = c.sch.chunk;
         const unsigned per = (unsigned)((T + ocm::kWG - 1) / ocm::kWG);
         // one workgroup per tile: the list's capacity in tiles
         const unsigned one = (unsigned)(c.n / T + c.G + 1) * per;
-#define OCM_BST(WT)                                                                              \
-    ocm::b::k_sweep_tile<WT><<<one, ocm::kWG, 0, c.st>>>(                                        \
+#define OCM_BST(WT, TIE, SUCC, WSEL)                                                             \
+    ocm::b::k_sweep_tile<WT, TIE><<<one, ocm::kWG, 0, c.st>>>(                                   \
         ws.chunks, &ws.bc->nchunks, T, ws.ga, c.row_ptr, c.col, (const WT*)c.w, c.neg, ws.V,     \
-        ws.pi, ws.onC, ws.V32, ws.bc, ws.succ, (WT*)ws.wsel)
-        if (c.wtype == OCM_W_I64) OCM_BST(long long);
-        else OCM_BST(int);
+        ws.pi, ws.onC, ws.V32, ws.bc, SUCC, WSEL, ws.hop, xs, ys, xcnt, xcap)
+        int* sc = !tie || walk ? ws.succ : nullptr;
+        if (c.wtype == OCM_W_I64) {
+            if (tie) OCM_BST(long long, true, sc, nullptr);
+            else OCM_BST(long long, false, sc, (long long*)ws.wsel);
+        } else {
+            if (tie) OCM_BST(int, true, sc, nullptr);
+            else OCM_BST(int, false, sc, (int*)ws.wsel);
+        }
 #undef OCM_BST
         return;
     }

@@ -286,6 +286,57 @@ def test_batched_hub_rows():
             assert res.tie(k) == bool(sol.tie), k
 
 
+def _ring_with_hub(n, chords, last=None):
+    """A ring 0 -> 1 -> ... -> n-1 -> 0 of weight-1 edges whose vertex 0
+    also has chords 0 -> 2, 0 -> 3, ... of weight 2 (never tight) and,
+    when last is given, a final chord 0 -> last of weight 1: tight, and a
+    second cycle of mean 1 (a tie), found only in that long row."""
+    rows = [[(1, 1)] + [(2 + k, 2) for k in range(chords)] + ([(last, 1)] if last else [])]
+    rows += [[((v + 1) % n, 1)] for v in range(1, n)]
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    cl = np.array([c for r in rows for c, _ in r], np.int32)
+    w = np.array([x for r in rows for _, x in r], np.int64)
+    return synth.Graph(rp, cl, w)
+
+
+def _two_rings_hub():
+    """Rings 0..99 and 100..109 of weight-1 edges, joined by 50 -> 100
+    (weight 1000) and 100 -> 0 (weight 1). Vertex 100's row holds 100 -> 0,
+    40 copies of 100 -> 0 of weight 50, then its ring edge 100 -> 101: with
+    C the first ring, that last edge is the one tight non-policy edge, and
+    the short walk from 101 comes back to 100 (a tie)."""
+    rows = [[((v + 1) % 100, 1)] + ([(100, 1000)] if v == 50 else []) for v in range(100)]
+    rows.append([(0, 1)] + [(0, 50)] * 40 + [(101, 1)])
+    rows += [[(101 + k if k < 9 else 100, 1)] for k in range(1, 10)]
+    rp = np.zeros(len(rows) + 1, np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    cl = np.array([c for r in rows for c, _ in r], np.int32)
+    w = np.array([x for r in rows for _, x in r], np.int64)
+    return synth.Graph(rp, cl, w)
+
+
+def test_batched_tie_in_long_rows():
+    """The tie scan walks rows of more than 32 keys with the whole wave: a
+    tie whose only tight edge sits at the end of such a row is found, and
+    rings whose long rows hold no tight edge stay untied (as the oracle)."""
+    gs = [_ring_with_hub(100, 60), _ring_with_hub(100, 60, 50), _ring_with_hub(3000, 2000),
+          _ring_with_hub(3000, 2000, 2500), _two_rings_hub(),
+          synth.random_digraph(2000, 1, 5, 1, 1000, np.int64, seed=[10, 1])]
+    u, vptr, eptr = synth.disjoint_union(gs)
+    for mode in ("min", "max"):
+        res = ocm.cycle_mean_batched(*to_dev(u), vptr, eptr, mode=mode)
+        assert all(s == ocm.OCM_OK for s in res.status)
+        ties = []
+        for k, g in enumerate(gs):
+            sol = native.solve(g.row_ptr, g.col, g.w, mode=mode)
+            assert (res.p[k], res.q[k], res.iterations[k]) == (sol.p, sol.q, sol.iterations), k
+            assert res.tie(k) == bool(sol.tie), k
+            ties.append(bool(sol.tie))
+        if mode == "min":
+            assert ties[:5] == [False, True, False, True, True]
+
+
 def _small_class_batch(seed):
     """Small graphs (the LDS class: n <= 2048) of every kind next to larger
     ones: random weights, equal weights (ties), two disjoint rings (not
