@@ -50,8 +50,12 @@ struct GArrays {              // device arrays with one entry per graph
     unsigned* changed;
     unsigned* cbroken;
     unsigned* vrun;           // values: 1 while the graph is propagating
-    unsigned* vact;           // values: some vertex unfinished after the round
-    unsigned* vprog;          // values: some vertex finished in the round
+    // values: some vertex unfinished after the round / some vertex finished
+    // in it, in three slots per graph ([4 g + slot]): round r reads slot
+    // r % 3 (the previous round's, the init's for r = 0), writes slot
+    // (r + 1) % 3 and clears slot (r + 2) % 3 for round r + 1
+    unsigned* vact;
+    unsigned* vprog;
     unsigned* ovf;
     int* fin;                 // values: ping-pong buffer holding the final entries
     unsigned char* have_c;
@@ -68,7 +72,8 @@ struct GArrays {              // device arrays with one entry per graph
 struct BCtl {
     unsigned nchunks;
     unsigned nactive, nfast, ngeneral, ndone;
-    unsigned vrun_round[32];   // value phase: graphs still running in round r
+    unsigned vrun_round[32];   // value phase: round r has a graph to advance
+    unsigned vlast;            // value phase: slot / buffer parity of the last round's output
     unsigned nspans;           // rebuild: spans holding a rebuilt graph
     unsigned ncyc;
     unsigned overflow;
@@ -608,7 +613,7 @@ __global__ __launch_bounds__(kWG) void k_after_sweep(int G, GArrays ga, int max_
 // from succ and wsel, and the entry already spans two policy edges (succ
 // and wsel of the successor are gathered); otherwise (after a rebuild) they
 // come from pi, col and w, the entry spans one edge, and succ and wsel are
-// written.  It also books the first round: a graph none of
+// written.  It also books the first round in slot 0: a graph none of
 // whose vertices has an entry short of s is finished (vact stays clear).
 template <typename WT, bool SEL>
 __global__ __launch_bounds__(kWG) void k_val_init(const int2* __restrict__ chunks,
@@ -617,7 +622,7 @@ __global__ __launch_bounds__(kWG) void k_val_init(const int2* __restrict__ chunk
                                                   const int* __restrict__ pi,
                                                   const WT* __restrict__ w, int neg,
                                                   int* __restrict__ succ, WT* __restrict__ wsel,
-                                                  VJ* __restrict__ Q)
+                                                  VJ* __restrict__ Q, BCtl* bc)
 {
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
         const int s = ga.s[g];
@@ -652,28 +657,63 @@ __global__ __launch_bounds__(kWG) void k_val_init(const int2* __restrict__ chunk
         if (threadIdx.x == 0) {
             ga.vrun[g] = 1;
             ga.ovf[g] = 0;
-            if (a) atomicOr(&ga.vact[g], 1u);
-            atomicOr(&ga.vprog[g], 1u);
+            if (a) {
+                atomicOr(&ga.vact[4 * g], 1u);
+                atomicOr(&bc->vrun_round[0], 1u);
+            }
+            atomicOr(&ga.vprog[4 * g], 1u);
         }
     });
 }
 
 constexpr int kValRoundU = 8;
 
+// Value round r: first the previous round's booking (slot r % 3) of each
+// graph: a graph with no unfinished vertex is finished (its entries stay in
+// buffer r & 1), one whose previous round finished none while some remain
+// never reaches s (fast path: C is no longer the only cycle; it falls back
+// to the general phases, a general graph fails).  Every workgroup of the
+// graph takes the same decision from the same slot.  The rest advance one
+// jump and book slot (r + 1) % 3; the graph's first chunk clears slot
+// (r + 2) % 3 for the next round.
 __global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chunks,
                                                    const unsigned* nch, int T, GArrays ga,
                                                    const VJ* __restrict__ Qin,
-                                                   VJ* __restrict__ Qout, const unsigned* running)
+                                                   VJ* __restrict__ Qout, int want, int r,
+                                                   BCtl* bc)
 {
-    if (*running == 0) return;   // every graph of the phase has finished: nothing to do
+    if (bc->vrun_round[r] == 0) return;   // no graph of the phase left to advance
+    if (blockIdx.x == 0 && threadIdx.x == 0) bc->vlast = (unsigned)r + 1u;
+    const int si = r % 3, so = (r + 1) % 3, sc = (r + 2) % 3;
+    unsigned any = 0;
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
-        if (!ga.vrun[g]) return;   // finished or stalled graph: its entries stay put
+        // independent loads, issued together
+        const unsigned run = ga.vrun[g];
+        const unsigned pa = ga.vact[4 * g + si], pp = ga.vprog[4 * g + si];
         const int s = ga.s[g];
+        const bool head = v0 == ga.vptr[g];
+        if (threadIdx.x == 0 && head) {
+            ga.vact[4 * g + sc] = 0;
+            ga.vprog[4 * g + sc] = 0;
+        }
+        if (!run) return;   // finished or stalled graph: its entries stay put
+        if (!pa || !pp) {
+            if (threadIdx.x == 0) {
+                ga.vrun[g] = 0;
+                if (!pa) ga.fin[g] = r & 1;
+                else if (want == kFast) ga.mode[g] = kGeneral;   // fall back
+                else {
+                    ga.mode[g] = kDone;
+                    ga.status[g] = OCM_E_NOT_STRONGLY_CONNECTED;
+                }
+            }
+            return;
+        }
         unsigned act = 0, prog = 0;
         // kValRoundU entries in flight per thread: loads, then the dependent gathers
         constexpr int U = kValRoundU;
         for (int64_t vb = v0 + threadIdx.x; vb < v1; vb += U * kWG) {
-            VJ q[U], r[U];
+            VJ q[U], rr[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t v = vb + u * kWG;
@@ -682,17 +722,17 @@ __global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chun
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (q[u].J != s) r[u] = Qin[q[u].J];
+                if (q[u].J != s) rr[u] = Qin[q[u].J];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t v = vb + u * kWG;
                 if (v >= v1) continue;
                 if (q[u].J != s) {
-                    const long long a = vj_d(q[u]), b = vj_d(r[u]);
+                    const long long a = vj_d(q[u]), b = vj_d(rr[u]);
                     long long d;
                     if (a == kDOverflow || b == kDOverflow || __builtin_add_overflow(a, b, &d))
                         d = kDOverflow;
-                    q[u] = vj_make(d, r[u].J);
+                    q[u] = vj_make(d, rr[u].J);
                     if (q[u].J == s) prog = 1;
                     else act = 1;
                 }
@@ -701,41 +741,36 @@ __global__ __launch_bounds__(kWG) void k_val_round(const int2* __restrict__ chun
         }
         const unsigned long long a = block_sum_u64(act), p = block_sum_u64(prog);
         if (threadIdx.x == 0) {
-            if (a) atomicOr(&ga.vact[g], 1u);
-            if (p) atomicOr(&ga.vprog[g], 1u);
+            if (a) atomicOr(&ga.vact[4 * g + so], 1u);
+            if (p) atomicOr(&ga.vprog[4 * g + so], 1u);
+            any |= a ? 1u : 0u;
         }
     });
+    if (threadIdx.x == 0 && any && r + 1 < 32) atomicOr(&bc->vrun_round[r + 1], 1u);
 }
 
-// After a value round: a graph is finished when no vertex is unfinished; a
-// graph whose round finished nothing while vertices remain never reaches s
-// (fast path: C is no longer the only cycle).
-__global__ __launch_bounds__(kWG) void k_val_update(int G, GArrays ga, int want, int rounds,
-                                                    BCtl* bc, const unsigned* halt)
+// After the last round: the same decision from the last round's booking
+// (slot vlast % 3, buffer vlast & 1) for the graphs still running.
+__global__ __launch_bounds__(kWG) void k_val_close(int G, GArrays ga, int want, const BCtl* bc,
+                                                   const unsigned* halt)
 {
     if (halt && *halt != 0u) return;
-    unsigned running = 0;
+    const unsigned k = bc->vlast;
     for (int g = blockIdx.x * kWG + threadIdx.x; g < G; g += gridDim.x * kWG) {
         if (ga.mode[g] != want || !ga.vrun[g]) continue;
-        const unsigned a = ga.vact[g], p = ga.vprog[g];
-        ga.vact[g] = 0;
-        ga.vprog[g] = 0;
+        const unsigned a = ga.vact[4 * g + k % 3u], p = ga.vprog[4 * g + k % 3u];
         if (!a) {
-            ga.vrun[g] = 0;           // finished: entries are in buffer rounds & 1
-            ga.fin[g] = rounds & 1;
+            ga.vrun[g] = 0;
+            ga.fin[g] = (int)(k & 1u);
         } else if (!p) {
             ga.vrun[g] = 0;
-            if (want == kFast) ga.mode[g] = kGeneral;   // fall back
+            if (want == kFast) ga.mode[g] = kGeneral;
             else {
                 ga.mode[g] = kDone;
                 ga.status[g] = OCM_E_NOT_STRONGLY_CONNECTED;
             }
-        } else {
-            ++running;
         }
     }
-    const unsigned long long r = block_sum_u64(running);
-    if (threadIdx.x == 0 && r) atomicAdd(&bc->vrun_round[rounds], (unsigned)r);
 }
 
 __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chunks,
@@ -748,6 +783,11 @@ __global__ __launch_bounds__(kWG) void k_val_final(const int2* __restrict__ chun
     for_each_chunk(chunks, nch, ga.vptr, T, [&](int g, int64_t v0, int64_t v1) {
         // mode[g] may be changed by another workgroup of this launch: decide once
         const int state = block_bcast(ga.mode[g] != want ? 0 : (ga.vrun[g] ? 1 : 2));
+        // the phase's bookings are read: leave every slot clear for the next phase
+        if (threadIdx.x < 3 && v0 == ga.vptr[g]) {
+            ga.vact[4 * g + threadIdx.x] = 0;
+            ga.vprog[4 * g + threadIdx.x] = 0;
+        }
         if (state == 0) return;   // fell back or failed
         if (state == 1) {         // did not finish within the rounds
             if (threadIdx.x == 0) {
@@ -1261,8 +1301,10 @@ __global__ __launch_bounds__(kWG) void k_graph_init(int G, GArrays ga)
         ga.changed[g] = 0;
         ga.cbroken[g] = 0;
         ga.vrun[g] = 0;
-        ga.vact[g] = 0;
-        ga.vprog[g] = 0;
+        for (int k = 0; k < 4; ++k) {
+            ga.vact[4 * g + k] = 0;
+            ga.vprog[4 * g + k] = 0;
+        }
         ga.ovf[g] = 0;
         ga.have_c[g] = 0;
         ga.tight[g] = 0;
@@ -1753,8 +1795,8 @@ BWs bcarve(void* base, int64_t G, int64_t n, int64_t m, size_t sub_bytes)
     a.changed = (unsigned*)take(4 * Gs);
     a.cbroken = (unsigned*)take(4 * Gs);
     a.vrun = (unsigned*)take(4 * Gs);
-    a.vact = (unsigned*)take(4 * Gs);
-    a.vprog = (unsigned*)take(4 * Gs);
+    a.vact = (unsigned*)take(16 * Gs);
+    a.vprog = (unsigned*)take(16 * Gs);
     a.ovf = (unsigned*)take(4 * Gs);
     a.fin = (int*)take(4 * Gs);
     a.have_c = (unsigned char*)take(Gs);
@@ -2014,13 +2056,15 @@ void enqueue_values(BCtx& c, int want, const unsigned* halt = nullptr)
     const int T = c.sch.chunk;
     const unsigned mc = chunk_grid(c);
     enqueue_chunks(c, want, halt);
+    // vrun_round and vlast (the init books round 0)
+    ocm::launch_fill_u32(ws.bc->vrun_round, 33, 0u, c.st);
     // the fast path's graphs keep succ and wsel from their sweeps; the
     // general path's were rebuilt
     const bool sel = want == ocm::b::kFast;
 #define OCM_BVI(WT, SEL)                                                                        \
     ocm::b::k_val_init<WT, SEL><<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a,     \
                                                           c.col, ws.pi, (const WT*)c.w, c.neg,  \
-                                                          ws.succ, (WT*)ws.wsel, ws.Q[0])
+                                                          ws.succ, (WT*)ws.wsel, ws.Q[0], ws.bc)
     if (c.wtype == OCM_W_I64) {
         if (sel) OCM_BVI(long long, true);
         else OCM_BVI(long long, false);
@@ -2033,15 +2077,10 @@ void enqueue_values(BCtx& c, int want, const unsigned* halt = nullptr)
     // one resident wave of round workgroups (its registers allow fewer than
     // the chunk grid)
     const unsigned vg = kgrid(chunk_grid(c), (const void*)ocm::b::k_val_round);
-    ocm::launch_fill_u32(ws.bc->vrun_round, 32, 0u, c.st);
-    for (int r = 0; r < R; ++r) {
-        ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, r,
-                                                                         ws.bc, halt);
+    for (int r = 0; r < R; ++r)
         ocm::b::k_val_round<<<vg, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, ws.Q[r & 1],
-                                                     ws.Q[(r + 1) & 1], &ws.bc->vrun_round[r]);
-    }
-    ocm::b::k_val_update<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, R, ws.bc,
-                                                                     halt);
+                                                     ws.Q[(r + 1) & 1], want, r, ws.bc);
+    ocm::b::k_val_close<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, ws.bc, halt);
     ocm::b::k_val_final<<<mc, ocm::kWG, 0, c.st>>>(ws.chunks, &ws.bc->nchunks, T, a, want, ws.Q[0],
                                                    ws.Q[1], ws.V, ws.V32, ws.bc);
     ocm::b::k_values_done<<<ocm::stride_grid(c.G), ocm::kWG, 0, c.st>>>((int)c.G, a, want, halt);
