@@ -94,7 +94,7 @@ def class_kernels(table, cls):
 # multichain files do not change its kernels).
 DIGEST_FILES = ("include/ocm.h", "paper_1111_0627_amd/csrc/kernels.h",
                 "paper_1111_0627_amd/csrc/device_util.h", "paper_1111_0627_amd/csrc/kernels.hip",
-                "paper_1111_0627_amd/csrc/solver.hip")
+                "paper_1111_0627_amd/csrc/solver.hip", "paper_1111_0627_amd/csrc/batch.hip")
 
 
 def source_digest():
@@ -453,9 +453,11 @@ def batched_cpu_sample(gs, budget_s=12.0):
             "sample": f"sequential solves of {done} of {G} graphs (every 16th first)"}
 
 
-def bench_batched(steps: int):
+def bench_batched(steps: int, full: bool = True):
     """The batched workload: 4,096 random digraphs solved in one batched call
-    (ocm_min_batched), against 4,096 sequential single-graph GPU calls."""
+    (ocm_min_batched), against 4,096 sequential single-graph GPU calls.
+    full=False (a kernel trace of the batched solves): a cold call and the
+    timed ones only."""
     import torch
     from paper_1111_0627_amd import ocm, synth
     t = time.time()
@@ -475,6 +477,9 @@ def bench_batched(steps: int):
         torch.cuda.synchronize()
         times.append((time.perf_counter() - t) * 1e3)
     assert (r.p, r.q, r.iterations) == (res.p, res.q, res.iterations)
+    if not full:
+        return {"workload": "batch4096", "graphs": len(gs), "vertices": u.n, "edges": u.m,
+                "steps": steps, "batched_ms": {"median": float(np.median(times)), "min": min(times)}}
     # the same graphs, one plain call each (graphs already resident)
     rps = [rp[int(vptr[k]):int(vptr[k + 1]) + 1] - int(eptr[k]) for k in range(len(gs))]
     plain_ms = 0.0
@@ -623,7 +628,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="product16x6")
+    ap.add_argument("--workload", default="product16x6",
+                    help="a single-graph workload, or batch4096: the batched solves alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -672,6 +678,9 @@ def main():
     from paper_1111_0627_amd import ocm, synth
 
     name = args.workload
+    if name == "batch4096":   # the batched solves alone (for a kernel trace)
+        print(json.dumps(bench_batched(max(1, args.steps), full=False)), flush=True)
+        return
     mode = synth.WORKLOADS[name]["mode"]
     t = time.time()
     g = synth.workload(name)
