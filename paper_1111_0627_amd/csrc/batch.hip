@@ -666,7 +666,9 @@ __global__ __launch_bounds__(kWG) void k_val_init(const int2* __restrict__ chunk
     });
 }
 
-constexpr int kValRoundU = 8;
+// entries in flight per thread in a value round (batch4096: 16 measured
+// fastest; 8, 12 and 24 slower, 32 spills)
+constexpr int kValRoundU = 16;
 
 // Value round r: first the previous round's booking (slot r % 3) of each
 // graph: a graph with no unfinished vertex is finished (its entries stay in
